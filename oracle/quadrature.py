@@ -1,0 +1,103 @@
+"""Element-pair quadrature rules (oracle; test infrastructure only).
+
+The paper does not state its quadrature.  The discrete operator used by both
+implementations is defined by the following rules on a pair of straight
+elements (test element e with local coordinate u in [0,1], trial element f
+with v in [0,1]); every rule returns reference points (u, v) and weights that
+already contain the reference Jacobians (the physical weight is w h_e h_f):
+
+* regular pair (different elements that share no vertex): tensor
+  Gauss-Legendre with Q points per element, Q chosen from the gap
+  delta = dist(e, f) relative to h = max(h_e, h_f):
+  delta >= FAR_RATIO h -> Q_FAR, delta >= NEAR_RATIO h -> Q_MID, else Q_NEAR.
+* coincident pair (e == f): the square is split along its diagonal; on each
+  triangle the offset d = |u - v| is mapped as d = s^P_COINC and s is
+  integrated with Q_COINC Gauss points, the position along the diagonal with
+  2 Gauss points on [0, 1 - d] (exact for the quadratic hat products).
+* adjacent pair (one shared vertex): coordinates measured from the shared
+  vertex; each of the two triangles is Duffy-mapped (u', v') = (xi, xi eta) or
+  (xi eta, xi), xi = s^P_ADJ, with Q_ADJ x Q_ADJ Gauss points in (s, eta).
+
+The Gauss-Legendre nodes come from ``numpy.polynomial.legendre.leggauss``.
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+Q_FAR = 4
+Q_MID = 6
+Q_NEAR = 10
+FAR_RATIO = 8.0
+NEAR_RATIO = 2.0
+Q_COINC = 20
+P_COINC = 6
+Q_ADJ = 12
+P_ADJ = 4
+Q_RHS = 6
+
+
+@functools.lru_cache(maxsize=None)
+def gauss01(q: int):
+    """q-point Gauss-Legendre rule on [0, 1]."""
+    x, w = np.polynomial.legendre.leggauss(q)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+@functools.lru_cache(maxsize=None)
+def tensor_rule(q: int):
+    g, w = gauss01(q)
+    u = np.repeat(g, q)
+    v = np.tile(g, q)
+    ww = np.repeat(w, q) * np.tile(w, q)
+    return u, v, ww
+
+
+@functools.lru_cache(maxsize=None)
+def coincident_rule(q: int = Q_COINC, p: int = P_COINC):
+    """Points (u, v, w, u - v) on [0,1]^2 for a log-singular kernel on u = v;
+    the signed offset u - v is returned exactly."""
+    s, ws = gauss01(q)
+    d = s ** p
+    wd = ws * p * s ** (p - 1)
+    g2, w2 = gauss01(2)
+    us, vs, wts, offs = [], [], [], []
+    for di, wdi in zip(d, wd):
+        ell = 1.0 - di
+        for gk, wk in zip(g2, w2):
+            t = ell * gk
+            # triangle u > v: u = t + d, v = t ; triangle u < v: u = t, v = t + d
+            us += [t + di, t]
+            vs += [t, t + di]
+            wts += [wdi * ell * wk, wdi * ell * wk]
+            offs += [di, -di]
+    return np.array(us), np.array(vs), np.array(wts), np.array(offs)
+
+
+@functools.lru_cache(maxsize=None)
+def adjacent_rule(q: int = Q_ADJ, p: int = P_ADJ):
+    """Points (u', v', w) on [0,1]^2 with the singular corner at (0, 0);
+    u' and v' are distances from the shared vertex, normalised by the
+    element lengths."""
+    s, ws = gauss01(q)
+    eta, we = gauss01(q)
+    xi = s ** p
+    wxi = ws * p * s ** (p - 1)
+    XI = np.repeat(xi, q)
+    WXI = np.repeat(wxi, q)
+    ETA = np.tile(eta, q)
+    WE = np.tile(we, q)
+    w = WXI * WE * XI
+    u1, v1 = XI, XI * ETA          # triangle u' >= v'
+    u2, v2 = XI * ETA, XI          # triangle v' > u'
+    return np.concatenate([u1, u2]), np.concatenate([v1, v2]), np.concatenate([w, w])
+
+
+def regular_order(delta, h):
+    """Tensor order for a regular pair with gap delta and longer element h."""
+    delta = np.asarray(delta)
+    q = np.full(delta.shape, Q_NEAR, dtype=np.int64)
+    q[delta >= NEAR_RATIO * h] = Q_MID
+    q[delta >= FAR_RATIO * h] = Q_FAR
+    return q

@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only *generates inputs*: polygon node coordinates of the
+scatterers and the list of incident plane waves.  It contains none of the
+solver's arithmetic (no normals, no kernels, no quadrature, no linear
+algebra), so the CPU oracle and the GPU path can both consume it without
+sharing any computation.
+
+Geometry convention: every closed curve is returned as an ``(n, 2)`` float64
+array of vertices in counter-clockwise order; the polygon is closed
+implicitly (the last vertex connects back to the first).  The paper
+approximates the boundary by an N-gon whose vertices are the nodes
+(Section 4).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "circle",
+    "ellipse",
+    "tripod",
+    "multi_cavity",
+    "plane_wave_angles",
+    "config_small",
+    "config_scale",
+]
+
+
+def circle(n: int, radius: float = 1.0, center=(0.0, 0.0), phase: float = 0.0) -> np.ndarray:
+    """n vertices uniformly spaced on a circle, counter-clockwise."""
+    t = phase + 2.0 * np.pi * np.arange(n) / n
+    return np.stack([center[0] + radius * np.cos(t), center[1] + radius * np.sin(t)], axis=1)
+
+
+def ellipse(n: int, a: float = 1.0, b: float = 0.5, center=(0.0, 0.0), angle: float = 0.0) -> np.ndarray:
+    """n vertices uniform in the parameter angle of an ellipse with semi-axes a, b,
+    rotated by ``angle`` about its centre; counter-clockwise."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    px, py = a * np.cos(t), b * np.sin(t)
+    c, s = math.cos(angle), math.sin(angle)
+    return np.stack([center[0] + c * px - s * py, center[1] + s * px + c * py], axis=1)
+
+
+def tripod(n: int, r: float = 1.0, a: float = 0.3, b: float = 3.0) -> np.ndarray:
+    """The three-lobed scatterer of the paper's numerical examples (Section 8,
+    figure of the scatterer): ((r + a cos b t) cos t, (r + a cos b t) sin t)/(1 + a)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    rad = (r + a * np.cos(b * t)) / (1.0 + a)
+    return np.stack([rad * np.cos(t), rad * np.sin(t)], axis=1)
+
+
+def _ellipse_perimeter(a: float, b: float) -> float:
+    # Ramanujan's second approximation
+    h = ((a - b) / (a + b)) ** 2
+    return math.pi * (a + b) * (1.0 + 3.0 * h / (10.0 + math.sqrt(4.0 - 3.0 * h)))
+
+
+def multi_cavity(seed: int, n_cavities: int, total_nodes: int, half_width: float = 20.0,
+                 radius_range=(0.2, 1.0), aspect_range=(0.5, 1.0), separation: float = 0.5,
+                 min_nodes: int = 32, max_tries: int = 200000):
+    """Seeded non-overlapping elliptical cavities.
+
+    Centres uniform in [-half_width, half_width]^2, major semi-axis uniform in
+    ``radius_range``, aspect ratio (minor/major) uniform in ``aspect_range``,
+    orientation uniform in [0, pi).  A candidate is rejected when its
+    circumscribed circle comes within ``separation`` of an accepted one.
+    Node counts are proportional to the perimeters (largest-remainder
+    rounding, each at least ``min_nodes``) and sum to ``total_nodes``.
+
+    Returns a list of ``(n_i, 2)`` arrays.
+    """
+    rng = np.random.default_rng(seed)
+    cav = []
+    tries = 0
+    while len(cav) < n_cavities:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place cavities")
+        c = rng.uniform(-half_width, half_width, size=2)
+        a = rng.uniform(*radius_range)
+        asp = rng.uniform(*aspect_range)
+        ang = rng.uniform(0.0, math.pi)
+        ok = True
+        for (c2, a2, _, _) in cav:
+            if math.hypot(c[0] - c2[0], c[1] - c2[1]) < a + a2 + separation:
+                ok = False
+                break
+        if ok:
+            cav.append((c, a, asp, ang))
+    per = np.array([_ellipse_perimeter(a, a * asp) for (_, a, asp, _) in cav])
+    if total_nodes < min_nodes * n_cavities:
+        raise ValueError("total_nodes too small")
+    spare = total_nodes - min_nodes * n_cavities
+    share = spare * per / per.sum()
+    base = np.floor(share).astype(np.int64)
+    rem = spare - int(base.sum())
+    order = np.argsort(-(share - base), kind="stable")
+    base[order[:rem]] += 1
+    counts = base + min_nodes
+    assert int(counts.sum()) == total_nodes
+    return [ellipse(int(m), a, a * asp, center=(c[0], c[1]), angle=ang)
+            for (c, a, asp, ang), m in zip(cav, counts)]
+
+
+def plane_wave_angles(nrhs: int, step_deg: float = 2.0) -> np.ndarray:
+    """Incidence angles 0, step, 2 step, ... in radians."""
+    return np.deg2rad(step_deg * np.arange(nrhs))
+
+
+def config_small():
+    """Small validation case: circle of radius 1 with 256 nodes, lambda=2, mu=1,
+    rho=1, omega=1 (k_T a = 1), leaf 32 nodes, ID tolerance 1e-10, one plane
+    P-wave at incidence angle 0."""
+    return dict(curves=[circle(256)], lam=2.0, mu=1.0, rho=1.0, omega=1.0, tol=1e-10,
+                leaf=32, kinds=[0], angles=[0.0])
+
+
+def config_scale(nrhs: int = 180):
+    """Full-size case: ellipse with semi-axes 1 and 0.5, 131072 nodes
+    (262144 complex unknowns), lambda=2, mu=1, rho=1, omega=4 (k_T a = 4),
+    leaf 64 nodes, ID tolerance 1e-8, plane P-waves at 0, 2, ..., 358 degrees."""
+    return dict(curves=[ellipse(131072, 1.0, 0.5)], lam=2.0, mu=1.0, rho=1.0, omega=4.0,
+                tol=1e-8, leaf=64, kinds=[0] * nrhs, angles=list(plane_wave_angles(nrhs)))
