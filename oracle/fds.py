@@ -1,0 +1,358 @@
+"""The proxy-surface fast direct solver, step by step in plain FP64
+(oracle; test infrastructure only).
+
+Follows the paper's algorithm summary (Section 7.3):
+
+1. mesh and binary tree of contiguous node ranges (Section 5.1);
+2. leaf index sets J_p;
+3. upward loop over levels l = L ... l0+1:
+   (a) U_i, V_i and skeletons from proxy-surface interaction matrices and
+       interpolative decompositions by column-pivoted QR (Sections 7.1, 7.2);
+   (b) A_i^{-1} U_i, A~_i = (V_i A_i^{-1} U_i)^{-1}  (Section 6.2; A_i^{-1}
+       is applied through its LU factors, never formed);
+   (c) the parent's diagonal block from [[A~_a, R_ab], [R_ba, A~_b]] in
+       component-major order (equation of the rearrangement of A, Section 6.2);
+4. dense solve of the compressed system at level l0 (Section 6.3);
+5. downward loop x_i = A_i^{-1} f_i - A_i^{-1} U_i f~_i + A_i^{-1} U_i A~_i y_i
+   (equation of the downward conversion, Section 6.3).
+
+Readings where the paper is silent or ambiguous:
+* four skeleton index sets per cell (rows/columns x displacement component);
+  each pair (row, column) of a component shares one rank
+  k_c = max(k_row, k_col) and uses the first k_c pivots of each pivoted QR
+  (pivots are nested), so that A~_i is square;
+* the ID rank is k = #{j : |R_jj| > tol |R_11|}; the pivot is the column of
+  largest exactly recomputed remaining norm, ties within a relative 1e-12
+  going to the lowest original column index;
+* the proxy surface of a cell is a 64-gon of radius 1.5 R about the centre
+  of the bounding box of the supports of its active hats (R the largest
+  distance from that centre to those support nodes), with P1 hats and the
+  outward normal;
+* the near field of a cell at level l is every active row (column) DOF of
+  the other level-l cells whose hat support meets the proxy disk;
+* entries between overlapping supports include I0/2.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import galerkin
+from .galerkin import Boundary, Polygon
+from .kernels import Material
+
+N_PROXY = 64
+PROXY_RATIO = 1.5
+TIE = 1e-12
+
+
+# ---------------------------------------------------------------- ID / CPQR
+def cpqr(M, kmax=None):
+    """Column-pivoted Householder QR, stopped after kmax steps.
+
+    Returns (piv, R) with M[:, piv] = Q R on the computed steps; R is the
+    (steps x n) upper-trapezoidal factor in pivoted column order."""
+    A = np.array(M, dtype=np.complex128, copy=True)
+    m, n = A.shape
+    steps = min(m, n) if kmax is None else min(m, n, kmax)
+    piv = np.arange(n)
+    for j in range(steps):
+        norms = np.sum(np.abs(A[j:, j:]) ** 2, axis=0)
+        top = norms.max()
+        cand = np.nonzero(norms >= top * (1.0 - TIE))[0]
+        p = j + cand[np.argmin(piv[j + cand])]
+        if p != j:
+            A[:, [j, p]] = A[:, [p, j]]
+            piv[[j, p]] = piv[[p, j]]
+        x = A[j:, j].copy()
+        nx = np.linalg.norm(x)
+        if nx == 0.0:
+            continue
+        ph = x[0] / abs(x[0]) if x[0] != 0 else 1.0
+        alpha = -ph * nx
+        v = x
+        v[0] -= alpha
+        v /= np.linalg.norm(v)
+        A[j:, j:] -= 2.0 * np.outer(v, v.conj() @ A[j:, j:])
+        A[j + 1:, j] = 0.0
+    return piv, np.triu(A[:steps, :])
+
+
+def id_rank(R, tol):
+    d = np.abs(np.diag(R))
+    if len(d) == 0 or d[0] == 0.0:
+        return 0
+    return int(np.sum(d > tol * d[0]))
+
+
+def id_matrix(piv, R, k, n):
+    """Interpolation matrix W = [I, R1^{-1} R2] P^T (k x n) of the column ID
+    M ~ M[:, piv[:k]] W (Section 7.1)."""
+    W = np.zeros((k, n), dtype=np.complex128)
+    W[np.arange(k), piv[:k]] = 1.0
+    if k < n:
+        T = sla.solve_triangular(R[:k, :k], R[:k, k:])
+        W[:, piv[k:]] = T
+    return W
+
+
+# ---------------------------------------------------------------- tree
+@dataclass
+class Cell:
+    index: int
+    level: int
+    lo: int = 0          # leaf node range [lo, hi)
+    hi: int = 0
+    rows: np.ndarray = None    # active row DOFs (global 2t+i), component-major
+    cols: np.ndarray = None
+    A: np.ndarray = None       # diagonal block A_i
+    lu: tuple = None
+    X: np.ndarray = None       # A_i^{-1} U_i
+    At: np.ndarray = None      # A~_i
+    V: np.ndarray = None
+    rskel: np.ndarray = None   # row skeleton DOFs, component-major
+    cskel: np.ndarray = None
+    k: tuple = (0, 0)
+    ranks: dict = field(default_factory=dict)
+    centre: np.ndarray = None
+    radius: float = 0.0
+
+
+def build_tree(n_nodes: int, leaf: int):
+    """Complete binary tree with heap indexing (Section 5.1): cell 0 is the
+    root, children of i are 2i+1 and 2i+2; leaves are contiguous node ranges
+    split at midpoints."""
+    L = max(0, int(math.ceil(math.log2(n_nodes / leaf)))) if n_nodes > leaf else 0
+    cells = {0: Cell(0, 0, 0, n_nodes)}
+    for lev in range(L):
+        for i in range(2 ** lev - 1, 2 ** (lev + 1) - 1):
+            c = cells[i]
+            mid = c.lo + (c.hi - c.lo) // 2
+            cells[2 * i + 1] = Cell(2 * i + 1, lev + 1, c.lo, mid)
+            cells[2 * i + 2] = Cell(2 * i + 2, lev + 1, mid, c.hi)
+    return L, cells
+
+
+def level_cells(cells, lev):
+    return [cells[i] for i in range(2 ** lev - 1, 2 ** (lev + 1) - 1)]
+
+
+# ---------------------------------------------------------------- helpers
+def _node_neighbours(bnd: Boundary, t):
+    c, l = bnd.local(t)
+    n = np.array([bnd.polys[ci].n for ci in c])
+    o = bnd.offsets[c]
+    return o + (l - 1) % n, o + (l + 1) % n
+
+
+def _supports(bnd, nodes):
+    pv, nx = _node_neighbours(bnd, nodes)
+    return np.unique(np.concatenate([pv, nodes, nx]))
+
+
+def _seg_dist(c, a, b):
+    d = b - a
+    t = np.clip(np.einsum("ik,ik->i", c[None, :] - a, d) / np.einsum("ik,ik->i", d, d), 0.0, 1.0)
+    q = a + t[:, None] * d
+    return np.hypot(q[:, 0] - c[0], q[:, 1] - c[1])
+
+
+def _support_meets_disk(bnd, nodes, c, rho):
+    pv, nx = _node_neighbours(bnd, nodes)
+    X = bnd.nodes
+    d1 = _seg_dist(c, X[pv], X[nodes])
+    d2 = _seg_dist(c, X[nodes], X[nx])
+    return np.minimum(d1, d2) < rho
+
+
+def entries(bnd: Boundary, rows, cols, mat, proxy_rows=None, proxy_cols=None):
+    """A(rows, cols) for global DOF lists; a proxy polygon may replace the
+    boundary on the row side (proxy_rows) or the column side (proxy_cols),
+    in which case rows/cols are DOFs 2s+i of that polygon's nodes."""
+    if proxy_rows is None and proxy_cols is None:
+        return galerkin.dof_block(bnd, rows, cols, mat)
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    if proxy_rows is not None:
+        P = proxy_rows
+        cn, ci = cols // 2, cols % 2
+        out = np.zeros((len(rows), len(cols)), dtype=np.complex128)
+        cc, cl = bnd.local(cn)
+        rn, ri = rows // 2, rows % 2
+        urn, rmap = np.unique(rn, return_inverse=True)
+        for b in np.unique(cc):
+            ib = np.nonzero(cc == b)[0]
+            ucl, cmap = np.unique(cl[ib], return_inverse=True)
+            blk = galerkin.node_block(P, urn, bnd.polys[b], ucl, mat)
+            out[:, ib] = blk[rmap[:, None], cmap[None, :], ri[:, None], ci[ib][None, :]]
+        return out
+    P = proxy_cols
+    rn, ri = rows // 2, rows % 2
+    out = np.zeros((len(rows), len(cols)), dtype=np.complex128)
+    rc, rl = bnd.local(rn)
+    cn, ci = cols // 2, cols % 2
+    ucn, cmap = np.unique(cn, return_inverse=True)
+    for a in np.unique(rc):
+        ia = np.nonzero(rc == a)[0]
+        url, rmap = np.unique(rl[ia], return_inverse=True)
+        blk = galerkin.node_block(bnd.polys[a], url, P, ucn, mat)
+        out[ia, :] = blk[rmap[:, None], cmap[None, :], ri[ia][:, None], ci[None, :]]
+    return out
+
+
+def proxy_polygon(c, rho):
+    t = 2.0 * np.pi * np.arange(N_PROXY) / N_PROXY
+    return Polygon(np.stack([c[0] + rho * np.cos(t), c[1] + rho * np.sin(t)], axis=1), sign=-1)
+
+
+# ---------------------------------------------------------------- factor
+class FDS:
+    """Factorisation of the Galerkin system; ``solve`` applies it."""
+
+    def __init__(self, curves, lam, mu, rho, omega, tol, leaf=64, root_level=1, alpha=None):
+        self.mat = Material(lam, mu, rho, omega, alpha)
+        self.bnd = Boundary(curves)
+        self.tol = float(tol)
+        self.L, self.cells = build_tree(self.bnd.n_nodes, leaf)
+        self.l0 = min(root_level, self.L)
+        self._factor()
+
+    def _compress_level(self, lev):
+        bnd, mat = self.bnd, self.mat
+        cells = level_cells(self.cells, lev)
+        for c in cells:
+            act = np.unique(np.concatenate([c.rows, c.cols]) // 2)
+            sup = bnd.nodes[_supports(bnd, act)]
+            lo, hi = sup.min(axis=0), sup.max(axis=0)
+            c.centre = 0.5 * (lo + hi)
+            c.radius = float(np.max(np.hypot(sup[:, 0] - c.centre[0], sup[:, 1] - c.centre[1])))
+        for c in cells:
+            rho = PROXY_RATIO * c.radius
+            P = proxy_polygon(c.centre, rho)
+            others = [o for o in cells if o is not c]
+            near_r = np.concatenate([o.rows for o in others]) if others else np.zeros(0, np.int64)
+            near_c = np.concatenate([o.cols for o in others]) if others else np.zeros(0, np.int64)
+            near_r = near_r[_support_meets_disk(bnd, near_r // 2, c.centre, rho)] if len(near_r) else near_r
+            near_c = near_c[_support_meets_disk(bnd, near_c // 2, c.centre, rho)] if len(near_c) else near_c
+            pdofs = np.arange(2 * N_PROXY)
+            MV = entries(bnd, pdofs, c.cols, mat, proxy_rows=P)
+            MU = entries(bnd, c.rows, pdofs, mat, proxy_cols=P)
+            if len(near_r):
+                MV = np.vstack([MV, entries(bnd, near_r, c.cols, mat)])
+            if len(near_c):
+                MU = np.hstack([MU, entries(bnd, c.rows, near_c, mat)])
+            nc = [int(np.sum(c.cols % 2 == q)) for q in (0, 1)]
+            nr = [int(np.sum(c.rows % 2 == q)) for q in (0, 1)]
+            assert nc == nr
+            Vb, Ub, rsk, csk, ks = [], [], [], [], []
+            off = 0
+            for q in (0, 1):
+                cidx = np.arange(off, off + nc[q])
+                pc, Rc = cpqr(MV[:, cidx])
+                pr, Rr = cpqr(MU[cidx, :].conj().T)
+                kc, kr = id_rank(Rc, self.tol), id_rank(Rr, self.tol)
+                k = max(kc, kr)
+                c.ranks[q] = (kr, kc)
+                Vb.append(id_matrix(pc, Rc, k, nc[q]))
+                Ub.append(id_matrix(pr, Rr, k, nc[q]).conj().T)
+                csk.append(c.cols[cidx][pc[:k]])
+                rsk.append(c.rows[cidx][pr[:k]])
+                ks.append(k)
+                off += nc[q]
+            c.k = tuple(ks)
+            c.V = sla.block_diag(*Vb)
+            U = sla.block_diag(*Ub)
+            c.cskel = np.concatenate(csk)
+            c.rskel = np.concatenate(rsk)
+            c.lu = sla.lu_factor(c.A)
+            c.X = sla.lu_solve(c.lu, U)
+            S = c.V @ c.X
+            c.At = np.linalg.inv(S)
+
+    def _merge(self, lev):
+        """Diagonal blocks of the level-(lev-1) cells (rearrangement, Section 6.2)."""
+        bnd, mat = self.bnd, self.mat
+        for p in level_cells(self.cells, lev - 1):
+            a, b = self.cells[2 * p.index + 1], self.cells[2 * p.index + 2]
+            ka, kb = a.k, b.k
+            p.rows = np.concatenate([a.rskel[:ka[0]], b.rskel[:kb[0]], a.rskel[ka[0]:], b.rskel[kb[0]:]])
+            p.cols = np.concatenate([a.cskel[:ka[0]], b.cskel[:kb[0]], a.cskel[ka[0]:], b.cskel[kb[0]:]])
+            # position of each parent DOF inside its child's skeleton list
+            own_r = np.concatenate([np.zeros(ka[0], int), np.ones(kb[0], int), np.zeros(ka[1], int), np.ones(kb[1], int)])
+            pos_r = np.concatenate([np.arange(ka[0]), np.arange(kb[0]), ka[0] + np.arange(ka[1]), kb[0] + np.arange(kb[1])])
+            A = entries(bnd, p.rows, p.cols, mat)
+            ia = np.nonzero(own_r == 0)[0]
+            ib = np.nonzero(own_r == 1)[0]
+            A[np.ix_(ia, ia)] = a.At[np.ix_(pos_r[ia], pos_r[ia])]
+            A[np.ix_(ib, ib)] = b.At[np.ix_(pos_r[ib], pos_r[ib])]
+            p.A = A
+            p.own, p.pos = own_r, pos_r
+
+    def _factor(self):
+        bnd, mat = self.bnd, self.mat
+        for c in level_cells(self.cells, self.L):
+            nodes = np.arange(c.lo, c.hi)
+            c.rows = np.concatenate([2 * nodes, 2 * nodes + 1])
+            c.cols = c.rows.copy()
+            c.A = entries(bnd, c.rows, c.cols, mat)
+        for lev in range(self.L, self.l0, -1):
+            self._compress_level(lev)
+            self._merge(lev)
+        top = level_cells(self.cells, self.l0)
+        self.root_rows = np.concatenate([c.rows for c in top])
+        self.root_cols = np.concatenate([c.cols for c in top])
+        Ar = entries(bnd, self.root_rows, self.root_cols, mat)
+        o = 0
+        for c in top:
+            n = len(c.rows)
+            Ar[o:o + n, o:o + n] = c.A
+            o += n
+        self.root_A = Ar
+        self.root_lu = sla.lu_factor(Ar)
+
+    # ------------------------------------------------------------ solve
+    def solve(self, F):
+        F = np.asarray(F, dtype=np.complex128)
+        one = F.ndim == 1
+        if one:
+            F = F[:, None]
+        f = {}
+        g = {}
+        ft = {}
+        for c in level_cells(self.cells, self.L):
+            f[c.index] = F[c.rows]
+        for lev in range(self.L, self.l0, -1):
+            for c in level_cells(self.cells, lev):
+                g[c.index] = sla.lu_solve(c.lu, f[c.index])
+                ft[c.index] = c.At @ (c.V @ g[c.index])
+            for p in level_cells(self.cells, lev - 1):
+                a, b = 2 * p.index + 1, 2 * p.index + 2
+                fa, fb = ft[a], ft[b]
+                ka, kb = self.cells[a].k, self.cells[b].k
+                f[p.index] = np.vstack([fa[:ka[0]], fb[:kb[0]], fa[ka[0]:], fb[kb[0]:]])
+        top = level_cells(self.cells, self.l0)
+        xr = sla.lu_solve(self.root_lu, np.vstack([f[c.index] for c in top]))
+        x = {}
+        o = 0
+        for c in top:
+            n = len(c.cols)
+            x[c.index] = xr[o:o + n]
+            o += n
+        for lev in range(self.l0 + 1, self.L + 1):
+            for c in level_cells(self.cells, lev):
+                p = self.cells[(c.index - 1) // 2]
+                side = 0 if c.index == 2 * p.index + 1 else 1
+                sel = np.nonzero(p.own == side)[0]
+                y = np.empty((len(c.cskel), F.shape[1]), dtype=np.complex128)
+                y[p.pos[sel]] = x[p.index][sel]
+                x[c.index] = g[c.index] + c.X @ (c.At @ y - ft[c.index])
+        out = np.zeros_like(F)
+        for c in level_cells(self.cells, self.L):
+            out[c.cols] = x[c.index]
+        return out[:, 0] if one else out
+
+    def rank_table(self):
+        return {i: (c.level, c.k, c.ranks) for i, c in self.cells.items() if c.ranks}

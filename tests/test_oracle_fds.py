@@ -1,0 +1,78 @@
+"""Pins of the oracle's fast direct solver.
+
+* CPQR gives the same pivots and |diag R| as LAPACK's pivoted QR when the
+  column norms are well separated; the ID residual is at the tolerance.
+* With an ID tolerance near rounding the compressed solve reproduces the
+  dense LU solution (the elimination is exact algebra, Section 6.2).
+* The error against the dense solution falls with the tolerance, the
+  pattern of the paper's Table 1.
+* The small validation case (256-node circle, tol 1e-10) matches the dense
+  solution within 1e-9.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synthetic as sy
+from oracle import dense, fds
+
+
+def test_cpqr_matches_lapack():
+    rng = np.random.default_rng(0)
+    M = (rng.standard_normal((40, 12)) + 1j * rng.standard_normal((40, 12))) * np.logspace(0, -6, 12)
+    piv, R = fds.cpqr(M)
+    Q2, R2, p2 = sla.qr(M, pivoting=True, mode="economic")
+    assert np.array_equal(piv, p2)
+    assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(R2)), rtol=1e-10)
+
+
+def test_id_residual_at_tolerance():
+    # smooth kernel matrix: well-separated source/target clusters
+    x = np.linspace(0, 1, 60)
+    y = np.linspace(3, 4, 50)
+    M = 1.0 / (x[:, None] - y[None, :]) + 0j
+    for tol in (1e-6, 1e-10):
+        piv, R = fds.cpqr(M)
+        k = fds.id_rank(R, tol)
+        W = fds.id_matrix(piv, R, k, M.shape[1])
+        err = np.linalg.norm(M - M[:, piv[:k]] @ W, 2)
+        assert 0 < k < M.shape[1]
+        assert err < 50 * tol * np.linalg.norm(M, 2)
+
+
+MAT = dict(lam=2.0, mu=1.0, rho=1.0)
+
+
+def _dense(nodes, omega, kinds, angles):
+    return dense.dense_solve([nodes], omega=omega, kinds=kinds, angles=angles, return_matrix=True, **MAT)
+
+
+def test_exact_algebra_at_rounding_tolerance():
+    nodes = sy.ellipse(96, 1.0, 0.5)
+    X, A, F = _dense(nodes, 2.0, [0, 1], [0.0, 1.0])
+    S = fds.FDS([nodes], omega=2.0, tol=1e-15, leaf=12, root_level=1, **MAT)
+    Y = S.solve(F)
+    assert np.linalg.norm(Y - X) < 1e-11 * np.linalg.norm(X)
+
+
+def test_error_falls_with_tolerance():
+    nodes = sy.ellipse(128, 1.0, 0.5)
+    X, A, F = _dense(nodes, 3.0, [0], [0.3])
+    errs = []
+    for tol in (1e-4, 1e-7, 1e-10):
+        S = fds.FDS([nodes], omega=3.0, tol=tol, leaf=16, root_level=1, **MAT)
+        errs.append(np.linalg.norm(S.solve(F) - X) / np.linalg.norm(X))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-8
+    assert errs[1] < 1e-5
+
+
+def test_small_validation_case():
+    cfg = sy.config_small()
+    nodes = cfg["curves"][0]
+    X, A, F = _dense(nodes, cfg["omega"], cfg["kinds"], cfg["angles"])
+    S = fds.FDS(cfg["curves"], cfg["lam"], cfg["mu"], cfg["rho"], cfg["omega"], cfg["tol"],
+                leaf=cfg["leaf"], root_level=1)
+    Y = S.solve(F)
+    assert S.L == 3
+    assert np.linalg.norm(Y - X) / np.linalg.norm(X) < 1e-9
