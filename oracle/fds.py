@@ -21,7 +21,7 @@ Readings where the paper is silent or ambiguous:
   each pair (row, column) of a component shares one rank
   k_c = max(k_row, k_col) and uses the first k_c pivots of each pivoted QR
   (pivots are nested), so that A~_i is square;
-* the ID rank is k = #{j : |R_jj| > tol |R_11|}; the pivot is the column of
+* the ID rank is the first j with |R_jj| <= tol |R_11|; the pivot is the column of
   largest exactly recomputed remaining norm, ties within a relative 1e-12
   going to the lowest original column index;
 * the proxy surface of a cell is a 64-gon of radius 1.5 R about the centre
@@ -82,10 +82,13 @@ def cpqr(M, kmax=None):
 
 
 def id_rank(R, tol):
+    """Rank of the ID: the first j with |R_jj| <= tol |R_11| (the diagonal
+    of a pivoted QR with exact norms does not increase)."""
     d = np.abs(np.diag(R))
     if len(d) == 0 or d[0] == 0.0:
         return 0
-    return int(np.sum(d > tol * d[0]))
+    small = np.nonzero(d <= tol * d[0])[0]
+    return int(small[0]) if len(small) else len(d)
 
 
 def id_matrix(piv, R, k, n):
