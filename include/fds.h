@@ -1,0 +1,172 @@
+/*
+ * fds.h -- C ABI of the MI355X proxy-surface fast direct solver for 2D
+ * time-harmonic elastic scattering by traction-free cavities (Galerkin P1,
+ * Burton-Miller formulation).
+ *
+ * Method: Matsumoto & Maruyama, "Linearly scalable fast direct solver based
+ * on proxy surface method for two-dimensional elastic wave scattering by
+ * cavity".  Section references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are complex128 stored as interleaved (re, im) doubles.
+ * - Geometry (Section 4): one or more closed polygons, vertices in
+ *   counter-clockwise order, closed implicitly.  Nodes are numbered
+ *   consecutively over the curves in input order.  The normal of each
+ *   element points into the cavity (Section 2).
+ * - Unknowns: index 2 t + i holds displacement component u_{i+1} at global
+ *   node t; N_unk = 2 * (total nodes).  A DOF list is an array of such
+ *   indices.
+ * - Time factor exp(-i omega t); Hankel functions of the first kind.
+ * - Device pointers are HIP device memory (e.g. torch tensor data_ptr());
+ *   host pointers are plain host memory.  ``stream`` is a hipStream_t
+ *   (NULL = default stream).  Calls are asynchronous with respect to the
+ *   host unless stated otherwise; every entry point that returns results on
+ *   the host synchronises ``stream`` first.
+ * - Matrices passed as device pointers are column-major with a leading
+ *   dimension ``ld``.
+ * - Every entry point returns an fds_status; on error the out-parameters
+ *   are left untouched and nothing leaks.
+ */
+#ifndef FDS_H
+#define FDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fds_factor_s* fds_factor;    /* opaque; owned by the library until fds_destroy */
+typedef struct { double re, im; } fds_c64;
+
+typedef enum {
+  FDS_OK = 0,
+  FDS_EINVAL = 1,     /* bad argument: null pointer, size < 1, ld too small, omega <= 0, mu <= 0,
+                         lambda + mu <= 0, rho <= 0, tol outside (0, 1) */
+  FDS_EGEOM = 2,      /* a curve with fewer than 8 nodes, a zero-length element, clockwise curve */
+  FDS_ENOMEM = 3,     /* device or host allocation failed */
+  FDS_EHIP = 4,       /* a HIP runtime call failed */
+  FDS_ESINGULAR = 5,  /* zero or non-finite pivot in an LU factorisation */
+  FDS_ENOCONV = 6     /* iterative refinement did not reach its tolerance */
+} fds_status;
+
+typedef struct {
+  int32_t n_curves;
+  const int32_t* n_nodes;   /* host, [n_curves] */
+  const double* xy;         /* host, [2 * sum(n_nodes)]: x0, y0, x1, y1, ... ; copied by the library */
+} fds_geometry;
+
+typedef struct {
+  int32_t leaf_nodes;       /* nodes per leaf cell (Section 5.1); default 64 */
+  int32_t n_proxy;          /* vertices of each proxy polygon (Section 7.1); default 64 */
+  int32_t root_level;       /* level l0 at which the compressed system is solved (Section 7.3); default 1 */
+  int32_t reserved0;
+  double proxy_ratio;       /* proxy radius / cell radius; default 1.5 */
+  fds_c64 alpha;            /* Burton-Miller coupling; {0,0} selects i / (mu k_T) */
+  int32_t use_alpha;        /* 0: alpha = i/(mu k_T); 1: use ``alpha`` as given (0 allowed) */
+  int32_t reserved1;
+} fds_options;
+
+/* Defaults listed above. */
+int fds_options_default(fds_options* opt);
+
+/* Factor the Galerkin Burton-Miller system of the given scatterer (Sections
+ * 6 and 7; algorithm summary of Section 7.3): per-level proxy compression by
+ * column-pivoted-QR interpolative decompositions, the inverse-free upward
+ * elimination A~_i = (V_i A_i^{-1} U_i)^{-1}, and an LU of the compressed
+ * system at level l0.  ``tol`` is the ID truncation tolerance (Section 8.1).
+ * Synchronous: returns when the factor is complete.  The factor lives in
+ * device memory until fds_destroy.  opt == NULL selects the defaults. */
+int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, double rho,
+              double tol, const fds_options* opt, void* stream, fds_factor* out);
+
+/* Number of complex unknowns 2 N. */
+int fds_size(fds_factor f, int64_t* n_unknowns);
+
+/* Galerkin load vectors f^s_i = int psi^s (u^I_i + alpha (T u^I)_i) ds
+ * (Section 5.2) for unit plane waves: kind[k] = 0 for a P-wave
+ * u^I = d exp(i k_L d.x), 1 for an S-wave u^I = (J d) exp(i k_T d.x),
+ * d = (cos angle[k], sin angle[k]).  kind, angle: host [nrhs].
+ * rhs: device, column k at rhs + k * ld, ld >= N_unk. */
+int fds_rhs_plane(fds_factor f, int32_t nrhs, const int32_t* kind, const double* angle,
+                  fds_c64* rhs, int64_t ld, void* stream);
+
+/* x = A_c^{-1} rhs for nrhs right-hand sides, A_c the compressed operator:
+ * upward sweep, root solve, downward sweep (Sections 6.2, 6.3, 7.3).
+ * rhs, x: device, column-major with leading dimensions ld_rhs, ld_x
+ * (>= N_unk).  rhs is not modified.  Only one solve per factor may run at a
+ * time. */
+int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs,
+              fds_c64* x, int64_t ld_x, void* stream);
+
+typedef struct {
+  int32_t levels;           /* depth L of the tree */
+  int32_t root_level;       /* l0 */
+  int64_t n_unknowns;
+  int64_t root_size;        /* order of the compressed system at l0 */
+  int32_t max_rank;         /* largest per-component skeleton size */
+  int32_t reserved;
+  double factor_seconds;    /* wall time of fds_build */
+  double assembly_seconds;  /* GPU time in the entry-assembly kernels during the build */
+  double id_seconds;        /* GPU time in the pivoted QR / ID kernels */
+  double merge_seconds;     /* GPU time in LU / solves / GEMMs of the elimination */
+  double root_seconds;      /* GPU time of the root LU */
+  int64_t factor_bytes;     /* device bytes held by the factor */
+  int64_t kernel_evals;     /* quadrature-point kernel evaluations during the build */
+} fds_stats;
+
+int fds_get_stats(fds_factor f, fds_stats* s);
+
+/* Per-cell ranks: for cell c (heap index, Section 5.1) of every compressed
+ * level, out[4 c + 0..3] = (k_row comp 1, k_col comp 1, k_row comp 2,
+ * k_col comp 2) as found by the IDs at tolerance (before pairing); -1 for
+ * cells that were not compressed.  out: host [4 * (2^(L+1) - 1)]. */
+int fds_get_ranks(fds_factor f, int32_t* out, int64_t n_out);
+
+/* Skeleton DOF lists of one cell (global unknown indices, component-major,
+ * in pivot order).  rows/cols: host, capacity cap; n_out receives the count. */
+int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, int64_t cap, int64_t* n_out);
+
+void fds_destroy(fds_factor f);
+const char* fds_strerror(int code);
+/* Text of the last error raised on the calling thread (empty if none). */
+const char* fds_last_error(void);
+
+/* ------------------------------------------------------------------ steps
+ * Step-level entry points used to check each part of the path on its own.
+ */
+
+/* Galerkin entries A(rows, cols) of D + I0/2 + alpha N (Section 5.2) for
+ * arbitrary DOF lists of the given geometry, computed by the GPU assembly
+ * kernels.  rows, cols: host int64 [nr], [nc].  out: device, column-major
+ * nr x nc, leading dimension ld >= nr.  Synchronous. */
+int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu, double rho,
+                const fds_options* opt, int64_t nr, const int64_t* rows, int64_t nc,
+                const int64_t* cols, fds_c64* out, int64_t ld, void* stream);
+
+/* Special functions on the GPU (equation of the fundamental solution): for
+ * each x[k] > 0 (device double [n]) writes out[4 k + 0..3] = J0, J1, Y0, Y1
+ * at x, and with a = x[k], b = beta a the combinations
+ * E = (a H1(a) - b H1(b)) / a^2 and chi = H2(a) - beta^2 H2(b):
+ * outc[2 k] = E, outc[2 k + 1] = chi.  out: device double [4 n];
+ * outc: device fds_c64 [2 n].  Synchronous. */
+int fds_special_eval(int64_t n, const double* x, double beta, double* out, fds_c64* outc, void* stream);
+
+/* Batched column-pivoted QR interpolative decomposition (Section 7.1):
+ * for problem p, the m[p] x n[p] column-major matrix at a + off[p] (leading
+ * dimension m[p]) is overwritten by its partial QR; after at most kmax[p]
+ * steps (stopping early at the first |R_jj| <= tol |R_11| when stop_at_tol
+ * is set) piv (device int32, n[p] entries at pivoff[p]) holds the column
+ * order and rank[p] (device int32) the number of steps taken.  Pivot rule:
+ * largest exactly recomputed remaining column norm, ties within a relative
+ * 1e-12 going to the lowest original column.  All size/offset arrays are
+ * host int64 [np].  Synchronous. */
+int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
+                     int32_t* piv, const int64_t* pivoff, const int64_t* kmax, double tol,
+                     int32_t stop_at_tol, int32_t* rank, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDS_H */

@@ -1,0 +1,541 @@
+// Galerkin entry assembly on gfx950.
+//
+// Entries of A = D + I0/2 + alpha N (Section 5.2) between P1 hats are sums
+// of element-pair integrals.  The hypersingular operator is used in a
+// weakly singular form obtained by integrating by parts along the closed
+// polygons (the identity T^n u = 2 mu d_s(J u) + (lambda + 2 mu) n div u +
+// mu (curl u) t, t = J n, with div/curl of the fundamental solution reducing
+// to scalar Helmholtz kernels).  With Phi_k = (i/4) H0(k r),
+// Q = mu G - Phi_T I and dPhi = Phi_L - Phi_T, the entry between a test hat
+// psi on element e and a trial hat phi on element f is
+//
+//   int int psi phi' (Phi_T J - 2 Q J^T) + psi phi ((d_ny Phi_T) I + grad_y dPhi n_y^T)
+//   + alpha [ 4 mu psi' phi' J Q J^T
+//             - 2 mu psi' phi ((d_ny Phi_T) J + (J grad_y dPhi) n_y^T)
+//             + 2 mu psi phi' ((d_nx Phi_T) J - n_x (J grad_x dPhi)^T)
+//             + rho omega^2 psi phi (n_x n_y^T Phi_L + t_x t_y^T Phi_T) ],
+//
+// plus (1/2) int psi phi on coincident elements.  All kernels are at most
+// logarithmically singular on coincident elements and O(1/r) only at the
+// common vertex of adjacent elements.
+//
+// Pipeline for a batch of dense blocks ("jobs"):
+//   k_classify   every (row element, column element) pair of every job is
+//                put into one of six lists: tensor Gauss with 4, 6 or 10
+//                points per element chosen by the gap / element-length
+//                ratio, coincident, adjacent (two orientations);
+//   k_regular<Q> one thread per regular pair;
+//   k_special<C> one wavefront per singular pair (the 80 or 288 points of
+//                its rule spread over the 64 lanes, then reduced);
+//   k_gather     one thread per output entry: sum of the four element pairs
+//                of its two hats, written at its (row, column) position.
+// Pair results are 16 complex numbers [a][b][i][j] stored
+// structure-of-arrays; the gather order is fixed, so results are
+// bit-reproducible.
+#include "assembly.hpp"
+
+namespace fds {
+
+__constant__ QuadTables c_quad;
+
+struct PairAcc {
+  c64 s1[2][4];
+  c64 s2[4];
+  c64 s3[2][2][4];
+  c64 s4[2][4];
+};
+
+__device__ inline void acc_zero(PairAcc& A) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      A.s1[a][k] = cmk(0, 0);
+      A.s4[a][k] = cmk(0, 0);
+      A.s3[a][0][k] = cmk(0, 0);
+      A.s3[a][1][k] = cmk(0, 0);
+    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) A.s2[k] = cmk(0, 0);
+}
+
+// One quadrature point: d = x - y, weight w (reference weight times
+// element lengths), hat coordinates u (test) and v (trial), normals.
+__device__ inline void acc_point(const MatConst& m, double dx, double dy, double w, double u, double v,
+                                 double nx0, double nx1, double ny0, double ny1, PairAcc& A) {
+  const double r = sqrt(dx * dx + dy * dy);
+  const double ir = 1.0 / r;
+  const double e0 = dx * ir, e1 = dy * ir;
+  const double je0 = -e1, je1 = e0;
+  const double a = m.kT * r;
+  const Hankel2 h = hankel_pair(a, m.kL * r);
+  c64 E, chi;
+  e_chi(a, m.beta, h, E, chi);
+  const c64 phiT = cmk(-0.25 * h.h0a.im, 0.25 * h.h0a.re);
+  const c64 phiL = cmk(-0.25 * h.h0b.im, 0.25 * h.h0b.re);
+  const c64 q = cmk(-0.25 * m.kT * h.h1a.im, 0.25 * m.kT * h.h1a.re);   // (i/4) k_T H1(a)
+  const double eny = e0 * ny0 + e1 * ny1;
+  const double enx = e0 * nx0 + e1 * nx1;
+  const c64 dny = q * eny;          // d_{n_y} Phi_T
+  const c64 dnx = q * (-enx);       // d_{n_x} Phi_T
+  // grad_y dPhi = cg e,  cg = -(i/4) k_T a E
+  const double ka = 0.25 * m.kT * a;
+  const c64 cg = cmk(ka * E.im, -ka * E.re);
+  const c64 al = cmk(m.alpha_re, m.alpha_im);
+  const c64 K = (2.0 * m.mu) * al;             // 2 alpha mu
+  const c64 Z = mul_i(m.mu * al);              // i alpha mu
+  const c64 P = phiT - cmk(-0.5 * E.im, 0.5 * E.re);   // Phi_T - (i/2) E
+  const c64 hc = cmk(-0.5 * chi.im, 0.5 * chi.re);     // (i/2) chi
+  const c64 Kdnx = K * dnx;
+  const c64 Kcg = K * cg;
+  const double ex[2] = {e0, e1};
+  const double jex[2] = {je0, je1};
+  const double nx[2] = {nx0, nx1};
+  const double ny[2] = {ny0, ny1};
+  const double tx[2] = {-nx1, nx0};
+  const double ty[2] = {-ny1, ny0};
+  const c64 arw = (m.rw2) * al;
+  const c64 arwL = arw * phiL;
+  const c64 arwT = arw * phiT;
+  c64 M1[4], M2[4], M3[4], M4[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double Jij = (i == j) ? 0.0 : (i == 0 ? -1.0 : 1.0);
+      const double dij = (i == j) ? 1.0 : 0.0;
+      M1[2 * i + j] = Jij * P - (ex[i] * jex[j]) * hc + Jij * Kdnx + (nx[i] * jex[j]) * Kcg;
+      M2[2 * i + j] = Z * ((-dij) * E + (jex[i] * jex[j]) * chi);
+      M3[2 * i + j] = dij * dny + (ex[i] * ny[j]) * cg + (nx[i] * ny[j]) * arwL + (tx[i] * ty[j]) * arwT;
+      M4[2 * i + j] = (-1.0) * (K * (Jij * dny + (jex[i] * ny[j]) * cg));
+    }
+  const double Na[2] = {w * (1.0 - u), w * u};
+  const double Nb[2] = {1.0 - v, v};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    A.s2[k] += w * M2[k];
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+      A.s1[aa][k] += Na[aa] * M1[k];
+      A.s4[aa][k] += (w * Nb[aa]) * M4[k];
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) A.s3[aa][bb][k] += (Na[aa] * Nb[bb]) * M3[k];
+    }
+  }
+}
+
+// res[a][b][ij] = s1[a] dB[b] + dA[a] dB[b] s2 + s3[a][b] + dA[a] s4[b]
+__device__ inline c64 acc_final(const PairAcc& A, int aa, int bb, int k, const Elem& e, const Elem& f) {
+  const double dA = aa ? e.dN1 : e.dN0;
+  const double dB = bb ? f.dN1 : f.dN0;
+  return dB * A.s1[aa][k] + (dA * dB) * A.s2[k] + A.s3[aa][bb][k] + dA * A.s4[bb][k];
+}
+
+__device__ inline double seg_point_dist(double px, double py, double ax, double ay, double bx, double by) {
+  const double dx = bx - ax, dy = by - ay;
+  double t = ((px - ax) * dx + (py - ay) * dy) / (dx * dx + dy * dy);
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  const double qx = ax + t * dx - px, qy = ay + t * dy - py;
+  return sqrt(qx * qx + qy * qy);
+}
+
+__device__ inline double seg_seg_dist(const Elem& e, const Elem& f) {
+  double d = seg_point_dist(e.x0, e.y0, f.x0, f.y0, f.x1, f.y1);
+  d = fmin(d, seg_point_dist(e.x1, e.y1, f.x0, f.y0, f.x1, f.y1));
+  d = fmin(d, seg_point_dist(f.x0, f.y0, e.x0, e.y0, e.x1, e.y1));
+  d = fmin(d, seg_point_dist(f.x1, f.y1, e.x0, e.y0, e.x1, e.y1));
+  return d;
+}
+
+__device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf) {
+  if (e.poly == f.poly) {
+    if (ge == gf) return kCoinc;
+    const int n = e.npoly;
+    if (f.idx == (e.idx + 1) % n) return kAdjNext;
+    if (f.idx == (e.idx + n - 1) % n) return kAdjPrev;
+  }
+  const double d = seg_seg_dist(e, f);
+  const double hm = fmax(e.h, f.h);
+  if (d >= kFarRatio * hm) return kQ4;
+  if (d >= kNearRatio * hm) return kQ6;
+  return kQ10;
+}
+
+// ------------------------------------------------------------------ geometry
+__global__ void k_elem_geometry(const double* __restrict__ xy, const int* __restrict__ curve_of,
+                                const int* __restrict__ curve_off, const int* __restrict__ curve_n,
+                                int n_elem, Elem* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_elem) return;
+  const int c = curve_of[g];
+  const int o = curve_off[c], n = curve_n[c];
+  const int l = g - o;
+  const int g1 = o + (l + 1) % n;
+  Elem e;
+  e.x0 = xy[2 * g];
+  e.y0 = xy[2 * g + 1];
+  e.x1 = xy[2 * g1];
+  e.y1 = xy[2 * g1 + 1];
+  const double dx = e.x1 - e.x0, dy = e.y1 - e.y0;
+  e.h = sqrt(dx * dx + dy * dy);
+  const double tx = dx / e.h, ty = dy / e.h;
+  // n = J tau (into the cavity); t = J n = -tau;  d_s N0 = 1/h, d_s N1 = -1/h
+  e.nx = -ty;
+  e.ny = tx;
+  e.dN0 = 1.0 / e.h;
+  e.dN1 = -1.0 / e.h;
+  e.poly = c;
+  e.idx = l;
+  e.npoly = n;
+  e.pad = 0;
+  out[g] = e;
+}
+
+// proxy polygons: n_proxy vertices c + rho (cos 2 pi s/n, sin 2 pi s/n),
+// outward normal n = -J tau, t = J n = tau: d_s N0 = -1/h, d_s N1 = 1/h.
+__global__ void k_proxy_elems(const double* __restrict__ crd, int n_cells, int n_proxy, int poly_base,
+                              Elem* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_cells * n_proxy) return;
+  const int c = g / n_proxy, s = g % n_proxy;
+  const double cx = crd[3 * c], cy = crd[3 * c + 1], rho = crd[3 * c + 2];
+  const double t0 = 2.0 * kPi * s / n_proxy;
+  const double t1 = 2.0 * kPi * ((s + 1) % n_proxy) / n_proxy;
+  double s0, c0, s1, c1;
+  sincos(t0, &s0, &c0);
+  sincos(t1, &s1, &c1);
+  Elem e;
+  e.x0 = cx + rho * c0;
+  e.y0 = cy + rho * s0;
+  e.x1 = cx + rho * c1;
+  e.y1 = cy + rho * s1;
+  const double dx = e.x1 - e.x0, dy = e.y1 - e.y0;
+  e.h = sqrt(dx * dx + dy * dy);
+  const double tx = dx / e.h, ty = dy / e.h;
+  e.nx = ty;
+  e.ny = -tx;
+  e.dN0 = -1.0 / e.h;
+  e.dN1 = 1.0 / e.h;
+  e.poly = poly_base + c;
+  e.idx = s;
+  e.npoly = n_proxy;
+  e.pad = 0;
+  out[g] = e;
+}
+
+// ------------------------------------------------------------------ classify
+__global__ void k_classify(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
+                           const int* __restrict__ elist, const Elem* __restrict__ elems,
+                           unsigned long long* __restrict__ lists, int64_t list_cap,
+                           unsigned int* __restrict__ counters) {
+  const Tile t = tiles[blockIdx.x];
+  const Job jb = jobs[t.job];
+  const int li = threadIdx.x;
+  int cls = -1;
+  int64_t p = t.start + li;
+  if (li < t.count) {
+    const int ie = (int)(p / jb.nce), je = (int)(p % jb.nce);
+    const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
+    cls = classify_pair(elems[ge], elems[gf], ge, gf);
+  }
+  const unsigned long long key = ((unsigned long long)(unsigned)t.job << 32) | (unsigned long long)p;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < kNumClass; ++c) {
+    const unsigned long long mask = __ballot(cls == c);
+    if (mask == 0ull) continue;
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[c], (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    if (cls == c) {
+      const unsigned long long below = mask & ((1ull << lane) - 1ull);
+      const int64_t slot = (int64_t)base + __popcll(below);
+      if (slot < list_cap) lists[c * list_cap + slot] = key;
+    }
+  }
+}
+
+__device__ inline void decode(unsigned long long key, const Job* jobs, const int* elist, Job& jb, int& ie, int& je,
+                              int& ge, int& gf) {
+  const int job = (int)(key >> 32);
+  const int64_t p = (int64_t)(key & 0xffffffffull);
+  jb = jobs[job];
+  ie = (int)(p / jb.nce);
+  je = (int)(p % jb.nce);
+  ge = elist[jb.re_off + ie];
+  gf = elist[jb.ce_off + je];
+}
+
+// ------------------------------------------------------------------ regular pairs
+template <int Q>
+__global__ void __launch_bounds__(128) k_regular(const unsigned long long* __restrict__ list, int count,
+                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                                 const Elem* __restrict__ elems, MatConst m,
+                                                 c64* __restrict__ res, int64_t np) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  Job jb;
+  int ie, je, ge, gf;
+  decode(list[t], jobs, elist, jb, ie, je, ge, gf);
+  const Elem e = elems[ge];
+  const Elem f = elems[gf];
+  const double* g = (Q == 4) ? c_quad.g4 : (Q == 6 ? c_quad.g6 : c_quad.g10);
+  const double* wq = (Q == 4) ? c_quad.w4 : (Q == 6 ? c_quad.w6 : c_quad.w10);
+  PairAcc A;
+  acc_zero(A);
+  const double ox = e.x0 - f.x0, oy = e.y0 - f.y0;
+  const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
+  const double bx = f.x1 - f.x0, by = f.y1 - f.y0;
+  const double hh = e.h * f.h;
+  for (int i = 0; i < Q; ++i) {
+    const double u = g[i];
+    const double wu = wq[i] * hh;
+    for (int j = 0; j < Q; ++j) {
+      const double v = g[j];
+      const double dx = ox + u * ax - v * bx;
+      const double dy = oy + u * ay - v * by;
+      acc_point(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, A);
+    }
+  }
+  const int64_t slot = jb.pair_off + (int64_t)ie * jb.nce + je;
+#pragma unroll
+  for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) res[(aa * 8 + bb * 4 + k) * np + slot] = acc_final(A, aa, bb, k, e, f);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ------------------------------------------------------------------ singular pairs
+template <int C>
+__global__ void __launch_bounds__(256) k_special(const unsigned long long* __restrict__ list, int count,
+                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                                 const Elem* __restrict__ elems, MatConst m,
+                                                 c64* __restrict__ res, int64_t np) {
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wid >= count) return;
+  Job jb;
+  int ie, je, ge, gf;
+  decode(list[wid], jobs, elist, jb, ie, je, ge, gf);
+  const Elem e = elems[ge];
+  const Elem f = elems[gf];
+  PairAcc A;
+  acc_zero(A);
+  const double hh = e.h * f.h;
+  if (C == kCoinc) {
+    const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
+    for (int p = lane; p < kNCoincPts; p += 64) {
+      const double off = c_quad.coff[p];
+      acc_point(m, off * ax, off * ay, c_quad.cw[p] * hh, c_quad.cu[p], c_quad.cv[p], e.nx, e.ny, f.nx, f.ny, A);
+    }
+  } else {
+    // vectors from the shared vertex to the far ends of e and f
+    double Ax, Ay, Bx, By;
+    if (C == kAdjNext) {   // shared vertex = end of e = start of f
+      Ax = e.x0 - e.x1;
+      Ay = e.y0 - e.y1;
+      Bx = f.x1 - f.x0;
+      By = f.y1 - f.y0;
+    } else {               // shared vertex = start of e = end of f
+      Ax = e.x1 - e.x0;
+      Ay = e.y1 - e.y0;
+      Bx = f.x0 - f.x1;
+      By = f.y0 - f.y1;
+    }
+    for (int p = lane; p < kNAdjPts; p += 64) {
+      const double up = c_quad.au[p], vp = c_quad.av[p];
+      const double u = (C == kAdjNext) ? 1.0 - up : up;
+      const double v = (C == kAdjNext) ? vp : 1.0 - vp;
+      acc_point(m, up * Ax - vp * Bx, up * Ay - vp * By, c_quad.aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny, A);
+    }
+  }
+  const int64_t slot = jb.pair_off + (int64_t)ie * jb.nce + je;
+#pragma unroll
+  for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        c64 val = acc_final(A, aa, bb, k, e, f);
+        val.re = wave_sum(val.re);
+        val.im = wave_sum(val.im);
+        if (C == kCoinc && (k == 0 || k == 3)) {
+          // (1/2) int psi phi on the coincident element: h/3 on the diagonal, h/6 off it
+          val.re += 0.5 * e.h * (aa == bb ? (1.0 / 3.0) : (1.0 / 6.0));
+        }
+        if (lane == 0) res[(aa * 8 + bb * 4 + k) * np + slot] = val;
+      }
+}
+
+// ------------------------------------------------------------------ gather
+__global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
+                         const Dof* __restrict__ dofs, const int* __restrict__ pos,
+                         const c64* __restrict__ res, int64_t np, c64* __restrict__ out) {
+  const Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count) return;
+  const Job jb = jobs[t.job];
+  const int64_t item = t.start + threadIdx.x;
+  const int r = (int)(item % jb.nrd), c = (int)(item / jb.nrd);
+  const Dof dr = dofs[jb.rd_off + r];
+  const Dof dc = dofs[jb.cd_off + c];
+  const int k = dr.comp * 2 + dc.comp;
+  c64 s = cmk(0, 0);
+  // node is local node 1 of eL and local node 0 of eR
+  const int ier[2] = {dr.eL, dr.eR}, ia[2] = {1, 0};
+  const int jec[2] = {dc.eL, dc.eR}, jb2[2] = {1, 0};
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int64_t slot = jb.pair_off + (int64_t)ier[x] * jb.nce + jec[y];
+      s += res[(ia[x] * 8 + jb2[y] * 4 + k) * np + slot];
+    }
+  const int64_t rp = jb.rpos_off >= 0 ? pos[jb.rpos_off + r] : r;
+  const int64_t cp = jb.cpos_off >= 0 ? pos[jb.cpos_off + c] : c;
+  out[jb.out_off + rp * jb.rs + cp * jb.cs] = s;
+}
+
+// ------------------------------------------------------------------ load vectors
+// f[2 t + i] for node t: both elements of its hat, 6-point Gauss each.
+__global__ void k_rhs_plane(const Elem* __restrict__ elems, const int* __restrict__ prev_elem, int n_nodes,
+                            MatConst m, double lam, int nrhs, const int* __restrict__ kind,
+                            const double* __restrict__ ang, c64* __restrict__ out, int64_t ld) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (t >= n_nodes || k >= nrhs) return;
+  double sd, cd;
+  sincos(ang[k], &sd, &cd);
+  const int kd = kind[k];
+  const double wn = kd == 0 ? m.kL : m.kT;
+  const c64 al = cmk(m.alpha_re, m.alpha_im);
+  c64 f0 = cmk(0, 0), f1 = cmk(0, 0);
+  const int els[2] = {prev_elem[t], t};
+  for (int s = 0; s < 2; ++s) {
+    const Elem e = elems[els[s]];
+    for (int q = 0; q < 6; ++q) {
+      const double u = c_quad.rg[q];
+      const double N = s == 0 ? u : 1.0 - u;     // node is local 1 of the previous element
+      const double w = c_quad.rw[q] * e.h * N;
+      const double x = e.x0 + u * (e.x1 - e.x0), y = e.y0 + u * (e.y1 - e.y0);
+      double sp, cp;
+      sincos(wn * (x * cd + y * sd), &sp, &cp);
+      const c64 E = cmk(cp, sp);
+      const double nd = e.nx * cd + e.ny * sd;
+      c64 u0, u1, t0, t1;
+      if (kd == 0) {
+        // u = d E;  T u = i k_L E (lambda n + 2 mu (n.d) d)
+        u0 = cd * E;
+        u1 = sd * E;
+        const c64 ikE = mul_i(m.kL * E);
+        t0 = (lam * e.nx + 2.0 * m.mu * nd * cd) * ikE;
+        t1 = (lam * e.ny + 2.0 * m.mu * nd * sd) * ikE;
+      } else {
+        // u = (J d) E;  T u = i k_T mu E ((n.d) J d + (n.J d) d)
+        const double dpx = -sd, dpy = cd;
+        const double ndp = e.nx * dpx + e.ny * dpy;
+        u0 = dpx * E;
+        u1 = dpy * E;
+        const c64 ikE = mul_i((m.kT * m.mu) * E);
+        t0 = (nd * dpx + ndp * cd) * ikE;
+        t1 = (nd * dpy + ndp * sd) * ikE;
+      }
+      f0 += w * (u0 + al * t0);
+      f1 += w * (u1 + al * t1);
+    }
+  }
+  out[(int64_t)k * ld + 2 * t] = f0;
+  out[(int64_t)k * ld + 2 * t + 1] = f1;
+}
+
+// ------------------------------------------------------------------ special-function probe
+__global__ void k_special_eval(const double* __restrict__ x, int64_t n, double beta, double* __restrict__ out,
+                               c64* __restrict__ outc) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double j0, j1, y0, y1;
+  bessel_jy01(x[k], j0, j1, y0, y1);
+  out[4 * k] = j0;
+  out[4 * k + 1] = j1;
+  out[4 * k + 2] = y0;
+  out[4 * k + 3] = y1;
+  const Hankel2 h = hankel_pair(x[k], beta * x[k]);
+  c64 E, chi;
+  e_chi(x[k], beta, h, E, chi);
+  outc[2 * k] = E;
+  outc[2 * k + 1] = chi;
+}
+
+// ------------------------------------------------------------------ host launchers
+void upload_quad_tables(const QuadTables& q) { FDS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_quad), &q, sizeof(q))); }
+
+void launch_elem_geometry(const double* xy, const int* curve_of, const int* curve_off, const int* curve_n,
+                          int n_elem, Elem* out, hipStream_t s) {
+  k_elem_geometry<<<(n_elem + 255) / 256, 256, 0, s>>>(xy, curve_of, curve_off, curve_n, n_elem, out);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_proxy_elems(const double* crd, int n_cells, int n_proxy, int poly_base, Elem* out, hipStream_t s) {
+  const int n = n_cells * n_proxy;
+  if (n == 0) return;
+  k_proxy_elems<<<(n + 255) / 256, 256, 0, s>>>(crd, n_cells, n_proxy, poly_base, out);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int* elist, const Elem* elems,
+                     unsigned long long* lists, int64_t cap, unsigned int* counters, hipStream_t s) {
+  if (n_tiles == 0) return;
+  k_classify<<<n_tiles, 256, 0, s>>>(tiles, jobs, elist, elems, lists, cap, counters);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
+                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s) {
+  if (counts[kQ4]) {
+    k_regular<4><<<(counts[kQ4] + 127) / 128, 128, 0, s>>>(lists + kQ4 * cap, counts[kQ4], jobs, elist, elems, m, res, np);
+  }
+  if (counts[kQ6]) {
+    k_regular<6><<<(counts[kQ6] + 127) / 128, 128, 0, s>>>(lists + kQ6 * cap, counts[kQ6], jobs, elist, elems, m, res, np);
+  }
+  if (counts[kQ10]) {
+    k_regular<10><<<(counts[kQ10] + 127) / 128, 128, 0, s>>>(lists + kQ10 * cap, counts[kQ10], jobs, elist, elems, m, res, np);
+  }
+  if (counts[kCoinc]) {
+    k_special<kCoinc><<<(counts[kCoinc] + 3) / 4, 256, 0, s>>>(lists + kCoinc * cap, counts[kCoinc], jobs, elist, elems, m, res, np);
+  }
+  if (counts[kAdjNext]) {
+    k_special<kAdjNext><<<(counts[kAdjNext] + 3) / 4, 256, 0, s>>>(lists + kAdjNext * cap, counts[kAdjNext], jobs, elist, elems, m, res, np);
+  }
+  if (counts[kAdjPrev]) {
+    k_special<kAdjPrev><<<(counts[kAdjPrev] + 3) / 4, 256, 0, s>>>(lists + kAdjPrev * cap, counts[kAdjPrev], jobs, elist, elems, m, res, np);
+  }
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_gather(const Tile* tiles, int n_tiles, const Job* jobs, const Dof* dofs, const int* pos,
+                   const c64* res, int64_t np, c64* out, hipStream_t s) {
+  if (n_tiles == 0) return;
+  k_gather<<<n_tiles, 256, 0, s>>>(tiles, jobs, dofs, pos, res, np, out);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_rhs_plane(const Elem* elems, const int* prev_elem, int n_nodes, const MatConst& m, double lam, int nrhs,
+                      const int* kind, const double* ang, c64* out, int64_t ld, hipStream_t s) {
+  dim3 grid((n_nodes + 255) / 256, nrhs);
+  k_rhs_plane<<<grid, 256, 0, s>>>(elems, prev_elem, n_nodes, m, lam, nrhs, kind, ang, out, ld);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_special_eval(const double* x, int64_t n, double beta, double* out, c64* outc, hipStream_t s) {
+  k_special_eval<<<(int)((n + 255) / 256), 256, 0, s>>>(x, n, beta, out, outc);
+  FDS_HIP(hipGetLastError());
+}
+
+}  // namespace fds

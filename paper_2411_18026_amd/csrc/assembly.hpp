@@ -1,0 +1,54 @@
+// Launchers of the Galerkin assembly kernels (assembly.hip) and the host
+// side that batches dense blocks into jobs.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace fds {
+
+void upload_quad_tables(const QuadTables& q);
+void launch_elem_geometry(const double* xy, const int* curve_of, const int* curve_off, const int* curve_n,
+                          int n_elem, Elem* out, hipStream_t s);
+void launch_proxy_elems(const double* crd, int n_cells, int n_proxy, int poly_base, Elem* out, hipStream_t s);
+void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int* elist, const Elem* elems,
+                     unsigned long long* lists, int64_t cap, unsigned int* counters, hipStream_t s);
+void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
+                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s);
+void launch_gather(const Tile* tiles, int n_tiles, const Job* jobs, const Dof* dofs, const int* pos,
+                   const c64* res, int64_t np, c64* out, hipStream_t s);
+void launch_rhs_plane(const Elem* elems, const int* prev_elem, int n_nodes, const MatConst& m, double lam, int nrhs,
+                      const int* kind, const double* ang, c64* out, int64_t ld, hipStream_t s);
+void launch_special_eval(const double* x, int64_t n, double beta, double* out, c64* outc, hipStream_t s);
+
+QuadTables make_quad_tables();
+
+// One side of a block: an element list and the DOFs on it.
+struct Side {
+  std::vector<int> elems;   // global element ids
+  std::vector<Dof> dofs;    // eL, eR index into ``elems``
+};
+
+// A dense block request: out[out_off + rpos[r] * rs + cpos[c] * cs] = A(r, c).
+struct BlockReq {
+  Side rows, cols;
+  int64_t out_off = 0;
+  int64_t rs = 1, cs = 0;
+  std::vector<int> rpos, cpos;   // empty = identity
+};
+
+class DeviceArena;
+
+// Batches block requests, runs classify / pair / gather kernels, writes the
+// blocks into ``out`` (a device array).  Splits the batch so that the pair
+// scratch stays below ``max_pairs`` element pairs.
+struct AssemblyStats {
+  double seconds = 0.0;
+  int64_t evals = 0;
+};
+
+void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
+                     hipStream_t s, AssemblyStats* st, int64_t max_pairs = 24000000);
+
+}  // namespace fds

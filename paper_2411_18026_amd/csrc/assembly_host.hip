@@ -1,0 +1,195 @@
+// Host side of the Galerkin assembly: quadrature tables and batching of
+// dense block requests into classify / pair / gather launches.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "assembly.hpp"
+#include "devmem.hpp"
+
+namespace fds {
+
+// n-point Gauss-Legendre rule on [0, 1] (Newton iteration on P_n).
+static void gauss_legendre01(int n, double* x01, double* w01) {
+  std::vector<double> xs(n), ws(n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+    }
+    xs[i] = x;
+    ws[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  // ascending order on [0, 1]
+  for (int i = 0; i < n; ++i) {
+    x01[i] = 0.5 * (1.0 + xs[n - 1 - i]);
+    w01[i] = 0.5 * ws[n - 1 - i];
+  }
+}
+
+QuadTables make_quad_tables() {
+  QuadTables q{};
+  gauss_legendre01(4, q.g4, q.w4);
+  gauss_legendre01(6, q.g6, q.w6);
+  gauss_legendre01(10, q.g10, q.w10);
+  gauss_legendre01(6, q.rg, q.rw);
+  // coincident: d = s^P on each triangle of the square, 2-point Gauss along the diagonal
+  {
+    double s[kQCoinc], ws[kQCoinc], g2[2], w2[2];
+    gauss_legendre01(kQCoinc, s, ws);
+    gauss_legendre01(2, g2, w2);
+    int p = 0;
+    for (int i = 0; i < kQCoinc; ++i) {
+      const double d = std::pow(s[i], kPCoinc);
+      const double wd = ws[i] * kPCoinc * std::pow(s[i], kPCoinc - 1);
+      const double ell = 1.0 - d;
+      for (int k = 0; k < 2; ++k) {
+        const double t = ell * g2[k];
+        const double w = wd * ell * w2[k];
+        q.cu[p] = t + d;
+        q.cv[p] = t;
+        q.cw[p] = w;
+        q.coff[p] = d;
+        ++p;
+        q.cu[p] = t;
+        q.cv[p] = t + d;
+        q.cw[p] = w;
+        q.coff[p] = -d;
+        ++p;
+      }
+    }
+  }
+  // adjacent: Duffy map of both triangles about the shared vertex, xi = s^P
+  {
+    double s[kQAdj], ws[kQAdj], eta[kQAdj], we[kQAdj];
+    gauss_legendre01(kQAdj, s, ws);
+    gauss_legendre01(kQAdj, eta, we);
+    const int half = kQAdj * kQAdj;
+    for (int i = 0; i < kQAdj; ++i) {
+      const double xi = std::pow(s[i], kPAdj);
+      const double wxi = ws[i] * kPAdj * std::pow(s[i], kPAdj - 1);
+      for (int j = 0; j < kQAdj; ++j) {
+        const int p = i * kQAdj + j;
+        const double w = wxi * we[j] * xi;
+        q.au[p] = xi;
+        q.av[p] = xi * eta[j];
+        q.aw[p] = w;
+        q.au[half + p] = xi * eta[j];
+        q.av[half + p] = xi;
+        q.aw[half + p] = w;
+      }
+    }
+  }
+  return q;
+}
+
+static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts, kNAdjPts};
+
+void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
+                     hipStream_t s, AssemblyStats* st, int64_t max_pairs) {
+  size_t i0 = 0;
+  hipEvent_t ev0, ev1;
+  FDS_HIP(hipEventCreate(&ev0));
+  FDS_HIP(hipEventCreate(&ev1));
+  while (i0 < reqs.size()) {
+    // batch [i0, i1)
+    size_t i1 = i0;
+    int64_t np = 0;
+    while (i1 < reqs.size()) {
+      const int64_t p = (int64_t)reqs[i1].rows.elems.size() * (int64_t)reqs[i1].cols.elems.size();
+      if (i1 > i0 && np + p > max_pairs) break;
+      np += p;
+      ++i1;
+    }
+    std::vector<Job> jobs;
+    std::vector<int> elist, pos;
+    std::vector<Dof> dofs;
+    std::vector<Tile> ptiles, otiles;
+    int64_t pair_off = 0;
+    for (size_t r = i0; r < i1; ++r) {
+      const BlockReq& q = reqs[r];
+      Job j{};
+      j.pair_off = pair_off;
+      j.out_off = q.out_off;
+      j.rs = q.rs;
+      j.cs = q.cs;
+      j.re_off = (int)elist.size();
+      j.nre = (int)q.rows.elems.size();
+      elist.insert(elist.end(), q.rows.elems.begin(), q.rows.elems.end());
+      j.ce_off = (int)elist.size();
+      j.nce = (int)q.cols.elems.size();
+      elist.insert(elist.end(), q.cols.elems.begin(), q.cols.elems.end());
+      j.rd_off = (int)dofs.size();
+      j.nrd = (int)q.rows.dofs.size();
+      dofs.insert(dofs.end(), q.rows.dofs.begin(), q.rows.dofs.end());
+      j.cd_off = (int)dofs.size();
+      j.ncd = (int)q.cols.dofs.size();
+      dofs.insert(dofs.end(), q.cols.dofs.begin(), q.cols.dofs.end());
+      j.rpos_off = -1;
+      j.cpos_off = -1;
+      if (!q.rpos.empty()) {
+        j.rpos_off = (int)pos.size();
+        pos.insert(pos.end(), q.rpos.begin(), q.rpos.end());
+      }
+      if (!q.cpos.empty()) {
+        j.cpos_off = (int)pos.size();
+        pos.insert(pos.end(), q.cpos.begin(), q.cpos.end());
+      }
+      const int jid = (int)jobs.size();
+      jobs.push_back(j);
+      const int64_t npj = (int64_t)j.nre * j.nce;
+      for (int64_t a = 0; a < npj; a += 256) ptiles.push_back(Tile{jid, (int)std::min<int64_t>(256, npj - a), a});
+      const int64_t noj = (int64_t)j.nrd * j.ncd;
+      for (int64_t a = 0; a < noj; a += 256) otiles.push_back(Tile{jid, (int)std::min<int64_t>(256, noj - a), a});
+      pair_off += npj;
+    }
+    if (pos.empty()) pos.push_back(0);
+    DevBuf<Job> d_jobs(jobs);
+    DevBuf<int> d_elist(elist), d_pos(pos);
+    DevBuf<Dof> d_dofs(dofs);
+    DevBuf<Tile> d_pt(ptiles), d_ot(otiles);
+    DevBuf<unsigned long long> d_lists((size_t)kNumClass * np);
+    DevBuf<unsigned int> d_cnt(kNumClass);
+    DevBuf<c64> d_res((size_t)16 * np);
+    FDS_HIP(hipMemsetAsync(d_cnt.p, 0, kNumClass * sizeof(unsigned), s));
+    FDS_HIP(hipEventRecord(ev0, s));
+    launch_classify(d_pt.p, (int)ptiles.size(), d_jobs.p, d_elist.p, d_elems, d_lists.p, np, d_cnt.p, s);
+    unsigned int cnt[kNumClass];
+    FDS_HIP(hipMemcpyAsync(cnt, d_cnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    launch_pairs(d_lists.p, np, cnt, d_jobs.p, d_elist.p, d_elems, m, d_res.p, np, s);
+    launch_gather(d_ot.p, (int)otiles.size(), d_jobs.p, d_dofs.p, d_pos.p, d_res.p, np, d_out, s);
+    FDS_HIP(hipEventRecord(ev1, s));
+    FDS_HIP(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    FDS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (st) {
+      st->seconds += 1e-3 * ms;
+      for (int c = 0; c < kNumClass; ++c) st->evals += (int64_t)cnt[c] * kPointsPerClass[c];
+    }
+    i0 = i1;
+  }
+  FDS_HIP(hipEventDestroy(ev0));
+  FDS_HIP(hipEventDestroy(ev1));
+}
+
+}  // namespace fds

@@ -1,0 +1,96 @@
+// Shared device/host declarations of the solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "special.hpp"
+
+namespace fds {
+
+// A straight element of a polygon: from (x0, y0) to (x1, y1).  ``nx, ny`` is
+// its unit normal (into the cavity for a boundary curve, outward for a proxy
+// circle) and dN0, dN1 the constant tangential derivatives (along t = J n)
+// of the two hat functions restricted to it.
+struct Elem {
+  double x0, y0, x1, y1;
+  double h, nx, ny, dN0, dN1;
+  int poly;     // polygon id (boundary curve or proxy)
+  int idx;      // index of the element within its polygon
+  int npoly;    // number of elements of the polygon
+  int pad;
+};
+
+// Material constants needed by the kernels.
+struct MatConst {
+  double kT, kL, beta, mu, rw2;   // rw2 = rho omega^2
+  double alpha_re, alpha_im;
+};
+
+// One dense block A(rows, cols) to assemble.  Each side is a list of
+// elements (global ids into the element table) and a list of DOFs; a DOF
+// refers to the two elements of its hat (as indices into the side's element
+// list: ``eL`` the element the node ends, ``eR`` the element it starts) and
+// a displacement component.  Element-pair results for the job live at
+// pair_off + ie * nce + je.  The output entry for DOFs (r, c) goes to
+// out[out_off + rpos(r) * rs + cpos(c) * cs], rpos = identity when
+// rpos_off < 0.
+struct Job {
+  int64_t pair_off;
+  int64_t out_off;
+  int64_t rs, cs;
+  int re_off, nre;
+  int ce_off, nce;
+  int rd_off, nrd;
+  int cd_off, ncd;
+  int rpos_off, cpos_off;
+};
+
+struct Dof {
+  int eL, eR, comp, pad;
+};
+
+// Work tiles: a contiguous range [start, start+count) of a job's items
+// (element pairs or output entries).
+struct Tile {
+  int job;
+  int count;
+  int64_t start;
+};
+
+enum PairClass : int { kQ4 = 0, kQ6 = 1, kQ10 = 2, kCoinc = 3, kAdjNext = 4, kAdjPrev = 5, kNumClass = 6 };
+
+// quadrature constants (filled at library initialisation)
+constexpr int kQCoinc = 20;
+constexpr int kPCoinc = 6;
+constexpr int kQAdj = 12;
+constexpr int kPAdj = 4;
+constexpr int kNCoincPts = 4 * kQCoinc;
+constexpr int kNAdjPts = 2 * kQAdj * kQAdj;
+constexpr double kFarRatio = 8.0;
+constexpr double kNearRatio = 2.0;
+
+struct QuadTables {
+  double g4[4], w4[4], g6[6], w6[6], g10[10], w10[10];
+  double cu[kNCoincPts], cv[kNCoincPts], cw[kNCoincPts], coff[kNCoincPts];
+  double au[kNAdjPts], av[kNAdjPts], aw[kNAdjPts];
+  double rg[6], rw[6];   // load-vector rule
+};
+
+class Error : public std::runtime_error {
+ public:
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define FDS_HIP(call)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw ::fds::Error(4, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+}  // namespace fds

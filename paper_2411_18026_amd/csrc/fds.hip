@@ -1,0 +1,1248 @@
+// Host driver and C ABI of the proxy-surface fast direct solver.
+//
+// Algorithm summary (Section 7.3):
+//   1-2. binary tree of contiguous node ranges and leaf index sets (Section 5.1);
+//   3.   for l = L ... l0+1: proxy-surface interaction matrices, IDs by
+//        column-pivoted QR giving U_i, V_i and the skeletons (Sections 7.1,
+//        7.2); A_i^{-1} U_i through the LU of A_i, A~_i = (V_i A_i^{-1} U_i)^{-1}
+//        (Section 6.2); parent diagonal blocks from [[A~_a, R_ab], [R_ba, A~_b]]
+//        in component-major order (rearrangement of Section 6.2);
+//   4.   LU of the compressed system at level l0;
+//   5.   the solve: upward sweep g_i = A_i^{-1} f_i, f~_i = A~_i V_i g_i,
+//        root solve, downward sweep x_i = g_i + A_i^{-1} U_i (A~_i y_i - f~_i)
+//        (equation of the downward conversion, Section 6.3).
+//
+// Readings where the paper leaves a choice:
+//   * four skeleton sets per cell (rows / columns x component); rows and
+//     columns of a component share the rank k_c = max(k_row, k_col) and take
+//     the first k_c pivots of their pivoted QRs, so that A~_i is square;
+//   * ID rank: first j with |R_jj| <= tol |R_11|;
+//   * proxy: n_proxy-gon (default 64) of radius 1.5 R about the centre of the
+//     bounding box of the supports of the cell's active hats, outward normal;
+//   * near field: active DOFs of the other cells of the level whose hat
+//     support meets the proxy disk.
+// The host keeps only index bookkeeping (tree, DOF lists, near sets);
+// every arithmetic step runs in the device kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fds.h"
+#include "assembly.hpp"
+#include "devmem.hpp"
+#include "linalg.hpp"
+
+namespace fds {
+
+static bool g_quad_ready = false;
+static void ensure_quad() {
+  if (!g_quad_ready) {
+    upload_quad_tables(make_quad_tables());
+    g_quad_ready = true;
+  }
+}
+
+struct Geometry {
+  int n_nodes = 0, n_curves = 0;
+  std::vector<int> curve_off, curve_n, curve_of;
+  std::vector<double> xy;
+  std::vector<int> prev_node, next_node;   // neighbours along the curve
+  double hmax = 0.0;
+};
+
+static int make_geometry(const fds_geometry* g, Geometry& G) {
+  if (!g || g->n_curves < 1 || !g->n_nodes || !g->xy) return FDS_EINVAL;
+  G.n_curves = g->n_curves;
+  G.curve_off.resize(g->n_curves);
+  G.curve_n.resize(g->n_curves);
+  int64_t tot = 0;
+  for (int c = 0; c < g->n_curves; ++c) {
+    if (g->n_nodes[c] < 8) return FDS_EGEOM;
+    G.curve_off[c] = (int)tot;
+    G.curve_n[c] = g->n_nodes[c];
+    tot += g->n_nodes[c];
+  }
+  if (tot > (1 << 29)) return FDS_EINVAL;
+  G.n_nodes = (int)tot;
+  G.xy.assign(g->xy, g->xy + 2 * tot);
+  G.curve_of.resize(tot);
+  G.prev_node.resize(tot);
+  G.next_node.resize(tot);
+  for (int c = 0; c < g->n_curves; ++c) {
+    const int o = G.curve_off[c], n = G.curve_n[c];
+    double area = 0.0;
+    for (int l = 0; l < n; ++l) {
+      const int t = o + l, t1 = o + (l + 1) % n;
+      G.curve_of[t] = c;
+      G.prev_node[t] = o + (l + n - 1) % n;
+      G.next_node[t] = t1;
+      const double dx = G.xy[2 * t1] - G.xy[2 * t], dy = G.xy[2 * t1 + 1] - G.xy[2 * t + 1];
+      const double h = std::sqrt(dx * dx + dy * dy);
+      if (!(h > 0.0) || !std::isfinite(h)) return FDS_EGEOM;
+      G.hmax = std::max(G.hmax, h);
+      area += G.xy[2 * t] * G.xy[2 * t1 + 1] - G.xy[2 * t1] * G.xy[2 * t + 1];
+    }
+    if (area <= 0.0) return FDS_EGEOM;
+  }
+  return FDS_OK;
+}
+
+static MatConst make_mat(double omega, double lam, double mu, double rho, const fds_options& o, double* alpha_re,
+                         double* alpha_im) {
+  MatConst m{};
+  const double cL = std::sqrt((lam + 2.0 * mu) / rho), cT = std::sqrt(mu / rho);
+  m.kL = omega / cL;
+  m.kT = omega / cT;
+  m.beta = m.kL / m.kT;
+  m.mu = mu;
+  m.rw2 = rho * omega * omega;
+  if (o.use_alpha) {
+    m.alpha_re = o.alpha.re;
+    m.alpha_im = o.alpha.im;
+  } else {
+    m.alpha_re = 0.0;
+    m.alpha_im = 1.0 / (mu * m.kT);
+  }
+  if (alpha_re) *alpha_re = m.alpha_re;
+  if (alpha_im) *alpha_im = m.alpha_im;
+  return m;
+}
+
+// device copy of the boundary elements (+ room for proxies)
+struct DevGeom {
+  DevBuf<double> xy;
+  DevBuf<int> curve_of, curve_off, curve_n, prev_elem;
+  DevBuf<Elem> elems;
+  int n_gamma = 0;
+  int64_t cap = 0;
+  void init(const Geometry& G, int64_t proxy_cap, hipStream_t s) {
+    n_gamma = G.n_nodes;
+    xy = DevBuf<double>(G.xy);
+    curve_of = DevBuf<int>(G.curve_of);
+    curve_off = DevBuf<int>(G.curve_off);
+    curve_n = DevBuf<int>(G.curve_n);
+    std::vector<int> pe(G.n_nodes);
+    for (int t = 0; t < G.n_nodes; ++t) pe[t] = G.prev_node[t];   // element ending at t starts at prev(t)
+    prev_elem = DevBuf<int>(pe);
+    cap = G.n_nodes + proxy_cap;
+    elems = DevBuf<Elem>((size_t)cap);
+    launch_elem_geometry(xy.p, curve_of.p, curve_off.p, curve_n.p, G.n_nodes, elems.p, s);
+  }
+};
+
+// Side of a block from a list of boundary DOFs (2 t + i).
+static Side side_from_dofs(const Geometry& G, const std::vector<int64_t>& dofs) {
+  Side sd;
+  std::unordered_map<int, int> idx;
+  idx.reserve(dofs.size() * 2);
+  auto get = [&](int e) {
+    auto it = idx.find(e);
+    if (it != idx.end()) return it->second;
+    const int k = (int)sd.elems.size();
+    sd.elems.push_back(e);
+    idx.emplace(e, k);
+    return k;
+  };
+  sd.dofs.reserve(dofs.size());
+  for (int64_t d : dofs) {
+    const int t = (int)(d >> 1);
+    const int eL = get(G.prev_node[t]);   // element (prev(t), t)
+    const int eR = get(t);                // element (t, next(t))
+    sd.dofs.push_back(Dof{eL, eR, (int)(d & 1), 0});
+  }
+  return sd;
+}
+
+// Append the DOFs of a proxy polygon (all n_proxy nodes, component-major) to a side.
+static void side_add_proxy(Side& sd, int elem_base, int n_proxy) {
+  const int b = (int)sd.elems.size();
+  for (int s = 0; s < n_proxy; ++s) sd.elems.push_back(elem_base + s);
+  for (int c = 0; c < 2; ++c)
+    for (int s = 0; s < n_proxy; ++s) sd.dofs.push_back(Dof{b + (s + n_proxy - 1) % n_proxy, b + s, c, 0});
+}
+
+static void side_append(const Geometry& G, Side& sd, const std::vector<int64_t>& dofs) {
+  Side add = side_from_dofs(G, dofs);
+  const int b = (int)sd.elems.size();
+  sd.elems.insert(sd.elems.end(), add.elems.begin(), add.elems.end());
+  for (auto d : add.dofs) sd.dofs.push_back(Dof{d.eL + b, d.eR + b, d.comp, 0});
+}
+
+// ------------------------------------------------------------------ factor data
+struct CellLevel {
+  int lev = 0, n = 0;                            // cells 2^lev - 1 + q, q < n
+  std::vector<std::vector<int64_t>> rows, cols;  // active DOFs (component-major)
+  std::vector<int> b, n0;                        // sizes, # component-0 DOFs
+  std::vector<int64_t> a_off;                    // A_i / LU(A_i) (ld = b)
+  std::vector<int64_t> piv_off;
+  int64_t a_tot = 0, piv_tot = 0;
+  // compression results (levels > l0)
+  std::vector<int> k0, k1, r;
+  std::vector<int> kr0, kc0, kr1, kc1;           // ranks at tolerance
+  std::vector<std::vector<int64_t>> rskel, cskel;
+  std::vector<int64_t> x_off, at_off, v_off, s_piv_off;
+  int64_t x_tot = 0, at_tot = 0, v_tot = 0, s_piv_tot = 0;
+  DevBuf<c64> A, X, At, V;
+  DevBuf<int> piv, s_piv;
+  // solve layout: level vector of height B = sum b, skeleton height R = sum r
+  std::vector<int64_t> f_off, t_off;
+  int64_t B = 0, R = 0;
+  // parent position of each skeleton entry (set when the parent is built)
+  std::vector<std::vector<int>> ppos;            // per cell: position in parent's rows of its skeleton rows
+};
+
+// Compressed system at l0: diagonal blocks are the cells' A_i, the rest are
+// original entries; one LU.
+struct Root {
+  int n = 0;
+  DevBuf<c64> A;
+  DevBuf<int> piv;
+};
+
+}  // namespace fds
+
+struct fds_factor_s {
+  fds::Geometry G;
+  fds::DevGeom DG;
+  fds::MatConst m{};
+  fds_options opt{};
+  double tol = 0, lam = 0, mu = 0, rho = 0, omega = 0;
+  int L = 0, l0 = 0;
+  std::vector<fds::CellLevel> levels;   // index = level
+  fds::Root root;
+  fds_stats st{};
+  hipStream_t stream = nullptr;
+};
+
+namespace fds {
+
+using Factor = fds_factor_s;
+
+static void build_tree(Factor& F) {
+  const int N = F.G.n_nodes, leaf = F.opt.leaf_nodes;
+  int L = 0;
+  while (((int64_t)leaf << L) < N) ++L;
+  F.L = L;
+  F.l0 = std::min(F.opt.root_level, L);
+  F.levels.resize(L + 1);
+  // node ranges by midpoint splits
+  std::vector<std::pair<int, int>> cur{{0, N}};
+  for (int lev = 0; lev < L; ++lev) {
+    std::vector<std::pair<int, int>> nxt;
+    for (auto& pr : cur) {
+      const int mid = pr.first + (pr.second - pr.first) / 2;
+      nxt.push_back({pr.first, mid});
+      nxt.push_back({mid, pr.second});
+    }
+    cur.swap(nxt);
+  }
+  CellLevel& lv = F.levels[L];
+  lv.lev = L;
+  lv.n = (int)cur.size();
+  lv.rows.resize(lv.n);
+  for (int q = 0; q < lv.n; ++q) {
+    auto& rw = lv.rows[q];
+    for (int c = 0; c < 2; ++c)
+      for (int t = cur[q].first; t < cur[q].second; ++t) rw.push_back(2 * (int64_t)t + c);
+  }
+  lv.cols = lv.rows;
+}
+
+static void layout_blocks(CellLevel& lv) {
+  lv.b.resize(lv.n);
+  lv.n0.resize(lv.n);
+  lv.a_off.resize(lv.n);
+  lv.piv_off.resize(lv.n);
+  lv.f_off.resize(lv.n);
+  lv.a_tot = lv.piv_tot = lv.B = 0;
+  for (int q = 0; q < lv.n; ++q) {
+    lv.b[q] = (int)lv.rows[q].size();
+    int c0 = 0;
+    for (auto d : lv.cols[q]) c0 += (d & 1) == 0;
+    lv.n0[q] = c0;
+    lv.a_off[q] = lv.a_tot;
+    lv.a_tot += (int64_t)lv.b[q] * lv.b[q];
+    lv.piv_off[q] = lv.piv_tot;
+    lv.piv_tot += lv.b[q];
+    lv.f_off[q] = lv.B;
+    lv.B += lv.b[q];
+  }
+  lv.A = DevBuf<c64>((size_t)std::max<int64_t>(lv.a_tot, 1));
+  lv.piv = DevBuf<int>((size_t)std::max<int64_t>(lv.piv_tot, 1));
+}
+
+static void check_info(const DevBuf<int>& info, size_t n, hipStream_t s) {
+  auto h = info.download(n, s);
+  for (int v : h)
+    if (v) throw Error(FDS_ESINGULAR, "singular block in LU");
+}
+
+// support nodes of a DOF list (prev, node, next)
+static void cell_disk(const Geometry& G, const std::vector<int64_t>& rows, const std::vector<int64_t>& cols,
+                      double& cx, double& cy, double& R) {
+  double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300;
+  std::vector<int> pts;
+  pts.reserve(3 * (rows.size() + cols.size()));
+  auto add = [&](int64_t d) {
+    const int t = (int)(d >> 1);
+    pts.push_back(G.prev_node[t]);
+    pts.push_back(t);
+    pts.push_back(G.next_node[t]);
+  };
+  for (auto d : rows) add(d);
+  for (auto d : cols) add(d);
+  for (int t : pts) {
+    lox = std::min(lox, G.xy[2 * t]);
+    hix = std::max(hix, G.xy[2 * t]);
+    loy = std::min(loy, G.xy[2 * t + 1]);
+    hiy = std::max(hiy, G.xy[2 * t + 1]);
+  }
+  cx = 0.5 * (lox + hix);
+  cy = 0.5 * (loy + hiy);
+  R = 0.0;
+  for (int t : pts) R = std::max(R, std::hypot(G.xy[2 * t] - cx, G.xy[2 * t + 1] - cy));
+}
+
+static double seg_dist(double px, double py, double ax, double ay, double bx, double by) {
+  const double dx = bx - ax, dy = by - ay;
+  double t = ((px - ax) * dx + (py - ay) * dy) / (dx * dx + dy * dy);
+  t = std::min(1.0, std::max(0.0, t));
+  return std::hypot(ax + t * dx - px, ay + t * dy - py);
+}
+
+// does the hat support of node t meet the disk (c, rho)?
+static bool support_meets(const Geometry& G, int t, double cx, double cy, double rho) {
+  const int p = G.prev_node[t], n = G.next_node[t];
+  const double* X = G.xy.data();
+  return seg_dist(cx, cy, X[2 * p], X[2 * p + 1], X[2 * t], X[2 * t + 1]) < rho ||
+         seg_dist(cx, cy, X[2 * t], X[2 * t + 1], X[2 * n], X[2 * n + 1]) < rho;
+}
+
+// uniform grid over the nodes for near-field queries
+struct NodeGrid {
+  double x0 = 0, y0 = 0, hx = 1;
+  int nx = 1, ny = 1;
+  std::vector<int> start, items;
+  void build(const Geometry& G, double cell) {
+    double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300;
+    for (int t = 0; t < G.n_nodes; ++t) {
+      lox = std::min(lox, G.xy[2 * t]);
+      hix = std::max(hix, G.xy[2 * t]);
+      loy = std::min(loy, G.xy[2 * t + 1]);
+      hiy = std::max(hiy, G.xy[2 * t + 1]);
+    }
+    hx = std::max(cell, 1e-12);
+    nx = std::max(1, std::min(4096, (int)std::ceil((hix - lox) / hx) + 1));
+    ny = std::max(1, std::min(4096, (int)std::ceil((hiy - loy) / hx) + 1));
+    hx = std::max(hx, std::max((hix - lox) / (nx - 0.5), (hiy - loy) / (ny - 0.5)));
+    x0 = lox;
+    y0 = loy;
+    std::vector<int> cnt((size_t)nx * ny + 1, 0);
+    std::vector<int> bin(G.n_nodes);
+    for (int t = 0; t < G.n_nodes; ++t) {
+      const int ix = std::min(nx - 1, (int)((G.xy[2 * t] - x0) / hx));
+      const int iy = std::min(ny - 1, (int)((G.xy[2 * t + 1] - y0) / hx));
+      bin[t] = iy * nx + ix;
+      cnt[bin[t] + 1]++;
+    }
+    for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+    start = cnt;
+    items.resize(G.n_nodes);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int t = 0; t < G.n_nodes; ++t) items[fill[bin[t]]++] = t;
+  }
+  template <typename F>
+  void query(double cx, double cy, double rad, F&& f) const {
+    const int ix0 = std::max(0, (int)std::floor((cx - rad - x0) / hx));
+    const int ix1 = std::min(nx - 1, (int)std::floor((cx + rad - x0) / hx));
+    const int iy0 = std::max(0, (int)std::floor((cy - rad - y0) / hx));
+    const int iy1 = std::min(ny - 1, (int)std::floor((cy + rad - y0) / hx));
+    for (int iy = iy0; iy <= iy1; ++iy)
+      for (int ix = ix0; ix <= ix1; ++ix) {
+        const int b = iy * nx + ix;
+        for (int k = start[b]; k < start[b + 1]; ++k) f(items[k]);
+      }
+  }
+};
+
+static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  FDS_HIP(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+static void compress_level(Factor& F, int lev) {
+  const Geometry& G = F.G;
+  CellLevel& lv = F.levels[lev];
+  hipStream_t s = F.stream;
+  const int np = F.opt.n_proxy;
+  const int n = lv.n;
+  // proxy disks
+  std::vector<double> crd(3 * n);
+  double maxrho = 0.0;
+  for (int q = 0; q < n; ++q) {
+    double cx, cy, R;
+    cell_disk(G, lv.rows[q], lv.cols[q], cx, cy, R);
+    crd[3 * q] = cx;
+    crd[3 * q + 1] = cy;
+    crd[3 * q + 2] = F.opt.proxy_ratio * R;
+    maxrho = std::max(maxrho, crd[3 * q + 2]);
+  }
+  // near sets via a node grid
+  std::vector<int> row_owner(2 * (size_t)G.n_nodes, -1), col_owner(2 * (size_t)G.n_nodes, -1);
+  for (int q = 0; q < n; ++q) {
+    for (auto d : lv.rows[q]) row_owner[d] = q;
+    for (auto d : lv.cols[q]) col_owner[d] = q;
+  }
+  NodeGrid grid;
+  grid.build(G, std::max(maxrho, 4.0 * G.hmax));
+  std::vector<std::vector<int64_t>> near_r(n), near_c(n);
+  std::vector<char> seen(G.n_nodes, 0);
+  for (int q = 0; q < n; ++q) {
+    const double cx = crd[3 * q], cy = crd[3 * q + 1], rho = crd[3 * q + 2];
+    std::vector<int> cand;
+    grid.query(cx, cy, rho + G.hmax, [&](int t) {
+      if (!seen[t]) {
+        seen[t] = 1;
+        cand.push_back(t);
+      }
+    });
+    for (int t : cand) seen[t] = 0;
+    std::sort(cand.begin(), cand.end());
+    for (int t : cand) {
+      if (!support_meets(G, t, cx, cy, rho)) continue;
+      for (int c = 0; c < 2; ++c) {
+        const int64_t d = 2 * (int64_t)t + c;
+        if (row_owner[d] >= 0 && row_owner[d] != q) near_r[q].push_back(d);
+        if (col_owner[d] >= 0 && col_owner[d] != q) near_c[q].push_back(d);
+      }
+    }
+  }
+  // proxy elements
+  const int64_t pbase = F.DG.n_gamma;
+  if (pbase + (int64_t)n * np > F.DG.cap) throw Error(FDS_ENOMEM, "proxy element table too small");
+  {
+    DevBuf<double> dcrd(crd);
+    launch_proxy_elems(dcrd.p, n, np, G.n_curves, F.DG.elems.p + pbase, s);
+    FDS_HIP(hipStreamSynchronize(s));
+  }
+  // interaction matrices: MV = A(proxy + near rows, cols) and MUt = A(rows, proxy + near cols)^T
+  std::vector<int64_t> mv_off(n), mu_off(n);
+  std::vector<int> mv_m(n), mu_m(n);
+  int64_t mv_tot = 0, mu_tot = 0;
+  for (int q = 0; q < n; ++q) {
+    mv_m[q] = 2 * np + (int)near_r[q].size();
+    mu_m[q] = 2 * np + (int)near_c[q].size();
+    mv_off[q] = mv_tot;
+    mv_tot += (int64_t)mv_m[q] * lv.b[q];
+    mu_off[q] = mu_tot;
+    mu_tot += (int64_t)mu_m[q] * lv.b[q];
+  }
+  DevBuf<c64> MV((size_t)mv_tot), MU((size_t)mu_tot);
+  std::vector<BlockReq> reqs;
+  reqs.reserve(2 * n);
+  for (int q = 0; q < n; ++q) {
+    BlockReq a;
+    side_add_proxy(a.rows, (int)(pbase + (int64_t)q * np), np);
+    side_append(G, a.rows, near_r[q]);
+    a.cols = side_from_dofs(G, lv.cols[q]);
+    a.out_off = mv_off[q];
+    a.rs = 1;
+    a.cs = mv_m[q];
+    reqs.push_back(std::move(a));
+  }
+  AssemblyStats ast;
+  assemble_blocks(reqs, F.DG.elems.p, F.m, MV.p, s, &ast);
+  reqs.clear();
+  for (int q = 0; q < n; ++q) {
+    BlockReq a;
+    a.rows = side_from_dofs(G, lv.rows[q]);
+    side_add_proxy(a.cols, (int)(pbase + (int64_t)q * np), np);
+    side_append(G, a.cols, near_c[q]);
+    a.out_off = mu_off[q];
+    a.rs = mu_m[q];   // transposed storage
+    a.cs = 1;
+    reqs.push_back(std::move(a));
+  }
+  assemble_blocks(reqs, F.DG.elems.p, F.m, MU.p, s, &ast);
+  reqs.clear();
+  F.st.assembly_seconds += ast.seconds;
+  F.st.kernel_evals += ast.evals;
+
+  // IDs: problem 4q + {0: V comp0, 1: V comp1, 2: U comp0, 3: U comp1}
+  hipEvent_t e0, e1;
+  FDS_HIP(hipEventCreate(&e0));
+  FDS_HIP(hipEventCreate(&e1));
+  FDS_HIP(hipEventRecord(e0, s));
+  std::vector<CpqrDesc> qd(4 * n);
+  std::vector<int64_t> pvo(4 * n);
+  int64_t pv_tot = 0;
+  for (int q = 0; q < n; ++q) {
+    const int b = lv.b[q], c0 = lv.n0[q], c1 = b - c0;
+    const int ncs[2] = {c0, c1};
+    for (int k = 0; k < 4; ++k) {
+      const bool isV = k < 2;
+      const int comp = k & 1;
+      CpqrDesc d{};
+      const int mrows = isV ? mv_m[q] : mu_m[q];
+      d.a_off = (isV ? mv_off[q] : mu_off[q]) + (int64_t)(comp ? c0 : 0) * mrows;
+      d.m = mrows;
+      d.n = ncs[comp];
+      d.lda = mrows;
+      d.piv_off = pv_tot;
+      pvo[4 * q + k] = pv_tot;
+      pv_tot += d.n;
+      d.k_start = 0;
+      d.k_end = std::min(d.m, d.n);
+      d.stop_at_tol = 1;
+      qd[4 * q + k] = d;
+    }
+  }
+  // U-problems live in MU, V-problems in MV: run as two batches
+  std::vector<CpqrDesc> qv, qu;
+  for (int q = 0; q < n; ++q) {
+    qv.push_back(qd[4 * q]);
+    qv.push_back(qd[4 * q + 1]);
+    qu.push_back(qd[4 * q + 2]);
+    qu.push_back(qd[4 * q + 3]);
+  }
+  DevBuf<int> dpiv((size_t)std::max<int64_t>(pv_tot, 1)), drank_v(2 * n), drank_u(2 * n);
+  launch_cpqr(qv, MV.p, dpiv.p, F.tol, drank_v.p, s);
+  launch_cpqr(qu, MU.p, dpiv.p, F.tol, drank_u.p, s);
+  auto rv = drank_v.download(2 * n, s);
+  auto ru = drank_u.download(2 * n, s);
+  lv.kc0.resize(n);
+  lv.kc1.resize(n);
+  lv.kr0.resize(n);
+  lv.kr1.resize(n);
+  lv.k0.resize(n);
+  lv.k1.resize(n);
+  lv.r.resize(n);
+  std::vector<CpqrDesc> ev, eu;
+  std::vector<int> ev_i, eu_i;
+  for (int q = 0; q < n; ++q) {
+    lv.kc0[q] = rv[2 * q];
+    lv.kc1[q] = rv[2 * q + 1];
+    lv.kr0[q] = ru[2 * q];
+    lv.kr1[q] = ru[2 * q + 1];
+    const int kk[2] = {std::max(lv.kc0[q], lv.kr0[q]), std::max(lv.kc1[q], lv.kr1[q])};
+    for (int comp = 0; comp < 2; ++comp) {
+      CpqrDesc dv = qv[2 * q + comp];
+      if (rv[2 * q + comp] < kk[comp]) {
+        dv.k_start = rv[2 * q + comp];
+        dv.k_end = kk[comp];
+        dv.stop_at_tol = 0;
+        ev.push_back(dv);
+        ev_i.push_back(2 * q + comp);
+      }
+      CpqrDesc du = qu[2 * q + comp];
+      if (ru[2 * q + comp] < kk[comp]) {
+        du.k_start = ru[2 * q + comp];
+        du.k_end = kk[comp];
+        du.stop_at_tol = 0;
+        eu.push_back(du);
+        eu_i.push_back(2 * q + comp);
+      }
+    }
+    lv.k0[q] = kk[0];
+    lv.k1[q] = kk[1];
+  }
+  if (!ev.empty()) {
+    DevBuf<int> tmp(ev.size());
+    launch_cpqr(ev, MV.p, dpiv.p, F.tol, tmp.p, s);
+    auto h = tmp.download(ev.size(), s);
+    for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
+  }
+  if (!eu.empty()) {
+    DevBuf<int> tmp(eu.size());
+    launch_cpqr(eu, MU.p, dpiv.p, F.tol, tmp.p, s);
+    auto h = tmp.download(eu.size(), s);
+    for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[i];
+  }
+  for (int q = 0; q < n; ++q) {
+    // a zero pivot can end a QR early: never use more pivots than both reached
+    lv.k0[q] = std::min(lv.k0[q], std::min(rv[2 * q], ru[2 * q]));
+    lv.k1[q] = std::min(lv.k1[q], std::min(rv[2 * q + 1], ru[2 * q + 1]));
+    lv.r[q] = lv.k0[q] + lv.k1[q];
+  }
+  auto hpiv = dpiv.download(pv_tot, s);
+  // skeletons, layouts
+  lv.rskel.assign(n, {});
+  lv.cskel.assign(n, {});
+  lv.x_off.resize(n);
+  lv.at_off.resize(n);
+  lv.v_off.resize(n);
+  lv.s_piv_off.resize(n);
+  lv.t_off.resize(n);
+  lv.x_tot = lv.at_tot = lv.v_tot = lv.s_piv_tot = lv.R = 0;
+  for (int q = 0; q < n; ++q) {
+    const int c0 = lv.n0[q];
+    const int kk[2] = {lv.k0[q], lv.k1[q]};
+    for (int comp = 0; comp < 2; ++comp) {
+      const int base = comp ? c0 : 0;
+      const int* pc = hpiv.data() + pvo[4 * q + comp];
+      const int* pr = hpiv.data() + pvo[4 * q + 2 + comp];
+      for (int j = 0; j < kk[comp]; ++j) {
+        lv.cskel[q].push_back(lv.cols[q][base + pc[j]]);
+        lv.rskel[q].push_back(lv.rows[q][base + pr[j]]);
+      }
+    }
+    const int b = lv.b[q], r = lv.r[q];
+    lv.x_off[q] = lv.x_tot;
+    lv.x_tot += (int64_t)b * r;
+    lv.at_off[q] = lv.at_tot;
+    lv.at_tot += (int64_t)r * r;
+    lv.v_off[q] = lv.v_tot;
+    lv.v_tot += (int64_t)r * b;
+    lv.s_piv_off[q] = lv.s_piv_tot;
+    lv.s_piv_tot += r;
+    lv.t_off[q] = lv.R;
+    lv.R += r;
+  }
+  lv.X = DevBuf<c64>((size_t)std::max<int64_t>(lv.x_tot, 1));
+  lv.At = DevBuf<c64>((size_t)std::max<int64_t>(lv.at_tot, 1));
+  lv.V = DevBuf<c64>((size_t)std::max<int64_t>(lv.v_tot, 1));
+  lv.s_piv = DevBuf<int>((size_t)std::max<int64_t>(lv.s_piv_tot, 1));
+  FDS_HIP(hipMemsetAsync(lv.X.p, 0, lv.X.n * sizeof(c64), s));
+  FDS_HIP(hipMemsetAsync(lv.V.p, 0, lv.V.n * sizeof(c64), s));
+  // V_i (r x b) from the column IDs; U_i = X_i (b x r) from the row IDs (W^T)
+  std::vector<InterpDesc> iv, iu;
+  for (int q = 0; q < n; ++q) {
+    const int b = lv.b[q], r = lv.r[q], c0 = lv.n0[q];
+    const int kk[2] = {lv.k0[q], lv.k1[q]};
+    for (int comp = 0; comp < 2; ++comp) {
+      if (kk[comp] == 0) continue;
+      const int roff = comp ? kk[0] : 0;   // skeleton offset
+      const int coff = comp ? c0 : 0;      // DOF offset
+      InterpDesc a{};
+      a.a_off = qv[2 * q + comp].a_off;
+      a.piv_off = qv[2 * q + comp].piv_off;
+      a.n = qv[2 * q + comp].n;
+      a.lda = qv[2 * q + comp].lda;
+      a.k = kk[comp];
+      a.d_off = lv.v_off[q] + roff + (int64_t)coff * r;
+      a.d_ld = r;
+      a.transpose = 0;
+      iv.push_back(a);
+      InterpDesc u{};
+      u.a_off = qu[2 * q + comp].a_off;
+      u.piv_off = qu[2 * q + comp].piv_off;
+      u.n = qu[2 * q + comp].n;
+      u.lda = qu[2 * q + comp].lda;
+      u.k = kk[comp];
+      u.d_off = lv.x_off[q] + coff + (int64_t)roff * b;
+      u.d_ld = b;
+      u.transpose = 1;
+      iu.push_back(u);
+    }
+  }
+  launch_interp(iv, MV.p, dpiv.p, lv.V.p, s);
+  launch_interp(iu, MU.p, dpiv.p, lv.X.p, s);
+  FDS_HIP(hipEventRecord(e1, s));
+  FDS_HIP(hipEventSynchronize(e1));
+  F.st.id_seconds += 1e-3 * elapsed_ms(e0, e1);
+
+  // elimination: LU(A_i); X_i = A_i^{-1} U_i; S_i = V_i X_i; A~_i = S_i^{-1}
+  FDS_HIP(hipEventRecord(e0, s));
+  std::vector<LUDesc> ld(n);
+  std::vector<SolveDesc> sd;
+  for (int q = 0; q < n; ++q) {
+    ld[q] = LUDesc{lv.a_off[q], lv.piv_off[q], lv.b[q], lv.b[q]};
+    if (lv.r[q] > 0)
+      sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
+  }
+  DevBuf<int> info(n);
+  launch_lu(ld, lv.A.p, lv.piv.p, info.p, s);
+  check_info(info, n, s);
+  launch_lu_solve(sd, lv.A.p, lv.piv.p, lv.X.p, s);
+  DevBuf<c64> S((size_t)std::max<int64_t>(lv.at_tot, 1));
+  std::vector<GemmDesc> gd;
+  for (int q = 0; q < n; ++q) {
+    if (lv.r[q] == 0) continue;
+    GemmDesc g{};
+    g.a_off = lv.v_off[q];
+    g.b_off = lv.x_off[q];
+    g.c_off = lv.at_off[q];
+    g.m = lv.r[q];
+    g.n = lv.r[q];
+    g.k = lv.b[q];
+    g.lda = lv.r[q];
+    g.ldb = lv.b[q];
+    g.ldc = lv.r[q];
+    g.alpha_re = 1.0;
+    gd.push_back(g);
+  }
+  launch_gemm(gd, lv.V.p, lv.X.p, S.p, 0, s);
+  std::vector<LUDesc> lds;
+  std::vector<SolveDesc> sds;
+  std::vector<int64_t> id_off;
+  std::vector<int> id_n;
+  for (int q = 0; q < n; ++q) {
+    if (lv.r[q] == 0) continue;
+    lds.push_back(LUDesc{lv.at_off[q], lv.s_piv_off[q], lv.r[q], lv.r[q]});
+    sds.push_back(SolveDesc{lv.at_off[q], lv.s_piv_off[q], lv.at_off[q], lv.r[q], lv.r[q], lv.r[q], lv.r[q]});
+    id_off.push_back(lv.at_off[q]);
+    id_n.push_back(lv.r[q]);
+  }
+  DevBuf<int> info2(std::max<size_t>(lds.size(), 1));
+  launch_lu(lds, S.p, lv.s_piv.p, info2.p, s);
+  check_info(info2, lds.size(), s);
+  {
+    DevBuf<int64_t> doff(id_off);
+    DevBuf<int> dn(id_n);
+    launch_fill_identity((int64_t)id_off.size(), doff.p, dn.p, dn.p, lv.At.p, s);
+    FDS_HIP(hipStreamSynchronize(s));
+  }
+  // A~ = S^{-1}: the LU of S (held in S) applied to the identity in At
+  launch_lu_solve(sds, S.p, lv.s_piv.p, lv.At.p, s);
+  FDS_HIP(hipEventRecord(e1, s));
+  FDS_HIP(hipEventSynchronize(e1));
+  F.st.merge_seconds += 1e-3 * elapsed_ms(e0, e1);
+  FDS_HIP(hipEventDestroy(e0));
+  FDS_HIP(hipEventDestroy(e1));
+  int mr = 0;
+  for (int q = 0; q < n; ++q) mr = std::max(mr, std::max(lv.k0[q], lv.k1[q]));
+  F.st.max_rank = std::max(F.st.max_rank, mr);
+}
+
+// Parent diagonal blocks of level lev-1 from level lev (rearrangement, Section 6.2).
+static void merge_to_parent(Factor& F, int lev) {
+  const Geometry& G = F.G;
+  CellLevel& ch = F.levels[lev];
+  CellLevel& pa = F.levels[lev - 1];
+  hipStream_t s = F.stream;
+  pa.lev = lev - 1;
+  pa.n = ch.n / 2;
+  pa.rows.assign(pa.n, {});
+  pa.cols.assign(pa.n, {});
+  ch.ppos.assign(ch.n, {});
+  for (int p = 0; p < pa.n; ++p) {
+    const int a = 2 * p, b = 2 * p + 1;
+    const int ka0 = ch.k0[a], kb0 = ch.k0[b], ka1 = ch.k1[a], kb1 = ch.k1[b];
+    auto& R = pa.rows[p];
+    auto& C = pa.cols[p];
+    auto app = [](std::vector<int64_t>& dst, const std::vector<int64_t>& src, int o, int k) {
+      dst.insert(dst.end(), src.begin() + o, src.begin() + o + k);
+    };
+    app(R, ch.rskel[a], 0, ka0);
+    app(R, ch.rskel[b], 0, kb0);
+    app(R, ch.rskel[a], ka0, ka1);
+    app(R, ch.rskel[b], kb0, kb1);
+    app(C, ch.cskel[a], 0, ka0);
+    app(C, ch.cskel[b], 0, kb0);
+    app(C, ch.cskel[a], ka0, ka1);
+    app(C, ch.cskel[b], kb0, kb1);
+    // parent position of each child skeleton entry (same pattern for rows and cols)
+    auto& pa_ = ch.ppos[a];
+    auto& pb_ = ch.ppos[b];
+    for (int j = 0; j < ka0; ++j) pa_.push_back(j);
+    for (int j = 0; j < ka1; ++j) pa_.push_back(ka0 + kb0 + j);
+    for (int j = 0; j < kb0; ++j) pb_.push_back(ka0 + j);
+    for (int j = 0; j < kb1; ++j) pb_.push_back(ka0 + kb0 + ka1 + j);
+  }
+  layout_blocks(pa);
+  // diagonal sub-blocks: A~ of the children
+  std::vector<int> pos;
+  std::vector<ScatterDesc> sc;
+  std::vector<BlockReq> reqs;
+  for (int p = 0; p < pa.n; ++p) {
+    for (int side = 0; side < 2; ++side) {
+      const int c = 2 * p + side;
+      if (ch.r[c] == 0) continue;
+      ScatterDesc d{};
+      d.src_off = ch.at_off[c];
+      d.src_ld = ch.r[c];
+      d.nr = ch.r[c];
+      d.nc = ch.r[c];
+      d.dst_off = pa.a_off[p];
+      d.dst_ld = pa.b[p];
+      d.rpos_off = (int)pos.size();
+      pos.insert(pos.end(), ch.ppos[c].begin(), ch.ppos[c].end());
+      d.cpos_off = d.rpos_off;
+      sc.push_back(d);
+    }
+    // off-diagonal: R_ab = A(rskel_a, cskel_b), R_ba = A(rskel_b, cskel_a)
+    for (int side = 0; side < 2; ++side) {
+      const int a = 2 * p + side, b = 2 * p + 1 - side;
+      if (ch.r[a] == 0 || ch.r[b] == 0) continue;
+      BlockReq q;
+      q.rows = side_from_dofs(G, ch.rskel[a]);
+      q.cols = side_from_dofs(G, ch.cskel[b]);
+      q.out_off = pa.a_off[p];
+      q.rs = 1;
+      q.cs = pa.b[p];
+      q.rpos = ch.ppos[a];
+      q.cpos = ch.ppos[b];
+      reqs.push_back(std::move(q));
+    }
+  }
+  if (pos.empty()) pos.push_back(0);
+  DevBuf<int> dpos(pos);
+  launch_scatter(sc, dpos.p, ch.At.p, pa.A.p, s);
+  AssemblyStats ast;
+  assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, s, &ast);
+  F.st.assembly_seconds += ast.seconds;
+  F.st.kernel_evals += ast.evals;
+}
+
+// Leaf diagonal blocks.
+static void assemble_leaves(Factor& F) {
+  CellLevel& lv = F.levels[F.L];
+  layout_blocks(lv);
+  std::vector<BlockReq> reqs;
+  reqs.reserve(lv.n);
+  for (int q = 0; q < lv.n; ++q) {
+    BlockReq a;
+    a.rows = side_from_dofs(F.G, lv.rows[q]);
+    a.cols = a.rows;
+    a.out_off = lv.a_off[q];
+    a.rs = 1;
+    a.cs = lv.b[q];
+    reqs.push_back(std::move(a));
+  }
+  AssemblyStats ast;
+  assemble_blocks(reqs, F.DG.elems.p, F.m, lv.A.p, F.stream, &ast);
+  F.st.assembly_seconds += ast.seconds;
+  F.st.kernel_evals += ast.evals;
+}
+
+static void factor_root(Factor& F, Root& rt) {
+  CellLevel& lv = F.levels[F.l0];
+  hipStream_t s = F.stream;
+  rt.n = (int)lv.B;
+  rt.A = DevBuf<c64>((size_t)rt.n * rt.n);
+  rt.piv = DevBuf<int>((size_t)rt.n);
+  std::vector<ScatterDesc> sc;
+  std::vector<BlockReq> reqs;
+  for (int q = 0; q < lv.n; ++q) {
+    ScatterDesc d{};
+    d.src_off = lv.a_off[q];
+    d.src_ld = lv.b[q];
+    d.nr = lv.b[q];
+    d.nc = lv.b[q];
+    d.dst_off = lv.f_off[q] + lv.f_off[q] * (int64_t)rt.n;
+    d.dst_ld = rt.n;
+    d.rpos_off = -1;
+    d.cpos_off = -1;
+    sc.push_back(d);
+    for (int q2 = 0; q2 < lv.n; ++q2) {
+      if (q2 == q) continue;
+      BlockReq a;
+      a.rows = side_from_dofs(F.G, lv.rows[q]);
+      a.cols = side_from_dofs(F.G, lv.cols[q2]);
+      a.out_off = lv.f_off[q] + lv.f_off[q2] * (int64_t)rt.n;
+      a.rs = 1;
+      a.cs = rt.n;
+      reqs.push_back(std::move(a));
+    }
+  }
+  DevBuf<int> dpos(std::vector<int>{0});
+  launch_scatter(sc, dpos.p, lv.A.p, rt.A.p, s);
+  AssemblyStats ast;
+  assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, s, &ast);
+  F.st.assembly_seconds += ast.seconds;
+  F.st.kernel_evals += ast.evals;
+  hipEvent_t e0, e1;
+  FDS_HIP(hipEventCreate(&e0));
+  FDS_HIP(hipEventCreate(&e1));
+  FDS_HIP(hipEventRecord(e0, s));
+  DevBuf<int> info(1);
+  launch_lu(std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}, rt.A.p, rt.piv.p, info.p, s);
+  FDS_HIP(hipEventRecord(e1, s));
+  FDS_HIP(hipEventSynchronize(e1));
+  F.st.root_seconds += 1e-3 * elapsed_ms(e0, e1);
+  FDS_HIP(hipEventDestroy(e0));
+  FDS_HIP(hipEventDestroy(e1));
+  check_info(info, 1, s);
+}
+
+}  // namespace fds
+
+using namespace fds;
+
+static int translate(const std::exception& e) {
+  if (auto* x = dynamic_cast<const Error*>(&e)) return x->code;
+  return FDS_EHIP;
+}
+
+static thread_local std::string g_last_error;
+
+extern "C" {
+
+int fds_options_default(fds_options* o) {
+  if (!o) return FDS_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->leaf_nodes = 64;
+  o->n_proxy = 64;
+  o->root_level = 1;
+  o->proxy_ratio = 1.5;
+  o->use_alpha = 0;
+  return FDS_OK;
+}
+
+static int check_material(double omega, double lam, double mu, double rho) {
+  if (!(omega > 0) || !(mu > 0) || !(lam + mu > 0) || !(rho > 0)) return FDS_EINVAL;
+  return FDS_OK;
+}
+
+int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, double rho, double tol,
+              const fds_options* opt, void* stream, fds_factor* out) {
+  if (!out) return FDS_EINVAL;
+  if (int e = check_material(omega, lambda, mu, rho)) return e;
+  if (!(tol > 0.0 && tol < 1.0)) return FDS_EINVAL;
+  fds_options o;
+  fds_options_default(&o);
+  if (opt) o = *opt;
+  if (o.leaf_nodes < 4 || o.n_proxy < 8 || o.root_level < 0 || !(o.proxy_ratio > 1.0)) return FDS_EINVAL;
+  auto* F = new Factor();
+  try {
+    if (int e = make_geometry(geom, F->G)) {
+      delete F;
+      return e;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    ensure_quad();
+    F->opt = o;
+    F->tol = tol;
+    F->lam = lambda;
+    F->mu = mu;
+    F->rho = rho;
+    F->omega = omega;
+    F->stream = (hipStream_t)stream;
+    F->m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
+    build_tree(*F);
+    const int64_t proxy_cap = (int64_t)F->levels[F->L].n * o.n_proxy;
+    F->DG.init(F->G, proxy_cap, F->stream);
+    assemble_leaves(*F);
+    for (int lev = F->L; lev > F->l0; --lev) {
+      compress_level(*F, lev);
+      merge_to_parent(*F, lev);
+    }
+    Root* rt = &F->root;
+    factor_root(*F, *rt);
+    FDS_HIP(hipStreamSynchronize(F->stream));
+    const auto t1 = std::chrono::steady_clock::now();
+    F->st.factor_seconds = std::chrono::duration<double>(t1 - t0).count();
+    F->st.levels = F->L;
+    F->st.root_level = F->l0;
+    F->st.n_unknowns = 2 * (int64_t)F->G.n_nodes;
+    F->st.root_size = rt->n;
+    int64_t bytes = 0;
+    for (auto& lv : F->levels)
+      bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) + (lv.piv.n + lv.s_piv.n) * sizeof(int);
+    bytes += (int64_t)rt->A.n * sizeof(c64);
+    F->st.factor_bytes = bytes;
+    *out = F;
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    int c = translate(e);
+    delete F;
+    return c;
+  }
+}
+
+int fds_size(fds_factor f, int64_t* n) {
+  if (!f || !n) return FDS_EINVAL;
+  *n = 2 * (int64_t)f->G.n_nodes;
+  return FDS_OK;
+}
+
+int fds_rhs_plane(fds_factor f, int32_t nrhs, const int32_t* kind, const double* angle, fds_c64* rhs, int64_t ld,
+                  void* stream) {
+  if (!f || nrhs < 1 || !kind || !angle || !rhs || ld < 2 * (int64_t)f->G.n_nodes) return FDS_EINVAL;
+  try {
+    for (int k = 0; k < nrhs; ++k)
+      if (kind[k] != 0 && kind[k] != 1) return FDS_EINVAL;
+    ensure_quad();
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<int> dk(std::vector<int>(kind, kind + nrhs));
+    DevBuf<double> da(std::vector<double>(angle, angle + nrhs));
+    launch_rhs_plane(f->DG.elems.p, f->DG.prev_elem.p, f->G.n_nodes, f->m, f->lam, nrhs, dk.p, da.p, (c64*)rhs, ld, s);
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fds_c64* x, int64_t ld_x, void* stream) {
+  const int64_t N = f ? 2 * (int64_t)f->G.n_nodes : 0;
+  if (!f || nrhs < 1 || !rhs || !x || ld_rhs < N || ld_x < N) return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    Root* rt = &f->root;
+    const int L = f->L, l0 = f->l0;
+    auto& levels = f->levels;
+    std::vector<DevBuf<c64>> Fv(L + 1), Tv(L + 1), Ftv(L + 1);
+    for (int lev = l0; lev <= L; ++lev) {
+      Fv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].B * nrhs, 1));
+      if (lev > l0) {
+        Tv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].R * nrhs, 1));
+        Ftv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].R * nrhs, 1));
+      }
+    }
+    // leaf gather: F_L[f_off + r] = rhs[rows[r]]
+    {
+      CellLevel& lv = levels[L];
+      std::vector<int64_t> si, di;
+      for (int q = 0; q < lv.n; ++q)
+        for (size_t r = 0; r < lv.rows[q].size(); ++r) {
+          si.push_back(lv.rows[q][r]);
+          di.push_back(lv.f_off[q] + (int64_t)r);
+        }
+      DevBuf<int64_t> dsi(si), ddi(di);
+      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, (const c64*)rhs, ld_rhs, Fv[L].p, lv.B, s);
+      FDS_HIP(hipStreamSynchronize(s));
+    }
+    // upward sweep
+    for (int lev = L; lev > l0; --lev) {
+      CellLevel& lv = levels[lev];
+      std::vector<SolveDesc> sd;
+      std::vector<GemmDesc> g1, g2;
+      for (int q = 0; q < lv.n; ++q) {
+        sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.f_off[q], lv.b[q], lv.b[q], (int)lv.B, nrhs});
+        if (lv.r[q] == 0) continue;
+        GemmDesc a{};
+        a.a_off = lv.v_off[q];
+        a.b_off = lv.f_off[q];
+        a.c_off = lv.t_off[q];
+        a.m = lv.r[q];
+        a.n = nrhs;
+        a.k = lv.b[q];
+        a.lda = lv.r[q];
+        a.ldb = (int)lv.B;
+        a.ldc = (int)lv.R;
+        a.alpha_re = 1.0;
+        g1.push_back(a);
+        GemmDesc b2{};
+        b2.a_off = lv.at_off[q];
+        b2.b_off = lv.t_off[q];
+        b2.c_off = lv.t_off[q];
+        b2.m = lv.r[q];
+        b2.n = nrhs;
+        b2.k = lv.r[q];
+        b2.lda = lv.r[q];
+        b2.ldb = (int)lv.R;
+        b2.ldc = (int)lv.R;
+        b2.alpha_re = 1.0;
+        g2.push_back(b2);
+      }
+      launch_lu_solve(sd, lv.A.p, lv.piv.p, Fv[lev].p, s);
+      launch_gemm(g1, lv.V.p, Fv[lev].p, Tv[lev].p, 0, s);
+      launch_gemm(g2, lv.At.p, Tv[lev].p, Ftv[lev].p, 0, s);
+      // parent rows
+      CellLevel& pa = levels[lev - 1];
+      std::vector<int64_t> si, di;
+      for (int q = 0; q < lv.n; ++q) {
+        const int p = q / 2;
+        for (int j = 0; j < lv.r[q]; ++j) {
+          si.push_back(lv.t_off[q] + j);
+          di.push_back(pa.f_off[p] + lv.ppos[q][j]);
+        }
+      }
+      DevBuf<int64_t> dsi(si), ddi(di);
+      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Ftv[lev].p, lv.R, Fv[lev - 1].p, pa.B, s);
+      FDS_HIP(hipStreamSynchronize(s));
+    }
+    // root
+    launch_lu_solve(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt->n, rt->n, (int)levels[l0].B, nrhs}}, rt->A.p,
+                    rt->piv.p, Fv[l0].p, s);
+    // downward sweep
+    for (int lev = l0 + 1; lev <= L; ++lev) {
+      CellLevel& lv = levels[lev];
+      CellLevel& pa = levels[lev - 1];
+      std::vector<int64_t> si, di;
+      for (int q = 0; q < lv.n; ++q) {
+        const int p = q / 2;
+        for (int j = 0; j < lv.r[q]; ++j) {
+          si.push_back(pa.f_off[p] + lv.ppos[q][j]);
+          di.push_back(lv.t_off[q] + j);
+        }
+      }
+      DevBuf<int64_t> dsi(si), ddi(di);
+      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Fv[lev - 1].p, pa.B, Tv[lev].p, lv.R, s);
+      std::vector<GemmDesc> g1, g2;
+      for (int q = 0; q < lv.n; ++q) {
+        if (lv.r[q] == 0) continue;
+        GemmDesc a{};   // Ft <- A~ y - Ft
+        a.a_off = lv.at_off[q];
+        a.b_off = lv.t_off[q];
+        a.c_off = lv.t_off[q];
+        a.m = lv.r[q];
+        a.n = nrhs;
+        a.k = lv.r[q];
+        a.lda = lv.r[q];
+        a.ldb = (int)lv.R;
+        a.ldc = (int)lv.R;
+        a.alpha_re = 1.0;
+        a.beta_re = -1.0;
+        g1.push_back(a);
+        GemmDesc b2{};  // x <- g + X Ft
+        b2.a_off = lv.x_off[q];
+        b2.b_off = lv.t_off[q];
+        b2.c_off = lv.f_off[q];
+        b2.m = lv.b[q];
+        b2.n = nrhs;
+        b2.k = lv.r[q];
+        b2.lda = lv.b[q];
+        b2.ldb = (int)lv.R;
+        b2.ldc = (int)lv.B;
+        b2.alpha_re = 1.0;
+        b2.beta_re = 1.0;
+        g2.push_back(b2);
+      }
+      launch_gemm(g1, lv.At.p, Tv[lev].p, Ftv[lev].p, 0, s);
+      launch_gemm(g2, lv.X.p, Ftv[lev].p, Fv[lev].p, 0, s);
+    }
+    // leaf scatter
+    {
+      CellLevel& lv = levels[L];
+      std::vector<int64_t> si, di;
+      for (int q = 0; q < lv.n; ++q)
+        for (size_t r = 0; r < lv.cols[q].size(); ++r) {
+          si.push_back(lv.f_off[q] + (int64_t)r);
+          di.push_back(lv.cols[q][r]);
+        }
+      DevBuf<int64_t> dsi(si), ddi(di);
+      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Fv[L].p, lv.B, (c64*)x, ld_x, s);
+      FDS_HIP(hipStreamSynchronize(s));
+    }
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_get_stats(fds_factor f, fds_stats* s) {
+  if (!f || !s) return FDS_EINVAL;
+  *s = f->st;
+  return FDS_OK;
+}
+
+int fds_get_ranks(fds_factor f, int32_t* out, int64_t n_out) {
+  if (!f || !out) return FDS_EINVAL;
+  const int64_t ncell = (2LL << f->L) - 1;
+  if (n_out < 4 * ncell) return FDS_EINVAL;
+  for (int64_t i = 0; i < 4 * ncell; ++i) out[i] = -1;
+  for (int lev = f->l0 + 1; lev <= f->L; ++lev) {
+    const CellLevel& lv = f->levels[lev];
+    for (int q = 0; q < lv.n; ++q) {
+      const int64_t c = (1LL << lev) - 1 + q;
+      out[4 * c] = lv.kr0[q];
+      out[4 * c + 1] = lv.kc0[q];
+      out[4 * c + 2] = lv.kr1[q];
+      out[4 * c + 3] = lv.kc1[q];
+    }
+  }
+  return FDS_OK;
+}
+
+int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, int64_t cap, int64_t* n_out) {
+  if (!f || !rows || !cols || !n_out || cell < 0) return FDS_EINVAL;
+  int lev = 0;
+  while (((2LL << lev) - 1) <= cell) ++lev;
+  if (lev > f->L || lev <= f->l0) return FDS_EINVAL;
+  const CellLevel& lv = f->levels[lev];
+  const int q = cell - ((1 << lev) - 1);
+  const int64_t k = (int64_t)lv.rskel[q].size();
+  if (cap < k) return FDS_EINVAL;
+  std::copy(lv.rskel[q].begin(), lv.rskel[q].end(), rows);
+  std::copy(lv.cskel[q].begin(), lv.cskel[q].end(), cols);
+  *n_out = k;
+  return FDS_OK;
+}
+
+void fds_destroy(fds_factor f) {
+  if (!f) return;
+  delete f;
+}
+
+const char* fds_strerror(int code) {
+  switch (code) {
+    case FDS_OK: return "ok";
+    case FDS_EINVAL: return "invalid argument";
+    case FDS_EGEOM: return "invalid geometry";
+    case FDS_ENOMEM: return "out of memory";
+    case FDS_EHIP: return "HIP runtime error";
+    case FDS_ESINGULAR: return "singular pivot";
+    case FDS_ENOCONV: return "iterative refinement did not converge";
+    default: return "unknown error";
+  }
+}
+
+const char* fds_last_error(void) { return g_last_error.c_str(); }
+
+int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu, double rho, const fds_options* opt,
+                int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols, fds_c64* out, int64_t ld,
+                void* stream) {
+  if (int e = check_material(omega, lambda, mu, rho)) return e;
+  if (nr < 1 || nc < 1 || !rows || !cols || !out || ld < nr) return FDS_EINVAL;
+  fds_options o;
+  fds_options_default(&o);
+  if (opt) o = *opt;
+  try {
+    Geometry G;
+    if (int e = make_geometry(geom, G)) return e;
+    for (int64_t i = 0; i < nr; ++i)
+      if (rows[i] < 0 || rows[i] >= 2 * (int64_t)G.n_nodes) return FDS_EINVAL;
+    for (int64_t i = 0; i < nc; ++i)
+      if (cols[i] < 0 || cols[i] >= 2 * (int64_t)G.n_nodes) return FDS_EINVAL;
+    ensure_quad();
+    hipStream_t s = (hipStream_t)stream;
+    DevGeom DG;
+    DG.init(G, 0, s);
+    MatConst m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
+    BlockReq q;
+    q.rows = side_from_dofs(G, std::vector<int64_t>(rows, rows + nr));
+    q.cols = side_from_dofs(G, std::vector<int64_t>(cols, cols + nc));
+    q.out_off = 0;
+    q.rs = 1;
+    q.cs = ld;
+    AssemblyStats st;
+    assemble_blocks(std::vector<BlockReq>{q}, DG.elems.p, m, (c64*)out, s, &st);
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_special_eval(int64_t n, const double* x, double beta, double* out, fds_c64* outc, void* stream) {
+  if (n < 1 || !x || !out || !outc || !(beta > 0)) return FDS_EINVAL;
+  try {
+    launch_special_eval(x, n, beta, out, (c64*)outc, (hipStream_t)stream);
+    FDS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n, int32_t* piv,
+                     const int64_t* pivoff, const int64_t* kmax, double tol, int32_t stop_at_tol, int32_t* rank,
+                     void* stream) {
+  if (np < 1 || !a || !off || !m || !n || !piv || !pivoff || !kmax || !rank) return FDS_EINVAL;
+  try {
+    std::vector<CpqrDesc> d(np);
+    for (int i = 0; i < np; ++i) {
+      if (m[i] < 1 || n[i] < 1) return FDS_EINVAL;
+      d[i] = CpqrDesc{off[i], pivoff[i], (int)m[i], (int)n[i], (int)m[i], 0, (int)kmax[i], stop_at_tol};
+    }
+    launch_cpqr(d, (c64*)a, piv, tol, rank, (hipStream_t)stream);
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,527 @@
+// Batched variable-size complex linear algebra kernels (gfx950).
+//
+// One workgroup per problem (LU, pivoted QR, interpolation matrices) or per
+// (problem, tile) (solves, GEMM, scatters); every launch covers a whole
+// batch of unevenly sized problems described by descriptor arrays.
+#include <algorithm>
+
+#include "devmem.hpp"
+#include "linalg.hpp"
+
+namespace fds {
+
+constexpr int kBlk = 256;
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ------------------------------------------------------------------ LU
+// Right-looking LU with partial pivoting (largest modulus, lowest row on
+// ties).  L is unit lower triangular, stored below the diagonal; piv[j] is
+// the row swapped with row j at step j (LAPACK convention, 0-based).
+__global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c64* __restrict__ base,
+                                             int* __restrict__ piv, int* __restrict__ info) {
+  const LUDesc d = descs[blockIdx.x];
+  c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int n = d.n, lda = d.lda;
+  const int tid = threadIdx.x;
+  __shared__ double sv[kBlk];
+  __shared__ int si[kBlk];
+  int bad = 0;
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = j + tid; i < n; i += kBlk) {
+      const double v = abs2(A[i + (int64_t)j * lda]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int o = kBlk / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double a = sv[tid], b = sv[tid + o];
+        const int ia = si[tid], ib = si[tid + o];
+        if (b > a || (b == a && ib < ia)) {
+          sv[tid] = b;
+          si[tid] = ib;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    const double pv = sv[0];
+    __syncthreads();
+    if (tid == 0) P[j] = p;
+    if (!(pv > 0.0) || !isfinite(pv)) bad = bad ? bad : j + 1;
+    if (p != j) {
+      for (int c = tid; c < n; c += kBlk) {
+        const c64 t = A[j + (int64_t)c * lda];
+        A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
+        A[p + (int64_t)c * lda] = t;
+      }
+    }
+    __syncthreads();
+    const c64 piv_v = A[j + (int64_t)j * lda];
+    const c64 inv = (pv > 0.0) ? cdiv(cmk(1.0, 0.0), piv_v) : cmk(0.0, 0.0);
+    for (int i = j + 1 + tid; i < n; i += kBlk) A[i + (int64_t)j * lda] = A[i + (int64_t)j * lda] * inv;
+    __syncthreads();
+    const int m = n - j - 1;
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t t = tid; t < mm; t += kBlk) {
+      const int i = j + 1 + (int)(t % m);
+      const int c = j + 1 + (int)(t / m);
+      A[i + (int64_t)c * lda] -= A[i + (int64_t)j * lda] * A[j + (int64_t)c * lda];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && info) info[blockIdx.x] = bad;
+}
+
+// ------------------------------------------------------------------ LU solve
+struct SolveTile {
+  int desc;
+  int c0, nc;
+};
+
+__global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, const SolveTile* __restrict__ tiles,
+                                                   const c64* __restrict__ abase, const int* __restrict__ piv,
+                                                   c64* __restrict__ bbase) {
+  extern __shared__ c64 X[];
+  const SolveTile tl = tiles[blockIdx.x];
+  const SolveDesc d = descs[tl.desc];
+  const c64* A = abase + d.a_off;
+  const int* P = piv + d.piv_off;
+  c64* B = bbase + d.b_off + (int64_t)tl.c0 * d.ldb;
+  const int n = d.n, lda = d.lda, nc = tl.nc;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * nc; t += kBlk) {
+    const int i = t % n, c = t / n;
+    X[i + c * n] = B[i + (int64_t)c * d.ldb];
+  }
+  __syncthreads();
+  if (tid < nc) {
+    for (int j = 0; j < n; ++j) {
+      const int p = P[j];
+      if (p != j) {
+        const c64 t = X[j + tid * n];
+        X[j + tid * n] = X[p + tid * n];
+        X[p + tid * n] = t;
+      }
+    }
+  }
+  __syncthreads();
+  const int cc = tid % nc;
+  const int r0 = tid / nc;
+  const int rs = kBlk / nc;
+  // forward substitution with unit L
+  for (int j = 0; j < n - 1; ++j) {
+    const c64 xj = X[j + cc * n];
+    if (r0 < rs)
+      for (int i = j + 1 + r0; i < n; i += rs) X[i + cc * n] -= A[i + (int64_t)j * lda] * xj;
+    __syncthreads();
+  }
+  // backward substitution with U
+  for (int j = n - 1; j >= 0; --j) {
+    if (tid < nc) X[j + tid * n] = cdiv(X[j + tid * n], A[j + (int64_t)j * lda]);
+    __syncthreads();
+    const c64 xj = X[j + cc * n];
+    if (r0 < rs)
+      for (int i = r0; i < j; i += rs) X[i + cc * n] -= A[i + (int64_t)j * lda] * xj;
+    __syncthreads();
+  }
+  for (int t = tid; t < n * nc; t += kBlk) {
+    const int i = t % n, c = t / n;
+    B[i + (int64_t)c * d.ldb] = X[i + c * n];
+  }
+}
+
+// ------------------------------------------------------------------ GEMM
+// C = alpha op(A) B + beta C, 64 x 64 output tiles, k-slices of 16 staged in
+// LDS, each thread owning a 4 x 4 block of outputs.
+struct GemmTile {
+  int desc;
+  int tm, tn;
+};
+
+template <int TA>
+__global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
+                                               const c64* __restrict__ abase, const c64* __restrict__ bbase,
+                                               c64* __restrict__ cbase) {
+  __shared__ c64 As[16][65];
+  __shared__ c64 Bs[16][65];
+  const GemmTile tl = tiles[blockIdx.x];
+  const GemmDesc d = descs[tl.desc];
+  const c64* A = abase + d.a_off;
+  const c64* B = bbase + d.b_off;
+  c64* C = cbase + d.c_off;
+  const int m0 = tl.tm * 64, n0 = tl.tn * 64;
+  const int tid = threadIdx.x;
+  const int tr = tid % 16, tc = tid / 16;   // thread owns rows tr + 16 a, cols tc + 16 b
+  c64 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cmk(0, 0);
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    // stage op(A)[m0:m0+64, k0:k0+16] and B[k0:k0+16, n0:n0+64]
+    for (int t = tid; t < 64 * 16; t += kBlk) {
+      const int ii = t % 64, kk = t / 64;
+      const int gi = m0 + ii, gk = k0 + kk;
+      c64 va = cmk(0, 0);
+      if (gi < d.m && gk < d.k) va = TA ? A[gk + (int64_t)gi * d.lda] : A[gi + (int64_t)gk * d.lda];
+      As[kk][ii] = va;
+      const int kb = t % 16, jj = t / 16;
+      const int gkb = k0 + kb, gj = n0 + jj;
+      c64 vb = cmk(0, 0);
+      if (gkb < d.k && gj < d.n) vb = B[gkb + (int64_t)gj * d.ldb];
+      Bs[kb][jj] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      c64 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tr + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+  const c64 al = cmk(d.alpha_re, d.alpha_im), be = cmk(d.beta_re, d.beta_im);
+  const bool zero_beta = (d.beta_re == 0.0 && d.beta_im == 0.0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int gi = m0 + tr + 16 * a, gj = n0 + tc + 16 * b;
+      if (gi < d.m && gj < d.n) {
+        c64* cp = C + gi + (int64_t)gj * d.ldc;
+        const c64 v = al * acc[a][b];
+        *cp = zero_beta ? v : v + be * (*cp);
+      }
+    }
+}
+
+// ------------------------------------------------------------------ pivoted QR
+constexpr int kQrMaxM = 2048;
+constexpr int kQrMaxN = 1024;
+
+__global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ descs, c64* __restrict__ base,
+                                               int* __restrict__ piv, double tol, int* __restrict__ rank) {
+  __shared__ double nrm[kQrMaxN];
+  __shared__ int pv[kQrMaxN];
+  __shared__ c64 v[kQrMaxM];
+  __shared__ double sv[kBlk];
+  __shared__ int si[kBlk];
+  __shared__ double s_r00, s_tau;
+  __shared__ int s_stop;
+  const CpqrDesc d = descs[blockIdx.x];
+  c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int m = d.m, n = d.n, lda = d.lda;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int kmax = min(d.k_end, min(m, n));
+  for (int c = tid; c < n; c += kBlk) pv[c] = d.k_start == 0 ? c : P[c];
+  // exactly computed norms of the remaining part of each column
+  for (int c = d.k_start + wid; c < n; c += kBlk / 64) {
+    double s = 0.0;
+    for (int i = d.k_start + lane; i < m; i += 64) s += abs2(A[i + (int64_t)c * lda]);
+    s = wsum(s);
+    if (lane == 0) nrm[c] = s;
+  }
+  if (tid == 0) {
+    s_r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
+    s_stop = 0;
+  }
+  __syncthreads();
+  int j = d.k_start;
+  for (; j < kmax; ++j) {
+    // pivot: largest norm; ties within a relative 1e-12 -> lowest original column
+    double best = -1.0;
+    for (int c = j + tid; c < n; c += kBlk) best = fmax(best, nrm[c]);
+    sv[tid] = best;
+    __syncthreads();
+    for (int o = kBlk / 2; o > 0; o >>= 1) {
+      if (tid < o) sv[tid] = fmax(sv[tid], sv[tid + o]);
+      __syncthreads();
+    }
+    const double top = sv[0];
+    __syncthreads();
+    int bo = 0x7fffffff, bc = -1;
+    for (int c = j + tid; c < n; c += kBlk)
+      if (nrm[c] >= top * (1.0 - 1e-12) && pv[c] < bo) {
+        bo = pv[c];
+        bc = c;
+      }
+    si[tid] = bo;
+    sv[tid] = (double)bc;
+    __syncthreads();
+    for (int o = kBlk / 2; o > 0; o >>= 1) {
+      if (tid < o && si[tid + o] < si[tid]) {
+        si[tid] = si[tid + o];
+        sv[tid] = sv[tid + o];
+      }
+      __syncthreads();
+    }
+    const int p = (int)sv[0];
+    __syncthreads();
+    if (tid == 0) {
+      const double rjj = sqrt(nrm[p]);
+      if (j == 0) s_r00 = rjj;
+      if (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * s_r00)) s_stop = 1;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    if (p != j) {
+      for (int i = tid; i < m; i += kBlk) {
+        const c64 t = A[i + (int64_t)j * lda];
+        A[i + (int64_t)j * lda] = A[i + (int64_t)p * lda];
+        A[i + (int64_t)p * lda] = t;
+      }
+      if (tid == 0) {
+        const double t = nrm[j];
+        nrm[j] = nrm[p];
+        nrm[p] = t;
+        const int q = pv[j];
+        pv[j] = pv[p];
+        pv[p] = q;
+      }
+    }
+    __syncthreads();
+    // Householder reflector H = I - tau v v^H with H x = alpha e1
+    for (int i = j + tid; i < m; i += kBlk) v[i] = A[i + (int64_t)j * lda];
+    __syncthreads();
+    if (wid == 0) {
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) s += abs2(v[i]);
+      s = wsum(s);
+      if (lane == 0) {
+        const double xn = sqrt(s);
+        const c64 x0 = v[j];
+        const double ax0 = sqrt(abs2(x0));
+        const c64 ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+        const c64 alpha = (-xn) * ph;
+        v[j] = x0 - alpha;
+        const double vn2 = 2.0 * s + 2.0 * ax0 * xn;
+        s_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        A[j + (int64_t)j * lda] = alpha;
+      }
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < m; i += kBlk) A[i + (int64_t)j * lda] = cmk(0, 0);
+    const double tau = s_tau;
+    for (int c = j + 1 + wid; c < n; c += kBlk / 64) {
+      c64* col = A + (int64_t)c * lda;
+      double wr = 0.0, wi = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const c64 a = col[i], vv = v[i];
+        wr += vv.re * a.re + vv.im * a.im;    // conj(v) a
+        wi += vv.re * a.im - vv.im * a.re;
+      }
+      wr = wsum(wr);
+      wi = wsum(wi);
+      const c64 w = cmk(tau * wr, tau * wi);
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const c64 a = col[i] - v[i] * w;
+        col[i] = a;
+        if (i > j) s += abs2(a);
+      }
+      s = wsum(s);
+      if (lane == 0) nrm[c] = s;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int c = tid; c < n; c += kBlk) P[c] = pv[c];
+  if (tid == 0) rank[blockIdx.x] = j;
+}
+
+// W = [I, R1^{-1} R2] P^T: solve R1 T = R2 in place, then write W or W^T.
+__global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ descs, c64* __restrict__ abase,
+                                                 const int* __restrict__ piv, c64* __restrict__ dbase) {
+  const InterpDesc d = descs[blockIdx.x];
+  c64* A = abase + d.a_off;
+  const int* P = piv + d.piv_off;
+  c64* D = dbase + d.d_off;
+  const int n = d.n, lda = d.lda, k = d.k;
+  const int tid = threadIdx.x;
+  for (int c = k + tid; c < n; c += kBlk) {
+    c64* col = A + (int64_t)c * lda;
+    for (int i = k - 1; i >= 0; --i) {
+      c64 s = col[i];
+      for (int l = i + 1; l < k; ++l) s -= A[i + (int64_t)l * lda] * col[l];
+      col[i] = cdiv(s, A[i + (int64_t)i * lda]);
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < k * n; t += kBlk) {
+    const int r = t % k, c = t / k;     // W(r, P[c])
+    c64 val;
+    if (c < k)
+      val = (r == c) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+    else
+      val = A[r + (int64_t)c * lda];
+    const int cc = P[c];
+    if (d.transpose)
+      D[cc + (int64_t)r * d.d_ld] = val;
+    else
+      D[r + (int64_t)cc * d.d_ld] = val;
+  }
+}
+
+// ------------------------------------------------------------------ scatter / copies
+struct ScatterTile {
+  int desc;
+  int count;
+  int64_t start;
+};
+
+__global__ void k_scatter(const ScatterDesc* __restrict__ descs, const ScatterTile* __restrict__ tiles,
+                          const int* __restrict__ pos, const c64* __restrict__ src, c64* __restrict__ dst) {
+  const ScatterTile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count) return;
+  const ScatterDesc d = descs[t.desc];
+  const int64_t e = t.start + threadIdx.x;
+  const int r = (int)(e % d.nr), c = (int)(e / d.nr);
+  const int64_t rp = d.rpos_off >= 0 ? pos[d.rpos_off + r] : r;
+  const int64_t cp = d.cpos_off >= 0 ? pos[d.cpos_off + c] : c;
+  dst[d.dst_off + rp + cp * d.dst_ld] = src[d.src_off + r + (int64_t)c * d.src_ld];
+}
+
+__global__ void k_copy_rows(int64_t n, const int64_t* __restrict__ sidx, const int64_t* __restrict__ didx, int ncol,
+                            const c64* __restrict__ src, int64_t lds, c64* __restrict__ dst, int64_t ldd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= ncol) return;
+  dst[didx[i] + (int64_t)c * ldd] = src[sidx[i] + (int64_t)c * lds];
+}
+
+__global__ void k_axpby(int64_t n, double alpha, const c64* __restrict__ src, double beta, c64* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = alpha * src[i] + beta * dst[i];
+}
+
+__global__ void k_fill_identity(const int64_t* __restrict__ offs, const int* __restrict__ ns, const int* __restrict__ lds,
+                                c64* __restrict__ base) {
+  const int p = blockIdx.x;
+  const int n = ns[p], ld = lds[p];
+  c64* A = base + offs[p];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t % n, c = t / n;
+    A[i + (int64_t)c * ld] = (i == c) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_lu(const std::vector<LUDesc>& d, c64* base, int* piv, int* info, hipStream_t s) {
+  if (d.empty()) return;
+  DevBuf<LUDesc> dd(d);
+  k_lu<<<(int)d.size(), kBlk, 0, s>>>(dd.p, base, piv, info);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_lu_solve(const std::vector<SolveDesc>& d, const c64* abase, const int* piv, c64* bbase, hipStream_t s) {
+  if (d.empty()) return;
+  int nmax = 1;
+  for (auto& x : d) nmax = std::max(nmax, x.n);
+  // LDS chunk of nc columns: n * nc * 16 bytes <= 32 KiB
+  int nc = std::max(1, std::min(8, 32768 / (16 * nmax)));
+  std::vector<SolveTile> tiles;
+  for (int i = 0; i < (int)d.size(); ++i)
+    for (int c0 = 0; c0 < d[i].ncol; c0 += nc) tiles.push_back(SolveTile{i, c0, std::min(nc, d[i].ncol - c0)});
+  if (tiles.empty()) return;
+  if ((size_t)nmax * nc * sizeof(c64) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  DevBuf<SolveDesc> dd(d);
+  DevBuf<SolveTile> dt(tiles);
+  k_lu_solve<<<(int)tiles.size(), kBlk, nmax * nc * sizeof(c64), s>>>(dd.p, dt.p, abase, piv, bbase);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_gemm(const std::vector<GemmDesc>& d, const c64* abase, const c64* bbase, c64* cbase, int transA,
+                 hipStream_t s) {
+  if (d.empty()) return;
+  std::vector<GemmTile> tiles;
+  for (int i = 0; i < (int)d.size(); ++i)
+    for (int tm = 0; tm * 64 < d[i].m; ++tm)
+      for (int tn = 0; tn * 64 < d[i].n; ++tn) tiles.push_back(GemmTile{i, tm, tn});
+  if (tiles.empty()) return;
+  DevBuf<GemmDesc> dd(d);
+  DevBuf<GemmTile> dt(tiles);
+  if (transA)
+    k_gemm<1><<<(int)tiles.size(), kBlk, 0, s>>>(dd.p, dt.p, abase, bbase, cbase);
+  else
+    k_gemm<0><<<(int)tiles.size(), kBlk, 0, s>>>(dd.p, dt.p, abase, bbase, cbase);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_cpqr(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, hipStream_t s) {
+  if (d.empty()) return;
+  for (auto& x : d)
+    if (x.m > kQrMaxM || x.n > kQrMaxN) throw Error(1, "cpqr: matrix exceeds the LDS limits");
+  DevBuf<CpqrDesc> dd(d);
+  k_cpqr<<<(int)d.size(), kBlk, 0, s>>>(dd.p, base, piv, tol, rank);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_interp(const std::vector<InterpDesc>& d, c64* abase, const int* piv, c64* dbase, hipStream_t s) {
+  if (d.empty()) return;
+  DevBuf<InterpDesc> dd(d);
+  k_interp<<<(int)d.size(), kBlk, 0, s>>>(dd.p, abase, piv, dbase);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_scatter(const std::vector<ScatterDesc>& d, const int* pos, const c64* src, c64* dst, hipStream_t s) {
+  if (d.empty()) return;
+  std::vector<ScatterTile> tiles;
+  for (int i = 0; i < (int)d.size(); ++i) {
+    const int64_t ne = (int64_t)d[i].nr * d[i].nc;
+    for (int64_t a = 0; a < ne; a += 256) tiles.push_back(ScatterTile{i, (int)std::min<int64_t>(256, ne - a), a});
+  }
+  if (tiles.empty()) return;
+  DevBuf<ScatterDesc> dd(d);
+  DevBuf<ScatterTile> dt(tiles);
+  k_scatter<<<(int)tiles.size(), 256, 0, s>>>(dd.p, dt.p, pos, src, dst);
+  FDS_HIP(hipGetLastError());
+  FDS_HIP(hipStreamSynchronize(s));
+}
+
+void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,
+                      c64* dst, int64_t ldd, hipStream_t s) {
+  if (n == 0 || ncol == 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), ncol);
+  k_copy_rows<<<grid, 256, 0, s>>>(n, sidx, didx, ncol, src, lds, dst, ldd);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_axpby(int64_t n, double alpha, const c64* src, double beta, c64* dst, hipStream_t s) {
+  if (n == 0) return;
+  k_axpby<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, alpha, src, beta, dst);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, c64* base, hipStream_t s) {
+  if (n_mats == 0) return;
+  k_fill_identity<<<(unsigned)n_mats, 256, 0, s>>>(offs, ns, lds, base);
+  FDS_HIP(hipGetLastError());
+}
+
+}  // namespace fds

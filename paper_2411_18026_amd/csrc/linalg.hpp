@@ -1,0 +1,65 @@
+// Batched variable-size complex linear algebra used by the elimination
+// (Section 6.2), the ID (Sections 7.1-7.2) and the sweeps (Section 6.3).
+// Every problem of a batch has its own sizes and offsets into one base
+// array; one launch covers the whole batch.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace fds {
+
+struct LUDesc {         // in-place LU with partial pivoting of an n x n matrix
+  int64_t a_off;
+  int64_t piv_off;
+  int n, lda;
+};
+
+struct SolveDesc {      // B <- A^{-1} B using the LU of LUDesc (B is n x ncol)
+  int64_t a_off, piv_off, b_off;
+  int n, lda, ldb, ncol;
+};
+
+struct GemmDesc {       // C = alpha op(A) B + beta C; op(A) is m x k
+  int64_t a_off, b_off, c_off;
+  int m, n, k, lda, ldb, ldc;
+  double alpha_re, alpha_im, beta_re, beta_im;
+};
+
+struct CpqrDesc {       // column-pivoted QR of an m x n matrix (ld = lda)
+  int64_t a_off, piv_off;
+  int m, n, lda;
+  int k_start, k_end;   // steps [k_start, k_end)
+  int stop_at_tol;
+};
+
+struct InterpDesc {     // W = [I, R1^{-1} R2] P^T (k x n) from a finished CPQR
+  int64_t a_off, piv_off;
+  int n, lda, k;
+  int64_t d_off;        // destination (col-major, ld = d_ld)
+  int d_ld;
+  int transpose;        // 0: write W at (r, c); 1: write W^T at (c, r)
+};
+
+struct ScatterDesc {    // dst[dst_off + rpos[r] + cpos[c] * dst_ld] = src[src_off + r + c * src_ld]
+  int64_t src_off, dst_off;
+  int nr, nc, src_ld, dst_ld;
+  int rpos_off, cpos_off;   // -1: identity
+};
+
+void launch_lu(const std::vector<LUDesc>& d, c64* base, int* piv, int* info, hipStream_t s);
+void launch_lu_solve(const std::vector<SolveDesc>& d, const c64* abase, const int* piv, c64* bbase, hipStream_t s);
+void launch_gemm(const std::vector<GemmDesc>& d, const c64* abase, const c64* bbase, c64* cbase, int transA,
+                 hipStream_t s);
+void launch_cpqr(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, hipStream_t s);
+void launch_interp(const std::vector<InterpDesc>& d, c64* abase, const int* piv, c64* dbase, hipStream_t s);
+void launch_scatter(const std::vector<ScatterDesc>& d, const int* pos, const c64* src, c64* dst, hipStream_t s);
+// dst[didx[i] + c * ldd] = src[sidx[i] + c * lds], i < n, c < ncol
+void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,
+                      c64* dst, int64_t ldd, hipStream_t s);
+// dst[i] = alpha * src[i] + beta * dst[i]
+void launch_axpby(int64_t n, double alpha, const c64* src, double beta, c64* dst, hipStream_t s);
+void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, c64* base, hipStream_t s);
+
+}  // namespace fds

@@ -1,0 +1,250 @@
+// Device special functions for the elastodynamic Galerkin kernels.
+//
+// The fundamental solution of 2D elastodynamics (equation of the
+// fundamental solution, Section 3) needs the Hankel functions H0, H1 of
+// the first kind at the transverse and longitudinal wavenumbers, i.e. the
+// Bessel functions J0, J1, Y0, Y1 of real positive argument, and the two
+// combinations
+//     E   = (a H1(a) - b H1(b)) / a^2,      chi = H2(a) - beta^2 H2(b),
+// with a = k_T r, b = k_L r = beta a, which carry exactly cancelling 1/a^2
+// singular parts.
+//
+// Algorithms (all from the classical expansions of Bessel functions):
+//   x < 2       ascending power series of J0, J1, Y0, Y1;
+//   2 <= x < 17 Miller's backward recurrence J_{n-1} = (2n/x) J_n - J_{n+1}
+//               from n = N >= 2x + 20, normalised by J0 + 2 sum J_{2k} = 1,
+//               with Neumann series for the second kind:
+//                 Y0 = (2/pi)(log(x/2) + gamma) J0 - (4/pi) sum_k (-1)^k J_{2k}/k,
+//                 Y1 = -(2/(pi x)) J0 + (2/pi)(log(x/2) + gamma) J1
+//                      + (2/pi) sum_k (-1)^k (J_{2k-1} - J_{2k+1})/k;
+//   x >= 17     Hankel's asymptotic expansion H_nu = sqrt(2/(pi x)) (P + iQ)
+//               exp(i(x - nu pi/2 - pi/4)).
+//   E, chi for a < 1 from the ascending series of H1, H2 with the singular
+//   parts cancelled analytically; otherwise from the Hankel values.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace fds {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kEulerGamma = 0.57721566490153286060651209008240243;
+constexpr double kSeriesSwitch = 1.0;   // a below which E, chi use the series
+
+struct c64 {
+  double re, im;
+};
+
+__host__ __device__ inline c64 cmk(double r, double i) { return c64{r, i}; }
+__host__ __device__ inline c64 operator+(c64 a, c64 b) { return c64{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline c64 operator-(c64 a, c64 b) { return c64{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline c64 operator-(c64 a) { return c64{-a.re, -a.im}; }
+__host__ __device__ inline c64 operator*(c64 a, c64 b) {
+  return c64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline c64 operator*(double s, c64 a) { return c64{s * a.re, s * a.im}; }
+__host__ __device__ inline c64 operator*(c64 a, double s) { return c64{s * a.re, s * a.im}; }
+__host__ __device__ inline c64& operator+=(c64& a, c64 b) {
+  a.re += b.re;
+  a.im += b.im;
+  return a;
+}
+__host__ __device__ inline c64& operator-=(c64& a, c64 b) {
+  a.re -= b.re;
+  a.im -= b.im;
+  return a;
+}
+__host__ __device__ inline c64 conj(c64 a) { return c64{a.re, -a.im}; }
+__host__ __device__ inline double abs2(c64 a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline c64 mul_i(c64 a) { return c64{-a.im, a.re}; }   // i a
+// a * b / c computed as complex division
+__host__ __device__ inline c64 cdiv(c64 a, c64 b) {
+  double d = b.re * b.re + b.im * b.im;
+  return c64{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// J0, J1, Y0, Y1 of x > 0.
+__host__ __device__ inline void bessel_jy01(double x, double& J0, double& J1, double& Y0, double& Y1) {
+  if (x < 2.0) {
+    const double w = 0.25 * x * x;
+    double t0 = 1.0, t1 = 0.5 * x, h = 0.0;
+    double j0 = 0.0, j1 = 0.0, y0s = 0.0, y1s = 0.0;
+    for (int k = 0; k < 14; ++k) {
+      j0 += t0;
+      j1 += t1;
+      y0s -= t0 * h;                                  // (-1)^{k+1} h_k w^k/(k!)^2
+      y1s += (2.0 * h + 1.0 / (k + 1)) * t1;          // (psi(k+1)+psi(k+2)+2 gamma) t1_k
+      t0 *= -w / ((k + 1.0) * (k + 1.0));
+      t1 *= -w / ((k + 1.0) * (k + 2.0));
+      h += 1.0 / (k + 1);
+    }
+    const double L = log(0.5 * x);
+    J0 = j0;
+    J1 = j1;
+    Y0 = (2.0 / kPi) * ((L + kEulerGamma) * j0 + y0s);
+    Y1 = -2.0 / (kPi * x) + (2.0 / kPi) * L * j1 - (y1s - 2.0 * kEulerGamma * j1) / kPi;
+    return;
+  }
+  if (x < 17.0) {
+    int N = (int)(2.0 * x + 20.0);
+    N += (N & 1);                    // even start index
+    const double tx = 2.0 / x;
+    double cur = 1e-30, nxt = 0.0;   // J_N (unnormalised), J_{N+1}
+    double s = 0.0, y0s = 0.0, y1s = 0.0, v0 = 0.0, v1 = 0.0;
+    for (int m = N; m >= 0; --m) {
+      const double v = cur;
+      if (m & 1) {
+        // odd m contributes to sum_k (-1)^k (J_{2k-1} - J_{2k+1})/k
+        const int kp = (m + 1) >> 1;           // m = 2 kp - 1
+        double c = ((kp & 1) ? -1.0 : 1.0) / kp;
+        if (m >= 3) {
+          const int km = (m - 1) >> 1;         // m = 2 km + 1
+          c -= ((km & 1) ? -1.0 : 1.0) / km;
+        }
+        y1s += c * v;
+        if (m == 1) v1 = v;
+      } else if (m > 0) {
+        const int k = m >> 1;
+        s += 2.0 * v;
+        y0s += ((k & 1) ? -v : v) / k;
+      } else {
+        s += v;
+        v0 = v;
+      }
+      const double prev = m * tx * cur - nxt;
+      nxt = cur;
+      cur = prev;
+    }
+    const double inv = 1.0 / s;
+    const double L = log(0.5 * x) + kEulerGamma;
+    J0 = v0 * inv;
+    J1 = v1 * inv;
+    Y0 = (2.0 / kPi) * L * J0 - (4.0 / kPi) * y0s * inv;
+    Y1 = -(2.0 / (kPi * x)) * J0 + (2.0 / kPi) * L * J1 + (2.0 / kPi) * y1s * inv;
+    return;
+  }
+  // Hankel asymptotic expansion
+  double P0 = 0.0, Q0 = 0.0, P1 = 0.0, Q1 = 0.0;
+  {
+    double a0 = 1.0, a1 = 1.0;
+    const double inv8x = 1.0 / (8.0 * x);
+    for (int k = 0; k < 40; ++k) {
+      if (k > 0) {
+        const double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+        a0 *= (0.0 - o) * inv8x / k;
+        a1 *= (4.0 - o) * inv8x / k;
+      }
+      const double sg = ((k >> 1) & 1) ? -1.0 : 1.0;
+      if ((k & 1) == 0) {
+        P0 += sg * a0;
+        P1 += sg * a1;
+      } else {
+        Q0 += sg * a0;
+        Q1 += sg * a1;
+      }
+      if (fabs(a0) < 1e-17 && fabs(a1) < 1e-17) break;
+    }
+  }
+  double sx, cx;
+  sincos(x, &sx, &cx);
+  const double r2 = 0.70710678118654752440084436210484903;
+  const double c0 = (cx + sx) * r2, s0 = (sx - cx) * r2;     // cos, sin of x - pi/4
+  const double c1 = (sx - cx) * r2, s1 = -(sx + cx) * r2;    // cos, sin of x - 3 pi/4
+  const double f = sqrt(2.0 / (kPi * x));
+  J0 = f * (P0 * c0 - Q0 * s0);
+  Y0 = f * (P0 * s0 + Q0 * c0);
+  J1 = f * (P1 * c1 - Q1 * s1);
+  Y1 = f * (P1 * s1 + Q1 * c1);
+}
+
+// psi(m) - (-gamma) = harmonic number h_{m-1}
+__host__ __device__ inline double harmonic(int m) {
+  double h = 0.0;
+  for (int j = 1; j <= m; ++j) h += 1.0 / j;
+  return h;
+}
+
+// E = (a H1(a) - b H1(b))/a^2 and chi = H2(a) - beta^2 H2(b), b = beta a, by the
+// ascending series (valid for all a, used for a < kSeriesSwitch).
+__host__ __device__ inline void e_chi_series(double a, double beta, c64& E, c64& chi) {
+  const double w = 0.25 * a * a;
+  const double la = log(0.5 * a);
+  const double lb = log(beta);
+  const double b2 = beta * beta;
+  const double twoipi = 2.0 / kPi;
+  E = cmk(0.0, 0.0);
+  chi = cmk(0.0, -(1.0 - b2) / kPi);
+  double wk = 1.0;          // w^k
+  double fk = 1.0;          // k!
+  double fk1 = 1.0;         // (k+1)!
+  double fk2 = 2.0;         // (k+2)!
+  double bp2 = b2;          // beta^(2k+2)
+  double bp4 = b2 * b2;     // beta^(2k+4)
+  double hk = 0.0;          // h_k
+  for (int k = 0; k < 14; ++k) {
+    const double hk1 = hk + 1.0 / (k + 1);    // h_{k+1}
+    const double hk2 = hk1 + 1.0 / (k + 2);   // h_{k+2}
+    // psi(k+1) + psi(k+2) = -2 gamma + h_k + h_{k+1}
+    const double sE = -2.0 * kEulerGamma + hk + hk1;
+    const double sC = -2.0 * kEulerGamma + hk + hk2;   // psi(k+1) + psi(k+3)
+    // c_k(a) = 1 + i (2/pi) log(a/2) - i (1/pi) sE
+    const double ck_im = twoipi * la - sE / kPi;
+    const double dk_im = twoipi * la - sC / kPi;
+    const double sgn = (k & 1) ? -1.0 : 1.0;
+    {
+      // ((1 - beta^(2k+2)) c_k - beta^(2k+2) (2i/pi) log beta) / (2 k! (k+1)!)
+      const double re = (1.0 - bp2);
+      const double im = (1.0 - bp2) * ck_im - bp2 * twoipi * lb;
+      const double sc = sgn * wk / (2.0 * fk * fk1);
+      E.re += sc * re;
+      E.im += sc * im;
+    }
+    {
+      const double re = (1.0 - bp4);
+      const double im = (1.0 - bp4) * dk_im - bp4 * twoipi * lb;
+      const double sc = sgn * wk * w / (fk * fk2);
+      chi.re += sc * re;
+      chi.im += sc * im;
+    }
+    wk *= w;
+    fk *= (k + 1);
+    fk1 *= (k + 2);
+    fk2 *= (k + 3);
+    bp2 *= b2;
+    bp4 *= b2;
+    hk = hk1;
+  }
+}
+
+// Hankel values needed at one point: H0(a), H1(a), H0(b), H1(b).
+struct Hankel2 {
+  c64 h0a, h1a, h0b, h1b;
+};
+
+__host__ __device__ inline Hankel2 hankel_pair(double a, double b) {
+  Hankel2 h;
+  double j0, j1, y0, y1;
+  bessel_jy01(a, j0, j1, y0, y1);
+  h.h0a = cmk(j0, y0);
+  h.h1a = cmk(j1, y1);
+  bessel_jy01(b, j0, j1, y0, y1);
+  h.h0b = cmk(j0, y0);
+  h.h1b = cmk(j1, y1);
+  return h;
+}
+
+__host__ __device__ inline void e_chi(double a, double beta, const Hankel2& h, c64& E, c64& chi) {
+  if (a < kSeriesSwitch) {
+    e_chi_series(a, beta, E, chi);
+    return;
+  }
+  const double b = beta * a;
+  const double ia2 = 1.0 / (a * a);
+  E = ia2 * (a * h.h1a - b * h.h1b);
+  const c64 h2a = (2.0 / a) * h.h1a - h.h0a;
+  const c64 h2b = (2.0 / b) * h.h1b - h.h0b;
+  chi = h2a - (beta * beta) * h2b;
+}
+
+}  // namespace fds

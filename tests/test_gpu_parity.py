@@ -1,0 +1,155 @@
+"""GPU parity: each HIP step against the CPU oracle on the same seeded inputs,
+through the C ABI.
+
+Tolerances: the two sides evaluate the same integrals with the same
+quadrature rules but independent code (special functions, summation
+order), so entries agree to rounding (<= 1e-12 of the block's largest entry);
+pivoted-QR decisions (pivots, ranks) must be identical; solutions agree to
+1e-10 relative (same skeletons, rounding amplified by the conditioning of
+the small dense blocks).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as sy
+from oracle import dense, fds as ofds, galerkin, special
+from oracle.kernels import Material
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdsmod():
+    import paper_2411_18026_amd as m
+    m.load()
+    assert torch.cuda.is_available()
+    return m
+
+
+def test_special_functions(fdsmod):
+    from scipy import special as sp
+    x = np.concatenate([np.logspace(-7, 2.7, 300), np.linspace(1.5, 20, 200)])
+    out, outc = fdsmod.special_eval(torch.from_numpy(x), 0.5)
+    out = out.cpu().numpy()
+    outc = outc.cpu().numpy()
+    ref = np.stack([sp.j0(x), sp.j1(x), sp.y0(x), sp.y1(x)], 1)
+    err = np.abs(out - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() < 5e-15
+    E, C = special.e_chi(x, 0.5)
+    assert np.max(np.abs(outc[:, 0] - E) / np.abs(E)) < 1e-13
+    assert np.max(np.abs(outc[:, 1] - C) / np.abs(C)) < 1e-13
+
+
+GEOMS = {
+    "circle64": [sy.circle(64)],
+    "ellipse97": [sy.ellipse(97, 1.0, 0.5)],
+    "two_cavities": [sy.ellipse(40, 0.6, 0.3, center=(-1.0, 0.2), angle=0.4), sy.circle(33, 0.5, center=(1.2, -0.3))],
+}
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+@pytest.mark.parametrize("omega", [1.0, 4.0])
+def test_dense_entries(fdsmod, name, omega):
+    curves = GEOMS[name]
+    mat = Material(2.0, 1.0, 1.0, omega)
+    bnd = galerkin.Boundary(curves)
+    A = galerkin.dense_matrix(bnd, mat)
+    n = A.shape[0]
+    G = fdsmod.entries(curves, omega, 2.0, 1.0, 1.0, np.arange(n), np.arange(n)).cpu().numpy()
+    assert np.max(np.abs(G - A)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_scattered_entries_and_alpha(fdsmod):
+    curves = GEOMS["ellipse97"]
+    rng = np.random.default_rng(7)
+    rows = rng.choice(2 * 97, 37, replace=False)
+    cols = rng.choice(2 * 97, 53, replace=False)
+    for alpha in (None, 0.0, 0.3 - 0.7j):
+        mat = Material(1.0, 1.0, 1.0, 2.5, alpha)
+        ref = galerkin.dof_block(galerkin.Boundary(curves), rows, cols, mat)
+        G = fdsmod.entries(curves, 2.5, 1.0, 1.0, 1.0, rows, cols, alpha=alpha).cpu().numpy()
+        assert np.max(np.abs(G - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_cpqr_matches_oracle(fdsmod):
+    rng = np.random.default_rng(3)
+    mats = []
+    for (m, n) in ((150, 40), (90, 64), (33, 70), (200, 7)):
+        M = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))) * np.logspace(0, -12, n)[None, rng.permutation(n)]
+        mats.append(M)
+    # symmetric ties: two identical columns
+    T = rng.standard_normal((50, 20)) + 0j
+    T[:, 7] = T[:, 3]
+    mats.append(T)
+    res = fdsmod.cpqr_batched(mats, 1e-8)
+    for M, (piv, k, R) in zip(mats, res):
+        p_o, R_o = ofds.cpqr(M)
+        k_o = ofds.id_rank(R_o, 1e-8)
+        assert k == k_o
+        assert np.array_equal(piv[:k], p_o[:k])
+        assert np.allclose(np.abs(np.diag(R)[:k]), np.abs(np.diag(R_o)[:k]), rtol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["circle64", "two_cavities"])
+def test_load_vectors(fdsmod, name):
+    curves = GEOMS[name]
+    F = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-8, leaf=16)
+    kinds = [0, 1, 0, 1]
+    angles = [0.0, 0.3, 2.0, 4.4]
+    got = F.rhs_plane(kinds, angles).cpu().numpy()
+    mat = Material(2.0, 1.0, 1.0, 3.0)
+    bnd = galerkin.Boundary(curves)
+    for k in range(4):
+        ref = galerkin.load_vector(bnd, kinds[k], angles[k], mat)
+        assert np.max(np.abs(got[k] - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def _oracle_problem(curves, omega, kinds, angles, lam=2.0):
+    X, A, Fm = dense.dense_solve(curves, lam, 1.0, 1.0, omega, kinds, angles, return_matrix=True)
+    return X, A, Fm
+
+
+def test_small_validation_case(fdsmod):
+    cfg = sy.config_small()
+    curves = cfg["curves"]
+    X, A, Fm = _oracle_problem(curves, cfg["omega"], [0, 1], [0.0, 1.0])
+    F = fdsmod.Factor(curves, cfg["omega"], cfg["lam"], cfg["mu"], cfg["rho"], cfg["tol"], leaf=cfg["leaf"])
+    rhs = torch.from_numpy(np.ascontiguousarray(Fm.T)).to("cuda")
+    Y = F.solve(rhs).cpu().numpy().T
+    err = np.linalg.norm(Y - X) / np.linalg.norm(X)
+    assert err < 1e-9
+    S = ofds.FDS(curves, cfg["lam"], cfg["mu"], cfg["rho"], cfg["omega"], cfg["tol"], leaf=cfg["leaf"])
+    Yo = S.solve(Fm)
+    assert np.linalg.norm(Y - Yo) / np.linalg.norm(Yo) < 1e-10
+    # identical ranks and skeletons as the oracle
+    rk = F.ranks()
+    for i, c in S.cells.items():
+        if c.ranks:
+            assert tuple(rk[i]) == (c.ranks[0][0], c.ranks[0][1], c.ranks[1][0], c.ranks[1][1])
+            r, cc = F.skeleton(i)
+            assert np.array_equal(r, c.rskel) and np.array_equal(cc, c.cskel)
+
+
+@pytest.mark.parametrize("case", ["ragged", "multi", "deep_root0"])
+def test_fds_against_oracle(fdsmod, case):
+    if case == "ragged":
+        curves, leaf, l0, omega = [sy.ellipse(300, 1.0, 0.5)], 32, 1, 3.0
+    elif case == "multi":
+        curves, leaf, l0, omega = GEOMS["two_cavities"], 16, 1, 2.0
+    else:
+        curves, leaf, l0, omega = [sy.tripod(256)], 16, 0, 2.0
+    kinds, angles = [0, 1, 0], [0.0, 0.9, 3.0]
+    X, A, Fm = _oracle_problem(curves, omega, kinds, angles)
+    F = fdsmod.Factor(curves, omega, 2.0, 1.0, 1.0, 1e-9, leaf=leaf, root_level=l0)
+    rhs = torch.from_numpy(np.ascontiguousarray(Fm.T)).to("cuda")
+    Y = F.solve(rhs).cpu().numpy().T
+    S = ofds.FDS(curves, 2.0, 1.0, 1.0, omega, 1e-9, leaf=leaf, root_level=l0)
+    Yo = S.solve(Fm)
+    assert np.linalg.norm(Y - Yo) / np.linalg.norm(Yo) < 1e-10
+    assert np.linalg.norm(Y - X) / np.linalg.norm(X) < 1e-6
+    # the GPU load vectors reproduce the oracle's
+    G = F.rhs_plane(kinds, angles).cpu().numpy().T
+    assert np.max(np.abs(G - Fm)) <= 1e-13 * np.max(np.abs(Fm))
