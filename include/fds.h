@@ -114,6 +114,11 @@ typedef struct {
   double root_seconds;      /* GPU time of the root LU */
   int64_t factor_bytes;     /* device bytes held by the factor */
   int64_t kernel_evals;     /* quadrature-point kernel evaluations during the build */
+  /* per quadrature class of element pairs: 0/1/2 tensor Gauss with 4/6/10
+   * points per element, 3 coincident, 4/5 adjacent (two orientations) */
+  double class_seconds[6];  /* GPU time of that class's integration kernel, summed over launches */
+  int64_t class_evals[6];   /* kernel evaluations (quadrature points) of that class */
+  int64_t class_launches[6];
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);

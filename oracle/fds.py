@@ -211,6 +211,84 @@ def proxy_polygon(c, rho):
     return Polygon(np.stack([c[0] + rho * np.cos(t), c[1] + rho * np.sin(t)], axis=1), sign=-1)
 
 
+def cell_disk(bnd, c):
+    """Centre (bounding-box midpoint of the supports of the cell's active
+    hats) and radius of a cell."""
+    act = np.unique(np.concatenate([c.rows, c.cols]) // 2)
+    sup = bnd.nodes[_supports(bnd, act)]
+    lo, hi = sup.min(axis=0), sup.max(axis=0)
+    c.centre = 0.5 * (lo + hi)
+    c.radius = float(np.max(np.hypot(sup[:, 0] - c.centre[0], sup[:, 1] - c.centre[1])))
+
+
+def compress_cell(bnd, mat, tol, c, others):
+    """One cell of the upward step (Section 7.3, steps 3a-3b): proxy and
+    near interaction matrices (Sections 7.1, 7.2), four IDs, and
+    X = A_i^{-1} U_i, A~_i = (V_i X)^{-1} (Section 6.2)."""
+    rho = PROXY_RATIO * c.radius
+    P = proxy_polygon(c.centre, rho)
+    near_r = np.concatenate([o.rows for o in others]) if others else np.zeros(0, np.int64)
+    near_c = np.concatenate([o.cols for o in others]) if others else np.zeros(0, np.int64)
+    near_r = near_r[_support_meets_disk(bnd, near_r // 2, c.centre, rho)] if len(near_r) else near_r
+    near_c = near_c[_support_meets_disk(bnd, near_c // 2, c.centre, rho)] if len(near_c) else near_c
+    pdofs = np.arange(2 * N_PROXY)
+    MV = entries(bnd, pdofs, c.cols, mat, proxy_rows=P)
+    MU = entries(bnd, c.rows, pdofs, mat, proxy_cols=P)
+    if len(near_r):
+        MV = np.vstack([MV, entries(bnd, near_r, c.cols, mat)])
+    if len(near_c):
+        MU = np.hstack([MU, entries(bnd, c.rows, near_c, mat)])
+    nc = [int(np.sum(c.cols % 2 == q)) for q in (0, 1)]
+    nr = [int(np.sum(c.rows % 2 == q)) for q in (0, 1)]
+    assert nc == nr
+    Vb, Ub, rsk, csk, ks = [], [], [], [], []
+    off = 0
+    for q in (0, 1):
+        cidx = np.arange(off, off + nc[q])
+        pc, Rc = cpqr(MV[:, cidx])
+        pr, Rr = cpqr(MU[cidx, :].conj().T)
+        kc, kr = id_rank(Rc, tol), id_rank(Rr, tol)
+        k = max(kc, kr)
+        c.ranks[q] = (kr, kc)
+        Vb.append(id_matrix(pc, Rc, k, nc[q]))
+        Ub.append(id_matrix(pr, Rr, k, nc[q]).conj().T)
+        csk.append(c.cols[cidx][pc[:k]])
+        rsk.append(c.rows[cidx][pr[:k]])
+        ks.append(k)
+        off += nc[q]
+    c.k = tuple(ks)
+    c.V = sla.block_diag(*Vb)
+    U = sla.block_diag(*Ub)
+    c.cskel = np.concatenate(csk)
+    c.rskel = np.concatenate(rsk)
+    c.lu = sla.lu_factor(c.A)
+    c.X = sla.lu_solve(c.lu, U)
+    S = c.V @ c.X
+    c.At = np.linalg.inv(S)
+
+
+def leaf_sample(curves, lam, mu, rho, omega, tol, leaf, sample):
+    """The upward-step work of a few leaf cells of the full tree (leaf block
+    assembly plus compress_cell), for timing the oracle on a bounded sample.
+    Returns the cells."""
+    mat = Material(lam, mu, rho, omega)
+    bnd = Boundary(curves)
+    L, cells = build_tree(bnd.n_nodes, leaf)
+    leaves = level_cells(cells, L)
+    for c in leaves:
+        nodes = np.arange(c.lo, c.hi)
+        c.rows = np.concatenate([2 * nodes, 2 * nodes + 1])
+        c.cols = c.rows.copy()
+    out = []
+    for q in sample:
+        c = leaves[q]
+        c.A = entries(bnd, c.rows, c.cols, mat)
+        cell_disk(bnd, c)
+        compress_cell(bnd, mat, tol, c, [o for o in leaves if o is not c])
+        out.append(c)
+    return out
+
+
 # ---------------------------------------------------------------- factor
 class FDS:
     """Factorisation of the Galerkin system; ``solve`` applies it."""
@@ -227,53 +305,9 @@ class FDS:
         bnd, mat = self.bnd, self.mat
         cells = level_cells(self.cells, lev)
         for c in cells:
-            act = np.unique(np.concatenate([c.rows, c.cols]) // 2)
-            sup = bnd.nodes[_supports(bnd, act)]
-            lo, hi = sup.min(axis=0), sup.max(axis=0)
-            c.centre = 0.5 * (lo + hi)
-            c.radius = float(np.max(np.hypot(sup[:, 0] - c.centre[0], sup[:, 1] - c.centre[1])))
+            cell_disk(bnd, c)
         for c in cells:
-            rho = PROXY_RATIO * c.radius
-            P = proxy_polygon(c.centre, rho)
-            others = [o for o in cells if o is not c]
-            near_r = np.concatenate([o.rows for o in others]) if others else np.zeros(0, np.int64)
-            near_c = np.concatenate([o.cols for o in others]) if others else np.zeros(0, np.int64)
-            near_r = near_r[_support_meets_disk(bnd, near_r // 2, c.centre, rho)] if len(near_r) else near_r
-            near_c = near_c[_support_meets_disk(bnd, near_c // 2, c.centre, rho)] if len(near_c) else near_c
-            pdofs = np.arange(2 * N_PROXY)
-            MV = entries(bnd, pdofs, c.cols, mat, proxy_rows=P)
-            MU = entries(bnd, c.rows, pdofs, mat, proxy_cols=P)
-            if len(near_r):
-                MV = np.vstack([MV, entries(bnd, near_r, c.cols, mat)])
-            if len(near_c):
-                MU = np.hstack([MU, entries(bnd, c.rows, near_c, mat)])
-            nc = [int(np.sum(c.cols % 2 == q)) for q in (0, 1)]
-            nr = [int(np.sum(c.rows % 2 == q)) for q in (0, 1)]
-            assert nc == nr
-            Vb, Ub, rsk, csk, ks = [], [], [], [], []
-            off = 0
-            for q in (0, 1):
-                cidx = np.arange(off, off + nc[q])
-                pc, Rc = cpqr(MV[:, cidx])
-                pr, Rr = cpqr(MU[cidx, :].conj().T)
-                kc, kr = id_rank(Rc, self.tol), id_rank(Rr, self.tol)
-                k = max(kc, kr)
-                c.ranks[q] = (kr, kc)
-                Vb.append(id_matrix(pc, Rc, k, nc[q]))
-                Ub.append(id_matrix(pr, Rr, k, nc[q]).conj().T)
-                csk.append(c.cols[cidx][pc[:k]])
-                rsk.append(c.rows[cidx][pr[:k]])
-                ks.append(k)
-                off += nc[q]
-            c.k = tuple(ks)
-            c.V = sla.block_diag(*Vb)
-            U = sla.block_diag(*Ub)
-            c.cskel = np.concatenate(csk)
-            c.rskel = np.concatenate(rsk)
-            c.lu = sla.lu_factor(c.A)
-            c.X = sla.lu_solve(c.lu, U)
-            S = c.V @ c.X
-            c.At = np.linalg.inv(S)
+            compress_cell(bnd, mat, self.tol, c, [o for o in cells if o is not c])
 
     def _merge(self, lev):
         """Diagonal blocks of the level-(lev-1) cells (rearrangement, Section 6.2)."""

@@ -48,7 +48,8 @@ class _Stats(ctypes.Structure):
                 ("factor_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double),
                 ("id_seconds", ctypes.c_double), ("merge_seconds", ctypes.c_double),
                 ("root_seconds", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
-                ("kernel_evals", ctypes.c_int64)]
+                ("kernel_evals", ctypes.c_int64), ("class_seconds", ctypes.c_double * 6),
+                ("class_evals", ctypes.c_int64 * 6), ("class_launches", ctypes.c_int64 * 6)]
 
 
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_get_stats",
@@ -187,7 +188,13 @@ class Factor:
     def stats(self):
         s = _Stats()
         _check(load().fds_get_stats(self._h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in _Stats._fields_ if not f.startswith("reserved")}
+        out = {}
+        for f, _ in _Stats._fields_:
+            if f.startswith("reserved"):
+                continue
+            v = getattr(s, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def ranks(self):
         st = self.stats()

@@ -68,12 +68,11 @@ __device__ inline void acc_point(const MatConst& m, double dx, double dy, double
   const double e0 = dx * ir, e1 = dy * ir;
   const double je0 = -e1, je1 = e0;
   const double a = m.kT * r;
-  const Hankel2 h = hankel_pair(a, m.kL * r);
-  c64 E, chi;
-  e_chi(a, m.beta, h, E, chi);
-  const c64 phiT = cmk(-0.25 * h.h0a.im, 0.25 * h.h0a.re);
-  const c64 phiL = cmk(-0.25 * h.h0b.im, 0.25 * h.h0b.re);
-  const c64 q = cmk(-0.25 * m.kT * h.h1a.im, 0.25 * m.kT * h.h1a.re);   // (i/4) k_T H1(a)
+  c64 h0a, h1a, h0b, E, chi;
+  kernel_values(a, m.sc, h0a, h1a, h0b, E, chi);
+  const c64 phiT = cmk(-0.25 * h0a.im, 0.25 * h0a.re);
+  const c64 phiL = cmk(-0.25 * h0b.im, 0.25 * h0b.re);
+  const c64 q = cmk(-0.25 * m.kT * h1a.im, 0.25 * m.kT * h1a.re);   // (i/4) k_T H1(a)
   const double eny = e0 * ny0 + e1 * ny1;
   const double enx = e0 * nx0 + e1 * nx1;
   const c64 dny = q * eny;          // d_{n_y} Phi_T
@@ -224,35 +223,63 @@ __global__ void k_proxy_elems(const double* __restrict__ crd, int n_cells, int n
 }
 
 // ------------------------------------------------------------------ classify
-__global__ void k_classify(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
-                           const int* __restrict__ elist, const Elem* __restrict__ elems,
-                           unsigned long long* __restrict__ lists, int64_t list_cap,
-                           unsigned int* __restrict__ counters) {
+// Each block takes a tile of up to kClsTile pairs (4 per thread); list slots
+// are reserved with one atomic per class per block.
+constexpr int kClsTile = 1024;
+
+__global__ void __launch_bounds__(256) k_classify(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
+                                                  const int* __restrict__ elist, const Elem* __restrict__ elems,
+                                                  unsigned long long* __restrict__ lists, int64_t list_cap,
+                                                  unsigned int* __restrict__ counters) {
+  __shared__ unsigned int s_wcnt[4][kNumClass];
+  __shared__ unsigned int s_base[4][kNumClass];
   const Tile t = tiles[blockIdx.x];
   const Job jb = jobs[t.job];
-  const int li = threadIdx.x;
-  int cls = -1;
-  int64_t p = t.start + li;
-  if (li < t.count) {
-    const int ie = (int)(p / jb.nce), je = (int)(p % jb.nce);
-    const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
-    cls = classify_pair(elems[ge], elems[gf], ge, gf);
-  }
-  const unsigned long long key = ((unsigned long long)(unsigned)t.job << 32) | (unsigned long long)p;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int cls[4];
+  unsigned int off[4];
+  unsigned int run[kNumClass];
 #pragma unroll
-  for (int c = 0; c < kNumClass; ++c) {
-    const unsigned long long mask = __ballot(cls == c);
-    if (mask == 0ull) continue;
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned int base = 0;
-    if (lane == leader) base = atomicAdd(&counters[c], (unsigned)__popcll(mask));
-    base = __shfl(base, leader);
-    if (cls == c) {
-      const unsigned long long below = mask & ((1ull << lane) - 1ull);
-      const int64_t slot = (int64_t)base + __popcll(below);
-      if (slot < list_cap) lists[c * list_cap + slot] = key;
+  for (int c = 0; c < kNumClass; ++c) run[c] = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int li = j * 256 + threadIdx.x;
+    cls[j] = -1;
+    if (li < t.count) {
+      const int64_t p = t.start + li;
+      const int ie = (int)(p / jb.nce), je = (int)(p % jb.nce);
+      const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
+      cls[j] = classify_pair(elems[ge], elems[gf], ge, gf);
     }
+    off[j] = 0;
+#pragma unroll
+    for (int c = 0; c < kNumClass; ++c) {
+      const unsigned long long mask = __ballot(cls[j] == c);
+      if (cls[j] == c) off[j] = run[c] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+      run[c] += (unsigned)__popcll(mask);
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < kNumClass; ++c) s_wcnt[wid][c] = run[c];
+  __syncthreads();
+  if (threadIdx.x < kNumClass) {
+    const int c = threadIdx.x;
+    const unsigned tot = s_wcnt[0][c] + s_wcnt[1][c] + s_wcnt[2][c] + s_wcnt[3][c];
+    unsigned b = tot ? atomicAdd(&counters[c], tot) : 0u;
+    for (int w = 0; w < 4; ++w) {
+      s_base[w][c] = b;
+      b += s_wcnt[w][c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (cls[j] < 0) continue;
+    const int64_t p = t.start + j * 256 + threadIdx.x;
+    const unsigned long long key = ((unsigned long long)(unsigned)t.job << 32) | (unsigned long long)p;
+    const int64_t slot = (int64_t)s_base[wid][cls[j]] + off[j];
+    if (slot < list_cap) lists[cls[j] * list_cap + slot] = key;
   }
 }
 
@@ -496,26 +523,40 @@ void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int*
   FDS_HIP(hipGetLastError());
 }
 
+int classify_tile_size() { return kClsTile; }
+
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
-                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s) {
+                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
+                  hipEvent_t* ev) {
+  // ev (optional): 7 events bracketing the six class launches in order
+  auto mark = [&](int i) {
+    if (ev) FDS_HIP(hipEventRecord(ev[i], s));
+  };
+  mark(0);
   if (counts[kQ4]) {
     k_regular<4><<<(counts[kQ4] + 127) / 128, 128, 0, s>>>(lists + kQ4 * cap, counts[kQ4], jobs, elist, elems, m, res, np);
   }
+  mark(1);
   if (counts[kQ6]) {
     k_regular<6><<<(counts[kQ6] + 127) / 128, 128, 0, s>>>(lists + kQ6 * cap, counts[kQ6], jobs, elist, elems, m, res, np);
   }
+  mark(2);
   if (counts[kQ10]) {
     k_regular<10><<<(counts[kQ10] + 127) / 128, 128, 0, s>>>(lists + kQ10 * cap, counts[kQ10], jobs, elist, elems, m, res, np);
   }
+  mark(3);
   if (counts[kCoinc]) {
     k_special<kCoinc><<<(counts[kCoinc] + 3) / 4, 256, 0, s>>>(lists + kCoinc * cap, counts[kCoinc], jobs, elist, elems, m, res, np);
   }
+  mark(4);
   if (counts[kAdjNext]) {
     k_special<kAdjNext><<<(counts[kAdjNext] + 3) / 4, 256, 0, s>>>(lists + kAdjNext * cap, counts[kAdjNext], jobs, elist, elems, m, res, np);
   }
+  mark(5);
   if (counts[kAdjPrev]) {
     k_special<kAdjPrev><<<(counts[kAdjPrev] + 3) / 4, 256, 0, s>>>(lists + kAdjPrev * cap, counts[kAdjPrev], jobs, elist, elems, m, res, np);
   }
+  mark(6);
   FDS_HIP(hipGetLastError());
 }
 

@@ -15,7 +15,9 @@ void launch_proxy_elems(const double* crd, int n_cells, int n_proxy, int poly_ba
 void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int* elist, const Elem* elems,
                      unsigned long long* lists, int64_t cap, unsigned int* counters, hipStream_t s);
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
-                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s);
+                  const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
+                  hipEvent_t* ev = nullptr);
+int classify_tile_size();
 void launch_gather(const Tile* tiles, int n_tiles, const Job* jobs, const Dof* dofs, const int* pos,
                    const c64* res, int64_t np, c64* out, hipStream_t s);
 void launch_rhs_plane(const Elem* elems, const int* prev_elem, int n_nodes, const MatConst& m, double lam, int nrhs,
@@ -46,6 +48,18 @@ class DeviceArena;
 struct AssemblyStats {
   double seconds = 0.0;
   int64_t evals = 0;
+  double class_seconds[kNumClass] = {0, 0, 0, 0, 0, 0};
+  int64_t class_evals[kNumClass] = {0, 0, 0, 0, 0, 0};
+  int64_t class_launches[kNumClass] = {0, 0, 0, 0, 0, 0};
+  void add(const AssemblyStats& o) {
+    seconds += o.seconds;
+    evals += o.evals;
+    for (int c = 0; c < kNumClass; ++c) {
+      class_seconds[c] += o.class_seconds[c];
+      class_evals[c] += o.class_evals[c];
+      class_launches[c] += o.class_launches[c];
+    }
+  }
 };
 
 void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,

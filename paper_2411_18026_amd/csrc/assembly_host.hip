@@ -107,9 +107,10 @@ static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts
 void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
                      hipStream_t s, AssemblyStats* st, int64_t max_pairs) {
   size_t i0 = 0;
-  hipEvent_t ev0, ev1;
+  hipEvent_t ev0, ev1, evc[7];
   FDS_HIP(hipEventCreate(&ev0));
   FDS_HIP(hipEventCreate(&ev1));
+  for (auto& e : evc) FDS_HIP(hipEventCreate(&e));
   while (i0 < reqs.size()) {
     // batch [i0, i1)
     size_t i1 = i0;
@@ -157,7 +158,8 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
       const int jid = (int)jobs.size();
       jobs.push_back(j);
       const int64_t npj = (int64_t)j.nre * j.nce;
-      for (int64_t a = 0; a < npj; a += 256) ptiles.push_back(Tile{jid, (int)std::min<int64_t>(256, npj - a), a});
+      const int ct = classify_tile_size();
+      for (int64_t a = 0; a < npj; a += ct) ptiles.push_back(Tile{jid, (int)std::min<int64_t>(ct, npj - a), a});
       const int64_t noj = (int64_t)j.nrd * j.ncd;
       for (int64_t a = 0; a < noj; a += 256) otiles.push_back(Tile{jid, (int)std::min<int64_t>(256, noj - a), a});
       pair_off += npj;
@@ -176,7 +178,7 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
     unsigned int cnt[kNumClass];
     FDS_HIP(hipMemcpyAsync(cnt, d_cnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
     FDS_HIP(hipStreamSynchronize(s));
-    launch_pairs(d_lists.p, np, cnt, d_jobs.p, d_elist.p, d_elems, m, d_res.p, np, s);
+    launch_pairs(d_lists.p, np, cnt, d_jobs.p, d_elist.p, d_elems, m, d_res.p, np, s, evc);
     launch_gather(d_ot.p, (int)otiles.size(), d_jobs.p, d_dofs.p, d_pos.p, d_res.p, np, d_out, s);
     FDS_HIP(hipEventRecord(ev1, s));
     FDS_HIP(hipEventSynchronize(ev1));
@@ -184,12 +186,20 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
     FDS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (st) {
       st->seconds += 1e-3 * ms;
-      for (int c = 0; c < kNumClass; ++c) st->evals += (int64_t)cnt[c] * kPointsPerClass[c];
+      for (int c = 0; c < kNumClass; ++c) {
+        st->evals += (int64_t)cnt[c] * kPointsPerClass[c];
+        st->class_evals[c] += (int64_t)cnt[c] * kPointsPerClass[c];
+        if (cnt[c]) st->class_launches[c] += 1;
+        float cm = 0.f;
+        FDS_HIP(hipEventElapsedTime(&cm, evc[c], evc[c + 1]));
+        st->class_seconds[c] += 1e-3 * cm;
+      }
     }
     i0 = i1;
   }
   FDS_HIP(hipEventDestroy(ev0));
   FDS_HIP(hipEventDestroy(ev1));
+  for (auto& e : evc) FDS_HIP(hipEventDestroy(e));
 }
 
 }  // namespace fds

@@ -28,6 +28,7 @@ struct Elem {
 struct MatConst {
   double kT, kL, beta, mu, rw2;   // rw2 = rho omega^2
   double alpha_re, alpha_im;
+  SeriesCoef sc;                  // small-argument expansions for this beta
 };
 
 // One dense block A(rows, cols) to assemble.  Each side is a list of

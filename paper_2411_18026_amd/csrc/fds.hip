@@ -100,6 +100,7 @@ static MatConst make_mat(double omega, double lam, double mu, double rho, const 
   m.beta = m.kL / m.kT;
   m.mu = mu;
   m.rw2 = rho * omega * omega;
+  m.sc = make_series_coef(m.beta);
   if (o.use_alpha) {
     m.alpha_re = o.alpha.re;
     m.alpha_im = o.alpha.im;
@@ -214,6 +215,7 @@ struct fds_factor_s {
   int L = 0, l0 = 0;
   std::vector<fds::CellLevel> levels;   // index = level
   fds::Root root;
+  fds::AssemblyStats ast;
   fds_stats st{};
   hipStream_t stream = nullptr;
 };
@@ -470,8 +472,7 @@ static void compress_level(Factor& F, int lev) {
   }
   assemble_blocks(reqs, F.DG.elems.p, F.m, MU.p, s, &ast);
   reqs.clear();
-  F.st.assembly_seconds += ast.seconds;
-  F.st.kernel_evals += ast.evals;
+  F.ast.add(ast);
 
   // IDs: problem 4q + {0: V comp0, 1: V comp1, 2: U comp0, 3: U comp1}
   hipEvent_t e0, e1;
@@ -785,8 +786,7 @@ static void merge_to_parent(Factor& F, int lev) {
   launch_scatter(sc, dpos.p, ch.At.p, pa.A.p, s);
   AssemblyStats ast;
   assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, s, &ast);
-  F.st.assembly_seconds += ast.seconds;
-  F.st.kernel_evals += ast.evals;
+  F.ast.add(ast);
 }
 
 // Leaf diagonal blocks.
@@ -806,8 +806,7 @@ static void assemble_leaves(Factor& F) {
   }
   AssemblyStats ast;
   assemble_blocks(reqs, F.DG.elems.p, F.m, lv.A.p, F.stream, &ast);
-  F.st.assembly_seconds += ast.seconds;
-  F.st.kernel_evals += ast.evals;
+  F.ast.add(ast);
 }
 
 static void factor_root(Factor& F, Root& rt) {
@@ -844,8 +843,7 @@ static void factor_root(Factor& F, Root& rt) {
   launch_scatter(sc, dpos.p, lv.A.p, rt.A.p, s);
   AssemblyStats ast;
   assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, s, &ast);
-  F.st.assembly_seconds += ast.seconds;
-  F.st.kernel_evals += ast.evals;
+  F.ast.add(ast);
   hipEvent_t e0, e1;
   FDS_HIP(hipEventCreate(&e0));
   FDS_HIP(hipEventCreate(&e1));
@@ -936,6 +934,13 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
       bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) + (lv.piv.n + lv.s_piv.n) * sizeof(int);
     bytes += (int64_t)rt->A.n * sizeof(c64);
     F->st.factor_bytes = bytes;
+    F->st.assembly_seconds = F->ast.seconds;
+    F->st.kernel_evals = F->ast.evals;
+    for (int c = 0; c < kNumClass; ++c) {
+      F->st.class_seconds[c] = F->ast.class_seconds[c];
+      F->st.class_evals[c] = F->ast.class_evals[c];
+      F->st.class_launches[c] = F->ast.class_launches[c];
+    }
     *out = F;
     return FDS_OK;
   } catch (const std::exception& e) {

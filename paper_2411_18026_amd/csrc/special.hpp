@@ -217,6 +217,63 @@ __host__ __device__ inline void e_chi_series(double a, double beta, c64& E, c64&
   }
 }
 
+// Small-argument expansions as polynomials in w = a^2/4 (a = k_T r < 1,
+// b = beta a): coefficient tables depend only on beta and are built once per
+// material on the host (make_series_coef).  Rows of ``c``:
+//   0 J0:  (-1)^k/(k!)^2                1 Y0 part: (-1)^(k+1) h_k/(k!)^2
+//   2 J1/(a/2): (-1)^k/(k!(k+1)!)       3 Y1 part: (-1)^k (psi(k+1)+psi(k+2))/(k!(k+1)!)
+//   4 E real part, 5 E imaginary part without the log(a/2) term,
+//   6 chi/w real part, 7 chi/w imaginary part without the log(a/2) term.
+// With L = log(a/2):
+//   J0 = P0(w), Y0 = (2/pi)((L + gamma) J0 + P1(w)),
+//   J1 = (a/2) P2(w), Y1 = -2/(pi a) + (2/pi) L J1 - (1/pi)(a/2) P3(w),
+//   E = P4(w) + i ((2/pi) L P4(w) + P5(w)),
+//   chi = -(i/pi)(1 - beta^2) + w (P6(w) + i ((2/pi) L P6(w) + P7(w))),
+// and H0(b) from rows 0, 1 at w_b = beta^2 w with log(b/2) = L + log beta.
+constexpr int kSerTerms = 10;
+struct SeriesCoef {
+  double c[8][kSerTerms];
+  double beta, logbeta, chi0;   // chi0 = -(1 - beta^2)/pi (imaginary part of the constant)
+};
+
+inline SeriesCoef make_series_coef(double beta) {
+  SeriesCoef s{};
+  s.beta = beta;
+  s.logbeta = log(beta);
+  s.chi0 = -(1.0 - beta * beta) / kPi;
+  double fk = 1.0, fk1 = 1.0, fk2 = 2.0, hk = 0.0;   // k!, (k+1)!, (k+2)!, h_k
+  double b2 = beta * beta, bp2 = b2, bp4 = b2 * b2;
+  for (int k = 0; k < kSerTerms; ++k) {
+    const double sg = (k & 1) ? -1.0 : 1.0;
+    const double hk1 = hk + 1.0 / (k + 1), hk2 = hk1 + 1.0 / (k + 2);
+    const double psiE = -2.0 * kEulerGamma + hk + hk1;   // psi(k+1) + psi(k+2)
+    const double psiC = -2.0 * kEulerGamma + hk + hk2;   // psi(k+1) + psi(k+3)
+    s.c[0][k] = sg / (fk * fk);
+    s.c[1][k] = -sg * hk / (fk * fk);
+    s.c[2][k] = sg / (fk * fk1);
+    s.c[3][k] = sg * psiE / (fk * fk1);
+    const double e1 = sg * (1.0 - bp2) / (2.0 * fk * fk1);
+    s.c[4][k] = e1;
+    s.c[5][k] = sg * (-(1.0 - bp2) * psiE / kPi - bp2 * (2.0 / kPi) * s.logbeta) / (2.0 * fk * fk1);
+    s.c[6][k] = sg * (1.0 - bp4) / (fk * fk2);
+    s.c[7][k] = sg * (-(1.0 - bp4) * psiC / kPi - bp4 * (2.0 / kPi) * s.logbeta) / (fk * fk2);
+    fk *= (k + 1);
+    fk1 *= (k + 2);
+    fk2 *= (k + 3);
+    bp2 *= b2;
+    bp4 *= b2;
+    hk = hk1;
+  }
+  return s;
+}
+
+__host__ __device__ inline double horner(const double* c, double w) {
+  double p = c[kSerTerms - 1];
+#pragma unroll
+  for (int k = kSerTerms - 2; k >= 0; --k) p = p * w + c[k];
+  return p;
+}
+
 // Hankel values needed at one point: H0(a), H1(a), H0(b), H1(b).
 struct Hankel2 {
   c64 h0a, h1a, h0b, h1b;
@@ -245,6 +302,33 @@ __host__ __device__ inline void e_chi(double a, double beta, const Hankel2& h, c
   const c64 h2a = (2.0 / a) * h.h1a - h.h0a;
   const c64 h2b = (2.0 / b) * h.h1b - h.h0b;
   chi = h2a - (beta * beta) * h2b;
+}
+
+// All kernel ingredients at one point: H0(a), H1(a), H0(b), E, chi.
+__host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b, c64& E,
+                                              c64& chi) {
+  if (a < kSeriesSwitch) {
+    const double w = 0.25 * a * a;
+    const double wb = sc.beta * sc.beta * w;
+    const double L = log(0.5 * a);
+    const double tp = 2.0 / kPi;
+    const double j0 = horner(sc.c[0], w);
+    const double j1 = 0.5 * a * horner(sc.c[2], w);
+    h0a = cmk(j0, tp * ((L + kEulerGamma) * j0 + horner(sc.c[1], w)));
+    h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * horner(sc.c[3], w));
+    const double j0b = horner(sc.c[0], wb);
+    h0b = cmk(j0b, tp * ((L + sc.logbeta + kEulerGamma) * j0b + horner(sc.c[1], wb)));
+    const double p4 = horner(sc.c[4], w);
+    E = cmk(p4, tp * L * p4 + horner(sc.c[5], w));
+    const double p6 = horner(sc.c[6], w);
+    chi = cmk(w * p6, sc.chi0 + w * (tp * L * p6 + horner(sc.c[7], w)));
+    return;
+  }
+  const Hankel2 h = hankel_pair(a, sc.beta * a);
+  h0a = h.h0a;
+  h1a = h.h1a;
+  h0b = h.h0b;
+  e_chi(a, sc.beta, h, E, chi);
 }
 
 }  // namespace fds
