@@ -61,7 +61,8 @@ typedef struct {
   int32_t leaf_nodes;       /* nodes per leaf cell (Section 5.1); default 64 */
   int32_t n_proxy;          /* vertices of each proxy polygon (Section 7.1); default 64 */
   int32_t root_level;       /* level l0 at which the compressed system is solved (Section 7.3); default 1 */
-  int32_t reserved0;
+  int32_t solve_graph;      /* 1: run the solve sweeps as a hipGraph captured once per nrhs on a library
+                               stream (the caller's stream is synchronised first); default 0 */
   double proxy_ratio;       /* proxy radius / cell radius; default 1.5 */
   fds_c64 alpha;            /* Burton-Miller coupling; {0,0} selects i / (mu k_T) */
   int32_t use_alpha;        /* 0: alpha = i/(mu k_T); 1: use ``alpha`` as given (0 allowed) */

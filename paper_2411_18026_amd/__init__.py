@@ -38,7 +38,7 @@ class _Geometry(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("leaf_nodes", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("root_level", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("proxy_ratio", ctypes.c_double), ("alpha", _C64),
+                ("solve_graph", ctypes.c_int32), ("proxy_ratio", ctypes.c_double), ("alpha", _C64),
                 ("use_alpha", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
@@ -109,10 +109,11 @@ def _geometry(curves):
     return g, (n, xy)
 
 
-def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None):
+def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
+    o.solve_graph = int(bool(solve_graph))
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
@@ -138,10 +139,10 @@ class Factor:
     """Factorisation of the Galerkin Burton-Miller system of a scatterer."""
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
-                 alpha=None, stream=None):
+                 alpha=None, stream=None, solve_graph=False):
         L = load()
         g, self._keep = _geometry(curves)
-        o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha)
+        o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))

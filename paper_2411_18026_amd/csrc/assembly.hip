@@ -32,6 +32,8 @@
 // Pair results are 16 complex numbers [a][b][i][j] stored
 // structure-of-arrays; the gather order is fixed, so results are
 // bit-reproducible.
+#include <algorithm>
+
 #include "assembly.hpp"
 
 namespace fds {
@@ -296,15 +298,12 @@ __device__ inline void decode(unsigned long long key, const Job* jobs, const int
 
 // ------------------------------------------------------------------ regular pairs
 template <int Q>
-__global__ void __launch_bounds__(128) k_regular(const unsigned long long* __restrict__ list, int count,
-                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
-                                                 const Elem* __restrict__ elems, MatConst m,
-                                                 c64* __restrict__ res, int64_t np) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+__device__ inline void regular_pair(unsigned long long key, const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                    const Elem* __restrict__ elems, const MatConst& m, c64* __restrict__ res,
+                                    int64_t np) {
   Job jb;
   int ie, je, ge, gf;
-  decode(list[t], jobs, elist, jb, ie, je, ge, gf);
+  decode(key, jobs, elist, jb, ie, je, ge, gf);
   const Elem e = elems[ge];
   const Elem f = elems[gf];
   const double* g = (Q == 4) ? c_quad.g4 : (Q == 6 ? c_quad.g6 : c_quad.g10);
@@ -334,6 +333,18 @@ __global__ void __launch_bounds__(128) k_regular(const unsigned long long* __res
       for (int k = 0; k < 4; ++k) res[(aa * 8 + bb * 4 + k) * np + slot] = acc_final(A, aa, bb, k, e, f);
 }
 
+// grid-stride over the class list; its length is read on the device
+template <int Q>
+__global__ void __launch_bounds__(128) k_regular(const unsigned long long* __restrict__ list,
+                                                 const unsigned int* __restrict__ count_ptr,
+                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                                 const Elem* __restrict__ elems, MatConst m,
+                                                 c64* __restrict__ res, int64_t np) {
+  const int64_t count = min((int64_t)*count_ptr, np);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+    regular_pair<Q>(list[t], jobs, elist, elems, m, res, np);
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -342,16 +353,31 @@ __device__ inline double wave_sum(double v) {
 
 // ------------------------------------------------------------------ singular pairs
 template <int C>
-__global__ void __launch_bounds__(256) k_special(const unsigned long long* __restrict__ list, int count,
+__device__ inline void special_pair(unsigned long long key, int lane, const Job* __restrict__ jobs,
+                                    const int* __restrict__ elist, const Elem* __restrict__ elems, const MatConst& m,
+                                    c64* __restrict__ res, int64_t np);
+
+// one wavefront per pair, grid-stride over the class list
+template <int C>
+__global__ void __launch_bounds__(256) k_special(const unsigned long long* __restrict__ list,
+                                                 const unsigned int* __restrict__ count_ptr,
                                                  const Job* __restrict__ jobs, const int* __restrict__ elist,
                                                  const Elem* __restrict__ elems, MatConst m,
                                                  c64* __restrict__ res, int64_t np) {
-  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t count = min((int64_t)*count_ptr, np);
   const int lane = threadIdx.x & 63;
-  if (wid >= count) return;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < count; w += nw)
+    special_pair<C>(list[w], lane, jobs, elist, elems, m, res, np);
+}
+
+template <int C>
+__device__ inline void special_pair(unsigned long long key, int lane, const Job* __restrict__ jobs,
+                                    const int* __restrict__ elist, const Elem* __restrict__ elems, const MatConst& m,
+                                    c64* __restrict__ res, int64_t np) {
   Job jb;
   int ie, je, ge, gf;
-  decode(list[wid], jobs, elist, jb, ie, je, ge, gf);
+  decode(key, jobs, elist, jb, ie, je, ge, gf);
   const Elem e = elems[ge];
   const Elem f = elems[gf];
   PairAcc A;
@@ -525,6 +551,8 @@ void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int*
 
 int classify_tile_size() { return kClsTile; }
 
+// Class list lengths stay on the device (``counts``); grids are sized from
+// the batch's pair count and the kernels stride over their list.
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
                   const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
                   hipEvent_t* ev) {
@@ -532,30 +560,20 @@ void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned i
   auto mark = [&](int i) {
     if (ev) FDS_HIP(hipEventRecord(ev[i], s));
   };
+  const unsigned greg = (unsigned)std::min<int64_t>((np + 127) / 128, 4096);
+  const unsigned gspc = (unsigned)std::min<int64_t>((np + 3) / 4, 2048);
   mark(0);
-  if (counts[kQ4]) {
-    k_regular<4><<<(counts[kQ4] + 127) / 128, 128, 0, s>>>(lists + kQ4 * cap, counts[kQ4], jobs, elist, elems, m, res, np);
-  }
+  k_regular<4><<<greg, 128, 0, s>>>(lists + kQ4 * cap, counts + kQ4, jobs, elist, elems, m, res, np);
   mark(1);
-  if (counts[kQ6]) {
-    k_regular<6><<<(counts[kQ6] + 127) / 128, 128, 0, s>>>(lists + kQ6 * cap, counts[kQ6], jobs, elist, elems, m, res, np);
-  }
+  k_regular<6><<<greg, 128, 0, s>>>(lists + kQ6 * cap, counts + kQ6, jobs, elist, elems, m, res, np);
   mark(2);
-  if (counts[kQ10]) {
-    k_regular<10><<<(counts[kQ10] + 127) / 128, 128, 0, s>>>(lists + kQ10 * cap, counts[kQ10], jobs, elist, elems, m, res, np);
-  }
+  k_regular<10><<<greg, 128, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
   mark(3);
-  if (counts[kCoinc]) {
-    k_special<kCoinc><<<(counts[kCoinc] + 3) / 4, 256, 0, s>>>(lists + kCoinc * cap, counts[kCoinc], jobs, elist, elems, m, res, np);
-  }
+  k_special<kCoinc><<<gspc, 256, 0, s>>>(lists + kCoinc * cap, counts + kCoinc, jobs, elist, elems, m, res, np);
   mark(4);
-  if (counts[kAdjNext]) {
-    k_special<kAdjNext><<<(counts[kAdjNext] + 3) / 4, 256, 0, s>>>(lists + kAdjNext * cap, counts[kAdjNext], jobs, elist, elems, m, res, np);
-  }
+  k_special<kAdjNext><<<gspc, 256, 0, s>>>(lists + kAdjNext * cap, counts + kAdjNext, jobs, elist, elems, m, res, np);
   mark(5);
-  if (counts[kAdjPrev]) {
-    k_special<kAdjPrev><<<(counts[kAdjPrev] + 3) / 4, 256, 0, s>>>(lists + kAdjPrev * cap, counts[kAdjPrev], jobs, elist, elems, m, res, np);
-  }
+  k_special<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
   mark(6);
   FDS_HIP(hipGetLastError());
 }

@@ -40,29 +40,30 @@ struct BlockReq {
   std::vector<int> rpos, cpos;   // empty = identity
 };
 
-class DeviceArena;
+class Workspace;
 
-// Batches block requests, runs classify / pair / gather kernels, writes the
-// blocks into ``out`` (a device array).  Splits the batch so that the pair
-// scratch stays below ``max_pairs`` element pairs.
+// Timing and work counts of the assembly launches.  Events and the device
+// class counters of every batch are recorded without synchronising;
+// ``resolve`` (after the stream has been synchronised) turns them into
+// seconds and evaluation counts.
 struct AssemblyStats {
+  static constexpr int kMaxBatches = 8192;
   double seconds = 0.0;
   int64_t evals = 0;
   double class_seconds[kNumClass] = {0, 0, 0, 0, 0, 0};
   int64_t class_evals[kNumClass] = {0, 0, 0, 0, 0, 0};
   int64_t class_launches[kNumClass] = {0, 0, 0, 0, 0, 0};
-  void add(const AssemblyStats& o) {
-    seconds += o.seconds;
-    evals += o.evals;
-    for (int c = 0; c < kNumClass; ++c) {
-      class_seconds[c] += o.class_seconds[c];
-      class_evals[c] += o.class_evals[c];
-      class_launches[c] += o.class_launches[c];
-    }
-  }
+  unsigned int* d_counts = nullptr;       // kMaxBatches x kNumClass device counters
+  std::vector<std::vector<hipEvent_t>> pending;   // per batch: start, 7 class marks, end
+  void resolve(hipStream_t s);
+  ~AssemblyStats();
 };
 
+// Batches block requests, runs classify / pair / gather kernels, writes the
+// blocks into ``out`` (a device array).  Splits the work so that the pair
+// scratch stays below ``max_pairs`` element pairs.  Asynchronous on the
+// workspace stream.
 void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
-                     hipStream_t s, AssemblyStats* st, int64_t max_pairs = 24000000);
+                     Workspace& ws, AssemblyStats* st, int64_t max_pairs = 24000000);
 
 }  // namespace fds

@@ -104,13 +104,39 @@ QuadTables make_quad_tables() {
 
 static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts, kNAdjPts};
 
+void AssemblyStats::resolve(hipStream_t s) {
+  if (pending.empty()) return;
+  FDS_HIP(hipStreamSynchronize(s));
+  std::vector<unsigned int> cnt(pending.size() * kNumClass);
+  FDS_HIP(hipMemcpy(cnt.data(), d_counts, cnt.size() * sizeof(unsigned), hipMemcpyDeviceToHost));
+  for (size_t b = 0; b < pending.size(); ++b) {
+    auto& ev = pending[b];
+    float ms = 0.f;
+    FDS_HIP(hipEventElapsedTime(&ms, ev[0], ev[8]));
+    seconds += 1e-3 * ms;
+    for (int c = 0; c < kNumClass; ++c) {
+      const unsigned n = cnt[b * kNumClass + c];
+      evals += (int64_t)n * kPointsPerClass[c];
+      class_evals[c] += (int64_t)n * kPointsPerClass[c];
+      if (n) class_launches[c] += 1;
+      float cm = 0.f;
+      FDS_HIP(hipEventElapsedTime(&cm, ev[1 + c], ev[2 + c]));
+      class_seconds[c] += 1e-3 * cm;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  pending.clear();
+}
+
+AssemblyStats::~AssemblyStats() {
+  for (auto& ev : pending)
+    for (auto e : ev) (void)hipEventDestroy(e);
+}
+
 void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
-                     hipStream_t s, AssemblyStats* st, int64_t max_pairs) {
+                     Workspace& ws, AssemblyStats* st, int64_t max_pairs) {
+  hipStream_t s = ws.stream();
   size_t i0 = 0;
-  hipEvent_t ev0, ev1, evc[7];
-  FDS_HIP(hipEventCreate(&ev0));
-  FDS_HIP(hipEventCreate(&ev1));
-  for (auto& e : evc) FDS_HIP(hipEventCreate(&e));
   while (i0 < reqs.size()) {
     // batch [i0, i1)
     size_t i1 = i0;
@@ -165,41 +191,36 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
       pair_off += npj;
     }
     if (pos.empty()) pos.push_back(0);
-    DevBuf<Job> d_jobs(jobs);
-    DevBuf<int> d_elist(elist), d_pos(pos);
-    DevBuf<Dof> d_dofs(dofs);
-    DevBuf<Tile> d_pt(ptiles), d_ot(otiles);
-    DevBuf<unsigned long long> d_lists((size_t)kNumClass * np);
-    DevBuf<unsigned int> d_cnt(kNumClass);
-    DevBuf<c64> d_res((size_t)16 * np);
-    FDS_HIP(hipMemsetAsync(d_cnt.p, 0, kNumClass * sizeof(unsigned), s));
-    FDS_HIP(hipEventRecord(ev0, s));
-    launch_classify(d_pt.p, (int)ptiles.size(), d_jobs.p, d_elist.p, d_elems, d_lists.p, np, d_cnt.p, s);
-    unsigned int cnt[kNumClass];
-    FDS_HIP(hipMemcpyAsync(cnt, d_cnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
-    FDS_HIP(hipStreamSynchronize(s));
-    launch_pairs(d_lists.p, np, cnt, d_jobs.p, d_elist.p, d_elems, m, d_res.p, np, s, evc);
-    launch_gather(d_ot.p, (int)otiles.size(), d_jobs.p, d_dofs.p, d_pos.p, d_res.p, np, d_out, s);
-    FDS_HIP(hipEventRecord(ev1, s));
-    FDS_HIP(hipEventSynchronize(ev1));
-    float ms = 0.f;
-    FDS_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    if (st) {
-      st->seconds += 1e-3 * ms;
-      for (int c = 0; c < kNumClass; ++c) {
-        st->evals += (int64_t)cnt[c] * kPointsPerClass[c];
-        st->class_evals[c] += (int64_t)cnt[c] * kPointsPerClass[c];
-        if (cnt[c]) st->class_launches[c] += 1;
-        float cm = 0.f;
-        FDS_HIP(hipEventElapsedTime(&cm, evc[c], evc[c + 1]));
-        st->class_seconds[c] += 1e-3 * cm;
-      }
+    Job* d_jobs = ws.upload("asm_jobs", jobs);
+    int* d_elist = ws.upload("asm_elist", elist);
+    int* d_pos = ws.upload("asm_pos", pos);
+    Dof* d_dofs = ws.upload("asm_dofs", dofs);
+    Tile* d_pt = ws.upload("asm_ptiles", ptiles);
+    Tile* d_ot = ws.upload("asm_otiles", otiles);
+    unsigned long long* d_lists = ws.get<unsigned long long>("asm_lists", (size_t)kNumClass * np);
+    c64* d_res = ws.get<c64>("asm_res", (size_t)16 * np);
+    unsigned int* d_cnt;
+    std::vector<hipEvent_t> ev;
+    if (st && (int)st->pending.size() < AssemblyStats::kMaxBatches) {
+      if (!st->d_counts)
+        st->d_counts = ws.get<unsigned int>("asm_counts", (size_t)AssemblyStats::kMaxBatches * kNumClass);
+      d_cnt = st->d_counts + st->pending.size() * kNumClass;
+      ev.resize(9);
+      for (auto& e : ev) FDS_HIP(hipEventCreate(&e));
+    } else {
+      d_cnt = ws.get<unsigned int>("asm_cnt_tmp", kNumClass);
+    }
+    FDS_HIP(hipMemsetAsync(d_cnt, 0, kNumClass * sizeof(unsigned), s));
+    if (!ev.empty()) FDS_HIP(hipEventRecord(ev[0], s));
+    launch_classify(d_pt, (int)ptiles.size(), d_jobs, d_elist, d_elems, d_lists, np, d_cnt, s);
+    launch_pairs(d_lists, np, d_cnt, d_jobs, d_elist, d_elems, m, d_res, np, s, ev.empty() ? nullptr : ev.data() + 1);
+    launch_gather(d_ot, (int)otiles.size(), d_jobs, d_dofs, d_pos, d_res, np, d_out, s);
+    if (!ev.empty()) {
+      FDS_HIP(hipEventRecord(ev[8], s));
+      st->pending.push_back(ev);
     }
     i0 = i1;
   }
-  FDS_HIP(hipEventDestroy(ev0));
-  FDS_HIP(hipEventDestroy(ev1));
-  for (auto& e : evc) FDS_HIP(hipEventDestroy(e));
 }
 
 }  // namespace fds

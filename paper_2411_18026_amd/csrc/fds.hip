@@ -28,13 +28,18 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <map>
+#include <memory>
 #include <unordered_map>
 #include <vector>
+#include <cstdio>
+#include <cstdlib>
 
 #include "../../include/fds.h"
 #include "assembly.hpp"
 #include "devmem.hpp"
 #include "linalg.hpp"
+#include "parallel.hpp"
 
 namespace fds {
 
@@ -135,18 +140,20 @@ struct DevGeom {
   }
 };
 
-// Side of a block from a list of boundary DOFs (2 t + i).
+// Side of a block from a list of boundary DOFs (2 t + i).  A per-thread slot
+// array over the boundary elements deduplicates the elements of the hats.
 static Side side_from_dofs(const Geometry& G, const std::vector<int64_t>& dofs) {
+  static thread_local std::vector<int> slot;
+  if ((int)slot.size() < G.n_nodes) slot.assign(G.n_nodes, -1);
   Side sd;
-  std::unordered_map<int, int> idx;
-  idx.reserve(dofs.size() * 2);
+  sd.elems.reserve(dofs.size() + 2);
   auto get = [&](int e) {
-    auto it = idx.find(e);
-    if (it != idx.end()) return it->second;
-    const int k = (int)sd.elems.size();
-    sd.elems.push_back(e);
-    idx.emplace(e, k);
-    return k;
+    int& s = slot[e];
+    if (s < 0) {
+      s = (int)sd.elems.size();
+      sd.elems.push_back(e);
+    }
+    return s;
   };
   sd.dofs.reserve(dofs.size());
   for (int64_t d : dofs) {
@@ -155,6 +162,7 @@ static Side side_from_dofs(const Geometry& G, const std::vector<int64_t>& dofs) 
     const int eR = get(t);                // element (t, next(t))
     sd.dofs.push_back(Dof{eL, eR, (int)(d & 1), 0});
   }
+  for (int e : sd.elems) slot[e] = -1;
   return sd;
 }
 
@@ -173,7 +181,18 @@ static void side_append(const Geometry& G, Side& sd, const std::vector<int64_t>&
   for (auto d : add.dofs) sd.dofs.push_back(Dof{d.eL + b, d.eR + b, d.comp, 0});
 }
 
+
 // ------------------------------------------------------------------ factor data
+// Device-resident solve plan of one compressed level (built once per factor).
+struct SolveLevel {
+  DevBuf<SolveDesc> lu;                      // g_i = A_i^{-1} f_i (ncol given at solve time)
+  DevBuf<GemmDesc> g_v, g_at, g_dn1, g_dn2;  // V g, A~ (V g), A~ y - f~, g + X f~
+  DevBuf<GemmTile> t_v, t_at, t_dn1, t_dn2;
+  int n_lu = 0, n_tv = 0, n_tat = 0, n_tdn1 = 0, n_tdn2 = 0, bmax = 0;
+  DevBuf<int64_t> up_src, up_dst;            // rows of f~ -> rows of the parent's F
+  int64_t n_up = 0;
+};
+
 struct CellLevel {
   int lev = 0, n = 0;                            // cells 2^lev - 1 + q, q < n
   std::vector<std::vector<int64_t>> rows, cols;  // active DOFs (component-major)
@@ -181,6 +200,7 @@ struct CellLevel {
   std::vector<int64_t> a_off;                    // A_i / LU(A_i) (ld = b)
   std::vector<int64_t> piv_off;
   int64_t a_tot = 0, piv_tot = 0;
+  int bmax = 0;
   // compression results (levels > l0)
   std::vector<int> k0, k1, r;
   std::vector<int> kr0, kc0, kr1, kc1;           // ranks at tolerance
@@ -193,7 +213,8 @@ struct CellLevel {
   std::vector<int64_t> f_off, t_off;
   int64_t B = 0, R = 0;
   // parent position of each skeleton entry (set when the parent is built)
-  std::vector<std::vector<int>> ppos;            // per cell: position in parent's rows of its skeleton rows
+  std::vector<std::vector<int>> ppos;
+  SolveLevel plan;
 };
 
 // Compressed system at l0: diagonal blocks are the cells' A_i, the rest are
@@ -202,6 +223,12 @@ struct Root {
   int n = 0;
   DevBuf<c64> A;
   DevBuf<int> piv;
+  DevBuf<SolveDesc> desc;
+};
+
+struct TimedSpan {
+  hipEvent_t a, b;
+  int what;   // 0 id, 1 merge, 2 root
 };
 
 }  // namespace fds
@@ -216,13 +243,40 @@ struct fds_factor_s {
   std::vector<fds::CellLevel> levels;   // index = level
   fds::Root root;
   fds::AssemblyStats ast;
+  std::vector<fds::TimedSpan> spans;
   fds_stats st{};
   hipStream_t stream = nullptr;
+  fds::Workspace ws;
+  fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
+  std::map<int, hipGraphExec_t> graphs;     // captured solve sweeps per nrhs
+  hipStream_t gstream = nullptr;            // library stream for graph capture and replay
+  ~fds_factor_s() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (gstream) {
+      (void)hipStreamSynchronize(gstream);
+      (void)hipStreamDestroy(gstream);
+    }
+    for (auto& sp : spans) {
+      (void)hipEventDestroy(sp.a);
+      (void)hipEventDestroy(sp.b);
+    }
+  }
 };
 
 namespace fds {
 
 using Factor = fds_factor_s;
+
+static void span_begin(Factor& F, int what) {
+  TimedSpan sp{};
+  FDS_HIP(hipEventCreate(&sp.a));
+  FDS_HIP(hipEventCreate(&sp.b));
+  sp.what = what;
+  FDS_HIP(hipEventRecord(sp.a, F.stream));
+  F.spans.push_back(sp);
+}
+
+static void span_end(Factor& F) { FDS_HIP(hipEventRecord(F.spans.back().b, F.stream)); }
 
 static void build_tree(Factor& F) {
   const int N = F.G.n_nodes, leaf = F.opt.leaf_nodes;
@@ -261,8 +315,10 @@ static void layout_blocks(CellLevel& lv) {
   lv.piv_off.resize(lv.n);
   lv.f_off.resize(lv.n);
   lv.a_tot = lv.piv_tot = lv.B = 0;
+  lv.bmax = 0;
   for (int q = 0; q < lv.n; ++q) {
     lv.b[q] = (int)lv.rows[q].size();
+    lv.bmax = std::max(lv.bmax, lv.b[q]);
     int c0 = 0;
     for (auto d : lv.cols[q]) c0 += (d & 1) == 0;
     lv.n0[q] = c0;
@@ -277,8 +333,23 @@ static void layout_blocks(CellLevel& lv) {
   lv.piv = DevBuf<int>((size_t)std::max<int64_t>(lv.piv_tot, 1));
 }
 
-static void check_info(const DevBuf<int>& info, size_t n, hipStream_t s) {
-  auto h = info.download(n, s);
+// Host wall-time of the factorisation's phases (printed when FDS_TIMING is set).
+static double g_host_t[8];
+static const char* g_host_name[8] = {"disks+near", "interaction requests", "device waits", "parent merge",
+                                     "leaf blocks", "root", "solve plan", "other"};
+struct HostTimer {
+  int k;
+  std::chrono::steady_clock::time_point t0;
+  explicit HostTimer(int kk) : k(kk), t0(std::chrono::steady_clock::now()) {}
+  ~HostTimer() { g_host_t[k] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+static void check_info(Workspace& ws, const int* d_info, size_t n) {
+  HostTimer ht(2);
+  if (n == 0) return;
+  std::vector<int> h(n);
+  FDS_HIP(hipMemcpyAsync(h.data(), d_info, n * sizeof(int), hipMemcpyDeviceToHost, ws.stream()));
+  FDS_HIP(hipStreamSynchronize(ws.stream()));
   for (int v : h)
     if (v) throw Error(FDS_ESINGULAR, "singular block in LU");
 }
@@ -371,29 +442,36 @@ struct NodeGrid {
   }
 };
 
-static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
-  float ms = 0.f;
-  FDS_HIP(hipEventElapsedTime(&ms, a, b));
-  return ms;
+template <typename T>
+static std::vector<T> download(Workspace& ws, const T* d, size_t n) {
+  HostTimer ht(2);
+  std::vector<T> h(n);
+  if (n) {
+    FDS_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, ws.stream()));
+    FDS_HIP(hipStreamSynchronize(ws.stream()));
+  }
+  return h;
 }
 
 static void compress_level(Factor& F, int lev) {
   const Geometry& G = F.G;
   CellLevel& lv = F.levels[lev];
+  Workspace& ws = F.ws;
   hipStream_t s = F.stream;
   const int np = F.opt.n_proxy;
   const int n = lv.n;
+  auto ht0 = std::make_unique<HostTimer>(0);
   // proxy disks
   std::vector<double> crd(3 * n);
   double maxrho = 0.0;
-  for (int q = 0; q < n; ++q) {
+  parallel_for(n, [&](int q) {
     double cx, cy, R;
     cell_disk(G, lv.rows[q], lv.cols[q], cx, cy, R);
     crd[3 * q] = cx;
     crd[3 * q + 1] = cy;
     crd[3 * q + 2] = F.opt.proxy_ratio * R;
-    maxrho = std::max(maxrho, crd[3 * q + 2]);
-  }
+  });
+  for (int q = 0; q < n; ++q) maxrho = std::max(maxrho, crd[3 * q + 2]);
   // near sets via a node grid
   std::vector<int> row_owner(2 * (size_t)G.n_nodes, -1), col_owner(2 * (size_t)G.n_nodes, -1);
   for (int q = 0; q < n; ++q) {
@@ -403,35 +481,31 @@ static void compress_level(Factor& F, int lev) {
   NodeGrid grid;
   grid.build(G, std::max(maxrho, 4.0 * G.hmax));
   std::vector<std::vector<int64_t>> near_r(n), near_c(n);
-  std::vector<char> seen(G.n_nodes, 0);
-  for (int q = 0; q < n; ++q) {
+  parallel_for(n, [&](int q) {
     const double cx = crd[3 * q], cy = crd[3 * q + 1], rho = crd[3 * q + 2];
+    // every node sits in exactly one grid bucket: no duplicates
     std::vector<int> cand;
-    grid.query(cx, cy, rho + G.hmax, [&](int t) {
-      if (!seen[t]) {
-        seen[t] = 1;
-        cand.push_back(t);
-      }
-    });
-    for (int t : cand) seen[t] = 0;
+    grid.query(cx, cy, rho + G.hmax, [&](int t) { cand.push_back(t); });
     std::sort(cand.begin(), cand.end());
+    const double rin = rho, rout = rho + G.hmax;
     for (int t : cand) {
-      if (!support_meets(G, t, cx, cy, rho)) continue;
+      const double dx = G.xy[2 * t] - cx, dy = G.xy[2 * t + 1] - cy;
+      const double d2 = dx * dx + dy * dy;
+      // the support lies within hmax of the node: decide cheaply away from the circle
+      if (d2 >= rout * rout) continue;
+      if (d2 >= rin * rin && !support_meets(G, t, cx, cy, rho)) continue;
       for (int c = 0; c < 2; ++c) {
         const int64_t d = 2 * (int64_t)t + c;
         if (row_owner[d] >= 0 && row_owner[d] != q) near_r[q].push_back(d);
         if (col_owner[d] >= 0 && col_owner[d] != q) near_c[q].push_back(d);
       }
     }
-  }
+  });
+  ht0.reset();
   // proxy elements
   const int64_t pbase = F.DG.n_gamma;
   if (pbase + (int64_t)n * np > F.DG.cap) throw Error(FDS_ENOMEM, "proxy element table too small");
-  {
-    DevBuf<double> dcrd(crd);
-    launch_proxy_elems(dcrd.p, n, np, G.n_curves, F.DG.elems.p + pbase, s);
-    FDS_HIP(hipStreamSynchronize(s));
-  }
+  launch_proxy_elems(ws.upload("crd", crd), n, np, G.n_curves, F.DG.elems.p + pbase, s);
   // interaction matrices: MV = A(proxy + near rows, cols) and MUt = A(rows, proxy + near cols)^T
   std::vector<int64_t> mv_off(n), mu_off(n);
   std::vector<int> mv_m(n), mu_m(n);
@@ -444,42 +518,40 @@ static void compress_level(Factor& F, int lev) {
     mu_off[q] = mu_tot;
     mu_tot += (int64_t)mu_m[q] * lv.b[q];
   }
-  DevBuf<c64> MV((size_t)mv_tot), MU((size_t)mu_tot);
-  std::vector<BlockReq> reqs;
-  reqs.reserve(2 * n);
-  for (int q = 0; q < n; ++q) {
-    BlockReq a;
-    side_add_proxy(a.rows, (int)(pbase + (int64_t)q * np), np);
-    side_append(G, a.rows, near_r[q]);
-    a.cols = side_from_dofs(G, lv.cols[q]);
-    a.out_off = mv_off[q];
-    a.rs = 1;
-    a.cs = mv_m[q];
-    reqs.push_back(std::move(a));
+  auto ht1 = std::make_unique<HostTimer>(1);
+  c64* MV = ws.get<c64>("MV", (size_t)mv_tot);
+  c64* MU = ws.get<c64>("MU", (size_t)mu_tot);
+  {
+    std::vector<BlockReq> reqs(n);
+    parallel_for(n, [&](int q) {
+      BlockReq& a = reqs[q];
+      side_add_proxy(a.rows, (int)(pbase + (int64_t)q * np), np);
+      side_append(G, a.rows, near_r[q]);
+      a.cols = side_from_dofs(G, lv.cols[q]);
+      a.out_off = mv_off[q];
+      a.rs = 1;
+      a.cs = mv_m[q];
+    });
+    assemble_blocks(reqs, F.DG.elems.p, F.m, MV, ws, &F.ast);
   }
-  AssemblyStats ast;
-  assemble_blocks(reqs, F.DG.elems.p, F.m, MV.p, s, &ast);
-  reqs.clear();
-  for (int q = 0; q < n; ++q) {
-    BlockReq a;
-    a.rows = side_from_dofs(G, lv.rows[q]);
-    side_add_proxy(a.cols, (int)(pbase + (int64_t)q * np), np);
-    side_append(G, a.cols, near_c[q]);
-    a.out_off = mu_off[q];
-    a.rs = mu_m[q];   // transposed storage
-    a.cs = 1;
-    reqs.push_back(std::move(a));
+  {
+    std::vector<BlockReq> reqs(n);
+    parallel_for(n, [&](int q) {
+      BlockReq& a = reqs[q];
+      a.rows = side_from_dofs(G, lv.rows[q]);
+      side_add_proxy(a.cols, (int)(pbase + (int64_t)q * np), np);
+      side_append(G, a.cols, near_c[q]);
+      a.out_off = mu_off[q];
+      a.rs = mu_m[q];   // transposed storage
+      a.cs = 1;
+    });
+    assemble_blocks(reqs, F.DG.elems.p, F.m, MU, ws, &F.ast);
   }
-  assemble_blocks(reqs, F.DG.elems.p, F.m, MU.p, s, &ast);
-  reqs.clear();
-  F.ast.add(ast);
 
-  // IDs: problem 4q + {0: V comp0, 1: V comp1, 2: U comp0, 3: U comp1}
-  hipEvent_t e0, e1;
-  FDS_HIP(hipEventCreate(&e0));
-  FDS_HIP(hipEventCreate(&e1));
-  FDS_HIP(hipEventRecord(e0, s));
-  std::vector<CpqrDesc> qd(4 * n);
+  ht1.reset();
+  // IDs: per cell V comp0, V comp1 (in MV) and U comp0, U comp1 (in MU^T)
+  span_begin(F, 0);
+  std::vector<CpqrDesc> qv, qu;
   std::vector<int64_t> pvo(4 * n);
   int64_t pv_tot = 0;
   for (int q = 0; q < n; ++q) {
@@ -500,22 +572,17 @@ static void compress_level(Factor& F, int lev) {
       d.k_start = 0;
       d.k_end = std::min(d.m, d.n);
       d.stop_at_tol = 1;
-      qd[4 * q + k] = d;
+      (isV ? qv : qu).push_back(d);
     }
   }
-  // U-problems live in MU, V-problems in MV: run as two batches
-  std::vector<CpqrDesc> qv, qu;
-  for (int q = 0; q < n; ++q) {
-    qv.push_back(qd[4 * q]);
-    qv.push_back(qd[4 * q + 1]);
-    qu.push_back(qd[4 * q + 2]);
-    qu.push_back(qd[4 * q + 3]);
-  }
-  DevBuf<int> dpiv((size_t)std::max<int64_t>(pv_tot, 1)), drank_v(2 * n), drank_u(2 * n);
-  launch_cpqr(qv, MV.p, dpiv.p, F.tol, drank_v.p, s);
-  launch_cpqr(qu, MU.p, dpiv.p, F.tol, drank_u.p, s);
-  auto rv = drank_v.download(2 * n, s);
-  auto ru = drank_u.download(2 * n, s);
+  check_cpqr_sizes(qv);
+  check_cpqr_sizes(qu);
+  int* dpiv = ws.get<int>("id_piv", (size_t)pv_tot);
+  int* drank = ws.get<int>("id_rank", (size_t)4 * n);
+  launch_cpqr(ws.upload("cpqr_v", qv), 2 * n, MV, dpiv, F.tol, drank, s);
+  launch_cpqr(ws.upload("cpqr_u", qu), 2 * n, MU, dpiv, F.tol, drank + 2 * n, s);
+  auto rk = download(ws, drank, (size_t)4 * n);
+  std::vector<int> rv(rk.begin(), rk.begin() + 2 * n), ru(rk.begin() + 2 * n, rk.end());
   lv.kc0.resize(n);
   lv.kc1.resize(n);
   lv.kr0.resize(n);
@@ -552,17 +619,13 @@ static void compress_level(Factor& F, int lev) {
     lv.k0[q] = kk[0];
     lv.k1[q] = kk[1];
   }
-  if (!ev.empty()) {
-    DevBuf<int> tmp(ev.size());
-    launch_cpqr(ev, MV.p, dpiv.p, F.tol, tmp.p, s);
-    auto h = tmp.download(ev.size(), s);
+  if (!ev.empty() || !eu.empty()) {
+    int* drank2 = ws.get<int>("id_rank2", ev.size() + eu.size());
+    launch_cpqr(ws.upload("cpqr_v2", ev), (int)ev.size(), MV, dpiv, F.tol, drank2, s);
+    launch_cpqr(ws.upload("cpqr_u2", eu), (int)eu.size(), MU, dpiv, F.tol, drank2 + ev.size(), s);
+    auto h = download(ws, drank2, ev.size() + eu.size());
     for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
-  }
-  if (!eu.empty()) {
-    DevBuf<int> tmp(eu.size());
-    launch_cpqr(eu, MU.p, dpiv.p, F.tol, tmp.p, s);
-    auto h = tmp.download(eu.size(), s);
-    for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[i];
+    for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[ev.size() + i];
   }
   for (int q = 0; q < n; ++q) {
     // a zero pivot can end a QR early: never use more pivots than both reached
@@ -570,7 +633,7 @@ static void compress_level(Factor& F, int lev) {
     lv.k1[q] = std::min(lv.k1[q], std::min(rv[2 * q + 1], ru[2 * q + 1]));
     lv.r[q] = lv.k0[q] + lv.k1[q];
   }
-  auto hpiv = dpiv.download(pv_tot, s);
+  auto hpiv = download(ws, dpiv, (size_t)pv_tot);
   // skeletons, layouts
   lv.rskel.assign(n, {});
   lv.cskel.assign(n, {});
@@ -580,6 +643,7 @@ static void compress_level(Factor& F, int lev) {
   lv.s_piv_off.resize(n);
   lv.t_off.resize(n);
   lv.x_tot = lv.at_tot = lv.v_tot = lv.s_piv_tot = lv.R = 0;
+  int rmax = 0;
   for (int q = 0; q < n; ++q) {
     const int c0 = lv.n0[q];
     const int kk[2] = {lv.k0[q], lv.k1[q]};
@@ -593,6 +657,7 @@ static void compress_level(Factor& F, int lev) {
       }
     }
     const int b = lv.b[q], r = lv.r[q];
+    rmax = std::max(rmax, r);
     lv.x_off[q] = lv.x_tot;
     lv.x_tot += (int64_t)b * r;
     lv.at_off[q] = lv.at_tot;
@@ -619,36 +684,18 @@ static void compress_level(Factor& F, int lev) {
       if (kk[comp] == 0) continue;
       const int roff = comp ? kk[0] : 0;   // skeleton offset
       const int coff = comp ? c0 : 0;      // DOF offset
-      InterpDesc a{};
-      a.a_off = qv[2 * q + comp].a_off;
-      a.piv_off = qv[2 * q + comp].piv_off;
-      a.n = qv[2 * q + comp].n;
-      a.lda = qv[2 * q + comp].lda;
-      a.k = kk[comp];
-      a.d_off = lv.v_off[q] + roff + (int64_t)coff * r;
-      a.d_ld = r;
-      a.transpose = 0;
-      iv.push_back(a);
-      InterpDesc u{};
-      u.a_off = qu[2 * q + comp].a_off;
-      u.piv_off = qu[2 * q + comp].piv_off;
-      u.n = qu[2 * q + comp].n;
-      u.lda = qu[2 * q + comp].lda;
-      u.k = kk[comp];
-      u.d_off = lv.x_off[q] + coff + (int64_t)roff * b;
-      u.d_ld = b;
-      u.transpose = 1;
-      iu.push_back(u);
+      const CpqrDesc& dv = qv[2 * q + comp];
+      iv.push_back(InterpDesc{dv.a_off, dv.piv_off, dv.n, dv.lda, kk[comp], lv.v_off[q] + roff + (int64_t)coff * r, r, 0});
+      const CpqrDesc& du = qu[2 * q + comp];
+      iu.push_back(InterpDesc{du.a_off, du.piv_off, du.n, du.lda, kk[comp], lv.x_off[q] + coff + (int64_t)roff * b, b, 1});
     }
   }
-  launch_interp(iv, MV.p, dpiv.p, lv.V.p, s);
-  launch_interp(iu, MU.p, dpiv.p, lv.X.p, s);
-  FDS_HIP(hipEventRecord(e1, s));
-  FDS_HIP(hipEventSynchronize(e1));
-  F.st.id_seconds += 1e-3 * elapsed_ms(e0, e1);
+  launch_interp(ws.upload("interp_v", iv), (int)iv.size(), MV, dpiv, lv.V.p, s);
+  launch_interp(ws.upload("interp_u", iu), (int)iu.size(), MU, dpiv, lv.X.p, s);
+  span_end(F);
 
   // elimination: LU(A_i); X_i = A_i^{-1} U_i; S_i = V_i X_i; A~_i = S_i^{-1}
-  FDS_HIP(hipEventRecord(e0, s));
+  span_begin(F, 1);
   std::vector<LUDesc> ld(n);
   std::vector<SolveDesc> sd;
   for (int q = 0; q < n; ++q) {
@@ -656,12 +703,15 @@ static void compress_level(Factor& F, int lev) {
     if (lv.r[q] > 0)
       sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
   }
-  DevBuf<int> info(n);
-  launch_lu(ld, lv.A.p, lv.piv.p, info.p, s);
-  check_info(info, n, s);
-  launch_lu_solve(sd, lv.A.p, lv.piv.p, lv.X.p, s);
-  DevBuf<c64> S((size_t)std::max<int64_t>(lv.at_tot, 1));
+  int* info = ws.get<int>("lu_info", (size_t)n);
+  launch_lu(ws.upload("lu_desc", ld), n, lv.A.p, lv.piv.p, info, s);
+  launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, lv.A.p, lv.piv.p, lv.X.p, s);
+  c64* S = ws.get<c64>("S", (size_t)lv.at_tot);
   std::vector<GemmDesc> gd;
+  std::vector<LUDesc> lds;
+  std::vector<SolveDesc> sds;
+  std::vector<int64_t> id_off;
+  std::vector<int> id_n;
   for (int q = 0; q < n; ++q) {
     if (lv.r[q] == 0) continue;
     GemmDesc g{};
@@ -676,35 +726,24 @@ static void compress_level(Factor& F, int lev) {
     g.ldc = lv.r[q];
     g.alpha_re = 1.0;
     gd.push_back(g);
-  }
-  launch_gemm(gd, lv.V.p, lv.X.p, S.p, 0, s);
-  std::vector<LUDesc> lds;
-  std::vector<SolveDesc> sds;
-  std::vector<int64_t> id_off;
-  std::vector<int> id_n;
-  for (int q = 0; q < n; ++q) {
-    if (lv.r[q] == 0) continue;
     lds.push_back(LUDesc{lv.at_off[q], lv.s_piv_off[q], lv.r[q], lv.r[q]});
     sds.push_back(SolveDesc{lv.at_off[q], lv.s_piv_off[q], lv.at_off[q], lv.r[q], lv.r[q], lv.r[q], lv.r[q]});
     id_off.push_back(lv.at_off[q]);
     id_n.push_back(lv.r[q]);
   }
-  DevBuf<int> info2(std::max<size_t>(lds.size(), 1));
-  launch_lu(lds, S.p, lv.s_piv.p, info2.p, s);
-  check_info(info2, lds.size(), s);
+  auto gt = gemm_tiles(gd);
+  launch_gemm(ws.upload("s_desc", gd), ws.upload("s_tiles", gt), (int)gt.size(), rmax, 0, lv.V.p, lv.X.p, S, 0, s);
+  int* info2 = ws.get<int>("lu_info2", std::max<size_t>(lds.size(), 1));
+  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), S, lv.s_piv.p, info2, s);
   {
-    DevBuf<int64_t> doff(id_off);
-    DevBuf<int> dn(id_n);
-    launch_fill_identity((int64_t)id_off.size(), doff.p, dn.p, dn.p, lv.At.p, s);
-    FDS_HIP(hipStreamSynchronize(s));
+    int* dn = ws.upload("id_n", id_n);
+    launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, lv.At.p, s);
   }
   // A~ = S^{-1}: the LU of S (held in S) applied to the identity in At
-  launch_lu_solve(sds, S.p, lv.s_piv.p, lv.At.p, s);
-  FDS_HIP(hipEventRecord(e1, s));
-  FDS_HIP(hipEventSynchronize(e1));
-  F.st.merge_seconds += 1e-3 * elapsed_ms(e0, e1);
-  FDS_HIP(hipEventDestroy(e0));
-  FDS_HIP(hipEventDestroy(e1));
+  launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, lv.At.p, s);
+  span_end(F);
+  check_info(ws, info, n);
+  check_info(ws, info2, lds.size());
   int mr = 0;
   for (int q = 0; q < n; ++q) mr = std::max(mr, std::max(lv.k0[q], lv.k1[q]));
   F.st.max_rank = std::max(F.st.max_rank, mr);
@@ -712,9 +751,11 @@ static void compress_level(Factor& F, int lev) {
 
 // Parent diagonal blocks of level lev-1 from level lev (rearrangement, Section 6.2).
 static void merge_to_parent(Factor& F, int lev) {
+  HostTimer ht(3);
   const Geometry& G = F.G;
   CellLevel& ch = F.levels[lev];
   CellLevel& pa = F.levels[lev - 1];
+  Workspace& ws = F.ws;
   hipStream_t s = F.stream;
   pa.lev = lev - 1;
   pa.n = ch.n / 2;
@@ -782,35 +823,34 @@ static void merge_to_parent(Factor& F, int lev) {
     }
   }
   if (pos.empty()) pos.push_back(0);
-  DevBuf<int> dpos(pos);
-  launch_scatter(sc, dpos.p, ch.At.p, pa.A.p, s);
-  AssemblyStats ast;
-  assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, s, &ast);
-  F.ast.add(ast);
+  auto st = scatter_tiles(sc);
+  launch_scatter(ws.upload("msc_desc", sc), ws.upload("msc_tiles", st), (int)st.size(), ws.upload("msc_pos", pos),
+                 ch.At.p, pa.A.p, s);
+  assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, ws, &F.ast);
 }
 
 // Leaf diagonal blocks.
 static void assemble_leaves(Factor& F) {
+  HostTimer ht(4);
   CellLevel& lv = F.levels[F.L];
   layout_blocks(lv);
-  std::vector<BlockReq> reqs;
-  reqs.reserve(lv.n);
-  for (int q = 0; q < lv.n; ++q) {
-    BlockReq a;
+  std::vector<BlockReq> reqs(lv.n);
+  parallel_for(lv.n, [&](int q) {
+    BlockReq& a = reqs[q];
     a.rows = side_from_dofs(F.G, lv.rows[q]);
     a.cols = a.rows;
     a.out_off = lv.a_off[q];
     a.rs = 1;
     a.cs = lv.b[q];
-    reqs.push_back(std::move(a));
-  }
-  AssemblyStats ast;
-  assemble_blocks(reqs, F.DG.elems.p, F.m, lv.A.p, F.stream, &ast);
-  F.ast.add(ast);
+  });
+  assemble_blocks(reqs, F.DG.elems.p, F.m, lv.A.p, F.ws, &F.ast);
 }
 
-static void factor_root(Factor& F, Root& rt) {
+static void factor_root(Factor& F) {
+  HostTimer ht(5);
   CellLevel& lv = F.levels[F.l0];
+  Root& rt = F.root;
+  Workspace& ws = F.ws;
   hipStream_t s = F.stream;
   rt.n = (int)lv.B;
   rt.A = DevBuf<c64>((size_t)rt.n * rt.n);
@@ -839,23 +879,199 @@ static void factor_root(Factor& F, Root& rt) {
       reqs.push_back(std::move(a));
     }
   }
-  DevBuf<int> dpos(std::vector<int>{0});
-  launch_scatter(sc, dpos.p, lv.A.p, rt.A.p, s);
-  AssemblyStats ast;
-  assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, s, &ast);
-  F.ast.add(ast);
-  hipEvent_t e0, e1;
-  FDS_HIP(hipEventCreate(&e0));
-  FDS_HIP(hipEventCreate(&e1));
-  FDS_HIP(hipEventRecord(e0, s));
-  DevBuf<int> info(1);
-  launch_lu(std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}, rt.A.p, rt.piv.p, info.p, s);
-  FDS_HIP(hipEventRecord(e1, s));
-  FDS_HIP(hipEventSynchronize(e1));
-  F.st.root_seconds += 1e-3 * elapsed_ms(e0, e1);
-  FDS_HIP(hipEventDestroy(e0));
-  FDS_HIP(hipEventDestroy(e1));
-  check_info(info, 1, s);
+  auto st = scatter_tiles(sc);
+  launch_scatter(ws.upload("rsc_desc", sc), ws.upload("rsc_tiles", st), (int)st.size(),
+                 ws.upload("rsc_pos", std::vector<int>{0}), lv.A.p, rt.A.p, s);
+  assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, ws, &F.ast);
+  span_begin(F, 2);
+  int* info = ws.get<int>("root_info", 1);
+  launch_lu(ws.upload("root_lu", std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}), 1, rt.A.p, rt.piv.p, info, s);
+  span_end(F);
+  check_info(ws, info, 1);
+  rt.desc = DevBuf<SolveDesc>(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt.n, rt.n, rt.n, 0}});
+}
+
+// Device descriptors of the solve (ncol = number of right-hand sides is
+// supplied at solve time).
+static void build_solve_plan(Factor& F) {
+  HostTimer ht(6);
+  const int L = F.L, l0 = F.l0;
+  for (int lev = L; lev > l0; --lev) {
+    CellLevel& lv = F.levels[lev];
+    CellLevel& pa = F.levels[lev - 1];
+    SolveLevel& P = lv.plan;
+    std::vector<SolveDesc> sd;
+    std::vector<GemmDesc> gv, gat, gd1, gd2;
+    for (int q = 0; q < lv.n; ++q) {
+      sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.f_off[q], lv.b[q], lv.b[q], (int)lv.B, 0});
+      if (lv.r[q] == 0) continue;
+      GemmDesc a{};   // T = V g
+      a.a_off = lv.v_off[q];
+      a.b_off = lv.f_off[q];
+      a.c_off = lv.t_off[q];
+      a.m = lv.r[q];
+      a.k = lv.b[q];
+      a.lda = lv.r[q];
+      a.ldb = (int)lv.B;
+      a.ldc = (int)lv.R;
+      a.alpha_re = 1.0;
+      gv.push_back(a);
+      GemmDesc b{};   // f~ = A~ T
+      b.a_off = lv.at_off[q];
+      b.b_off = lv.t_off[q];
+      b.c_off = lv.t_off[q];
+      b.m = lv.r[q];
+      b.k = lv.r[q];
+      b.lda = lv.r[q];
+      b.ldb = (int)lv.R;
+      b.ldc = (int)lv.R;
+      b.alpha_re = 1.0;
+      gat.push_back(b);
+      GemmDesc c = b;  // f~ <- A~ y - f~
+      c.beta_re = -1.0;
+      gd1.push_back(c);
+      GemmDesc d{};    // x <- g + X f~
+      d.a_off = lv.x_off[q];
+      d.b_off = lv.t_off[q];
+      d.c_off = lv.f_off[q];
+      d.m = lv.b[q];
+      d.k = lv.r[q];
+      d.lda = lv.b[q];
+      d.ldb = (int)lv.R;
+      d.ldc = (int)lv.B;
+      d.alpha_re = 1.0;
+      d.beta_re = 1.0;
+      gd2.push_back(d);
+    }
+    P.lu = DevBuf<SolveDesc>(sd);
+    P.n_lu = (int)sd.size();
+    P.bmax = lv.bmax;
+    auto tv = gemm_tiles(gv), tat = gemm_tiles(gat), td1 = gemm_tiles(gd1), td2 = gemm_tiles(gd2);
+    P.g_v = DevBuf<GemmDesc>(gv);
+    P.g_at = DevBuf<GemmDesc>(gat);
+    P.g_dn1 = DevBuf<GemmDesc>(gd1);
+    P.g_dn2 = DevBuf<GemmDesc>(gd2);
+    P.t_v = DevBuf<GemmTile>(tv);
+    P.t_at = DevBuf<GemmTile>(tat);
+    P.t_dn1 = DevBuf<GemmTile>(td1);
+    P.t_dn2 = DevBuf<GemmTile>(td2);
+    P.n_tv = (int)tv.size();
+    P.n_tat = (int)tat.size();
+    P.n_tdn1 = (int)td1.size();
+    P.n_tdn2 = (int)td2.size();
+    std::vector<int64_t> si, di;
+    for (int q = 0; q < lv.n; ++q)
+      for (int j = 0; j < lv.r[q]; ++j) {
+        si.push_back(lv.t_off[q] + j);
+        di.push_back(pa.f_off[q / 2] + lv.ppos[q][j]);
+      }
+    P.up_src = DevBuf<int64_t>(si);
+    P.up_dst = DevBuf<int64_t>(di);
+    P.n_up = (int64_t)si.size();
+  }
+  CellLevel& lf = F.levels[L];
+  std::vector<int64_t> rows, cols, iota;
+  for (int q = 0; q < lf.n; ++q) {
+    rows.insert(rows.end(), lf.rows[q].begin(), lf.rows[q].end());
+    cols.insert(cols.end(), lf.cols[q].begin(), lf.cols[q].end());
+  }
+  iota.resize(rows.size());
+  std::iota(iota.begin(), iota.end(), 0);
+  F.leaf_dofs_rows = DevBuf<int64_t>(rows);
+  F.leaf_dofs_cols = DevBuf<int64_t>(cols);
+  F.leaf_iota = DevBuf<int64_t>(iota);
+}
+
+struct SweepBufs {
+  std::vector<c64*> F, T, Y;
+};
+
+// Level vectors of a solve with nrhs columns.  Graph replays use buffers of
+// their own per nrhs so that the captured pointers stay valid.
+static SweepBufs sweep_buffers(Factor& F, int nrhs, const std::string& prefix) {
+  SweepBufs b;
+  b.F.assign(F.L + 1, nullptr);
+  b.T.assign(F.L + 1, nullptr);
+  b.Y.assign(F.L + 1, nullptr);
+  for (int lev = F.l0; lev <= F.L; ++lev) {
+    const std::string l = std::to_string(lev);
+    b.F[lev] = F.ws.get<c64>(prefix + "F" + l, (size_t)F.levels[lev].B * nrhs);
+    if (lev > F.l0) {
+      b.T[lev] = F.ws.get<c64>(prefix + "T" + l, (size_t)F.levels[lev].R * nrhs);
+      b.Y[lev] = F.ws.get<c64>(prefix + "Y" + l, (size_t)F.levels[lev].R * nrhs);
+    }
+  }
+  return b;
+}
+
+// Upward sweep, root solve, downward sweep on the level vectors (pure
+// launch sequence: no allocation, no host work, no synchronisation).
+static void run_sweeps(Factor& F, int nrhs, const SweepBufs& b, hipStream_t s) {
+  const int L = F.L, l0 = F.l0;
+  auto& levels = F.levels;
+  // upward: g = A^{-1} f (in F), f~ = A~ (V g) (V g in Y, f~ in T)
+  for (int lev = L; lev > l0; --lev) {
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, b.F[lev], s);
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.F[lev], b.Y[lev], 0, s);
+    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s);
+    launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
+  }
+  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.F[l0], s);
+  // downward: y from the parent (in Y), f~ <- A~ y - f~, x = g + X f~
+  for (int lev = l0 + 1; lev <= L; ++lev) {
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.F[lev - 1], levels[lev - 1].B, b.Y[lev], lv.R, s);
+    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.T[lev], b.F[lev], 0, s);
+  }
+}
+
+static void run_solve(Factor& F, int nrhs, const c64* rhs, int64_t ld_rhs, c64* x, int64_t ld_x, hipStream_t s,
+                      bool graph) {
+  CellLevel& lf = F.levels[F.L];
+  const SweepBufs b = sweep_buffers(F, nrhs, graph ? "g" + std::to_string(nrhs) + "_" : "sv_");
+  launch_copy_rows(lf.B, F.leaf_dofs_rows.p, F.leaf_iota.p, nrhs, rhs, ld_rhs, b.F[F.L], lf.B, s);
+  if (graph) {
+    auto it = F.graphs.find(nrhs);
+    if (it == F.graphs.end()) {
+      hipGraph_t g;
+      FDS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        run_sweeps(F, nrhs, b, s);
+      } catch (...) {
+        hipGraph_t dummy;
+        (void)hipStreamEndCapture(s, &dummy);
+        throw;
+      }
+      FDS_HIP(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ex;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      FDS_HIP(e);
+      it = F.graphs.emplace(nrhs, ex).first;
+    }
+    FDS_HIP(hipGraphLaunch(it->second, s));
+  } else {
+    run_sweeps(F, nrhs, b, s);
+  }
+  launch_copy_rows(lf.B, F.leaf_iota.p, F.leaf_dofs_cols.p, nrhs, b.F[F.L], lf.B, x, ld_x, s);
+}
+
+static void resolve_stats(Factor& F) {
+  F.ast.resolve(F.stream);
+  FDS_HIP(hipStreamSynchronize(F.stream));
+  for (auto& sp : F.spans) {
+    float ms = 0.f;
+    FDS_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
+    double* dst = sp.what == 0 ? &F.st.id_seconds : (sp.what == 1 ? &F.st.merge_seconds : &F.st.root_seconds);
+    *dst += 1e-3 * ms;
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  F.spans.clear();
 }
 
 }  // namespace fds
@@ -911,6 +1127,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->rho = rho;
     F->omega = omega;
     F->stream = (hipStream_t)stream;
+    F->ws.set_stream(F->stream);
     F->m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
     build_tree(*F);
     const int64_t proxy_cap = (int64_t)F->levels[F->L].n * o.n_proxy;
@@ -920,19 +1137,25 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
       compress_level(*F, lev);
       merge_to_parent(*F, lev);
     }
-    Root* rt = &F->root;
-    factor_root(*F, *rt);
+    factor_root(*F);
+    build_solve_plan(*F);
     FDS_HIP(hipStreamSynchronize(F->stream));
     const auto t1 = std::chrono::steady_clock::now();
+    resolve_stats(*F);
+    if (std::getenv("FDS_TIMING")) {
+      for (int k = 0; k < 8; ++k) std::fprintf(stderr, "[fds host] %-22s %8.2f ms\n", g_host_name[k], 1e3 * g_host_t[k]);
+      std::fprintf(stderr, "[fds host] factor wall %8.2f ms\n", 1e3 * std::chrono::duration<double>(t1 - t0).count());
+    }
+    for (double& v : g_host_t) v = 0.0;
     F->st.factor_seconds = std::chrono::duration<double>(t1 - t0).count();
     F->st.levels = F->L;
     F->st.root_level = F->l0;
     F->st.n_unknowns = 2 * (int64_t)F->G.n_nodes;
-    F->st.root_size = rt->n;
+    F->st.root_size = F->root.n;
     int64_t bytes = 0;
     for (auto& lv : F->levels)
       bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) + (lv.piv.n + lv.s_piv.n) * sizeof(int);
-    bytes += (int64_t)rt->A.n * sizeof(c64);
+    bytes += (int64_t)F->root.A.n * sizeof(c64);
     F->st.factor_bytes = bytes;
     F->st.assembly_seconds = F->ast.seconds;
     F->st.kernel_evals = F->ast.evals;
@@ -946,6 +1169,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
   } catch (const std::exception& e) {
     g_last_error = e.what();
     int c = translate(e);
+    if (F->stream) (void)hipStreamSynchronize(F->stream);
     delete F;
     return c;
   }
@@ -981,143 +1205,20 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fd
   if (!f || nrhs < 1 || !rhs || !x || ld_rhs < N || ld_x < N) return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
-    Root* rt = &f->root;
-    const int L = f->L, l0 = f->l0;
-    auto& levels = f->levels;
-    std::vector<DevBuf<c64>> Fv(L + 1), Tv(L + 1), Ftv(L + 1);
-    for (int lev = l0; lev <= L; ++lev) {
-      Fv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].B * nrhs, 1));
-      if (lev > l0) {
-        Tv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].R * nrhs, 1));
-        Ftv[lev] = DevBuf<c64>((size_t)std::max<int64_t>(levels[lev].R * nrhs, 1));
-      }
-    }
-    // leaf gather: F_L[f_off + r] = rhs[rows[r]]
-    {
-      CellLevel& lv = levels[L];
-      std::vector<int64_t> si, di;
-      for (int q = 0; q < lv.n; ++q)
-        for (size_t r = 0; r < lv.rows[q].size(); ++r) {
-          si.push_back(lv.rows[q][r]);
-          di.push_back(lv.f_off[q] + (int64_t)r);
-        }
-      DevBuf<int64_t> dsi(si), ddi(di);
-      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, (const c64*)rhs, ld_rhs, Fv[L].p, lv.B, s);
+    const bool graph = f->opt.solve_graph != 0;
+    if (graph) {
+      // capture needs a stream of our own; the caller's stream is drained first
       FDS_HIP(hipStreamSynchronize(s));
+      if (!f->gstream) FDS_HIP(hipStreamCreateWithFlags(&f->gstream, hipStreamNonBlocking));
+      s = f->gstream;
     }
-    // upward sweep
-    for (int lev = L; lev > l0; --lev) {
-      CellLevel& lv = levels[lev];
-      std::vector<SolveDesc> sd;
-      std::vector<GemmDesc> g1, g2;
-      for (int q = 0; q < lv.n; ++q) {
-        sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.f_off[q], lv.b[q], lv.b[q], (int)lv.B, nrhs});
-        if (lv.r[q] == 0) continue;
-        GemmDesc a{};
-        a.a_off = lv.v_off[q];
-        a.b_off = lv.f_off[q];
-        a.c_off = lv.t_off[q];
-        a.m = lv.r[q];
-        a.n = nrhs;
-        a.k = lv.b[q];
-        a.lda = lv.r[q];
-        a.ldb = (int)lv.B;
-        a.ldc = (int)lv.R;
-        a.alpha_re = 1.0;
-        g1.push_back(a);
-        GemmDesc b2{};
-        b2.a_off = lv.at_off[q];
-        b2.b_off = lv.t_off[q];
-        b2.c_off = lv.t_off[q];
-        b2.m = lv.r[q];
-        b2.n = nrhs;
-        b2.k = lv.r[q];
-        b2.lda = lv.r[q];
-        b2.ldb = (int)lv.R;
-        b2.ldc = (int)lv.R;
-        b2.alpha_re = 1.0;
-        g2.push_back(b2);
-      }
-      launch_lu_solve(sd, lv.A.p, lv.piv.p, Fv[lev].p, s);
-      launch_gemm(g1, lv.V.p, Fv[lev].p, Tv[lev].p, 0, s);
-      launch_gemm(g2, lv.At.p, Tv[lev].p, Ftv[lev].p, 0, s);
-      // parent rows
-      CellLevel& pa = levels[lev - 1];
-      std::vector<int64_t> si, di;
-      for (int q = 0; q < lv.n; ++q) {
-        const int p = q / 2;
-        for (int j = 0; j < lv.r[q]; ++j) {
-          si.push_back(lv.t_off[q] + j);
-          di.push_back(pa.f_off[p] + lv.ppos[q][j]);
-        }
-      }
-      DevBuf<int64_t> dsi(si), ddi(di);
-      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Ftv[lev].p, lv.R, Fv[lev - 1].p, pa.B, s);
-      FDS_HIP(hipStreamSynchronize(s));
+    if (s != f->ws.stream()) {
+      // workspace buffers are reused in stream order: keep them on one stream
+      FDS_HIP(hipStreamSynchronize(f->ws.stream()));
+      f->ws.set_stream(s);
     }
-    // root
-    launch_lu_solve(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt->n, rt->n, (int)levels[l0].B, nrhs}}, rt->A.p,
-                    rt->piv.p, Fv[l0].p, s);
-    // downward sweep
-    for (int lev = l0 + 1; lev <= L; ++lev) {
-      CellLevel& lv = levels[lev];
-      CellLevel& pa = levels[lev - 1];
-      std::vector<int64_t> si, di;
-      for (int q = 0; q < lv.n; ++q) {
-        const int p = q / 2;
-        for (int j = 0; j < lv.r[q]; ++j) {
-          si.push_back(pa.f_off[p] + lv.ppos[q][j]);
-          di.push_back(lv.t_off[q] + j);
-        }
-      }
-      DevBuf<int64_t> dsi(si), ddi(di);
-      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Fv[lev - 1].p, pa.B, Tv[lev].p, lv.R, s);
-      std::vector<GemmDesc> g1, g2;
-      for (int q = 0; q < lv.n; ++q) {
-        if (lv.r[q] == 0) continue;
-        GemmDesc a{};   // Ft <- A~ y - Ft
-        a.a_off = lv.at_off[q];
-        a.b_off = lv.t_off[q];
-        a.c_off = lv.t_off[q];
-        a.m = lv.r[q];
-        a.n = nrhs;
-        a.k = lv.r[q];
-        a.lda = lv.r[q];
-        a.ldb = (int)lv.R;
-        a.ldc = (int)lv.R;
-        a.alpha_re = 1.0;
-        a.beta_re = -1.0;
-        g1.push_back(a);
-        GemmDesc b2{};  // x <- g + X Ft
-        b2.a_off = lv.x_off[q];
-        b2.b_off = lv.t_off[q];
-        b2.c_off = lv.f_off[q];
-        b2.m = lv.b[q];
-        b2.n = nrhs;
-        b2.k = lv.r[q];
-        b2.lda = lv.b[q];
-        b2.ldb = (int)lv.R;
-        b2.ldc = (int)lv.B;
-        b2.alpha_re = 1.0;
-        b2.beta_re = 1.0;
-        g2.push_back(b2);
-      }
-      launch_gemm(g1, lv.At.p, Tv[lev].p, Ftv[lev].p, 0, s);
-      launch_gemm(g2, lv.X.p, Ftv[lev].p, Fv[lev].p, 0, s);
-    }
-    // leaf scatter
-    {
-      CellLevel& lv = levels[L];
-      std::vector<int64_t> si, di;
-      for (int q = 0; q < lv.n; ++q)
-        for (size_t r = 0; r < lv.cols[q].size(); ++r) {
-          si.push_back(lv.f_off[q] + (int64_t)r);
-          di.push_back(lv.cols[q][r]);
-        }
-      DevBuf<int64_t> dsi(si), ddi(di);
-      launch_copy_rows((int64_t)si.size(), dsi.p, ddi.p, nrhs, Fv[L].p, lv.B, (c64*)x, ld_x, s);
-      FDS_HIP(hipStreamSynchronize(s));
-    }
+    run_solve(*f, nrhs, (const c64*)rhs, ld_rhs, (c64*)x, ld_x, s, graph);
+    FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {
     g_last_error = e.what();
@@ -1166,6 +1267,7 @@ int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, i
 
 void fds_destroy(fds_factor f) {
   if (!f) return;
+  if (f->ws.stream()) (void)hipStreamSynchronize(f->ws.stream());
   delete f;
 }
 
@@ -1210,12 +1312,13 @@ int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu
     q.out_off = 0;
     q.rs = 1;
     q.cs = ld;
-    AssemblyStats st;
-    assemble_blocks(std::vector<BlockReq>{q}, DG.elems.p, m, (c64*)out, s, &st);
+    Workspace ws(s);
+    assemble_blocks(std::vector<BlockReq>{q}, DG.elems.p, m, (c64*)out, ws, nullptr);
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {
     g_last_error = e.what();
+    if (stream) (void)hipStreamSynchronize((hipStream_t)stream);
     return translate(e);
   }
 }
@@ -1242,7 +1345,11 @@ int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* 
       if (m[i] < 1 || n[i] < 1) return FDS_EINVAL;
       d[i] = CpqrDesc{off[i], pivoff[i], (int)m[i], (int)n[i], (int)m[i], 0, (int)kmax[i], stop_at_tol};
     }
-    launch_cpqr(d, (c64*)a, piv, tol, rank, (hipStream_t)stream);
+    check_cpqr_sizes(d);
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<CpqrDesc> dd(d);
+    launch_cpqr(dd.p, np, (c64*)a, piv, tol, rank, s);
+    FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {
     g_last_error = e.what();

@@ -86,21 +86,20 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c
 }
 
 // ------------------------------------------------------------------ LU solve
-struct SolveTile {
-  int desc;
-  int c0, nc;
-};
-
-__global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, const SolveTile* __restrict__ tiles,
+// block (blockIdx.x = problem, blockIdx.y = chunk of ``chunk`` columns);
+// ncol_override > 0 replaces every problem's column count.
+__global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, int chunk, int ncol_override,
                                                    const c64* __restrict__ abase, const int* __restrict__ piv,
                                                    c64* __restrict__ bbase) {
   extern __shared__ c64 X[];
-  const SolveTile tl = tiles[blockIdx.x];
-  const SolveDesc d = descs[tl.desc];
+  const SolveDesc d = descs[blockIdx.x];
+  const int ncol = ncol_override > 0 ? ncol_override : d.ncol;
+  const int c0 = blockIdx.y * chunk;
+  if (c0 >= ncol || d.n == 0) return;
   const c64* A = abase + d.a_off;
   const int* P = piv + d.piv_off;
-  c64* B = bbase + d.b_off + (int64_t)tl.c0 * d.ldb;
-  const int n = d.n, lda = d.lda, nc = tl.nc;
+  c64* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
+  const int n = d.n, lda = d.lda, nc = min(chunk, ncol - c0);
   const int tid = threadIdx.x;
   for (int t = tid; t < n * nc; t += kBlk) {
     const int i = t % n, c = t / n;
@@ -146,23 +145,22 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 // ------------------------------------------------------------------ GEMM
 // C = alpha op(A) B + beta C, 64 x 64 output tiles, k-slices of 16 staged in
 // LDS, each thread owning a 4 x 4 block of outputs.
-struct GemmTile {
-  int desc;
-  int tm, tn;
-};
-
+// block (blockIdx.x = row tile (problem, tm) from ``tiles``, blockIdx.y = tn);
+// n_override > 0 replaces every problem's column count.
 template <int TA>
 __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
-                                               const c64* __restrict__ abase, const c64* __restrict__ bbase,
-                                               c64* __restrict__ cbase) {
+                                               int n_override, const c64* __restrict__ abase,
+                                               const c64* __restrict__ bbase, c64* __restrict__ cbase) {
   __shared__ c64 As[16][65];
   __shared__ c64 Bs[16][65];
   const GemmTile tl = tiles[blockIdx.x];
-  const GemmDesc d = descs[tl.desc];
+  GemmDesc d = descs[tl.desc];
+  if (n_override > 0) d.n = n_override;
+  if ((int)blockIdx.y * 64 >= d.n) return;
   const c64* A = abase + d.a_off;
   const c64* B = bbase + d.b_off;
   c64* C = cbase + d.c_off;
-  const int m0 = tl.tm * 64, n0 = tl.tn * 64;
+  const int m0 = tl.tm * 64, n0 = blockIdx.y * 64;
   const int tid = threadIdx.x;
   const int tr = tid % 16, tc = tid / 16;   // thread owns rows tr + 16 a, cols tc + 16 b
   c64 acc[4][4];
@@ -383,12 +381,6 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
 }
 
 // ------------------------------------------------------------------ scatter / copies
-struct ScatterTile {
-  int desc;
-  int count;
-  int64_t start;
-};
-
 __global__ void k_scatter(const ScatterDesc* __restrict__ descs, const ScatterTile* __restrict__ tiles,
                           const int* __restrict__ pos, const c64* __restrict__ src, c64* __restrict__ dst) {
   const ScatterTile t = tiles[blockIdx.x];
@@ -427,81 +419,75 @@ __global__ void k_fill_identity(const int64_t* __restrict__ offs, const int* __r
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_lu(const std::vector<LUDesc>& d, c64* base, int* piv, int* info, hipStream_t s) {
-  if (d.empty()) return;
-  DevBuf<LUDesc> dd(d);
-  k_lu<<<(int)d.size(), kBlk, 0, s>>>(dd.p, base, piv, info);
+// All launchers are asynchronous on ``s``: descriptor arrays are device
+// pointers owned by the caller (workspace or factor storage).
+void launch_lu(const LUDesc* d, int n, c64* base, int* piv, int* info, hipStream_t s) {
+  if (n == 0) return;
+  k_lu<<<n, kBlk, 0, s>>>(d, base, piv, info);
   FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
 }
 
-void launch_lu_solve(const std::vector<SolveDesc>& d, const c64* abase, const int* piv, c64* bbase, hipStream_t s) {
-  if (d.empty()) return;
-  int nmax = 1;
-  for (auto& x : d) nmax = std::max(nmax, x.n);
-  // LDS chunk of nc columns: n * nc * 16 bytes <= 32 KiB
-  int nc = std::max(1, std::min(8, 32768 / (16 * nmax)));
-  std::vector<SolveTile> tiles;
-  for (int i = 0; i < (int)d.size(); ++i)
-    for (int c0 = 0; c0 < d[i].ncol; c0 += nc) tiles.push_back(SolveTile{i, c0, std::min(nc, d[i].ncol - c0)});
-  if (tiles.empty()) return;
+int solve_chunk(int nmax) { return std::max(1, std::min(8, 32768 / (16 * std::max(1, nmax)))); }
+
+void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const c64* abase,
+                     const int* piv, c64* bbase, hipStream_t s) {
+  if (n == 0 || ncol_max == 0) return;
+  const int nc = solve_chunk(nmax);
   if ((size_t)nmax * nc * sizeof(c64) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
-  DevBuf<SolveDesc> dd(d);
-  DevBuf<SolveTile> dt(tiles);
-  k_lu_solve<<<(int)tiles.size(), kBlk, nmax * nc * sizeof(c64), s>>>(dd.p, dt.p, abase, piv, bbase);
+  dim3 grid(n, (ncol_max + nc - 1) / nc);
+  k_lu_solve<<<grid, kBlk, nmax * nc * sizeof(c64), s>>>(d, nc, ncol_override, abase, piv, bbase);
   FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
 }
 
-void launch_gemm(const std::vector<GemmDesc>& d, const c64* abase, const c64* bbase, c64* cbase, int transA,
-                 hipStream_t s) {
-  if (d.empty()) return;
-  std::vector<GemmTile> tiles;
+std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d) {
+  std::vector<GemmTile> t;
   for (int i = 0; i < (int)d.size(); ++i)
-    for (int tm = 0; tm * 64 < d[i].m; ++tm)
-      for (int tn = 0; tn * 64 < d[i].n; ++tn) tiles.push_back(GemmTile{i, tm, tn});
-  if (tiles.empty()) return;
-  DevBuf<GemmDesc> dd(d);
-  DevBuf<GemmTile> dt(tiles);
-  if (transA)
-    k_gemm<1><<<(int)tiles.size(), kBlk, 0, s>>>(dd.p, dt.p, abase, bbase, cbase);
-  else
-    k_gemm<0><<<(int)tiles.size(), kBlk, 0, s>>>(dd.p, dt.p, abase, bbase, cbase);
-  FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
+    for (int tm = 0; tm * 64 < d[i].m; ++tm) t.push_back(GemmTile{i, tm});
+  return t;
 }
 
-void launch_cpqr(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, hipStream_t s) {
-  if (d.empty()) return;
+void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const c64* abase,
+                 const c64* bbase, c64* cbase, int transA, hipStream_t s) {
+  if (n_tiles == 0 || n_max == 0) return;
+  dim3 grid(n_tiles, (n_max + 63) / 64);
+  if (transA)
+    k_gemm<1><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+  else
+    k_gemm<0><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+  FDS_HIP(hipGetLastError());
+}
+
+void check_cpqr_sizes(const std::vector<CpqrDesc>& d) {
   for (auto& x : d)
     if (x.m > kQrMaxM || x.n > kQrMaxN) throw Error(1, "cpqr: matrix exceeds the LDS limits");
-  DevBuf<CpqrDesc> dd(d);
-  k_cpqr<<<(int)d.size(), kBlk, 0, s>>>(dd.p, base, piv, tol, rank);
-  FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
 }
 
-void launch_interp(const std::vector<InterpDesc>& d, c64* abase, const int* piv, c64* dbase, hipStream_t s) {
-  if (d.empty()) return;
-  DevBuf<InterpDesc> dd(d);
-  k_interp<<<(int)d.size(), kBlk, 0, s>>>(dd.p, abase, piv, dbase);
+void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s) {
+  if (n == 0) return;
+  k_cpqr<<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
   FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
 }
 
-void launch_scatter(const std::vector<ScatterDesc>& d, const int* pos, const c64* src, c64* dst, hipStream_t s) {
-  if (d.empty()) return;
+void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s) {
+  if (n == 0) return;
+  k_interp<<<n, kBlk, 0, s>>>(d, abase, piv, dbase);
+  FDS_HIP(hipGetLastError());
+}
+
+std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d) {
   std::vector<ScatterTile> tiles;
   for (int i = 0; i < (int)d.size(); ++i) {
     const int64_t ne = (int64_t)d[i].nr * d[i].nc;
     for (int64_t a = 0; a < ne; a += 256) tiles.push_back(ScatterTile{i, (int)std::min<int64_t>(256, ne - a), a});
   }
-  if (tiles.empty()) return;
-  DevBuf<ScatterDesc> dd(d);
-  DevBuf<ScatterTile> dt(tiles);
-  k_scatter<<<(int)tiles.size(), 256, 0, s>>>(dd.p, dt.p, pos, src, dst);
+  return tiles;
+}
+
+void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const c64* src,
+                    c64* dst, hipStream_t s) {
+  if (n_tiles == 0) return;
+  k_scatter<<<n_tiles, 256, 0, s>>>(d, tiles, pos, src, dst);
   FDS_HIP(hipGetLastError());
-  FDS_HIP(hipStreamSynchronize(s));
 }
 
 void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,

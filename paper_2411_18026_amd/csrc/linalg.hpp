@@ -48,13 +48,30 @@ struct ScatterDesc {    // dst[dst_off + rpos[r] + cpos[c] * dst_ld] = src[src_o
   int rpos_off, cpos_off;   // -1: identity
 };
 
-void launch_lu(const std::vector<LUDesc>& d, c64* base, int* piv, int* info, hipStream_t s);
-void launch_lu_solve(const std::vector<SolveDesc>& d, const c64* abase, const int* piv, c64* bbase, hipStream_t s);
-void launch_gemm(const std::vector<GemmDesc>& d, const c64* abase, const c64* bbase, c64* cbase, int transA,
-                 hipStream_t s);
-void launch_cpqr(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, hipStream_t s);
-void launch_interp(const std::vector<InterpDesc>& d, c64* abase, const int* piv, c64* dbase, hipStream_t s);
-void launch_scatter(const std::vector<ScatterDesc>& d, const int* pos, const c64* src, c64* dst, hipStream_t s);
+struct GemmTile {         // one 64-row tile of a GEMM problem
+  int desc, tm;
+};
+
+struct ScatterTile {
+  int desc;
+  int count;
+  int64_t start;
+};
+
+// Asynchronous launchers; descriptor arrays are device pointers.
+void launch_lu(const LUDesc* d, int n, c64* base, int* piv, int* info, hipStream_t s);
+int solve_chunk(int nmax);
+void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const c64* abase,
+                     const int* piv, c64* bbase, hipStream_t s);
+std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d);
+void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const c64* abase,
+                 const c64* bbase, c64* cbase, int transA, hipStream_t s);
+void check_cpqr_sizes(const std::vector<CpqrDesc>& d);
+void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s);
+void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s);
+std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d);
+void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const c64* src,
+                    c64* dst, hipStream_t s);
 // dst[didx[i] + c * ldd] = src[sidx[i] + c * lds], i < n, c < ncol
 void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,
                       c64* dst, int64_t ldd, hipStream_t s);

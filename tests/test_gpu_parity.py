@@ -153,3 +153,24 @@ def test_fds_against_oracle(fdsmod, case):
     # the GPU load vectors reproduce the oracle's
     G = F.rhs_plane(kinds, angles).cpu().numpy().T
     assert np.max(np.abs(G - Fm)) <= 1e-13 * np.max(np.abs(Fm))
+
+
+def test_graph_solve_replays_match_eager(fdsmod):
+    """Solve sweeps captured as a hipGraph: every replay (with eager work in
+    between) reproduces the eager solve."""
+    curves = [sy.ellipse(300, 1.0, 0.5)]
+    Fe = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    Fg = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32, solve_graph=True)
+    rhs = Fe.rhs_plane([0, 1, 0], [0.0, 0.9, 3.0])
+    rhs2 = (rhs * (0.5 - 2.0j)).contiguous()
+    xe = Fe.solve(rhs)
+    xe2 = Fe.solve(rhs2)
+    for k in range(4):
+        xg = Fg.solve(rhs)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), k
+        _ = Fe.solve(rhs2)               # eager work between replays
+        xg2 = Fg.solve(rhs2)
+        assert torch.equal(xg2, xe2), k
+    x1 = Fg.solve(rhs[1])                # another nrhs: a second graph
+    assert torch.equal(x1, Fe.solve(rhs[1]))
