@@ -704,7 +704,7 @@ static void compress_level(Factor& F, int lev) {
       sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
   }
   int* info = ws.get<int>("lu_info", (size_t)n);
-  launch_lu(ws.upload("lu_desc", ld), n, lv.A.p, lv.piv.p, info, s);
+  launch_lu(ws.upload("lu_desc", ld), n, lv.bmax, lv.A.p, lv.piv.p, info, s);
   launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, lv.A.p, lv.piv.p, lv.X.p, s);
   c64* S = ws.get<c64>("S", (size_t)lv.at_tot);
   std::vector<GemmDesc> gd;
@@ -734,7 +734,7 @@ static void compress_level(Factor& F, int lev) {
   auto gt = gemm_tiles(gd);
   launch_gemm(ws.upload("s_desc", gd), ws.upload("s_tiles", gt), (int)gt.size(), rmax, 0, lv.V.p, lv.X.p, S, 0, s);
   int* info2 = ws.get<int>("lu_info2", std::max<size_t>(lds.size(), 1));
-  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), S, lv.s_piv.p, info2, s);
+  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), rmax, S, lv.s_piv.p, info2, s);
   {
     int* dn = ws.upload("id_n", id_n);
     launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, lv.At.p, s);
@@ -885,7 +885,7 @@ static void factor_root(Factor& F) {
   assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, ws, &F.ast);
   span_begin(F, 2);
   int* info = ws.get<int>("root_info", 1);
-  launch_lu(ws.upload("root_lu", std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}), 1, rt.A.p, rt.piv.p, info, s);
+  launch_lu(ws.upload("root_lu", std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}), 1, rt.n, rt.A.p, rt.piv.p, info, s);
   span_end(F);
   check_info(ws, info, 1);
   rt.desc = DevBuf<SolveDesc>(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt.n, rt.n, rt.n, 0}});

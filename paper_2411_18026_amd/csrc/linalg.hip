@@ -85,6 +85,138 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c
   if (tid == 0 && info) info[blockIdx.x] = bad;
 }
 
+// Blocked right-looking LU with partial pivoting, panel width NB.  Same
+// pivot rule and output layout as k_lu.  The panel (rows k0.., NB columns)
+// is factored in LDS; its row interchanges are then applied to the other
+// columns, U12 = L11^{-1} A12 is formed column by column, and the trailing
+// matrix gets one rank-NB update per panel.
+template <int NB>
+__global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ descs, c64* __restrict__ base,
+                                                 int* __restrict__ piv, int* __restrict__ info) {
+  extern __shared__ c64 Pn[];          // panel, column-major with leading dimension ldp
+  __shared__ double sv[kBlk / 64];
+  __shared__ int si[kBlk / 64];
+  __shared__ int s_p;
+  const LUDesc d = descs[blockIdx.x];
+  c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int n = d.n, lda = d.lda;
+  const int ldp = n;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int bad = 0;
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int nb = min(NB, n - k0), mp = n - k0;
+    for (int t = tid; t < mp * nb; t += kBlk) {
+      const int i = t % mp, c = t / mp;
+      Pn[i + c * ldp] = A[(k0 + i) + (int64_t)(k0 + c) * lda];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      // pivot: largest modulus in panel column j at rows >= j, lowest row on ties
+      double best = -1.0;
+      int bi = mp;
+      for (int i = j + tid; i < mp; i += kBlk) {
+        const double v = abs2(Pn[i + j * ldp]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double b = sv[0];
+        int ib = si[0];
+        for (int w = 1; w < kBlk / 64; ++w)
+          if (sv[w] > b || (sv[w] == b && si[w] < ib)) {
+            b = sv[w];
+            ib = si[w];
+          }
+        s_p = ib;
+        P[k0 + j] = k0 + ib;
+        if (!(b > 0.0) || !isfinite(b)) bad = bad ? bad : k0 + j + 1;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (p != j && tid < nb) {
+        const c64 t = Pn[j + tid * ldp];
+        Pn[j + tid * ldp] = Pn[p + tid * ldp];
+        Pn[p + tid * ldp] = t;
+      }
+      __syncthreads();
+      const c64 pj = Pn[j + j * ldp];
+      const c64 inv = abs2(pj) > 0.0 ? cdiv(cmk(1.0, 0.0), pj) : cmk(0.0, 0.0);
+      for (int i = j + 1 + tid; i < mp; i += kBlk) {
+        const c64 l = Pn[i + j * ldp] * inv;
+        Pn[i + j * ldp] = l;
+        for (int c = j + 1; c < nb; ++c) Pn[i + c * ldp] -= l * Pn[j + c * ldp];
+      }
+      __syncthreads();
+    }
+    for (int t = tid; t < mp * nb; t += kBlk) {
+      const int i = t % mp, c = t / mp;
+      A[(k0 + i) + (int64_t)(k0 + c) * lda] = Pn[i + c * ldp];
+    }
+    // row interchanges of this panel on the columns outside it, one thread per column
+    for (int c = tid; c < n; c += kBlk) {
+      if (c >= k0 && c < k0 + nb) continue;
+      c64* col = A + (int64_t)c * lda;
+      for (int j = 0; j < nb; ++j) {
+        const int p = P[k0 + j];
+        if (p != k0 + j) {
+          const c64 t = col[k0 + j];
+          col[k0 + j] = col[p];
+          col[p] = t;
+        }
+      }
+    }
+    __syncthreads();
+    // U12 = L11^{-1} A12, one thread per column
+    for (int c = k0 + nb + tid; c < n; c += kBlk) {
+      c64* col = A + (int64_t)c * lda + k0;
+      c64 x[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        if (r < nb) {
+          c64 s = col[r];
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+            if (q < r) s -= Pn[r + q * ldp] * x[q];
+          x[r] = s;
+          col[r] = s;
+        }
+      }
+    }
+    __syncthreads();
+    // A22 -= L21 U12
+    const int m2 = n - k0 - nb;
+    const int64_t tot = (int64_t)m2 * m2;
+    for (int64_t t = tid; t < tot; t += kBlk) {
+      const int i = (int)(t % m2), c = (int)(t / m2);
+      const c64* u = A + (int64_t)(k0 + nb + c) * lda + k0;
+      c64 s = A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda];
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < nb) s -= Pn[(nb + i) + q * ldp] * u[q];
+      A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda] = s;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && info) info[blockIdx.x] = bad;
+}
+
 // ------------------------------------------------------------------ LU solve
 // block (blockIdx.x = problem, blockIdx.y = chunk of ``chunk`` columns);
 // ncol_override > 0 replaces every problem's column count.
@@ -120,20 +252,68 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   const int cc = tid % nc;
   const int r0 = tid / nc;
   const int rs = kBlk / nc;
-  // forward substitution with unit L
-  for (int j = 0; j < n - 1; ++j) {
-    const c64 xj = X[j + cc * n];
+  constexpr int SB = 16;   // rows per substitution block
+  // diagonal-block solves: lane = 16 * (column within the wave) + row; the
+  // solved entry of each row is broadcast to the later rows by shuffles
+  const int br = tid & 15;            // row within the block
+  const int bc = tid >> 4;            // column handled by this lane group
+  // forward substitution with unit L, SB rows at a time
+  for (int k0 = 0; k0 < n; k0 += SB) {
+    const int nb = min(SB, n - k0);
+    if (tid < 8 * 16) {               // two wavefronts, up to 8 columns
+      const bool act = bc < nc && br < nb;
+      c64 x = act ? X[k0 + br + bc * n] : cmk(0, 0);
+      c64 l[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : cmk(0, 0);
+#pragma unroll
+      for (int q = 0; q < SB - 1; ++q) {
+        const int src = ((tid & 63) & ~15) + q;
+        c64 xq;
+        xq.re = __shfl(x.re, src);
+        xq.im = __shfl(x.im, src);
+        if (br > q) x -= l[q] * xq;
+      }
+      if (act) X[k0 + br + bc * n] = x;
+    }
+    __syncthreads();
     if (r0 < rs)
-      for (int i = j + 1 + r0; i < n; i += rs) X[i + cc * n] -= A[i + (int64_t)j * lda] * xj;
+      for (int i = k0 + nb + r0; i < n; i += rs) {
+        c64 s = X[i + cc * n];
+        for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        X[i + cc * n] = s;
+      }
     __syncthreads();
   }
-  // backward substitution with U
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid < nc) X[j + tid * n] = cdiv(X[j + tid * n], A[j + (int64_t)j * lda]);
+  // backward substitution with U, SB rows at a time from the bottom
+  for (int k1 = n; k1 > 0; k1 -= SB) {
+    const int k0 = max(0, k1 - SB), nb = k1 - k0;
+    if (tid < 8 * 16) {
+      const bool act = bc < nc && br < nb;
+      c64 x = act ? X[k0 + br + bc * n] : cmk(0, 0);
+      c64 u[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q)
+        u[q] = (act && q >= br && q < nb) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : cmk(0, 0);
+      // u[q] holds U(row, k0 + q) for q >= row; the diagonal sits at u[row]
+#pragma unroll
+      for (int q = SB - 1; q >= 0; --q) {
+        if (act && q < nb && br == q) x = cdiv(x, u[q]);
+        const int src = ((tid & 63) & ~15) + q;
+        c64 xq;
+        xq.re = __shfl(x.re, src);
+        xq.im = __shfl(x.im, src);
+        if (q < nb && br < q) x -= u[q] * xq;
+      }
+      if (act) X[k0 + br + bc * n] = x;
+    }
     __syncthreads();
-    const c64 xj = X[j + cc * n];
     if (r0 < rs)
-      for (int i = r0; i < j; i += rs) X[i + cc * n] -= A[i + (int64_t)j * lda] * xj;
+      for (int i = r0; i < k0; i += rs) {
+        c64 s = X[i + cc * n];
+        for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        X[i + cc * n] = s;
+      }
     __syncthreads();
   }
   for (int t = tid; t < n * nc; t += kBlk) {
@@ -421,9 +601,18 @@ __global__ void k_fill_identity(const int64_t* __restrict__ offs, const int* __r
 // ------------------------------------------------------------------ launchers
 // All launchers are asynchronous on ``s``: descriptor arrays are device
 // pointers owned by the caller (workspace or factor storage).
-void launch_lu(const LUDesc* d, int n, c64* base, int* piv, int* info, hipStream_t s) {
+void launch_lu(const LUDesc* d, int n, int nmax, c64* base, int* piv, int* info, hipStream_t s) {
   if (n == 0) return;
-  k_lu<<<n, kBlk, 0, s>>>(d, base, piv, info);
+  // panel of NB columns staged in LDS: nmax * NB * 16 bytes <= 48 KiB
+  const size_t row = (size_t)std::max(1, nmax) * sizeof(c64);
+  if (row * 16 <= 49152)
+    k_lu_blk<16><<<n, kBlk, row * 16, s>>>(d, base, piv, info);
+  else if (row * 8 <= 49152)
+    k_lu_blk<8><<<n, kBlk, row * 8, s>>>(d, base, piv, info);
+  else if (row * 4 <= 49152)
+    k_lu_blk<4><<<n, kBlk, row * 4, s>>>(d, base, piv, info);
+  else
+    k_lu<<<n, kBlk, 0, s>>>(d, base, piv, info);
   FDS_HIP(hipGetLastError());
 }
 

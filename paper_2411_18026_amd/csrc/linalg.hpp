@@ -59,7 +59,7 @@ struct ScatterTile {
 };
 
 // Asynchronous launchers; descriptor arrays are device pointers.
-void launch_lu(const LUDesc* d, int n, c64* base, int* piv, int* info, hipStream_t s);
+void launch_lu(const LUDesc* d, int n, int nmax, c64* base, int* piv, int* info, hipStream_t s);
 int solve_chunk(int nmax);
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const c64* abase,
                      const int* piv, c64* bbase, hipStream_t s);
