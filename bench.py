@@ -39,6 +39,7 @@ def _args():
     p.add_argument("--no-accuracy", action="store_true",
                    help="skip the accuracy checks (second factorisation, sampled rows) after the timed steps")
     p.add_argument("--residual-rows", type=int, default=32)
+    p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     return p.parse_args()
 
 
@@ -148,6 +149,10 @@ def main():
                "per_rhs_us": round(1e6 * (tg2 - tg1) / max(1, a.nrhs - 1), 2), "identical_to_plain": same}
     del Fg
 
+    mixed = None
+    if not a.no_mixed:
+        mixed = mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf)
@@ -183,6 +188,7 @@ def main():
         "class_seconds": [round(x, 5) for x in cls_s],
         "class_evals": [int(x) for x in cls_e],
         "batched_graph_form": batched,
+        "mixed_form": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -193,6 +199,41 @@ def main():
 # the assembly: Hankel functions at k_T r and k_L r plus the tensor algebra
 # of the four 2x2 kernel blocks and their accumulation)
 FLOP_PER_EVAL = 500
+
+
+def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2):
+    """The mixed-precision form on the same input: FP32 elimination and
+    sweeps, FP64 IDs / root LU, each solve refined against the FP64
+    compressed operator (default stop rule).  Reports the factor and solve
+    times (best of ``reps``) and the per-RHS relative difference from the
+    plain FP64 solutions."""
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fm = fds.Factor([nodes], omega, lam, mu, rho, tol, leaf=leaf, mixed=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        y1 = Fm.solve(rhs[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        it1 = Fm.stats()["ir_iterations"]
+        yr = Fm.solve(rhs[1:])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        st = Fm.stats()
+        cur = (t1 - t0, t2 - t1, t3 - t2)
+        best = cur if best is None else tuple(min(u, v) for u, v in zip(best, cur))
+        del Fm
+    X = torch.cat([x1.reshape(1, -1), xr], 0)
+    Y = torch.cat([y1.reshape(1, -1), yr], 0)
+    err = (torch.linalg.norm(Y - X, dim=1) / torch.linalg.norm(X, dim=1)).cpu().numpy()
+    return {"factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
+            "per_rhs_us": round(1e6 * best[2] / max(1, len(rhs) - 1), 2),
+            "ir_iterations_first": int(it1), "ir_iterations_batch": int(st["ir_iterations"]),
+            "ir_residual": st["ir_residual"], "factor_gb": round(st["factor_bytes"] / 1e9, 3),
+            "err_vs_plain_fp64_max": float(err.max()), "err_vs_plain_fp64_median": float(np.median(err))}
 
 
 def cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf, n_sample=16):

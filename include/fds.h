@@ -66,8 +66,19 @@ typedef struct {
   double proxy_ratio;       /* proxy radius / cell radius; default 1.5 */
   fds_c64 alpha;            /* Burton-Miller coupling; {0,0} selects i / (mu k_T) */
   int32_t use_alpha;        /* 0: alpha = i/(mu k_T); 1: use ``alpha`` as given (0 allowed) */
+  int32_t precision;        /* FDS_PREC_FP64 (default): every step in complex FP64.
+                               FDS_PREC_MIXED: assembly, IDs and the root LU in FP64; the per-cell LUs,
+                               A_i^{-1} U_i, V_i X_i, A~_i and the solve sweeps in complex FP32; each
+                               solve refined iteratively against the FP64 compressed operator A_c */
+  int32_t ir_max_iter;      /* mixed form: refinement steps allowed per solve; default 10 */
   int32_t reserved1;
+  double ir_rtol;           /* mixed form: stop when every column has ||f - A_c x|| <= ir_rtol ||f||
+                               (default 1e-9) ... */
+  double ir_dtol;           /* ... and its last correction ||delta|| <= ir_dtol ||x|| (default 1.0, i.e.
+                               the residual alone decides) */
 } fds_options;
+
+enum { FDS_PREC_FP64 = 0, FDS_PREC_MIXED = 1 };
 
 /* Defaults listed above. */
 int fds_options_default(fds_options* opt);
@@ -97,9 +108,23 @@ int fds_rhs_plane(fds_factor f, int32_t nrhs, const int32_t* kind, const double*
  * upward sweep, root solve, downward sweep (Sections 6.2, 6.3, 7.3).
  * rhs, x: device, column-major with leading dimensions ld_rhs, ld_x
  * (>= N_unk).  rhs is not modified.  Only one solve per factor may run at a
- * time. */
+ * time.
+ * Mixed form: x_0 from the FP32 sweeps, then x_{j+1} = x_j + delta_j with
+ * delta_j the FP32 sweeps applied to f - A_c x_j, the product with A_c
+ * taken in FP64 through the compressed (nested U, V, diagonal-block) form;
+ * ends when the ir_rtol / ir_dtol rule holds for every column, else after
+ * ir_max_iter steps with FDS_ENOCONV (x is written either way; the stats
+ * hold the residual).  Synchronises the stream once per step. */
 int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs,
               fds_c64* x, int64_t ld_x, void* stream);
+
+/* y = A_c x with the FP64 compressed operator (Section 6.1: block-diagonal
+ * part plus U (skeleton interactions) V, nested over the levels; Section
+ * 6.2 for the parents' blocks), for a factor built with FDS_PREC_MIXED (the
+ * plain form does not keep U_i and the unfactored blocks: FDS_EINVAL).
+ * x, y: device, column-major, ld_x, ld_y >= N_unk.  Synchronous. */
+int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c64* y, int64_t ld_y,
+              void* stream);
 
 typedef struct {
   int32_t levels;           /* depth L of the tree */
@@ -120,6 +145,12 @@ typedef struct {
   double class_seconds[6];  /* GPU time of that class's integration kernel, summed over launches */
   int64_t class_evals[6];   /* kernel evaluations (quadrature points) of that class */
   int64_t class_launches[6];
+  /* mixed form, last solve: refinement steps taken, and the largest column
+   * values of ||f - A_c x|| / ||f|| and ||delta|| / ||x|| at exit */
+  int32_t precision;
+  int32_t ir_iterations;
+  double ir_residual;
+  double ir_correction;
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);

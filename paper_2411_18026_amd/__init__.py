@@ -39,7 +39,8 @@ class _Geometry(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("leaf_nodes", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("root_level", ctypes.c_int32),
                 ("solve_graph", ctypes.c_int32), ("proxy_ratio", ctypes.c_double), ("alpha", _C64),
-                ("use_alpha", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("use_alpha", ctypes.c_int32), ("precision", ctypes.c_int32), ("ir_max_iter", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -49,10 +50,15 @@ class _Stats(ctypes.Structure):
                 ("id_seconds", ctypes.c_double), ("merge_seconds", ctypes.c_double),
                 ("root_seconds", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
                 ("kernel_evals", ctypes.c_int64), ("class_seconds", ctypes.c_double * 6),
-                ("class_evals", ctypes.c_int64 * 6), ("class_launches", ctypes.c_int64 * 6)]
+                ("class_evals", ctypes.c_int64 * 6), ("class_launches", ctypes.c_int64 * 6),
+                ("precision", ctypes.c_int32), ("ir_iterations", ctypes.c_int32), ("ir_residual", ctypes.c_double),
+                ("ir_correction", ctypes.c_double)]
+
+PREC_FP64, PREC_MIXED = 0, 1
+ENOCONV = 6
 
 
-EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_get_stats",
+EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
            "fds_get_ranks", "fds_get_skeleton", "fds_destroy", "fds_strerror", "fds_last_error",
            "fds_entries", "fds_special_eval", "fds_cpqr_batched"]
 
@@ -87,6 +93,7 @@ def load():
     L.fds_last_error.restype = ctypes.c_char_p
     L.fds_entries.argtypes = [ctypes.POINTER(_Geometry), dbl, dbl, dbl, dbl, ctypes.POINTER(_Options), i64,
                               ctypes.POINTER(i64), i64, ctypes.POINTER(i64), vp, i64, vp]
+    L.fds_apply.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.fds_special_eval.argtypes = [i64, vp, dbl, vp, vp, vp]
     L.fds_cpqr_batched.argtypes = [i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, i32, vp, vp]
@@ -109,11 +116,19 @@ def _geometry(curves):
     return g, (n, xy)
 
 
-def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False):
+def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False, mixed=False,
+             ir_max_iter=None, ir_rtol=None, ir_dtol=None):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
     o.solve_graph = int(bool(solve_graph))
+    o.precision = PREC_MIXED if mixed else PREC_FP64
+    if ir_max_iter is not None:
+        o.ir_max_iter = int(ir_max_iter)
+    if ir_rtol is not None:
+        o.ir_rtol = float(ir_rtol)
+    if ir_dtol is not None:
+        o.ir_dtol = float(ir_dtol)
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
@@ -135,14 +150,29 @@ def _cuda_c128(t):
     return t
 
 
+class NotConverged(FdsError):
+    """Iterative refinement of the mixed form hit its step limit; ``x`` holds
+    the last iterate."""
+
+    def __init__(self, msg, x):
+        super().__init__(msg)
+        self.x = x
+
+
 class Factor:
-    """Factorisation of the Galerkin Burton-Miller system of a scatterer."""
+    """Factorisation of the Galerkin Burton-Miller system of a scatterer.
+
+    ``mixed=True`` selects the mixed-precision form (FP32 elimination and
+    sweeps, FP64 assembly / IDs / root LU, iterative refinement of every
+    solve against the FP64 compressed operator)."""
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
-                 alpha=None, stream=None, solve_graph=False):
+                 alpha=None, stream=None, solve_graph=False, mixed=False, ir_max_iter=None, ir_rtol=None,
+                 ir_dtol=None):
         L = load()
         g, self._keep = _geometry(curves)
-        o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph)
+        o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph, mixed, ir_max_iter, ir_rtol,
+                     ir_dtol)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))
@@ -182,7 +212,22 @@ class Factor:
         _cuda_c128(r)
         if out is None:
             out = torch.empty_like(r)
-        _check(load().fds_solve(self._h, r.shape[0], ctypes.c_void_p(r.data_ptr()), self.n_unknowns,
+        code = load().fds_solve(self._h, r.shape[0], ctypes.c_void_p(r.data_ptr()), self.n_unknowns,
+                                ctypes.c_void_p(out.data_ptr()), self.n_unknowns, _stream(stream))
+        if code == ENOCONV:
+            raise NotConverged(load().fds_last_error().decode(), out[0] if one else out)
+        _check(code)
+        return out[0] if one else out
+
+    def apply(self, x, out=None, stream=None):
+        """y = A_c x with the FP64 compressed operator (mixed-form factors)."""
+        import torch
+        one = x.dim() == 1
+        v = x.reshape(1, -1) if one else x
+        _cuda_c128(v)
+        if out is None:
+            out = torch.empty_like(v)
+        _check(load().fds_apply(self._h, v.shape[0], ctypes.c_void_p(v.data_ptr()), self.n_unknowns,
                                 ctypes.c_void_p(out.data_ptr()), self.n_unknowns, _stream(stream)))
         return out[0] if one else out
 

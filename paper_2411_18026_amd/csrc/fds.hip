@@ -207,7 +207,13 @@ struct CellLevel {
   std::vector<std::vector<int64_t>> rskel, cskel;
   std::vector<int64_t> x_off, at_off, v_off, s_piv_off;
   int64_t x_tot = 0, at_tot = 0, v_tot = 0, s_piv_tot = 0;
+  // plain form: A = LU(A_i), X = A_i^{-1} U_i, At = A~_i, V = V_i.
+  // mixed form: A = the FP64 diagonal block without the children's A~
+  // (the full A_i at the leaves), X = U_i, V = V_i (all FP64, for the
+  // compressed-operator product); A32 = LU(A_i), X32 = A_i^{-1} U_i,
+  // At32 = A~_i, V32 = V_i in FP32.
   DevBuf<c64> A, X, At, V;
+  DevBuf<c32> A32, X32, At32, V32;
   DevBuf<int> piv, s_piv;
   // solve layout: level vector of height B = sum b, skeleton height R = sum r
   std::vector<int64_t> f_off, t_off;
@@ -215,6 +221,10 @@ struct CellLevel {
   // parent position of each skeleton entry (set when the parent is built)
   std::vector<std::vector<int>> ppos;
   SolveLevel plan;
+  // compressed-operator product (mixed form): y = B z per cell
+  DevBuf<GemmDesc> g_diag;
+  DevBuf<GemmTile> t_diag;
+  int n_tdiag = 0;
 };
 
 // Compressed system at l0: diagonal blocks are the cells' A_i, the rest are
@@ -222,6 +232,10 @@ struct CellLevel {
 struct Root {
   int n = 0;
   DevBuf<c64> A;
+  DevBuf<c64> B;            // mixed form: the root system without the children's A~
+  DevBuf<GemmDesc> g_b;
+  DevBuf<GemmTile> t_b;
+  int n_tb = 0;
   DevBuf<int> piv;
   DevBuf<SolveDesc> desc;
 };
@@ -453,6 +467,100 @@ static std::vector<T> download(Workspace& ws, const T* d, size_t n) {
   return h;
 }
 
+// Children's A~ (level lev + 1) into the diagonal blocks of level lev at
+// their parent positions: block p starts at dst_off(p), leading dimension
+// dst_ld(p).  TS -> TD converts on the fly.
+template <typename TS, typename TD, typename Off, typename Ld>
+static void place_child_at_t(Factor& F, int lev, Off dst_off, Ld dst_ld, const TS* src, TD* dst, const char* tag) {
+  CellLevel& ch = F.levels[lev + 1];
+  const int np = F.levels[lev].n;
+  std::vector<int> pos;
+  std::vector<ScatterDesc> sc;
+  for (int p = 0; p < np; ++p)
+    for (int side = 0; side < 2; ++side) {
+      const int c = 2 * p + side;
+      if (ch.r[c] == 0) continue;
+      ScatterDesc d{};
+      d.src_off = ch.at_off[c];
+      d.src_ld = ch.r[c];
+      d.nr = ch.r[c];
+      d.nc = ch.r[c];
+      d.dst_off = dst_off(p);
+      d.dst_ld = dst_ld(p);
+      d.rpos_off = (int)pos.size();
+      pos.insert(pos.end(), ch.ppos[c].begin(), ch.ppos[c].end());
+      d.cpos_off = d.rpos_off;
+      sc.push_back(d);
+    }
+  if (pos.empty()) pos.push_back(0);
+  const std::string t(tag);
+  auto st = scatter_tiles(sc);
+  launch_scatter(F.ws.upload("pca_desc" + t, sc), F.ws.upload("pca_tiles" + t, st), (int)st.size(),
+                 F.ws.upload("pca_pos" + t, pos), src, dst, F.stream);
+}
+
+template <typename Off, typename Ld>
+static void place_child_at(Factor& F, int lev, Off dst_off, Ld dst_ld, c32* dst, const char* tag) {
+  place_child_at_t(F, lev, dst_off, dst_ld, F.levels[lev + 1].At32.p, dst, tag);
+}
+
+// Inverse-free elimination of one level (Section 6.2) in the scalar type of
+// the buffers: LU(A_i) in place; X_i <- A_i^{-1} X_i; S_i = V_i X_i; LU(S_i);
+// At_i = S_i^{-1} (the LU of S_i applied to the identity).
+template <typename T>
+static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* At, const std::string& tag,
+                      std::vector<std::pair<int*, size_t>>& infos) {
+  Workspace& ws = F.ws;
+  hipStream_t s = F.stream;
+  const int n = lv.n;
+  std::vector<LUDesc> ld(n);
+  std::vector<SolveDesc> sd;
+  for (int q = 0; q < n; ++q) {
+    ld[q] = LUDesc{lv.a_off[q], lv.piv_off[q], lv.b[q], lv.b[q]};
+    if (lv.r[q] > 0)
+      sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
+  }
+  int* info = ws.get<int>("lu_info", (size_t)n);
+  launch_lu(ws.upload("lu_desc", ld), n, lv.bmax, A, lv.piv.p, info, s);
+  launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, A, lv.piv.p, X, s);
+  T* S = ws.get<T>("S" + tag, (size_t)std::max<int64_t>(lv.at_tot, 1));
+  std::vector<GemmDesc> gd;
+  std::vector<LUDesc> lds;
+  std::vector<SolveDesc> sds;
+  std::vector<int64_t> id_off;
+  std::vector<int> id_n;
+  for (int q = 0; q < n; ++q) {
+    if (lv.r[q] == 0) continue;
+    GemmDesc g{};
+    g.a_off = lv.v_off[q];
+    g.b_off = lv.x_off[q];
+    g.c_off = lv.at_off[q];
+    g.m = lv.r[q];
+    g.n = lv.r[q];
+    g.k = lv.b[q];
+    g.lda = lv.r[q];
+    g.ldb = lv.b[q];
+    g.ldc = lv.r[q];
+    g.alpha_re = 1.0;
+    gd.push_back(g);
+    lds.push_back(LUDesc{lv.at_off[q], lv.s_piv_off[q], lv.r[q], lv.r[q]});
+    sds.push_back(SolveDesc{lv.at_off[q], lv.s_piv_off[q], lv.at_off[q], lv.r[q], lv.r[q], lv.r[q], lv.r[q]});
+    id_off.push_back(lv.at_off[q]);
+    id_n.push_back(lv.r[q]);
+  }
+  auto gt = gemm_tiles(gd);
+  launch_gemm(ws.upload("s_desc", gd), ws.upload("s_tiles", gt), (int)gt.size(), rmax, 0, V, X, S, 0, s);
+  int* info2 = ws.get<int>("lu_info2", std::max<size_t>(lds.size(), 1));
+  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), rmax, S, lv.s_piv.p, info2, s);
+  {
+    int* dn = ws.upload("id_n", id_n);
+    launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, At, s);
+  }
+  launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, At, s);
+  infos.emplace_back(info, (size_t)n);
+  infos.emplace_back(info2, lds.size());
+}
+
 static void compress_level(Factor& F, int lev) {
   const Geometry& G = F.G;
   CellLevel& lv = F.levels[lev];
@@ -670,7 +778,7 @@ static void compress_level(Factor& F, int lev) {
     lv.R += r;
   }
   lv.X = DevBuf<c64>((size_t)std::max<int64_t>(lv.x_tot, 1));
-  lv.At = DevBuf<c64>((size_t)std::max<int64_t>(lv.at_tot, 1));
+  lv.At = DevBuf<c64>(F.opt.precision == FDS_PREC_MIXED ? 1 : (size_t)std::max<int64_t>(lv.at_tot, 1));
   lv.V = DevBuf<c64>((size_t)std::max<int64_t>(lv.v_tot, 1));
   lv.s_piv = DevBuf<int>((size_t)std::max<int64_t>(lv.s_piv_tot, 1));
   FDS_HIP(hipMemsetAsync(lv.X.p, 0, lv.X.n * sizeof(c64), s));
@@ -696,54 +804,24 @@ static void compress_level(Factor& F, int lev) {
 
   // elimination: LU(A_i); X_i = A_i^{-1} U_i; S_i = V_i X_i; A~_i = S_i^{-1}
   span_begin(F, 1);
-  std::vector<LUDesc> ld(n);
-  std::vector<SolveDesc> sd;
-  for (int q = 0; q < n; ++q) {
-    ld[q] = LUDesc{lv.a_off[q], lv.piv_off[q], lv.b[q], lv.b[q]};
-    if (lv.r[q] > 0)
-      sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
+  std::vector<std::pair<int*, size_t>> infos;
+  if (F.opt.precision == FDS_PREC_MIXED) {
+    // FP32 copies: A_i (the FP64 block plus the children's FP32 A~), U_i, V_i
+    lv.A32 = DevBuf<c32>((size_t)std::max<int64_t>(lv.a_tot, 1));
+    lv.X32 = DevBuf<c32>((size_t)std::max<int64_t>(lv.x_tot, 1));
+    lv.V32 = DevBuf<c32>((size_t)std::max<int64_t>(lv.v_tot, 1));
+    lv.At32 = DevBuf<c32>((size_t)std::max<int64_t>(lv.at_tot, 1));
+    launch_convert(lv.a_tot, lv.A.p, lv.A32.p, s);
+    if (lev < F.L) place_child_at(F, lev, [&](int p) { return lv.a_off[p]; }, [&](int p) { return lv.b[p]; },
+                                  lv.A32.p, "c32");
+    launch_convert(lv.x_tot, lv.X.p, lv.X32.p, s);
+    launch_convert(lv.v_tot, lv.V.p, lv.V32.p, s);
+    eliminate(F, lv, rmax, lv.A32.p, lv.X32.p, lv.V32.p, lv.At32.p, "32", infos);
+  } else {
+    eliminate(F, lv, rmax, lv.A.p, lv.X.p, lv.V.p, lv.At.p, "64", infos);
   }
-  int* info = ws.get<int>("lu_info", (size_t)n);
-  launch_lu(ws.upload("lu_desc", ld), n, lv.bmax, lv.A.p, lv.piv.p, info, s);
-  launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, lv.A.p, lv.piv.p, lv.X.p, s);
-  c64* S = ws.get<c64>("S", (size_t)lv.at_tot);
-  std::vector<GemmDesc> gd;
-  std::vector<LUDesc> lds;
-  std::vector<SolveDesc> sds;
-  std::vector<int64_t> id_off;
-  std::vector<int> id_n;
-  for (int q = 0; q < n; ++q) {
-    if (lv.r[q] == 0) continue;
-    GemmDesc g{};
-    g.a_off = lv.v_off[q];
-    g.b_off = lv.x_off[q];
-    g.c_off = lv.at_off[q];
-    g.m = lv.r[q];
-    g.n = lv.r[q];
-    g.k = lv.b[q];
-    g.lda = lv.r[q];
-    g.ldb = lv.b[q];
-    g.ldc = lv.r[q];
-    g.alpha_re = 1.0;
-    gd.push_back(g);
-    lds.push_back(LUDesc{lv.at_off[q], lv.s_piv_off[q], lv.r[q], lv.r[q]});
-    sds.push_back(SolveDesc{lv.at_off[q], lv.s_piv_off[q], lv.at_off[q], lv.r[q], lv.r[q], lv.r[q], lv.r[q]});
-    id_off.push_back(lv.at_off[q]);
-    id_n.push_back(lv.r[q]);
-  }
-  auto gt = gemm_tiles(gd);
-  launch_gemm(ws.upload("s_desc", gd), ws.upload("s_tiles", gt), (int)gt.size(), rmax, 0, lv.V.p, lv.X.p, S, 0, s);
-  int* info2 = ws.get<int>("lu_info2", std::max<size_t>(lds.size(), 1));
-  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), rmax, S, lv.s_piv.p, info2, s);
-  {
-    int* dn = ws.upload("id_n", id_n);
-    launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, lv.At.p, s);
-  }
-  // A~ = S^{-1}: the LU of S (held in S) applied to the identity in At
-  launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, lv.At.p, s);
   span_end(F);
-  check_info(ws, info, n);
-  check_info(ws, info2, lds.size());
+  for (auto& c : infos) check_info(ws, c.first, c.second);
   int mr = 0;
   for (int q = 0; q < n; ++q) mr = std::max(mr, std::max(lv.k0[q], lv.k1[q]));
   F.st.max_rank = std::max(F.st.max_rank, mr);
@@ -787,27 +865,17 @@ static void merge_to_parent(Factor& F, int lev) {
     for (int j = 0; j < kb1; ++j) pb_.push_back(ka0 + kb0 + ka1 + j);
   }
   layout_blocks(pa);
-  // diagonal sub-blocks: A~ of the children
-  std::vector<int> pos;
-  std::vector<ScatterDesc> sc;
+  // diagonal sub-blocks: A~ of the children (plain form); the mixed form
+  // keeps them out of the FP64 block and adds its FP32 A~ when the parent
+  // level is eliminated
+  if (F.opt.precision == FDS_PREC_MIXED)
+    FDS_HIP(hipMemsetAsync(pa.A.p, 0, pa.A.n * sizeof(c64), s));
+  else
+    place_child_at_t(F, lev - 1, [&](int p) { return pa.a_off[p]; }, [&](int p) { return pa.b[p]; }, ch.At.p,
+                     pa.A.p, "c64");
+  // off-diagonal: R_ab = A(rskel_a, cskel_b), R_ba = A(rskel_b, cskel_a)
   std::vector<BlockReq> reqs;
   for (int p = 0; p < pa.n; ++p) {
-    for (int side = 0; side < 2; ++side) {
-      const int c = 2 * p + side;
-      if (ch.r[c] == 0) continue;
-      ScatterDesc d{};
-      d.src_off = ch.at_off[c];
-      d.src_ld = ch.r[c];
-      d.nr = ch.r[c];
-      d.nc = ch.r[c];
-      d.dst_off = pa.a_off[p];
-      d.dst_ld = pa.b[p];
-      d.rpos_off = (int)pos.size();
-      pos.insert(pos.end(), ch.ppos[c].begin(), ch.ppos[c].end());
-      d.cpos_off = d.rpos_off;
-      sc.push_back(d);
-    }
-    // off-diagonal: R_ab = A(rskel_a, cskel_b), R_ba = A(rskel_b, cskel_a)
     for (int side = 0; side < 2; ++side) {
       const int a = 2 * p + side, b = 2 * p + 1 - side;
       if (ch.r[a] == 0 || ch.r[b] == 0) continue;
@@ -822,10 +890,6 @@ static void merge_to_parent(Factor& F, int lev) {
       reqs.push_back(std::move(q));
     }
   }
-  if (pos.empty()) pos.push_back(0);
-  auto st = scatter_tiles(sc);
-  launch_scatter(ws.upload("msc_desc", sc), ws.upload("msc_tiles", st), (int)st.size(), ws.upload("msc_pos", pos),
-                 ch.At.p, pa.A.p, s);
   assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, ws, &F.ast);
 }
 
@@ -883,6 +947,24 @@ static void factor_root(Factor& F) {
   launch_scatter(ws.upload("rsc_desc", sc), ws.upload("rsc_tiles", st), (int)st.size(),
                  ws.upload("rsc_pos", std::vector<int>{0}), lv.A.p, rt.A.p, s);
   assemble_blocks(reqs, F.DG.elems.p, F.m, rt.A.p, ws, &F.ast);
+  if (F.opt.precision == FDS_PREC_MIXED) {
+    // keep the system without the children's A~ for the compressed-operator
+    // product, then add their FP32 A~ (widened) for the FP64 LU
+    rt.B = DevBuf<c64>((size_t)rt.n * rt.n);
+    FDS_HIP(hipMemcpyAsync(rt.B.p, rt.A.p, rt.B.n * sizeof(c64), hipMemcpyDeviceToDevice, s));
+    if (F.L > F.l0)
+      place_child_at_t(F, F.l0, [&](int q) { return lv.f_off[q] + lv.f_off[q] * (int64_t)rt.n; },
+                       [&](int) { return rt.n; }, F.levels[F.l0 + 1].At32.p, rt.A.p, "root");
+    GemmDesc g{};
+    g.m = g.n = g.k = rt.n;
+    g.lda = g.ldb = g.ldc = rt.n;
+    g.alpha_re = 1.0;
+    std::vector<GemmDesc> gd{g};
+    auto gt = gemm_tiles(gd);
+    rt.g_b = DevBuf<GemmDesc>(gd);
+    rt.t_b = DevBuf<GemmTile>(gt);
+    rt.n_tb = (int)gt.size();
+  }
   span_begin(F, 2);
   int* info = ws.get<int>("root_info", 1);
   launch_lu(ws.upload("root_lu", std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}), 1, rt.n, rt.A.p, rt.piv.p, info, s);
@@ -969,6 +1051,31 @@ static void build_solve_plan(Factor& F) {
     P.up_dst = DevBuf<int64_t>(di);
     P.n_up = (int64_t)si.size();
   }
+  if (F.opt.precision == FDS_PREC_MIXED) {
+    // products with the FP64 diagonal blocks (without the children's A~) of
+    // every compressed level: y_i = B_i z_i on the level vectors
+    for (int lev = L; lev > l0; --lev) {
+      CellLevel& lv = F.levels[lev];
+      std::vector<GemmDesc> gd;
+      for (int q = 0; q < lv.n; ++q) {
+        GemmDesc g{};
+        g.a_off = lv.a_off[q];
+        g.b_off = lv.f_off[q];
+        g.c_off = lv.f_off[q];
+        g.m = lv.b[q];
+        g.k = lv.b[q];
+        g.lda = lv.b[q];
+        g.ldb = (int)lv.B;
+        g.ldc = (int)lv.B;
+        g.alpha_re = 1.0;
+        gd.push_back(g);
+      }
+      auto t = gemm_tiles(gd);
+      lv.g_diag = DevBuf<GemmDesc>(gd);
+      lv.t_diag = DevBuf<GemmTile>(t);
+      lv.n_tdiag = (int)t.size();
+    }
+  }
   CellLevel& lf = F.levels[L];
   std::vector<int64_t> rows, cols, iota;
   for (int q = 0; q < lf.n; ++q) {
@@ -1029,35 +1136,176 @@ static void run_sweeps(Factor& F, int nrhs, const SweepBufs& b, hipStream_t s) {
   }
 }
 
+// Run ``launches`` (a pure launch sequence) directly, or as a hipGraph
+// captured on first use under ``key`` and replayed afterwards.
+template <typename Fn>
+static void run_maybe_captured(Factor& F, bool graph, int64_t key, hipStream_t s, Fn&& launches) {
+  if (!graph) {
+    launches();
+    return;
+  }
+  auto it = F.graphs.find(key);
+  if (it == F.graphs.end()) {
+    hipGraph_t g;
+    FDS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      launches();
+    } catch (...) {
+      hipGraph_t dummy;
+      (void)hipStreamEndCapture(s, &dummy);
+      throw;
+    }
+    FDS_HIP(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FDS_HIP(e);
+    it = F.graphs.emplace(key, ex).first;
+  }
+  FDS_HIP(hipGraphLaunch(it->second, s));
+}
+
 static void run_solve(Factor& F, int nrhs, const c64* rhs, int64_t ld_rhs, c64* x, int64_t ld_x, hipStream_t s,
                       bool graph) {
   CellLevel& lf = F.levels[F.L];
   const SweepBufs b = sweep_buffers(F, nrhs, graph ? "g" + std::to_string(nrhs) + "_" : "sv_");
   launch_copy_rows(lf.B, F.leaf_dofs_rows.p, F.leaf_iota.p, nrhs, rhs, ld_rhs, b.F[F.L], lf.B, s);
-  if (graph) {
-    auto it = F.graphs.find(nrhs);
-    if (it == F.graphs.end()) {
-      hipGraph_t g;
-      FDS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      try {
-        run_sweeps(F, nrhs, b, s);
-      } catch (...) {
-        hipGraph_t dummy;
-        (void)hipStreamEndCapture(s, &dummy);
-        throw;
-      }
-      FDS_HIP(hipStreamEndCapture(s, &g));
-      hipGraphExec_t ex;
-      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      FDS_HIP(e);
-      it = F.graphs.emplace(nrhs, ex).first;
-    }
-    FDS_HIP(hipGraphLaunch(it->second, s));
-  } else {
-    run_sweeps(F, nrhs, b, s);
-  }
+  run_maybe_captured(F, graph, 4 * (int64_t)nrhs, s, [&] { run_sweeps(F, nrhs, b, s); });
   launch_copy_rows(lf.B, F.leaf_iota.p, F.leaf_dofs_cols.p, nrhs, b.F[F.L], lf.B, x, ld_x, s);
+}
+
+// ------------------------------------------------------------------ mixed form
+struct MixedBufs {
+  std::vector<c32*> F, T, Y;   // FP32 sweep level vectors
+  c64* root = nullptr;         // FP64 root vector (order of the root system x nrhs)
+  std::vector<c64*> Z, W, M;   // compressed-operator product: input, output and skeleton level vectors
+  c64* f = nullptr;            // right-hand sides in leaf row order
+  double* norms = nullptr;     // |f|^2, |r|^2, |x|^2, |delta|^2 per column
+};
+
+static MixedBufs mixed_buffers(Factor& F, int nrhs, const std::string& prefix) {
+  MixedBufs b;
+  b.F.assign(F.L + 1, nullptr);
+  b.T.assign(F.L + 1, nullptr);
+  b.Y.assign(F.L + 1, nullptr);
+  b.Z.assign(F.L + 1, nullptr);
+  b.W.assign(F.L + 1, nullptr);
+  b.M.assign(F.L + 1, nullptr);
+  for (int lev = F.l0; lev <= F.L; ++lev) {
+    const std::string l = std::to_string(lev);
+    const size_t nb = (size_t)F.levels[lev].B * nrhs;
+    b.F[lev] = F.ws.get<c32>(prefix + "F32_" + l, nb);
+    b.Z[lev] = F.ws.get<c64>(prefix + "Z" + l, nb);
+    b.W[lev] = F.ws.get<c64>(prefix + "W" + l, nb);
+    if (lev > F.l0) {
+      const size_t nr = (size_t)F.levels[lev].R * nrhs;
+      b.T[lev] = F.ws.get<c32>(prefix + "T32_" + l, nr);
+      b.Y[lev] = F.ws.get<c32>(prefix + "Y32_" + l, nr);
+      b.M[lev] = F.ws.get<c64>(prefix + "M" + l, nr);
+    }
+  }
+  b.root = F.ws.get<c64>(prefix + "root", (size_t)F.root.n * nrhs);
+  b.f = F.ws.get<c64>(prefix + "f", (size_t)F.levels[F.L].B * nrhs);
+  b.norms = F.ws.get<double>(prefix + "norms", (size_t)4 * nrhs);
+  return b;
+}
+
+// FP32 upward sweep, FP64 root solve, FP32 downward sweep: F[L] <- A_c^{-1} F[L]
+// (the same plan as the plain form on the FP32 factors).
+static void run_sweeps32(Factor& F, int nrhs, const MixedBufs& b, hipStream_t s) {
+  const int L = F.L, l0 = F.l0;
+  auto& levels = F.levels;
+  for (int lev = L; lev > l0; --lev) {
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A32.p, lv.piv.p, b.F[lev], s);
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V32.p, b.F[lev], b.Y[lev], 0, s);
+    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s);
+    launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
+  }
+  const int64_t nroot = (int64_t)F.root.n * nrhs;
+  launch_convert(nroot, b.F[l0], b.root, s);
+  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.root, s);
+  launch_convert(nroot, b.root, b.F[l0], s);
+  for (int lev = l0 + 1; lev <= L; ++lev) {
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.F[lev - 1], levels[lev - 1].B, b.Y[lev], lv.R, s);
+    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X32.p, b.T[lev], b.F[lev], 0, s);
+  }
+}
+
+// W[L] = A_c Z[L] in FP64 through the nested form of the compressed operator:
+// A_c = B_L + U_L (B_{L-1} + U_{L-1} ( ... B_l0 ... ) V_{L-1}) V_L, where B_l
+// holds the FP64 diagonal blocks of level l without the children's A~
+// (the plain leaf blocks at L) and B_l0 the root system likewise.
+static void run_apply(Factor& F, int nrhs, const MixedBufs& b, hipStream_t s) {
+  const int L = F.L, l0 = F.l0;
+  auto& levels = F.levels;
+  for (int lev = L; lev > l0; --lev) {   // skeleton values z_{l-1} = V_l z_l
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.Z[lev], b.M[lev], 0, s);
+    launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.M[lev], lv.R, b.Z[lev - 1], levels[lev - 1].B, s);
+  }
+  launch_gemm(F.root.g_b.p, F.root.t_b.p, F.root.n_tb, nrhs, nrhs, F.root.B.p, b.Z[l0], b.W[l0], 0, s);
+  for (int lev = l0 + 1; lev <= L; ++lev) {   // w_l = B_l z_l + U_l w_{l-1}
+    CellLevel& lv = levels[lev];
+    SolveLevel& P = lv.plan;
+    launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.W[lev - 1], levels[lev - 1].B, b.M[lev], lv.R, s);
+    launch_gemm(lv.g_diag.p, lv.t_diag.p, lv.n_tdiag, nrhs, nrhs, lv.A.p, b.Z[lev], b.W[lev], 0, s);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.M[lev], b.W[lev], 0, s);
+  }
+}
+
+// Iterative refinement against the FP64 compressed operator (mixed form).
+// Returns FDS_OK or FDS_ENOCONV; x is written in both cases.
+static int run_solve_mixed(Factor& F, int nrhs, const c64* rhs, int64_t ld_rhs, c64* x, int64_t ld_x, hipStream_t s,
+                           bool graph) {
+  CellLevel& lf = F.levels[F.L];
+  const int L = F.L;
+  const int64_t nl = lf.B * (int64_t)nrhs;
+  const MixedBufs b = mixed_buffers(F, nrhs, graph ? "mg" + std::to_string(nrhs) + "_" : "mx_");
+  launch_copy_rows(lf.B, F.leaf_dofs_rows.p, F.leaf_iota.p, nrhs, rhs, ld_rhs, b.f, lf.B, s);
+  launch_colnorm2(lf.B, nrhs, b.f, lf.B, b.norms, s);
+  launch_convert(nl, b.f, b.F[L], s);
+  run_maybe_captured(F, graph, 4 * (int64_t)nrhs + 1, s, [&] { run_sweeps32(F, nrhs, b, s); });
+  launch_convert(nl, b.F[L], b.Z[L], s);   // x_0 in leaf column order
+  std::vector<double> h(4 * (size_t)nrhs);
+  int it = 0, status = FDS_OK;
+  double res = 0.0, cor = 1.0;
+  for (;;) {
+    run_maybe_captured(F, graph, 4 * (int64_t)nrhs + 2, s, [&] { run_apply(F, nrhs, b, s); });
+    launch_axpby(nl, 1.0, b.f, -1.0, b.W[L], s);   // r = f - A_c x
+    launch_colnorm2(lf.B, nrhs, b.W[L], lf.B, b.norms + nrhs, s);
+    launch_colnorm2(lf.B, nrhs, b.Z[L], lf.B, b.norms + 2 * nrhs, s);
+    FDS_HIP(hipMemcpyAsync(h.data(), b.norms, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    res = 0.0;
+    cor = it == 0 ? 1.0 : 0.0;
+    for (int k = 0; k < nrhs; ++k) {
+      const double f2 = h[k], r2 = h[nrhs + k], x2 = h[2 * nrhs + k], d2 = h[3 * nrhs + k];
+      res = std::max(res, f2 > 0 ? std::sqrt(r2 / f2) : (r2 > 0 ? INFINITY : 0.0));
+      if (it > 0) cor = std::max(cor, x2 > 0 ? std::sqrt(d2 / x2) : (d2 > 0 ? INFINITY : 0.0));
+    }
+    if (!std::isfinite(res)) throw Error(FDS_ESINGULAR, "mixed solve: non-finite residual");
+    if (res <= F.opt.ir_rtol && cor <= F.opt.ir_dtol) break;
+    if (it >= F.opt.ir_max_iter) {
+      status = FDS_ENOCONV;
+      break;
+    }
+    launch_convert(nl, b.W[L], b.F[L], s);
+    run_maybe_captured(F, graph, 4 * (int64_t)nrhs + 1, s, [&] { run_sweeps32(F, nrhs, b, s); });
+    launch_colnorm2(lf.B, nrhs, b.F[L], lf.B, b.norms + 3 * nrhs, s);
+    launch_add_c32(nl, b.F[L], b.Z[L], s);
+    ++it;
+  }
+  launch_copy_rows(lf.B, F.leaf_iota.p, F.leaf_dofs_cols.p, nrhs, b.Z[L], lf.B, x, ld_x, s);
+  F.st.ir_iterations = it;
+  F.st.ir_residual = res;
+  F.st.ir_correction = cor;
+  return status;
 }
 
 static void resolve_stats(Factor& F) {
@@ -1095,6 +1343,10 @@ int fds_options_default(fds_options* o) {
   o->root_level = 1;
   o->proxy_ratio = 1.5;
   o->use_alpha = 0;
+  o->precision = FDS_PREC_FP64;
+  o->ir_max_iter = 10;
+  o->ir_rtol = 1e-9;
+  o->ir_dtol = 1.0;
   return FDS_OK;
 }
 
@@ -1112,6 +1364,9 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
   fds_options_default(&o);
   if (opt) o = *opt;
   if (o.leaf_nodes < 4 || o.n_proxy < 8 || o.root_level < 0 || !(o.proxy_ratio > 1.0)) return FDS_EINVAL;
+  if (o.precision != FDS_PREC_FP64 && o.precision != FDS_PREC_MIXED) return FDS_EINVAL;
+  if (o.precision == FDS_PREC_MIXED && (o.ir_max_iter < 0 || !(o.ir_rtol > 0) || !(o.ir_dtol > 0)))
+    return FDS_EINVAL;
   auto* F = new Factor();
   try {
     if (int e = make_geometry(geom, F->G)) {
@@ -1154,8 +1409,11 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->st.root_size = F->root.n;
     int64_t bytes = 0;
     for (auto& lv : F->levels)
-      bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) + (lv.piv.n + lv.s_piv.n) * sizeof(int);
-    bytes += (int64_t)F->root.A.n * sizeof(c64);
+      bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) +
+               (int64_t)(lv.A32.n + lv.X32.n + lv.At32.n + lv.V32.n) * sizeof(c32) +
+               (lv.piv.n + lv.s_piv.n) * sizeof(int);
+    bytes += (int64_t)(F->root.A.n + F->root.B.n) * sizeof(c64);
+    F->st.precision = o.precision;
     F->st.factor_bytes = bytes;
     F->st.assembly_seconds = F->ast.seconds;
     F->st.kernel_evals = F->ast.evals;
@@ -1217,7 +1475,39 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fd
       FDS_HIP(hipStreamSynchronize(f->ws.stream()));
       f->ws.set_stream(s);
     }
-    run_solve(*f, nrhs, (const c64*)rhs, ld_rhs, (c64*)x, ld_x, s, graph);
+    int status = FDS_OK;
+    if (f->opt.precision == FDS_PREC_MIXED)
+      status = run_solve_mixed(*f, nrhs, (const c64*)rhs, ld_rhs, (c64*)x, ld_x, s, graph);
+    else
+      run_solve(*f, nrhs, (const c64*)rhs, ld_rhs, (c64*)x, ld_x, s, graph);
+    FDS_HIP(hipStreamSynchronize(s));
+    if (status == FDS_ENOCONV) g_last_error = "iterative refinement did not reach its tolerance";
+    return status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c64* y, int64_t ld_y, void* stream) {
+  const int64_t N = f ? 2 * (int64_t)f->G.n_nodes : 0;
+  if (!f || nrhs < 1 || !x || !y || ld_x < N || ld_y < N) return FDS_EINVAL;
+  if (f->opt.precision != FDS_PREC_MIXED) {
+    g_last_error = "fds_apply needs a factor built with FDS_PREC_MIXED";
+    return FDS_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    if (s != f->ws.stream()) {
+      FDS_HIP(hipStreamSynchronize(f->ws.stream()));
+      f->ws.set_stream(s);
+    }
+    Factor& F = *f;
+    CellLevel& lf = F.levels[F.L];
+    const MixedBufs b = mixed_buffers(F, nrhs, "ap_");
+    launch_copy_rows(lf.B, F.leaf_dofs_cols.p, F.leaf_iota.p, nrhs, (const c64*)x, ld_x, b.Z[F.L], lf.B, s);
+    run_apply(F, nrhs, b, s);
+    launch_copy_rows(lf.B, F.leaf_iota.p, F.leaf_dofs_rows.p, nrhs, b.W[F.L], lf.B, (c64*)y, ld_y, s);
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {

@@ -2,7 +2,10 @@
 //
 // One workgroup per problem (LU, pivoted QR, interpolation matrices) or per
 // (problem, tile) (solves, GEMM, scatters); every launch covers a whole
-// batch of unevenly sized problems described by descriptor arrays.
+// batch of unevenly sized problems described by descriptor arrays.  The LU,
+// LU-solve, GEMM and copy kernels are templated on the complex scalar type:
+// complex FP64 for the plain form, complex FP32 (FP32 accumulation) for the
+// merges and sweeps of the mixed-precision form.
 #include <algorithm>
 
 #include "devmem.hpp"
@@ -18,14 +21,26 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
+template <typename T>
+__device__ inline T zero() {
+  return Cx<T>::make(0.0, 0.0);
+}
+
+template <typename TD, typename TS>
+__device__ inline TD cvt(TS a) {
+  return Cx<TD>::make((double)a.re, (double)a.im);
+}
+
 // ------------------------------------------------------------------ LU
 // Right-looking LU with partial pivoting (largest modulus, lowest row on
 // ties).  L is unit lower triangular, stored below the diagonal; piv[j] is
 // the row swapped with row j at step j (LAPACK convention, 0-based).
-__global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c64* __restrict__ base,
+// Unblocked form: the fallback for matrices too large for the panel in LDS.
+template <typename T>
+__global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, T* __restrict__ base,
                                              int* __restrict__ piv, int* __restrict__ info) {
   const LUDesc d = descs[blockIdx.x];
-  c64* A = base + d.a_off;
+  T* A = base + d.a_off;
   int* P = piv + d.piv_off;
   const int n = d.n, lda = d.lda;
   const int tid = threadIdx.x;
@@ -63,14 +78,14 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c
     if (!(pv > 0.0) || !isfinite(pv)) bad = bad ? bad : j + 1;
     if (p != j) {
       for (int c = tid; c < n; c += kBlk) {
-        const c64 t = A[j + (int64_t)c * lda];
+        const T t = A[j + (int64_t)c * lda];
         A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
         A[p + (int64_t)c * lda] = t;
       }
     }
     __syncthreads();
-    const c64 piv_v = A[j + (int64_t)j * lda];
-    const c64 inv = (pv > 0.0) ? cdiv(cmk(1.0, 0.0), piv_v) : cmk(0.0, 0.0);
+    const T piv_v = A[j + (int64_t)j * lda];
+    const T inv = (pv > 0.0) ? cdiv(Cx<T>::make(1.0, 0.0), piv_v) : zero<T>();
     for (int i = j + 1 + tid; i < n; i += kBlk) A[i + (int64_t)j * lda] = A[i + (int64_t)j * lda] * inv;
     __syncthreads();
     const int m = n - j - 1;
@@ -90,15 +105,16 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, c
 // is factored in LDS; its row interchanges are then applied to the other
 // columns, U12 = L11^{-1} A12 is formed column by column, and the trailing
 // matrix gets one rank-NB update per panel.
-template <int NB>
-__global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ descs, c64* __restrict__ base,
+template <int NB, typename T>
+__global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ descs, T* __restrict__ base,
                                                  int* __restrict__ piv, int* __restrict__ info) {
-  extern __shared__ c64 Pn[];          // panel, column-major with leading dimension ldp
+  extern __shared__ unsigned char smem_lu[];
+  T* Pn = reinterpret_cast<T*>(smem_lu);   // panel, column-major with leading dimension ldp
   __shared__ double sv[kBlk / 64];
   __shared__ int si[kBlk / 64];
   __shared__ int s_p;
   const LUDesc d = descs[blockIdx.x];
-  c64* A = base + d.a_off;
+  T* A = base + d.a_off;
   int* P = piv + d.piv_off;
   const int n = d.n, lda = d.lda;
   const int ldp = n;
@@ -151,15 +167,15 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
       __syncthreads();
       const int p = s_p;
       if (p != j && tid < nb) {
-        const c64 t = Pn[j + tid * ldp];
+        const T t = Pn[j + tid * ldp];
         Pn[j + tid * ldp] = Pn[p + tid * ldp];
         Pn[p + tid * ldp] = t;
       }
       __syncthreads();
-      const c64 pj = Pn[j + j * ldp];
-      const c64 inv = abs2(pj) > 0.0 ? cdiv(cmk(1.0, 0.0), pj) : cmk(0.0, 0.0);
+      const T pj = Pn[j + j * ldp];
+      const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
       for (int i = j + 1 + tid; i < mp; i += kBlk) {
-        const c64 l = Pn[i + j * ldp] * inv;
+        const T l = Pn[i + j * ldp] * inv;
         Pn[i + j * ldp] = l;
         for (int c = j + 1; c < nb; ++c) Pn[i + c * ldp] -= l * Pn[j + c * ldp];
       }
@@ -172,11 +188,11 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
     // row interchanges of this panel on the columns outside it, one thread per column
     for (int c = tid; c < n; c += kBlk) {
       if (c >= k0 && c < k0 + nb) continue;
-      c64* col = A + (int64_t)c * lda;
+      T* col = A + (int64_t)c * lda;
       for (int j = 0; j < nb; ++j) {
         const int p = P[k0 + j];
         if (p != k0 + j) {
-          const c64 t = col[k0 + j];
+          const T t = col[k0 + j];
           col[k0 + j] = col[p];
           col[p] = t;
         }
@@ -185,12 +201,12 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
     __syncthreads();
     // U12 = L11^{-1} A12, one thread per column
     for (int c = k0 + nb + tid; c < n; c += kBlk) {
-      c64* col = A + (int64_t)c * lda + k0;
-      c64 x[NB];
+      T* col = A + (int64_t)c * lda + k0;
+      T x[NB];
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
         if (r < nb) {
-          c64 s = col[r];
+          T s = col[r];
 #pragma unroll
           for (int q = 0; q < NB; ++q)
             if (q < r) s -= Pn[r + q * ldp] * x[q];
@@ -205,8 +221,8 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
     const int64_t tot = (int64_t)m2 * m2;
     for (int64_t t = tid; t < tot; t += kBlk) {
       const int i = (int)(t % m2), c = (int)(t / m2);
-      const c64* u = A + (int64_t)(k0 + nb + c) * lda + k0;
-      c64 s = A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda];
+      const T* u = A + (int64_t)(k0 + nb + c) * lda + k0;
+      T s = A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda];
 #pragma unroll
       for (int q = 0; q < NB; ++q)
         if (q < nb) s -= Pn[(nb + i) + q * ldp] * u[q];
@@ -219,18 +235,23 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
 
 // ------------------------------------------------------------------ LU solve
 // block (blockIdx.x = problem, blockIdx.y = chunk of ``chunk`` columns);
-// ncol_override > 0 replaces every problem's column count.
+// ncol_override > 0 replaces every problem's column count.  The chunk of B
+// is staged in LDS; substitution proceeds by blocks of 16 rows: the
+// diagonal block is solved by 16 lanes per column with shuffles, the rest
+// of the chunk is updated with one barrier pair per block.
+template <typename T>
 __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, int chunk, int ncol_override,
-                                                   const c64* __restrict__ abase, const int* __restrict__ piv,
-                                                   c64* __restrict__ bbase) {
-  extern __shared__ c64 X[];
+                                                   const T* __restrict__ abase, const int* __restrict__ piv,
+                                                   T* __restrict__ bbase) {
+  extern __shared__ unsigned char smem_sv[];
+  T* X = reinterpret_cast<T*>(smem_sv);
   const SolveDesc d = descs[blockIdx.x];
   const int ncol = ncol_override > 0 ? ncol_override : d.ncol;
   const int c0 = blockIdx.y * chunk;
   if (c0 >= ncol || d.n == 0) return;
-  const c64* A = abase + d.a_off;
+  const T* A = abase + d.a_off;
   const int* P = piv + d.piv_off;
-  c64* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
+  T* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
   const int n = d.n, lda = d.lda, nc = min(chunk, ncol - c0);
   const int tid = threadIdx.x;
   for (int t = tid; t < n * nc; t += kBlk) {
@@ -242,7 +263,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     for (int j = 0; j < n; ++j) {
       const int p = P[j];
       if (p != j) {
-        const c64 t = X[j + tid * n];
+        const T t = X[j + tid * n];
         X[j + tid * n] = X[p + tid * n];
         X[p + tid * n] = t;
       }
@@ -253,23 +274,21 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   const int r0 = tid / nc;
   const int rs = kBlk / nc;
   constexpr int SB = 16;   // rows per substitution block
-  // diagonal-block solves: lane = 16 * (column within the wave) + row; the
-  // solved entry of each row is broadcast to the later rows by shuffles
   const int br = tid & 15;            // row within the block
   const int bc = tid >> 4;            // column handled by this lane group
-  // forward substitution with unit L, SB rows at a time
+  // forward substitution with unit L
   for (int k0 = 0; k0 < n; k0 += SB) {
     const int nb = min(SB, n - k0);
     if (tid < 8 * 16) {               // two wavefronts, up to 8 columns
       const bool act = bc < nc && br < nb;
-      c64 x = act ? X[k0 + br + bc * n] : cmk(0, 0);
-      c64 l[SB];
+      T x = act ? X[k0 + br + bc * n] : zero<T>();
+      T l[SB];
 #pragma unroll
-      for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : cmk(0, 0);
+      for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
 #pragma unroll
       for (int q = 0; q < SB - 1; ++q) {
         const int src = ((tid & 63) & ~15) + q;
-        c64 xq;
+        T xq;
         xq.re = __shfl(x.re, src);
         xq.im = __shfl(x.im, src);
         if (br > q) x -= l[q] * xq;
@@ -279,28 +298,28 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     __syncthreads();
     if (r0 < rs)
       for (int i = k0 + nb + r0; i < n; i += rs) {
-        c64 s = X[i + cc * n];
+        T s = X[i + cc * n];
         for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
         X[i + cc * n] = s;
       }
     __syncthreads();
   }
-  // backward substitution with U, SB rows at a time from the bottom
+  // backward substitution with U, from the bottom
   for (int k1 = n; k1 > 0; k1 -= SB) {
     const int k0 = max(0, k1 - SB), nb = k1 - k0;
     if (tid < 8 * 16) {
       const bool act = bc < nc && br < nb;
-      c64 x = act ? X[k0 + br + bc * n] : cmk(0, 0);
-      c64 u[SB];
+      T x = act ? X[k0 + br + bc * n] : zero<T>();
+      T u[SB];
 #pragma unroll
       for (int q = 0; q < SB; ++q)
-        u[q] = (act && q >= br && q < nb) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : cmk(0, 0);
+        u[q] = (act && q >= br && q < nb) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
       // u[q] holds U(row, k0 + q) for q >= row; the diagonal sits at u[row]
 #pragma unroll
       for (int q = SB - 1; q >= 0; --q) {
         if (act && q < nb && br == q) x = cdiv(x, u[q]);
         const int src = ((tid & 63) & ~15) + q;
-        c64 xq;
+        T xq;
         xq.re = __shfl(x.re, src);
         xq.im = __shfl(x.im, src);
         if (q < nb && br < q) x -= u[q] * xq;
@@ -310,7 +329,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     __syncthreads();
     if (r0 < rs)
       for (int i = r0; i < k0; i += rs) {
-        c64 s = X[i + cc * n];
+        T s = X[i + cc * n];
         for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
         X[i + cc * n] = s;
       }
@@ -327,45 +346,44 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 // LDS, each thread owning a 4 x 4 block of outputs.
 // block (blockIdx.x = row tile (problem, tm) from ``tiles``, blockIdx.y = tn);
 // n_override > 0 replaces every problem's column count.
-template <int TA>
+template <int TA, typename T>
 __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
-                                               int n_override, const c64* __restrict__ abase,
-                                               const c64* __restrict__ bbase, c64* __restrict__ cbase) {
-  __shared__ c64 As[16][65];
-  __shared__ c64 Bs[16][65];
+                                               int n_override, const T* __restrict__ abase,
+                                               const T* __restrict__ bbase, T* __restrict__ cbase) {
+  __shared__ T As[16][65];
+  __shared__ T Bs[16][65];
   const GemmTile tl = tiles[blockIdx.x];
   GemmDesc d = descs[tl.desc];
   if (n_override > 0) d.n = n_override;
   if ((int)blockIdx.y * 64 >= d.n) return;
-  const c64* A = abase + d.a_off;
-  const c64* B = bbase + d.b_off;
-  c64* C = cbase + d.c_off;
+  const T* A = abase + d.a_off;
+  const T* B = bbase + d.b_off;
+  T* C = cbase + d.c_off;
   const int m0 = tl.tm * 64, n0 = blockIdx.y * 64;
   const int tid = threadIdx.x;
   const int tr = tid % 16, tc = tid / 16;   // thread owns rows tr + 16 a, cols tc + 16 b
-  c64 acc[4][4];
+  T acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = cmk(0, 0);
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero<T>();
   for (int k0 = 0; k0 < d.k; k0 += 16) {
-    // stage op(A)[m0:m0+64, k0:k0+16] and B[k0:k0+16, n0:n0+64]
     for (int t = tid; t < 64 * 16; t += kBlk) {
       const int ii = t % 64, kk = t / 64;
       const int gi = m0 + ii, gk = k0 + kk;
-      c64 va = cmk(0, 0);
+      T va = zero<T>();
       if (gi < d.m && gk < d.k) va = TA ? A[gk + (int64_t)gi * d.lda] : A[gi + (int64_t)gk * d.lda];
       As[kk][ii] = va;
       const int kb = t % 16, jj = t / 16;
       const int gkb = k0 + kb, gj = n0 + jj;
-      c64 vb = cmk(0, 0);
+      T vb = zero<T>();
       if (gkb < d.k && gj < d.n) vb = B[gkb + (int64_t)gj * d.ldb];
       Bs[kb][jj] = vb;
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < 16; ++kk) {
-      c64 av[4], bv[4];
+      T av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = As[kk][tr + 16 * a];
 #pragma unroll
@@ -377,7 +395,7 @@ __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ desc
     }
     __syncthreads();
   }
-  const c64 al = cmk(d.alpha_re, d.alpha_im), be = cmk(d.beta_re, d.beta_im);
+  const T al = Cx<T>::make(d.alpha_re, d.alpha_im), be = Cx<T>::make(d.beta_re, d.beta_im);
   const bool zero_beta = (d.beta_re == 0.0 && d.beta_im == 0.0);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -385,8 +403,8 @@ __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ desc
     for (int b = 0; b < 4; ++b) {
       const int gi = m0 + tr + 16 * a, gj = n0 + tc + 16 * b;
       if (gi < d.m && gj < d.n) {
-        c64* cp = C + gi + (int64_t)gj * d.ldc;
-        const c64 v = al * acc[a][b];
+        T* cp = C + gi + (int64_t)gj * d.ldc;
+        const T v = al * acc[a][b];
         *cp = zero_beta ? v : v + be * (*cp);
       }
     }
@@ -560,9 +578,12 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
   }
 }
 
+
 // ------------------------------------------------------------------ scatter / copies
+// Block scatter with an optional type conversion (FP32 A~ into FP64 blocks and back).
+template <typename TS, typename TD>
 __global__ void k_scatter(const ScatterDesc* __restrict__ descs, const ScatterTile* __restrict__ tiles,
-                          const int* __restrict__ pos, const c64* __restrict__ src, c64* __restrict__ dst) {
+                          const int* __restrict__ pos, const TS* __restrict__ src, TD* __restrict__ dst) {
   const ScatterTile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count) return;
   const ScatterDesc d = descs[t.desc];
@@ -570,11 +591,12 @@ __global__ void k_scatter(const ScatterDesc* __restrict__ descs, const ScatterTi
   const int r = (int)(e % d.nr), c = (int)(e / d.nr);
   const int64_t rp = d.rpos_off >= 0 ? pos[d.rpos_off + r] : r;
   const int64_t cp = d.cpos_off >= 0 ? pos[d.cpos_off + c] : c;
-  dst[d.dst_off + rp + cp * d.dst_ld] = src[d.src_off + r + (int64_t)c * d.src_ld];
+  dst[d.dst_off + rp + cp * d.dst_ld] = cvt<TD>(src[d.src_off + r + (int64_t)c * d.src_ld]);
 }
 
+template <typename T>
 __global__ void k_copy_rows(int64_t n, const int64_t* __restrict__ sidx, const int64_t* __restrict__ didx, int ncol,
-                            const c64* __restrict__ src, int64_t lds, c64* __restrict__ dst, int64_t ldd) {
+                            const T* __restrict__ src, int64_t lds, T* __restrict__ dst, int64_t ldd) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (i >= n || c >= ncol) return;
@@ -587,44 +609,83 @@ __global__ void k_axpby(int64_t n, double alpha, const c64* __restrict__ src, do
   dst[i] = alpha * src[i] + beta * dst[i];
 }
 
+// dst = convert(src) (contiguous)
+template <typename TS, typename TD>
+__global__ void k_convert(int64_t n, const TS* __restrict__ src, TD* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = cvt<TD>(src[i]);
+}
+
+// dst += (double) src
+__global__ void k_add_c32(int64_t n, const c32* __restrict__ src, c64* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] += cvt<c64>(src[i]);
+}
+
+// out[c] = sum_i |src[i + c ld]|^2 in FP64, one block per column
+template <typename T>
+__global__ void __launch_bounds__(kBlk) k_colnorm2(int64_t n, const T* __restrict__ src, int64_t ld,
+                                                   double* __restrict__ out) {
+  __shared__ double part[kBlk / 64];
+  const T* p = src + (int64_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlk) {
+    const double re = (double)p[i].re, im = (double)p[i].im;
+    s += re * re + im * im;
+  }
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlk / 64; ++w) t += part[w];
+    out[blockIdx.x] = t;
+  }
+}
+
+template <typename T>
 __global__ void k_fill_identity(const int64_t* __restrict__ offs, const int* __restrict__ ns, const int* __restrict__ lds,
-                                c64* __restrict__ base) {
+                                T* __restrict__ base) {
   const int p = blockIdx.x;
   const int n = ns[p], ld = lds[p];
-  c64* A = base + offs[p];
+  T* A = base + offs[p];
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
     const int i = t % n, c = t / n;
-    A[i + (int64_t)c * ld] = (i == c) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+    A[i + (int64_t)c * ld] = Cx<T>::make(i == c ? 1.0 : 0.0, 0.0);
   }
 }
 
 // ------------------------------------------------------------------ launchers
 // All launchers are asynchronous on ``s``: descriptor arrays are device
 // pointers owned by the caller (workspace or factor storage).
-void launch_lu(const LUDesc* d, int n, int nmax, c64* base, int* piv, int* info, hipStream_t s) {
+template <typename T>
+void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, hipStream_t s) {
   if (n == 0) return;
-  // panel of NB columns staged in LDS: nmax * NB * 16 bytes <= 48 KiB
-  const size_t row = (size_t)std::max(1, nmax) * sizeof(c64);
+  // panel of NB columns staged in LDS: nmax * NB * sizeof(T) <= 48 KiB
+  const size_t row = (size_t)std::max(1, nmax) * sizeof(T);
   if (row * 16 <= 49152)
-    k_lu_blk<16><<<n, kBlk, row * 16, s>>>(d, base, piv, info);
+    k_lu_blk<16, T><<<n, kBlk, row * 16, s>>>(d, base, piv, info);
   else if (row * 8 <= 49152)
-    k_lu_blk<8><<<n, kBlk, row * 8, s>>>(d, base, piv, info);
+    k_lu_blk<8, T><<<n, kBlk, row * 8, s>>>(d, base, piv, info);
   else if (row * 4 <= 49152)
-    k_lu_blk<4><<<n, kBlk, row * 4, s>>>(d, base, piv, info);
+    k_lu_blk<4, T><<<n, kBlk, row * 4, s>>>(d, base, piv, info);
   else
-    k_lu<<<n, kBlk, 0, s>>>(d, base, piv, info);
+    k_lu<T><<<n, kBlk, 0, s>>>(d, base, piv, info);
   FDS_HIP(hipGetLastError());
 }
 
 int solve_chunk(int nmax) { return std::max(1, std::min(8, 32768 / (16 * std::max(1, nmax)))); }
 
-void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const c64* abase,
-                     const int* piv, c64* bbase, hipStream_t s) {
+template <typename T>
+void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
+                     const int* piv, T* bbase, hipStream_t s) {
   if (n == 0 || ncol_max == 0) return;
   const int nc = solve_chunk(nmax);
-  if ((size_t)nmax * nc * sizeof(c64) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  if ((size_t)nmax * nc * sizeof(T) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
   dim3 grid(n, (ncol_max + nc - 1) / nc);
-  k_lu_solve<<<grid, kBlk, nmax * nc * sizeof(c64), s>>>(d, nc, ncol_override, abase, piv, bbase);
+  k_lu_solve<T><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
   FDS_HIP(hipGetLastError());
 }
 
@@ -635,14 +696,15 @@ std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d) {
   return t;
 }
 
-void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const c64* abase,
-                 const c64* bbase, c64* cbase, int transA, hipStream_t s) {
+template <typename T>
+void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
+                 const T* bbase, T* cbase, int transA, hipStream_t s) {
   if (n_tiles == 0 || n_max == 0) return;
   dim3 grid(n_tiles, (n_max + 63) / 64);
   if (transA)
-    k_gemm<1><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+    k_gemm<1, T><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
   else
-    k_gemm<0><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+    k_gemm<0, T><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
   FDS_HIP(hipGetLastError());
 }
 
@@ -672,18 +734,20 @@ std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d) {
   return tiles;
 }
 
-void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const c64* src,
-                    c64* dst, hipStream_t s) {
+template <typename TS, typename TD>
+void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const TS* src,
+                    TD* dst, hipStream_t s) {
   if (n_tiles == 0) return;
-  k_scatter<<<n_tiles, 256, 0, s>>>(d, tiles, pos, src, dst);
+  k_scatter<TS, TD><<<n_tiles, 256, 0, s>>>(d, tiles, pos, src, dst);
   FDS_HIP(hipGetLastError());
 }
 
-void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,
-                      c64* dst, int64_t ldd, hipStream_t s) {
+template <typename T>
+void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const T* src, int64_t lds,
+                      T* dst, int64_t ldd, hipStream_t s) {
   if (n == 0 || ncol == 0) return;
   dim3 grid((unsigned)((n + 255) / 256), ncol);
-  k_copy_rows<<<grid, 256, 0, s>>>(n, sidx, didx, ncol, src, lds, dst, ldd);
+  k_copy_rows<T><<<grid, 256, 0, s>>>(n, sidx, didx, ncol, src, lds, dst, ldd);
   FDS_HIP(hipGetLastError());
 }
 
@@ -693,10 +757,52 @@ void launch_axpby(int64_t n, double alpha, const c64* src, double beta, c64* dst
   FDS_HIP(hipGetLastError());
 }
 
-void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, c64* base, hipStream_t s) {
-  if (n_mats == 0) return;
-  k_fill_identity<<<(unsigned)n_mats, 256, 0, s>>>(offs, ns, lds, base);
+template <typename TS, typename TD>
+void launch_convert(int64_t n, const TS* src, TD* dst, hipStream_t s) {
+  if (n == 0) return;
+  k_convert<TS, TD><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, src, dst);
   FDS_HIP(hipGetLastError());
 }
+
+void launch_add_c32(int64_t n, const c32* src, c64* dst, hipStream_t s) {
+  if (n == 0) return;
+  k_add_c32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, src, dst);
+  FDS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_colnorm2(int64_t n, int ncol, const T* src, int64_t ld, double* out, hipStream_t s) {
+  if (ncol == 0) return;
+  k_colnorm2<T><<<ncol, kBlk, 0, s>>>(n, src, ld, out);
+  FDS_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, T* base, hipStream_t s) {
+  if (n_mats == 0) return;
+  k_fill_identity<T><<<(unsigned)n_mats, 256, 0, s>>>(offs, ns, lds, base);
+  FDS_HIP(hipGetLastError());
+}
+
+#define FDS_INST(T)                                                                                                 \
+  template void launch_lu<T>(const LUDesc*, int, int, T*, int*, int*, hipStream_t);                                \
+  template void launch_lu_solve<T>(const SolveDesc*, int, int, int, int, const T*, const int*, T*, hipStream_t);   \
+  template void launch_gemm<T>(const GemmDesc*, const GemmTile*, int, int, int, const T*, const T*, T*, int,       \
+                               hipStream_t);                                                                        \
+  template void launch_copy_rows<T>(int64_t, const int64_t*, const int64_t*, int, const T*, int64_t, T*, int64_t,  \
+                                    hipStream_t);                                                                   \
+  template void launch_colnorm2<T>(int64_t, int, const T*, int64_t, double*, hipStream_t);                         \
+  template void launch_fill_identity<T>(int64_t, const int64_t*, const int*, const int*, T*, hipStream_t);
+FDS_INST(c64)
+FDS_INST(c32)
+#undef FDS_INST
+template void launch_scatter<c64, c64>(const ScatterDesc*, const ScatterTile*, int, const int*, const c64*, c64*,
+                                       hipStream_t);
+template void launch_scatter<c32, c32>(const ScatterDesc*, const ScatterTile*, int, const int*, const c32*, c32*,
+                                       hipStream_t);
+template void launch_scatter<c32, c64>(const ScatterDesc*, const ScatterTile*, int, const int*, const c32*, c64*,
+                                       hipStream_t);
+template void launch_convert<c64, c32>(int64_t, const c64*, c32*, hipStream_t);
+template void launch_convert<c32, c64>(int64_t, const c32*, c64*, hipStream_t);
 
 }  // namespace fds

@@ -58,25 +58,42 @@ struct ScatterTile {
   int64_t start;
 };
 
-// Asynchronous launchers; descriptor arrays are device pointers.
-void launch_lu(const LUDesc* d, int n, int nmax, c64* base, int* piv, int* info, hipStream_t s);
+// Asynchronous launchers; descriptor arrays are device pointers.  The
+// templated ones exist for T = c64 (plain form) and T = c32 (the FP32 merges
+// and sweeps of the mixed-precision form).
+template <typename T>
+void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, hipStream_t s);
 int solve_chunk(int nmax);
-void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const c64* abase,
-                     const int* piv, c64* bbase, hipStream_t s);
+template <typename T>
+void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
+                     const int* piv, T* bbase, hipStream_t s);
 std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d);
-void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const c64* abase,
-                 const c64* bbase, c64* cbase, int transA, hipStream_t s);
+template <typename T>
+void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
+                 const T* bbase, T* cbase, int transA, hipStream_t s);
 void check_cpqr_sizes(const std::vector<CpqrDesc>& d);
 void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s);
 void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s);
 std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d);
-void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const c64* src,
-                    c64* dst, hipStream_t s);
+// (TS, TD) in {(c64, c64), (c32, c32), (c32, c64)}
+template <typename TS, typename TD>
+void launch_scatter(const ScatterDesc* d, const ScatterTile* tiles, int n_tiles, const int* pos, const TS* src,
+                    TD* dst, hipStream_t s);
 // dst[didx[i] + c * ldd] = src[sidx[i] + c * lds], i < n, c < ncol
-void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const c64* src, int64_t lds,
-                      c64* dst, int64_t ldd, hipStream_t s);
+template <typename T>
+void launch_copy_rows(int64_t n, const int64_t* sidx, const int64_t* didx, int ncol, const T* src, int64_t lds,
+                      T* dst, int64_t ldd, hipStream_t s);
 // dst[i] = alpha * src[i] + beta * dst[i]
 void launch_axpby(int64_t n, double alpha, const c64* src, double beta, c64* dst, hipStream_t s);
-void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, c64* base, hipStream_t s);
+// dst[i] = src[i] converted, (TS, TD) in {(c64, c32), (c32, c64)}
+template <typename TS, typename TD>
+void launch_convert(int64_t n, const TS* src, TD* dst, hipStream_t s);
+// dst[i] += src[i] (FP32 correction added to an FP64 vector)
+void launch_add_c32(int64_t n, const c32* src, c64* dst, hipStream_t s);
+// out[c] = sum_{i<n} |src[i + c ld]|^2 (FP64), c < ncol
+template <typename T>
+void launch_colnorm2(int64_t n, int ncol, const T* src, int64_t ld, double* out, hipStream_t s);
+template <typename T>
+void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, T* base, hipStream_t s);
 
 }  // namespace fds

@@ -64,6 +64,45 @@ __host__ __device__ inline c64 cdiv(c64 a, c64 b) {
   return c64{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
+// complex FP32 (mixed-precision merges and sweeps)
+struct c32 {
+  float re, im;
+};
+__host__ __device__ inline c32 operator+(c32 a, c32 b) { return c32{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline c32 operator-(c32 a, c32 b) { return c32{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline c32 operator*(c32 a, c32 b) {
+  return c32{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline c32& operator+=(c32& a, c32 b) {
+  a.re += b.re;
+  a.im += b.im;
+  return a;
+}
+__host__ __device__ inline c32& operator-=(c32& a, c32 b) {
+  a.re -= b.re;
+  a.im -= b.im;
+  return a;
+}
+__host__ __device__ inline float abs2(c32 a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline c32 cdiv(c32 a, c32 b) {
+  const float d = b.re * b.re + b.im * b.im;
+  return c32{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// scalar-type helpers for kernels templated on c64 / c32
+template <typename T>
+struct Cx;
+template <>
+struct Cx<c64> {
+  using real = double;
+  __host__ __device__ static c64 make(double r, double i) { return c64{r, i}; }
+};
+template <>
+struct Cx<c32> {
+  using real = float;
+  __host__ __device__ static c32 make(double r, double i) { return c32{(float)r, (float)i}; }
+};
+
 // J0, J1, Y0, Y1 of x > 0.
 __host__ __device__ inline void bessel_jy01(double x, double& J0, double& J1, double& Y0, double& Y1) {
   if (x < 2.0) {
