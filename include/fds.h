@@ -73,9 +73,10 @@ typedef struct {
   int32_t ir_max_iter;      /* mixed form: refinement steps allowed per solve; default 10 */
   int32_t reserved1;
   double ir_rtol;           /* mixed form: stop when every column has ||f - A_c x|| <= ir_rtol ||f||
-                               (default 1e-9) ... */
-  double ir_dtol;           /* ... and its last correction ||delta|| <= ir_dtol ||x|| (default 1.0, i.e.
-                               the residual alone decides) */
+                               (default 1e-8) ... */
+  double ir_dtol;           /* ... and its last correction ||delta|| <= ir_dtol ||x|| (default 1e-6; the
+                               correction measures the error of the previous iterate, which the step
+                               then reduces by the contraction factor of the FP32 solve) */
 } fds_options;
 
 enum { FDS_PREC_FP64 = 0, FDS_PREC_MIXED = 1 };

@@ -122,6 +122,7 @@ class Cell:
     ranks: dict = field(default_factory=dict)
     centre: np.ndarray = None
     radius: float = 0.0
+    n_near: tuple = (0, 0)     # near rows / near columns of the proxy matrices
 
 
 def build_tree(n_nodes: int, leaf: int):
@@ -231,6 +232,7 @@ def compress_cell(bnd, mat, tol, c, others):
     near_c = np.concatenate([o.cols for o in others]) if others else np.zeros(0, np.int64)
     near_r = near_r[_support_meets_disk(bnd, near_r // 2, c.centre, rho)] if len(near_r) else near_r
     near_c = near_c[_support_meets_disk(bnd, near_c // 2, c.centre, rho)] if len(near_c) else near_c
+    c.n_near = (len(near_r), len(near_c))
     pdofs = np.arange(2 * N_PROXY)
     MV = entries(bnd, pdofs, c.cols, mat, proxy_rows=P)
     MU = entries(bnd, c.rows, pdofs, mat, proxy_cols=P)

@@ -1345,8 +1345,8 @@ int fds_options_default(fds_options* o) {
   o->use_alpha = 0;
   o->precision = FDS_PREC_FP64;
   o->ir_max_iter = 10;
-  o->ir_rtol = 1e-9;
-  o->ir_dtol = 1.0;
+  o->ir_rtol = 1e-8;
+  o->ir_dtol = 1e-6;
   return FDS_OK;
 }
 

@@ -7,7 +7,8 @@ iterative refinement against the FP64 compressed operator A_c.
   FDS solve: A_c (A_c^{-1} f) = f to rounding, with A_c^{-1} f taken from the
   CPU oracle (independent code).
 * The refined solutions match the plain FP64 solutions per right-hand side:
-  <= 1e-6 relative at the default stop rule (residual <= 1e-9), <= 1e-9 when
+  <= 1e-6 relative at the default stop rule (residual <= 1e-8, last
+  correction <= 1e-6), <= 1e-9 when
   refined to ir_rtol = 1e-12.
 * The step limit is honoured: ir_max_iter = 0 returns FDS_ENOCONV with the
   unrefined FP32 solution written.
@@ -54,7 +55,7 @@ def test_mixed_against_plain_and_oracle(fdsmod, case):
     xm = Fm.solve(rhs)
     st = Fm.stats()
     assert st["precision"] == fdsmod.PREC_MIXED
-    assert st["ir_residual"] <= 1e-9 and st["ir_iterations"] >= 1
+    assert st["ir_residual"] <= 1e-8 and st["ir_correction"] <= 1e-6 and st["ir_iterations"] >= 1
     assert _rel_cols(xm, xp) < 1e-6
     # A_c applied to the oracle's FDS solution gives back the right-hand side
     X, A, Fmat = dense.dense_solve(curves, 2.0, 1.0, 1.0, omega, kinds, angles, return_matrix=True)
@@ -82,7 +83,7 @@ def test_mixed_step_limit(fdsmod):
     with pytest.raises(fdsmod.NotConverged) as e:
         Fm.solve(rhs)
     st = Fm.stats()
-    assert st["ir_iterations"] == 0 and st["ir_residual"] > 1e-9
+    assert st["ir_iterations"] == 0 and st["ir_residual"] > 1e-8
     # the unrefined FP32 solution is written: FP32-accurate, not FP64-accurate
     err = _rel_cols(e.value.x, xp)
     assert 1e-12 < err < 1e-3

@@ -48,7 +48,7 @@ def test_options_defaults_without_gpu():
         pytest.skip("library not built")
     o = m._options()
     assert (o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio, o.use_alpha) == (64, 64, 1, 1.5, 0)
-    assert (o.precision, o.ir_max_iter, o.ir_rtol, o.ir_dtol) == (m.PREC_FP64, 10, 1e-9, 1.0)
+    assert (o.precision, o.ir_max_iter, o.ir_rtol, o.ir_dtol) == (m.PREC_FP64, 10, 1e-8, 1e-6)
 
 
 def test_binding_structs_match_the_header(tmp_path):
