@@ -77,9 +77,19 @@ typedef struct {
   double ir_dtol;           /* ... and its last correction ||delta|| <= ir_dtol ||x|| (default 1e-6; the
                                correction measures the error of the previous iterate, which the step
                                then reduces by the contraction factor of the FP32 solve) */
+  int32_t rank_mode;        /* FDS_RANK_ADAPTIVE (default): every ID by the pivoted QR of its interaction
+                               matrix (Sections 7.1, 7.2).  FDS_RANK_LEARNED: the rank predictor pre-sizes a
+                               randomized ID (sketch of ceil(k_pred) + oversample rows); its result is kept
+                               when the sketch reveals the rank (taken at tol / 4) and the residual judge
+                               passes (every residual column within tol of the largest column of the
+                               interaction matrix itself), else the cell falls back to the pivoted QR */
+  int32_t oversample;       /* learned form: extra sketch rows; default 8 */
+  uint64_t seed;            /* learned form: seed of the sketches (SplitMix64); default 0x5EED */
+  const float* predictor;   /* learned form: host, FDS_MLP_BLOB floats (see fds_mlp_forward); copied */
 } fds_options;
 
 enum { FDS_PREC_FP64 = 0, FDS_PREC_MIXED = 1 };
+enum { FDS_RANK_ADAPTIVE = 0, FDS_RANK_LEARNED = 1 };
 
 /* Defaults listed above. */
 int fds_options_default(fds_options* opt);
@@ -152,6 +162,16 @@ typedef struct {
   int32_t ir_iterations;
   double ir_residual;
   double ir_correction;
+  /* IDs: cells of all compressed levels; learned form: cells whose IDs came
+   * from the sketch, and cells that fell back to the pivoted QR because the
+   * sketch did not reveal a rank or because the judge rejected it */
+  int32_t rank_mode;
+  int32_t reserved2;
+  int64_t cells_compressed;
+  int64_t cells_sketched;
+  int64_t cells_fallback_rank;
+  int64_t cells_fallback_judge;
+  double predict_seconds;   /* host wall time of the rank predictions (features, inference, copy back) */
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);
@@ -165,6 +185,25 @@ int fds_get_ranks(fds_factor f, int32_t* out, int64_t n_out);
 /* Skeleton DOF lists of one cell (global unknown indices, component-major,
  * in pivot order).  rows/cols: host, capacity cap; n_out receives the count. */
 int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, int64_t cap, int64_t* n_out);
+
+/* One record per cell of every compressed level, in the order the levels
+ * were compressed (leaves first): the predictor's training data.
+ * feat: k_T d, k_L d (d = 2 R, R the cell radius used for its proxy circle),
+ * level, active DOFs per component, rows of the proxy-plus-near interaction
+ * matrix, -log10(tol).  rank: (k_row comp 1, k_col comp 1, k_row comp 2,
+ * k_col comp 2) at tolerance.  k_pred: the learned form's prediction (-1 in
+ * the adaptive form).  fallback: 0 none, 1 rank not revealed by the sketch,
+ * 2 judge rejected, 3 not sketched (sketch size outside 1..64 or more than 128
+ * columns).  out: host, capacity cap records; n_out receives the count
+ * (records beyond cap are not written). */
+typedef struct {
+  int32_t cell, level;
+  int32_t rank[4];
+  int32_t k_pred, fallback;
+  double feat[6];
+} fds_rank_record;
+
+int fds_get_rank_log(fds_factor f, fds_rank_record* out, int64_t cap, int64_t* n_out);
 
 void fds_destroy(fds_factor f);
 const char* fds_strerror(int code);
@@ -203,6 +242,62 @@ int fds_special_eval(int64_t n, const double* x, double beta, double* out, fds_c
 int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
                      int32_t* piv, const int64_t* pivoff, const int64_t* kmax, double tol,
                      int32_t stop_at_tol, int32_t* rank, void* stream);
+
+/* Randomized column ID with residual judge (learned form of the IDs of
+ * Sections 7.1, 7.2): for problem p with the m[p] x n[p] column-major matrix
+ * M at a + off[p] (device, ld m[p]; not modified), Y = Omega M with Omega
+ * s[p] x m[p], entry (i, l) = (+-1) + i (+-1) from bits 0 and 1 of
+ * SplitMix64(seed) output number (gid[p] << 44) | (i << 24) | l; pivoted QR
+ * of Y (pivot rule of fds_cpqr_batched) to the first
+ * |R_jj| <= sketch_tol |R_11| (the learned factorisation uses tol / 4),
+ * giving rank[p] and piv (host int32, n[p] entries at pivoff[p], the first
+ * rank[p] being the skeleton); revealed[p] = rank[p] < min(s[p], n[p]) or
+ * s[p] >= n[p]; ratio[p] = max_j |M(:,j) - M(:,J) W(:,j)| / max_j |M(:,j)|
+ * with J, W the ID of rank[p] from the sketch.  1 <= s[p] <= 64,
+ * n[p] <= 128.  Host arrays are int64 [np] unless stated.  Synchronous. */
+int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
+                    const int64_t* s, const int64_t* gid, uint64_t seed, double sketch_tol, int32_t* piv,
+                    const int64_t* pivoff, int32_t* rank, int32_t* revealed, double* ratio, void* stream);
+
+/* Rank predictor: 6-64-64-64-1 perceptron with ReLU.  A predictor is a
+ * float blob of FDS_MLP_BLOB entries: W1 (64 x 6, row-major, row j = hidden
+ * unit j), b1 (64), W2 (64 x 64), b2, W3 (64 x 64), b3, w4 (64), b4 (1) --
+ * the FDS_MLP_PARAMS trainable entries -- then mu (6), sigma (6), y_scale.
+ * The prediction for features x is y_scale * (w4 . h3 + b4) with
+ * h1 = relu(W1 (x - mu) / sigma + b1), h2 = relu(W2 h1 + b2),
+ * h3 = relu(W3 h2 + b3). */
+#define FDS_MLP_PARAMS 8833
+#define FDS_MLP_BLOB 8846
+
+/* A fresh predictor for training data x (device float n x 6 row-major),
+ * y (device float [n]): mu, sigma = mean and population standard deviation
+ * of each feature (sigma 1 where it is 0), y_scale = max(1, max y); weights
+ * He-uniform, entry p (flat index in the blob) = lim (2 u - 1) with
+ * u = (SplitMix64(seed) output p >> 11) 2^-53 and lim = sqrt(6 / fan_in);
+ * biases 0.  blob: host [FDS_MLP_BLOB], written.  Synchronous. */
+int fds_mlp_init(float* blob, int64_t n, const float* x, const float* y, uint64_t seed, void* stream);
+
+/* Predictions for n feature rows.  blob: host; x: device float n x 6
+ * row-major; y: device float [n].  bf16 = 1 rounds weights, inputs and
+ * activations to bfloat16 (FP32 accumulation), as the learned factor does;
+ * 0 computes in FP32.  Synchronous. */
+int fds_mlp_forward(const float* blob, int64_t n, const float* x, float* y, int32_t bf16, void* stream);
+
+/* Mean squared error L = mean_k (net(x_k) - y_k / y_scale)^2 over all n
+ * rows and its gradient with respect to the trainable parameters (FP32,
+ * deterministic).  blob, grad (FDS_MLP_PARAMS), loss: host; x, y: device.
+ * Synchronous. */
+int fds_mlp_loss_grad(const float* blob, int64_t n, const float* x, const float* y, float* grad, float* loss,
+                      void* stream);
+
+/* Train on the GPU: ``steps`` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8,
+ * learning rate lr) on minibatches of ``batch`` rows drawn with replacement
+ * (row SplitMix64(seed) output (step << 32) | slot, mod n, step 1-based);
+ * batch = 0 uses all rows every step.  blob: host, updated in place (only the
+ * trainable entries change); loss_hist: host [steps] or NULL, the minibatch
+ * loss before each step.  Synchronous. */
+int fds_mlp_train(float* blob, int64_t n, const float* x, const float* y, int32_t steps, int64_t batch, float lr,
+                  uint64_t seed, float* loss_hist, void* stream);
 
 #ifdef __cplusplus
 }

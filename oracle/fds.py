@@ -222,10 +222,9 @@ def cell_disk(bnd, c):
     c.radius = float(np.max(np.hypot(sup[:, 0] - c.centre[0], sup[:, 1] - c.centre[1])))
 
 
-def compress_cell(bnd, mat, tol, c, others):
-    """One cell of the upward step (Section 7.3, steps 3a-3b): proxy and
-    near interaction matrices (Sections 7.1, 7.2), four IDs, and
-    X = A_i^{-1} U_i, A~_i = (V_i X)^{-1} (Section 6.2)."""
+def interaction_matrices(bnd, mat, c, others):
+    """Proxy-plus-near interaction matrices of a cell (Sections 7.1, 7.2):
+    MV = A(proxy + near rows, cols) and MU = A(rows, proxy + near cols)."""
     rho = PROXY_RATIO * c.radius
     P = proxy_polygon(c.centre, rho)
     near_r = np.concatenate([o.rows for o in others]) if others else np.zeros(0, np.int64)
@@ -240,6 +239,14 @@ def compress_cell(bnd, mat, tol, c, others):
         MV = np.vstack([MV, entries(bnd, near_r, c.cols, mat)])
     if len(near_c):
         MU = np.hstack([MU, entries(bnd, c.rows, near_c, mat)])
+    return MV, MU
+
+
+def compress_cell(bnd, mat, tol, c, others):
+    """One cell of the upward step (Section 7.3, steps 3a-3b): proxy and
+    near interaction matrices (Sections 7.1, 7.2), four IDs, and
+    X = A_i^{-1} U_i, A~_i = (V_i X)^{-1} (Section 6.2)."""
+    MV, MU = interaction_matrices(bnd, mat, c, others)
     nc = [int(np.sum(c.cols % 2 == q)) for q in (0, 1)]
     nr = [int(np.sum(c.rows % 2 == q)) for q in (0, 1)]
     assert nc == nr

@@ -40,7 +40,9 @@ class _Options(ctypes.Structure):
     _fields_ = [("leaf_nodes", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("root_level", ctypes.c_int32),
                 ("solve_graph", ctypes.c_int32), ("proxy_ratio", ctypes.c_double), ("alpha", _C64),
                 ("use_alpha", ctypes.c_int32), ("precision", ctypes.c_int32), ("ir_max_iter", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double)]
+                ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double),
+                ("rank_mode", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("predictor", ctypes.POINTER(ctypes.c_float))]
 
 
 class _Stats(ctypes.Structure):
@@ -52,15 +54,27 @@ class _Stats(ctypes.Structure):
                 ("kernel_evals", ctypes.c_int64), ("class_seconds", ctypes.c_double * 6),
                 ("class_evals", ctypes.c_int64 * 6), ("class_launches", ctypes.c_int64 * 6),
                 ("precision", ctypes.c_int32), ("ir_iterations", ctypes.c_int32), ("ir_residual", ctypes.c_double),
-                ("ir_correction", ctypes.c_double)]
+                ("ir_correction", ctypes.c_double), ("rank_mode", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("cells_compressed", ctypes.c_int64), ("cells_sketched", ctypes.c_int64),
+                ("cells_fallback_rank", ctypes.c_int64), ("cells_fallback_judge", ctypes.c_int64),
+                ("predict_seconds", ctypes.c_double)]
+
+
+class _RankRecord(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32), ("level", ctypes.c_int32), ("rank", ctypes.c_int32 * 4),
+                ("k_pred", ctypes.c_int32), ("fallback", ctypes.c_int32), ("feat", ctypes.c_double * 6)]
+
 
 PREC_FP64, PREC_MIXED = 0, 1
+RANK_ADAPTIVE, RANK_LEARNED = 0, 1
+MLP_PARAMS, MLP_BLOB = 8833, 8846
 ENOCONV = 6
 
 
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
-           "fds_get_ranks", "fds_get_skeleton", "fds_destroy", "fds_strerror", "fds_last_error",
-           "fds_entries", "fds_special_eval", "fds_cpqr_batched"]
+           "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
+           "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_rid_batched", "fds_mlp_init",
+           "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train"]
 
 
 def lib_path() -> str:
@@ -94,6 +108,14 @@ def load():
     L.fds_entries.argtypes = [ctypes.POINTER(_Geometry), dbl, dbl, dbl, dbl, ctypes.POINTER(_Options), i64,
                               ctypes.POINTER(i64), i64, ctypes.POINTER(i64), vp, i64, vp]
     L.fds_apply.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    pi64, pi32, pf = ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)
+    L.fds_get_rank_log.argtypes = [vp, ctypes.POINTER(_RankRecord), i64, pi64]
+    L.fds_rid_batched.argtypes = [i32, vp, pi64, pi64, pi64, pi64, pi64, ctypes.c_uint64, dbl, pi32, pi64, pi32, pi32,
+                                  ctypes.POINTER(dbl), vp]
+    L.fds_mlp_init.argtypes = [pf, i64, vp, vp, ctypes.c_uint64, vp]
+    L.fds_mlp_forward.argtypes = [pf, i64, vp, vp, i32, vp]
+    L.fds_mlp_loss_grad.argtypes = [pf, i64, vp, vp, pf, pf, vp]
+    L.fds_mlp_train.argtypes = [pf, i64, vp, vp, i32, i64, ctypes.c_float, ctypes.c_uint64, pf, vp]
     L.fds_special_eval.argtypes = [i64, vp, dbl, vp, vp, vp]
     L.fds_cpqr_batched.argtypes = [i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, i32, vp, vp]
@@ -117,7 +139,7 @@ def _geometry(curves):
 
 
 def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False, mixed=False,
-             ir_max_iter=None, ir_rtol=None, ir_dtol=None):
+             ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
@@ -129,11 +151,27 @@ def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, sol
         o.ir_rtol = float(ir_rtol)
     if ir_dtol is not None:
         o.ir_dtol = float(ir_dtol)
+    if predictor is not None:
+        blob = _blob(predictor)
+        o.rank_mode = RANK_LEARNED
+        o.predictor = blob.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        o._keep_blob = blob
+    if oversample is not None:
+        o.oversample = int(oversample)
+    if seed is not None:
+        o.seed = int(seed)
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
         o.use_alpha = 1
     return o
+
+
+def _blob(b):
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    if b.shape != (MLP_BLOB,):
+        raise FdsError(f"a predictor is {MLP_BLOB} float32 values")
+    return b
 
 
 def _stream(stream):
@@ -168,11 +206,11 @@ class Factor:
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
                  alpha=None, stream=None, solve_graph=False, mixed=False, ir_max_iter=None, ir_rtol=None,
-                 ir_dtol=None):
+                 ir_dtol=None, predictor=None, oversample=None, seed=None):
         L = load()
         g, self._keep = _geometry(curves)
         o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph, mixed, ir_max_iter, ir_rtol,
-                     ir_dtol)
+                     ir_dtol, predictor, oversample, seed)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))
@@ -241,6 +279,22 @@ class Factor:
             v = getattr(s, f)
             out[f] = list(v) if hasattr(v, "__len__") else v
         return out
+
+    def rank_log(self):
+        """Per compressed cell: dict of arrays cell, level, rank (n x 4),
+        k_pred, fallback, feat (n x 6)."""
+        L = load()
+        n = ctypes.c_int64()
+        _check(L.fds_get_rank_log(self._h, None, 0, ctypes.byref(n)))
+        recs = (_RankRecord * max(1, n.value))()
+        _check(L.fds_get_rank_log(self._h, recs, n.value, ctypes.byref(n)))
+        recs = recs[:n.value]
+        return {"cell": np.array([r.cell for r in recs], np.int32),
+                "level": np.array([r.level for r in recs], np.int32),
+                "rank": np.array([list(r.rank) for r in recs], np.int32).reshape(-1, 4),
+                "k_pred": np.array([r.k_pred for r in recs], np.int32),
+                "fallback": np.array([r.fallback for r in recs], np.int32),
+                "feat": np.array([list(r.feat) for r in recs], np.float64).reshape(-1, 6)}
 
     def ranks(self):
         st = self.stats()
@@ -324,3 +378,91 @@ def cpqr_batched(mats, tol, kmax=None, stop_at_tol=True, stream=None):
         k = int(rk[i])
         res.append((pv[pvo[i]:pvo[i] + m.shape[1]].copy(), k, np.triu(A[:k, :])))
     return res
+
+
+def rid_batched(mats, sizes, tol, seed, gids=None, stream=None):
+    """Randomized IDs with residual judge on the GPU; returns per matrix
+    (piv, rank, revealed, ratio)."""
+    import torch
+    L = load()
+    ms = [np.asarray(m, dtype=np.complex128) for m in mats]
+    offs, mm, nn, pvo = [], [], [], []
+    o = p = 0
+    for m in ms:
+        offs.append(o)
+        mm.append(m.shape[0])
+        nn.append(m.shape[1])
+        pvo.append(p)
+        o += m.size
+        p += m.shape[1]
+    buf = torch.from_numpy(np.concatenate([np.asfortranarray(m).ravel(order="F") for m in ms])).to("cuda")
+    a64 = lambda v: np.ascontiguousarray(v, dtype=np.int64)
+    offs, mm, nn, pvo, ss = a64(offs), a64(mm), a64(nn), a64(pvo), a64(sizes)
+    gids = a64(np.arange(len(ms)) if gids is None else gids)
+    piv = np.zeros(p, np.int32)
+    rank = np.zeros(len(ms), np.int32)
+    rev = np.zeros(len(ms), np.int32)
+    ratio = np.zeros(len(ms), np.float64)
+    P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    _check(L.fds_rid_batched(len(ms), ctypes.c_void_p(buf.data_ptr()), P(offs, ctypes.c_int64),
+                             P(mm, ctypes.c_int64), P(nn, ctypes.c_int64), P(ss, ctypes.c_int64),
+                             P(gids, ctypes.c_int64), int(seed), float(tol), P(piv, ctypes.c_int32),
+                             P(pvo, ctypes.c_int64), P(rank, ctypes.c_int32), P(rev, ctypes.c_int32),
+                             P(ratio, ctypes.c_double), _stream(stream)))
+    return [(piv[pvo[i]:pvo[i] + nn[i]].copy(), int(rank[i]), bool(rev[i]), float(ratio[i])) for i in range(len(ms))]
+
+
+def _f32_cuda(a, shape):
+    import torch
+    t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a, dtype=np.float32))
+    t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    if tuple(t.shape) != tuple(shape):
+        raise FdsError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def mlp_init(x, y, seed, stream=None):
+    """A fresh predictor blob (float32 [MLP_BLOB]) for features x (n x 6) and targets y (n)."""
+    n = len(y)
+    xt, yt = _f32_cuda(x, (n, 6)), _f32_cuda(y, (n,))
+    blob = np.zeros(MLP_BLOB, np.float32)
+    _check(load().fds_mlp_init(blob.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, ctypes.c_void_p(xt.data_ptr()),
+                               ctypes.c_void_p(yt.data_ptr()), int(seed), _stream(stream)))
+    return blob
+
+
+def mlp_forward(blob, x, bf16=False, stream=None):
+    """Predictions (float32 CUDA tensor [n]) of a predictor blob for features x (n x 6)."""
+    import torch
+    b = _blob(blob)
+    n = len(x)
+    xt = _f32_cuda(x, (n, 6))
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(load().fds_mlp_forward(b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, ctypes.c_void_p(xt.data_ptr()),
+                                  ctypes.c_void_p(y.data_ptr()), int(bool(bf16)), _stream(stream)))
+    return y
+
+
+def mlp_loss_grad(blob, x, y, stream=None):
+    """(loss, gradient [MLP_PARAMS]) of the mean squared error over all rows."""
+    b = _blob(blob)
+    n = len(y)
+    xt, yt = _f32_cuda(x, (n, 6)), _f32_cuda(y, (n,))
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    _check(load().fds_mlp_loss_grad(P(b), n, ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(yt.data_ptr()), P(g),
+                                    P(loss), _stream(stream)))
+    return float(loss[0]), g
+
+
+def mlp_train(blob, x, y, steps, batch, lr, seed, stream=None):
+    """Adam training on the GPU; returns (trained blob, loss history)."""
+    b = _blob(blob).copy()
+    n = len(y)
+    xt, yt = _f32_cuda(x, (n, 6)), _f32_cuda(y, (n,))
+    hist = np.zeros(max(1, steps), np.float32)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    _check(load().fds_mlp_train(P(b), n, ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(yt.data_ptr()), int(steps),
+                                int(batch), float(lr), int(seed), P(hist), _stream(stream)))
+    return b, hist[:steps]

@@ -38,6 +38,7 @@
 #include "../../include/fds.h"
 #include "assembly.hpp"
 #include "devmem.hpp"
+#include "learned.hpp"
 #include "linalg.hpp"
 #include "parallel.hpp"
 
@@ -262,7 +263,9 @@ struct fds_factor_s {
   hipStream_t stream = nullptr;
   fds::Workspace ws;
   fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
-  std::map<int, hipGraphExec_t> graphs;     // captured solve sweeps per nrhs
+  fds::DevBuf<float> pred;                  // learned form: predictor blob
+  std::vector<fds_rank_record> rank_log;    // per compressed cell: features, ranks, prediction
+  std::map<int64_t, hipGraphExec_t> graphs; // captured solve sweeps per (nrhs, kind)
   hipStream_t gstream = nullptr;            // library stream for graph capture and replay
   ~fds_factor_s() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -561,6 +564,276 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
   infos.emplace_back(info2, lds.size());
 }
 
+// Pair the ranks of each component (k_c = max(k_row, k_col)) and extend
+// the shorter pivoted QR to k_c steps (Section 7.3 reading: nested pivots).
+// dv / du: the V / U problems of ``cells`` (2 per cell, comp 0 then 1),
+// already factored to tolerance with ranks rv / ru; their matrices live
+// in baseV / baseU.  Fills the cells' ranks in lv.
+static void pair_and_extend(Factor& F, CellLevel& lv, const std::vector<int>& cells, const std::vector<CpqrDesc>& dv,
+                            const std::vector<CpqrDesc>& du, std::vector<int>& rv, std::vector<int>& ru, c64* baseV,
+                            c64* baseU, int* dpiv, double tol) {
+  Workspace& ws = F.ws;
+  std::vector<CpqrDesc> ev, eu;
+  std::vector<int> ev_i, eu_i;
+  for (size_t ci = 0; ci < cells.size(); ++ci) {
+    const int q = cells[ci];
+    lv.kc0[q] = rv[2 * ci];
+    lv.kc1[q] = rv[2 * ci + 1];
+    lv.kr0[q] = ru[2 * ci];
+    lv.kr1[q] = ru[2 * ci + 1];
+    const int kk[2] = {std::max(lv.kc0[q], lv.kr0[q]), std::max(lv.kc1[q], lv.kr1[q])};
+    for (int comp = 0; comp < 2; ++comp) {
+      const size_t i = 2 * ci + comp;
+      if (rv[i] < kk[comp]) {
+        CpqrDesc d = dv[i];
+        d.k_start = rv[i];
+        d.k_end = kk[comp];
+        d.stop_at_tol = 0;
+        ev.push_back(d);
+        ev_i.push_back((int)i);
+      }
+      if (ru[i] < kk[comp]) {
+        CpqrDesc d = du[i];
+        d.k_start = ru[i];
+        d.k_end = kk[comp];
+        d.stop_at_tol = 0;
+        eu.push_back(d);
+        eu_i.push_back((int)i);
+      }
+    }
+    lv.k0[q] = kk[0];
+    lv.k1[q] = kk[1];
+  }
+  if (!ev.empty() || !eu.empty()) {
+    int* drank2 = ws.get<int>("id_rank2", ev.size() + eu.size());
+    launch_cpqr(ws.upload("cpqr_v2", ev), (int)ev.size(), baseV, dpiv, tol, drank2, F.stream);
+    launch_cpqr(ws.upload("cpqr_u2", eu), (int)eu.size(), baseU, dpiv, tol, drank2 + ev.size(), F.stream);
+    auto h = download(ws, drank2, ev.size() + eu.size());
+    for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
+    for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[ev.size() + i];
+  }
+  for (size_t ci = 0; ci < cells.size(); ++ci) {
+    const int q = cells[ci];
+    // a zero pivot can end a QR early: never use more pivots than both reached
+    lv.k0[q] = std::min(lv.k0[q], std::min(rv[2 * ci], ru[2 * ci]));
+    lv.k1[q] = std::min(lv.k1[q], std::min(rv[2 * ci + 1], ru[2 * ci + 1]));
+  }
+}
+
+// IDs of ``cells`` by the pivoted QR of their interaction matrices
+// (Sections 7.1, 7.2).
+static void adaptive_ids(Factor& F, CellLevel& lv, const std::vector<int>& cells, const std::vector<CpqrDesc>& qv,
+                         const std::vector<CpqrDesc>& qu, c64* MV, c64* MU, int* dpiv) {
+  if (cells.empty()) return;
+  Workspace& ws = F.ws;
+  const size_t nc = cells.size();
+  std::vector<CpqrDesc> dv(2 * nc), du(2 * nc);
+  for (size_t ci = 0; ci < nc; ++ci)
+    for (int comp = 0; comp < 2; ++comp) {
+      dv[2 * ci + comp] = qv[2 * cells[ci] + comp];
+      du[2 * ci + comp] = qu[2 * cells[ci] + comp];
+    }
+  int* drank = ws.get<int>("id_rank", 4 * nc);
+  launch_cpqr(ws.upload("cpqr_v", dv), (int)(2 * nc), MV, dpiv, F.tol, drank, F.stream);
+  launch_cpqr(ws.upload("cpqr_u", du), (int)(2 * nc), MU, dpiv, F.tol, drank + 2 * nc, F.stream);
+  auto rk = download(ws, drank, 4 * nc);
+  std::vector<int> rv(rk.begin(), rk.begin() + 2 * nc), ru(rk.begin() + 2 * nc, rk.end());
+  pair_and_extend(F, lv, cells, dv, du, rv, ru, MV, MU, dpiv, F.tol);
+}
+
+// Predictor inputs of the cells of a level: k_T d, k_L d (d = 2 R), level,
+// active DOFs per component, rows of the proxy-plus-near matrix, -log10 tol.
+static std::vector<float> cell_features(const Factor& F, int lev, const std::vector<double>& crd,
+                                        const std::vector<int>& mv_m) {
+  const CellLevel& lv = F.levels[lev];
+  std::vector<float> x((size_t)lv.n * kMlpIn);
+  for (int q = 0; q < lv.n; ++q) {
+    const double d = 2.0 * crd[3 * q + 2] / F.opt.proxy_ratio;
+    float* f = x.data() + (size_t)q * kMlpIn;
+    f[0] = (float)(F.m.kT * d);
+    f[1] = (float)(F.m.kL * d);
+    f[2] = (float)lev;
+    f[3] = (float)(0.5 * lv.b[q]);
+    f[4] = (float)mv_m[q];
+    f[5] = (float)(-std::log10(F.tol));
+  }
+  return x;
+}
+
+// Learned form: per cell, the predictor's rank pre-sizes a sketch of
+// s = ceil(k_pred) + oversample rows; the IDs of the sketch are accepted
+// when the sketch reveals their rank and the residual judge passes on the
+// interaction matrices themselves.  Returns the cells left to the pivoted QR
+// of their matrices (too large to sketch, rank not revealed, judge failed);
+// srcv / srcu point the accepted cells' interpolation at the sketches.
+static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double>& crd, const std::vector<int>& mv_m,
+                                    const std::vector<CpqrDesc>& qv, const std::vector<CpqrDesc>& qu, c64* MV,
+                                    c64* MU, int* dpiv, std::vector<CpqrDesc>& srcv, std::vector<CpqrDesc>& srcu,
+                                    std::vector<int>& kpred, std::vector<int>& fallback) {
+  CellLevel& lv = F.levels[lev];
+  Workspace& ws = F.ws;
+  hipStream_t s = F.stream;
+  const int n = lv.n;
+  auto th = std::chrono::steady_clock::now();
+  const std::vector<float> feat = cell_features(F, lev, crd, mv_m);
+  float* dpred = ws.get<float>("pred", (size_t)n);
+  launch_mlp_forward(n, ws.upload("feat", feat), F.pred.p, dpred, 1, s);
+  const std::vector<float> pred = download(ws, dpred, (size_t)n);
+  F.st.predict_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - th).count();
+  std::vector<int> plain, sk;
+  std::vector<int> sz(n, 0);
+  for (int q = 0; q < n; ++q) {
+    const float p = pred[q];
+    kpred[q] = std::isfinite(p) ? std::max(0, (int)std::ceil(p)) : kSketchMaxS;
+    const int ss = kpred[q] + F.opt.oversample;
+    bool ok = ss >= 1 && ss <= kSketchMaxS;
+    for (int c = 0; c < 2; ++c) ok = ok && qv[2 * q + c].n <= kSketchMaxN && qu[2 * q + c].n <= kSketchMaxN;
+    if (ok) {
+      sz[q] = ss;
+      sk.push_back(q);
+    } else {
+      fallback[q] = 3;
+      plain.push_back(q);
+    }
+  }
+  if (sk.empty()) return plain;
+  // sketches Y = Omega M of the 4 problems of every sketched cell
+  const size_t ns = sk.size();
+  std::vector<SketchDesc> sv(2 * ns), su(2 * ns);
+  std::vector<CpqrDesc> yd(4 * ns);   // V problems, then U problems
+  int64_t ytot = 0;
+  for (size_t ci = 0; ci < ns; ++ci) {
+    const int q = sk[ci];
+    const int64_t cell = ((int64_t)1 << lev) - 1 + q;
+    for (int k = 0; k < 4; ++k) {
+      const bool isV = k < 2;
+      const int comp = k & 1;
+      const CpqrDesc& m = isV ? qv[2 * q + comp] : qu[2 * q + comp];
+      SketchDesc d{};
+      d.m_off = m.a_off;
+      d.y_off = ytot;
+      d.gid = 4 * cell + k;
+      d.m = m.m;
+      d.n = m.n;
+      d.lda = m.lda;
+      d.s = sz[q];
+      (isV ? sv : su)[2 * ci + comp] = d;
+      CpqrDesc y{};
+      y.a_off = ytot;
+      y.piv_off = m.piv_off;
+      y.m = sz[q];
+      y.n = m.n;
+      y.lda = sz[q];
+      y.k_start = 0;
+      y.k_end = std::min(y.m, y.n);
+      y.stop_at_tol = 1;
+      yd[(isV ? 0 : 2 * ns) + 2 * ci + comp] = y;
+      ytot += (int64_t)sz[q] * m.n;
+    }
+  }
+  c64* Y = ws.get<c64>("sketch_Y", (size_t)std::max<int64_t>(ytot, 1));
+  launch_sketch(ws.upload("sk_v", sv), (int)sv.size(), MV, Y, F.opt.seed, s);
+  launch_sketch(ws.upload("sk_u", su), (int)su.size(), MU, Y, F.opt.seed, s);
+  int* drank = ws.get<int>("sk_rank", 4 * ns);
+  launch_cpqr(ws.upload("sk_cpqr", yd), (int)yd.size(), Y, dpiv, kSketchTolFactor * F.tol, drank, s);
+  const auto rk = download(ws, drank, 4 * ns);
+  // the sketch must reveal every rank: a crossing inside it, or s >= n
+  std::vector<int> acc;
+  std::vector<CpqrDesc> av, au;
+  std::vector<int> rv, ru;
+  for (size_t ci = 0; ci < ns; ++ci) {
+    bool revealed = true;
+    for (int k = 0; k < 4; ++k) {
+      const CpqrDesc& y = yd[(k < 2 ? 0 : 2 * ns) + 2 * ci + (k & 1)];
+      const int r = rk[(k < 2 ? 0 : 2 * ns) + 2 * ci + (k & 1)];
+      revealed = revealed && (r < std::min(y.m, y.n) || y.m >= y.n);
+    }
+    const int q = sk[ci];
+    if (!revealed) {
+      fallback[q] = 1;
+      continue;
+    }
+    acc.push_back(q);
+    for (int comp = 0; comp < 2; ++comp) {
+      av.push_back(yd[2 * ci + comp]);
+      au.push_back(yd[2 * ns + 2 * ci + comp]);
+      rv.push_back(rk[2 * ci + comp]);
+      ru.push_back(rk[2 * ns + 2 * ci + comp]);
+    }
+  }
+  if (!acc.empty()) {
+    pair_and_extend(F, lv, acc, av, au, rv, ru, Y, Y, dpiv, kSketchTolFactor * F.tol);
+    // residual judge on the interaction matrices themselves
+    std::vector<InterpDesc> iw;
+    std::vector<JudgeDesc> jv, ju;
+    int64_t wtot = 0;
+    for (size_t ai = 0; ai < acc.size(); ++ai) {
+      const int q = acc[ai];
+      for (int k = 0; k < 4; ++k) {
+        const bool isV = k < 2;
+        const int comp = k & 1;
+        const int kk = comp ? lv.k1[q] : lv.k0[q];
+        const CpqrDesc& y = isV ? av[2 * ai + comp] : au[2 * ai + comp];
+        const CpqrDesc& m = isV ? qv[2 * q + comp] : qu[2 * q + comp];
+        if (kk > 0) iw.push_back(InterpDesc{y.a_off, y.piv_off, y.n, y.lda, kk, wtot, kk, 0});
+        (isV ? jv : ju).push_back(JudgeDesc{m.a_off, wtot, m.piv_off, m.m, m.n, m.lda, kk});
+        wtot += (int64_t)kk * y.n;
+      }
+    }
+    c64* Wj = ws.get<c64>("judge_W", (size_t)std::max<int64_t>(wtot, 1));
+    double* ratio = ws.get<double>("judge_ratio", jv.size() + ju.size());
+    launch_interp(ws.upload("judge_interp", iw), (int)iw.size(), Y, dpiv, Wj, s);
+    launch_judge(ws.upload("judge_v", jv), (int)jv.size(), MV, Wj, dpiv, ratio, s);
+    launch_judge(ws.upload("judge_u", ju), (int)ju.size(), MU, Wj, dpiv, ratio + jv.size(), s);
+    const auto rt = download(ws, ratio, jv.size() + ju.size());
+    for (size_t ai = 0; ai < acc.size(); ++ai) {
+      const int q = acc[ai];
+      bool pass = true;
+      for (int comp = 0; comp < 2; ++comp)
+        pass = pass && rt[2 * ai + comp] <= F.tol && rt[jv.size() + 2 * ai + comp] <= F.tol;
+      if (!pass) {
+        fallback[q] = 2;
+        continue;
+      }
+      for (int comp = 0; comp < 2; ++comp) {
+        srcv[2 * q + comp] = av[2 * ai + comp];
+        srcu[2 * q + comp] = au[2 * ai + comp];
+      }
+    }
+  }
+  for (int q : sk)
+    if (fallback[q] != 0) plain.push_back(q);
+  std::sort(plain.begin(), plain.end());
+  for (int q : sk) {
+    F.st.cells_sketched += fallback[q] == 0;
+    F.st.cells_fallback_rank += fallback[q] == 1;
+    F.st.cells_fallback_judge += fallback[q] == 2;
+  }
+  return plain;
+}
+
+// Rank log entry of every cell of a compressed level (the predictor's
+// training data).
+static void record_ranks(Factor& F, int lev, const std::vector<double>& crd, const std::vector<int>& mv_m,
+                         const std::vector<int>& kpred, const std::vector<int>& fallback) {
+  const CellLevel& lv = F.levels[lev];
+  const std::vector<float> feat = cell_features(F, lev, crd, mv_m);
+  for (int q = 0; q < lv.n; ++q) {
+    fds_rank_record r{};
+    r.cell = (int32_t)(((int64_t)1 << lev) - 1 + q);
+    r.level = lev;
+    r.rank[0] = lv.kr0[q];
+    r.rank[1] = lv.kc0[q];
+    r.rank[2] = lv.kr1[q];
+    r.rank[3] = lv.kc1[q];
+    r.k_pred = kpred[q];
+    r.fallback = fallback[q];
+    for (int c = 0; c < kMlpIn; ++c) r.feat[c] = feat[(size_t)q * kMlpIn + c];
+    F.rank_log.push_back(r);
+  }
+  F.st.cells_compressed += lv.n;
+}
+
 static void compress_level(Factor& F, int lev) {
   const Geometry& G = F.G;
   CellLevel& lv = F.levels[lev];
@@ -659,8 +932,7 @@ static void compress_level(Factor& F, int lev) {
   ht1.reset();
   // IDs: per cell V comp0, V comp1 (in MV) and U comp0, U comp1 (in MU^T)
   span_begin(F, 0);
-  std::vector<CpqrDesc> qv, qu;
-  std::vector<int64_t> pvo(4 * n);
+  std::vector<CpqrDesc> qv(2 * n), qu(2 * n);
   int64_t pv_tot = 0;
   for (int q = 0; q < n; ++q) {
     const int b = lv.b[q], c0 = lv.n0[q], c1 = b - c0;
@@ -675,72 +947,36 @@ static void compress_level(Factor& F, int lev) {
       d.n = ncs[comp];
       d.lda = mrows;
       d.piv_off = pv_tot;
-      pvo[4 * q + k] = pv_tot;
       pv_tot += d.n;
       d.k_start = 0;
       d.k_end = std::min(d.m, d.n);
       d.stop_at_tol = 1;
-      (isV ? qv : qu).push_back(d);
+      (isV ? qv : qu)[2 * q + comp] = d;
     }
   }
   check_cpqr_sizes(qv);
   check_cpqr_sizes(qu);
   int* dpiv = ws.get<int>("id_piv", (size_t)pv_tot);
-  int* drank = ws.get<int>("id_rank", (size_t)4 * n);
-  launch_cpqr(ws.upload("cpqr_v", qv), 2 * n, MV, dpiv, F.tol, drank, s);
-  launch_cpqr(ws.upload("cpqr_u", qu), 2 * n, MU, dpiv, F.tol, drank + 2 * n, s);
-  auto rk = download(ws, drank, (size_t)4 * n);
-  std::vector<int> rv(rk.begin(), rk.begin() + 2 * n), ru(rk.begin() + 2 * n, rk.end());
-  lv.kc0.resize(n);
-  lv.kc1.resize(n);
-  lv.kr0.resize(n);
-  lv.kr1.resize(n);
-  lv.k0.resize(n);
-  lv.k1.resize(n);
-  lv.r.resize(n);
-  std::vector<CpqrDesc> ev, eu;
-  std::vector<int> ev_i, eu_i;
-  for (int q = 0; q < n; ++q) {
-    lv.kc0[q] = rv[2 * q];
-    lv.kc1[q] = rv[2 * q + 1];
-    lv.kr0[q] = ru[2 * q];
-    lv.kr1[q] = ru[2 * q + 1];
-    const int kk[2] = {std::max(lv.kc0[q], lv.kr0[q]), std::max(lv.kc1[q], lv.kr1[q])};
-    for (int comp = 0; comp < 2; ++comp) {
-      CpqrDesc dv = qv[2 * q + comp];
-      if (rv[2 * q + comp] < kk[comp]) {
-        dv.k_start = rv[2 * q + comp];
-        dv.k_end = kk[comp];
-        dv.stop_at_tol = 0;
-        ev.push_back(dv);
-        ev_i.push_back(2 * q + comp);
-      }
-      CpqrDesc du = qu[2 * q + comp];
-      if (ru[2 * q + comp] < kk[comp]) {
-        du.k_start = ru[2 * q + comp];
-        du.k_end = kk[comp];
-        du.stop_at_tol = 0;
-        eu.push_back(du);
-        eu_i.push_back(2 * q + comp);
-      }
-    }
-    lv.k0[q] = kk[0];
-    lv.k1[q] = kk[1];
+  lv.kc0.assign(n, 0);
+  lv.kc1.assign(n, 0);
+  lv.kr0.assign(n, 0);
+  lv.kr1.assign(n, 0);
+  lv.k0.assign(n, 0);
+  lv.k1.assign(n, 0);
+  lv.r.assign(n, 0);
+  // where each ID's triangular factor lives (M itself, or its sketch)
+  std::vector<CpqrDesc> srcv = qv, srcu = qu;
+  std::vector<int> kpred(n, -1), fallback(n, 0);
+  std::vector<int> plain;
+  if (F.opt.rank_mode == FDS_RANK_LEARNED) {
+    plain = learned_ids(F, lev, crd, mv_m, qv, qu, MV, MU, dpiv, srcv, srcu, kpred, fallback);
+  } else {
+    plain.resize(n);
+    std::iota(plain.begin(), plain.end(), 0);
   }
-  if (!ev.empty() || !eu.empty()) {
-    int* drank2 = ws.get<int>("id_rank2", ev.size() + eu.size());
-    launch_cpqr(ws.upload("cpqr_v2", ev), (int)ev.size(), MV, dpiv, F.tol, drank2, s);
-    launch_cpqr(ws.upload("cpqr_u2", eu), (int)eu.size(), MU, dpiv, F.tol, drank2 + ev.size(), s);
-    auto h = download(ws, drank2, ev.size() + eu.size());
-    for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
-    for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[ev.size() + i];
-  }
-  for (int q = 0; q < n; ++q) {
-    // a zero pivot can end a QR early: never use more pivots than both reached
-    lv.k0[q] = std::min(lv.k0[q], std::min(rv[2 * q], ru[2 * q]));
-    lv.k1[q] = std::min(lv.k1[q], std::min(rv[2 * q + 1], ru[2 * q + 1]));
-    lv.r[q] = lv.k0[q] + lv.k1[q];
-  }
+  adaptive_ids(F, lv, plain, qv, qu, MV, MU, dpiv);
+  for (int q = 0; q < n; ++q) lv.r[q] = lv.k0[q] + lv.k1[q];
+  record_ranks(F, lev, crd, mv_m, kpred, fallback);
   auto hpiv = download(ws, dpiv, (size_t)pv_tot);
   // skeletons, layouts
   lv.rskel.assign(n, {});
@@ -757,8 +993,8 @@ static void compress_level(Factor& F, int lev) {
     const int kk[2] = {lv.k0[q], lv.k1[q]};
     for (int comp = 0; comp < 2; ++comp) {
       const int base = comp ? c0 : 0;
-      const int* pc = hpiv.data() + pvo[4 * q + comp];
-      const int* pr = hpiv.data() + pvo[4 * q + 2 + comp];
+      const int* pc = hpiv.data() + qv[2 * q + comp].piv_off;
+      const int* pr = hpiv.data() + qu[2 * q + comp].piv_off;
       for (int j = 0; j < kk[comp]; ++j) {
         lv.cskel[q].push_back(lv.cols[q][base + pc[j]]);
         lv.rskel[q].push_back(lv.rows[q][base + pr[j]]);
@@ -784,22 +1020,32 @@ static void compress_level(Factor& F, int lev) {
   FDS_HIP(hipMemsetAsync(lv.X.p, 0, lv.X.n * sizeof(c64), s));
   FDS_HIP(hipMemsetAsync(lv.V.p, 0, lv.V.n * sizeof(c64), s));
   // V_i (r x b) from the column IDs; U_i = X_i (b x r) from the row IDs (W^T)
-  std::vector<InterpDesc> iv, iu;
+  std::vector<InterpDesc> ivm, ium, ivy, iuy;
   for (int q = 0; q < n; ++q) {
     const int b = lv.b[q], r = lv.r[q], c0 = lv.n0[q];
     const int kk[2] = {lv.k0[q], lv.k1[q]};
+    const bool sk = F.opt.rank_mode == FDS_RANK_LEARNED && fallback[q] == 0;
     for (int comp = 0; comp < 2; ++comp) {
       if (kk[comp] == 0) continue;
       const int roff = comp ? kk[0] : 0;   // skeleton offset
       const int coff = comp ? c0 : 0;      // DOF offset
-      const CpqrDesc& dv = qv[2 * q + comp];
-      iv.push_back(InterpDesc{dv.a_off, dv.piv_off, dv.n, dv.lda, kk[comp], lv.v_off[q] + roff + (int64_t)coff * r, r, 0});
-      const CpqrDesc& du = qu[2 * q + comp];
-      iu.push_back(InterpDesc{du.a_off, du.piv_off, du.n, du.lda, kk[comp], lv.x_off[q] + coff + (int64_t)roff * b, b, 1});
+      // the sketches' triangular systems were solved in place for the judge
+      const int solved = sk ? 1 : 0;
+      const CpqrDesc& dv = srcv[2 * q + comp];
+      (sk ? ivy : ivm).push_back(InterpDesc{dv.a_off, dv.piv_off, dv.n, dv.lda, kk[comp],
+                                            lv.v_off[q] + roff + (int64_t)coff * r, r, 0, solved});
+      const CpqrDesc& du = srcu[2 * q + comp];
+      (sk ? iuy : ium).push_back(InterpDesc{du.a_off, du.piv_off, du.n, du.lda, kk[comp],
+                                            lv.x_off[q] + coff + (int64_t)roff * b, b, 1, solved});
     }
   }
-  launch_interp(ws.upload("interp_v", iv), (int)iv.size(), MV, dpiv, lv.V.p, s);
-  launch_interp(ws.upload("interp_u", iu), (int)iu.size(), MU, dpiv, lv.X.p, s);
+  launch_interp(ws.upload("interp_v", ivm), (int)ivm.size(), MV, dpiv, lv.V.p, s);
+  launch_interp(ws.upload("interp_u", ium), (int)ium.size(), MU, dpiv, lv.X.p, s);
+  if (!ivy.empty() || !iuy.empty()) {
+    c64* Y = ws.get<c64>("sketch_Y", 1);
+    launch_interp(ws.upload("interp_vy", ivy), (int)ivy.size(), Y, dpiv, lv.V.p, s);
+    launch_interp(ws.upload("interp_uy", iuy), (int)iuy.size(), Y, dpiv, lv.X.p, s);
+  }
   span_end(F);
 
   // elimination: LU(A_i); X_i = A_i^{-1} U_i; S_i = V_i X_i; A~_i = S_i^{-1}
@@ -1347,6 +1593,10 @@ int fds_options_default(fds_options* o) {
   o->ir_max_iter = 10;
   o->ir_rtol = 1e-8;
   o->ir_dtol = 1e-6;
+  o->rank_mode = FDS_RANK_ADAPTIVE;
+  o->oversample = 8;
+  o->seed = 0x5EED;
+  o->predictor = nullptr;
   return FDS_OK;
 }
 
@@ -1367,6 +1617,9 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
   if (o.precision != FDS_PREC_FP64 && o.precision != FDS_PREC_MIXED) return FDS_EINVAL;
   if (o.precision == FDS_PREC_MIXED && (o.ir_max_iter < 0 || !(o.ir_rtol > 0) || !(o.ir_dtol > 0)))
     return FDS_EINVAL;
+  if (o.rank_mode != FDS_RANK_ADAPTIVE && o.rank_mode != FDS_RANK_LEARNED) return FDS_EINVAL;
+  if (o.rank_mode == FDS_RANK_LEARNED && (!o.predictor || o.oversample < 0 || o.oversample > kSketchMaxS))
+    return FDS_EINVAL;
   auto* F = new Factor();
   try {
     if (int e = make_geometry(geom, F->G)) {
@@ -1384,6 +1637,11 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->stream = (hipStream_t)stream;
     F->ws.set_stream(F->stream);
     F->m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
+    if (o.rank_mode == FDS_RANK_LEARNED) {
+      F->pred = DevBuf<float>(std::vector<float>(o.predictor, o.predictor + kMlpBlob));
+      F->opt.predictor = nullptr;   // the caller's array is not kept
+    }
+    F->st.rank_mode = o.rank_mode;
     build_tree(*F);
     const int64_t proxy_cap = (int64_t)F->levels[F->L].n * o.n_proxy;
     F->DG.init(F->G, proxy_cap, F->stream);
@@ -1618,6 +1876,186 @@ int fds_special_eval(int64_t n, const double* x, double beta, double* out, fds_c
   try {
     launch_special_eval(x, n, beta, out, (c64*)outc, (hipStream_t)stream);
     FDS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_get_rank_log(fds_factor f, fds_rank_record* out, int64_t cap, int64_t* n_out) {
+  if (!f || !n_out || cap < 0 || (cap > 0 && !out)) return FDS_EINVAL;
+  const int64_t n = (int64_t)f->rank_log.size();
+  for (int64_t i = 0; i < std::min(n, cap); ++i) out[i] = f->rank_log[i];
+  *n_out = n;
+  return FDS_OK;
+}
+
+int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
+                    const int64_t* sz, const int64_t* gid, uint64_t seed, double tol, int32_t* piv,
+                    const int64_t* pivoff, int32_t* rank, int32_t* revealed, double* ratio, void* stream) {
+  // ``tol`` is the sketch's stopping tolerance (sketch_tol in the header)
+  if (np < 1 || !a || !off || !m || !n || !sz || !gid || !piv || !pivoff || !rank || !revealed || !ratio ||
+      !(tol > 0.0 && tol < 1.0))
+    return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<SketchDesc> sd(np);
+    std::vector<CpqrDesc> yd(np);
+    int64_t ytot = 0, ptot = 0;
+    for (int i = 0; i < np; ++i) {
+      if (m[i] < 1 || n[i] < 1 || n[i] > kSketchMaxN || sz[i] < 1 || sz[i] > kSketchMaxS || m[i] > 2048)
+        return FDS_EINVAL;
+      sd[i] = SketchDesc{off[i], ytot, gid[i], (int)m[i], (int)n[i], (int)m[i], (int)sz[i]};
+      yd[i] = CpqrDesc{ytot, pivoff[i], (int)sz[i], (int)n[i], (int)sz[i], 0, (int)std::min(sz[i], n[i]), 1};
+      ytot += sz[i] * n[i];
+      ptot = std::max(ptot, pivoff[i] + n[i]);
+    }
+    DevBuf<SketchDesc> dsd(sd);
+    DevBuf<CpqrDesc> dyd(yd);
+    DevBuf<c64> Y((size_t)ytot);
+    DevBuf<int> dpiv((size_t)ptot), drank((size_t)np);
+    launch_sketch(dsd.p, np, (const c64*)a, Y.p, seed, s);
+    launch_cpqr(dyd.p, np, Y.p, dpiv.p, tol, drank.p, s);
+    std::vector<int> hr(np);
+    FDS_HIP(hipMemcpyAsync(hr.data(), drank.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    std::vector<InterpDesc> iw;
+    std::vector<JudgeDesc> jd(np);
+    int64_t wtot = 0;
+    for (int i = 0; i < np; ++i) {
+      const int k = hr[i];
+      if (k > 0) iw.push_back(InterpDesc{yd[i].a_off, pivoff[i], (int)n[i], (int)sz[i], k, wtot, k, 0});
+      jd[i] = JudgeDesc{off[i], wtot, pivoff[i], (int)m[i], (int)n[i], (int)m[i], k};
+      wtot += (int64_t)k * n[i];
+    }
+    DevBuf<InterpDesc> diw(iw);
+    DevBuf<JudgeDesc> djd(jd);
+    DevBuf<c64> W((size_t)std::max<int64_t>(wtot, 1));
+    DevBuf<double> dratio((size_t)np);
+    launch_interp(diw.p, (int)iw.size(), Y.p, dpiv.p, W.p, s);
+    launch_judge(djd.p, np, (const c64*)a, W.p, dpiv.p, dratio.p, s);
+    FDS_HIP(hipMemcpyAsync(ratio, dratio.p, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipMemcpyAsync(piv, dpiv.p, ptot * sizeof(int), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < np; ++i) {
+      rank[i] = hr[i];
+      revealed[i] = (hr[i] < std::min(sz[i], n[i]) || sz[i] >= n[i]) ? 1 : 0;
+    }
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_mlp_init(float* blob, int64_t n, const float* x, const float* y, uint64_t seed, void* stream) {
+  if (!blob || n < 1 || !x || !y) return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> hx((size_t)n * kMlpIn), hy((size_t)n);
+    FDS_HIP(hipMemcpyAsync(hx.data(), x, hx.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipMemcpyAsync(hy.data(), y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    double mu[kMlpIn] = {}, sd[kMlpIn] = {}, ymax = 1.0;
+    for (int64_t k = 0; k < n; ++k)
+      for (int c = 0; c < kMlpIn; ++c) mu[c] += hx[k * kMlpIn + c];
+    for (int c = 0; c < kMlpIn; ++c) mu[c] /= (double)n;
+    for (int64_t k = 0; k < n; ++k) {
+      for (int c = 0; c < kMlpIn; ++c) {
+        const double d = hx[k * kMlpIn + c] - mu[c];
+        sd[c] += d * d;
+      }
+      ymax = std::max(ymax, (double)hy[k]);
+    }
+    for (int c = 0; c < kMlpIn; ++c) {
+      sd[c] = std::sqrt(sd[c] / (double)n);
+      if (sd[c] == 0.0) sd[c] = 1.0;
+    }
+    // He-uniform weights lim (2 u - 1), u from SplitMix64 output p; zero biases
+    const int layout[8][3] = {{0, kMlpH * kMlpIn, kMlpIn}, {kMlpH * kMlpIn, kMlpH, 0},
+                              {kMlpH * kMlpIn + kMlpH, kMlpH * kMlpH, kMlpH},
+                              {kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH, kMlpH, 0},
+                              {kMlpH * kMlpIn + 2 * kMlpH + kMlpH * kMlpH, kMlpH * kMlpH, kMlpH},
+                              {kMlpH * kMlpIn + 2 * kMlpH + 2 * kMlpH * kMlpH, kMlpH, 0},
+                              {kMlpH * kMlpIn + 3 * kMlpH + 2 * kMlpH * kMlpH, kMlpH, kMlpH},
+                              {kMlpH * kMlpIn + 4 * kMlpH + 2 * kMlpH * kMlpH, 1, 0}};
+    for (auto& L : layout) {
+      const double lim = L[2] ? std::sqrt(6.0 / L[2]) : 0.0;
+      for (int p = L[0]; p < L[0] + L[1]; ++p) {
+        const double u = (double)(splitmix64(seed, (uint64_t)p) >> 11) * 0x1.0p-53;
+        blob[p] = L[2] ? (float)(lim * (2.0 * u - 1.0)) : 0.0f;
+      }
+    }
+    for (int c = 0; c < kMlpIn; ++c) {
+      blob[kMlpParams + c] = (float)mu[c];
+      blob[kMlpParams + kMlpIn + c] = (float)sd[c];
+    }
+    blob[kMlpParams + 2 * kMlpIn] = (float)ymax;
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_mlp_forward(const float* blob, int64_t n, const float* x, float* y, int32_t bf16, void* stream) {
+  if (!blob || n < 1 || !x || !y) return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> b(std::vector<float>(blob, blob + kMlpBlob));
+    launch_mlp_forward(n, x, b.p, y, bf16 ? 1 : 0, s);
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_mlp_loss_grad(const float* blob, int64_t n, const float* x, const float* y, float* grad, float* loss,
+                      void* stream) {
+  if (!blob || n < 1 || !x || !y || !grad || !loss) return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> b(std::vector<float>(blob, blob + kMlpBlob));
+    MlpWork w;
+    w.n_waves = mlp_grad_waves();
+    DevBuf<float> part((size_t)w.n_waves * (kMlpParams + 1)), g(kMlpParams), l(1);
+    w.partial = part.p;
+    launch_mlp_grad(n, n, x, y, b.p, 0, -1, w, g.p, l.p, s);
+    FDS_HIP(hipMemcpyAsync(grad, g.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipMemcpyAsync(loss, l.p, sizeof(float), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_mlp_train(float* blob, int64_t n, const float* x, const float* y, int32_t steps, int64_t batch, float lr,
+                  uint64_t seed, float* loss_hist, void* stream) {
+  if (!blob || n < 1 || !x || !y || steps < 0 || batch < 0 || !(lr > 0.0f)) return FDS_EINVAL;
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> b(std::vector<float>(blob, blob + kMlpBlob));
+    MlpWork w;
+    w.n_waves = mlp_grad_waves();
+    DevBuf<float> part((size_t)w.n_waves * (kMlpParams + 1)), g(kMlpParams), l((size_t)std::max(steps, 1));
+    DevBuf<float> m(std::vector<float>(kMlpParams, 0.0f)), v(std::vector<float>(kMlpParams, 0.0f));
+    w.partial = part.p;
+    for (int t = 1; t <= steps; ++t) {
+      if (batch == 0)
+        launch_mlp_grad(n, n, x, y, b.p, seed, -1, w, g.p, l.p + (t - 1), s);
+      else
+        launch_mlp_grad(n, batch, x, y, b.p, seed, t, w, g.p, l.p + (t - 1), s);
+      launch_adam(g.p, b.p, m.p, v.p, t, lr, s);
+    }
+    FDS_HIP(hipMemcpyAsync(blob, b.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (loss_hist && steps > 0)
+      FDS_HIP(hipMemcpyAsync(loss_hist, l.p, steps * sizeof(float), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {
     g_last_error = e.what();

@@ -545,7 +545,8 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   if (tid == 0) rank[blockIdx.x] = j;
 }
 
-// W = [I, R1^{-1} R2] P^T: solve R1 T = R2 in place, then write W or W^T.
+// W = [I, R1^{-1} R2] P^T: solve R1 T = R2 in place (unless already solved),
+// then write W or W^T.
 __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ descs, c64* __restrict__ abase,
                                                  const int* __restrict__ piv, c64* __restrict__ dbase) {
   const InterpDesc d = descs[blockIdx.x];
@@ -554,7 +555,7 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
   c64* D = dbase + d.d_off;
   const int n = d.n, lda = d.lda, k = d.k;
   const int tid = threadIdx.x;
-  for (int c = k + tid; c < n; c += kBlk) {
+  for (int c = k + tid; c < n && !d.solved; c += kBlk) {
     c64* col = A + (int64_t)c * lda;
     for (int i = k - 1; i >= 0; --i) {
       c64 s = col[i];

@@ -40,6 +40,7 @@ struct InterpDesc {     // W = [I, R1^{-1} R2] P^T (k x n) from a finished CPQR
   int64_t d_off;        // destination (col-major, ld = d_ld)
   int d_ld;
   int transpose;        // 0: write W at (r, c); 1: write W^T at (c, r)
+  int solved;           // 1: R12 already holds T = R11^{-1} R12 (an earlier launch solved in place)
 };
 
 struct ScatterDesc {    // dst[dst_off + rpos[r] + cpos[c] * dst_ld] = src[src_off + r + c * src_ld]

@@ -129,6 +129,20 @@ def test_training_fits_a_smooth_target():
     assert ol.loss_grad(blob, X, y)[0] < 0.05 * l0
 
 
+def test_init_blob_is_he_uniform():
+    mu, sd, ys = ol.standardise(np.array([[1.0, 2, 3, 4, 5, 8], [3.0, 2, 5, 4, 7, 8]]), [3.0, 40.0])
+    assert np.allclose(mu, [2, 2, 4, 4, 6, 8]) and np.allclose(sd, [1, 1, 1, 1, 1, 1]) and ys == 40.0
+    b = ol.init_blob(9, mu, sd, ys)
+    p = ol.unpack(b)
+    for name, fan in (("W1", 6), ("W2", 64), ("W3", 64), ("w4", 64)):
+        w = p[name].ravel()
+        lim = math.sqrt(6.0 / fan)
+        assert np.all(np.abs(w) <= lim) and np.std(w) > 0.4 * lim   # uniform on (-lim, lim): std lim/sqrt(3)
+    for name in ("b1", "b2", "b3", "b4"):
+        assert not np.any(p[name])
+    assert p["y_scale"] == 40.0 and np.array_equal(p["mu"], mu)
+
+
 def test_minibatch_indices_in_range():
     idx = ol.minibatch(3, 11, 1000, 37)
     assert idx.min() >= 0 and idx.max() < 37 and len(np.unique(idx)) == 37
