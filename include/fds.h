@@ -243,6 +243,19 @@ int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* 
                      int32_t* piv, const int64_t* pivoff, const int64_t* kmax, double tol,
                      int32_t stop_at_tol, int32_t* rank, void* stream);
 
+/* Batched LU with partial pivoting (the factorisation of the diagonal
+ * blocks A_i and of the compressed system, Sections 6.2, 6.3): for matrix p
+ * the n[p] x n[p] column-major matrix at a + off[p] (device, ld n[p]) is
+ * overwritten by L (unit lower, below the diagonal) and U; piv (device int32,
+ * n[p] entries at pivoff[p]) records that row k was swapped with row piv[k]
+ * at step k (0-based).  Pivot: largest modulus in the column, lowest row on
+ * ties.  Matrices up to 768 rows are factored by one workgroup each with the
+ * panel in LDS, larger ones by the multi-workgroup blocked form (panels of
+ * 32 columns).  info (host int32 [np]): 0, or 1 + the first step with a zero
+ * or non-finite pivot.  Synchronous. */
+int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n, int32_t* piv,
+                   const int64_t* pivoff, int32_t* info, void* stream);
+
 /* Randomized column ID with residual judge (learned form of the IDs of
  * Sections 7.1, 7.2): for problem p with the m[p] x n[p] column-major matrix
  * M at a + off[p] (device, ld m[p]; not modified), Y = Omega M with Omega

@@ -125,19 +125,66 @@ class Cell:
     n_near: tuple = (0, 0)     # near rows / near columns of the proxy matrices
 
 
-def build_tree(n_nodes: int, leaf: int):
+def morton_order(centres):
+    """Order of the curves along the Morton (Z-order) curve of their centres:
+    each coordinate scaled to the bounding box of the centres, quantised to
+    16 bits (floor of 65535 times the scaled value), bits interleaved with x
+    in the even positions; equal codes keep the input order."""
+    C = np.asarray(centres, dtype=np.float64).reshape(-1, 2)
+    if len(C) <= 1:
+        return np.arange(len(C))
+    lo, hi = C.min(axis=0), C.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    q = np.clip(np.floor((C - lo) / span * 65535.0), 0, 65535).astype(np.int64)
+    code = np.zeros(len(C), dtype=np.int64)
+    for b in range(16):
+        code |= ((q[:, 0] >> b) & 1) << (2 * b)
+        code |= ((q[:, 1] >> b) & 1) << (2 * b + 1)
+    return np.argsort(code, kind="stable")
+
+
+def curve_centres(bnd: Boundary):
+    """Bounding-box centre of each curve's nodes."""
+    return np.array([0.5 * (p.nodes.min(axis=0) + p.nodes.max(axis=0)) for p in bnd.polys])
+
+
+def build_tree(bnd: Boundary, leaf: int):
     """Complete binary tree with heap indexing (Section 5.1): cell 0 is the
-    root, children of i are 2i+1 and 2i+2; leaves are contiguous node ranges
-    split at midpoints."""
+    root, children of i are 2i+1 and 2i+2, depth L = ceil(log2(N / leaf)).
+    Cells are contiguous ranges [lo, hi) of a node numbering that takes the
+    curves in Morton order of their centres.  A cell holding two or more
+    whole curves splits its curve list into two groups of node counts as
+    equal as possible (curves kept whole; ties to the first such split);
+    a cell within one curve splits its node range at the midpoint.
+    Returns (L, cells, perm) with perm[p] the input index of node p."""
+    n_nodes = bnd.n_nodes
+    order = morton_order(curve_centres(bnd))
+    sizes = np.array([bnd.polys[c].n for c in order])
+    perm = np.concatenate([np.arange(bnd.offsets[c], bnd.offsets[c + 1]) for c in order])
+    pstart = np.concatenate([[0], np.cumsum(sizes)])
     L = max(0, int(math.ceil(math.log2(n_nodes / leaf)))) if n_nodes > leaf else 0
     cells = {0: Cell(0, 0, 0, n_nodes)}
+    cav = {0: (0, len(order))}      # whole curves [a, b) held by a cell; None within one curve
     for lev in range(L):
         for i in range(2 ** lev - 1, 2 ** (lev + 1) - 1):
             c = cells[i]
-            mid = c.lo + (c.hi - c.lo) // 2
+            g = cav[i]
+            if g is not None and g[1] - g[0] >= 2:
+                a, b = g
+                cand = np.arange(a + 1, b)
+                left = pstart[cand] - c.lo
+                sp = int(cand[np.argmin(np.abs(2 * left - (c.hi - c.lo)))])
+                mid = int(pstart[sp])
+                ga, gb = (a, sp), (sp, b)
+            else:
+                mid = c.lo + (c.hi - c.lo) // 2
+                ga = gb = None
+            if mid == c.lo or mid == c.hi:
+                raise ValueError("a tree cell would have no nodes: use a larger leaf size")
             cells[2 * i + 1] = Cell(2 * i + 1, lev + 1, c.lo, mid)
             cells[2 * i + 2] = Cell(2 * i + 2, lev + 1, mid, c.hi)
-    return L, cells
+            cav[2 * i + 1], cav[2 * i + 2] = ga, gb
+    return L, cells, perm
 
 
 def level_cells(cells, lev):
@@ -282,10 +329,10 @@ def leaf_sample(curves, lam, mu, rho, omega, tol, leaf, sample):
     Returns the cells."""
     mat = Material(lam, mu, rho, omega)
     bnd = Boundary(curves)
-    L, cells = build_tree(bnd.n_nodes, leaf)
+    L, cells, perm = build_tree(bnd, leaf)
     leaves = level_cells(cells, L)
     for c in leaves:
-        nodes = np.arange(c.lo, c.hi)
+        nodes = perm[c.lo:c.hi]
         c.rows = np.concatenate([2 * nodes, 2 * nodes + 1])
         c.cols = c.rows.copy()
     out = []
@@ -306,7 +353,7 @@ class FDS:
         self.mat = Material(lam, mu, rho, omega, alpha)
         self.bnd = Boundary(curves)
         self.tol = float(tol)
-        self.L, self.cells = build_tree(self.bnd.n_nodes, leaf)
+        self.L, self.cells, self.perm = build_tree(self.bnd, leaf)
         self.l0 = min(root_level, self.L)
         self._factor()
 
@@ -340,7 +387,7 @@ class FDS:
     def _factor(self):
         bnd, mat = self.bnd, self.mat
         for c in level_cells(self.cells, self.L):
-            nodes = np.arange(c.lo, c.hi)
+            nodes = self.perm[c.lo:c.hi]
             c.rows = np.concatenate([2 * nodes, 2 * nodes + 1])
             c.cols = c.rows.copy()
             c.A = entries(bnd, c.rows, c.cols, mat)

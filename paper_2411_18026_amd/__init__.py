@@ -73,7 +73,7 @@ ENOCONV = 6
 
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
-           "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_rid_batched", "fds_mlp_init",
+           "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
            "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train"]
 
 
@@ -109,6 +109,7 @@ def load():
                               ctypes.POINTER(i64), i64, ctypes.POINTER(i64), vp, i64, vp]
     L.fds_apply.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     pi64, pi32, pf = ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)
+    L.fds_lu_batched.argtypes = [i32, vp, pi64, pi64, vp, pi64, pi32, vp]
     L.fds_get_rank_log.argtypes = [vp, ctypes.POINTER(_RankRecord), i64, pi64]
     L.fds_rid_batched.argtypes = [i32, vp, pi64, pi64, pi64, pi64, pi64, ctypes.c_uint64, dbl, pi32, pi64, pi32, pi32,
                                   ctypes.POINTER(dbl), vp]
@@ -466,3 +467,32 @@ def mlp_train(blob, x, y, steps, batch, lr, seed, stream=None):
     _check(load().fds_mlp_train(P(b), n, ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(yt.data_ptr()), int(steps),
                                 int(batch), float(lr), int(seed), P(hist), _stream(stream)))
     return b, hist[:steps]
+
+
+def lu_batched(mats, stream=None):
+    """LU with partial pivoting of square complex matrices on the GPU.
+    Returns per matrix (LU packed as LAPACK does, pivots, info)."""
+    import torch
+    L = load()
+    ms = [np.asarray(m, dtype=np.complex128) for m in mats]
+    offs, nn, pvo = [], [], []
+    o = p = 0
+    for m in ms:
+        offs.append(o)
+        nn.append(m.shape[0])
+        pvo.append(p)
+        o += m.size
+        p += m.shape[0]
+    dev = torch.from_numpy(np.concatenate([m.T.ravel() for m in ms])).to("cuda")
+    piv = torch.zeros(p, dtype=torch.int32, device="cuda")
+    info = np.zeros(len(ms), np.int32)
+    a64 = lambda v: np.ascontiguousarray(v, dtype=np.int64)
+    offs, nn, pvo = a64(offs), a64(nn), a64(pvo)
+    P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    _check(L.fds_lu_batched(len(ms), ctypes.c_void_p(dev.data_ptr()), P(offs, ctypes.c_int64), P(nn, ctypes.c_int64),
+                            ctypes.c_void_p(piv.data_ptr()), P(pvo, ctypes.c_int64), P(info, ctypes.c_int32),
+                            _stream(stream)))
+    flat = dev.cpu().numpy()
+    pv = piv.cpu().numpy()
+    return [(flat[offs[i]:offs[i] + m.size].reshape(m.shape[1], m.shape[0]).T.copy(), pv[pvo[i]:pvo[i] + nn[i]].copy(),
+             int(info[i])) for i, m in enumerate(ms)]

@@ -295,21 +295,95 @@ static void span_begin(Factor& F, int what) {
 
 static void span_end(Factor& F) { FDS_HIP(hipEventRecord(F.spans.back().b, F.stream)); }
 
+// Curves in Morton (Z-order) order of their bounding-box centres: each
+// coordinate scaled to the bounding box of the centres, quantised to 16 bits,
+// bits interleaved with x in the even positions; equal codes keep input order.
+static std::vector<int> morton_order(const Geometry& G) {
+  const int nc = G.n_curves;
+  std::vector<double> cx(nc), cy(nc);
+  for (int c = 0; c < nc; ++c) {
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int t = G.curve_off[c]; t < G.curve_off[c] + G.curve_n[c]; ++t) {
+      x0 = std::min(x0, G.xy[2 * t]);
+      x1 = std::max(x1, G.xy[2 * t]);
+      y0 = std::min(y0, G.xy[2 * t + 1]);
+      y1 = std::max(y1, G.xy[2 * t + 1]);
+    }
+    cx[c] = 0.5 * (x0 + x1);
+    cy[c] = 0.5 * (y0 + y1);
+  }
+  std::vector<int> order(nc);
+  std::iota(order.begin(), order.end(), 0);
+  if (nc <= 1) return order;
+  const double lx = *std::min_element(cx.begin(), cx.end()), hx = *std::max_element(cx.begin(), cx.end());
+  const double ly = *std::min_element(cy.begin(), cy.end()), hy = *std::max_element(cy.begin(), cy.end());
+  const double sx = hx > lx ? hx - lx : 1.0, sy = hy > ly ? hy - ly : 1.0;
+  std::vector<uint64_t> code(nc, 0);
+  for (int c = 0; c < nc; ++c) {
+    const int64_t qx = std::min<int64_t>(65535, std::max<int64_t>(0, (int64_t)std::floor((cx[c] - lx) / sx * 65535.0)));
+    const int64_t qy = std::min<int64_t>(65535, std::max<int64_t>(0, (int64_t)std::floor((cy[c] - ly) / sy * 65535.0)));
+    for (int b = 0; b < 16; ++b) {
+      code[c] |= (uint64_t)((qx >> b) & 1) << (2 * b);
+      code[c] |= (uint64_t)((qy >> b) & 1) << (2 * b + 1);
+    }
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
+  return order;
+}
+
+// Complete binary tree of depth L = ceil(log2(N / leaf)) (Section 5.1) over
+// a node numbering that takes the curves in Morton order: a cell holding two
+// or more whole curves splits its curve list into two groups of node counts
+// as equal as possible (curves kept whole, ties to the first split); a cell
+// within one curve splits its node range at the midpoint.
 static void build_tree(Factor& F) {
-  const int N = F.G.n_nodes, leaf = F.opt.leaf_nodes;
+  const Geometry& G = F.G;
+  const int N = G.n_nodes, leaf = F.opt.leaf_nodes;
   int L = 0;
   while (((int64_t)leaf << L) < N) ++L;
   F.L = L;
   F.l0 = std::min(F.opt.root_level, L);
   F.levels.resize(L + 1);
-  // node ranges by midpoint splits
-  std::vector<std::pair<int, int>> cur{{0, N}};
+  const std::vector<int> order = morton_order(G);
+  const int nc = G.n_curves;
+  std::vector<int> perm;
+  std::vector<int64_t> pstart(nc + 1, 0);
+  perm.reserve(N);
+  for (int k = 0; k < nc; ++k) {
+    const int c = order[k];
+    for (int t = 0; t < G.curve_n[c]; ++t) perm.push_back(G.curve_off[c] + t);
+    pstart[k + 1] = pstart[k] + G.curve_n[c];
+  }
+  struct Range {
+    int lo, hi, ca, cb;   // node range; whole curves [ca, cb) or ca = -1 within one curve
+  };
+  std::vector<Range> cur{{0, N, 0, nc}};
   for (int lev = 0; lev < L; ++lev) {
-    std::vector<std::pair<int, int>> nxt;
-    for (auto& pr : cur) {
-      const int mid = pr.first + (pr.second - pr.first) / 2;
-      nxt.push_back({pr.first, mid});
-      nxt.push_back({mid, pr.second});
+    std::vector<Range> nxt;
+    for (const Range& r : cur) {
+      int mid;
+      Range a{}, b{};
+      if (r.ca >= 0 && r.cb - r.ca >= 2) {
+        int sp = r.ca + 1;
+        int64_t best = INT64_MAX;
+        for (int k = r.ca + 1; k < r.cb; ++k) {
+          const int64_t d = std::llabs(2 * (pstart[k] - r.lo) - (int64_t)(r.hi - r.lo));
+          if (d < best) {
+            best = d;
+            sp = k;
+          }
+        }
+        mid = (int)pstart[sp];
+        a = Range{r.lo, mid, r.ca, sp};
+        b = Range{mid, r.hi, sp, r.cb};
+      } else {
+        mid = r.lo + (r.hi - r.lo) / 2;
+        a = Range{r.lo, mid, -1, -1};
+        b = Range{mid, r.hi, -1, -1};
+      }
+      if (mid == r.lo || mid == r.hi) throw Error(FDS_EGEOM, "a tree cell would have no nodes: use a larger leaf size");
+      nxt.push_back(a);
+      nxt.push_back(b);
     }
     cur.swap(nxt);
   }
@@ -320,7 +394,7 @@ static void build_tree(Factor& F) {
   for (int q = 0; q < lv.n; ++q) {
     auto& rw = lv.rows[q];
     for (int c = 0; c < 2; ++c)
-      for (int t = cur[q].first; t < cur[q].second; ++t) rw.push_back(2 * (int64_t)t + c);
+      for (int p = cur[q].lo; p < cur[q].hi; ++p) rw.push_back(2 * (int64_t)perm[p] + c);
   }
   lv.cols = lv.rows;
 }
@@ -524,7 +598,7 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
       sd.push_back(SolveDesc{lv.a_off[q], lv.piv_off[q], lv.x_off[q], lv.b[q], lv.b[q], lv.b[q], lv.r[q]});
   }
   int* info = ws.get<int>("lu_info", (size_t)n);
-  launch_lu(ws.upload("lu_desc", ld), n, lv.bmax, A, lv.piv.p, info, s);
+  lu_factor(ld, A, lv.piv.p, info, ws, "lu_desc", s);
   launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, A, lv.piv.p, X, s);
   T* S = ws.get<T>("S" + tag, (size_t)std::max<int64_t>(lv.at_tot, 1));
   std::vector<GemmDesc> gd;
@@ -554,7 +628,7 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
   auto gt = gemm_tiles(gd);
   launch_gemm(ws.upload("s_desc", gd), ws.upload("s_tiles", gt), (int)gt.size(), rmax, 0, V, X, S, 0, s);
   int* info2 = ws.get<int>("lu_info2", std::max<size_t>(lds.size(), 1));
-  launch_lu(ws.upload("slu_desc", lds), (int)lds.size(), rmax, S, lv.s_piv.p, info2, s);
+  lu_factor(lds, S, lv.s_piv.p, info2, ws, "slu_desc", s);
   {
     int* dn = ws.upload("id_n", id_n);
     launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, At, s);
@@ -606,8 +680,8 @@ static void pair_and_extend(Factor& F, CellLevel& lv, const std::vector<int>& ce
   }
   if (!ev.empty() || !eu.empty()) {
     int* drank2 = ws.get<int>("id_rank2", ev.size() + eu.size());
-    launch_cpqr(ws.upload("cpqr_v2", ev), (int)ev.size(), baseV, dpiv, tol, drank2, F.stream);
-    launch_cpqr(ws.upload("cpqr_u2", eu), (int)eu.size(), baseU, dpiv, tol, drank2 + ev.size(), F.stream);
+    cpqr_factor(ev, baseV, dpiv, tol, drank2, ws, "cpqr_v2", F.stream);
+    cpqr_factor(eu, baseU, dpiv, tol, drank2 + ev.size(), ws, "cpqr_u2", F.stream);
     auto h = download(ws, drank2, ev.size() + eu.size());
     for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
     for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[ev.size() + i];
@@ -634,8 +708,8 @@ static void adaptive_ids(Factor& F, CellLevel& lv, const std::vector<int>& cells
       du[2 * ci + comp] = qu[2 * cells[ci] + comp];
     }
   int* drank = ws.get<int>("id_rank", 4 * nc);
-  launch_cpqr(ws.upload("cpqr_v", dv), (int)(2 * nc), MV, dpiv, F.tol, drank, F.stream);
-  launch_cpqr(ws.upload("cpqr_u", du), (int)(2 * nc), MU, dpiv, F.tol, drank + 2 * nc, F.stream);
+  cpqr_factor(dv, MV, dpiv, F.tol, drank, ws, "cpqr_v", F.stream);
+  cpqr_factor(du, MU, dpiv, F.tol, drank + 2 * nc, ws, "cpqr_u", F.stream);
   auto rk = download(ws, drank, 4 * nc);
   std::vector<int> rv(rk.begin(), rk.begin() + 2 * nc), ru(rk.begin() + 2 * nc, rk.end());
   pair_and_extend(F, lv, cells, dv, du, rv, ru, MV, MU, dpiv, F.tol);
@@ -735,7 +809,8 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
   launch_sketch(ws.upload("sk_v", sv), (int)sv.size(), MV, Y, F.opt.seed, s);
   launch_sketch(ws.upload("sk_u", su), (int)su.size(), MU, Y, F.opt.seed, s);
   int* drank = ws.get<int>("sk_rank", 4 * ns);
-  launch_cpqr(ws.upload("sk_cpqr", yd), (int)yd.size(), Y, dpiv, kSketchTolFactor * F.tol, drank, s);
+  launch_cpqr(ws.upload("sk_cpqr", yd), (int)yd.size(), Y, dpiv, kSketchTolFactor * F.tol, drank, s,
+              check_cpqr_sizes(yd));
   const auto rk = download(ws, drank, 4 * ns);
   // the sketch must reveal every rank: a crossing inside it, or s >= n
   std::vector<int> acc;
@@ -1213,7 +1288,7 @@ static void factor_root(Factor& F) {
   }
   span_begin(F, 2);
   int* info = ws.get<int>("root_info", 1);
-  launch_lu(ws.upload("root_lu", std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}), 1, rt.n, rt.A.p, rt.piv.p, info, s);
+  lu_factor(std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}, rt.A.p, rt.piv.p, info, ws, "root_lu", s);
   span_end(F);
   check_info(ws, info, 1);
   rt.desc = DevBuf<SolveDesc>(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt.n, rt.n, rt.n, 0}});
@@ -1891,6 +1966,28 @@ int fds_get_rank_log(fds_factor f, fds_rank_record* out, int64_t cap, int64_t* n
   return FDS_OK;
 }
 
+int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n, int32_t* piv,
+                   const int64_t* pivoff, int32_t* info, void* stream) {
+  if (np < 1 || !a || !off || !n || !piv || !pivoff || !info) return FDS_EINVAL;
+  try {
+    std::vector<LUDesc> d(np);
+    for (int i = 0; i < np; ++i) {
+      if (n[i] < 1 || n[i] > INT32_MAX / 2) return FDS_EINVAL;
+      d[i] = LUDesc{off[i], pivoff[i], (int)n[i], (int)n[i]};
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    int* dinfo = ws.get<int>("info", (size_t)np);
+    lu_factor(d, (c64*)a, piv, dinfo, ws, "lu", s);
+    FDS_HIP(hipMemcpyAsync(info, dinfo, np * sizeof(int), hipMemcpyDeviceToHost, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
 int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
                     const int64_t* sz, const int64_t* gid, uint64_t seed, double tol, int32_t* piv,
                     const int64_t* pivoff, int32_t* rank, int32_t* revealed, double* ratio, void* stream) {
@@ -1916,7 +2013,7 @@ int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int6
     DevBuf<c64> Y((size_t)ytot);
     DevBuf<int> dpiv((size_t)ptot), drank((size_t)np);
     launch_sketch(dsd.p, np, (const c64*)a, Y.p, seed, s);
-    launch_cpqr(dyd.p, np, Y.p, dpiv.p, tol, drank.p, s);
+    launch_cpqr(dyd.p, np, Y.p, dpiv.p, tol, drank.p, s, check_cpqr_sizes(yd));
     std::vector<int> hr(np);
     FDS_HIP(hipMemcpyAsync(hr.data(), drank.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
     FDS_HIP(hipStreamSynchronize(s));
@@ -2075,8 +2172,8 @@ int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* 
     }
     check_cpqr_sizes(d);
     hipStream_t s = (hipStream_t)stream;
-    DevBuf<CpqrDesc> dd(d);
-    launch_cpqr(dd.p, np, (c64*)a, piv, tol, rank, s);
+    Workspace ws(s);
+    cpqr_factor(d, (c64*)a, piv, tol, rank, ws, "cpqr", s);
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {

@@ -233,6 +233,144 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
   if (tid == 0 && info) info[blockIdx.x] = bad;
 }
 
+// Blocked LU for matrices too large for the LDS panel of k_lu_blk, spread
+// over many workgroups: per panel of kPanel columns, k_panel_lu factors the
+// panel (one workgroup per matrix), k_swap_outside applies its row
+// interchanges to the other columns, k_trsm_u12 forms U12 = L11^{-1} A12 and
+// the batched GEMM updates the trailing matrix.  Same pivot rule and output
+// layout as k_lu.
+constexpr int kPanel = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlk) k_panel_lu(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base,
+                                                   int* __restrict__ piv, int* __restrict__ info) {
+  __shared__ double sv[kBlk / 64];
+  __shared__ int si[kBlk / 64];
+  __shared__ int s_p;
+  const LUDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  T* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int n = d.n, lda = d.lda, nb = min(kPanel, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int j = 0; j < nb; ++j) {
+    const int col = k0 + j;
+    T* cj = A + (int64_t)col * lda;
+    double best = -1.0;
+    int bi = n;
+    for (int i = col + tid; i < n; i += kBlk) {
+      const double v = abs2(cj[i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      sv[wid] = best;
+      si[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = sv[0];
+      int ib = si[0];
+      for (int w = 1; w < kBlk / 64; ++w)
+        if (sv[w] > b || (sv[w] == b && si[w] < ib)) {
+          b = sv[w];
+          ib = si[w];
+        }
+      s_p = ib;
+      P[col] = ib;
+      if ((!(b > 0.0) || !isfinite(b)) && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != col && tid < nb) {
+      T* cc = A + (int64_t)(k0 + tid) * lda;
+      const T t = cc[col];
+      cc[col] = cc[p];
+      cc[p] = t;
+    }
+    __syncthreads();
+    const T pj = cj[col];
+    const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
+    for (int i = col + 1 + tid; i < n; i += kBlk) {
+      const T l = cj[i] * inv;
+      cj[i] = l;
+      for (int c = j + 1; c < nb; ++c) {
+        T* cc = A + (int64_t)(k0 + c) * lda;
+        cc[i] -= l * cc[col];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// row interchanges of panel k0 on every column outside it (one thread per column)
+template <typename T>
+__global__ void k_swap_outside(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base,
+                               const int* __restrict__ piv) {
+  const LUDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k0 >= d.n || c >= d.n) return;
+  const int nb = min(kPanel, d.n - k0);
+  if (c >= k0 && c < k0 + nb) return;
+  T* col = base + d.a_off + (int64_t)c * d.lda;
+  const int* P = piv + d.piv_off;
+  for (int j = 0; j < nb; ++j) {
+    const int p = P[k0 + j];
+    if (p != k0 + j) {
+      const T t = col[k0 + j];
+      col[k0 + j] = col[p];
+      col[p] = t;
+    }
+  }
+}
+
+// U12 = L11^{-1} A12 for the columns right of panel k0 (one thread per column)
+template <typename T>
+__global__ void __launch_bounds__(kBlk) k_trsm_u12(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base) {
+  __shared__ T L11[kPanel][kPanel + 1];
+  const LUDesc d = descs[blockIdx.y];
+  if (k0 >= d.n) return;
+  const int nb = min(kPanel, d.n - k0);
+  T* A = base + d.a_off;
+  for (int t = threadIdx.x; t < nb * nb; t += kBlk) {
+    const int r = t % nb, c = t / nb;
+    L11[r][c] = A[(k0 + r) + (int64_t)(k0 + c) * d.lda];
+  }
+  __syncthreads();
+  const int c = k0 + nb + blockIdx.x * kBlk + threadIdx.x;
+  if (c >= d.n) return;
+  T* col = A + (int64_t)c * d.lda + k0;
+  T x[kPanel];
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) {
+    if (r < nb) {
+      T s = col[r];
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q < r) s -= L11[r][q] * x[q];
+      x[r] = s;
+      col[r] = s;
+    }
+  }
+}
+
+__global__ void k_scatter_int(int64_t n, const int64_t* __restrict__ sidx, const int64_t* __restrict__ didx,
+                              const int* __restrict__ src, int* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[didx[i]] = src[sidx[i]];
+}
+
 // ------------------------------------------------------------------ LU solve
 // block (blockIdx.x = problem, blockIdx.y = chunk of ``chunk`` columns);
 // ncol_override > 0 replaces every problem's column count.  The chunk of B
@@ -411,14 +549,23 @@ __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ desc
 }
 
 // ------------------------------------------------------------------ pivoted QR
-constexpr int kQrMaxM = 2048;
+constexpr int kQrMaxM = 2048;    // rows with the Householder vector in LDS
 constexpr int kQrMaxN = 1024;
+constexpr int kQrMaxNTall = 4096;
+constexpr int64_t kQrwMinElems = 1 << 18;   // problems this large use the multi-workgroup QR
 
+// TALL = false: the Householder vector is staged in LDS (m <= kQrMaxM,
+// n <= kQrMaxN).  TALL = true: any m, n <= kQrMaxNTall; the vector is read
+// in place from column j (its entries below the diagonal are the column's
+// own), its top entry kept in LDS, and the column cleared after the update.
+template <bool TALL>
 __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ descs, c64* __restrict__ base,
                                                int* __restrict__ piv, double tol, int* __restrict__ rank) {
-  __shared__ double nrm[kQrMaxN];
-  __shared__ int pv[kQrMaxN];
-  __shared__ c64 v[kQrMaxM];
+  constexpr int NMAX = TALL ? kQrMaxNTall : kQrMaxN;
+  __shared__ double nrm[NMAX];
+  __shared__ int pv[NMAX];
+  __shared__ c64 v_lds[TALL ? 1 : kQrMaxM];
+  __shared__ c64 s_vtop;
   __shared__ double sv[kBlk];
   __shared__ int si[kBlk];
   __shared__ double s_r00, s_tau;
@@ -497,32 +644,38 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
     }
     __syncthreads();
     // Householder reflector H = I - tau v v^H with H x = alpha e1
-    for (int i = j + tid; i < m; i += kBlk) v[i] = A[i + (int64_t)j * lda];
-    __syncthreads();
+    c64* colj = A + (int64_t)j * lda;
+    const c64* v = TALL ? colj : v_lds;   // v[i] for i > j; v[j] is s_vtop
+    if (!TALL) {
+      for (int i = j + tid; i < m; i += kBlk) v_lds[i] = colj[i];
+      __syncthreads();
+    }
     if (wid == 0) {
       double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) s += abs2(v[i]);
+      for (int i = j + lane; i < m; i += 64) s += abs2(TALL ? colj[i] : v_lds[i]);
       s = wsum(s);
       if (lane == 0) {
         const double xn = sqrt(s);
-        const c64 x0 = v[j];
+        const c64 x0 = colj[j];
         const double ax0 = sqrt(abs2(x0));
         const c64 ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
         const c64 alpha = (-xn) * ph;
-        v[j] = x0 - alpha;
+        s_vtop = x0 - alpha;
         const double vn2 = 2.0 * s + 2.0 * ax0 * xn;
         s_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-        A[j + (int64_t)j * lda] = alpha;
+        colj[j] = alpha;
       }
     }
     __syncthreads();
-    for (int i = j + 1 + tid; i < m; i += kBlk) A[i + (int64_t)j * lda] = cmk(0, 0);
+    if (!TALL)
+      for (int i = j + 1 + tid; i < m; i += kBlk) colj[i] = cmk(0, 0);
     const double tau = s_tau;
+    const c64 vtop = s_vtop;
     for (int c = j + 1 + wid; c < n; c += kBlk / 64) {
       c64* col = A + (int64_t)c * lda;
       double wr = 0.0, wi = 0.0;
       for (int i = j + lane; i < m; i += 64) {
-        const c64 a = col[i], vv = v[i];
+        const c64 a = col[i], vv = i == j ? vtop : v[i];
         wr += vv.re * a.re + vv.im * a.im;    // conj(v) a
         wi += vv.re * a.im - vv.im * a.re;
       }
@@ -531,7 +684,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
       const c64 w = cmk(tau * wr, tau * wi);
       double s = 0.0;
       for (int i = j + lane; i < m; i += 64) {
-        const c64 a = col[i] - v[i] * w;
+        const c64 a = col[i] - (i == j ? vtop : v[i]) * w;
         col[i] = a;
         if (i > j) s += abs2(a);
       }
@@ -539,10 +692,193 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
       if (lane == 0) nrm[c] = s;
     }
     __syncthreads();
+    if (TALL) {
+      for (int i = j + 1 + tid; i < m; i += kBlk) colj[i] = cmk(0, 0);
+      __syncthreads();
+    }
   }
   __syncthreads();
   for (int c = tid; c < n; c += kBlk) P[c] = pv[c];
   if (tid == 0) rank[blockIdx.x] = j;
+}
+
+// Multi-workgroup pivoted QR for large problems (same pivot and stopping
+// rules as k_cpqr): a host loop over steps j launches k_qrw_pivot (one
+// workgroup per problem: clear the previous reflector's column, choose the
+// pivot, swap, form the reflector in place) and k_qrw_update (problem x
+// column chunks: apply the reflector, recompute the exact remaining norms).
+struct QrwState {
+  double r00, tau;
+  c64 vtop;
+  int stop, rank;
+};
+
+constexpr int kQrwCols = 16;   // columns per workgroup of k_qrw_update (4 per wavefront)
+
+__global__ void k_qrw_init(const CpqrDesc* __restrict__ descs, c64* __restrict__ base, int* __restrict__ piv,
+                           double* __restrict__ nrm, QrwState* __restrict__ st) {
+  const CpqrDesc d = descs[blockIdx.y];
+  const c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  double* N = nrm + d.piv_off;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = blockIdx.x * kQrwCols + wid; c < min(d.n, (int)(blockIdx.x + 1) * kQrwCols); c += blockDim.x / 64) {
+    if (lane == 0 && d.k_start == 0) P[c] = c;
+    if (c < d.k_start) continue;
+    double s = 0.0;
+    for (int i = d.k_start + lane; i < d.m; i += 64) s += abs2(A[i + (int64_t)c * d.lda]);
+    s = wsum(s);
+    if (lane == 0) N[c] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    QrwState q{};
+    q.r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
+    q.stop = 0;
+    q.rank = d.k_start;
+    st[blockIdx.y] = q;
+  }
+}
+
+__global__ void __launch_bounds__(kBlk) k_qrw_pivot(const CpqrDesc* __restrict__ descs, int j, c64* __restrict__ base,
+                                                    int* __restrict__ piv, double* __restrict__ nrm,
+                                                    QrwState* __restrict__ st, double tol) {
+  __shared__ double sv[kBlk];
+  __shared__ int si[kBlk];
+  __shared__ int s_p, s_stop;
+  const CpqrDesc d = descs[blockIdx.x];
+  if (j < d.k_start || st[blockIdx.x].stop) return;
+  c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  double* N = nrm + d.piv_off;
+  const int m = d.m, n = d.n, lda = d.lda;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int kmax = min(d.k_end, min(m, n));
+  // the previous step's reflector is no longer needed: clear it
+  if (j > d.k_start)
+    for (int i = j + tid; i < m; i += kBlk) A[i + (int64_t)(j - 1) * lda] = cmk(0.0, 0.0);
+  if (j >= kmax) {
+    if (tid == 0) {
+      st[blockIdx.x].stop = 1;
+      st[blockIdx.x].rank = j;
+    }
+    return;
+  }
+  double best = -1.0;
+  for (int c = j + tid; c < n; c += kBlk) best = fmax(best, N[c]);
+  sv[tid] = best;
+  __syncthreads();
+  for (int o = kBlk / 2; o > 0; o >>= 1) {
+    if (tid < o) sv[tid] = fmax(sv[tid], sv[tid + o]);
+    __syncthreads();
+  }
+  const double top = sv[0];
+  __syncthreads();
+  int bo = 0x7fffffff, bc = -1;
+  for (int c = j + tid; c < n; c += kBlk)
+    if (N[c] >= top * (1.0 - 1e-12) && P[c] < bo) {
+      bo = P[c];
+      bc = c;
+    }
+  si[tid] = bo;
+  sv[tid] = (double)bc;
+  __syncthreads();
+  for (int o = kBlk / 2; o > 0; o >>= 1) {
+    if (tid < o && si[tid + o] < si[tid]) {
+      si[tid] = si[tid + o];
+      sv[tid] = sv[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int p = (int)sv[0];
+    const double rjj = sqrt(N[p]);
+    QrwState q = st[blockIdx.x];
+    if (j == 0) q.r00 = rjj;
+    s_stop = (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * q.r00)) ? 1 : 0;
+    if (s_stop) {
+      q.stop = 1;
+      q.rank = j;
+    }
+    st[blockIdx.x] = q;
+    s_p = p;
+  }
+  __syncthreads();
+  if (s_stop) return;
+  const int p = s_p;
+  if (p != j) {
+    for (int i = tid; i < m; i += kBlk) {
+      const c64 t = A[i + (int64_t)j * lda];
+      A[i + (int64_t)j * lda] = A[i + (int64_t)p * lda];
+      A[i + (int64_t)p * lda] = t;
+    }
+    if (tid == 0) {
+      const double t = N[j];
+      N[j] = N[p];
+      N[p] = t;
+      const int q = P[j];
+      P[j] = P[p];
+      P[p] = q;
+    }
+  }
+  __syncthreads();
+  c64* colj = A + (int64_t)j * lda;
+  double s = 0.0;
+  for (int i = j + tid; i < m; i += kBlk) s += abs2(colj[i]);
+  s = wsum(s);
+  if (lane == 0) sv[wid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlk / 64; ++w) t += sv[w];
+    const double xn = sqrt(t);
+    const c64 x0 = colj[j];
+    const double ax0 = sqrt(abs2(x0));
+    const c64 ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+    const c64 alpha = (-xn) * ph;
+    const double vn2 = 2.0 * t + 2.0 * ax0 * xn;
+    st[blockIdx.x].vtop = x0 - alpha;
+    st[blockIdx.x].tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    colj[j] = alpha;
+  }
+}
+
+__global__ void __launch_bounds__(kBlk) k_qrw_update(const CpqrDesc* __restrict__ descs, int j,
+                                                     c64* __restrict__ base, double* __restrict__ nrm,
+                                                     const QrwState* __restrict__ st) {
+  const CpqrDesc d = descs[blockIdx.y];
+  const QrwState q = st[blockIdx.y];
+  if (j < d.k_start || q.stop) return;
+  c64* A = base + d.a_off;
+  double* N = nrm + d.piv_off;
+  const int m = d.m, lda = d.lda;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const c64* v = A + (int64_t)j * lda;
+  const int c_lo = j + 1 + (int)blockIdx.x * kQrwCols, c_hi = min(d.n, c_lo + kQrwCols);
+  for (int c = c_lo + wid; c < c_hi; c += kBlk / 64) {
+    c64* col = A + (int64_t)c * lda;
+    double wr = 0.0, wi = 0.0;
+    for (int i = j + lane; i < m; i += 64) {
+      const c64 a = col[i], vv = i == j ? q.vtop : v[i];
+      wr += vv.re * a.re + vv.im * a.im;
+      wi += vv.re * a.im - vv.im * a.re;
+    }
+    wr = wsum(wr);
+    wi = wsum(wi);
+    const c64 w = cmk(q.tau * wr, q.tau * wi);
+    double s = 0.0;
+    for (int i = j + lane; i < m; i += 64) {
+      const c64 a = col[i] - (i == j ? q.vtop : v[i]) * w;
+      col[i] = a;
+      if (i > j) s += abs2(a);
+    }
+    s = wsum(s);
+    if (lane == 0) N[c] = s;
+  }
+}
+
+__global__ void k_qrw_rank(int n, const QrwState* __restrict__ st, const int* __restrict__ idx, int* __restrict__ rank) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rank[idx[i]] = st[i].rank;
 }
 
 // W = [I, R1^{-1} R2] P^T: solve R1 T = R2 in place (unless already solved),
@@ -677,6 +1013,88 @@ void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, h
   FDS_HIP(hipGetLastError());
 }
 
+template <typename T>
+void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Workspace& ws, const std::string& tag,
+               hipStream_t s) {
+  if (d.empty()) return;
+  // matrices whose 4-column LDS panel fits go to the one-workgroup kernels
+  std::vector<LUDesc> small, big;
+  std::vector<int> small_i, big_i;
+  int nsmall = 0, nbig = 0;
+  for (int i = 0; i < (int)d.size(); ++i) {
+    if ((size_t)d[i].n * sizeof(T) * 4 <= 49152) {
+      small.push_back(d[i]);
+      small_i.push_back(i);
+      nsmall = std::max(nsmall, d[i].n);
+    } else {
+      big.push_back(d[i]);
+      big_i.push_back(i);
+      nbig = std::max(nbig, d[i].n);
+    }
+  }
+  if (big.empty()) {
+    launch_lu(ws.upload(tag + "_d", d), (int)d.size(), nsmall, base, piv, info, s);
+    return;
+  }
+  // info slots follow the caller's order: small matrices first report into
+  // a scratch array, then everything is scattered back by index
+  int* inf_s = ws.get<int>(tag + "_is", std::max<size_t>(small.size(), 1));
+  int* inf_b = ws.get<int>(tag + "_ib", big.size());
+  FDS_HIP(hipMemsetAsync(inf_b, 0, big.size() * sizeof(int), s));
+  if (!small.empty()) launch_lu(ws.upload(tag + "_ds", small), (int)small.size(), nsmall, base, piv, inf_s, s);
+  const LUDesc* db = ws.upload(tag + "_db", big);
+  for (int k0 = 0; k0 < nbig; k0 += kPanel) {
+    k_panel_lu<T><<<(unsigned)big.size(), kBlk, 0, s>>>(db, k0, base, piv, inf_b);
+    FDS_HIP(hipGetLastError());
+    dim3 gs((unsigned)((nbig + 255) / 256), (unsigned)big.size());
+    k_swap_outside<T><<<gs, 256, 0, s>>>(db, k0, base, piv);
+    FDS_HIP(hipGetLastError());
+    const int rest = nbig - k0 - kPanel;
+    if (rest <= 0) continue;
+    dim3 gt((unsigned)((rest + kBlk - 1) / kBlk), (unsigned)big.size());
+    k_trsm_u12<T><<<gt, kBlk, 0, s>>>(db, k0, base);
+    FDS_HIP(hipGetLastError());
+    std::vector<GemmDesc> gd;
+    for (const LUDesc& x : big) {
+      const int r = x.n - k0 - kPanel;
+      if (r <= 0) continue;
+      GemmDesc g{};
+      g.a_off = x.a_off + (k0 + kPanel) + (int64_t)k0 * x.lda;
+      g.b_off = x.a_off + k0 + (int64_t)(k0 + kPanel) * x.lda;
+      g.c_off = x.a_off + (k0 + kPanel) + (int64_t)(k0 + kPanel) * x.lda;
+      g.m = g.n = r;
+      g.k = kPanel;
+      g.lda = g.ldb = g.ldc = x.lda;
+      g.alpha_re = -1.0;
+      g.beta_re = 1.0;
+      gd.push_back(g);
+    }
+    const auto gt2 = gemm_tiles(gd);
+    launch_gemm(ws.upload(tag + "_g", gd), ws.upload(tag + "_gt", gt2), (int)gt2.size(), rest, 0, base, base, base,
+                0, s);
+  }
+  if (info) {
+    // info slots back in the caller's order
+    std::vector<int64_t> src, dst;
+    for (size_t i = 0; i < small_i.size(); ++i) {
+      src.push_back((int64_t)i);
+      dst.push_back(small_i[i]);
+    }
+    const size_t ns = src.size();
+    for (size_t i = 0; i < big_i.size(); ++i) {
+      src.push_back((int64_t)(ns + i));
+      dst.push_back(big_i[i]);
+    }
+    int* both = ws.get<int>(tag + "_ia", src.size());
+    if (ns) FDS_HIP(hipMemcpyAsync(both, inf_s, ns * sizeof(int), hipMemcpyDeviceToDevice, s));
+    FDS_HIP(hipMemcpyAsync(both + ns, inf_b, big_i.size() * sizeof(int), hipMemcpyDeviceToDevice, s));
+    const int64_t* ds = ws.upload(tag + "_is_src", src);
+    const int64_t* dd = ws.upload(tag + "_is_dst", dst);
+    k_scatter_int<<<(unsigned)((src.size() + 255) / 256), 256, 0, s>>>((int64_t)src.size(), ds, dd, both, info);
+    FDS_HIP(hipGetLastError());
+  }
+}
+
 int solve_chunk(int nmax) { return std::max(1, std::min(8, 32768 / (16 * std::max(1, nmax)))); }
 
 template <typename T>
@@ -709,14 +1127,92 @@ void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_ma
   FDS_HIP(hipGetLastError());
 }
 
-void check_cpqr_sizes(const std::vector<CpqrDesc>& d) {
-  for (auto& x : d)
-    if (x.m > kQrMaxM || x.n > kQrMaxN) throw Error(1, "cpqr: matrix exceeds the LDS limits");
+int check_cpqr_sizes(const std::vector<CpqrDesc>& d) {
+  int tall = 0;
+  for (auto& x : d) {
+    if (x.n > kQrMaxNTall) throw Error(1, "cpqr: more than 4096 columns");
+    if (x.m > kQrMaxM || x.n > kQrMaxN) tall = 1;
+  }
+  return tall;
 }
 
-void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s) {
+void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, Workspace& ws,
+                 const std::string& tag, hipStream_t s) {
+  if (d.empty()) return;
+  std::vector<CpqrDesc> one, wide;
+  std::vector<int> one_i, wide_i;
+  for (int i = 0; i < (int)d.size(); ++i) {
+    // large problems: spread each step over many workgroups
+    if ((int64_t)d[i].m * d[i].n >= kQrwMinElems || d[i].n > kQrMaxN) {
+      wide.push_back(d[i]);
+      wide_i.push_back(i);
+    } else {
+      one.push_back(d[i]);
+      one_i.push_back(i);
+    }
+  }
+  if (wide.empty()) {
+    launch_cpqr(ws.upload(tag + "_d", d), (int)d.size(), base, piv, tol, rank, s, check_cpqr_sizes(d));
+    return;
+  }
+  if (!one.empty()) {
+    int* r1 = ws.get<int>(tag + "_r1", one.size());
+    launch_cpqr(ws.upload(tag + "_d1", one), (int)one.size(), base, piv, tol, r1, s, check_cpqr_sizes(one));
+    std::vector<int64_t> src(one.size()), dst(one.size());
+    for (size_t i = 0; i < one.size(); ++i) {
+      src[i] = (int64_t)i;
+      dst[i] = one_i[i];
+    }
+    k_scatter_int<<<(unsigned)((one.size() + 255) / 256), 256, 0, s>>>(
+        (int64_t)one.size(), ws.upload(tag + "_s1", src), ws.upload(tag + "_t1", dst), r1, rank);
+    FDS_HIP(hipGetLastError());
+  }
+  int nmax = 0, j0 = INT32_MAX, j1 = 0;
+  int64_t ntot = 0;
+  for (const CpqrDesc& x : wide) {
+    if (x.n > kQrMaxNTall) throw Error(1, "cpqr: more than 4096 columns");
+    nmax = std::max(nmax, x.n);
+    j0 = std::min(j0, x.k_start);
+    j1 = std::max(j1, std::min(x.k_end, std::min(x.m, x.n)));
+    ntot = std::max<int64_t>(ntot, x.piv_off + x.n);
+  }
+  const CpqrDesc* dw = ws.upload(tag + "_dw", wide);
+  double* nrm = ws.get<double>(tag + "_nrm", (size_t)ntot);
+  QrwState* stt = ws.get<QrwState>(tag + "_st", wide.size());
+  const unsigned chunks = (unsigned)((nmax + kQrwCols - 1) / kQrwCols);
+  k_qrw_init<<<dim3(chunks, (unsigned)wide.size()), kBlk, 0, s>>>(dw, base, piv, nrm, stt);
+  FDS_HIP(hipGetLastError());
+  std::vector<QrwState> hs(wide.size());
+  for (int j = j0; j <= j1; ++j) {
+    k_qrw_pivot<<<(unsigned)wide.size(), kBlk, 0, s>>>(dw, j, base, piv, nrm, stt, tol);
+    FDS_HIP(hipGetLastError());
+    if (j < j1) {
+      const unsigned ch = (unsigned)((nmax - j - 1 + kQrwCols - 1) / kQrwCols);
+      if (ch > 0) {
+        k_qrw_update<<<dim3(ch, (unsigned)wide.size()), kBlk, 0, s>>>(dw, j, base, nrm, stt);
+        FDS_HIP(hipGetLastError());
+      }
+    }
+    // every 32 steps: stop early once every problem has reached its rank
+    if ((j - j0) % 32 == 31 && j < j1) {
+      FDS_HIP(hipMemcpyAsync(hs.data(), stt, hs.size() * sizeof(QrwState), hipMemcpyDeviceToHost, s));
+      FDS_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (auto& q : hs) all = all && q.stop;
+      if (all) break;
+    }
+  }
+  k_qrw_rank<<<(unsigned)((wide.size() + 255) / 256), 256, 0, s>>>((int)wide.size(), stt,
+                                                                    ws.upload(tag + "_wi", wide_i), rank);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s, int tall) {
   if (n == 0) return;
-  k_cpqr<<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
+  if (tall)
+    k_cpqr<true><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
+  else
+    k_cpqr<false><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
   FDS_HIP(hipGetLastError());
 }
 
@@ -787,6 +1283,8 @@ void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, co
 
 #define FDS_INST(T)                                                                                                 \
   template void launch_lu<T>(const LUDesc*, int, int, T*, int*, int*, hipStream_t);                                \
+  template void lu_factor<T>(const std::vector<LUDesc>&, T*, int*, int*, Workspace&, const std::string&,           \
+                             hipStream_t);                                                                          \
   template void launch_lu_solve<T>(const SolveDesc*, int, int, int, int, const T*, const int*, T*, hipStream_t);   \
   template void launch_gemm<T>(const GemmDesc*, const GemmTile*, int, int, int, const T*, const T*, T*, int,       \
                                hipStream_t);                                                                        \

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "devmem.hpp"
 
 namespace fds {
 
@@ -64,6 +65,13 @@ struct ScatterTile {
 // and sweeps of the mixed-precision form).
 template <typename T>
 void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, hipStream_t s);
+// LU of a batch given on the host: one workgroup per matrix where its panel
+// fits in LDS, the multi-workgroup blocked LU (panels of 32 columns, GEMM
+// trailing updates) for larger ones.  Descriptors go through ``ws`` under
+// keys starting with ``tag``; info[i] for d[i] as in launch_lu.
+template <typename T>
+void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Workspace& ws, const std::string& tag,
+               hipStream_t s);
 int solve_chunk(int nmax);
 template <typename T>
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
@@ -72,8 +80,16 @@ std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d);
 template <typename T>
 void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
                  const T* bbase, T* cbase, int transA, hipStream_t s);
-void check_cpqr_sizes(const std::vector<CpqrDesc>& d);
-void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s);
+// 1 if some problem needs the tall variant (m > 2048 or n > 1024); throws
+// beyond 4096 columns
+int check_cpqr_sizes(const std::vector<CpqrDesc>& d);
+void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s, int tall);
+// Pivoted QR of a batch given on the host: one workgroup per problem for the
+// usual sizes, the multi-workgroup step loop for problems of 2^18 elements
+// or more (results identical in rule; rank[i] for d[i]).  Synchronises the
+// stream every 32 steps of the multi-workgroup loop.
+void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, Workspace& ws,
+                 const std::string& tag, hipStream_t s);
 void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s);
 std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d);
 // (TS, TD) in {(c64, c64), (c32, c32), (c32, c64)}

@@ -133,12 +133,14 @@ def test_small_validation_case(fdsmod):
             assert np.array_equal(r, c.rskel) and np.array_equal(cc, c.cskel)
 
 
-@pytest.mark.parametrize("case", ["ragged", "multi", "deep_root0"])
+@pytest.mark.parametrize("case", ["ragged", "multi", "deep_root0", "cavities4"])
 def test_fds_against_oracle(fdsmod, case):
     if case == "ragged":
         curves, leaf, l0, omega = [sy.ellipse(300, 1.0, 0.5)], 32, 1, 3.0
     elif case == "multi":
         curves, leaf, l0, omega = GEOMS["two_cavities"], 16, 1, 2.0
+    elif case == "cavities4":  # tree over several curves (Morton order, whole-curve groups)
+        curves, leaf, l0, omega = sy.multi_cavity(21, 4, 220, half_width=2.5), 16, 1, 2.0
     else:
         curves, leaf, l0, omega = [sy.tripod(256)], 16, 0, 2.0
     kinds, angles = [0, 1, 0], [0.0, 0.9, 3.0]
@@ -174,3 +176,46 @@ def test_graph_solve_replays_match_eager(fdsmod):
         assert torch.equal(xg2, xe2), k
     x1 = Fg.solve(rhs[1])                # another nrhs: a second graph
     assert torch.equal(x1, Fe.solve(rhs[1]))
+
+
+def test_cpqr_tall_variant_matches_oracle(fdsmod):
+    """Matrices beyond the LDS-staged sizes (more than 2048 rows or 1024
+    columns) go through the variant that reads the reflector in place."""
+    rng = np.random.default_rng(8)
+    A = (rng.standard_normal((2500, 70)) + 1j * rng.standard_normal((2500, 70))) * np.logspace(0, -12, 70)[None, :]
+    B = rng.standard_normal((300, 1100)) + 1j * rng.standard_normal((300, 1100))
+    resA = fdsmod.cpqr_batched([A], 1e-8)
+    p_o, R_o = ofds.cpqr(A)
+    k_o = ofds.id_rank(R_o, 1e-8)
+    piv, k, R = resA[0]
+    assert k == k_o and np.array_equal(piv[:k], p_o[:k])
+    assert np.allclose(np.abs(np.diag(R)[:k]), np.abs(np.diag(R_o)[:k]), rtol=1e-10)
+    resB = fdsmod.cpqr_batched([B], 1e-8, kmax=[25], stop_at_tol=False)
+    p_o, R_o = ofds.cpqr(B, kmax=25)
+    piv, k, R = resB[0]
+    assert k == 25 and np.array_equal(piv[:25], p_o[:25])
+    assert np.allclose(np.abs(np.diag(R)[:25]), np.abs(np.diag(R_o)[:25]), rtol=1e-10)
+
+
+def test_lu_batched_is_a_partial_pivoting_lu(fdsmod):
+    """P A = L U to rounding with |L| <= 1 and every pivot the column's
+    largest modulus, for sizes on both sides of the one-workgroup limit
+    (768): the LDS-panel kernels and the multi-workgroup blocked form."""
+    rng = np.random.default_rng(12)
+    sizes = [7, 130, 700, 900, 1300]
+    mats = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in sizes]
+    for A, (LU, piv, info) in zip(mats, fdsmod.lu_batched(mats)):
+        n = A.shape[0]
+        assert info == 0
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
+        PA = A.copy()
+        for k in range(n):
+            assert k <= piv[k] < n
+            PA[[k, piv[k]]] = PA[[piv[k], k]]
+        assert np.linalg.norm(PA - L @ U) <= 1e-13 * n * np.linalg.norm(A)
+        assert np.abs(L).max() <= 1.0 + 1e-12
+    # a zero column is reported at its step
+    Z = rng.standard_normal((900, 900)) + 0j
+    Z[:, 5] = 0.0
+    assert fdsmod.lu_batched([Z])[0][2] == 6

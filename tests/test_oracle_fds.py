@@ -14,7 +14,7 @@ import pytest
 import scipy.linalg as sla
 
 import synthetic as sy
-from oracle import dense, fds
+from oracle import dense, fds, galerkin
 
 
 def test_cpqr_matches_lapack():
@@ -76,3 +76,57 @@ def test_small_validation_case():
     Y = S.solve(F)
     assert S.L == 3
     assert np.linalg.norm(Y - X) / np.linalg.norm(X) < 1e-9
+
+
+# ---------------------------------------------------------------- tree over several curves
+def test_morton_order_visits_quadrants_in_z_order():
+    # corners of a square: Z-order visits (0,0), (1,0), (0,1), (1,1)
+    order = fds.morton_order([(0, 0), (1, 1), (1, 0), (0, 1)])
+    assert list(order) == [0, 2, 3, 1]
+    # nested: the four points of the lower-left quadrant come before any other
+    pts = [(0.9, 0.9), (0.1, 0.1), (0.4, 0.1), (0.1, 0.4), (0.4, 0.4), (0.6, 0.1)]
+    order = list(fds.morton_order(pts))
+    assert order[:4] == [1, 2, 3, 4] and order[-1] == 0
+
+
+def _check_tree(bnd, leaf):
+    L, cells, perm = fds.build_tree(bnd, leaf)
+    assert sorted(perm) == list(range(bnd.n_nodes))
+    assert L == (0 if bnd.n_nodes <= leaf else int(np.ceil(np.log2(bnd.n_nodes / leaf))))
+    # every node numbered position lies in exactly one leaf
+    leaves = fds.level_cells(cells, L)
+    cover = np.zeros(bnd.n_nodes, int)
+    for c in leaves:
+        assert c.hi > c.lo
+        cover[c.lo:c.hi] += 1
+    assert np.all(cover == 1)
+    # curve index of each position of the numbering
+    cur = bnd.curve_of[perm]
+    for lev in range(L):
+        for p in fds.level_cells(cells, lev):
+            a, b = cells[2 * p.index + 1], cells[2 * p.index + 2]
+            assert (a.lo, a.hi, b.lo, b.hi) == (p.lo, a.hi, a.hi, p.hi)
+            curves = np.unique(cur[p.lo:p.hi])
+            whole = all(np.sum(cur == k) == np.sum(cur[p.lo:p.hi] == k) for k in curves)
+            if len(curves) >= 2 and whole:
+                # split at a curve boundary, most balanced among all boundaries
+                bounds = [i for i in range(p.lo + 1, p.hi) if cur[i] != cur[i - 1]]
+                assert a.hi in bounds
+                best = min(abs(2 * (i - p.lo) - (p.hi - p.lo)) for i in bounds)
+                assert abs(2 * (a.hi - p.lo) - (p.hi - p.lo)) == best
+            else:
+                assert len(curves) == 1
+                assert a.hi == p.lo + (p.hi - p.lo) // 2
+    return L, cells, perm
+
+
+def test_tree_over_several_curves():
+    curves = sy.multi_cavity(3, 12, 3000)
+    bnd = galerkin.Boundary(curves)
+    _check_tree(bnd, 64)
+
+
+def test_tree_of_one_curve_is_the_midpoint_tree():
+    bnd = galerkin.Boundary([sy.ellipse(1000, 1.0, 0.5)])
+    L, cells, perm = _check_tree(bnd, 64)
+    assert np.array_equal(perm, np.arange(1000))
