@@ -80,10 +80,12 @@ typedef struct {
   int32_t rank_mode;        /* FDS_RANK_ADAPTIVE (default): every ID by the pivoted QR of its interaction
                                matrix (Sections 7.1, 7.2).  FDS_RANK_LEARNED: the rank predictor pre-sizes a
                                randomized ID (sketch of ceil(k_pred) + oversample rows); its result is kept
-                               when the sketch reveals the rank (taken at tol / 4) and the residual judge
-                               passes (every residual column within tol of the largest column of the
-                               interaction matrix itself), else the cell falls back to the pivoted QR */
-  int32_t oversample;       /* learned form: extra sketch rows; default 8 */
+                               when the sketch reveals the rank (taken at tol / 10, with 4 rows to spare)
+                               and the residual judge passes (every residual column within tol of the
+                               largest column of the interaction matrix itself), else the cell falls back
+                               to the pivoted QR; the predictor abstains for cells whose standardised
+                               inputs lie beyond 4 of its training sigma */
+  int32_t oversample;       /* learned form: extra sketch rows; default 10 */
   uint64_t seed;            /* learned form: seed of the sketches (SplitMix64); default 0x5EED */
   const float* predictor;   /* learned form: host, FDS_MLP_BLOB floats (see fds_mlp_forward); copied */
 } fds_options;
@@ -171,7 +173,8 @@ typedef struct {
   int64_t cells_sketched;
   int64_t cells_fallback_rank;
   int64_t cells_fallback_judge;
-  double predict_seconds;   /* host wall time of the rank predictions (features, inference, copy back) */
+  double predict_seconds;   /* host time spent waiting for the rank predictions (launched ahead of each
+                               level's assembly) */
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);
@@ -188,13 +191,14 @@ int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, i
 
 /* One record per cell of every compressed level, in the order the levels
  * were compressed (leaves first): the predictor's training data.
- * feat: k_T d, k_L d (d = 2 R, R the cell radius used for its proxy circle),
- * level, active DOFs per component, rows of the proxy-plus-near interaction
- * matrix, -log10(tol).  rank: (k_row comp 1, k_col comp 1, k_row comp 2,
+ * feat: log(k_T d), log(k_L d) (d = 2 R, R the cell radius used for its
+ * proxy circle), level (root 0), log(active DOFs per component), log(rows of
+ * the proxy-plus-near interaction matrix), -log10(tol).  rank: (k_row comp 1, k_col comp 1, k_row comp 2,
  * k_col comp 2) at tolerance.  k_pred: the learned form's prediction (-1 in
- * the adaptive form).  fallback: 0 none, 1 rank not revealed by the sketch,
- * 2 judge rejected, 3 not sketched (sketch size outside 1..64 or more than 128
- * columns).  out: host, capacity cap records; n_out receives the count
+ * the adaptive form, or when the predictor abstained).  fallback: 0 none,
+ * 1 rank not revealed by the sketch, 2 judge rejected, 3 not sketched
+ * (predictor abstained, or the sketch would not be smaller than the
+ * interaction matrices).  out: host, capacity cap records; n_out receives the count
  * (records beyond cap are not written). */
 typedef struct {
   int32_t cell, level;
@@ -262,12 +266,14 @@ int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n,
  * s[p] x m[p], entry (i, l) = (+-1) + i (+-1) from bits 0 and 1 of
  * SplitMix64(seed) output number (gid[p] << 44) | (i << 24) | l; pivoted QR
  * of Y (pivot rule of fds_cpqr_batched) to the first
- * |R_jj| <= sketch_tol |R_11| (the learned factorisation uses tol / 4),
+ * |R_jj| <= sketch_tol |R_11| (the learned factorisation uses tol / 10),
  * giving rank[p] and piv (host int32, n[p] entries at pivoff[p], the first
- * rank[p] being the skeleton); revealed[p] = rank[p] < min(s[p], n[p]) or
+ * rank[p] being the skeleton); revealed[p] = rank[p] + 4 <= s[p] or
  * s[p] >= n[p]; ratio[p] = max_j |M(:,j) - M(:,J) W(:,j)| / max_j |M(:,j)|
- * with J, W the ID of rank[p] from the sketch.  1 <= s[p] <= 64,
- * n[p] <= 128.  Host arrays are int64 [np] unless stated.  Synchronous. */
+ * with J, W the ID of rank[p] from the sketch.  1 <= s[p] <= m[p],
+ * n[p] <= 4096 (sketches of up to 64 rows and 128 columns by the LDS
+ * kernel, larger ones by GEMM, as in the learned factorisation).  Host
+ * arrays are int64 [np] unless stated.  Synchronous. */
 int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
                     const int64_t* s, const int64_t* gid, uint64_t seed, double sketch_tol, int32_t* piv,
                     const int64_t* pivoff, int32_t* rank, int32_t* revealed, double* ratio, void* stream);

@@ -7,9 +7,9 @@ Omega an s x m matrix of random entries (+-1 +- i); a column-pivoted QR of
 Y gives the skeleton columns J and the interpolation matrix
 W = [I, R11^{-1} R12] P^T exactly as the ID of Section 7.1 does for M itself;
 its rank is the first j with |R_jj| <= tol_s |R_11| of the sketch's QR
-(tol_s = tol / 4 in the learned factorisation, see SKETCH_TOL_FACTOR).  The
-sketch reveals the rank only if that crossing happens inside it
-(k < min(s, n), or s >= n).  The judge then checks the guarantee the
+(tol_s = tol / 10 in the learned factorisation, see SKETCH_TOL_FACTOR).  The
+sketch reveals the rank only if that crossing happens with a few rows to
+spare (k + 4 <= s), or if s >= n.  The judge then checks the guarantee the
 pivoted QR of M would give: every column of M - M[:, J] W has norm at most
 tol times the largest column norm of M.  A prediction that fails either test
 falls back to the pivoted QR of M.
@@ -20,11 +20,12 @@ and Flood, 2014; the 64-bit finaliser with the golden-ratio increment)
 seeded with ``seed``: bit 0 gives the sign of the real part, bit 1 that of
 the imaginary part.
 
-Rank predictor.  Features of a cell of the upward step: k_T d, k_L d (d the
-cell diameter 2 R, R the radius of the cell's disk), the level, the active
-DOFs per component b / 2, the rows of the proxy-plus-near matrix
-2 n_proxy + (near rows), and -log10(tol); target: the largest of the cell's
-four ID ranks.  Network 6-64-64-64-1 with ReLU, inputs standardised by
+Rank predictor.  Features of a cell of the upward step: log(k_T d),
+log(k_L d) (d the cell diameter 2 R, R the radius of the cell's disk), the
+level (root 0), log of the active DOFs per component b / 2, log of the rows
+of the proxy-plus-near matrix 2 n_proxy + (near rows), and -log10(tol);
+target: the largest of the cell's four ID ranks.  Logarithms keep the
+size-like inputs of different discretisations in one range.  Network 6-64-64-64-1 with ReLU, inputs standardised by
 (mu, sigma), output scaled by y_scale.  Trained by minibatch Adam on the mean
 squared error in units of y_scale.
 """
@@ -73,10 +74,13 @@ def sketch_matrix(seed: int, gid: int, s: int, m: int):
 
 # ---------------------------------------------------------------- randomized ID
 # The sketch's rank is taken at SKETCH_TOL_FACTOR * tol: the sketch's column
-# norms are a random projection of M's, distorted by up to about 2x at these
-# sizes, so a first crossing at tol itself leaves residuals of up to ~3 tol on
-# M; at tol / 4 the judge (at tol, on M) passes with margin.
-SKETCH_TOL_FACTOR = 0.25
+# norms are a random projection of M's, distorted by a factor of a few at
+# these sizes, so a first crossing at tol itself leaves residuals of up to
+# ~3 tol on M (and ~1.2 tol at tol / 4); at tol / 10 the judge (at tol, on M)
+# passes with margin, at about one pivot more than the pivoted QR of M.
+SKETCH_TOL_FACTOR = 0.1
+# A sketch reveals a rank only with this many rows to spare.
+REVEAL_MARGIN = 4
 
 
 def randomized_id(M, s, tol, seed, gid, k_use=None, sketch_tol=None):
@@ -91,8 +95,7 @@ def randomized_id(M, s, tol, seed, gid, k_use=None, sketch_tol=None):
     Y = sketch_matrix(seed, gid, s, m) @ M
     piv, R = ofds.cpqr(Y)
     k = ofds.id_rank(R, tol if sketch_tol is None else sketch_tol)
-    steps = min(s, n)
-    revealed = (k < steps) or (s >= n)
+    revealed = (k + REVEAL_MARGIN <= s) or (s >= n)
     kw = k if k_use is None else int(k_use)
     W = ofds.id_matrix(piv, R, kw, n)
     E = M - M[:, piv[:kw]] @ W
@@ -118,8 +121,8 @@ def best_interpolation_ratio(M, J):
 def cell_features(c, mat, tol, n_proxy, n_near_rows):
     """Predictor inputs of a cell (see module docstring)."""
     d = 2.0 * c.radius
-    return np.array([mat.kT * d, mat.kL * d, float(c.level), len(c.cols) / 2.0,
-                     float(2 * n_proxy + n_near_rows), -math.log10(tol)])
+    return np.array([math.log(mat.kT * d), math.log(mat.kL * d), float(c.level),
+                     math.log(len(c.cols) / 2.0), math.log(float(2 * n_proxy + n_near_rows)), -math.log10(tol)])
 
 
 # ---------------------------------------------------------------- MLP

@@ -88,6 +88,9 @@ def load():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise FdsError(f"{_LIB_PATH} is missing: build it with `python -m paper_2411_18026_amd.build`")
+    # the library works on PyTorch's device memory and streams: let PyTorch
+    # bring in the HIP runtime first so that both share one
+    import torch  # noqa: F401
     L = ctypes.CDLL(_LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.fds_options_default.argtypes = [ctypes.POINTER(_Options)]

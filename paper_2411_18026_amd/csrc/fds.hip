@@ -264,10 +264,15 @@ struct fds_factor_s {
   fds::Workspace ws;
   fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
+  float* pred_host = nullptr;               // learned form: pinned copy of a level's predictions
+  size_t pred_host_n = 0;
+  hipEvent_t pred_ev = nullptr;
   std::vector<fds_rank_record> rank_log;    // per compressed cell: features, ranks, prediction
   std::map<int64_t, hipGraphExec_t> graphs; // captured solve sweeps per (nrhs, kind)
   hipStream_t gstream = nullptr;            // library stream for graph capture and replay
   ~fds_factor_s() {
+    if (pred_host) (void)hipHostFree(pred_host);
+    if (pred_ev) (void)hipEventDestroy(pred_ev);
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (gstream) {
       (void)hipStreamSynchronize(gstream);
@@ -715,8 +720,9 @@ static void adaptive_ids(Factor& F, CellLevel& lv, const std::vector<int>& cells
   pair_and_extend(F, lv, cells, dv, du, rv, ru, MV, MU, dpiv, F.tol);
 }
 
-// Predictor inputs of the cells of a level: k_T d, k_L d (d = 2 R), level,
-// active DOFs per component, rows of the proxy-plus-near matrix, -log10 tol.
+// Predictor inputs of the cells of a level: log(k_T d), log(k_L d) (d = 2 R),
+// level (root 0), log(active DOFs per component), log(rows of the
+// proxy-plus-near matrix), -log10 tol.
 static std::vector<float> cell_features(const Factor& F, int lev, const std::vector<double>& crd,
                                         const std::vector<int>& mv_m) {
   const CellLevel& lv = F.levels[lev];
@@ -724,22 +730,45 @@ static std::vector<float> cell_features(const Factor& F, int lev, const std::vec
   for (int q = 0; q < lv.n; ++q) {
     const double d = 2.0 * crd[3 * q + 2] / F.opt.proxy_ratio;
     float* f = x.data() + (size_t)q * kMlpIn;
-    f[0] = (float)(F.m.kT * d);
-    f[1] = (float)(F.m.kL * d);
+    f[0] = (float)std::log(F.m.kT * d);
+    f[1] = (float)std::log(F.m.kL * d);
     f[2] = (float)lev;
-    f[3] = (float)(0.5 * lv.b[q]);
-    f[4] = (float)mv_m[q];
+    f[3] = (float)std::log(0.5 * lv.b[q]);
+    f[4] = (float)std::log((double)mv_m[q]);
     f[5] = (float)(-std::log10(F.tol));
   }
   return x;
 }
 
+// Learned form: the predictions of a level, launched before the level's
+// interaction matrices are assembled and copied to pinned host memory, so
+// that waiting for them does not wait for the assembly.
+static void launch_predictions(Factor& F, int lev, const std::vector<double>& crd, const std::vector<int>& mv_m) {
+  const int n = F.levels[lev].n;
+  if (F.pred_host_n < (size_t)n) {
+    if (F.pred_host) FDS_HIP(hipHostFree(F.pred_host));
+    F.pred_host = nullptr;
+    F.pred_host_n = 0;
+    FDS_HIP(hipHostMalloc((void**)&F.pred_host, (size_t)n * sizeof(float), hipHostMallocDefault));
+    F.pred_host_n = (size_t)n;
+  }
+  if (!F.pred_ev) FDS_HIP(hipEventCreateWithFlags(&F.pred_ev, hipEventDisableTiming));
+  const std::vector<float> feat = cell_features(F, lev, crd, mv_m);
+  float* dpred = F.ws.get<float>("pred", (size_t)n);
+  launch_mlp_forward(n, F.ws.upload("feat", feat), F.pred.p, dpred, 1, F.stream, kAbstainSigma);
+  FDS_HIP(hipMemcpyAsync(F.pred_host, dpred, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, F.stream));
+  FDS_HIP(hipEventRecord(F.pred_ev, F.stream));
+}
+
 // Learned form: per cell, the predictor's rank pre-sizes a sketch of
 // s = ceil(k_pred) + oversample rows; the IDs of the sketch are accepted
 // when the sketch reveals their rank and the residual judge passes on the
-// interaction matrices themselves.  Returns the cells left to the pivoted QR
-// of their matrices (too large to sketch, rank not revealed, judge failed);
-// srcv / srcu point the accepted cells' interpolation at the sketches.
+// interaction matrices themselves.  Sketches of at most 64 rows and 128
+// columns use the LDS kernels; larger ones draw Omega into a buffer and use
+// the batched GEMM for Y = Omega M and for the judge's residual.  Returns the
+// cells left to the pivoted QR of their matrices (sketch no smaller than the
+// matrix, rank not revealed, judge failed); srcv / srcu point the accepted
+// cells' interpolation at the sketches.
 static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double>& crd, const std::vector<int>& mv_m,
                                     const std::vector<CpqrDesc>& qv, const std::vector<CpqrDesc>& qu, c64* MV,
                                     c64* MU, int* dpiv, std::vector<CpqrDesc>& srcv, std::vector<CpqrDesc>& srcu,
@@ -749,19 +778,19 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
   hipStream_t s = F.stream;
   const int n = lv.n;
   auto th = std::chrono::steady_clock::now();
-  const std::vector<float> feat = cell_features(F, lev, crd, mv_m);
-  float* dpred = ws.get<float>("pred", (size_t)n);
-  launch_mlp_forward(n, ws.upload("feat", feat), F.pred.p, dpred, 1, s);
-  const std::vector<float> pred = download(ws, dpred, (size_t)n);
+  FDS_HIP(hipEventSynchronize(F.pred_ev));
+  const std::vector<float> pred(F.pred_host, F.pred_host + n);
   F.st.predict_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - th).count();
   std::vector<int> plain, sk;
   std::vector<int> sz(n, 0);
   for (int q = 0; q < n; ++q) {
     const float p = pred[q];
-    kpred[q] = std::isfinite(p) ? std::max(0, (int)std::ceil(p)) : kSketchMaxS;
+    // NaN: the predictor abstained (inputs outside its training range)
+    kpred[q] = std::isfinite(p) ? (int)std::min(1e6f, std::max(0.0f, std::ceil(p))) : -1;
     const int ss = kpred[q] + F.opt.oversample;
-    bool ok = ss >= 1 && ss <= kSketchMaxS;
-    for (int c = 0; c < 2; ++c) ok = ok && qv[2 * q + c].n <= kSketchMaxN && qu[2 * q + c].n <= kSketchMaxN;
+    // a sketch pays only when it has fewer rows than every matrix it replaces
+    bool ok = kpred[q] >= 0 && ss >= 1;
+    for (int c = 0; c < 2; ++c) ok = ok && ss < qv[2 * q + c].m && ss < qu[2 * q + c].m;
     if (ok) {
       sz[q] = ss;
       sk.push_back(q);
@@ -771,27 +800,50 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
     }
   }
   if (sk.empty()) return plain;
-  // sketches Y = Omega M of the 4 problems of every sketched cell
+  // the 4 problems of every sketched cell: V comp 0/1 (MV), U comp 0/1 (MU)
   const size_t ns = sk.size();
-  std::vector<SketchDesc> sv(2 * ns), su(2 * ns);
-  std::vector<CpqrDesc> yd(4 * ns);   // V problems, then U problems
-  int64_t ytot = 0;
+  struct Prob {
+    int q, comp;
+    bool isV, big;
+    CpqrDesc m;
+    int s;
+    int64_t y_off;
+  };
+  std::vector<Prob> pr(4 * ns);   // index: V problems 2 ci + comp, then U problems 2 ns + 2 ci + comp
+  std::vector<CpqrDesc> yd(4 * ns);
+  std::vector<SketchDesc> sv, su;
+  std::vector<OmegaDesc> om;
+  std::vector<GemmDesc> gv, gu;
+  int64_t ytot = 0, otot = 0, omax = 0;
   for (size_t ci = 0; ci < ns; ++ci) {
     const int q = sk[ci];
     const int64_t cell = ((int64_t)1 << lev) - 1 + q;
     for (int k = 0; k < 4; ++k) {
       const bool isV = k < 2;
       const int comp = k & 1;
+      const size_t pi = (isV ? 0 : 2 * ns) + 2 * ci + comp;
       const CpqrDesc& m = isV ? qv[2 * q + comp] : qu[2 * q + comp];
-      SketchDesc d{};
-      d.m_off = m.a_off;
-      d.y_off = ytot;
-      d.gid = 4 * cell + k;
-      d.m = m.m;
-      d.n = m.n;
-      d.lda = m.lda;
-      d.s = sz[q];
-      (isV ? sv : su)[2 * ci + comp] = d;
+      Prob P{q, comp, isV, sz[q] > kSketchMaxS || m.n > kSketchMaxN, m, sz[q], ytot};
+      pr[pi] = P;
+      if (!P.big) {
+        (isV ? sv : su).push_back(SketchDesc{m.a_off, ytot, 4 * cell + k, m.m, m.n, m.lda, sz[q]});
+      } else {
+        om.push_back(OmegaDesc{otot, 4 * cell + k, sz[q], m.m});
+        GemmDesc g{};
+        g.a_off = otot;
+        g.b_off = m.a_off;
+        g.c_off = ytot;
+        g.m = sz[q];
+        g.n = m.n;
+        g.k = m.m;
+        g.lda = sz[q];
+        g.ldb = m.lda;
+        g.ldc = sz[q];
+        g.alpha_re = 1.0;
+        (isV ? gv : gu).push_back(g);
+        omax = std::max<int64_t>(omax, (int64_t)sz[q] * m.m);
+        otot += (int64_t)sz[q] * m.m;
+      }
       CpqrDesc y{};
       y.a_off = ytot;
       y.piv_off = m.piv_off;
@@ -801,27 +853,38 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
       y.k_start = 0;
       y.k_end = std::min(y.m, y.n);
       y.stop_at_tol = 1;
-      yd[(isV ? 0 : 2 * ns) + 2 * ci + comp] = y;
+      yd[pi] = y;
       ytot += (int64_t)sz[q] * m.n;
     }
   }
   c64* Y = ws.get<c64>("sketch_Y", (size_t)std::max<int64_t>(ytot, 1));
   launch_sketch(ws.upload("sk_v", sv), (int)sv.size(), MV, Y, F.opt.seed, s);
   launch_sketch(ws.upload("sk_u", su), (int)su.size(), MU, Y, F.opt.seed, s);
+  if (!om.empty()) {
+    c64* O = ws.get<c64>("sketch_O", (size_t)otot);
+    launch_omega(ws.upload("sk_om", om), (int)om.size(), omax, O, F.opt.seed, s);
+    int nmax = 0;
+    for (auto& g : gv) nmax = std::max(nmax, g.n);
+    for (auto& g : gu) nmax = std::max(nmax, g.n);
+    const auto tv = gemm_tiles(gv), tu = gemm_tiles(gu);
+    launch_gemm(ws.upload("sk_gv", gv), ws.upload("sk_tv", tv), (int)tv.size(), nmax, 0, (const c64*)O,
+                (const c64*)MV, Y, 0, s);
+    launch_gemm(ws.upload("sk_gu", gu), ws.upload("sk_tu", tu), (int)tu.size(), nmax, 0, (const c64*)O,
+                (const c64*)MU, Y, 0, s);
+  }
   int* drank = ws.get<int>("sk_rank", 4 * ns);
-  launch_cpqr(ws.upload("sk_cpqr", yd), (int)yd.size(), Y, dpiv, kSketchTolFactor * F.tol, drank, s,
-              check_cpqr_sizes(yd));
+  cpqr_factor(yd, Y, dpiv, kSketchTolFactor * F.tol, drank, ws, "sk_cpqr", s);
   const auto rk = download(ws, drank, 4 * ns);
   // the sketch must reveal every rank: a crossing inside it, or s >= n
   std::vector<int> acc;
+  std::vector<size_t> acc_ci;
   std::vector<CpqrDesc> av, au;
   std::vector<int> rv, ru;
   for (size_t ci = 0; ci < ns; ++ci) {
     bool revealed = true;
     for (int k = 0; k < 4; ++k) {
-      const CpqrDesc& y = yd[(k < 2 ? 0 : 2 * ns) + 2 * ci + (k & 1)];
-      const int r = rk[(k < 2 ? 0 : 2 * ns) + 2 * ci + (k & 1)];
-      revealed = revealed && (r < std::min(y.m, y.n) || y.m >= y.n);
+      const size_t pi = (k < 2 ? 0 : 2 * ns) + 2 * ci + (k & 1);
+      revealed = revealed && (rk[pi] + kRevealMargin <= yd[pi].m || yd[pi].m >= yd[pi].n);
     }
     const int q = sk[ci];
     if (!revealed) {
@@ -829,6 +892,7 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
       continue;
     }
     acc.push_back(q);
+    acc_ci.push_back(ci);
     for (int comp = 0; comp < 2; ++comp) {
       av.push_back(yd[2 * ci + comp]);
       au.push_back(yd[2 * ns + 2 * ci + comp]);
@@ -838,34 +902,94 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
   }
   if (!acc.empty()) {
     pair_and_extend(F, lv, acc, av, au, rv, ru, Y, Y, dpiv, kSketchTolFactor * F.tol);
-    // residual judge on the interaction matrices themselves
+    // residual judge on the interaction matrices themselves; W (k x n) of
+    // every problem first, then the small problems by the LDS kernel and
+    // the large ones by gather + GEMM + column norms
     std::vector<InterpDesc> iw;
     std::vector<JudgeDesc> jv, ju;
-    int64_t wtot = 0;
+    std::vector<ColGatherDesc> ecv, ecu, gcv, gcu;
+    std::vector<GemmDesc> rgv, rgu;
+    std::vector<RatioDesc> rdv, rdu;
+    std::vector<size_t> jv_i, ju_i, rdv_i, rdu_i;   // accepted-problem slots (4 per accepted cell)
+    int64_t wtot = 0, etot = 0, gtot = 0;
+    int ecmax = 0, gcmax = 0, rnmax = 0;
     for (size_t ai = 0; ai < acc.size(); ++ai) {
       const int q = acc[ai];
+      const size_t ci = acc_ci[ai];
       for (int k = 0; k < 4; ++k) {
         const bool isV = k < 2;
         const int comp = k & 1;
+        const size_t slot = 4 * ai + k;
+        const Prob& P = pr[(isV ? 0 : 2 * ns) + 2 * ci + comp];
         const int kk = comp ? lv.k1[q] : lv.k0[q];
         const CpqrDesc& y = isV ? av[2 * ai + comp] : au[2 * ai + comp];
-        const CpqrDesc& m = isV ? qv[2 * q + comp] : qu[2 * q + comp];
-        if (kk > 0) iw.push_back(InterpDesc{y.a_off, y.piv_off, y.n, y.lda, kk, wtot, kk, 0});
-        (isV ? jv : ju).push_back(JudgeDesc{m.a_off, wtot, m.piv_off, m.m, m.n, m.lda, kk});
+        const CpqrDesc& m = P.m;
+        if (kk > 0) iw.push_back(InterpDesc{y.a_off, y.piv_off, y.n, y.lda, kk, wtot, kk, 0, 0});
+        if (!P.big) {
+          (isV ? jv : ju).push_back(JudgeDesc{m.a_off, wtot, m.piv_off, m.m, m.n, m.lda, kk});
+          (isV ? jv_i : ju_i).push_back(slot);
+        } else {
+          (isV ? ecv : ecu).push_back(ColGatherDesc{m.a_off, etot, -1, m.m, m.n, m.lda, m.m});
+          ecmax = std::max(ecmax, m.n);
+          if (kk > 0) {
+            (isV ? gcv : gcu).push_back(ColGatherDesc{m.a_off, gtot, m.piv_off, m.m, kk, m.lda, m.m});
+            gcmax = std::max(gcmax, kk);
+            GemmDesc g{};
+            g.a_off = gtot;
+            g.b_off = wtot;
+            g.c_off = etot;
+            g.m = m.m;
+            g.n = m.n;
+            g.k = kk;
+            g.lda = m.m;
+            g.ldb = kk;
+            g.ldc = m.m;
+            g.alpha_re = -1.0;
+            g.beta_re = 1.0;
+            (isV ? rgv : rgu).push_back(g);
+            rnmax = std::max(rnmax, m.n);
+          }
+          (isV ? rdv : rdu).push_back(RatioDesc{etot, m.a_off, m.m, m.n, m.m, m.lda});
+          (isV ? rdv_i : rdu_i).push_back(slot);
+          etot += (int64_t)m.m * m.n;
+          gtot += (int64_t)m.m * kk;
+        }
         wtot += (int64_t)kk * y.n;
       }
     }
     c64* Wj = ws.get<c64>("judge_W", (size_t)std::max<int64_t>(wtot, 1));
-    double* ratio = ws.get<double>("judge_ratio", jv.size() + ju.size());
-    launch_interp(ws.upload("judge_interp", iw), (int)iw.size(), Y, dpiv, Wj, s);
+    const size_t nj = jv.size() + ju.size() + rdv.size() + rdu.size();
+    double* ratio = ws.get<double>("judge_ratio", nj);
+    launch_interp(ws.upload("judge_interp", iw), (int)iw.size(), Y, dpiv, Wj, s, interp_nmax(iw));
     launch_judge(ws.upload("judge_v", jv), (int)jv.size(), MV, Wj, dpiv, ratio, s);
     launch_judge(ws.upload("judge_u", ju), (int)ju.size(), MU, Wj, dpiv, ratio + jv.size(), s);
-    const auto rt = download(ws, ratio, jv.size() + ju.size());
+    if (!rdv.empty() || !rdu.empty()) {
+      c64* E = ws.get<c64>("judge_E", (size_t)std::max<int64_t>(etot, 1));
+      c64* G = ws.get<c64>("judge_G", (size_t)std::max<int64_t>(gtot, 1));
+      launch_gather_cols(ws.upload("jg_ecv", ecv), (int)ecv.size(), ecmax, MV, dpiv, E, s);
+      launch_gather_cols(ws.upload("jg_ecu", ecu), (int)ecu.size(), ecmax, MU, dpiv, E, s);
+      launch_gather_cols(ws.upload("jg_gcv", gcv), (int)gcv.size(), gcmax, MV, dpiv, G, s);
+      launch_gather_cols(ws.upload("jg_gcu", gcu), (int)gcu.size(), gcmax, MU, dpiv, G, s);
+      std::vector<GemmDesc> rg(rgv);
+      rg.insert(rg.end(), rgu.begin(), rgu.end());
+      const auto rt = gemm_tiles(rg);
+      launch_gemm(ws.upload("jg_g", rg), ws.upload("jg_t", rt), (int)rt.size(), rnmax, 0, (const c64*)G,
+                  (const c64*)Wj, E, 0, s);
+      const size_t o = jv.size() + ju.size();
+      launch_ratio(ws.upload("jg_rv", rdv), (int)rdv.size(), E, MV, ratio + o, s);
+      launch_ratio(ws.upload("jg_ru", rdu), (int)rdu.size(), E, MU, ratio + o + rdv.size(), s);
+    }
+    const auto rt = download(ws, ratio, nj);
+    std::vector<double> slot_ratio(4 * acc.size(), 0.0);
+    size_t o = 0;
+    for (size_t i = 0; i < jv_i.size(); ++i) slot_ratio[jv_i[i]] = rt[o++];
+    for (size_t i = 0; i < ju_i.size(); ++i) slot_ratio[ju_i[i]] = rt[o++];
+    for (size_t i = 0; i < rdv_i.size(); ++i) slot_ratio[rdv_i[i]] = rt[o++];
+    for (size_t i = 0; i < rdu_i.size(); ++i) slot_ratio[rdu_i[i]] = rt[o++];
     for (size_t ai = 0; ai < acc.size(); ++ai) {
       const int q = acc[ai];
       bool pass = true;
-      for (int comp = 0; comp < 2; ++comp)
-        pass = pass && rt[2 * ai + comp] <= F.tol && rt[jv.size() + 2 * ai + comp] <= F.tol;
+      for (int k = 0; k < 4; ++k) pass = pass && slot_ratio[4 * ai + k] <= F.tol;
       if (!pass) {
         fallback[q] = 2;
         continue;
@@ -974,6 +1098,7 @@ static void compress_level(Factor& F, int lev) {
     mu_off[q] = mu_tot;
     mu_tot += (int64_t)mu_m[q] * lv.b[q];
   }
+  if (F.opt.rank_mode == FDS_RANK_LEARNED) launch_predictions(F, lev, crd, mv_m);
   auto ht1 = std::make_unique<HostTimer>(1);
   c64* MV = ws.get<c64>("MV", (size_t)mv_tot);
   c64* MU = ws.get<c64>("MU", (size_t)mu_tot);
@@ -1114,12 +1239,12 @@ static void compress_level(Factor& F, int lev) {
                                             lv.x_off[q] + coff + (int64_t)roff * b, b, 1, solved});
     }
   }
-  launch_interp(ws.upload("interp_v", ivm), (int)ivm.size(), MV, dpiv, lv.V.p, s);
-  launch_interp(ws.upload("interp_u", ium), (int)ium.size(), MU, dpiv, lv.X.p, s);
+  launch_interp(ws.upload("interp_v", ivm), (int)ivm.size(), MV, dpiv, lv.V.p, s, interp_nmax(ivm));
+  launch_interp(ws.upload("interp_u", ium), (int)ium.size(), MU, dpiv, lv.X.p, s, interp_nmax(ium));
   if (!ivy.empty() || !iuy.empty()) {
     c64* Y = ws.get<c64>("sketch_Y", 1);
-    launch_interp(ws.upload("interp_vy", ivy), (int)ivy.size(), Y, dpiv, lv.V.p, s);
-    launch_interp(ws.upload("interp_uy", iuy), (int)iuy.size(), Y, dpiv, lv.X.p, s);
+    launch_interp(ws.upload("interp_vy", ivy), (int)ivy.size(), Y, dpiv, lv.V.p, s, interp_nmax(ivy));
+    launch_interp(ws.upload("interp_uy", iuy), (int)iuy.size(), Y, dpiv, lv.X.p, s, interp_nmax(iuy));
   }
   span_end(F);
 
@@ -1669,7 +1794,7 @@ int fds_options_default(fds_options* o) {
   o->ir_rtol = 1e-8;
   o->ir_dtol = 1e-6;
   o->rank_mode = FDS_RANK_ADAPTIVE;
-  o->oversample = 8;
+  o->oversample = 10;
   o->seed = 0x5EED;
   o->predictor = nullptr;
   return FDS_OK;
@@ -1997,47 +2122,120 @@ int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int6
     return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
-    std::vector<SketchDesc> sd(np);
+    Workspace ws(s);
+    const c64* M = (const c64*)a;
+    // sketches: the LDS kernel for s <= 64 and n <= 128, Omega + GEMM beyond
+    std::vector<SketchDesc> sd;
+    std::vector<OmegaDesc> od;
+    std::vector<GemmDesc> gd;
     std::vector<CpqrDesc> yd(np);
-    int64_t ytot = 0, ptot = 0;
+    std::vector<char> big(np);
+    int64_t ytot = 0, otot = 0, omax = 0, ptot = 0;
+    int gnmax = 0;
     for (int i = 0; i < np; ++i) {
-      if (m[i] < 1 || n[i] < 1 || n[i] > kSketchMaxN || sz[i] < 1 || sz[i] > kSketchMaxS || m[i] > 2048)
-        return FDS_EINVAL;
-      sd[i] = SketchDesc{off[i], ytot, gid[i], (int)m[i], (int)n[i], (int)m[i], (int)sz[i]};
+      if (m[i] < 1 || n[i] < 1 || n[i] > 4096 || sz[i] < 1 || sz[i] > m[i]) return FDS_EINVAL;
+      big[i] = sz[i] > kSketchMaxS || n[i] > kSketchMaxN;
+      if (!big[i]) {
+        sd.push_back(SketchDesc{off[i], ytot, gid[i], (int)m[i], (int)n[i], (int)m[i], (int)sz[i]});
+      } else {
+        od.push_back(OmegaDesc{otot, gid[i], (int)sz[i], (int)m[i]});
+        GemmDesc g{};
+        g.a_off = otot;
+        g.b_off = off[i];
+        g.c_off = ytot;
+        g.m = (int)sz[i];
+        g.n = (int)n[i];
+        g.k = (int)m[i];
+        g.lda = (int)sz[i];
+        g.ldb = (int)m[i];
+        g.ldc = (int)sz[i];
+        g.alpha_re = 1.0;
+        gd.push_back(g);
+        gnmax = std::max(gnmax, (int)n[i]);
+        omax = std::max<int64_t>(omax, sz[i] * m[i]);
+        otot += sz[i] * m[i];
+      }
       yd[i] = CpqrDesc{ytot, pivoff[i], (int)sz[i], (int)n[i], (int)sz[i], 0, (int)std::min(sz[i], n[i]), 1};
       ytot += sz[i] * n[i];
       ptot = std::max(ptot, pivoff[i] + n[i]);
     }
-    DevBuf<SketchDesc> dsd(sd);
-    DevBuf<CpqrDesc> dyd(yd);
-    DevBuf<c64> Y((size_t)ytot);
-    DevBuf<int> dpiv((size_t)ptot), drank((size_t)np);
-    launch_sketch(dsd.p, np, (const c64*)a, Y.p, seed, s);
-    launch_cpqr(dyd.p, np, Y.p, dpiv.p, tol, drank.p, s, check_cpqr_sizes(yd));
-    std::vector<int> hr(np);
-    FDS_HIP(hipMemcpyAsync(hr.data(), drank.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
-    FDS_HIP(hipStreamSynchronize(s));
+    c64* Y = ws.get<c64>("Y", (size_t)ytot);
+    int* dpiv = ws.get<int>("piv", (size_t)ptot);
+    int* drank = ws.get<int>("rank", (size_t)np);
+    launch_sketch(ws.upload("sd", sd), (int)sd.size(), M, Y, seed, s);
+    if (!od.empty()) {
+      c64* O = ws.get<c64>("O", (size_t)otot);
+      launch_omega(ws.upload("od", od), (int)od.size(), omax, O, seed, s);
+      const auto t = gemm_tiles(gd);
+      launch_gemm(ws.upload("gd", gd), ws.upload("gt", t), (int)t.size(), gnmax, 0, (const c64*)O, M, Y, 0, s);
+    }
+    cpqr_factor(yd, Y, dpiv, tol, drank, ws, "qr", s);
+    const std::vector<int> hr = download(ws, drank, (size_t)np);
+    // judge: W from the sketch, then the LDS kernel or gather + GEMM + norms
     std::vector<InterpDesc> iw;
-    std::vector<JudgeDesc> jd(np);
-    int64_t wtot = 0;
+    std::vector<JudgeDesc> jd;
+    std::vector<int> jd_i, rd_i;
+    std::vector<ColGatherDesc> ec, gc;
+    std::vector<GemmDesc> rg;
+    std::vector<RatioDesc> rd;
+    int64_t wtot = 0, etot = 0, gtot = 0;
+    int ecmax = 0, gcmax = 0, rnmax = 0;
     for (int i = 0; i < np; ++i) {
       const int k = hr[i];
-      if (k > 0) iw.push_back(InterpDesc{yd[i].a_off, pivoff[i], (int)n[i], (int)sz[i], k, wtot, k, 0});
-      jd[i] = JudgeDesc{off[i], wtot, pivoff[i], (int)m[i], (int)n[i], (int)m[i], k};
+      if (k > 0) iw.push_back(InterpDesc{yd[i].a_off, pivoff[i], (int)n[i], (int)sz[i], k, wtot, k, 0, 0});
+      if (!big[i]) {
+        jd.push_back(JudgeDesc{off[i], wtot, pivoff[i], (int)m[i], (int)n[i], (int)m[i], k});
+        jd_i.push_back(i);
+      } else {
+        ec.push_back(ColGatherDesc{off[i], etot, -1, (int)m[i], (int)n[i], (int)m[i], (int)m[i]});
+        ecmax = std::max(ecmax, (int)n[i]);
+        if (k > 0) {
+          gc.push_back(ColGatherDesc{off[i], gtot, pivoff[i], (int)m[i], k, (int)m[i], (int)m[i]});
+          gcmax = std::max(gcmax, k);
+          GemmDesc g{};
+          g.a_off = gtot;
+          g.b_off = wtot;
+          g.c_off = etot;
+          g.m = (int)m[i];
+          g.n = (int)n[i];
+          g.k = k;
+          g.lda = (int)m[i];
+          g.ldb = k;
+          g.ldc = (int)m[i];
+          g.alpha_re = -1.0;
+          g.beta_re = 1.0;
+          rg.push_back(g);
+          rnmax = std::max(rnmax, (int)n[i]);
+        }
+        rd.push_back(RatioDesc{etot, off[i], (int)m[i], (int)n[i], (int)m[i], (int)m[i]});
+        rd_i.push_back(i);
+        etot += m[i] * n[i];
+        gtot += m[i] * k;
+      }
       wtot += (int64_t)k * n[i];
     }
-    DevBuf<InterpDesc> diw(iw);
-    DevBuf<JudgeDesc> djd(jd);
-    DevBuf<c64> W((size_t)std::max<int64_t>(wtot, 1));
-    DevBuf<double> dratio((size_t)np);
-    launch_interp(diw.p, (int)iw.size(), Y.p, dpiv.p, W.p, s);
-    launch_judge(djd.p, np, (const c64*)a, W.p, dpiv.p, dratio.p, s);
-    FDS_HIP(hipMemcpyAsync(ratio, dratio.p, np * sizeof(double), hipMemcpyDeviceToHost, s));
-    FDS_HIP(hipMemcpyAsync(piv, dpiv.p, ptot * sizeof(int), hipMemcpyDeviceToHost, s));
+    c64* W = ws.get<c64>("W", (size_t)std::max<int64_t>(wtot, 1));
+    double* dratio = ws.get<double>("ratio", (size_t)np);
+    launch_interp(ws.upload("iw", iw), (int)iw.size(), Y, dpiv, W, s, interp_nmax(iw));
+    launch_judge(ws.upload("jd", jd), (int)jd.size(), M, W, dpiv, dratio, s);
+    if (!rd.empty()) {
+      c64* E = ws.get<c64>("E", (size_t)etot);
+      c64* G = ws.get<c64>("G", (size_t)std::max<int64_t>(gtot, 1));
+      launch_gather_cols(ws.upload("ec", ec), (int)ec.size(), ecmax, M, dpiv, E, s);
+      launch_gather_cols(ws.upload("gc", gc), (int)gc.size(), gcmax, M, dpiv, G, s);
+      const auto t = gemm_tiles(rg);
+      launch_gemm(ws.upload("rg", rg), ws.upload("rt", t), (int)t.size(), rnmax, 0, (const c64*)G, (const c64*)W,
+                  E, 0, s);
+      launch_ratio(ws.upload("rd", rd), (int)rd.size(), E, M, dratio + jd.size(), s);
+    }
+    const std::vector<double> hratio = download(ws, dratio, (size_t)np);
+    FDS_HIP(hipMemcpyAsync(piv, dpiv, ptot * sizeof(int), hipMemcpyDeviceToHost, s));
     FDS_HIP(hipStreamSynchronize(s));
+    for (size_t t = 0; t < jd_i.size(); ++t) ratio[jd_i[t]] = hratio[t];
+    for (size_t t = 0; t < rd_i.size(); ++t) ratio[rd_i[t]] = hratio[jd_i.size() + t];
     for (int i = 0; i < np; ++i) {
       rank[i] = hr[i];
-      revealed[i] = (hr[i] < std::min(sz[i], n[i]) || sz[i] >= n[i]) ? 1 : 0;
+      revealed[i] = (hr[i] + kRevealMargin <= sz[i] || sz[i] >= n[i]) ? 1 : 0;
     }
     return FDS_OK;
   } catch (const std::exception& e) {

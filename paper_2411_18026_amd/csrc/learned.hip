@@ -158,6 +158,62 @@ __global__ void __launch_bounds__(kLB) k_judge(const JudgeDesc* __restrict__ des
   }
 }
 
+// ------------------------------------------------------------------ large sketches
+__global__ void k_omega(const OmegaDesc* __restrict__ descs, c64* __restrict__ obase, uint64_t seed) {
+  const OmegaDesc d = descs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d.s * d.m) return;
+  const int i = (int)(e % d.s), l = (int)(e / d.s);
+  const uint64_t z = splitmix64(seed, ((uint64_t)d.gid << 44) | ((uint64_t)i << 24) | (uint64_t)l);
+  obase[d.o_off + e] = cmk((z & 1u) ? -1.0 : 1.0, (z & 2u) ? -1.0 : 1.0);
+}
+
+__global__ void k_gather_cols(const ColGatherDesc* __restrict__ descs, const c64* __restrict__ src,
+                              const int* __restrict__ idx, c64* __restrict__ dst) {
+  const ColGatherDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.ncol) return;
+  const int sc = d.idx_off >= 0 ? idx[d.idx_off + c] : c;
+  const c64* from = src + d.src_off + (int64_t)sc * d.lds;
+  c64* to = dst + d.dst_off + (int64_t)c * d.ldd;
+  for (int i = threadIdx.x; i < d.m; i += blockDim.x) to[i] = from[i];
+}
+
+__global__ void __launch_bounds__(kLB) k_ratio(const RatioDesc* __restrict__ descs, const c64* __restrict__ ebase,
+                                               const c64* __restrict__ mbase, double* __restrict__ ratio) {
+  __shared__ double se[kLB / 64], sm[kLB / 64];
+  const RatioDesc d = descs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double me = 0.0, mm = 0.0;
+  for (int c = w; c < d.n; c += kLB / 64) {
+    const c64* e = ebase + d.e_off + (int64_t)c * d.lde;
+    const c64* m = mbase + d.m_off + (int64_t)c * d.ldm;
+    double a = 0.0, b = 0.0;
+    for (int i = lane; i < d.m; i += 64) {
+      a += abs2(e[i]);
+      b += abs2(m[i]);
+    }
+    a = wsum_d(a);
+    b = wsum_d(b);
+    me = fmax(me, a);
+    mm = fmax(mm, b);
+  }
+  if (lane == 0) {
+    se[w] = me;
+    sm[w] = mm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kLB / 64; ++k) {
+      me = fmax(se[0], se[k]);
+      se[0] = me;
+      mm = fmax(sm[0], sm[k]);
+      sm[0] = mm;
+    }
+    ratio[blockIdx.x] = sm[0] > 0.0 ? sqrt(se[0] / sm[0]) : 0.0;
+  }
+}
+
 // ------------------------------------------------------------------ MLP
 constexpr int oW1 = 0, ob1 = oW1 + kMlpH * kMlpIn, oW2 = ob1 + kMlpH, ob2 = oW2 + kMlpH * kMlpH,
               oW3 = ob2 + kMlpH, ob3 = oW3 + kMlpH * kMlpH, ow4 = ob3 + kMlpH, ob4 = ow4 + kMlpH,
@@ -234,16 +290,20 @@ __device__ inline MlpAct mlp_fwd(const MlpLds& L, const float* __restrict__ x, b
   return a;
 }
 
-// predictions y_scale * out, one wavefront per sample
+// predictions y_scale * out, one wavefront per sample; with abstain > 0 a
+// sample with a standardised input beyond +-abstain gets NaN (no prediction)
 __global__ void __launch_bounds__(kLB) k_mlp_forward(int64_t n, const float* __restrict__ x,
                                                      const float* __restrict__ blob, float* __restrict__ out,
-                                                     int bf16) {
+                                                     int bf16, float abstain) {
   __shared__ MlpLds L;
   mlp_load(L, blob, bf16 != 0);
   const int64_t nw = (int64_t)gridDim.x * (kLB / 64);
   for (int64_t smp = (int64_t)blockIdx.x * (kLB / 64) + (threadIdx.x >> 6); smp < n; smp += nw) {
     const MlpAct a = mlp_fwd(L, x + smp * kMlpIn, bf16 != 0);
-    if ((threadIdx.x & 63) == 0) out[smp] = L.ys * a.out;
+    bool far = false;
+    if (abstain > 0.0f)
+      for (int c = 0; c < kMlpIn; ++c) far = far || fabsf((x[smp * kMlpIn + c] - L.mu[c]) / L.sig[c]) > abstain;
+    if ((threadIdx.x & 63) == 0) out[smp] = far ? __int_as_float(0x7fc00000) : L.ys * a.out;
   }
 }
 
@@ -349,10 +409,30 @@ void launch_judge(const JudgeDesc* d, int n, const c64* mbase, const c64* wbase,
   FDS_HIP(hipGetLastError());
 }
 
-void launch_mlp_forward(int64_t n, const float* x, const float* blob, float* out, int bf16, hipStream_t s) {
+void launch_omega(const OmegaDesc* d, int n, int64_t max_elems, c64* obase, uint64_t seed, hipStream_t s) {
+  if (n == 0 || max_elems == 0) return;
+  k_omega<<<dim3((unsigned)((max_elems + 255) / 256), (unsigned)n), 256, 0, s>>>(d, obase, seed);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_gather_cols(const ColGatherDesc* d, int n, int max_cols, const c64* src, const int* idx, c64* dst,
+                        hipStream_t s) {
+  if (n == 0 || max_cols == 0) return;
+  k_gather_cols<<<dim3((unsigned)max_cols, (unsigned)n), 256, 0, s>>>(d, src, idx, dst);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_ratio(const RatioDesc* d, int n, const c64* ebase, const c64* mbase, double* ratio, hipStream_t s) {
+  if (n == 0) return;
+  k_ratio<<<n, kLB, 0, s>>>(d, ebase, mbase, ratio);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_mlp_forward(int64_t n, const float* x, const float* blob, float* out, int bf16, hipStream_t s,
+                        float abstain) {
   if (n == 0) return;
   const int64_t blocks = std::min<int64_t>((n + 3) / 4, 1024);
-  k_mlp_forward<<<(unsigned)blocks, kLB, 0, s>>>(n, x, blob, out, bf16);
+  k_mlp_forward<<<(unsigned)blocks, kLB, 0, s>>>(n, x, blob, out, bf16, abstain);
   FDS_HIP(hipGetLastError());
 }
 

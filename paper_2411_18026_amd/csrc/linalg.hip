@@ -552,7 +552,7 @@ __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ desc
 constexpr int kQrMaxM = 2048;    // rows with the Householder vector in LDS
 constexpr int kQrMaxN = 1024;
 constexpr int kQrMaxNTall = 4096;
-constexpr int64_t kQrwMinElems = 1 << 18;   // problems this large use the multi-workgroup QR
+constexpr int64_t kQrwMinElems = 1 << 16;   // problems this large use the multi-workgroup QR
 
 // TALL = false: the Householder vector is staged in LDS (m <= kQrMaxM,
 // n <= kQrMaxN).  TALL = true: any m, n <= kQrMaxNTall; the vector is read
@@ -842,18 +842,68 @@ __global__ void __launch_bounds__(kBlk) k_qrw_pivot(const CpqrDesc* __restrict__
   }
 }
 
+// NR > 0: the workgroup takes the chunk's columns one at a time, rows
+// j..m-1 held in NR registers per thread (m - j <= 256 NR), so each column is
+// read once; NR = 0: one wavefront per column, two passes over memory.
+template <int NR>
 __global__ void __launch_bounds__(kBlk) k_qrw_update(const CpqrDesc* __restrict__ descs, int j,
                                                      c64* __restrict__ base, double* __restrict__ nrm,
                                                      const QrwState* __restrict__ st) {
+  __shared__ double red[3][kBlk / 64];
   const CpqrDesc d = descs[blockIdx.y];
   const QrwState q = st[blockIdx.y];
   if (j < d.k_start || q.stop) return;
   c64* A = base + d.a_off;
   double* N = nrm + d.piv_off;
   const int m = d.m, lda = d.lda;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const c64* v = A + (int64_t)j * lda;
   const int c_lo = j + 1 + (int)blockIdx.x * kQrwCols, c_hi = min(d.n, c_lo + kQrwCols);
+  if (NR > 0 && m - j <= kBlk * NR) {
+    c64 vr[NR > 0 ? NR : 1];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = j + tid + kBlk * r;
+      vr[r] = i < m ? (i == j ? q.vtop : v[i]) : cmk(0.0, 0.0);
+    }
+    for (int c = c_lo; c < c_hi; ++c) {
+      c64* col = A + (int64_t)c * lda;
+      c64 a[NR > 0 ? NR : 1];
+      double wr = 0.0, wi = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int i = j + tid + kBlk * r;
+        a[r] = i < m ? col[i] : cmk(0.0, 0.0);
+        wr += vr[r].re * a[r].re + vr[r].im * a[r].im;
+        wi += vr[r].re * a[r].im - vr[r].im * a[r].re;
+      }
+      wr = wsum(wr);
+      wi = wsum(wi);
+      if (lane == 0) {
+        red[0][wid] = wr;
+        red[1][wid] = wi;
+      }
+      __syncthreads();
+      wr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      wi = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+      const c64 w = cmk(q.tau * wr, q.tau * wi);
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int i = j + tid + kBlk * r;
+        if (i < m) {
+          const c64 b = a[r] - vr[r] * w;
+          col[i] = b;
+          if (i > j) s += abs2(b);
+        }
+      }
+      s = wsum(s);
+      if (lane == 0) red[2][wid] = s;
+      __syncthreads();
+      if (tid == 0) N[c] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    }
+    return;
+  }
   for (int c = c_lo + wid; c < c_hi; c += kBlk / 64) {
     c64* col = A + (int64_t)c * lda;
     double wr = 0.0, wi = 0.0;
@@ -883,15 +933,21 @@ __global__ void k_qrw_rank(int n, const QrwState* __restrict__ st, const int* __
 
 // W = [I, R1^{-1} R2] P^T: solve R1 T = R2 in place (unless already solved),
 // then write W or W^T.
+// Grid: (problem, chunk of kInterpCols columns of W).
+constexpr int kInterpCols = 64;
+
 __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ descs, c64* __restrict__ abase,
                                                  const int* __restrict__ piv, c64* __restrict__ dbase) {
   const InterpDesc d = descs[blockIdx.x];
+  const int c_lo = blockIdx.y * kInterpCols;
+  if (c_lo >= d.n) return;
+  const int c_hi = min(d.n, c_lo + kInterpCols);
   c64* A = abase + d.a_off;
   const int* P = piv + d.piv_off;
   c64* D = dbase + d.d_off;
-  const int n = d.n, lda = d.lda, k = d.k;
+  const int lda = d.lda, k = d.k;
   const int tid = threadIdx.x;
-  for (int c = k + tid; c < n && !d.solved; c += kBlk) {
+  for (int c = max(k, c_lo) + tid; c < c_hi && !d.solved; c += kBlk) {
     c64* col = A + (int64_t)c * lda;
     for (int i = k - 1; i >= 0; --i) {
       c64 s = col[i];
@@ -900,8 +956,8 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
     }
   }
   __syncthreads();
-  for (int t = tid; t < k * n; t += kBlk) {
-    const int r = t % k, c = t / k;     // W(r, P[c])
+  for (int t = tid; t < k * (c_hi - c_lo); t += kBlk) {
+    const int r = t % k, c = c_lo + t / k;     // W(r, P[c])
     c64 val;
     if (c < k)
       val = (r == c) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
@@ -1017,12 +1073,13 @@ template <typename T>
 void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Workspace& ws, const std::string& tag,
                hipStream_t s) {
   if (d.empty()) return;
-  // matrices whose 4-column LDS panel fits go to the one-workgroup kernels
+  // matrices whose 8-column LDS panel fits go to the one-workgroup kernels;
+  // larger ones are few per level and get the multi-workgroup form
   std::vector<LUDesc> small, big;
   std::vector<int> small_i, big_i;
   int nsmall = 0, nbig = 0;
   for (int i = 0; i < (int)d.size(); ++i) {
-    if ((size_t)d[i].n * sizeof(T) * 4 <= 49152) {
+    if ((size_t)d[i].n * sizeof(T) * 8 <= 49152) {
       small.push_back(d[i]);
       small_i.push_back(i);
       nsmall = std::max(nsmall, d[i].n);
@@ -1167,11 +1224,12 @@ void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol
         (int64_t)one.size(), ws.upload(tag + "_s1", src), ws.upload(tag + "_t1", dst), r1, rank);
     FDS_HIP(hipGetLastError());
   }
-  int nmax = 0, j0 = INT32_MAX, j1 = 0;
+  int nmax = 0, mmax = 0, j0 = INT32_MAX, j1 = 0;
   int64_t ntot = 0;
   for (const CpqrDesc& x : wide) {
     if (x.n > kQrMaxNTall) throw Error(1, "cpqr: more than 4096 columns");
     nmax = std::max(nmax, x.n);
+    mmax = std::max(mmax, x.m);
     j0 = std::min(j0, x.k_start);
     j1 = std::max(j1, std::min(x.k_end, std::min(x.m, x.n)));
     ntot = std::max<int64_t>(ntot, x.piv_off + x.n);
@@ -1189,7 +1247,10 @@ void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol
     if (j < j1) {
       const unsigned ch = (unsigned)((nmax - j - 1 + kQrwCols - 1) / kQrwCols);
       if (ch > 0) {
-        k_qrw_update<<<dim3(ch, (unsigned)wide.size()), kBlk, 0, s>>>(dw, j, base, nrm, stt);
+        if (mmax - j <= kBlk * 12)
+          k_qrw_update<12><<<dim3(ch, (unsigned)wide.size()), kBlk, 0, s>>>(dw, j, base, nrm, stt);
+        else
+          k_qrw_update<0><<<dim3(ch, (unsigned)wide.size()), kBlk, 0, s>>>(dw, j, base, nrm, stt);
         FDS_HIP(hipGetLastError());
       }
     }
@@ -1216,10 +1277,17 @@ void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int*
   FDS_HIP(hipGetLastError());
 }
 
-void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s) {
+void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s, int nmax) {
   if (n == 0) return;
-  k_interp<<<n, kBlk, 0, s>>>(d, abase, piv, dbase);
+  k_interp<<<dim3((unsigned)n, (unsigned)((std::max(nmax, 1) + kInterpCols - 1) / kInterpCols)), kBlk, 0, s>>>(
+      d, abase, piv, dbase);
   FDS_HIP(hipGetLastError());
+}
+
+int interp_nmax(const std::vector<InterpDesc>& d) {
+  int m = 0;
+  for (auto& x : d) m = std::max(m, x.n);
+  return m;
 }
 
 std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d) {

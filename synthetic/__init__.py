@@ -124,3 +124,29 @@ def config_scale(nrhs: int = 180):
     leaf 64 nodes, ID tolerance 1e-8, plane P-waves at 0, 2, ..., 358 degrees."""
     return dict(curves=[ellipse(131072, 1.0, 0.5)], lam=2.0, mu=1.0, rho=1.0, omega=4.0,
                 tol=1e-8, leaf=64, kinds=[0] * nrhs, angles=list(plane_wave_angles(nrhs)))
+
+
+def config_batching(nrhs: int = 180):
+    """Uneven-leaf case: 64 cavities (seed 3) in [-20, 20]^2, 65536 nodes,
+    lambda=2, mu=1, rho=1, omega=2 (k_T = 2), leaf 64 nodes on average, ID
+    tolerance 1e-8, plane waves at 0, 2, ..., 358 degrees alternating P
+    (even index) and S (odd index)."""
+    return dict(curves=multi_cavity(3, 64, 65536), lam=2.0, mu=1.0, rho=1.0, omega=2.0, tol=1e-8, leaf=64,
+                kinds=[k % 2 for k in range(nrhs)], angles=list(plane_wave_angles(nrhs)))
+
+
+def training_geometry(i: int, nodes: int = 16384):
+    """Training geometry i of the rank predictor: seed 1000 + i, between 8
+    and 40 cavities in [-20, 20]^2 with ``nodes`` nodes in total, and k_T
+    uniform in [1, 10] (omega = k_T for mu = rho = 1).  Returns (curves, k_T)."""
+    rng = np.random.default_rng(1000 + i)
+    n_cav = int(rng.integers(8, 41))
+    k_t = float(rng.uniform(1.0, 10.0))
+    return multi_cavity(1000 + i, n_cav, nodes), k_t
+
+
+def config_learned_eval():
+    """Evaluation case of the rank predictor: 128 cavities (seed 5), 131072
+    nodes (262144 complex unknowns), k_T = 8, lambda=2, mu=1, rho=1, leaf 64,
+    ID tolerance 1e-8."""
+    return dict(curves=multi_cavity(5, 128, 131072), lam=2.0, mu=1.0, rho=1.0, omega=8.0, tol=1e-8, leaf=64)

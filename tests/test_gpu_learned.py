@@ -60,6 +60,22 @@ def test_randomized_id_matches_oracle(fdsmod):
     assert all(r[3] <= 1e-8 for i, r in enumerate(res) if i != 3)
 
 
+def test_large_randomized_id_matches_oracle(fdsmod):
+    """Sketches beyond the LDS kernel (more than 64 rows or 128 columns) go
+    through Omega + GEMM and the GEMM residual judge."""
+    rng = np.random.default_rng(13)
+    cases = [(700, 200, 90, 110), (900, 150, 60, 72), (400, 300, 140, 120)]
+    mats = [_gapped(m, n, k, rng) for m, n, k, _ in cases]
+    sizes = [s for *_, s in cases]
+    res = fdsmod.rid_batched(mats, sizes, 1e-8, seed=77, gids=[9, 10, 11])
+    for M, s, g, (piv, k, rev, ratio), case in zip(mats, sizes, [9, 10, 11], res, cases):
+        o = ol.randomized_id(M, s, 1e-8, 77, g)
+        assert k == o["rank"] and rev == o["revealed"], case
+        assert np.array_equal(piv[:k], o["piv"][:k]), case
+        assert abs(ratio - o["ratio"]) <= 1e-6 * o["ratio"] + 1e-13, case
+    assert res[0][2] and res[1][2] and not res[2][2]
+
+
 def _rand_blob(seed, scale=0.3):
     rng = np.random.default_rng(seed)
     b = ol.init_blob(seed, rng.standard_normal(6), rng.uniform(0.5, 2, 6), 24.0)
@@ -118,10 +134,11 @@ def test_mlp_init_and_training_match_oracle(fdsmod):
 
 
 def _const_blob(value, y_scale=64.0):
-    """A predictor whose output is ``value`` for every cell."""
+    """A predictor whose output is ``value`` for every cell (wide sigma: it
+    never abstains)."""
     b = np.zeros(ol.N_BLOB, np.float32)
     b[ol.N_PARAM - 1] = value / y_scale      # b4
-    b[ol.N_PARAM + 6:ol.N_PARAM + 12] = 1.0  # sigma
+    b[ol.N_PARAM + 6:ol.N_PARAM + 12] = 1e3  # sigma
     b[-1] = y_scale
     return b
 
@@ -138,6 +155,17 @@ def test_undersized_sketches_fall_back_to_the_adaptive_factor(fdsmod):
     assert np.array_equal(Fa.ranks(), Fl.ranks())
     rhs = Fa.rhs_plane([0, 1], [0.3, 2.0])
     assert torch.equal(Fa.solve(rhs), Fl.solve(rhs))
+
+
+def test_predictor_abstains_outside_its_training_range(fdsmod):
+    curves = [sy.ellipse(300, 1.0, 0.5)]
+    b = _const_blob(30.0)
+    b[ol.N_PARAM + 6:ol.N_PARAM + 12] = 1e-3   # every input far from mu in sigma units
+    Fl = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32, predictor=b)
+    log = Fl.rank_log()
+    assert np.all(log["k_pred"] == -1) and np.all(log["fallback"] == 3)
+    Fa = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    assert np.array_equal(Fa.ranks(), Fl.ranks())
 
 
 def test_learned_factor_accepts_sketches_and_stays_accurate(fdsmod):

@@ -154,4 +154,4 @@ def test_cell_features_closed_form():
     c.cols = np.arange(90)
     c.radius = 0.25
     f = ol.cell_features(c, mat, 1e-8, 64, 37)
-    assert np.allclose(f, [4.0 * 0.5, 2.0 * 0.5, 2.0, 45.0, 165.0, 8.0])
+    assert np.allclose(f, [math.log(4.0 * 0.5), math.log(2.0 * 0.5), 2.0, math.log(45.0), math.log(165.0), 8.0])
