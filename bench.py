@@ -28,6 +28,11 @@ sys.path.insert(0, ROOT)
 import numpy as np
 
 
+def log(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _args():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -40,6 +45,8 @@ def _args():
                    help="skip the accuracy checks (second factorisation, sampled rows) after the timed steps")
     p.add_argument("--residual-rows", type=int, default=32)
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    p.add_argument("--no-learned", action="store_true", help="skip the learned form")
+    p.add_argument("--no-multi", action="store_true", help="skip the multi-cavity configurations")
     return p.parse_args()
 
 
@@ -79,6 +86,7 @@ def main():
         t4 = time.perf_counter()
         return F, rhs, x1, xr, dict(factor=t1 - t0, rhs=t2 - t1, first=t3 - t2, rest=t4 - t3, total=t4 - t0)
 
+    log("plain FP64 form: warm-up and timed steps")
     for _ in range(a.warmup):
         F, rhs, x1, xr, tm = step()
         del F, rhs, x1, xr
@@ -98,6 +106,7 @@ def main():
 
     rel_res = comp_err = None
     if not a.no_accuracy:
+        log("accuracy checks")
         # relative residual on sampled rows of the exact Galerkin matrix
         rng = np.random.default_rng(11)
         n_unk = F.n_unknowns
@@ -126,6 +135,7 @@ def main():
                 "flop_per_eval": FLOP_PER_EVAL, "evals": int(cls_e[dom]), "launches": int(cls_n[dom]),
                 "avg_launch_ms": round(1e3 * cls_s[dom] / max(1, cls_n[dom]), 3)}
 
+    log("graph-captured solve form")
     # batched form: the same factorisation with the solve sweeps replayed as a
     # hipGraph captured once per nrhs (first call captures, the timed calls replay)
     del F
@@ -151,10 +161,23 @@ def main():
 
     mixed = None
     if not a.no_mixed:
+        log("mixed-precision form")
         mixed = mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr)
+    learned = learned_mixed = None
+    blob = np.load(PREDICTOR) if not a.no_learned else None
+    if blob is not None:
+        log("learned forms")
+        learned = other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, predictor=blob)
+        learned_mixed = other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, predictor=blob,
+                                   mixed=True, solve_graph=True)
+    multi = None
+    if not a.no_multi:
+        log("multi-cavity configurations")
+        multi = multi_cavity_configs(fds, blob)
 
     cpu = None
     if not a.no_cpu_baseline:
+        log("CPU oracle baseline")
         cpu = cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf)
 
     out = {
@@ -189,6 +212,9 @@ def main():
         "class_evals": [int(x) for x in cls_e],
         "batched_graph_form": batched,
         "mixed_form": mixed,
+        "learned_form": learned,
+        "learned_graph_mixed_form": learned_mixed,
+        "multi_cavity": multi,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -199,6 +225,98 @@ def main():
 # the assembly: Hankel functions at k_T r and k_L r plus the tensor algebra
 # of the four 2x2 kernel blocks and their accumulation)
 FLOP_PER_EVAL = 500
+
+
+PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")
+
+
+def other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2, **kw):
+    """Another form of the factorisation on the same input (best of ``reps``):
+    factor and solve times, the learned form's sketch / fallback counts, and
+    the per-RHS relative difference from the plain FP64 solutions."""
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fm = fds.Factor([nodes], omega, lam, mu, rho, tol, leaf=leaf, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        y1 = Fm.solve(rhs[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        yr = Fm.solve(rhs[1:])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        st = Fm.stats()
+        cur = (t1 - t0, t2 - t1, t3 - t2)
+        best = cur if best is None else tuple(min(u, v) for u, v in zip(best, cur))
+        del Fm
+    X = torch.cat([x1.reshape(1, -1), xr], 0)
+    Y = torch.cat([y1.reshape(1, -1), yr], 0)
+    err = (torch.linalg.norm(Y - X, dim=1) / torch.linalg.norm(X, dim=1)).cpu().numpy()
+    out = {"options": {k: (v if not isinstance(v, np.ndarray) else "rank_mlp_multicavity16k") for k, v in kw.items()},
+           "factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
+           "per_rhs_us": round(1e6 * best[2] / max(1, len(rhs) - 1), 2), "id_s": round(st["id_seconds"], 4),
+           "cells": int(st["cells_compressed"]), "cells_sketched": int(st["cells_sketched"]),
+           "fallback_rank": int(st["cells_fallback_rank"]), "fallback_judge": int(st["cells_fallback_judge"]),
+           "err_vs_plain_fp64_max": float(err.max())}
+    if kw.get("mixed"):
+        out["ir_iterations_batch"] = int(st["ir_iterations"])
+    return out
+
+
+def multi_cavity_configs(fds, blob, reps=2):
+    """The uneven-leaf 64-cavity case (adaptive IDs; graph-captured solve of
+    180 alternating P/S waves) and the learned form's 128-cavity k_T = 8
+    evaluation case (adaptive against learned factor times)."""
+    import torch
+    import synthetic as sy
+    out = {}
+    c = sy.config_batching()
+    ts, tsol = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = fds.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"], solve_graph=True)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        rhs = F.rhs_plane(c["kinds"], c["angles"])
+        F.solve(rhs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F.solve(rhs)
+        torch.cuda.synchronize()
+        tsol.append(time.perf_counter() - t1)
+        st = F.stats()
+        del F
+    out["batching_64_cavities"] = {"workload": "64 cavities (seed 3), 65536 nodes, k_T=2, tol 1e-8, leaf 64 (uneven), "
+                                               "180 alternating P/S waves, graph-captured solve",
+                                   "factor_s": round(min(ts), 4), "per_rhs_us": round(1e6 * min(tsol) / 180, 2),
+                                   "root_size": int(st["root_size"]), "max_rank": int(st["max_rank"]),
+                                   "levels": int(st["levels"])}
+    c = sy.config_learned_eval()
+    res = {}
+    for name, kw in (("adaptive", {}), ("learned", {"predictor": blob} if blob is not None else None)):
+        if kw is None:
+            continue
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = fds.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"], **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            st = F.stats()
+            del F
+        res[name] = {"factor_s": round(min(ts), 4), "id_s": round(st["id_seconds"], 4),
+                     "cells": int(st["cells_compressed"]), "cells_sketched": int(st["cells_sketched"]),
+                     "fallback_rank": int(st["cells_fallback_rank"]), "fallback_judge": int(st["cells_fallback_judge"])}
+    if "learned" in res:
+        res["learned_speedup"] = round(res["adaptive"]["factor_s"] / res["learned"]["factor_s"], 4)
+    res["workload"] = "128 cavities (seed 5), 131072 nodes (262144 unknowns), k_T=8, tol 1e-8, leaf 64"
+    out["learned_eval_128_cavities"] = res
+    return out
 
 
 def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2):

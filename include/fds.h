@@ -88,6 +88,14 @@ typedef struct {
   int32_t oversample;       /* learned form: extra sketch rows; default 10 */
   uint64_t seed;            /* learned form: seed of the sketches (SplitMix64); default 0x5EED */
   const float* predictor;   /* learned form: host, FDS_MLP_BLOB floats (see fds_mlp_forward); copied */
+  int32_t autotune;         /* 1 (default): during the build, time the candidate launch shapes of the solve
+                               sweeps (right-hand-side columns per workgroup of the block LU solves: 1, 2,
+                               4, ..., 32; GEMM output tiles of 64 x 64 or 64 x 16) on the leaf level of
+                               the factor itself, for 1, 8, 32 and 128 right-hand sides, and keep
+                               the fastest per class of nrhs (1 | 2-8 | 9-32 | 33+); the choice is cached per
+                               device and leaf shape for later factorisations in the process; every shape
+                               gives bitwise identical results.  0: fixed shapes */
+  int32_t reserved2;
 } fds_options;
 
 enum { FDS_PREC_FP64 = 0, FDS_PREC_MIXED = 1 };
@@ -175,6 +183,11 @@ typedef struct {
   int64_t cells_fallback_judge;
   double predict_seconds;   /* host time spent waiting for the rank predictions (launched ahead of each
                                level's assembly) */
+  /* autotuner: chosen columns per workgroup of the LU solves and GEMM tile
+   * width for nrhs classes 1 | 2-8 | 9-32 | 33+, and its wall time */
+  int32_t tune_chunk[4];
+  int32_t tune_gemm_cols[4];
+  double tune_seconds;
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);

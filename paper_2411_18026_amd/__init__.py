@@ -42,7 +42,8 @@ class _Options(ctypes.Structure):
                 ("use_alpha", ctypes.c_int32), ("precision", ctypes.c_int32), ("ir_max_iter", ctypes.c_int32),
                 ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double),
                 ("rank_mode", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("predictor", ctypes.POINTER(ctypes.c_float))]
+                ("predictor", ctypes.POINTER(ctypes.c_float)), ("autotune", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -57,7 +58,8 @@ class _Stats(ctypes.Structure):
                 ("ir_correction", ctypes.c_double), ("rank_mode", ctypes.c_int32), ("reserved2", ctypes.c_int32),
                 ("cells_compressed", ctypes.c_int64), ("cells_sketched", ctypes.c_int64),
                 ("cells_fallback_rank", ctypes.c_int64), ("cells_fallback_judge", ctypes.c_int64),
-                ("predict_seconds", ctypes.c_double)]
+                ("predict_seconds", ctypes.c_double), ("tune_chunk", ctypes.c_int32 * 4),
+                ("tune_gemm_cols", ctypes.c_int32 * 4), ("tune_seconds", ctypes.c_double)]
 
 
 class _RankRecord(ctypes.Structure):
@@ -143,7 +145,7 @@ def _geometry(curves):
 
 
 def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False, mixed=False,
-             ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None):
+             ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
@@ -164,6 +166,7 @@ def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, sol
         o.oversample = int(oversample)
     if seed is not None:
         o.seed = int(seed)
+    o.autotune = int(bool(autotune))
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
@@ -210,11 +213,11 @@ class Factor:
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
                  alpha=None, stream=None, solve_graph=False, mixed=False, ir_max_iter=None, ir_rtol=None,
-                 ir_dtol=None, predictor=None, oversample=None, seed=None):
+                 ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True):
         L = load()
         g, self._keep = _geometry(curves)
         o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph, mixed, ir_max_iter, ir_rtol,
-                     ir_dtol, predictor, oversample, seed)
+                     ir_dtol, predictor, oversample, seed, autotune)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))

@@ -30,6 +30,8 @@
 #include <numeric>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 #include <cstdio>
@@ -264,6 +266,8 @@ struct fds_factor_s {
   fds::Workspace ws;
   fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
+  int tune_chunk[4] = {0, 0, 0, 0};         // autotuned LU-solve columns per workgroup per nrhs class
+  int tune_bn[4] = {64, 64, 64, 64};        // autotuned GEMM tile width per nrhs class
   float* pred_host = nullptr;               // learned form: pinned copy of a level's predictions
   size_t pred_host_n = 0;
   hipEvent_t pred_ev = nullptr;
@@ -1535,6 +1539,107 @@ static void build_solve_plan(Factor& F) {
   F.leaf_iota = DevBuf<int64_t>(iota);
 }
 
+// nrhs classes of the autotuner: 1 | 2-8 | 9-32 | 33+
+static int nrhs_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 8 ? 1 : nrhs <= 32 ? 2 : 3; }
+
+// Autotuner of the solve sweeps: on the leaf level of the factor itself,
+// time each candidate LU-solve chunk and GEMM tile width for a
+// representative nrhs of every class and keep the fastest.  Candidates
+// only repartition the outputs, so the choice never changes the results.
+// Tuning results per (device, leaf block order, leaf skeleton order class):
+// later factorisations of the same shape in the process reuse them.
+struct TuneKey {
+  int device, bmax, rclass;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, bmax, rclass) < std::tie(o.device, o.bmax, o.rclass);
+  }
+};
+struct TuneVal {
+  int chunk[4], bn[4];
+};
+static std::map<TuneKey, TuneVal> g_tune_cache;
+static std::mutex g_tune_mutex;
+
+static void autotune_sweeps(Factor& F) {
+  if (!F.opt.autotune || F.L == F.l0) return;
+  const auto t0 = std::chrono::steady_clock::now();
+  CellLevel& lv = F.levels[F.L];
+  SolveLevel& P = lv.plan;
+  hipStream_t s = F.stream;
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  int rmax = 0;
+  for (int q = 0; q < lv.n; ++q) rmax = std::max(rmax, lv.r[q]);
+  const TuneKey key{dev, P.bmax, (rmax + 15) / 16};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int c = 0; c < 4; ++c) {
+        F.tune_chunk[c] = F.st.tune_chunk[c] = it->second.chunk[c];
+        F.tune_bn[c] = F.st.tune_gemm_cols[c] = it->second.bn[c];
+      }
+      F.st.tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return;
+    }
+  }
+  // the whole leaf level: a subset would not fill the GPU the way the sweeps do
+  const int n_lu = P.n_lu, n_tv = P.n_tv;
+  const int reps[4] = {1, 8, 32, 128};
+  c64* Fb = F.ws.get<c64>("tune_F", (size_t)lv.B * 128);
+  c64* Yb = F.ws.get<c64>("tune_Y", (size_t)std::max<int64_t>(lv.R, 1) * 128);
+  FDS_HIP(hipMemsetAsync(Fb, 0, (size_t)lv.B * 128 * sizeof(c64), s));
+  hipEvent_t e0, e1;
+  FDS_HIP(hipEventCreate(&e0));
+  FDS_HIP(hipEventCreate(&e1));
+  auto timed = [&](auto&& launch) {
+    launch();   // warm
+    FDS_HIP(hipEventRecord(e0, s));
+    launch();
+    FDS_HIP(hipEventRecord(e1, s));
+    FDS_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    FDS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  for (int c = 0; c < 4; ++c) {
+    const int nrhs = reps[c];
+    float best = 1e30f;
+    for (int chunk = std::max(1, nrhs / 16); chunk <= 32 && chunk <= std::max(nrhs, 1); chunk *= 2) {
+      if ((size_t)P.bmax * chunk * sizeof(c64) > 65536) break;
+      const float ms = timed([&] {
+        launch_lu_solve(P.lu.p, n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, Fb, s, chunk);
+      });
+      if (ms < best) {
+        best = ms;
+        F.tune_chunk[c] = chunk;
+      }
+    }
+    best = 1e30f;
+    for (int bn : {16, 64}) {
+      const float ms = timed([&] {
+        launch_gemm(P.g_v.p, P.t_v.p, n_tv, nrhs, nrhs, lv.V.p, Fb, Yb, 0, s, bn);
+      });
+      if (ms < best) {
+        best = ms;
+        F.tune_bn[c] = bn;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TuneVal tv{};
+  for (int c = 0; c < 4; ++c) {
+    F.st.tune_chunk[c] = tv.chunk[c] = F.tune_chunk[c];
+    F.st.tune_gemm_cols[c] = tv.bn[c] = F.tune_bn[c];
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mutex);
+    g_tune_cache[key] = tv;
+  }
+  F.st.tune_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 struct SweepBufs {
   std::vector<c64*> F, T, Y;
 };
@@ -1562,23 +1667,24 @@ static SweepBufs sweep_buffers(Factor& F, int nrhs, const std::string& prefix) {
 static void run_sweeps(Factor& F, int nrhs, const SweepBufs& b, hipStream_t s) {
   const int L = F.L, l0 = F.l0;
   auto& levels = F.levels;
+  const int ck = F.tune_chunk[nrhs_class(nrhs)], bn = F.tune_bn[nrhs_class(nrhs)];
   // upward: g = A^{-1} f (in F), f~ = A~ (V g) (V g in Y, f~ in T)
   for (int lev = L; lev > l0; --lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
-    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, b.F[lev], s);
-    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.F[lev], b.Y[lev], 0, s);
-    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s);
+    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, b.F[lev], s, ck);
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.F[lev], b.Y[lev], 0, s, bn);
+    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s, bn);
     launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
   }
-  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.F[l0], s);
+  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.F[l0], s, ck);
   // downward: y from the parent (in Y), f~ <- A~ y - f~, x = g + X f~
   for (int lev = l0 + 1; lev <= L; ++lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
     launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.F[lev - 1], levels[lev - 1].B, b.Y[lev], lv.R, s);
-    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s);
-    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.T[lev], b.F[lev], 0, s);
+    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s, bn);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.T[lev], b.F[lev], 0, s, bn);
   }
 }
 
@@ -1661,24 +1767,25 @@ static MixedBufs mixed_buffers(Factor& F, int nrhs, const std::string& prefix) {
 static void run_sweeps32(Factor& F, int nrhs, const MixedBufs& b, hipStream_t s) {
   const int L = F.L, l0 = F.l0;
   auto& levels = F.levels;
+  const int ck = F.tune_chunk[nrhs_class(nrhs)], bn = F.tune_bn[nrhs_class(nrhs)];
   for (int lev = L; lev > l0; --lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
-    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A32.p, lv.piv.p, b.F[lev], s);
-    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V32.p, b.F[lev], b.Y[lev], 0, s);
-    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s);
+    launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A32.p, lv.piv.p, b.F[lev], s, ck);
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V32.p, b.F[lev], b.Y[lev], 0, s, bn);
+    launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s, bn);
     launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
   }
   const int64_t nroot = (int64_t)F.root.n * nrhs;
   launch_convert(nroot, b.F[l0], b.root, s);
-  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.root, s);
+  launch_lu_solve(F.root.desc.p, 1, F.root.n, nrhs, nrhs, F.root.A.p, F.root.piv.p, b.root, s, ck);
   launch_convert(nroot, b.root, b.F[l0], s);
   for (int lev = l0 + 1; lev <= L; ++lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
     launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.F[lev - 1], levels[lev - 1].B, b.Y[lev], lv.R, s);
-    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s);
-    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X32.p, b.T[lev], b.F[lev], 0, s);
+    launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At32.p, b.Y[lev], b.T[lev], 0, s, bn);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X32.p, b.T[lev], b.F[lev], 0, s, bn);
   }
 }
 
@@ -1689,19 +1796,20 @@ static void run_sweeps32(Factor& F, int nrhs, const MixedBufs& b, hipStream_t s)
 static void run_apply(Factor& F, int nrhs, const MixedBufs& b, hipStream_t s) {
   const int L = F.L, l0 = F.l0;
   auto& levels = F.levels;
+  const int bn = F.tune_bn[nrhs_class(nrhs)];
   for (int lev = L; lev > l0; --lev) {   // skeleton values z_{l-1} = V_l z_l
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
-    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.Z[lev], b.M[lev], 0, s);
+    launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.Z[lev], b.M[lev], 0, s, bn);
     launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.M[lev], lv.R, b.Z[lev - 1], levels[lev - 1].B, s);
   }
-  launch_gemm(F.root.g_b.p, F.root.t_b.p, F.root.n_tb, nrhs, nrhs, F.root.B.p, b.Z[l0], b.W[l0], 0, s);
+  launch_gemm(F.root.g_b.p, F.root.t_b.p, F.root.n_tb, nrhs, nrhs, F.root.B.p, b.Z[l0], b.W[l0], 0, s, bn);
   for (int lev = l0 + 1; lev <= L; ++lev) {   // w_l = B_l z_l + U_l w_{l-1}
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
     launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.W[lev - 1], levels[lev - 1].B, b.M[lev], lv.R, s);
-    launch_gemm(lv.g_diag.p, lv.t_diag.p, lv.n_tdiag, nrhs, nrhs, lv.A.p, b.Z[lev], b.W[lev], 0, s);
-    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.M[lev], b.W[lev], 0, s);
+    launch_gemm(lv.g_diag.p, lv.t_diag.p, lv.n_tdiag, nrhs, nrhs, lv.A.p, b.Z[lev], b.W[lev], 0, s, bn);
+    launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.M[lev], b.W[lev], 0, s, bn);
   }
 }
 
@@ -1797,6 +1905,7 @@ int fds_options_default(fds_options* o) {
   o->oversample = 10;
   o->seed = 0x5EED;
   o->predictor = nullptr;
+  o->autotune = 1;
   return FDS_OK;
 }
 
@@ -1852,6 +1961,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     }
     factor_root(*F);
     build_solve_plan(*F);
+    autotune_sweeps(*F);
     FDS_HIP(hipStreamSynchronize(F->stream));
     const auto t1 = std::chrono::steady_clock::now();
     resolve_stats(*F);

@@ -26,6 +26,21 @@ __device__ inline T zero() {
   return Cx<T>::make(0.0, 0.0);
 }
 
+// acc += a b with explicitly fused multiply-adds, so that every tile shape
+// performs the same floating-point operations
+__device__ inline void cfma(c64& acc, c64 a, c64 b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+__device__ inline void cfma(c32& acc, c32 a, c32 b) {
+  acc.re = fmaf(a.re, b.re, acc.re);
+  acc.re = fmaf(-a.im, b.im, acc.re);
+  acc.im = fmaf(a.re, b.im, acc.im);
+  acc.im = fmaf(a.im, b.re, acc.im);
+}
+
 template <typename TD, typename TS>
 __device__ inline TD cvt(TS a) {
   return Cx<TD>::make((double)a.re, (double)a.im);
@@ -377,7 +392,8 @@ __global__ void k_scatter_int(int64_t n, const int64_t* __restrict__ sidx, const
 // is staged in LDS; substitution proceeds by blocks of 16 rows: the
 // diagonal block is solved by 16 lanes per column with shuffles, the rest
 // of the chunk is updated with one barrier pair per block.
-template <typename T>
+// WIDE: more than 8 columns per workgroup (diagonal blocks in groups of 8).
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, int chunk, int ncol_override,
                                                    const T* __restrict__ abase, const int* __restrict__ piv,
                                                    T* __restrict__ bbase) {
@@ -417,9 +433,10 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   // forward substitution with unit L
   for (int k0 = 0; k0 < n; k0 += SB) {
     const int nb = min(SB, n - k0);
-    if (tid < 8 * 16) {               // two wavefronts, up to 8 columns
-      const bool act = bc < nc && br < nb;
-      T x = act ? X[k0 + br + bc * n] : zero<T>();
+    for (int cg = 0; cg < (WIDE ? nc : 1) && tid < 8 * 16; cg += 8) {   // two wavefronts, 8 columns at a time
+      const int col = cg + bc;
+      const bool act = col < nc && br < nb;
+      T x = act ? X[k0 + br + col * n] : zero<T>();
       T l[SB];
 #pragma unroll
       for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
@@ -431,7 +448,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         xq.im = __shfl(x.im, src);
         if (br > q) x -= l[q] * xq;
       }
-      if (act) X[k0 + br + bc * n] = x;
+      if (act) X[k0 + br + col * n] = x;
     }
     __syncthreads();
     if (r0 < rs)
@@ -445,9 +462,10 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   // backward substitution with U, from the bottom
   for (int k1 = n; k1 > 0; k1 -= SB) {
     const int k0 = max(0, k1 - SB), nb = k1 - k0;
-    if (tid < 8 * 16) {
-      const bool act = bc < nc && br < nb;
-      T x = act ? X[k0 + br + bc * n] : zero<T>();
+    for (int cg = 0; cg < (WIDE ? nc : 1) && tid < 8 * 16; cg += 8) {
+      const int col = cg + bc;
+      const bool act = col < nc && br < nb;
+      T x = act ? X[k0 + br + col * n] : zero<T>();
       T u[SB];
 #pragma unroll
       for (int q = 0; q < SB; ++q)
@@ -462,7 +480,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         xq.im = __shfl(x.im, src);
         if (q < nb && br < q) x -= u[q] * xq;
       }
-      if (act) X[k0 + br + bc * n] = x;
+      if (act) X[k0 + br + col * n] = x;
     }
     __syncthreads();
     if (r0 < rs)
@@ -484,52 +502,59 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 // LDS, each thread owning a 4 x 4 block of outputs.
 // block (blockIdx.x = row tile (problem, tm) from ``tiles``, blockIdx.y = tn);
 // n_override > 0 replaces every problem's column count.
-template <int TA, typename T>
+// BN: output columns per workgroup (64, or 16 for few right-hand sides);
+// the accumulation order over k is the same for both, so the two tile
+// shapes give bitwise identical results.
+template <int TA, typename T, int BN>
 __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
                                                int n_override, const T* __restrict__ abase,
                                                const T* __restrict__ bbase, T* __restrict__ cbase) {
+  constexpr int NB = BN / 16;
   __shared__ T As[16][65];
-  __shared__ T Bs[16][65];
+  __shared__ T Bs[16][BN + 1];
   const GemmTile tl = tiles[blockIdx.x];
   GemmDesc d = descs[tl.desc];
   if (n_override > 0) d.n = n_override;
-  if ((int)blockIdx.y * 64 >= d.n) return;
+  if ((int)blockIdx.y * BN >= d.n) return;
   const T* A = abase + d.a_off;
   const T* B = bbase + d.b_off;
   T* C = cbase + d.c_off;
-  const int m0 = tl.tm * 64, n0 = blockIdx.y * 64;
+  const int m0 = tl.tm * 64, n0 = blockIdx.y * BN;
   const int tid = threadIdx.x;
   const int tr = tid % 16, tc = tid / 16;   // thread owns rows tr + 16 a, cols tc + 16 b
-  T acc[4][4];
+  T acc[4][NB];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = zero<T>();
+    for (int b = 0; b < NB; ++b) acc[a][b] = zero<T>();
   for (int k0 = 0; k0 < d.k; k0 += 16) {
+    // stage op(A)[m0:m0+64, k0:k0+16] and B[k0:k0+16, n0:n0+BN] in one loop
     for (int t = tid; t < 64 * 16; t += kBlk) {
       const int ii = t % 64, kk = t / 64;
       const int gi = m0 + ii, gk = k0 + kk;
       T va = zero<T>();
       if (gi < d.m && gk < d.k) va = TA ? A[gk + (int64_t)gi * d.lda] : A[gi + (int64_t)gk * d.lda];
       As[kk][ii] = va;
-      const int kb = t % 16, jj = t / 16;
-      const int gkb = k0 + kb, gj = n0 + jj;
-      T vb = zero<T>();
-      if (gkb < d.k && gj < d.n) vb = B[gkb + (int64_t)gj * d.ldb];
-      Bs[kb][jj] = vb;
+      if (t < BN * 16) {
+        const int kb = t % 16, jj = t / 16;
+        const int gkb = k0 + kb, gj = n0 + jj;
+        T vb = zero<T>();
+        if (gkb < d.k && gj < d.n) vb = B[gkb + (int64_t)gj * d.ldb];
+        Bs[kb][jj] = vb;
+      }
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < 16; ++kk) {
-      T av[4], bv[4];
+      T av[4], bv[NB];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = As[kk][tr + 16 * a];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tc + 16 * b];
+      for (int b = 0; b < NB; ++b) bv[b] = Bs[kk][tc + 16 * b];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        for (int b = 0; b < NB; ++b) cfma(acc[a][b], av[a], bv[b]);
     }
     __syncthreads();
   }
@@ -538,12 +563,14 @@ __global__ void __launch_bounds__(kBlk) k_gemm(const GemmDesc* __restrict__ desc
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NB; ++b) {
       const int gi = m0 + tr + 16 * a, gj = n0 + tc + 16 * b;
       if (gi < d.m && gj < d.n) {
         T* cp = C + gi + (int64_t)gj * d.ldc;
-        const T v = al * acc[a][b];
-        *cp = zero_beta ? v : v + be * (*cp);
+        T v = zero<T>();
+        cfma(v, al, acc[a][b]);
+        if (!zero_beta) cfma(v, be, *cp);
+        *cp = v;
       }
     }
 }
@@ -1156,12 +1183,16 @@ int solve_chunk(int nmax) { return std::max(1, std::min(8, 32768 / (16 * std::ma
 
 template <typename T>
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
-                     const int* piv, T* bbase, hipStream_t s) {
+                     const int* piv, T* bbase, hipStream_t s, int chunk) {
   if (n == 0 || ncol_max == 0) return;
-  const int nc = solve_chunk(nmax);
+  int nc = solve_chunk(nmax);
+  if (chunk > 0 && (size_t)std::max(1, nmax) * chunk * sizeof(T) <= 65536) nc = chunk;
   if ((size_t)nmax * nc * sizeof(T) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
   dim3 grid(n, (ncol_max + nc - 1) / nc);
-  k_lu_solve<T><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
+  if (nc > 8)
+    k_lu_solve<T, true><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
+  else
+    k_lu_solve<T, false><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
   FDS_HIP(hipGetLastError());
 }
 
@@ -1174,13 +1205,21 @@ std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d) {
 
 template <typename T>
 void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
-                 const T* bbase, T* cbase, int transA, hipStream_t s) {
+                 const T* bbase, T* cbase, int transA, hipStream_t s, int bn) {
   if (n_tiles == 0 || n_max == 0) return;
-  dim3 grid(n_tiles, (n_max + 63) / 64);
-  if (transA)
-    k_gemm<1, T><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
-  else
-    k_gemm<0, T><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+  if (bn == 16) {
+    dim3 grid(n_tiles, (n_max + 15) / 16);
+    if (transA)
+      k_gemm<1, T, 16><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+    else
+      k_gemm<0, T, 16><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+  } else {
+    dim3 grid(n_tiles, (n_max + 63) / 64);
+    if (transA)
+      k_gemm<1, T, 64><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+    else
+      k_gemm<0, T, 64><<<grid, kBlk, 0, s>>>(d, tiles, n_override, abase, bbase, cbase);
+  }
   FDS_HIP(hipGetLastError());
 }
 
@@ -1353,9 +1392,10 @@ void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, co
   template void launch_lu<T>(const LUDesc*, int, int, T*, int*, int*, hipStream_t);                                \
   template void lu_factor<T>(const std::vector<LUDesc>&, T*, int*, int*, Workspace&, const std::string&,           \
                              hipStream_t);                                                                          \
-  template void launch_lu_solve<T>(const SolveDesc*, int, int, int, int, const T*, const int*, T*, hipStream_t);   \
+  template void launch_lu_solve<T>(const SolveDesc*, int, int, int, int, const T*, const int*, T*, hipStream_t,     \
+                                   int);                                                                            \
   template void launch_gemm<T>(const GemmDesc*, const GemmTile*, int, int, int, const T*, const T*, T*, int,       \
-                               hipStream_t);                                                                        \
+                               hipStream_t, int);                                                                   \
   template void launch_copy_rows<T>(int64_t, const int64_t*, const int64_t*, int, const T*, int64_t, T*, int64_t,  \
                                     hipStream_t);                                                                   \
   template void launch_colnorm2<T>(int64_t, int, const T*, int64_t, double*, hipStream_t);                         \

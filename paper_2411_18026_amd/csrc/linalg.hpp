@@ -73,13 +73,16 @@ template <typename T>
 void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Workspace& ws, const std::string& tag,
                hipStream_t s);
 int solve_chunk(int nmax);
+// chunk > 0: right-hand-side columns per workgroup (if its LDS staging fits),
+// else solve_chunk(nmax)
 template <typename T>
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
-                     const int* piv, T* bbase, hipStream_t s);
+                     const int* piv, T* bbase, hipStream_t s, int chunk = 0);
 std::vector<GemmTile> gemm_tiles(const std::vector<GemmDesc>& d);
+// bn: output columns per workgroup, 64 (default) or 16; same results
 template <typename T>
 void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
-                 const T* bbase, T* cbase, int transA, hipStream_t s);
+                 const T* bbase, T* cbase, int transA, hipStream_t s, int bn = 64);
 // 1 if some problem needs the tall variant (m > 2048 or n > 1024); throws
 // beyond 4096 columns
 int check_cpqr_sizes(const std::vector<CpqrDesc>& d);

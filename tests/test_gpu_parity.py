@@ -219,3 +219,17 @@ def test_lu_batched_is_a_partial_pivoting_lu(fdsmod):
     Z = rng.standard_normal((900, 900)) + 0j
     Z[:, 5] = 0.0
     assert fdsmod.lu_batched([Z])[0][2] == 6
+
+
+def test_autotuned_shapes_give_identical_solutions(fdsmod):
+    """The autotuner only repartitions the sweeps' outputs: solutions with and
+    without it are bitwise equal for every nrhs class."""
+    curves = [sy.ellipse(1200, 1.0, 0.5)]
+    Ft = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    Ff = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32, autotune=False)
+    st = Ft.stats()
+    assert all(c >= 1 for c in st["tune_chunk"]) and all(c in (16, 64) for c in st["tune_gemm_cols"])
+    assert Ff.stats()["tune_seconds"] == 0.0
+    for nrhs in (1, 5, 20, 40):
+        rhs = Ft.rhs_plane([k % 2 for k in range(nrhs)], np.linspace(0.0, 6.0, nrhs))
+        assert torch.equal(Ft.solve(rhs), Ff.solve(rhs)), nrhs
