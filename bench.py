@@ -202,6 +202,8 @@ def main():
         "rhs_assembly_ms": round(1e3 * mean["rhs"], 3),
         "factor_breakdown_s": {k: round(st[k], 4) for k in ("assembly_seconds", "id_seconds", "merge_seconds",
                                                             "root_seconds")},
+        "autotune": {"lu_solve_cols_per_wg": list(st["tune_chunk"]), "gemm_tile_cols": list(st["tune_gemm_cols"]),
+                     "nrhs_classes": ["1", "2-8", "9-32", "33+"]},
         "kernel_evals": int(st["kernel_evals"]),
         "root_size": int(st["root_size"]),
         "max_rank": int(st["max_rank"]),
