@@ -223,6 +223,20 @@ typedef struct {
 int fds_get_rank_log(fds_factor f, fds_rank_record* out, int64_t cap, int64_t* n_out);
 
 void fds_destroy(fds_factor f);
+
+/* Device memory: the library takes its device buffers from a process-wide
+ * cache of blocks, so that a factorisation after the first reuses the
+ * blocks of earlier (destroyed) factors instead of calling hipMalloc and
+ * hipFree.  A freed block is handed out again at once for work on the
+ * stream that freed it, and for another stream only after that stream has
+ * passed the free.  At most FDS_CACHE_LIMIT_MB (environment, default
+ * 65536) MiB are kept per device.  fds_release_cache hands every cached
+ * block back to the runtime (blocks held by live factors are not touched);
+ * fds_cached_bytes gives the bytes currently held by the cache.  Both are
+ * safe to call at any time from the host. */
+void fds_release_cache(void);
+int64_t fds_cached_bytes(void);
+
 const char* fds_strerror(int code);
 /* Text of the last error raised on the calling thread (empty if none). */
 const char* fds_last_error(void);

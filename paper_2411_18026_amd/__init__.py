@@ -76,7 +76,7 @@ ENOCONV = 6
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
            "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
-           "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train"]
+           "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes"]
 
 
 def lib_path() -> str:
@@ -123,6 +123,10 @@ def load():
     L.fds_mlp_loss_grad.argtypes = [pf, i64, vp, vp, pf, pf, vp]
     L.fds_mlp_train.argtypes = [pf, i64, vp, vp, i32, i64, ctypes.c_float, ctypes.c_uint64, pf, vp]
     L.fds_special_eval.argtypes = [i64, vp, dbl, vp, vp, vp]
+    L.fds_release_cache.argtypes = []
+    L.fds_release_cache.restype = None
+    L.fds_cached_bytes.argtypes = []
+    L.fds_cached_bytes.restype = i64
     L.fds_cpqr_batched.argtypes = [i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, i32, vp, vp]
     _lib = L
@@ -318,6 +322,16 @@ class Factor:
         _check(load().fds_get_skeleton(self._h, int(cell), r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                        c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap, ctypes.byref(n)))
         return r[:n.value].copy(), c[:n.value].copy()
+
+
+def release_cache():
+    """Hand the library's cached device blocks back to the runtime."""
+    load().fds_release_cache()
+
+
+def cached_bytes() -> int:
+    """Bytes of device memory held by the library's block cache."""
+    return int(load().fds_cached_bytes())
 
 
 def entries(curves, omega, lam, mu, rho, rows, cols, alpha=None, stream=None):

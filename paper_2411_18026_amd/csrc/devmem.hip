@@ -1,0 +1,191 @@
+// Process-wide cache of device blocks (see devmem.hpp).
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "devmem.hpp"
+
+namespace fds {
+
+namespace {
+
+thread_local hipStream_t t_alloc_stream = nullptr;
+thread_local bool t_alloc_scoped = false;
+
+// block sizes: powers of two up to 1 MiB, then multiples of 2 MiB
+size_t round_block(size_t bytes) {
+  if (bytes <= (1u << 20)) {
+    size_t b = 512;
+    while (b < bytes) b <<= 1;
+    return b;
+  }
+  const size_t g = size_t(2) << 20;
+  return (bytes + g - 1) / g * g;
+}
+
+struct FreeBlock {
+  void* p;
+  hipStream_t s;      // stream of the last owner
+  hipEvent_t ev;      // recorded on s when the block was returned
+};
+
+struct DeviceCache {
+  std::multimap<size_t, FreeBlock> free;   // by block size
+  size_t cached = 0;                       // bytes held in ``free``
+};
+
+class BlockCache {
+ public:
+  static BlockCache& get() {
+    static BlockCache* c = new BlockCache();   // never destroyed: frees at exit would race the runtime's teardown
+    return *c;
+  }
+
+  void* alloc(size_t bytes, hipStream_t s, size_t* got) {
+    const size_t b = round_block(std::max<size_t>(bytes, 1));
+    int dev = 0;
+    FDS_HIP(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      DeviceCache& dc = devs_[dev];
+      // exact size class; a block freed on another stream only once its event has completed
+      auto range = dc.free.equal_range(b);
+      auto pick = dc.free.end();
+      for (auto it = range.first; it != range.second; ++it) {
+        if (it->second.s == s) {
+          pick = it;
+          break;
+        }
+        if (pick == dc.free.end() && hipEventQuery(it->second.ev) == hipSuccess) pick = it;
+      }
+      if (pick != dc.free.end()) {
+        void* p = pick->second.p;
+        events_.push_back(pick->second.ev);
+        dc.free.erase(pick);
+        dc.cached -= b;
+        live_[p] = Live{b, dev};
+        *got = b;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      release_device(dev);
+      if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(3, "hipMalloc failed");
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    live_[p] = Live{b, dev};
+    *got = b;
+    return p;
+  }
+
+  void free(void* p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) {
+      (void)hipFree(p);
+      return;
+    }
+    const Live l = it->second;
+    live_.erase(it);
+    hipEvent_t ev = nullptr;
+    if (!events_.empty()) {
+      ev = events_.back();
+      events_.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
+    }
+    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+      // no way to order a later reuse: give the block back to the runtime
+      (void)hipGetLastError();
+      if (ev) events_.push_back(ev);
+      (void)hipFree(p);
+      return;
+    }
+    DeviceCache& dc = devs_[l.dev];
+    dc.free.emplace(l.bytes, FreeBlock{p, s, ev});
+    dc.cached += l.bytes;
+    if (dc.cached > limit()) trim_locked(dc, limit() / 2);
+  }
+
+  size_t cached_bytes() {
+    std::lock_guard<std::mutex> g(mu_);
+    size_t t = 0;
+    for (auto& kv : devs_) t += kv.second.cached;
+    return t;
+  }
+
+  void release_all() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : devs_) trim_locked(kv.second, 0);
+  }
+
+ private:
+  struct Live {
+    size_t bytes;
+    int dev;
+  };
+
+  void release_device(int dev) {
+    std::lock_guard<std::mutex> g(mu_);
+    trim_locked(devs_[dev], 0);
+  }
+
+  // hipFree waits for the device, so blocks still in use by queued work
+  // are safe to hand back; the largest go first.
+  void trim_locked(DeviceCache& dc, size_t target) {
+    while (dc.cached > target && !dc.free.empty()) {
+      auto it = std::prev(dc.free.end());
+      (void)hipFree(it->second.p);
+      events_.push_back(it->second.ev);
+      dc.cached -= it->first;
+      dc.free.erase(it);
+    }
+  }
+
+  static size_t limit() {
+    static const size_t lim = [] {
+      const char* e = std::getenv("FDS_CACHE_LIMIT_MB");
+      const long long mb = e ? std::atoll(e) : 65536;   // 64 GiB of the 288 GB per GPU
+      return (size_t)std::max(0LL, mb) << 20;
+    }();
+    return lim;
+  }
+
+  std::mutex mu_;
+  std::map<int, DeviceCache> devs_;
+  std::unordered_map<void*, Live> live_;
+  std::vector<hipEvent_t> events_;
+};
+
+}  // namespace
+
+void set_alloc_stream(hipStream_t s, bool scoped) {
+  t_alloc_stream = s;
+  t_alloc_scoped = scoped;
+}
+hipStream_t alloc_stream() { return t_alloc_stream; }
+bool alloc_scoped() { return t_alloc_scoped; }
+
+void* cache_alloc(size_t bytes, size_t* block_bytes) {
+  size_t got = 0;
+  void* p = BlockCache::get().alloc(bytes, t_alloc_stream, &got);
+  if (block_bytes) *block_bytes = got;
+  return p;
+}
+
+void cache_free(void* p, hipStream_t s) { BlockCache::get().free(p, s); }
+
+size_t cache_bytes() { return BlockCache::get().cached_bytes(); }
+
+void cache_release() { BlockCache::get().release_all(); }
+
+}  // namespace fds

@@ -2,6 +2,19 @@
 // device buffers that keeps per-level temporaries, descriptor arrays and
 // scratch alive across launches, so launchers never allocate, free or
 // synchronise.
+//
+// Both take their memory from a process-wide cache of device blocks, so a
+// factorisation after the first reuses the blocks of those before it
+// instead of calling hipMalloc / hipFree (hipFree also waits for the whole
+// device).  Ordering: every entry point runs its work on one stream, named
+// for the calling thread by an AllocScope.  A block given back inside an
+// entry point is marked with an event on that stream; it is handed out again
+// at once for work on the same stream (stream order protects it) and for
+// another stream only once the event has completed.  Entry points end by
+// synchronising their stream, so blocks freed afterwards are idle.
+// Size classes: powers of two up to 1 MiB, then multiples of 2 MiB.  The
+// cache holds at most FDS_CACHE_LIMIT_MB (default 65536) MiB per device and
+// gives everything back on fds_release_cache().
 #pragma once
 
 #include <map>
@@ -12,15 +25,39 @@
 
 namespace fds {
 
+void set_alloc_stream(hipStream_t s, bool scoped);
+hipStream_t alloc_stream();
+bool alloc_scoped();
+void* cache_alloc(size_t bytes, size_t* block_bytes = nullptr);
+void cache_free(void* p, hipStream_t s);
+size_t cache_bytes();
+void cache_release();
+
+// names the stream of the calling entry point for the block cache
+struct AllocScope {
+  hipStream_t prev;
+  bool prev_scoped;
+  explicit AllocScope(hipStream_t s) : prev(alloc_stream()), prev_scoped(alloc_scoped()) { set_alloc_stream(s, true); }
+  ~AllocScope() { set_alloc_stream(prev, prev_scoped); }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
+  // inside an AllocScope: stream-ordered upload on the scope's stream (the
+  // host data is staged before the call returns); otherwise synchronous
   explicit DevBuf(const std::vector<T>& h) {
     alloc(h.size());
-    if (!h.empty()) FDS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (h.empty()) return;
+    if (alloc_scoped())
+      FDS_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, alloc_stream()));
+    else
+      FDS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -43,16 +80,17 @@ struct DevBuf {
     release();
     n = count;
     if (count) {
-      hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
-      if (e != hipSuccess) {
+      try {
+        p = static_cast<T*>(cache_alloc(count * sizeof(T)));
+      } catch (...) {
         p = nullptr;
         n = 0;
-        throw Error(3, "hipMalloc failed");
+        throw;
       }
     }
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) cache_free(p, alloc_stream());
     p = nullptr;
     n = 0;
   }
@@ -67,17 +105,19 @@ struct DevBuf {
 };
 
 // Named grow-only device buffers.  A buffer is reallocated only when a
-// larger size is requested; the stream is synchronised first so that no
-// in-flight kernel still uses the old allocation.  Uploads are stream
-// ordered (hipMemcpyAsync on the workspace stream).
+// larger size is requested; the old block goes back to the cache marked
+// with the workspace stream, so kernels still queued on that stream keep
+// it.  Uploads are stream ordered (hipMemcpyAsync on the workspace stream).
 class Workspace {
  public:
   explicit Workspace(hipStream_t s = nullptr) : s_(s) {}
   Workspace(const Workspace&) = delete;
   Workspace& operator=(const Workspace&) = delete;
+  // destroyed after the owner's last synchronisation: the blocks are idle,
+  // and the stream they were used on may no longer exist
   ~Workspace() {
     for (auto& kv : bufs_)
-      if (kv.second.p) (void)hipFree(kv.second.p);
+      if (kv.second.p) cache_free(kv.second.p, alloc_stream());
   }
   void set_stream(hipStream_t s) { s_ = s; }
   hipStream_t stream() const { return s_; }
@@ -87,18 +127,20 @@ class Workspace {
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
     Buf& b = bufs_[key];
     if (b.bytes < bytes) {
+      const size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
       if (b.p) {
-        FDS_HIP(hipStreamSynchronize(s_));
-        FDS_HIP(hipFree(b.p));
+        cache_free(b.p, s_);
         b.p = nullptr;
         b.bytes = 0;
       }
-      const size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
-      if (hipMalloc(&b.p, nb) != hipSuccess) {
+      AllocScope scope(s_);
+      try {
+        b.p = cache_alloc(nb, &b.bytes);
+      } catch (const Error&) {
         b.p = nullptr;
+        b.bytes = 0;
         throw Error(3, "hipMalloc failed for workspace buffer " + key);
       }
-      b.bytes = nb;
     }
     return reinterpret_cast<T*>(b.p);
   }

@@ -266,6 +266,7 @@ struct fds_factor_s {
   fds::Workspace ws;
   fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
+  fds::DevBuf<int> sing;                    // per level: a block LU met a zero pivot
   int tune_chunk[4] = {0, 0, 0, 0};         // autotuned LU-solve columns per workgroup per nrhs class
   int tune_bn[4] = {64, 64, 64, 64};        // autotuned GEMM tile width per nrhs class
   float* pred_host = nullptr;               // learned form: pinned copy of a level's predictions
@@ -444,16 +445,6 @@ struct HostTimer {
   ~HostTimer() { g_host_t[k] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
-static void check_info(Workspace& ws, const int* d_info, size_t n) {
-  HostTimer ht(2);
-  if (n == 0) return;
-  std::vector<int> h(n);
-  FDS_HIP(hipMemcpyAsync(h.data(), d_info, n * sizeof(int), hipMemcpyDeviceToHost, ws.stream()));
-  FDS_HIP(hipStreamSynchronize(ws.stream()));
-  for (int v : h)
-    if (v) throw Error(FDS_ESINGULAR, "singular block in LU");
-}
-
 // support nodes of a DOF list (prev, node, next)
 static void cell_disk(const Geometry& G, const std::vector<int64_t>& rows, const std::vector<int64_t>& cols,
                       double& cx, double& cy, double& R) {
@@ -500,14 +491,17 @@ struct NodeGrid {
   double x0 = 0, y0 = 0, hx = 1;
   int nx = 1, ny = 1;
   std::vector<int> start, items;
-  void build(const Geometry& G, double cell) {
+  // bins the listed nodes only (a level's near sets can only hold nodes that
+  // still carry an active DOF)
+  void build(const Geometry& G, const std::vector<int>& nodes, double cell) {
     double lox = 1e300, loy = 1e300, hix = -1e300, hiy = -1e300;
-    for (int t = 0; t < G.n_nodes; ++t) {
+    for (int t : nodes) {
       lox = std::min(lox, G.xy[2 * t]);
       hix = std::max(hix, G.xy[2 * t]);
       loy = std::min(loy, G.xy[2 * t + 1]);
       hiy = std::max(hiy, G.xy[2 * t + 1]);
     }
+    if (nodes.empty()) lox = loy = hix = hiy = 0.0;
     hx = std::max(cell, 1e-12);
     nx = std::max(1, std::min(4096, (int)std::ceil((hix - lox) / hx) + 1));
     ny = std::max(1, std::min(4096, (int)std::ceil((hiy - loy) / hx) + 1));
@@ -515,18 +509,19 @@ struct NodeGrid {
     x0 = lox;
     y0 = loy;
     std::vector<int> cnt((size_t)nx * ny + 1, 0);
-    std::vector<int> bin(G.n_nodes);
-    for (int t = 0; t < G.n_nodes; ++t) {
+    std::vector<int> bin(nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      const int t = nodes[i];
       const int ix = std::min(nx - 1, (int)((G.xy[2 * t] - x0) / hx));
       const int iy = std::min(ny - 1, (int)((G.xy[2 * t + 1] - y0) / hx));
-      bin[t] = iy * nx + ix;
-      cnt[bin[t] + 1]++;
+      bin[i] = iy * nx + ix;
+      cnt[bin[i] + 1]++;
     }
     for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
     start = cnt;
-    items.resize(G.n_nodes);
+    items.resize(nodes.size());
     std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int t = 0; t < G.n_nodes; ++t) items[fill[bin[t]]++] = t;
+    for (size_t i = 0; i < nodes.size(); ++i) items[fill[bin[i]]++] = nodes[i];
   }
   template <typename F>
   void query(double cx, double cy, double rad, F&& f) const {
@@ -594,8 +589,7 @@ static void place_child_at(Factor& F, int lev, Off dst_off, Ld dst_ld, c32* dst,
 // the buffers: LU(A_i) in place; X_i <- A_i^{-1} X_i; S_i = V_i X_i; LU(S_i);
 // At_i = S_i^{-1} (the LU of S_i applied to the identity).
 template <typename T>
-static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* At, const std::string& tag,
-                      std::vector<std::pair<int*, size_t>>& infos) {
+static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* At, const std::string& tag) {
   Workspace& ws = F.ws;
   hipStream_t s = F.stream;
   const int n = lv.n;
@@ -643,8 +637,9 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
     launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, At, s);
   }
   launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, At, s);
-  infos.emplace_back(info, (size_t)n);
-  infos.emplace_back(info2, lds.size());
+  // zero pivots are reported once the build has finished (no wait here)
+  launch_flag_nonzero(n, info, F.sing.p + lv.lev, s);
+  launch_flag_nonzero((int64_t)lds.size(), info2, F.sing.p + lv.lev, s);
 }
 
 // Pair the ranks of each component (k_c = max(k_row, k_col)) and extend
@@ -1062,8 +1057,12 @@ static void compress_level(Factor& F, int lev) {
     for (auto d : lv.rows[q]) row_owner[d] = q;
     for (auto d : lv.cols[q]) col_owner[d] = q;
   }
+  std::vector<int> active;
+  for (int t = 0; t < G.n_nodes; ++t)
+    if (row_owner[2 * t] >= 0 || row_owner[2 * t + 1] >= 0 || col_owner[2 * t] >= 0 || col_owner[2 * t + 1] >= 0)
+      active.push_back(t);
   NodeGrid grid;
-  grid.build(G, std::max(maxrho, 4.0 * G.hmax));
+  grid.build(G, active, std::max(maxrho, 4.0 * G.hmax));
   std::vector<std::vector<int64_t>> near_r(n), near_c(n);
   parallel_for(n, [&](int q) {
     const double cx = crd[3 * q], cy = crd[3 * q + 1], rho = crd[3 * q + 2];
@@ -1254,7 +1253,6 @@ static void compress_level(Factor& F, int lev) {
 
   // elimination: LU(A_i); X_i = A_i^{-1} U_i; S_i = V_i X_i; A~_i = S_i^{-1}
   span_begin(F, 1);
-  std::vector<std::pair<int*, size_t>> infos;
   if (F.opt.precision == FDS_PREC_MIXED) {
     // FP32 copies: A_i (the FP64 block plus the children's FP32 A~), U_i, V_i
     lv.A32 = DevBuf<c32>((size_t)std::max<int64_t>(lv.a_tot, 1));
@@ -1266,12 +1264,11 @@ static void compress_level(Factor& F, int lev) {
                                   lv.A32.p, "c32");
     launch_convert(lv.x_tot, lv.X.p, lv.X32.p, s);
     launch_convert(lv.v_tot, lv.V.p, lv.V32.p, s);
-    eliminate(F, lv, rmax, lv.A32.p, lv.X32.p, lv.V32.p, lv.At32.p, "32", infos);
+    eliminate(F, lv, rmax, lv.A32.p, lv.X32.p, lv.V32.p, lv.At32.p, "32");
   } else {
-    eliminate(F, lv, rmax, lv.A.p, lv.X.p, lv.V.p, lv.At.p, "64", infos);
+    eliminate(F, lv, rmax, lv.A.p, lv.X.p, lv.V.p, lv.At.p, "64");
   }
   span_end(F);
-  for (auto& c : infos) check_info(ws, c.first, c.second);
   int mr = 0;
   for (int q = 0; q < n; ++q) mr = std::max(mr, std::max(lv.k0[q], lv.k1[q]));
   F.st.max_rank = std::max(F.st.max_rank, mr);
@@ -1419,7 +1416,7 @@ static void factor_root(Factor& F) {
   int* info = ws.get<int>("root_info", 1);
   lu_factor(std::vector<LUDesc>{LUDesc{0, 0, rt.n, rt.n}}, rt.A.p, rt.piv.p, info, ws, "root_lu", s);
   span_end(F);
-  check_info(ws, info, 1);
+  launch_flag_nonzero(1, info, F.sing.p + F.l0, s);
   rt.desc = DevBuf<SolveDesc>(std::vector<SolveDesc>{SolveDesc{0, 0, 0, rt.n, rt.n, rt.n, 0}});
 }
 
@@ -1916,6 +1913,7 @@ static int check_material(double omega, double lam, double mu, double rho) {
 
 int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, double rho, double tol,
               const fds_options* opt, void* stream, fds_factor* out) {
+  AllocScope scope((hipStream_t)stream);
   if (!out) return FDS_EINVAL;
   if (int e = check_material(omega, lambda, mu, rho)) return e;
   if (!(tol > 0.0 && tol < 1.0)) return FDS_EINVAL;
@@ -1952,6 +1950,8 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     }
     F->st.rank_mode = o.rank_mode;
     build_tree(*F);
+    F->sing = DevBuf<int>((size_t)F->L + 1);
+    FDS_HIP(hipMemsetAsync(F->sing.p, 0, F->sing.n * sizeof(int), F->stream));
     const int64_t proxy_cap = (int64_t)F->levels[F->L].n * o.n_proxy;
     F->DG.init(F->G, proxy_cap, F->stream);
     assemble_leaves(*F);
@@ -1964,6 +1964,13 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     autotune_sweeps(*F);
     FDS_HIP(hipStreamSynchronize(F->stream));
     const auto t1 = std::chrono::steady_clock::now();
+    {
+      const auto sing = download(F->ws, F->sing.p, F->sing.n);
+      for (int lev = 0; lev <= F->L; ++lev)
+        if (sing[lev])
+          throw Error(FDS_ESINGULAR, lev == F->l0 ? std::string("singular root LU")
+                                                  : "singular block LU at level " + std::to_string(lev));
+    }
     resolve_stats(*F);
     if (std::getenv("FDS_TIMING")) {
       for (int k = 0; k < 8; ++k) std::fprintf(stderr, "[fds host] %-22s %8.2f ms\n", g_host_name[k], 1e3 * g_host_t[k]);
@@ -2009,6 +2016,7 @@ int fds_size(fds_factor f, int64_t* n) {
 
 int fds_rhs_plane(fds_factor f, int32_t nrhs, const int32_t* kind, const double* angle, fds_c64* rhs, int64_t ld,
                   void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (!f || nrhs < 1 || !kind || !angle || !rhs || ld < 2 * (int64_t)f->G.n_nodes) return FDS_EINVAL;
   try {
     for (int k = 0; k < nrhs; ++k)
@@ -2043,6 +2051,7 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fd
       FDS_HIP(hipStreamSynchronize(f->ws.stream()));
       f->ws.set_stream(s);
     }
+    AllocScope scope(s);
     int status = FDS_OK;
     if (f->opt.precision == FDS_PREC_MIXED)
       status = run_solve_mixed(*f, nrhs, (const c64*)rhs, ld_rhs, (c64*)x, ld_x, s, graph);
@@ -2058,6 +2067,7 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fd
 }
 
 int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c64* y, int64_t ld_y, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   const int64_t N = f ? 2 * (int64_t)f->G.n_nodes : 0;
   if (!f || nrhs < 1 || !x || !y || ld_x < N || ld_y < N) return FDS_EINVAL;
   if (f->opt.precision != FDS_PREC_MIXED) {
@@ -2123,6 +2133,10 @@ int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, i
   return FDS_OK;
 }
 
+void fds_release_cache(void) { cache_release(); }
+
+int64_t fds_cached_bytes(void) { return (int64_t)cache_bytes(); }
+
 void fds_destroy(fds_factor f) {
   if (!f) return;
   if (f->ws.stream()) (void)hipStreamSynchronize(f->ws.stream());
@@ -2147,6 +2161,7 @@ const char* fds_last_error(void) { return g_last_error.c_str(); }
 int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu, double rho, const fds_options* opt,
                 int64_t nr, const int64_t* rows, int64_t nc, const int64_t* cols, fds_c64* out, int64_t ld,
                 void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (int e = check_material(omega, lambda, mu, rho)) return e;
   if (nr < 1 || nc < 1 || !rows || !cols || !out || ld < nr) return FDS_EINVAL;
   fds_options o;
@@ -2182,6 +2197,7 @@ int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu
 }
 
 int fds_special_eval(int64_t n, const double* x, double beta, double* out, fds_c64* outc, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (n < 1 || !x || !out || !outc || !(beta > 0)) return FDS_EINVAL;
   try {
     launch_special_eval(x, n, beta, out, (c64*)outc, (hipStream_t)stream);
@@ -2203,6 +2219,7 @@ int fds_get_rank_log(fds_factor f, fds_rank_record* out, int64_t cap, int64_t* n
 
 int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n, int32_t* piv,
                    const int64_t* pivoff, int32_t* info, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (np < 1 || !a || !off || !n || !piv || !pivoff || !info) return FDS_EINVAL;
   try {
     std::vector<LUDesc> d(np);
@@ -2226,6 +2243,7 @@ int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n,
 int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
                     const int64_t* sz, const int64_t* gid, uint64_t seed, double tol, int32_t* piv,
                     const int64_t* pivoff, int32_t* rank, int32_t* revealed, double* ratio, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   // ``tol`` is the sketch's stopping tolerance (sketch_tol in the header)
   if (np < 1 || !a || !off || !m || !n || !sz || !gid || !piv || !pivoff || !rank || !revealed || !ratio ||
       !(tol > 0.0 && tol < 1.0))
@@ -2355,6 +2373,7 @@ int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int6
 }
 
 int fds_mlp_init(float* blob, int64_t n, const float* x, const float* y, uint64_t seed, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (!blob || n < 1 || !x || !y) return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
@@ -2405,6 +2424,7 @@ int fds_mlp_init(float* blob, int64_t n, const float* x, const float* y, uint64_
 }
 
 int fds_mlp_forward(const float* blob, int64_t n, const float* x, float* y, int32_t bf16, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (!blob || n < 1 || !x || !y) return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
@@ -2420,6 +2440,7 @@ int fds_mlp_forward(const float* blob, int64_t n, const float* x, float* y, int3
 
 int fds_mlp_loss_grad(const float* blob, int64_t n, const float* x, const float* y, float* grad, float* loss,
                       void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (!blob || n < 1 || !x || !y || !grad || !loss) return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
@@ -2441,6 +2462,7 @@ int fds_mlp_loss_grad(const float* blob, int64_t n, const float* x, const float*
 
 int fds_mlp_train(float* blob, int64_t n, const float* x, const float* y, int32_t steps, int64_t batch, float lr,
                   uint64_t seed, float* loss_hist, void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (!blob || n < 1 || !x || !y || steps < 0 || batch < 0 || !(lr > 0.0f)) return FDS_EINVAL;
   try {
     hipStream_t s = (hipStream_t)stream;
@@ -2471,6 +2493,7 @@ int fds_mlp_train(float* blob, int64_t n, const float* x, const float* y, int32_
 int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n, int32_t* piv,
                      const int64_t* pivoff, const int64_t* kmax, double tol, int32_t stop_at_tol, int32_t* rank,
                      void* stream) {
+  AllocScope scope((hipStream_t)stream);
   if (np < 1 || !a || !off || !m || !n || !piv || !pivoff || !kmax || !rank) return FDS_EINVAL;
   try {
     std::vector<CpqrDesc> d(np);

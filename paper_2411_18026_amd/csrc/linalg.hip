@@ -1077,6 +1077,12 @@ __global__ void k_fill_identity(const int64_t* __restrict__ offs, const int* __r
   }
 }
 
+// flag[0] = 1 when any of info[0..n) is nonzero (every writer stores the same value)
+__global__ void k_flag_nonzero(int64_t n, const int* __restrict__ info, int* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (info[i] != 0) flag[0] = 1;
+}
+
 // ------------------------------------------------------------------ launchers
 // All launchers are asynchronous on ``s``: descriptor arrays are device
 // pointers owned by the caller (workspace or factor storage).
@@ -1378,6 +1384,12 @@ template <typename T>
 void launch_colnorm2(int64_t n, int ncol, const T* src, int64_t ld, double* out, hipStream_t s) {
   if (ncol == 0) return;
   k_colnorm2<T><<<ncol, kBlk, 0, s>>>(n, src, ld, out);
+  FDS_HIP(hipGetLastError());
+}
+
+void launch_flag_nonzero(int64_t n, const int* info, int* flag, hipStream_t s) {
+  if (n <= 0) return;
+  k_flag_nonzero<<<(unsigned)std::min<int64_t>((n + 255) / 256, 1024), 256, 0, s>>>(n, info, flag);
   FDS_HIP(hipGetLastError());
 }
 

@@ -115,6 +115,8 @@ void launch_add_c32(int64_t n, const c32* src, c64* dst, hipStream_t s);
 // out[c] = sum_{i<n} |src[i + c ld]|^2 (FP64), c < ncol
 template <typename T>
 void launch_colnorm2(int64_t n, int ncol, const T* src, int64_t ld, double* out, hipStream_t s);
+// flag[0] = 1 if any of the n ints at info is nonzero (flag is never cleared here)
+void launch_flag_nonzero(int64_t n, const int* info, int* flag, hipStream_t s);
 template <typename T>
 void launch_fill_identity(int64_t n_mats, const int64_t* offs, const int* ns, const int* lds, T* base, hipStream_t s);
 

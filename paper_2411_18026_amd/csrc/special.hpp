@@ -103,19 +103,63 @@ struct Cx<c32> {
   __host__ __device__ static c32 make(double r, double i) { return c32{(float)r, (float)i}; }
 };
 
+// Miller's backward recurrence for J_n(x) started at an even index N
+// (N >= 2x + 20), normalised by 1 = J_0 + 2 sum_k J_2k, with the Neumann
+// series of Y0 and Y1 accumulated on the way down.  N is a compile-time
+// constant: the loop unrolls, every coefficient folds to a constant and all
+// lanes of a wavefront run the same instructions.
+template <int N>
+__host__ __device__ inline void bessel_miller(double x, double& J0, double& J1, double& Y0, double& Y1) {
+  const double tx = 2.0 / x;
+  double cur = 1e-30, nxt = 0.0;   // J_m (unnormalised), J_{m+1}
+  double s = 0.0, y0s = 0.0, y1s = 0.0, v0 = 0.0, v1 = 0.0;
+#pragma unroll
+  for (int m = N; m >= 0; --m) {
+    const double v = cur;
+    if (m & 1) {
+      // odd m contributes to sum_k (-1)^k (J_{2k-1} - J_{2k+1}) / k
+      const int kp = (m + 1) >> 1;   // m = 2 kp - 1
+      double c = ((kp & 1) ? -1.0 : 1.0) / kp;
+      if (m >= 3) {
+        const int km = (m - 1) >> 1;   // m = 2 km + 1
+        c -= ((km & 1) ? -1.0 : 1.0) / km;
+      }
+      y1s += c * v;
+      if (m == 1) v1 = v;
+    } else if (m > 0) {
+      const int k = m >> 1;
+      s += 2.0 * v;
+      y0s += (((k & 1) ? -1.0 : 1.0) / k) * v;
+    } else {
+      s += v;
+      v0 = v;
+    }
+    const double prev = (m * tx) * cur - nxt;
+    nxt = cur;
+    cur = prev;
+  }
+  const double inv = 1.0 / s;
+  const double L = log(0.5 * x) + kEulerGamma;
+  J0 = v0 * inv;
+  J1 = v1 * inv;
+  Y0 = (2.0 / kPi) * L * J0 - (4.0 / kPi) * y0s * inv;
+  Y1 = -(2.0 / (kPi * x)) * J0 + (2.0 / kPi) * L * J1 + (2.0 / kPi) * y1s * inv;
+}
+
 // J0, J1, Y0, Y1 of x > 0.
 __host__ __device__ inline void bessel_jy01(double x, double& J0, double& J1, double& Y0, double& Y1) {
   if (x < 2.0) {
     const double w = 0.25 * x * x;
     double t0 = 1.0, t1 = 0.5 * x, h = 0.0;
     double j0 = 0.0, j1 = 0.0, y0s = 0.0, y1s = 0.0;
+#pragma unroll
     for (int k = 0; k < 14; ++k) {
       j0 += t0;
       j1 += t1;
       y0s -= t0 * h;                                  // (-1)^{k+1} h_k w^k/(k!)^2
       y1s += (2.0 * h + 1.0 / (k + 1)) * t1;          // (psi(k+1)+psi(k+2)+2 gamma) t1_k
-      t0 *= -w / ((k + 1.0) * (k + 1.0));
-      t1 *= -w / ((k + 1.0) * (k + 2.0));
+      t0 *= -w * (1.0 / ((k + 1.0) * (k + 1.0)));
+      t1 *= -w * (1.0 / ((k + 1.0) * (k + 2.0)));
       h += 1.0 / (k + 1);
     }
     const double L = log(0.5 * x);
@@ -125,42 +169,12 @@ __host__ __device__ inline void bessel_jy01(double x, double& J0, double& J1, do
     Y1 = -2.0 / (kPi * x) + (2.0 / kPi) * L * j1 - (y1s - 2.0 * kEulerGamma * j1) / kPi;
     return;
   }
+  if (x < 8.0) {
+    bessel_miller<36>(x, J0, J1, Y0, Y1);
+    return;
+  }
   if (x < 17.0) {
-    int N = (int)(2.0 * x + 20.0);
-    N += (N & 1);                    // even start index
-    const double tx = 2.0 / x;
-    double cur = 1e-30, nxt = 0.0;   // J_N (unnormalised), J_{N+1}
-    double s = 0.0, y0s = 0.0, y1s = 0.0, v0 = 0.0, v1 = 0.0;
-    for (int m = N; m >= 0; --m) {
-      const double v = cur;
-      if (m & 1) {
-        // odd m contributes to sum_k (-1)^k (J_{2k-1} - J_{2k+1})/k
-        const int kp = (m + 1) >> 1;           // m = 2 kp - 1
-        double c = ((kp & 1) ? -1.0 : 1.0) / kp;
-        if (m >= 3) {
-          const int km = (m - 1) >> 1;         // m = 2 km + 1
-          c -= ((km & 1) ? -1.0 : 1.0) / km;
-        }
-        y1s += c * v;
-        if (m == 1) v1 = v;
-      } else if (m > 0) {
-        const int k = m >> 1;
-        s += 2.0 * v;
-        y0s += ((k & 1) ? -v : v) / k;
-      } else {
-        s += v;
-        v0 = v;
-      }
-      const double prev = m * tx * cur - nxt;
-      nxt = cur;
-      cur = prev;
-    }
-    const double inv = 1.0 / s;
-    const double L = log(0.5 * x) + kEulerGamma;
-    J0 = v0 * inv;
-    J1 = v1 * inv;
-    Y0 = (2.0 / kPi) * L * J0 - (4.0 / kPi) * y0s * inv;
-    Y1 = -(2.0 / (kPi * x)) * J0 + (2.0 / kPi) * L * J1 + (2.0 / kPi) * y1s * inv;
+    bessel_miller<54>(x, J0, J1, Y0, Y1);
     return;
   }
   // Hankel asymptotic expansion
@@ -257,59 +271,71 @@ __host__ __device__ inline void e_chi_series(double a, double beta, c64& E, c64&
 }
 
 // Small-argument expansions as polynomials in w = a^2/4 (a = k_T r < 1,
-// b = beta a): coefficient tables depend only on beta and are built once per
-// material on the host (make_series_coef).  Rows of ``c``:
-//   0 J0:  (-1)^k/(k!)^2                1 Y0 part: (-1)^(k+1) h_k/(k!)^2
-//   2 J1/(a/2): (-1)^k/(k!(k+1)!)       3 Y1 part: (-1)^k (psi(k+1)+psi(k+2))/(k!(k+1)!)
-//   4 E real part, 5 E imaginary part without the log(a/2) term,
-//   6 chi/w real part, 7 chi/w imaginary part without the log(a/2) term.
-// With L = log(a/2):
-//   J0 = P0(w), Y0 = (2/pi)((L + gamma) J0 + P1(w)),
-//   J1 = (a/2) P2(w), Y1 = -2/(pi a) + (2/pi) L J1 - (1/pi)(a/2) P3(w),
-//   E = P4(w) + i ((2/pi) L P4(w) + P5(w)),
-//   chi = -(i/pi)(1 - beta^2) + w (P6(w) + i ((2/pi) L P6(w) + P7(w))),
-// and H0(b) from rows 0, 1 at w_b = beta^2 w with log(b/2) = L + log beta.
+// b = beta a, w_b = beta^2 w).  The coefficient rows do not depend on the
+// material and are compile-time constants (they fold into the code, so no
+// table occupies registers):
+//   S0 (-1)^k/(k!)^2                 S1 (-1)^(k+1) h_k/(k!)^2
+//   S2 (-1)^k/(k!(k+1)!)             S3 (-1)^k (psi(k+1)+psi(k+2))/(k!(k+1)!)
+//   S6 (-1)^k/(k!(k+2)!)             S7 (-1)^k (psi(k+1)+psi(k+3))/(k!(k+2)!)
+// With L = log(a/2), Pi = Si(w), Qi = Si(w_b):
+//   J0 = P0, Y0 = (2/pi)((L + gamma) J0 + P1),
+//   J1 = (a/2) P2, Y1 = -2/(pi a) + (2/pi) L J1 - (1/pi)(a/2) P3,
+//   H0(b) from Q0, Q1 with log(b/2) = L + log beta,
+//   E   = e + i ((2/pi) L e + e'),     e  = (P2 - beta^2 Q2)/2,
+//         e' = -(P3 - beta^2 Q3)/(2 pi) - (log beta/pi) beta^2 Q2,
+//   chi = -(i/pi)(1 - beta^2) + w (c + i ((2/pi) L c + c')),
+//         c  = P6 - beta^4 Q6,   c' = -(P7 - beta^4 Q7)/pi - (2 log beta/pi) beta^4 Q6
+// (the 1/a^2 parts of E and chi cancel term by term in these forms).
 constexpr int kSerTerms = 10;
+struct SerTab {
+  double c[6][kSerTerms];
+};
+
+constexpr SerTab make_ser_tab() {
+  SerTab t{};
+  double fk = 1.0, fk1 = 1.0, fk2 = 2.0, hk = 0.0;   // k!, (k+1)!, (k+2)!, h_k
+  for (int k = 0; k < kSerTerms; ++k) {
+    const double sg = (k & 1) ? -1.0 : 1.0;
+    const double hk1 = hk + 1.0 / (k + 1), hk2 = hk1 + 1.0 / (k + 2);
+    const double psiE = -2.0 * kEulerGamma + hk + hk1;   // psi(k+1) + psi(k+2)
+    const double psiC = -2.0 * kEulerGamma + hk + hk2;   // psi(k+1) + psi(k+3)
+    t.c[0][k] = sg / (fk * fk);
+    t.c[1][k] = -sg * hk / (fk * fk);
+    t.c[2][k] = sg / (fk * fk1);
+    t.c[3][k] = sg * psiE / (fk * fk1);
+    t.c[4][k] = sg / (fk * fk2);
+    t.c[5][k] = sg * psiC / (fk * fk2);
+    fk *= (k + 1);
+    fk1 *= (k + 2);
+    fk2 *= (k + 3);
+    hk = hk1;
+  }
+  return t;
+}
+
+constexpr SerTab kSerTab = make_ser_tab();
+
+// material constants of the series (host-built once per material)
 struct SeriesCoef {
-  double c[8][kSerTerms];
-  double beta, logbeta, chi0;   // chi0 = -(1 - beta^2)/pi (imaginary part of the constant)
+  double beta, logbeta, b2, b4;   // b2 = beta^2, b4 = beta^4
+  double chi0;                    // -(1 - beta^2)/pi (imaginary part of chi's constant)
 };
 
 inline SeriesCoef make_series_coef(double beta) {
   SeriesCoef s{};
   s.beta = beta;
   s.logbeta = log(beta);
-  s.chi0 = -(1.0 - beta * beta) / kPi;
-  double fk = 1.0, fk1 = 1.0, fk2 = 2.0, hk = 0.0;   // k!, (k+1)!, (k+2)!, h_k
-  double b2 = beta * beta, bp2 = b2, bp4 = b2 * b2;
-  for (int k = 0; k < kSerTerms; ++k) {
-    const double sg = (k & 1) ? -1.0 : 1.0;
-    const double hk1 = hk + 1.0 / (k + 1), hk2 = hk1 + 1.0 / (k + 2);
-    const double psiE = -2.0 * kEulerGamma + hk + hk1;   // psi(k+1) + psi(k+2)
-    const double psiC = -2.0 * kEulerGamma + hk + hk2;   // psi(k+1) + psi(k+3)
-    s.c[0][k] = sg / (fk * fk);
-    s.c[1][k] = -sg * hk / (fk * fk);
-    s.c[2][k] = sg / (fk * fk1);
-    s.c[3][k] = sg * psiE / (fk * fk1);
-    const double e1 = sg * (1.0 - bp2) / (2.0 * fk * fk1);
-    s.c[4][k] = e1;
-    s.c[5][k] = sg * (-(1.0 - bp2) * psiE / kPi - bp2 * (2.0 / kPi) * s.logbeta) / (2.0 * fk * fk1);
-    s.c[6][k] = sg * (1.0 - bp4) / (fk * fk2);
-    s.c[7][k] = sg * (-(1.0 - bp4) * psiC / kPi - bp4 * (2.0 / kPi) * s.logbeta) / (fk * fk2);
-    fk *= (k + 1);
-    fk1 *= (k + 2);
-    fk2 *= (k + 3);
-    bp2 *= b2;
-    bp4 *= b2;
-    hk = hk1;
-  }
+  s.b2 = beta * beta;
+  s.b4 = s.b2 * s.b2;
+  s.chi0 = -(1.0 - s.b2) / kPi;
   return s;
 }
 
-__host__ __device__ inline double horner(const double* c, double w) {
-  double p = c[kSerTerms - 1];
+template <int R>
+__host__ __device__ inline double ser(double w) {
+  double p = kSerTab.c[R][kSerTerms - 1];
 #pragma unroll
-  for (int k = kSerTerms - 2; k >= 0; --k) p = p * w + c[k];
+  for (int k = kSerTerms - 2; k >= 0; --k) p = p * w + kSerTab.c[R][k];
   return p;
 }
 
@@ -348,19 +374,22 @@ __host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c6
                                               c64& chi) {
   if (a < kSeriesSwitch) {
     const double w = 0.25 * a * a;
-    const double wb = sc.beta * sc.beta * w;
+    const double wb = sc.b2 * w;
     const double L = log(0.5 * a);
     const double tp = 2.0 / kPi;
-    const double j0 = horner(sc.c[0], w);
-    const double j1 = 0.5 * a * horner(sc.c[2], w);
-    h0a = cmk(j0, tp * ((L + kEulerGamma) * j0 + horner(sc.c[1], w)));
-    h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * horner(sc.c[3], w));
-    const double j0b = horner(sc.c[0], wb);
-    h0b = cmk(j0b, tp * ((L + sc.logbeta + kEulerGamma) * j0b + horner(sc.c[1], wb)));
-    const double p4 = horner(sc.c[4], w);
-    E = cmk(p4, tp * L * p4 + horner(sc.c[5], w));
-    const double p6 = horner(sc.c[6], w);
-    chi = cmk(w * p6, sc.chi0 + w * (tp * L * p6 + horner(sc.c[7], w)));
+    const double P0 = ser<0>(w), P1 = ser<1>(w), P2 = ser<2>(w), P3 = ser<3>(w), P6 = ser<4>(w), P7 = ser<5>(w);
+    const double Q0 = ser<0>(wb), Q1 = ser<1>(wb), Q2 = ser<2>(wb), Q3 = ser<3>(wb), Q6 = ser<4>(wb),
+                 Q7 = ser<5>(wb);
+    const double j1 = 0.5 * a * P2;
+    h0a = cmk(P0, tp * ((L + kEulerGamma) * P0 + P1));
+    h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * P3);
+    h0b = cmk(Q0, tp * ((L + sc.logbeta + kEulerGamma) * Q0 + Q1));
+    const double e = 0.5 * (P2 - sc.b2 * Q2);
+    const double e1 = -(0.5 / kPi) * (P3 - sc.b2 * Q3) - (sc.logbeta / kPi) * sc.b2 * Q2;
+    E = cmk(e, tp * L * e + e1);
+    const double c = P6 - sc.b4 * Q6;
+    const double c1 = -(1.0 / kPi) * (P7 - sc.b4 * Q7) - (2.0 * sc.logbeta / kPi) * sc.b4 * Q6;
+    chi = cmk(w * c, sc.chi0 + w * (tp * L * c + c1));
     return;
   }
   const Hankel2 h = hankel_pair(a, sc.beta * a);
