@@ -61,10 +61,14 @@ __device__ inline void acc_zero(PairAcc& A) {
   for (int k = 0; k < 4; ++k) A.s2[k] = cmk(0, 0);
 }
 
-// One quadrature point: d = x - y, weight w (reference weight times
-// element lengths), hat coordinates u (test) and v (trial), normals.
-__device__ inline void acc_point(const MatConst& m, double dx, double dy, double w, double u, double v,
-                                 double nx0, double nx1, double ny0, double ny1, PairAcc& A) {
+// The four 2 x 2 blocks of one quadrature point (d = x - y, normals n_x,
+// n_y of the test and trial elements) whose hat-weighted sums make up a
+// pair's 16 entries:
+//   entry[a][b][ij] += N_a dN_b M1 + w dN_a dN_b M2 + N_a N_b M3 + w dN_a N_b M4
+// (N the hat values, dN their constant tangential derivatives, w the
+// quadrature weight; N_a carries w).
+__device__ inline void point_blocks(const MatConst& m, double dx, double dy, double nx0, double nx1, double ny0,
+                                    double ny1, c64 (&M1)[4], c64 (&M2)[4], c64 (&M3)[4], c64 (&M4)[4]) {
   const double r = sqrt(dx * dx + dy * dy);
   const double ir = 1.0 / r;
   const double e0 = dx * ir, e1 = dy * ir;
@@ -98,7 +102,6 @@ __device__ inline void acc_point(const MatConst& m, double dx, double dy, double
   const c64 arw = (m.rw2) * al;
   const c64 arwL = arw * phiL;
   const c64 arwT = arw * phiT;
-  c64 M1[4], M2[4], M3[4], M4[4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -110,6 +113,14 @@ __device__ inline void acc_point(const MatConst& m, double dx, double dy, double
       M3[2 * i + j] = dij * dny + (ex[i] * ny[j]) * cg + (nx[i] * ny[j]) * arwL + (tx[i] * ty[j]) * arwT;
       M4[2 * i + j] = (-1.0) * (K * (Jij * dny + (jex[i] * ny[j]) * cg));
     }
+}
+
+// Special pairs: the hat-weighted sums kept apart (36 accumulators), so a
+// wavefront can reduce them over its lanes before the 16 entries are formed.
+__device__ inline void acc_point(const MatConst& m, double dx, double dy, double w, double u, double v,
+                                 double nx0, double nx1, double ny0, double ny1, PairAcc& A) {
+  c64 M1[4], M2[4], M3[4], M4[4];
+  point_blocks(m, dx, dy, nx0, nx1, ny0, ny1, M1, M2, M3, M4);
   const double Na[2] = {w * (1.0 - u), w * u};
   const double Nb[2] = {1.0 - v, v};
 #pragma unroll
@@ -123,6 +134,32 @@ __device__ inline void acc_point(const MatConst& m, double dx, double dy, double
       for (int bb = 0; bb < 2; ++bb) A.s3[aa][bb][k] += (Na[aa] * Nb[bb]) * M3[k];
     }
   }
+}
+
+// Regular pairs: the 16 entries accumulated directly (64 registers instead
+// of 144, which lets two wavefronts share a SIMD).
+struct PairRes {
+  c64 R[16];
+};
+
+__device__ inline void acc_point_direct(const MatConst& m, double dx, double dy, double w, double u, double v,
+                                        double nx0, double nx1, double ny0, double ny1, double dA0, double dA1,
+                                        double dB0, double dB1, PairRes& A) {
+  c64 M1[4], M2[4], M3[4], M4[4];
+  point_blocks(m, dx, dy, nx0, nx1, ny0, ny1, M1, M2, M3, M4);
+  const double Na[2] = {w * (1.0 - u), w * u};
+  const double Nb[2] = {1.0 - v, v};
+  const double wdA[2] = {w * dA0, w * dA1};
+  const double dB[2] = {dB0, dB1};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const c64 T = dB[bb] * M1[k] + Nb[bb] * M3[k];
+      const c64 U = dB[bb] * M2[k] + Nb[bb] * M4[k];
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa) A.R[aa * 8 + bb * 4 + k] += Na[aa] * T + wdA[aa] * U;
+    }
 }
 
 // res[a][b][ij] = s1[a] dB[b] + dA[a] dB[b] s2 + s3[a][b] + dA[a] s4[b]
@@ -308,8 +345,9 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
   const Elem f = elems[gf];
   const double* g = (Q == 4) ? c_quad.g4 : (Q == 6 ? c_quad.g6 : c_quad.g10);
   const double* wq = (Q == 4) ? c_quad.w4 : (Q == 6 ? c_quad.w6 : c_quad.w10);
-  PairAcc A;
-  acc_zero(A);
+  PairRes A;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) A.R[k] = cmk(0.0, 0.0);
   const double ox = e.x0 - f.x0, oy = e.y0 - f.y0;
   const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
   const double bx = f.x1 - f.x0, by = f.y1 - f.y0;
@@ -321,21 +359,18 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
       const double v = g[j];
       const double dx = ox + u * ax - v * bx;
       const double dy = oy + u * ay - v * by;
-      acc_point(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, A);
+      acc_point_direct(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   }
   const int64_t slot = jb.pair_off + (int64_t)ie * jb.nce + je;
 #pragma unroll
-  for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) res[(aa * 8 + bb * 4 + k) * np + slot] = acc_final(A, aa, bb, k, e, f);
+  for (int k = 0; k < 16; ++k) res[k * np + slot] = A.R[k];
 }
 
-// grid-stride over the class list; its length is read on the device
+// grid-stride over the class list; its length is read on the device.  Two
+// wavefronts per SIMD: the register budget is 256 per lane.
 template <int Q>
-__global__ void __launch_bounds__(128) k_regular(const unsigned long long* __restrict__ list,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) k_regular(const unsigned long long* __restrict__ list,
                                                  const unsigned int* __restrict__ count_ptr,
                                                  const Job* __restrict__ jobs, const int* __restrict__ elist,
                                                  const Elem* __restrict__ elems, MatConst m,
