@@ -581,22 +581,117 @@ constexpr int kQrMaxN = 1024;
 constexpr int kQrMaxNTall = 4096;
 constexpr int64_t kQrwMinElems = 1 << 16;   // problems this large use the multi-workgroup QR
 
+// Reflector update of columns c[0..G) (g < ng valid) of one problem by one
+// wavefront: w = tau v^H a, a <- a - v w, and the exact norm of the part
+// below row j.  CH > 0: the trailing rows j.. of each column (at most 64 CH
+// of them) stay in registers between the two passes; CH = 0: two passes
+// over memory.  Per lane the rows are visited in the same order either way,
+// so the results do not depend on the variant.
+template <int G, int CH>
+__device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j, const int (&cols)[G], int ng,
+                                      const c64* v, c64 vtop, double tau, int lane, double* __restrict__ nrm) {
+  double wr[G], wi[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) wr[g] = wi[g] = 0.0;
+  if constexpr (CH > 0) {
+    c64 a[G][CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int i = j + lane + 64 * t;
+      const bool in = i < m;
+      const c64 vv = i == j ? vtop : (in ? v[i] : cmk(0, 0));
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        a[g][t] = (in && g < ng) ? A[i + (int64_t)cols[g] * lda] : cmk(0, 0);
+        wr[g] += vv.re * a[g][t].re + vv.im * a[g][t].im;   // conj(v) a
+        wi[g] += vv.re * a[g][t].im - vv.im * a[g][t].re;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      wr[g] = wsum(wr[g]);
+      wi[g] = wsum(wi[g]);
+    }
+    double sq[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) sq[g] = 0.0;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int i = j + lane + 64 * t;
+      if (i >= m) continue;
+      const c64 vv = i == j ? vtop : v[i];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g >= ng) continue;
+        const c64 w = cmk(tau * wr[g], tau * wi[g]);
+        const c64 x = a[g][t] - vv * w;
+        A[i + (int64_t)cols[g] * lda] = x;
+        if (i > j) sq[g] += abs2(x);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sq[g] = wsum(sq[g]);
+      if (lane == 0 && g < ng) nrm[cols[g]] = sq[g];
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g >= ng) continue;
+      const c64* col = A + (int64_t)cols[g] * lda;
+      for (int i = j + lane; i < m; i += 64) {
+        const c64 x = col[i], vv = i == j ? vtop : v[i];
+        wr[g] += vv.re * x.re + vv.im * x.im;
+        wi[g] += vv.re * x.im - vv.im * x.re;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      wr[g] = wsum(wr[g]);
+      wi[g] = wsum(wi[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g >= ng) continue;
+      c64* col = A + (int64_t)cols[g] * lda;
+      const c64 w = cmk(tau * wr[g], tau * wi[g]);
+      double sq = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const c64 x = col[i] - (i == j ? vtop : v[i]) * w;
+        col[i] = x;
+        if (i > j) sq += abs2(x);
+      }
+      sq = wsum(sq);
+      if (lane == 0) nrm[cols[g]] = sq;
+    }
+  }
+}
+
+__device__ inline double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
 // TALL = false: the Householder vector is staged in LDS (m <= kQrMaxM,
 // n <= kQrMaxN).  TALL = true: any m, n <= kQrMaxNTall; the vector is read
 // in place from column j (its entries below the diagonal are the column's
 // own), its top entry kept in LDS, and the column cleared after the update.
+// Per step: pivot search by wavefront reductions (two barriers), column
+// swap, reflector (one wavefront), and the update of the trailing columns,
+// four at a time per wavefront.
 template <bool TALL>
 __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ descs, c64* __restrict__ base,
                                                int* __restrict__ piv, double tol, int* __restrict__ rank) {
   constexpr int NMAX = TALL ? kQrMaxNTall : kQrMaxN;
+  constexpr int NW = kBlk / 64;
+  constexpr int G = 4;
   __shared__ double nrm[NMAX];
   __shared__ int pv[NMAX];
   __shared__ c64 v_lds[TALL ? 1 : kQrMaxM];
   __shared__ c64 s_vtop;
-  __shared__ double sv[kBlk];
-  __shared__ int si[kBlk];
-  __shared__ double s_r00, s_tau;
-  __shared__ int s_stop;
+  __shared__ double s_max[NW], s_tau;
+  __shared__ int s_org[NW], s_col[NW];
   const CpqrDesc d = descs[blockIdx.x];
   c64* A = base + d.a_off;
   int* P = piv + d.piv_off;
@@ -605,81 +700,81 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   const int kmax = min(d.k_end, min(m, n));
   for (int c = tid; c < n; c += kBlk) pv[c] = d.k_start == 0 ? c : P[c];
   // exactly computed norms of the remaining part of each column
-  for (int c = d.k_start + wid; c < n; c += kBlk / 64) {
+  for (int c = d.k_start + wid; c < n; c += NW) {
     double s = 0.0;
     for (int i = d.k_start + lane; i < m; i += 64) s += abs2(A[i + (int64_t)c * lda]);
     s = wsum(s);
     if (lane == 0) nrm[c] = s;
   }
-  if (tid == 0) {
-    s_r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
-    s_stop = 0;
-  }
+  double r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
   __syncthreads();
   int j = d.k_start;
   for (; j < kmax; ++j) {
     // pivot: largest norm; ties within a relative 1e-12 -> lowest original column
     double best = -1.0;
     for (int c = j + tid; c < n; c += kBlk) best = fmax(best, nrm[c]);
-    sv[tid] = best;
+    best = wmax(best);
+    if (lane == 0) s_max[wid] = best;
     __syncthreads();
-    for (int o = kBlk / 2; o > 0; o >>= 1) {
-      if (tid < o) sv[tid] = fmax(sv[tid], sv[tid + o]);
-      __syncthreads();
-    }
-    const double top = sv[0];
-    __syncthreads();
+    double top = s_max[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) top = fmax(top, s_max[w]);
     int bo = 0x7fffffff, bc = -1;
     for (int c = j + tid; c < n; c += kBlk)
       if (nrm[c] >= top * (1.0 - 1e-12) && pv[c] < bo) {
         bo = pv[c];
         bc = c;
       }
-    si[tid] = bo;
-    sv[tid] = (double)bc;
-    __syncthreads();
-    for (int o = kBlk / 2; o > 0; o >>= 1) {
-      if (tid < o && si[tid + o] < si[tid]) {
-        si[tid] = si[tid + o];
-        sv[tid] = sv[tid + o];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int ob = __shfl_xor(bo, o), oc = __shfl_xor(bc, o);
+      if (ob < bo) {
+        bo = ob;
+        bc = oc;
       }
-      __syncthreads();
     }
-    const int p = (int)sv[0];
-    __syncthreads();
-    if (tid == 0) {
-      const double rjj = sqrt(nrm[p]);
-      if (j == 0) s_r00 = rjj;
-      if (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * s_r00)) s_stop = 1;
+    if (lane == 0) {
+      s_org[wid] = bo;
+      s_col[wid] = bc;
     }
     __syncthreads();
-    if (s_stop) break;
+    int p = s_col[0], po = s_org[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (s_org[w] < po) {
+        po = s_org[w];
+        p = s_col[w];
+      }
+    // every thread takes the same stopping decision from the same values
+    const double rjj = sqrt(nrm[p]);
+    if (j == 0) r00 = rjj;
+    if (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * r00)) break;
     if (p != j) {
       for (int i = tid; i < m; i += kBlk) {
         const c64 t = A[i + (int64_t)j * lda];
         A[i + (int64_t)j * lda] = A[i + (int64_t)p * lda];
         A[i + (int64_t)p * lda] = t;
       }
-      if (tid == 0) {
-        const double t = nrm[j];
-        nrm[j] = nrm[p];
-        nrm[p] = t;
-        const int q = pv[j];
-        pv[j] = pv[p];
-        pv[p] = q;
-      }
     }
     __syncthreads();
-    // Householder reflector H = I - tau v v^H with H x = alpha e1
+    if (p != j && tid == 0) {
+      const double t = nrm[j];
+      nrm[j] = nrm[p];
+      nrm[p] = t;
+      const int q = pv[j];
+      pv[j] = pv[p];
+      pv[p] = q;
+    }
+    // Householder reflector H = I - tau v v^H with H x = alpha e1 (one wavefront)
     c64* colj = A + (int64_t)j * lda;
     const c64* v = TALL ? colj : v_lds;   // v[i] for i > j; v[j] is s_vtop
-    if (!TALL) {
-      for (int i = j + tid; i < m; i += kBlk) v_lds[i] = colj[i];
-      __syncthreads();
-    }
     if (wid == 0) {
       double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) s += abs2(TALL ? colj[i] : v_lds[i]);
+      for (int i = j + lane; i < m; i += 64) {
+        const c64 x = colj[i];
+        if (!TALL) v_lds[i] = x;
+        s += abs2(x);
+      }
       s = wsum(s);
       if (lane == 0) {
         const double xn = sqrt(s);
@@ -698,25 +793,20 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
       for (int i = j + 1 + tid; i < m; i += kBlk) colj[i] = cmk(0, 0);
     const double tau = s_tau;
     const c64 vtop = s_vtop;
-    for (int c = j + 1 + wid; c < n; c += kBlk / 64) {
-      c64* col = A + (int64_t)c * lda;
-      double wr = 0.0, wi = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const c64 a = col[i], vv = i == j ? vtop : v[i];
-        wr += vv.re * a.re + vv.im * a.im;    // conj(v) a
-        wi += vv.re * a.im - vv.im * a.re;
-      }
-      wr = wsum(wr);
-      wi = wsum(wi);
-      const c64 w = cmk(tau * wr, tau * wi);
-      double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const c64 a = col[i] - (i == j ? vtop : v[i]) * w;
-        col[i] = a;
-        if (i > j) s += abs2(a);
-      }
-      s = wsum(s);
-      if (lane == 0) nrm[c] = s;
+    const int rows = m - j;
+    for (int c0 = j + 1 + wid * G; c0 < n; c0 += NW * G) {
+      int cols[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) cols[g] = c0 + g;
+      const int ng = min(G, n - c0);
+      if (rows <= 64)
+        qr_update_cols<G, 1>(A, lda, m, j, cols, ng, v, vtop, tau, lane, nrm);
+      else if (rows <= 128)
+        qr_update_cols<G, 2>(A, lda, m, j, cols, ng, v, vtop, tau, lane, nrm);
+      else if (rows <= 256)
+        qr_update_cols<G, 4>(A, lda, m, j, cols, ng, v, vtop, tau, lane, nrm);
+      else
+        qr_update_cols<G, 0>(A, lda, m, j, cols, ng, v, vtop, tau, lane, nrm);
     }
     __syncthreads();
     if (TALL) {
