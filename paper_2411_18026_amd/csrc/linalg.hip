@@ -21,6 +21,28 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wavefront with DPP moves inside each row of 16
+// lanes (swap neighbours, swap pairs, half-row mirror, row mirror: after
+// these every lane holds its row's sum) and the four row sums read out of
+// lanes 0, 16, 32, 48.  Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline double wsum_full(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 template <typename T>
 __device__ inline T zero() {
   return Cx<T>::make(0.0, 0.0);
@@ -609,8 +631,8 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      wr[g] = wsum(wr[g]);
-      wi[g] = wsum(wi[g]);
+      wr[g] = wsum_full(wr[g]);
+      wi[g] = wsum_full(wi[g]);
     }
     double sq[G];
 #pragma unroll
@@ -631,7 +653,7 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      sq[g] = wsum(sq[g]);
+      sq[g] = wsum_full(sq[g]);
       if (lane == 0 && g < ng) nrm[cols[g]] = sq[g];
     }
   } else {
@@ -647,8 +669,8 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      wr[g] = wsum(wr[g]);
-      wi[g] = wsum(wi[g]);
+      wr[g] = wsum_full(wr[g]);
+      wi[g] = wsum_full(wi[g]);
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -661,16 +683,19 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
         col[i] = x;
         if (i > j) sq += abs2(x);
       }
-      sq = wsum(sq);
+      sq = wsum_full(sq);
       if (lane == 0) nrm[cols[g]] = sq;
     }
   }
 }
 
-__device__ inline double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+// maximum over the 64 lanes (same DPP pattern as wsum_full; every lane active)
+__device__ inline double wmax_full(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // TALL = false: the Householder vector is staged in LDS (m <= kQrMaxM,
@@ -703,7 +728,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   for (int c = d.k_start + wid; c < n; c += NW) {
     double s = 0.0;
     for (int i = d.k_start + lane; i < m; i += 64) s += abs2(A[i + (int64_t)c * lda]);
-    s = wsum(s);
+    s = wsum_full(s);
     if (lane == 0) nrm[c] = s;
   }
   double r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
@@ -713,7 +738,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
     // pivot: largest norm; ties within a relative 1e-12 -> lowest original column
     double best = -1.0;
     for (int c = j + tid; c < n; c += kBlk) best = fmax(best, nrm[c]);
-    best = wmax(best);
+    best = wmax_full(best);
     if (lane == 0) s_max[wid] = best;
     __syncthreads();
     double top = s_max[0];
@@ -775,7 +800,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
         if (!TALL) v_lds[i] = x;
         s += abs2(x);
       }
-      s = wsum(s);
+      s = wsum_full(s);
       if (lane == 0) {
         const double xn = sqrt(s);
         const c64 x0 = colj[j];
