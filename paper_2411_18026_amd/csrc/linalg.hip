@@ -844,6 +844,226 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   if (tid == 0) rank[blockIdx.x] = j;
 }
 
+// Integer minimum over the 64 lanes (same DPP pattern; every lane active).
+template <int CTRL>
+__device__ inline int dpp_move_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline int wmin_int_full(int v) {
+  v = min(v, dpp_move_int<0xB1>(v));
+  v = min(v, dpp_move_int<0x4E>(v));
+  v = min(v, dpp_move_int<0x141>(v));
+  v = min(v, dpp_move_int<0x140>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Register-resident pivoted QR for small problems (m <= 64 CH rows, n <= 8 NS
+// columns), same pivot and stopping rules as k_cpqr.  Eight wavefronts;
+// column c lives in wavefront c % 8, register slot c / 8, lane l holding
+// rows l + 64 t.  The matrix is read once and written back once; a step
+// touches only registers and LDS: every wavefront picks the pivot from the
+// norms in LDS, the two owners swap columns through LDS, the owner of
+// column j forms the reflector into LDS, and every wavefront updates its
+// columns.
+constexpr int kQrRegWaves = 8;
+constexpr int kQrRegRows = 256;
+constexpr int kQrRegCols = 64;
+
+template <int NS, int CH>
+__global__ void __launch_bounds__(64 * kQrRegWaves) k_cpqr_reg(const CpqrDesc* __restrict__ descs,
+                                                              c64* __restrict__ base, int* __restrict__ piv, double tol,
+                                                              int* __restrict__ rank) {
+  constexpr int NW = kQrRegWaves;
+  constexpr int NC = NW * NS;
+  constexpr int MR = 64 * CH;
+  static_assert(NC <= 64, "pivot keys hold the column in 6 bits");
+  __shared__ double nrm[NC];
+  __shared__ int pv[NC];
+  __shared__ c64 vbuf[MR];
+  __shared__ c64 xbuf[2][MR];
+  __shared__ double s_tau;
+  const CpqrDesc d = descs[blockIdx.x];
+  c64* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int m = d.m, n = d.n, lda = d.lda;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int kmax = min(d.k_end, min(m, n));
+  c64 a[NS][CH];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = sl * NW + wid;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int i = lane + 64 * t;
+      a[sl][t] = (c < n && i < m) ? A[i + (int64_t)c * lda] : cmk(0, 0);
+    }
+  }
+  for (int c = tid; c < n; c += 64 * NW) pv[c] = d.k_start == 0 ? c : P[c];
+  {
+    double sq[NS];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      sq[sl] = 0.0;
+#pragma unroll
+      for (int t = 0; t < CH; ++t)
+        if (lane + 64 * t >= d.k_start) sq[sl] += abs2(a[sl][t]);
+      sq[sl] = wsum_full(sq[sl]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl * NW + wid < n) nrm[sl * NW + wid] = sq[sl];
+    }
+  }
+  double r00 = d.k_start > 0 ? sqrt(abs2(A[0])) : 0.0;
+  __syncthreads();
+  int j = d.k_start;
+  for (; j < kmax; ++j) {
+    // pivot, found by every wavefront from the same LDS values: largest
+    // norm; ties within a relative 1e-12 -> lowest original column
+    const int cc = j + lane;
+    const double nv = cc < n ? nrm[cc] : -1.0;
+    const double top = wmax_full(nv);
+    const int key = (cc < n && nv >= top * (1.0 - 1e-12)) ? pv[cc] * 64 + cc : 0x7fffffff;
+    const int p = wmin_int_full(key) & 63;
+    const double rjj = sqrt(nrm[p]);
+    if (j == 0) r00 = rjj;
+    if (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * r00)) break;
+    const int wj = j % NW, sj = j / NW;
+    if (p != j) {
+      const int wp = p % NW, sp = p / NW;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        if (wid == wj && sl == sj)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) xbuf[0][lane + 64 * t] = a[sl][t];
+        if (wid == wp && sl == sp)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) xbuf[1][lane + 64 * t] = a[sl][t];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        if (wid == wj && sl == sj)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) a[sl][t] = xbuf[1][lane + 64 * t];
+        if (wid == wp && sl == sp)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) a[sl][t] = xbuf[0][lane + 64 * t];
+      }
+      if (tid == 0) {
+        const double tn = nrm[j];
+        nrm[j] = nrm[p];
+        nrm[p] = tn;
+        const int q = pv[j];
+        pv[j] = pv[p];
+        pv[p] = q;
+      }
+    }
+    // Householder reflector H = I - tau v v^H with H x = alpha e1, formed by
+    // the owner of column j: v (rows < j zero, row j its top entry) to LDS
+    if (wid == wj) {
+      c64 x[CH];
+#pragma unroll
+      for (int t = 0; t < CH; ++t) x[t] = cmk(0, 0);
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == sj)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) x[t] = a[sl][t];
+      double ss = 0.0;
+      c64 xt = cmk(0, 0);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int i = lane + 64 * t;
+        if (i >= j) ss += abs2(x[t]);
+        if (t == j / 64) xt = x[t];
+      }
+      ss = wsum_full(ss);
+      const int jl = j % 64;
+      const c64 x0 = cmk(lane_value(xt.re, jl), lane_value(xt.im, jl));
+      const double xn = sqrt(ss);
+      const double ax0 = sqrt(abs2(x0));
+      const c64 ph = ax0 > 0.0 ? cmk(x0.re / ax0, x0.im / ax0) : cmk(1.0, 0.0);
+      const c64 alpha = (-xn) * ph;
+      const c64 vtop = x0 - alpha;
+      const double vn2 = 2.0 * ss + 2.0 * ax0 * xn;
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int i = lane + 64 * t;
+        vbuf[i] = (i < j || i >= m) ? cmk(0, 0) : (i == j ? vtop : x[t]);
+      }
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == sj)
+#pragma unroll
+          for (int t = 0; t < CH; ++t) {
+            const int i = lane + 64 * t;
+            if (i == j) a[sl][t] = alpha;
+            else if (i > j) a[sl][t] = cmk(0, 0);
+          }
+      if (lane == 0) s_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    c64 vv[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) vv[t] = vbuf[lane + 64 * t];
+    double wr[NS], wi[NS];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      wr[sl] = wi[sl] = 0.0;
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        wr[sl] += vv[t].re * a[sl][t].re + vv[t].im * a[sl][t].im;   // conj(v) a
+        wi[sl] += vv[t].re * a[sl][t].im - vv[t].im * a[sl][t].re;
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      wr[sl] = wsum_full(wr[sl]);
+      wi[sl] = wsum_full(wi[sl]);
+    }
+    double sq[NS];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      sq[sl] = 0.0;
+      const int c = sl * NW + wid;
+      if (c > j && c < n) {
+        const c64 w = cmk(tau * wr[sl], tau * wi[sl]);
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+          a[sl][t] = a[sl][t] - vv[t] * w;
+          if (lane + 64 * t > j) sq[sl] += abs2(a[sl][t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) sq[sl] = wsum_full(sq[sl]);
+    if (lane == 0) {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        const int c = sl * NW + wid;
+        if (c > j && c < n) nrm[c] = sq[sl];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = sl * NW + wid;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int i = lane + 64 * t;
+      if (c < n && i < m) A[i + (int64_t)c * lda] = a[sl][t];
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < n; c += 64 * NW) P[c] = pv[c];
+  if (tid == 0) rank[blockIdx.x] = j;
+}
+
 // Multi-workgroup pivoted QR for large problems (same pivot and stopping
 // rules as k_cpqr): a host loop over steps j launches k_qrw_pivot (one
 // workgroup per problem: clear the previous reflector's column, choose the
@@ -1353,37 +1573,66 @@ int check_cpqr_sizes(const std::vector<CpqrDesc>& d) {
   return tall;
 }
 
+// small problems: register-resident kernel, sized by the group's largest problem
+static void launch_cpqr_reg(const CpqrDesc* d, int n, int mmax, int nmax, c64* base, int* piv, double tol, int* rank,
+                            hipStream_t s) {
+  const dim3 blk(64 * kQrRegWaves);
+  const int ch = (mmax + 63) / 64;
+  if (nmax <= 32) {
+    if (ch <= 2) k_cpqr_reg<4, 2><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+    else if (ch <= 3) k_cpqr_reg<4, 3><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+    else k_cpqr_reg<4, 4><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+  } else {
+    if (ch <= 2) k_cpqr_reg<8, 2><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+    else if (ch <= 3) k_cpqr_reg<8, 3><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+    else k_cpqr_reg<8, 4><<<n, blk, 0, s>>>(d, base, piv, tol, rank);
+  }
+  FDS_HIP(hipGetLastError());
+}
+
 void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, Workspace& ws,
                  const std::string& tag, hipStream_t s) {
   if (d.empty()) return;
-  std::vector<CpqrDesc> one, wide;
-  std::vector<int> one_i, wide_i;
+  // three groups: register-resident (m <= 256, n <= 64), one workgroup per
+  // problem, many workgroups per problem (large problems)
+  std::vector<CpqrDesc> grp[3];
+  std::vector<int> gidx[3];
+  int rm = 0, rn = 0;
   for (int i = 0; i < (int)d.size(); ++i) {
-    // large problems: spread each step over many workgroups
-    if ((int64_t)d[i].m * d[i].n >= kQrwMinElems || d[i].n > kQrMaxN) {
-      wide.push_back(d[i]);
-      wide_i.push_back(i);
-    } else {
-      one.push_back(d[i]);
-      one_i.push_back(i);
+    int g = 1;
+    if ((int64_t)d[i].m * d[i].n >= kQrwMinElems || d[i].n > kQrMaxN) g = 2;
+    else if (d[i].m <= kQrRegRows && d[i].n <= kQrRegCols) g = 0;
+    if (g == 0) {
+      rm = std::max(rm, d[i].m);
+      rn = std::max(rn, d[i].n);
+    }
+    grp[g].push_back(d[i]);
+    gidx[g].push_back(i);
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (grp[g].empty()) continue;
+    const std::string k = tag + (g == 0 ? "_r" : "_o");
+    const bool all = grp[g].size() == d.size();
+    int* r = all ? rank : ws.get<int>(k + "_rk", grp[g].size());
+    const CpqrDesc* dd = ws.upload(k + "_d", grp[g]);
+    if (g == 0)
+      launch_cpqr_reg(dd, (int)grp[g].size(), rm, rn, base, piv, tol, r, s);
+    else
+      launch_cpqr(dd, (int)grp[g].size(), base, piv, tol, r, s, check_cpqr_sizes(grp[g]));
+    if (!all) {
+      std::vector<int64_t> src(grp[g].size()), dst(grp[g].size());
+      for (size_t i = 0; i < grp[g].size(); ++i) {
+        src[i] = (int64_t)i;
+        dst[i] = gidx[g][i];
+      }
+      k_scatter_int<<<(unsigned)((src.size() + 255) / 256), 256, 0, s>>>(
+          (int64_t)src.size(), ws.upload(k + "_s", src), ws.upload(k + "_t", dst), r, rank);
+      FDS_HIP(hipGetLastError());
     }
   }
-  if (wide.empty()) {
-    launch_cpqr(ws.upload(tag + "_d", d), (int)d.size(), base, piv, tol, rank, s, check_cpqr_sizes(d));
-    return;
-  }
-  if (!one.empty()) {
-    int* r1 = ws.get<int>(tag + "_r1", one.size());
-    launch_cpqr(ws.upload(tag + "_d1", one), (int)one.size(), base, piv, tol, r1, s, check_cpqr_sizes(one));
-    std::vector<int64_t> src(one.size()), dst(one.size());
-    for (size_t i = 0; i < one.size(); ++i) {
-      src[i] = (int64_t)i;
-      dst[i] = one_i[i];
-    }
-    k_scatter_int<<<(unsigned)((one.size() + 255) / 256), 256, 0, s>>>(
-        (int64_t)one.size(), ws.upload(tag + "_s1", src), ws.upload(tag + "_t1", dst), r1, rank);
-    FDS_HIP(hipGetLastError());
-  }
+  if (grp[2].empty()) return;
+  const std::vector<CpqrDesc>& wide = grp[2];
+  const std::vector<int>& wide_i = gidx[2];
   int nmax = 0, mmax = 0, j0 = INT32_MAX, j1 = 0;
   int64_t ntot = 0;
   for (const CpqrDesc& x : wide) {

@@ -93,6 +93,30 @@ def test_cpqr_matches_oracle(fdsmod):
         assert np.allclose(np.abs(np.diag(R)[:k]), np.abs(np.diag(R_o)[:k]), rtol=1e-10)
 
 
+def test_cpqr_register_variants_match_oracle(fdsmod):
+    """Batches of small problems only (m <= 256, n <= 64) run the
+    register-resident kernel, sized by the batch's largest problem: one
+    batch within 128 x 32, one up to 256 x 64.  Edge cases: a zero matrix
+    (rank 0), an exact rank-one matrix, fewer rows than columns."""
+    rng = np.random.default_rng(21)
+    for shapes in (((100, 30), (64, 32), (20, 25)), ((180, 50), (256, 64), (5, 64))):
+        mats = []
+        for (m, n) in shapes:
+            M = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))) * \
+                np.logspace(0, -12, n)[None, rng.permutation(n)]
+            mats.append(M)
+        mats.append(np.zeros((40, 10), dtype=np.complex128))
+        u = rng.standard_normal(60) + 1j * rng.standard_normal(60)
+        mats.append(np.outer(u, rng.standard_normal(12)))
+        res = fdsmod.cpqr_batched(mats, 1e-8)
+        for M, (piv, k, R) in zip(mats, res):
+            p_o, R_o = ofds.cpqr(M)
+            k_o = ofds.id_rank(R_o, 1e-8)
+            assert k == k_o
+            assert np.array_equal(piv[:k], p_o[:k])
+            assert np.allclose(np.abs(np.diag(R)[:k]), np.abs(np.diag(R_o)[:k]), rtol=1e-10)
+
+
 @pytest.mark.parametrize("name", ["circle64", "two_cavities"])
 def test_load_vectors(fdsmod, name):
     curves = GEOMS[name]
