@@ -1442,12 +1442,15 @@ void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Works
                hipStream_t s) {
   if (d.empty()) return;
   // matrices whose 8-column LDS panel fits go to the one-workgroup kernels;
-  // larger ones are few per level and get the multi-workgroup form
+  // larger ones are few per level and get the multi-workgroup form, and so
+  // do the matrices above 128 of a batch of at most 8 (the root, the top
+  // levels), where one workgroup per matrix would leave the chip idle
   std::vector<LUDesc> small, big;
   std::vector<int> small_i, big_i;
   int nsmall = 0, nbig = 0;
+  const bool few = d.size() <= 8;
   for (int i = 0; i < (int)d.size(); ++i) {
-    if ((size_t)d[i].n * sizeof(T) * 8 <= 49152) {
+    if ((size_t)d[i].n * sizeof(T) * 8 <= 49152 && !(few && d[i].n > 128)) {
       small.push_back(d[i]);
       small_i.push_back(i);
       nsmall = std::max(nsmall, d[i].n);

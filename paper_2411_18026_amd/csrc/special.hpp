@@ -331,11 +331,12 @@ inline SeriesCoef make_series_coef(double beta) {
   return s;
 }
 
-template <int R>
+// row R of the table summed to K terms (K <= kSerTerms)
+template <int K, int R>
 __host__ __device__ inline double ser(double w) {
-  double p = kSerTab.c[R][kSerTerms - 1];
+  double p = kSerTab.c[R][K - 1];
 #pragma unroll
-  for (int k = kSerTerms - 2; k >= 0; --k) p = p * w + kSerTab.c[R][k];
+  for (int k = K - 2; k >= 0; --k) p = p * w + kSerTab.c[R][k];
   return p;
 }
 
@@ -369,27 +370,46 @@ __host__ __device__ inline void e_chi(double a, double beta, const Hankel2& h, c
   chi = h2a - (beta * beta) * h2b;
 }
 
-// All kernel ingredients at one point: H0(a), H1(a), H0(b), E, chi.
+// Small-argument form of the kernel ingredients with K terms of each series.
+template <int K>
+__host__ __device__ inline void series_values(double a, double w, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b,
+                                              c64& E, c64& chi) {
+  const double wb = sc.b2 * w;
+  const double L = log(0.5 * a);
+  const double tp = 2.0 / kPi;
+  const double P0 = ser<K, 0>(w), P1 = ser<K, 1>(w), P2 = ser<K, 2>(w), P3 = ser<K, 3>(w), P6 = ser<K, 4>(w), P7 = ser<K, 5>(w);
+  const double Q0 = ser<K, 0>(wb), Q1 = ser<K, 1>(wb), Q2 = ser<K, 2>(wb), Q3 = ser<K, 3>(wb), Q6 = ser<K, 4>(wb),
+               Q7 = ser<K, 5>(wb);
+  const double j1 = 0.5 * a * P2;
+  h0a = cmk(P0, tp * ((L + kEulerGamma) * P0 + P1));
+  h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * P3);
+  h0b = cmk(Q0, tp * ((L + sc.logbeta + kEulerGamma) * Q0 + Q1));
+  const double e = 0.5 * (P2 - sc.b2 * Q2);
+  const double e1 = -(0.5 / kPi) * (P3 - sc.b2 * Q3) - (sc.logbeta / kPi) * sc.b2 * Q2;
+  E = cmk(e, tp * L * e + e1);
+  const double c = P6 - sc.b4 * Q6;
+  const double c1 = -(1.0 / kPi) * (P7 - sc.b4 * Q7) - (2.0 * sc.logbeta / kPi) * sc.b4 * Q6;
+  chi = cmk(w * c, sc.chi0 + w * (tp * L * c + c1));
+}
+
+// All kernel ingredients at one point: H0(a), H1(a), H0(b), E, chi.  Below
+// kSeriesSwitch the series are summed to as many terms as the point's
+// w = a^2/4 needs (the neglected tail stays below 4e-19 for every row: 4
+// terms for w < 1e-4, 6 for w < 5e-3, 8 for w < 5e-2, else 10).  The choice
+// depends on the point alone, so a result does not depend on which other
+// points share its wavefront.
 __host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b, c64& E,
                                               c64& chi) {
   if (a < kSeriesSwitch) {
     const double w = 0.25 * a * a;
-    const double wb = sc.b2 * w;
-    const double L = log(0.5 * a);
-    const double tp = 2.0 / kPi;
-    const double P0 = ser<0>(w), P1 = ser<1>(w), P2 = ser<2>(w), P3 = ser<3>(w), P6 = ser<4>(w), P7 = ser<5>(w);
-    const double Q0 = ser<0>(wb), Q1 = ser<1>(wb), Q2 = ser<2>(wb), Q3 = ser<3>(wb), Q6 = ser<4>(wb),
-                 Q7 = ser<5>(wb);
-    const double j1 = 0.5 * a * P2;
-    h0a = cmk(P0, tp * ((L + kEulerGamma) * P0 + P1));
-    h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * P3);
-    h0b = cmk(Q0, tp * ((L + sc.logbeta + kEulerGamma) * Q0 + Q1));
-    const double e = 0.5 * (P2 - sc.b2 * Q2);
-    const double e1 = -(0.5 / kPi) * (P3 - sc.b2 * Q3) - (sc.logbeta / kPi) * sc.b2 * Q2;
-    E = cmk(e, tp * L * e + e1);
-    const double c = P6 - sc.b4 * Q6;
-    const double c1 = -(1.0 / kPi) * (P7 - sc.b4 * Q7) - (2.0 * sc.logbeta / kPi) * sc.b4 * Q6;
-    chi = cmk(w * c, sc.chi0 + w * (tp * L * c + c1));
+    if (w >= 5e-2)
+      series_values<10>(a, w, sc, h0a, h1a, h0b, E, chi);
+    else if (w >= 5e-3)
+      series_values<8>(a, w, sc, h0a, h1a, h0b, E, chi);
+    else if (w >= 1e-4)
+      series_values<6>(a, w, sc, h0a, h1a, h0b, E, chi);
+    else
+      series_values<4>(a, w, sc, h0a, h1a, h0b, E, chi);
     return;
   }
   const Hankel2 h = hankel_pair(a, sc.beta * a);
