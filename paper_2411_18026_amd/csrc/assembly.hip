@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(256) k_classify(const Tile* __restrict__ tiles
     cls[j] = -1;
     if (li < t.count) {
       const int64_t p = t.start + li;
-      const int ie = (int)(p / jb.nce), je = (int)(p % jb.nce);
+      int ie, je;
+      pair_elems(jb, p, ie, je);
       const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
       cls[j] = classify_pair(elems[ge], elems[gf], ge, gf);
     }
@@ -327,8 +328,7 @@ __device__ inline void decode(unsigned long long key, const Job* jobs, const int
   const int job = (int)(key >> 32);
   const int64_t p = (int64_t)(key & 0xffffffffull);
   jb = jobs[job];
-  ie = (int)(p / jb.nce);
-  je = (int)(p % jb.nce);
+  pair_elems(jb, p, ie, je);
   ge = elist[jb.re_off + ie];
   gf = elist[jb.ce_off + je];
 }
@@ -362,7 +362,7 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
       acc_point_direct(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   }
-  const int64_t slot = jb.pair_off + (int64_t)ie * jb.nce + je;
+  const int64_t slot = pair_slot(jb, ie, je);
 #pragma unroll
   for (int k = 0; k < 16; ++k) res[k * np + slot] = A.R[k];
 }
@@ -445,7 +445,7 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
       acc_point(m, up * Ax - vp * Bx, up * Ay - vp * By, c_quad.aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny, A);
     }
   }
-  const int64_t slot = jb.pair_off + (int64_t)ie * jb.nce + je;
+  const int64_t slot = pair_slot(jb, ie, je);
 #pragma unroll
   for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
@@ -471,7 +471,9 @@ __global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__
   if ((int)threadIdx.x >= t.count) return;
   const Job jb = jobs[t.job];
   const int64_t item = t.start + threadIdx.x;
-  const int r = (int)(item % jb.nrd), c = (int)(item / jb.nrd);
+  // consecutive threads: consecutive output entries and pair results
+  const bool rf = job_rows_fast(jb);
+  const int r = (int)(rf ? item % jb.nrd : item / jb.ncd), c = (int)(rf ? item / jb.nrd : item % jb.ncd);
   const Dof dr = dofs[jb.rd_off + r];
   const Dof dc = dofs[jb.cd_off + c];
   const int k = dr.comp * 2 + dc.comp;
@@ -483,7 +485,7 @@ __global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
-      const int64_t slot = jb.pair_off + (int64_t)ier[x] * jb.nce + jec[y];
+      const int64_t slot = pair_slot(jb, ier[x], jec[y]);
       s += res[(ia[x] * 8 + jb2[y] * 4 + k) * np + slot];
     }
   const int64_t rp = jb.rpos_off >= 0 ? pos[jb.rpos_off + r] : r;

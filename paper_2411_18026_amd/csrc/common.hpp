@@ -35,10 +35,12 @@ struct MatConst {
 // elements (global ids into the element table) and a list of DOFs; a DOF
 // refers to the two elements of its hat (as indices into the side's element
 // list: ``eL`` the element the node ends, ``eR`` the element it starts) and
-// a displacement component.  Element-pair results for the job live at
-// pair_off + ie * nce + je.  The output entry for DOFs (r, c) goes to
+// a displacement component.  The output entry for DOFs (r, c) goes to
 // out[out_off + rpos(r) * rs + cpos(c) * cs], rpos = identity when
-// rpos_off < 0.
+// rpos_off < 0.  Element-pair results for the job live at pair_off +
+// je * nre + ie when the output's rows are its fast direction (rs == 1, or
+// cs != 1), else at pair_off + ie * nce + je: the gather then walks the
+// output in its fast direction and reads the pair results in order.
 struct Job {
   int64_t pair_off;
   int64_t out_off;
@@ -49,6 +51,21 @@ struct Job {
   int cd_off, ncd;
   int rpos_off, cpos_off;
 };
+
+__host__ __device__ inline bool job_rows_fast(const Job& j) { return j.rs == 1 || j.cs != 1; }
+__host__ __device__ inline int64_t pair_slot(const Job& j, int ie, int je) {
+  return j.pair_off + (job_rows_fast(j) ? (int64_t)je * j.nre + ie : (int64_t)ie * j.nce + je);
+}
+// the element pair of a job's pair number p (its slot is pair_off + p)
+__host__ __device__ inline void pair_elems(const Job& j, int64_t p, int& ie, int& je) {
+  if (job_rows_fast(j)) {
+    ie = (int)(p % j.nre);
+    je = (int)(p / j.nre);
+  } else {
+    ie = (int)(p / j.nce);
+    je = (int)(p % j.nce);
+  }
+}
 
 struct Dof {
   int eL, eR, comp, pad;
