@@ -476,7 +476,15 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     if (r0 < rs)
       for (int i = k0 + nb + r0; i < n; i += rs) {
         T s = X[i + cc * n];
-        for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        if (nb == SB) {   // full block: all loads of the factor in flight at once
+          T a[SB];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) s -= a[q] * X[k0 + q + cc * n];
+        } else {
+          for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        }
         X[i + cc * n] = s;
       }
     __syncthreads();
@@ -508,7 +516,15 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     if (r0 < rs)
       for (int i = r0; i < k0; i += rs) {
         T s = X[i + cc * n];
-        for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        if (nb == SB) {
+          T a[SB];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) s -= a[q] * X[k0 + q + cc * n];
+        } else {
+          for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+        }
         X[i + cc * n] = s;
       }
     __syncthreads();
