@@ -684,8 +684,18 @@ static void pair_and_extend(Factor& F, CellLevel& lv, const std::vector<int>& ce
   }
   if (!ev.empty() || !eu.empty()) {
     int* drank2 = ws.get<int>("id_rank2", ev.size() + eu.size());
-    cpqr_factor(ev, baseV, dpiv, tol, drank2, ws, "cpqr_v2", F.stream);
-    cpqr_factor(eu, baseU, dpiv, tol, drank2 + ev.size(), ws, "cpqr_u2", F.stream);
+    // one launch when the U matrices lie in the V matrices' allocation
+    if (baseU >= baseV) {
+      std::vector<CpqrDesc> both = ev;
+      for (CpqrDesc x : eu) {
+        x.a_off += baseU - baseV;
+        both.push_back(x);
+      }
+      cpqr_factor(both, baseV, dpiv, tol, drank2, ws, "cpqr_vu2", F.stream);
+    } else {
+      cpqr_factor(ev, baseV, dpiv, tol, drank2, ws, "cpqr_v2", F.stream);
+      cpqr_factor(eu, baseU, dpiv, tol, drank2 + ev.size(), ws, "cpqr_u2", F.stream);
+    }
     auto h = download(ws, drank2, ev.size() + eu.size());
     for (size_t i = 0; i < ev.size(); ++i) rv[ev_i[i]] = h[i];
     for (size_t i = 0; i < eu.size(); ++i) ru[eu_i[i]] = h[ev.size() + i];
@@ -712,8 +722,13 @@ static void adaptive_ids(Factor& F, CellLevel& lv, const std::vector<int>& cells
       du[2 * ci + comp] = qu[2 * cells[ci] + comp];
     }
   int* drank = ws.get<int>("id_rank", 4 * nc);
-  cpqr_factor(dv, MV, dpiv, F.tol, drank, ws, "cpqr_v", F.stream);
-  cpqr_factor(du, MU, dpiv, F.tol, drank + 2 * nc, ws, "cpqr_u", F.stream);
+  // V and U problems in one launch (MU lies in the same allocation after MV)
+  std::vector<CpqrDesc> both = dv;
+  for (CpqrDesc x : du) {
+    x.a_off += MU - MV;
+    both.push_back(x);
+  }
+  cpqr_factor(both, MV, dpiv, F.tol, drank, ws, "cpqr_vu", F.stream);
   auto rk = download(ws, drank, 4 * nc);
   std::vector<int> rv(rk.begin(), rk.begin() + 2 * nc), ru(rk.begin() + 2 * nc, rk.end());
   pair_and_extend(F, lv, cells, dv, du, rv, ru, MV, MU, dpiv, F.tol);
@@ -1103,8 +1118,9 @@ static void compress_level(Factor& F, int lev) {
   }
   if (F.opt.rank_mode == FDS_RANK_LEARNED) launch_predictions(F, lev, crd, mv_m);
   auto ht1 = std::make_unique<HostTimer>(1);
-  c64* MV = ws.get<c64>("MV", (size_t)mv_tot);
-  c64* MU = ws.get<c64>("MU", (size_t)mu_tot);
+  // one allocation: the V and U problems of a level then share each QR launch
+  c64* MV = ws.get<c64>("MVU", (size_t)(mv_tot + mu_tot));
+  c64* MU = MV + mv_tot;
   {
     std::vector<BlockReq> reqs(n);
     parallel_for(n, [&](int q) {
