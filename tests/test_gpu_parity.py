@@ -202,6 +202,33 @@ def test_graph_solve_replays_match_eager(fdsmod):
     assert torch.equal(x1, Fe.solve(rhs[1]))
 
 
+def test_device_block_cache_reuse_and_release(fdsmod):
+    """Device buffers come from the library's block cache: a destroyed
+    factor's blocks stay cached and are reused by the next factor (which
+    gives bitwise the same solution), the cache empties on release, and a
+    factor built after the release (fresh allocations) again gives the same
+    solution."""
+    import gc
+    curves = [sy.ellipse(400, 1.0, 0.5)]
+    F1 = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    rhs = F1.rhs_plane([0, 1], [0.2, 1.1])
+    x1 = F1.solve(rhs)
+    torch.cuda.synchronize()
+    del F1
+    gc.collect()
+    cached = fdsmod.cached_bytes()
+    assert cached > 0
+    F2 = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    assert fdsmod.cached_bytes() < cached
+    assert torch.equal(F2.solve(rhs), x1)
+    del F2
+    gc.collect()
+    fdsmod.release_cache()
+    assert fdsmod.cached_bytes() == 0
+    F3 = fdsmod.Factor(curves, 3.0, 2.0, 1.0, 1.0, 1e-9, leaf=32)
+    assert torch.equal(F3.solve(rhs), x1)
+
+
 def test_cpqr_tall_variant_matches_oracle(fdsmod):
     """Matrices beyond the LDS-staged sizes (more than 2048 rows or 1024
     columns) go through the variant that reads the reflector in place."""
