@@ -63,6 +63,12 @@ __device__ inline void cfma(c32& acc, c32 a, c32 b) {
   acc.im = fmaf(a.im, b.re, acc.im);
 }
 
+// acc -= a b with explicit fused multiply-adds (same rounding in every kernel)
+template <typename T>
+__device__ inline void cfms(T& acc, T a, T b) {
+  cfma(acc, Cx<T>::make(-(double)a.re, -(double)a.im), b);
+}
+
 template <typename TD, typename TS>
 __device__ inline TD cvt(TS a) {
   return Cx<TD>::make((double)a.re, (double)a.im);
@@ -468,7 +474,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         T xq;
         xq.re = __shfl(x.re, src);
         xq.im = __shfl(x.im, src);
-        if (br > q) x -= l[q] * xq;
+        if (br > q) cfms(x, l[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
     }
@@ -481,9 +487,9 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 #pragma unroll
           for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
 #pragma unroll
-          for (int q = 0; q < SB; ++q) s -= a[q] * X[k0 + q + cc * n];
+          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * n]);
         } else {
-          for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * n]);
         }
         X[i + cc * n] = s;
       }
@@ -508,7 +514,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         T xq;
         xq.re = __shfl(x.re, src);
         xq.im = __shfl(x.im, src);
-        if (q < nb && br < q) x -= u[q] * xq;
+        if (q < nb && br < q) cfms(x, u[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
     }
@@ -521,14 +527,142 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 #pragma unroll
           for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
 #pragma unroll
-          for (int q = 0; q < SB; ++q) s -= a[q] * X[k0 + q + cc * n];
+          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * n]);
         } else {
-          for (int q = 0; q < nb; ++q) s -= A[i + (int64_t)(k0 + q) * lda] * X[k0 + q + cc * n];
+          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * n]);
         }
         X[i + cc * n] = s;
       }
     __syncthreads();
   }
+  for (int t = tid; t < n * nc; t += kBlk) {
+    const int i = t % n, c = t / n;
+    B[i + (int64_t)c * d.ldb] = X[i + c * n];
+  }
+}
+
+// Triangular solves with many right-hand sides, NC (16 or 32) columns per
+// workgroup.  The diagonal 16 x 16 blocks are solved one column per thread
+// with the block staged in LDS; the updates of the other rows are small
+// GEMMs, two threads per row each owning NC/2 columns: the row of the factor
+// is read once from memory (consecutive threads, consecutive rows) and the
+// solved rows are broadcast from LDS.  Every entry sees the same operations
+// in the same order as in k_lu_solve (explicit fused multiply-adds), so the
+// two kernels give identical results and the chunk width is a pure launch
+// choice.
+template <typename T, int NC>
+__global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restrict__ descs, int ncol_override,
+                                                        const T* __restrict__ abase, const int* __restrict__ piv,
+                                                        T* __restrict__ bbase) {
+  constexpr int SB = 16, CPT = NC / 2, RPP = kBlk / 2;
+  extern __shared__ unsigned char smem_sw[];
+  T* X = reinterpret_cast<T*>(smem_sw);   // n x NC, column-major (ld n)
+  const SolveDesc d = descs[blockIdx.x];
+  const int ncol = ncol_override > 0 ? ncol_override : d.ncol;
+  const int c0 = blockIdx.y * NC;
+  if (c0 >= ncol || d.n == 0) return;
+  const T* A = abase + d.a_off;
+  const int* P = piv + d.piv_off;
+  T* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
+  const int n = d.n, lda = d.lda, nc = min(NC, ncol - c0);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * NC; t += kBlk) {
+    const int i = t % n, c = t / n;
+    X[i + c * n] = c < nc ? B[i + (int64_t)c * d.ldb] : zero<T>();
+  }
+  __syncthreads();
+  if (tid < nc) {
+    for (int j = 0; j < n; ++j) {
+      const int p = P[j];
+      if (p != j) {
+        const T t = X[j + tid * n];
+        X[j + tid * n] = X[p + tid * n];
+        X[p + tid * n] = t;
+      }
+    }
+  }
+  const int tr = tid % RPP, cg = (tid / RPP) * CPT;   // update: row slot, first column
+  const int br = tid & 15, bc = tid >> 4;             // diagonal: row in block, column
+  // forward substitution with unit L
+  for (int k0 = 0; k0 < n; k0 += SB) {
+    const int nb = min(SB, n - k0);
+    __syncthreads();
+    // diagonal block: 16 lanes per column (one row each), 16 columns at a time
+    for (int cgd = 0; cgd < nc; cgd += 16) {
+      const int col = cgd + bc;
+      const bool act = col < nc && br < nb;
+      T x = act ? X[k0 + br + col * n] : zero<T>();
+      T l[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
+#pragma unroll
+      for (int q = 0; q < SB - 1; ++q) {
+        const int src = ((tid & 63) & ~15) + q;
+        T xq;
+        xq.re = __shfl(x.re, src);
+        xq.im = __shfl(x.im, src);
+        if (br > q) cfms(x, l[q], xq);
+      }
+      if (act) X[k0 + br + col * n] = x;
+    }
+    __syncthreads();
+    for (int i = k0 + nb + tr; i < n; i += RPP) {
+      T l[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) l[q] = q < nb ? A[i + (int64_t)(k0 + q) * lda] : zero<T>();
+      T acc[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) acc[c] = X[i + (cg + c) * n];
+#pragma unroll 4
+      for (int q = 0; q < SB; ++q)
+        if (q < nb)
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) cfms(acc[c], l[q], X[k0 + q + (cg + c) * n]);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) X[i + (cg + c) * n] = acc[c];
+    }
+  }
+  // backward substitution with U, from the bottom
+  for (int k1 = n; k1 > 0; k1 -= SB) {
+    const int k0 = max(0, k1 - SB), nb = k1 - k0;
+    __syncthreads();
+    for (int cgd = 0; cgd < nc; cgd += 16) {
+      const int col = cgd + bc;
+      const bool act = col < nc && br < nb;
+      T x = act ? X[k0 + br + col * n] : zero<T>();
+      T u[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q)
+        u[q] = (act && q >= br && q < nb) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
+#pragma unroll
+      for (int q = SB - 1; q >= 0; --q) {
+        if (act && q < nb && br == q) x = cdiv(x, u[q]);
+        const int src = ((tid & 63) & ~15) + q;
+        T xq;
+        xq.re = __shfl(x.re, src);
+        xq.im = __shfl(x.im, src);
+        if (q < nb && br < q) cfms(x, u[q], xq);
+      }
+      if (act) X[k0 + br + col * n] = x;
+    }
+    __syncthreads();
+    for (int i = tr; i < k0; i += RPP) {
+      T u[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) u[q] = q < nb ? A[i + (int64_t)(k0 + q) * lda] : zero<T>();
+      T acc[CPT];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) acc[c] = X[i + (cg + c) * n];
+#pragma unroll 4
+      for (int q = 0; q < SB; ++q)
+        if (q < nb)
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) cfms(acc[c], u[q], X[k0 + q + (cg + c) * n]);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) X[i + (cg + c) * n] = acc[c];
+    }
+  }
+  __syncthreads();
   for (int t = tid; t < n * nc; t += kBlk) {
     const int i = t % n, c = t / n;
     B[i + (int64_t)c * d.ldb] = X[i + c * n];
@@ -1549,10 +1683,17 @@ void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol
   if (chunk > 0 && (size_t)std::max(1, nmax) * chunk * sizeof(T) <= 65536) nc = chunk;
   if ((size_t)nmax * nc * sizeof(T) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
   dim3 grid(n, (ncol_max + nc - 1) / nc);
-  if (nc > 8)
+  if (nc == 16 || nc == 32) {
+    // many right-hand sides: diagonal blocks per column, updates as small GEMMs
+    if (nc == 16)
+      k_lu_solve_wide<T, 16><<<grid, kBlk, nmax * 16 * sizeof(T), s>>>(d, ncol_override, abase, piv, bbase);
+    else
+      k_lu_solve_wide<T, 32><<<grid, kBlk, nmax * 32 * sizeof(T), s>>>(d, ncol_override, abase, piv, bbase);
+  } else if (nc > 8) {
     k_lu_solve<T, true><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
-  else
+  } else {
     k_lu_solve<T, false><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
+  }
   FDS_HIP(hipGetLastError());
 }
 
