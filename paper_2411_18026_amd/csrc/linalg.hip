@@ -63,6 +63,30 @@ __device__ inline void cfma(c32& acc, c32 a, c32 b) {
   acc.im = fmaf(a.im, b.re, acc.im);
 }
 
+// Value of lane q of each row of 16 lanes, broadcast to the row (DPP
+// row_newbcast: a register move, no LDS round trip).  All lanes active.
+template <int Q>
+__device__ inline double row_bcast_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + Q, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + Q, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int Q>
+__device__ inline float row_bcast_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + Q, 0xF, 0xF, false));
+}
+template <typename T>
+__device__ inline T row_bcast(T v, int q) {   // q is a constant once the caller's loop is unrolled
+  switch (q) {
+#define FDS_RB(Q) \
+  case Q: v.re = row_bcast_lane<Q>(v.re); v.im = row_bcast_lane<Q>(v.im); return v;
+    FDS_RB(0) FDS_RB(1) FDS_RB(2) FDS_RB(3) FDS_RB(4) FDS_RB(5) FDS_RB(6) FDS_RB(7)
+    FDS_RB(8) FDS_RB(9) FDS_RB(10) FDS_RB(11) FDS_RB(12) FDS_RB(13) FDS_RB(14) FDS_RB(15)
+#undef FDS_RB
+    default: return v;
+  }
+}
+
 // acc -= a b with explicit fused multiply-adds (same rounding in every kernel)
 template <typename T>
 __device__ inline void cfms(T& acc, T a, T b) {
@@ -470,10 +494,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
       for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
 #pragma unroll
       for (int q = 0; q < SB - 1; ++q) {
-        const int src = ((tid & 63) & ~15) + q;
-        T xq;
-        xq.re = __shfl(x.re, src);
-        xq.im = __shfl(x.im, src);
+        const T xq = row_bcast(x, q);
         if (br > q) cfms(x, l[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
@@ -510,10 +531,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 #pragma unroll
       for (int q = SB - 1; q >= 0; --q) {
         if (act && q < nb && br == q) x = cdiv(x, u[q]);
-        const int src = ((tid & 63) & ~15) + q;
-        T xq;
-        xq.re = __shfl(x.re, src);
-        xq.im = __shfl(x.im, src);
+        const T xq = row_bcast(x, q);
         if (q < nb && br < q) cfms(x, u[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
@@ -597,10 +615,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restr
       for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
 #pragma unroll
       for (int q = 0; q < SB - 1; ++q) {
-        const int src = ((tid & 63) & ~15) + q;
-        T xq;
-        xq.re = __shfl(x.re, src);
-        xq.im = __shfl(x.im, src);
+        const T xq = row_bcast(x, q);
         if (br > q) cfms(x, l[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
@@ -637,10 +652,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restr
 #pragma unroll
       for (int q = SB - 1; q >= 0; --q) {
         if (act && q < nb && br == q) x = cdiv(x, u[q]);
-        const int src = ((tid & 63) & ~15) + q;
-        T xq;
-        xq.re = __shfl(x.re, src);
-        xq.im = __shfl(x.im, src);
+        const T xq = row_bcast(x, q);
         if (q < nb && br < q) cfms(x, u[q], xq);
       }
       if (act) X[k0 + br + col * n] = x;
