@@ -1619,7 +1619,7 @@ static void autotune_sweeps(Factor& F) {
     const int nrhs = reps[c];
     float best = 1e30f;
     for (int chunk = std::max(1, nrhs / 16); chunk <= 32 && chunk <= std::max(nrhs, 1); chunk *= 2) {
-      if ((size_t)P.bmax * chunk * sizeof(c64) > 65536) break;
+      if (lu_solve_smem(P.bmax, chunk, sizeof(c64)) > 65536) break;
       const float ms = timed([&] {
         launch_lu_solve(P.lu.p, n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, Fb, s, chunk);
       });

@@ -445,10 +445,61 @@ __global__ void k_scatter_int(int64_t n, const int64_t* __restrict__ sidx, const
 // diagonal block is solved by 16 lanes per column with shuffles, the rest
 // of the chunk is updated with one barrier pair per block.
 // WIDE: more than 8 columns per workgroup (diagonal blocks in groups of 8).
+// Rows of the right-hand sides in pivoted order: the row interchanges of
+// the LU (row j with row P[j], j ascending) composed into one permutation in
+// LDS by one thread (pivots staged first, so no step waits on memory), then
+// X(i, c) = B(perm(i), c) gathered by all threads; columns c >= nc are
+// zero.  perm and pv: 2 n ints of LDS.  Without room for them (staged =
+// 0: very large single matrices) the interchanges are applied to X in place,
+// one thread per column, with the same result.
+template <typename T>
+__device__ inline void load_permuted(const T* __restrict__ B, int64_t ldb, const int* __restrict__ P, int n, int nc,
+                                     int ncols, T* __restrict__ X, int* perm, int* pv, int staged) {
+  const int tid = threadIdx.x;
+  if (!staged) {
+    for (int t = tid; t < n * ncols; t += kBlk) {
+      const int i = t % n, c = t / n;
+      X[i + c * n] = c < nc ? B[i + (int64_t)c * ldb] : zero<T>();
+    }
+    __syncthreads();
+    if (tid < nc)
+      for (int j = 0; j < n; ++j) {
+        const int p = P[j];
+        if (p != j) {
+          const T t = X[j + tid * n];
+          X[j + tid * n] = X[p + tid * n];
+          X[p + tid * n] = t;
+        }
+      }
+    __syncthreads();
+    return;
+  }
+  for (int t = tid; t < n; t += kBlk) {
+    perm[t] = t;
+    pv[t] = P[t];
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (int j = 0; j < n; ++j) {
+      const int p = pv[j];
+      if (p != j) {
+        const int a = perm[j];
+        perm[j] = perm[p];
+        perm[p] = a;
+      }
+    }
+  __syncthreads();
+  for (int t = tid; t < n * ncols; t += kBlk) {
+    const int i = t % n, c = t / n;
+    X[i + c * n] = c < nc ? B[perm[i] + (int64_t)c * ldb] : zero<T>();
+  }
+  __syncthreads();
+}
+
 template <typename T, bool WIDE>
 __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, int chunk, int ncol_override,
                                                    const T* __restrict__ abase, const int* __restrict__ piv,
-                                                   T* __restrict__ bbase) {
+                                                   T* __restrict__ bbase, int staged) {
   extern __shared__ unsigned char smem_sv[];
   T* X = reinterpret_cast<T*>(smem_sv);
   const SolveDesc d = descs[blockIdx.x];
@@ -460,22 +511,8 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   T* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
   const int n = d.n, lda = d.lda, nc = min(chunk, ncol - c0);
   const int tid = threadIdx.x;
-  for (int t = tid; t < n * nc; t += kBlk) {
-    const int i = t % n, c = t / n;
-    X[i + c * n] = B[i + (int64_t)c * d.ldb];
-  }
-  __syncthreads();
-  if (tid < nc) {
-    for (int j = 0; j < n; ++j) {
-      const int p = P[j];
-      if (p != j) {
-        const T t = X[j + tid * n];
-        X[j + tid * n] = X[p + tid * n];
-        X[p + tid * n] = t;
-      }
-    }
-  }
-  __syncthreads();
+  int* perm = reinterpret_cast<int*>(X + (size_t)n * chunk);
+  load_permuted(B, d.ldb, P, n, nc, nc, X, perm, perm + n, staged);
   const int cc = tid % nc;
   const int r0 = tid / nc;
   const int rs = kBlk / nc;
@@ -571,7 +608,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
 template <typename T, int NC>
 __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restrict__ descs, int ncol_override,
                                                         const T* __restrict__ abase, const int* __restrict__ piv,
-                                                        T* __restrict__ bbase) {
+                                                        T* __restrict__ bbase, int staged) {
   constexpr int SB = 16, CPT = NC / 2, RPP = kBlk / 2;
   extern __shared__ unsigned char smem_sw[];
   T* X = reinterpret_cast<T*>(smem_sw);   // n x NC, column-major (ld n)
@@ -584,21 +621,8 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restr
   T* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
   const int n = d.n, lda = d.lda, nc = min(NC, ncol - c0);
   const int tid = threadIdx.x;
-  for (int t = tid; t < n * NC; t += kBlk) {
-    const int i = t % n, c = t / n;
-    X[i + c * n] = c < nc ? B[i + (int64_t)c * d.ldb] : zero<T>();
-  }
-  __syncthreads();
-  if (tid < nc) {
-    for (int j = 0; j < n; ++j) {
-      const int p = P[j];
-      if (p != j) {
-        const T t = X[j + tid * n];
-        X[j + tid * n] = X[p + tid * n];
-        X[p + tid * n] = t;
-      }
-    }
-  }
+  int* perm = reinterpret_cast<int*>(X + (size_t)n * NC);
+  load_permuted(B, d.ldb, P, n, nc, NC, X, perm, perm + n, staged);
   const int tr = tid % RPP, cg = (tid / RPP) * CPT;   // update: row slot, first column
   const int br = tid & 15, bc = tid >> 4;             // diagonal: row in block, column
   // forward substitution with unit L
@@ -628,7 +652,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restr
       T acc[CPT];
 #pragma unroll
       for (int c = 0; c < CPT; ++c) acc[c] = X[i + (cg + c) * n];
-#pragma unroll 4
+#pragma unroll
       for (int q = 0; q < SB; ++q)
         if (q < nb)
 #pragma unroll
@@ -665,7 +689,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve_wide(const SolveDesc* __restr
       T acc[CPT];
 #pragma unroll
       for (int c = 0; c < CPT; ++c) acc[c] = X[i + (cg + c) * n];
-#pragma unroll 4
+#pragma unroll
       for (int q = 0; q < SB; ++q)
         if (q < nb)
 #pragma unroll
@@ -1686,25 +1710,34 @@ void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Works
 }
 
 int solve_chunk(int nmax) { return std::max(1, std::min(8, 32768 / (16 * std::max(1, nmax)))); }
+// LDS of an LU solve launch: the n x chunk block plus the pivots and the
+// composed permutation (2 n ints)
+size_t lu_solve_smem(int nmax, int chunk, size_t elem) {
+  const size_t n = (size_t)std::max(1, nmax);
+  return n * (size_t)chunk * elem + 2 * n * sizeof(int);
+}
 
 template <typename T>
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
                      const int* piv, T* bbase, hipStream_t s, int chunk) {
   if (n == 0 || ncol_max == 0) return;
   int nc = solve_chunk(nmax);
-  if (chunk > 0 && (size_t)std::max(1, nmax) * chunk * sizeof(T) <= 65536) nc = chunk;
-  if ((size_t)nmax * nc * sizeof(T) > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  if (chunk > 0 && lu_solve_smem(nmax, chunk, sizeof(T)) <= 65536) nc = chunk;
+  // the pivots staged in LDS when they fit next to the block (else in place)
+  const int staged = lu_solve_smem(nmax, nc, sizeof(T)) <= 65536 ? 1 : 0;
+  const size_t smem = staged ? lu_solve_smem(nmax, nc, sizeof(T)) : (size_t)std::max(1, nmax) * nc * sizeof(T);
+  if (smem > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
   dim3 grid(n, (ncol_max + nc - 1) / nc);
   if (nc == 16 || nc == 32) {
     // many right-hand sides: diagonal blocks per column, updates as small GEMMs
     if (nc == 16)
-      k_lu_solve_wide<T, 16><<<grid, kBlk, nmax * 16 * sizeof(T), s>>>(d, ncol_override, abase, piv, bbase);
+      k_lu_solve_wide<T, 16><<<grid, kBlk, smem, s>>>(d, ncol_override, abase, piv, bbase, staged);
     else
-      k_lu_solve_wide<T, 32><<<grid, kBlk, nmax * 32 * sizeof(T), s>>>(d, ncol_override, abase, piv, bbase);
+      k_lu_solve_wide<T, 32><<<grid, kBlk, smem, s>>>(d, ncol_override, abase, piv, bbase, staged);
   } else if (nc > 8) {
-    k_lu_solve<T, true><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
+    k_lu_solve<T, true><<<grid, kBlk, smem, s>>>(d, nc, ncol_override, abase, piv, bbase, staged);
   } else {
-    k_lu_solve<T, false><<<grid, kBlk, nmax * nc * sizeof(T), s>>>(d, nc, ncol_override, abase, piv, bbase);
+    k_lu_solve<T, false><<<grid, kBlk, smem, s>>>(d, nc, ncol_override, abase, piv, bbase, staged);
   }
   FDS_HIP(hipGetLastError());
 }

@@ -75,6 +75,8 @@ void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Works
 int solve_chunk(int nmax);
 // chunk > 0: right-hand-side columns per workgroup (if its LDS staging fits),
 // else solve_chunk(nmax)
+// LDS bytes of an LU-solve launch for blocks up to nmax rows, chunk columns
+size_t lu_solve_smem(int nmax, int chunk, size_t elem);
 template <typename T>
 void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol_override, const T* abase,
                      const int* piv, T* bbase, hipStream_t s, int chunk = 0);
