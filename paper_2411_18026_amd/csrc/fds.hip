@@ -586,6 +586,15 @@ static void place_child_at(Factor& F, int lev, Off dst_off, Ld dst_ld, c32* dst,
 }
 
 // Inverse-free elimination of one level (Section 6.2) in the scalar type of
+// right-hand-side columns per workgroup of the elimination's triangular
+// solves (many columns: the updates run as small GEMMs): 32 where the
+// staged block fits in LDS, else 16, else the default
+static int elim_chunk(int nmax, size_t elem) {
+  for (int c : {32, 16})
+    if (lu_solve_smem(nmax, c, elem) <= 65536) return c;
+  return 0;
+}
+
 // the buffers: LU(A_i) in place; X_i <- A_i^{-1} X_i; S_i = V_i X_i; LU(S_i);
 // At_i = S_i^{-1} (the LU of S_i applied to the identity).
 template <typename T>
@@ -602,7 +611,8 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
   }
   int* info = ws.get<int>("lu_info", (size_t)n);
   lu_factor(ld, A, lv.piv.p, info, ws, "lu_desc", s);
-  launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, A, lv.piv.p, X, s);
+  launch_lu_solve(ws.upload("x_desc", sd), (int)sd.size(), lv.bmax, rmax, 0, A, lv.piv.p, X, s,
+                  elim_chunk(lv.bmax, sizeof(T)));
   T* S = ws.get<T>("S" + tag, (size_t)std::max<int64_t>(lv.at_tot, 1));
   std::vector<GemmDesc> gd;
   std::vector<LUDesc> lds;
@@ -636,7 +646,8 @@ static void eliminate(Factor& F, CellLevel& lv, int rmax, T* A, T* X, T* V, T* A
     int* dn = ws.upload("id_n", id_n);
     launch_fill_identity((int64_t)id_off.size(), ws.upload("id_off", id_off), dn, dn, At, s);
   }
-  launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, At, s);
+  launch_lu_solve(ws.upload("at_desc", sds), (int)sds.size(), rmax, rmax, 0, S, lv.s_piv.p, At, s,
+                  elim_chunk(rmax, sizeof(T)));
   // zero pivots are reported once the build has finished (no wait here)
   launch_flag_nonzero(n, info, F.sing.p + lv.lev, s);
   launch_flag_nonzero((int64_t)lds.size(), info2, F.sing.p + lv.lev, s);
