@@ -25,8 +25,10 @@
 //                points per element chosen by the gap / element-length
 //                ratio, coincident, adjacent (two orientations);
 //   k_regular<Q> one thread per regular pair;
-//   k_special<C> one wavefront per singular pair (the 80 or 288 points of
-//                its rule spread over the 64 lanes, then reduced);
+//   k_special<C>, k_special2<C>
+//                one wavefront per singular pair (the 80 or 288 points of
+//                its rule spread over the 64 lanes, then reduced); the
+//                adjacent classes run at two wavefronts per SIMD;
 //   k_gather     one thread per output entry: sum of the four element pairs
 //                of its two hats, written at its (row, column) position.
 // Pair results are 16 complex numbers [a][b][i][j] stored
@@ -39,27 +41,6 @@
 namespace fds {
 
 __constant__ QuadTables c_quad;
-
-struct PairAcc {
-  c64 s1[2][4];
-  c64 s2[4];
-  c64 s3[2][2][4];
-  c64 s4[2][4];
-};
-
-__device__ inline void acc_zero(PairAcc& A) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      A.s1[a][k] = cmk(0, 0);
-      A.s4[a][k] = cmk(0, 0);
-      A.s3[a][0][k] = cmk(0, 0);
-      A.s3[a][1][k] = cmk(0, 0);
-    }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) A.s2[k] = cmk(0, 0);
-}
 
 // The four 2 x 2 blocks of one quadrature point (d = x - y, normals n_x,
 // n_y of the test and trial elements) whose hat-weighted sums make up a
@@ -115,29 +96,9 @@ __device__ inline void point_blocks(const MatConst& m, double dx, double dy, dou
     }
 }
 
-// Special pairs: the hat-weighted sums kept apart (36 accumulators), so a
-// wavefront can reduce them over its lanes before the 16 entries are formed.
-__device__ inline void acc_point(const MatConst& m, double dx, double dy, double w, double u, double v,
-                                 double nx0, double nx1, double ny0, double ny1, PairAcc& A) {
-  c64 M1[4], M2[4], M3[4], M4[4];
-  point_blocks(m, dx, dy, nx0, nx1, ny0, ny1, M1, M2, M3, M4);
-  const double Na[2] = {w * (1.0 - u), w * u};
-  const double Nb[2] = {1.0 - v, v};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    A.s2[k] += w * M2[k];
-#pragma unroll
-    for (int aa = 0; aa < 2; ++aa) {
-      A.s1[aa][k] += Na[aa] * M1[k];
-      A.s4[aa][k] += (w * Nb[aa]) * M4[k];
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) A.s3[aa][bb][k] += (Na[aa] * Nb[bb]) * M3[k];
-    }
-  }
-}
-
-// Regular pairs: the 16 entries accumulated directly (64 registers instead
-// of 144, which lets two wavefronts share a SIMD).
+// A pair's 16 entries accumulated point by point (64 registers, which lets
+// two wavefronts share a SIMD; the special pairs sum them over the lanes of
+// their wavefront afterwards).
 struct PairRes {
   c64 R[16];
 };
@@ -160,13 +121,6 @@ __device__ inline void acc_point_direct(const MatConst& m, double dx, double dy,
 #pragma unroll
       for (int aa = 0; aa < 2; ++aa) A.R[aa * 8 + bb * 4 + k] += Na[aa] * T + wdA[aa] * U;
     }
-}
-
-// res[a][b][ij] = s1[a] dB[b] + dA[a] dB[b] s2 + s3[a][b] + dA[a] s4[b]
-__device__ inline c64 acc_final(const PairAcc& A, int aa, int bb, int k, const Elem& e, const Elem& f) {
-  const double dA = aa ? e.dN1 : e.dN0;
-  const double dB = bb ? f.dN1 : f.dN0;
-  return dB * A.s1[aa][k] + (dA * dB) * A.s2[k] + A.s3[aa][bb][k] + dA * A.s4[bb][k];
 }
 
 __device__ inline double seg_point_dist(double px, double py, double ax, double ay, double bx, double by) {
@@ -380,12 +334,6 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     regular_pair<Q>(list[t], jobs, elist, elems, m, res, np);
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 // ------------------------------------------------------------------ singular pairs
 template <int C>
 __device__ inline void special_pair(unsigned long long key, int lane, const Job* __restrict__ jobs,
@@ -394,16 +342,34 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
 
 // one wavefront per pair, grid-stride over the class list
 template <int C>
-__global__ void __launch_bounds__(256) k_special(const unsigned long long* __restrict__ list,
-                                                 const unsigned int* __restrict__ count_ptr,
-                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
-                                                 const Elem* __restrict__ elems, MatConst m,
-                                                 c64* __restrict__ res, int64_t np) {
+__device__ inline void special_loop(const unsigned long long* __restrict__ list, const unsigned int* __restrict__ count_ptr,
+                                    const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                    const Elem* __restrict__ elems, const MatConst& m, c64* __restrict__ res,
+                                    int64_t np) {
   const int64_t count = min((int64_t)*count_ptr, np);
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < count; w += nw)
     special_pair<C>(list[w], lane, jobs, elist, elems, m, res, np);
+}
+
+// coincident pairs: one wavefront per SIMD (all registers)
+template <int C>
+__global__ void __launch_bounds__(256) k_special(const unsigned long long* __restrict__ list,
+                                                 const unsigned int* __restrict__ count_ptr,
+                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
+                                                 const Elem* __restrict__ elems, MatConst m,
+                                                 c64* __restrict__ res, int64_t np) {
+  special_loop<C>(list, count_ptr, jobs, elist, elems, m, res, np);
+}
+
+// adjacent pairs (288 points): two wavefronts per SIMD measured faster
+template <int C>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_special2(const unsigned long long* __restrict__ list, const unsigned int* __restrict__ count_ptr,
+           const Job* __restrict__ jobs, const int* __restrict__ elist, const Elem* __restrict__ elems, MatConst m,
+           c64* __restrict__ res, int64_t np) {
+  special_loop<C>(list, count_ptr, jobs, elist, elems, m, res, np);
 }
 
 template <int C>
@@ -415,14 +381,16 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
   decode(key, jobs, elist, jb, ie, je, ge, gf);
   const Elem e = elems[ge];
   const Elem f = elems[gf];
-  PairAcc A;
-  acc_zero(A);
+  PairRes A;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) A.R[k] = cmk(0.0, 0.0);
   const double hh = e.h * f.h;
   if (C == kCoinc) {
     const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
     for (int p = lane; p < kNCoincPts; p += 64) {
       const double off = c_quad.coff[p];
-      acc_point(m, off * ax, off * ay, c_quad.cw[p] * hh, c_quad.cu[p], c_quad.cv[p], e.nx, e.ny, f.nx, f.ny, A);
+      acc_point_direct(m, off * ax, off * ay, c_quad.cw[p] * hh, c_quad.cu[p], c_quad.cv[p], e.nx, e.ny, f.nx, f.ny,
+                       e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   } else {
     // vectors from the shared vertex to the far ends of e and f
@@ -442,7 +410,8 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
       const double up = c_quad.au[p], vp = c_quad.av[p];
       const double u = (C == kAdjNext) ? 1.0 - up : up;
       const double v = (C == kAdjNext) ? vp : 1.0 - vp;
-      acc_point(m, up * Ax - vp * Bx, up * Ay - vp * By, c_quad.aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny, A);
+      acc_point_direct(m, up * Ax - vp * Bx, up * Ay - vp * By, c_quad.aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny,
+                       e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   }
   const int64_t slot = pair_slot(jb, ie, je);
@@ -452,9 +421,9 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        c64 val = acc_final(A, aa, bb, k, e, f);
-        val.re = wave_sum(val.re);
-        val.im = wave_sum(val.im);
+        c64 val = A.R[aa * 8 + bb * 4 + k];
+        val.re = wsum_full(val.re);
+        val.im = wsum_full(val.im);
         if (C == kCoinc && (k == 0 || k == 3)) {
           // (1/2) int psi phi on the coincident element: h/3 on the diagonal, h/6 off it
           val.re += 0.5 * e.h * (aa == bb ? (1.0 / 3.0) : (1.0 / 6.0));
@@ -608,9 +577,9 @@ void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned i
   mark(3);
   k_special<kCoinc><<<gspc, 256, 0, s>>>(lists + kCoinc * cap, counts + kCoinc, jobs, elist, elems, m, res, np);
   mark(4);
-  k_special<kAdjNext><<<gspc, 256, 0, s>>>(lists + kAdjNext * cap, counts + kAdjNext, jobs, elist, elems, m, res, np);
+  k_special2<kAdjNext><<<gspc, 256, 0, s>>>(lists + kAdjNext * cap, counts + kAdjNext, jobs, elist, elems, m, res, np);
   mark(5);
-  k_special<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
+  k_special2<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
   mark(6);
   FDS_HIP(hipGetLastError());
 }

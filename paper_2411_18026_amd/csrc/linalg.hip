@@ -21,28 +21,6 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// Sum over the 64 lanes of a wavefront with DPP moves inside each row of 16
-// lanes (swap neighbours, swap pairs, half-row mirror, row mirror: after
-// these every lane holds its row's sum) and the four row sums read out of
-// lanes 0, 16, 32, 48.  Every lane of the wavefront must be active.
-template <int CTRL>
-__device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ inline double lane_value(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ inline double wsum_full(double v) {
-  v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_move<0x141>(v);   // row_half_mirror
-  v += dpp_move<0x140>(v);   // row_mirror
-  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
-
 template <typename T>
 __device__ inline T zero() {
   return Cx<T>::make(0.0, 0.0);
