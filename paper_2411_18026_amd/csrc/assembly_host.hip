@@ -6,6 +6,7 @@
 
 #include "assembly.hpp"
 #include "devmem.hpp"
+#include "parallel.hpp"
 
 namespace fds {
 
@@ -147,49 +148,57 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
       np += p;
       ++i1;
     }
-    std::vector<Job> jobs;
-    std::vector<int> elist, pos;
-    std::vector<Dof> dofs;
-    std::vector<Tile> ptiles, otiles;
+    // pack the batch's tables: sizes and offsets first, then every request
+    // filled in parallel (the layout is the one a serial append would give)
+    const size_t nb = i1 - i0;
+    const int ct = classify_tile_size();
+    std::vector<Job> jobs(nb);
+    std::vector<int64_t> e_off(nb + 1, 0), d_off(nb + 1, 0), p_off(nb + 1, 0), pt_off(nb + 1, 0),
+        ot_off(nb + 1, 0);
     int64_t pair_off = 0;
-    for (size_t r = i0; r < i1; ++r) {
-      const BlockReq& q = reqs[r];
-      Job j{};
+    for (size_t k = 0; k < nb; ++k) {
+      const BlockReq& q = reqs[i0 + k];
+      Job& j = jobs[k];
       j.pair_off = pair_off;
       j.out_off = q.out_off;
       j.rs = q.rs;
       j.cs = q.cs;
-      j.re_off = (int)elist.size();
       j.nre = (int)q.rows.elems.size();
-      elist.insert(elist.end(), q.rows.elems.begin(), q.rows.elems.end());
-      j.ce_off = (int)elist.size();
       j.nce = (int)q.cols.elems.size();
-      elist.insert(elist.end(), q.cols.elems.begin(), q.cols.elems.end());
-      j.rd_off = (int)dofs.size();
       j.nrd = (int)q.rows.dofs.size();
-      dofs.insert(dofs.end(), q.rows.dofs.begin(), q.rows.dofs.end());
-      j.cd_off = (int)dofs.size();
       j.ncd = (int)q.cols.dofs.size();
-      dofs.insert(dofs.end(), q.cols.dofs.begin(), q.cols.dofs.end());
-      j.rpos_off = -1;
-      j.cpos_off = -1;
-      if (!q.rpos.empty()) {
-        j.rpos_off = (int)pos.size();
-        pos.insert(pos.end(), q.rpos.begin(), q.rpos.end());
-      }
-      if (!q.cpos.empty()) {
-        j.cpos_off = (int)pos.size();
-        pos.insert(pos.end(), q.cpos.begin(), q.cpos.end());
-      }
-      const int jid = (int)jobs.size();
-      jobs.push_back(j);
-      const int64_t npj = (int64_t)j.nre * j.nce;
-      const int ct = classify_tile_size();
-      for (int64_t a = 0; a < npj; a += ct) ptiles.push_back(Tile{jid, (int)std::min<int64_t>(ct, npj - a), a});
-      const int64_t noj = (int64_t)j.nrd * j.ncd;
-      for (int64_t a = 0; a < noj; a += 256) otiles.push_back(Tile{jid, (int)std::min<int64_t>(256, noj - a), a});
+      j.re_off = (int)e_off[k];
+      j.ce_off = (int)(e_off[k] + j.nre);
+      e_off[k + 1] = e_off[k] + j.nre + j.nce;
+      j.rd_off = (int)d_off[k];
+      j.cd_off = (int)(d_off[k] + j.nrd);
+      d_off[k + 1] = d_off[k] + j.nrd + j.ncd;
+      j.rpos_off = q.rpos.empty() ? -1 : (int)p_off[k];
+      j.cpos_off = q.cpos.empty() ? -1 : (int)(p_off[k] + q.rpos.size());
+      p_off[k + 1] = p_off[k] + (int64_t)q.rpos.size() + (int64_t)q.cpos.size();
+      const int64_t npj = (int64_t)j.nre * j.nce, noj = (int64_t)j.nrd * j.ncd;
+      pt_off[k + 1] = pt_off[k] + (npj + ct - 1) / ct;
+      ot_off[k + 1] = ot_off[k] + (noj + 255) / 256;
       pair_off += npj;
     }
+    std::vector<int> elist((size_t)e_off[nb]), pos((size_t)p_off[nb]);
+    std::vector<Dof> dofs((size_t)d_off[nb]);
+    std::vector<Tile> ptiles((size_t)pt_off[nb]), otiles((size_t)ot_off[nb]);
+    parallel_for((int)nb, [&](int k) {
+      const BlockReq& q = reqs[i0 + k];
+      const Job& j = jobs[k];
+      std::copy(q.rows.elems.begin(), q.rows.elems.end(), elist.begin() + j.re_off);
+      std::copy(q.cols.elems.begin(), q.cols.elems.end(), elist.begin() + j.ce_off);
+      std::copy(q.rows.dofs.begin(), q.rows.dofs.end(), dofs.begin() + j.rd_off);
+      std::copy(q.cols.dofs.begin(), q.cols.dofs.end(), dofs.begin() + j.cd_off);
+      std::copy(q.rpos.begin(), q.rpos.end(), pos.begin() + p_off[k]);
+      std::copy(q.cpos.begin(), q.cpos.end(), pos.begin() + p_off[k] + q.rpos.size());
+      const int64_t npj = (int64_t)j.nre * j.nce, noj = (int64_t)j.nrd * j.ncd;
+      int64_t t = pt_off[k];
+      for (int64_t a = 0; a < npj; a += ct) ptiles[t++] = Tile{(int)k, (int)std::min<int64_t>(ct, npj - a), a};
+      t = ot_off[k];
+      for (int64_t a = 0; a < noj; a += 256) otiles[t++] = Tile{(int)k, (int)std::min<int64_t>(256, noj - a), a};
+    });
     if (pos.empty()) pos.push_back(0);
     Job* d_jobs = ws.upload("asm_jobs", jobs);
     int* d_elist = ws.upload("asm_elist", elist);
