@@ -47,6 +47,7 @@ def _args():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     p.add_argument("--no-learned", action="store_true", help="skip the learned form")
     p.add_argument("--no-multi", action="store_true", help="skip the multi-cavity configurations")
+    p.add_argument("--no-ladder", action="store_true", help="skip the tripod accuracy ladder")
     return p.parse_args()
 
 
@@ -175,6 +176,11 @@ def main():
         log("multi-cavity configurations")
         multi = multi_cavity_configs(fds, blob)
 
+    ladder = None
+    if not a.no_ladder:
+        log("tripod accuracy ladder")
+        ladder = tripod_ladder(fds)
+
     cpu = None
     if not a.no_cpu_baseline:
         log("CPU oracle baseline")
@@ -217,6 +223,7 @@ def main():
         "learned_form": learned,
         "learned_graph_mixed_form": learned_mixed,
         "multi_cavity": multi,
+        "tripod_accuracy_ladder": ladder,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -266,6 +273,47 @@ def other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2, 
     if kw.get("mixed"):
         out["ir_iterations_batch"] = int(st["ir_iterations"])
     return out
+
+
+def tripod_ladder(fds, sizes=(400, 800, 1600, 3200)):
+    """Accuracy experiment of Section 8.1 (Tables 1 and 2) on the tripod:
+    relative 2-norm error of the factor's solution against a dense solve of
+    the same Galerkin system (entries from the assembly kernels, solved by
+    LAPACK on the host), one plane P-wave at angle 0; multi-level (root at
+    level 1) at three ID tolerances and single-level (root at level L - 1)
+    at 1e-8.  The paper's printed values are listed beside ours."""
+    import synthetic as sy
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "tripod_error_tables.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                t, n, L, l0, eps, err = line.split()
+                paper[(int(t), int(n), float(eps))] = float(err)
+    rows = []
+    for n in sizes:
+        base = sy.config_tripod(n, 1e-8)
+        curves = base["curves"]
+        dofs = np.arange(2 * n)
+        A = fds.entries(curves, base["omega"], base["lam"], base["mu"], base["rho"], dofs, dofs).cpu().numpy()
+        ref = None
+        for single, tols in ((False, (1e-8, 1e-9, 1e-10)), (True, (1e-8,))):
+            if single and base["L"] - 1 == 1:
+                continue   # the single-level variant is the multi-level one here
+            for tol in tols:
+                c = sy.config_tripod(n, tol, single)
+                F = fds.Factor(curves, c["omega"], c["lam"], c["mu"], c["rho"], tol, leaf=c["leaf"],
+                               root_level=c["root_level"], autotune=False)
+                b = F.rhs_plane([0], [0.0])
+                x = F.solve(b).cpu().numpy()[0]
+                if ref is None:
+                    ref = np.linalg.solve(A, b.cpu().numpy()[0])
+                err = float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+                tab = 2 if single else 1
+                rows.append({"table": tab, "N": n, "L": c["L"], "l0": c["root_level"], "eps": tol,
+                             "rel_err": err, "paper_rel_err": paper.get((tab, n, tol))})
+                del F
+    return {"workload": "tripod r=1 a=0.3 b=3, c_L=sqrt(3), c_T=1, rho=1, omega=2, cells of 100 nodes, "
+                        "1 plane P-wave; error vs dense solve of the same system", "rows": rows}
 
 
 def multi_cavity_configs(fds, blob, reps=2):

@@ -105,6 +105,25 @@ def multi_cavity(seed: int, n_cavities: int, total_nodes: int, half_width: float
             for (c, a, asp, ang), m in zip(cav, counts)]
 
 
+def tripod(n: int, r: float = 1.0, a: float = 0.3, b: float = 3.0) -> np.ndarray:
+    """The scatterer of the paper's numerical examples (Section 8, figure of
+    the scatterer): x = (r + a cos(b t)) (cos t, sin t) / (1 + a), n vertices
+    uniform in t, counter-clockwise."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    rad = (r + a * np.cos(b * t)) / (1.0 + a)
+    return np.stack([rad * np.cos(t), rad * np.sin(t)], axis=1)
+
+
+def config_tripod(n: int, tol: float, single_level: bool = False):
+    """Accuracy experiment of Section 8.1 (Tables 1 and 2): the tripod with n
+    nodes, c_L = sqrt(3), c_T = 1, rho = 1 (so mu = 1, lambda = 1), omega = 2,
+    cells of 100 nodes (L = log2(n / 100)), root at level 1 (multi-level) or
+    at level L - 1 (single-level variant), one plane P-wave at angle 0."""
+    L = int(round(math.log2(n / 100)))
+    return dict(curves=[tripod(n)], lam=1.0, mu=1.0, rho=1.0, omega=2.0, tol=tol, leaf=100,
+                root_level=(L - 1) if single_level else 1, L=L)
+
+
 def plane_wave_angles(nrhs: int, step_deg: float = 2.0) -> np.ndarray:
     """Incidence angles 0, step, 2 step, ... in radians."""
     return np.deg2rad(step_deg * np.arange(nrhs))

@@ -1,0 +1,63 @@
+"""Accuracy experiment of Section 8.1 (Tables 1 and 2) on the tripod
+scatterer, through the C ABI: the relative error of the factor's solution
+against a dense solve of the same Galerkin system (entries from the
+assembly kernels, which the parity tests pin to the oracle; LAPACK solve on
+the host) falls with the ID tolerance and is of the size the paper prints
+(tests/golden/tripod_error_tables.txt)."""
+import os
+
+import numpy as np
+import pytest
+
+import synthetic as sy
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tripod_error_tables.txt")
+
+
+def _paper():
+    out = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                t, n, L, l0, eps, err = line.split()
+                out[(int(t), int(n), float(eps))] = float(err)
+    return out
+
+
+@pytest.fixture(scope="module")
+def fdsmod():
+    import paper_2411_18026_amd as m
+    m.load()
+    assert torch.cuda.is_available()
+    return m
+
+
+def _error(fdsmod, n, tol, single, A=None):
+    c = sy.config_tripod(n, tol, single)
+    F = fdsmod.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], tol, leaf=c["leaf"],
+                      root_level=c["root_level"], autotune=False)
+    b = F.rhs_plane([0], [0.0])
+    x = F.solve(b).cpu().numpy()[0]
+    if A is None:
+        dofs = np.arange(2 * n)
+        A = fdsmod.entries(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], dofs, dofs).cpu().numpy()
+    ref = np.linalg.solve(A, b.cpu().numpy()[0])
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref)), A
+
+
+@pytest.mark.parametrize("n", [400, 800, 1600])
+def test_tripod_error_ladder(fdsmod, n):
+    paper = _paper()
+    errs, A = [], None
+    for tol in (1e-8, 1e-9, 1e-10):
+        e, A = _error(fdsmod, n, tol, False, A)
+        errs.append(e)
+        # the same order of magnitude as the paper's Table 1 entry
+        assert e < 10.0 * paper[(1, n, tol)], (n, tol, e)
+    assert errs[0] > errs[1] > errs[2], errs
+    if n > 400:
+        e1, _ = _error(fdsmod, n, 1e-8, True, A)
+        assert e1 < 10.0 * paper[(2, n, 1e-8)], (n, e1)
