@@ -49,6 +49,7 @@ def _args():
     p.add_argument("--no-multi", action="store_true", help="skip the multi-cavity configurations")
     p.add_argument("--no-ladder", action="store_true", help="skip the tripod accuracy ladder")
     p.add_argument("--no-sweep", action="store_true", help="skip the fictitious-frequency sweep")
+    p.add_argument("--no-omega", action="store_true", help="skip the angular-frequency sweep")
     return p.parse_args()
 
 
@@ -186,6 +187,10 @@ def main():
     if not a.no_sweep:
         log("fictitious-frequency sweep")
         sweep = fictitious_sweep(fds)
+    osweep = None
+    if not a.no_omega:
+        log("angular-frequency sweep")
+        osweep = omega_sweep(fds)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -231,6 +236,7 @@ def main():
         "multi_cavity": multi,
         "tripod_accuracy_ladder": ladder,
         "fictitious_frequency_sweep": sweep,
+        "angular_frequency_sweep": osweep,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -436,6 +442,64 @@ def fictitious_sweep(fds, n=400, omegas=None, n_refine=3):
             "omegas_nonbm_sigma_below_tenth_of_median": [float(w) for w, r in zip(omegas, r_nbm) if r < 0.1],
             "omegas_bm_sigma_below_tenth_of_median": [float(w) for w, r in zip(omegas, r_bm) if r < 0.1],
             "deepest_nonbm_dips_refined": refined}
+
+
+def omega_sweep(fds, n=6400, omegas=None, proxies=(64, 128)):
+    """After the first two figures of Section 8.4 (time and error against
+    omega): the tripod with n nodes, omega = 0.5 ... 14.5 in steps of 0.5,
+    tol 1e-8, cells of 100 nodes, root at level 1, one plane P-wave.  For
+    every omega and proxy polygon size: factor seconds (best of two), first
+    solve milliseconds, largest rank, root size, and the relative error of
+    the factor's solution against a dense solve of the same assembled
+    system (LU on the GPU; dense_s is that solve's assembly plus LU time,
+    the conventional BEM on this GPU).  Context: the paper's error at
+    omega = 2 for this size and tolerance is 8.4e-7 (Table 1)."""
+    import torch
+    import synthetic as sy
+    if omegas is None:
+        omegas = np.round(np.arange(0.5, 14.5 + 1e-9, 0.5), 4)
+    c = sy.config_tripod(n, 1e-8)
+    curves = c["curves"]
+    dofs = np.arange(2 * n)
+    rows = []
+    for w in omegas:
+        w = float(w)
+        log(f"  omega {w}")
+        ref = None
+        for npx in proxies:
+            ts = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F = fds.Factor(curves, w, c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"], n_proxy=npx,
+                               autotune=False)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                if len(ts) < 2:
+                    del F
+            b = F.rhs_plane([0], [0.0])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x = F.solve(b)
+            torch.cuda.synchronize()
+            tsol = time.perf_counter() - t1
+            if ref is None:
+                torch.cuda.synchronize()
+                td = time.perf_counter()
+                A = fds.entries(curves, w, c["lam"], c["mu"], c["rho"], dofs, dofs)
+                ref = torch.linalg.solve(A, b[0])
+                torch.cuda.synchronize()
+                dense_s = time.perf_counter() - td
+                del A
+            err = float(torch.linalg.norm(x[0] - ref) / torch.linalg.norm(ref))
+            st = F.stats()
+            del F
+            rows.append({"omega": w, "n_proxy": npx, "factor_s": round(min(ts), 4),
+                         "first_solve_ms": round(1e3 * tsol, 3), "max_rank": int(st["max_rank"]),
+                         "root_size": int(st["root_size"]), "rel_err": err, "dense_s": round(dense_s, 3)})
+        del ref
+    return {"workload": f"tripod, {n} nodes, omega {omegas[0]}..{omegas[-1]} step 0.5, tol 1e-8, cells of 100 "
+                        "nodes, 1 plane P-wave; error vs dense LU of the same system", "rows": rows}
 
 
 def multi_cavity_configs(fds, blob, reps=2):
