@@ -44,14 +44,6 @@ def ellipse(n: int, a: float = 1.0, b: float = 0.5, center=(0.0, 0.0), angle: fl
     return np.stack([center[0] + c * px - s * py, center[1] + s * px + c * py], axis=1)
 
 
-def tripod(n: int, r: float = 1.0, a: float = 0.3, b: float = 3.0) -> np.ndarray:
-    """The three-lobed scatterer of the paper's numerical examples (Section 8,
-    figure of the scatterer): ((r + a cos b t) cos t, (r + a cos b t) sin t)/(1 + a)."""
-    t = 2.0 * np.pi * np.arange(n) / n
-    rad = (r + a * np.cos(b * t)) / (1.0 + a)
-    return np.stack([rad * np.cos(t), rad * np.sin(t)], axis=1)
-
-
 def _ellipse_perimeter(a: float, b: float) -> float:
     # Ramanujan's second approximation
     h = ((a - b) / (a + b)) ** 2
