@@ -24,6 +24,15 @@ For a radial function f(r), r = |d|, e = d / r, derivatives in d = x - y:
 and the radial derivatives of H0(k r) are k^m times scipy's derivatives of
 H0^(1).  d_{y_q} = -d_{d_q}.
 
+For k_T r < 1 the difference g = (H0(k_T r) - H0(k_L r)) / k_T^2 is not
+formed from the two Hankel functions (their third derivatives, each of
+size 1/r^3, cancel to a result of size 1/r, losing about 2 log10(1/(k r))
+digits).  It is summed from the power series of J0 and Y0 (Abramowitz and
+Stegun 9.1.12-13), H0(k r) = sum_m c_m (k r / 2)^{2m} [1 + (2i/pi)(ln(k r / 2)
++ gamma - H_m)], c_m = (-1)^m / (m!)^2, H_m the harmonic numbers, with the
+two wavenumbers' coefficients subtracted before any power of r multiplies
+them, and differentiated term by term.
+
 Quadrature: every element is split into S equal panels with
 S = ceil(2 h / dist) (at least 1, at most ``max_panels``), dist the distance
 from x to the element and h its length, and each panel gets 20-point
@@ -48,15 +57,55 @@ def _radial(k, r, m):
     return k ** m * sp.h1vp(0, k * r, m)
 
 
-def _third_derivative(f1, f2, f3, r, e):
-    """d_i d_k d_q f for a radial f with f', f'', f''' given; shape (..., 2, 2, 2)."""
+def _g_series(r, kT, kL, terms=24):
+    """(g', g''/r - g'/r^2, g''') of g = (H0(k_T r) - H0(k_L r)) / k_T^2 from
+    the power series (for k_T r < 1)."""
+    r = np.asarray(r, dtype=np.float64)
+    lr = np.log(r)
+    g1 = np.zeros(r.shape, dtype=np.complex128)
+    A = np.zeros(r.shape, dtype=np.complex128)
+    g3 = np.zeros(r.shape, dtype=np.complex128)
+    two_i_pi = 2j / math.pi
+    Hm = 0.0
+    for m in range(1, terms):
+        Hm += 1.0 / m
+        cm = (-1.0) ** m / math.factorial(m) ** 2
+        pT, pL = (kT / 2.0) ** (2 * m), (kL / 2.0) ** (2 * m)
+        # coefficients of r^n and of r^n ln r in k_T^2 g, n = 2 m (the m = 0
+        # term is a constant)
+        a = cm * (pT * (1.0 + two_i_pi * (math.log(kT / 2.0) + np.euler_gamma - Hm))
+                  - pL * (1.0 + two_i_pi * (math.log(kL / 2.0) + np.euler_gamma - Hm)))
+        b = cm * two_i_pi * (pT - pL)
+        n = 2 * m
+        rn1, rn3 = r ** (n - 1), r ** (n - 3)
+        g1 += a * n * rn1 + b * rn1 * (n * lr + 1.0)
+        A += a * n * (n - 2) * rn3 + b * rn3 * (n * (n - 2) * lr + 2 * n - 2)
+        g3 += a * n * (n - 1) * (n - 2) * rn3 + b * rn3 * (n * (n - 1) * (n - 2) * lr + 3 * n * n - 6 * n + 2)
+    return g1 / kT ** 2, A / kT ** 2, g3 / kT ** 2
+
+
+def _g_parts(r, kT, kL):
+    """(g', g''/r - g'/r^2, g''') of g = (H0(k_T r) - H0(k_L r)) / k_T^2."""
+    g1 = (_radial(kT, r, 1) - _radial(kL, r, 1)) / kT ** 2
+    g2 = (_radial(kT, r, 2) - _radial(kL, r, 2)) / kT ** 2
+    g3 = (_radial(kT, r, 3) - _radial(kL, r, 3)) / kT ** 2
+    A = g2 / r - g1 / r ** 2
+    small = kT * r < 1.0
+    if np.any(small):
+        s1, sA, s3 = _g_series(r[small], kT, kL)
+        g1[small], A[small], g3[small] = s1, sA, s3
+    return g1, A, g3
+
+
+def _third_derivative(f1, A, f3, e):
+    """d_i d_k d_q f for a radial f, given f', A = f''/r - f'/r^2 and the
+    third derivative f3; shape (..., 2, 2, 2)."""
     I = np.eye(2)
     eee = e[..., :, None, None] * e[..., None, :, None] * e[..., None, None, :]
     S = (I[:, None, :] * e[..., None, :, None]          # d_iq e_k
          + I[None, :, :] * e[..., :, None, None]        # d_kq e_i
          + I[:, :, None] * e[..., None, None, :]        # d_ik e_q
          - 3.0 * eee)
-    A = f2 / r - f1 / r ** 2
     return f3[..., None, None, None] * eee + A[..., None, None, None] * S
 
 
@@ -70,13 +119,11 @@ def traction_kernel(x, y, ny, mat: Material):
     kT, kL = mat.kT, mat.kL
     # G_ik = (i / 4 mu) [h_T d_ik + d_i d_k g],  g = (h_T - h_L) / k_T^2
     hT1 = _radial(kT, r, 1)
-    g1 = (hT1 - _radial(kL, r, 1)) / kT ** 2
-    g2 = (_radial(kT, r, 2) - _radial(kL, r, 2)) / kT ** 2
-    g3 = (_radial(kT, r, 3) - _radial(kL, r, 3)) / kT ** 2
+    g1, A, g3 = (v.reshape(r.shape) for v in _g_parts(np.atleast_1d(r), kT, kL))
     I = np.eye(2)
     # dG[..., i, k, q] = d_{d_q} G_ik
     dG = (1j / (4.0 * mat.mu)) * ((hT1[..., None, None, None] * I[:, :, None] * e[..., None, None, :])
-                                  + _third_derivative(g1, g2, g3, r, e))
+                                  + _third_derivative(g1, A, g3, e))
     dGy = -dG                                            # derivatives in y
     lam, mu = mat.lam, mat.mu
     # t_j = lam n_j d_k w_k + mu (n_q d_q w_j + n_k d_j w_k), w_k = G_ik(x - .)

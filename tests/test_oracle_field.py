@@ -13,6 +13,8 @@ representation of Section 3).
   agrees with the closed form (the whole chain).
 * A rotated wave and rotated targets on the regular N-gon give the rotated
   field.
+* Near the boundary the kernel takes the difference of the two Hankel
+  functions from its power series; its derivatives match 40-digit mpmath.
 """
 import math
 
@@ -115,3 +117,19 @@ def test_rotational_symmetry():
     U0 = field.field([nodes], X[:, 0], OUT, kinds=[1], angles=[0.2], **MAT)[0]
     U1 = field.field([nodes], X[:, 1], OUT @ Rm.T, kinds=[1], angles=[0.2 + ang], **MAT)[0]
     assert np.max(np.abs(U1 - U0 @ Rm.T)) < 1e-11 * np.max(np.abs(U0))
+
+
+def test_hankel_difference_series_matches_high_precision():
+    # the small-argument path of the kernel: derivatives of
+    # g = (H0(k_T r) - H0(k_L r)) / k_T^2 from the power series against
+    # mpmath at 40 digits (the direct difference loses ~7 digits at r = 4e-4)
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    for kT, kL in ((2.0, 2.0 / math.sqrt(3.0)), (0.7, 0.35)):
+        f = lambda rr: (mp.hankel1(0, kT * rr) - mp.hankel1(0, kL * rr)) / kT ** 2
+        for r in (0.9 / kT, 0.2, 1e-2, 4e-4, 1e-5):
+            d1, d2, d3 = (complex(mp.diff(f, mp.mpf(r), m)) for m in (1, 2, 3))
+            g1, A, g3 = field._g_series(np.array([r]), kT, kL)
+            assert abs(g1[0] - d1) < 1e-14 * abs(d1)
+            assert abs(A[0] - (d2 / r - d1 / r ** 2)) < 1e-14 * abs(d2 / r - d1 / r ** 2)
+            assert abs(g3[0] - d3) < 1e-14 * abs(d3)
