@@ -147,6 +147,34 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs,
 int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c64* y, int64_t ld_y,
               void* stream);
 
+/* Displacement at points of the solid from boundary solutions, by the
+ * integral representation of Section 3:
+ *   u_i(x) = u^I_i(x) - int_Gamma T^{n_y}_{jk} G_ik(x - y) u_j(y) ds(y),
+ * u the piecewise-linear interpolant of each solution's nodal values
+ * (Section 4).  geom, omega, lambda, mu, rho: the scatterer and material the
+ * solutions belong to (as for fds_build).  x: device, solution r at
+ * x + r * ld_x (ld_x >= N_unk), e.g. as written by fds_solve.
+ * targets: device, n_target points as (x1, x2) pairs.  kind, angle: host
+ * [nrhs], the plane wave of each solution (as for fds_rhs_plane), whose
+ * field is added; both NULL: the scattered part only.  out: device,
+ * out[r * ld_out + 2 m + i] = u_{i+1} at target m for solution r
+ * (ld_out >= 2 n_target).  n_near: host, optional: the number of targets
+ * closer to some element than 1/64 of its length.
+ * Quadrature per (target, element) by the distance d to the element and its
+ * length h: 4-, 6- or 10-point Gauss-Legendre for d >= 8h, 2h, h; for
+ * d < h the element is split into min(64, ceil(h/d)) 10-point panels.
+ * Targets counted in n_near get less accuracy; the representation does not
+ * hold on Gamma itself, and inside a cavity it gives (approximately) zero.
+ * nrhs == 0 or n_target == 0: nothing to do (FDS_OK).  Errors: FDS_EINVAL
+ * (sizes, pointers, kind not 0/1, only one of kind/angle given, nrhs >
+ * 65535, leading dimensions above 2^31 - 1), FDS_EGEOM, FDS_ENOMEM,
+ * FDS_EHIP.  Device scratch: the evaluation matrix of up to
+ * FDS_FIELD_CHUNK_MB (environment, default 2048) MiB of targets at a time.
+ * Synchronous. */
+int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, double rho, int32_t nrhs,
+              const fds_c64* x, int64_t ld_x, int64_t n_target, const double* targets, const int32_t* kind,
+              const double* angle, fds_c64* out, int64_t ld_out, int64_t* n_near, void* stream);
+
 typedef struct {
   int32_t levels;           /* depth L of the tree */
   int32_t root_level;       /* l0 */

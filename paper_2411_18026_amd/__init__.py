@@ -76,7 +76,8 @@ ENOCONV = 6
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
            "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
-           "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes"]
+           "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes",
+           "fds_field"]
 
 
 def lib_path() -> str:
@@ -123,6 +124,8 @@ def load():
     L.fds_mlp_loss_grad.argtypes = [pf, i64, vp, vp, pf, pf, vp]
     L.fds_mlp_train.argtypes = [pf, i64, vp, vp, i32, i64, ctypes.c_float, ctypes.c_uint64, pf, vp]
     L.fds_special_eval.argtypes = [i64, vp, dbl, vp, vp, vp]
+    L.fds_field.argtypes = [ctypes.POINTER(_Geometry), dbl, dbl, dbl, dbl, i32, vp, i64, i64, vp,
+                            ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i64, pi64, vp]
     L.fds_release_cache.argtypes = []
     L.fds_release_cache.restype = None
     L.fds_cached_bytes.argtypes = []
@@ -349,6 +352,39 @@ def entries(curves, omega, lam, mu, rho, rows, cols, alpha=None, stream=None):
                          cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.c_void_p(out.data_ptr()),
                          len(rows), _stream(stream)))
     return out.t()
+
+
+def field(curves, omega, lam, mu, rho, x, targets, kinds=None, angles=None, stream=None):
+    """Displacement at ``targets`` (M x 2 points of the solid) from boundary
+    solutions ``x`` ((nrhs, 2N) or (2N,) complex128 CUDA tensor) by the
+    integral representation, computed by the GPU field kernels.  With
+    ``kinds``/``angles`` (the plane wave of each solution) the incident
+    field is added.  Returns (out, n_near): out of shape (nrhs, M, 2)
+    complex128 on the GPU (or (M, 2) for a single vector), n_near the number
+    of targets closer to some element than 1/64 of its length."""
+    import torch
+    L = load()
+    g, keep = _geometry(curves)
+    one = x.dim() == 1
+    X = x.reshape(1, -1) if one else x
+    _cuda_c128(X)
+    t = torch.as_tensor(targets, dtype=torch.float64).reshape(-1, 2).to("cuda").contiguous()
+    nrhs, M = X.shape[0], t.shape[0]
+    out = torch.empty((nrhs, max(M, 1), 2), dtype=torch.complex128, device="cuda")
+    kp = ap = None
+    if kinds is not None:
+        k = np.ascontiguousarray(kinds, dtype=np.int32)
+        a = np.ascontiguousarray(angles, dtype=np.float64)
+        if len(k) != nrhs or len(a) != nrhs:
+            raise ValueError("one incident wave per solution")
+        kp = k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        ap = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    nn = ctypes.c_int64()
+    _check(L.fds_field(ctypes.byref(g), omega, lam, mu, rho, nrhs, ctypes.c_void_p(X.data_ptr()), X.stride(0), M,
+                       ctypes.c_void_p(t.data_ptr()), kp, ap, ctypes.c_void_p(out.data_ptr()), 2 * max(M, 1),
+                       ctypes.byref(nn), _stream(stream)))
+    out = out[:, :M]
+    return (out[0] if one else out), int(nn.value)
 
 
 def special_eval(x, beta, stream=None):

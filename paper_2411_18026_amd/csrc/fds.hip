@@ -40,6 +40,7 @@
 #include "../../include/fds.h"
 #include "assembly.hpp"
 #include "devmem.hpp"
+#include "field.hpp"
 #include "learned.hpp"
 #include "linalg.hpp"
 #include "parallel.hpp"
@@ -2214,6 +2215,99 @@ int fds_entries(const fds_geometry* geom, double omega, double lambda, double mu
     q.cs = ld;
     Workspace ws(s);
     assemble_blocks(std::vector<BlockReq>{q}, DG.elems.p, m, (c64*)out, ws, nullptr);
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    if (stream) (void)hipStreamSynchronize((hipStream_t)stream);
+    return translate(e);
+  }
+}
+
+int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, double rho, int32_t nrhs,
+              const fds_c64* x, int64_t ld_x, int64_t n_target, const double* targets, const int32_t* kind,
+              const double* angle, fds_c64* out, int64_t ld_out, int64_t* n_near, void* stream) {
+  AllocScope scope((hipStream_t)stream);
+  if (int e = check_material(omega, lambda, mu, rho)) return e;
+  if (nrhs < 0 || nrhs > 65535 || n_target < 0 || (kind == nullptr) != (angle == nullptr)) return FDS_EINVAL;
+  if (kind)
+    for (int32_t r = 0; r < nrhs; ++r)
+      if (kind[r] != 0 && kind[r] != 1) return FDS_EINVAL;
+  try {
+    Geometry G;
+    if (int e = make_geometry(geom, G)) return e;
+    const int64_t nu = 2 * (int64_t)G.n_nodes;
+    if (nrhs == 0 || n_target == 0) {
+      if (n_near) *n_near = 0;
+      return FDS_OK;
+    }
+    if (!x || !targets || !out || ld_x < nu || ld_out < 2 * n_target || ld_x > INT32_MAX || ld_out > INT32_MAX)
+      return FDS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_quad();
+    ensure_field_quad(make_quad_tables());
+    DevGeom DG;
+    DG.init(G, 0, s);
+    fds_options o;
+    fds_options_default(&o);
+    const MatConst m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
+    Workspace ws(s);
+    const auto runs = field_runs(G.curve_off, G.curve_n, G.prev_node);
+    const FieldRun* d_runs = ws.upload("field_runs", runs);
+    unsigned int* d_near = ws.get<unsigned int>("field_near", (size_t)n_target);
+    FDS_HIP(hipMemsetAsync(d_near, 0, (size_t)n_target * sizeof(unsigned int), s));
+    int* d_kind = nullptr;
+    double* d_ang = nullptr;
+    if (kind) {
+      d_kind = ws.upload("field_kind", std::vector<int>(kind, kind + nrhs));
+      d_ang = ws.upload("field_ang", std::vector<double>(angle, angle + nrhs));
+    }
+    launch_field_incident(targets, n_target, m, nrhs, d_kind, d_ang, (c64*)out, ld_out, s);
+    // targets per chunk of E^T (2 nu x 2 mc complex): at most FDS_FIELD_CHUNK_MB
+    // (default 2048) MiB, a multiple of 32 targets (one 64-row GEMM tile)
+    const char* env_chunk = std::getenv("FDS_FIELD_CHUNK_MB");
+    const int64_t chunk_mb = env_chunk ? std::max<int64_t>(1, std::atoll(env_chunk)) : (int64_t)2048;
+    const int64_t per_target = 2 * nu * (int64_t)sizeof(c64);
+    int64_t mc = std::max<int64_t>(32, ((chunk_mb << 20) / per_target) / 32 * 32);
+    mc = std::min<int64_t>({mc, n_target, (int64_t)4 * 65535});
+    c64* Et = ws.get<c64>("field_E", (size_t)(nu * 2 * mc));
+    std::vector<GemmDesc> gd;
+    for (int64_t m0 = 0; m0 < n_target; m0 += mc) {
+      const int64_t cur = std::min(mc, n_target - m0);
+      GemmDesc g{};
+      g.a_off = 0;
+      g.b_off = 0;
+      g.c_off = 2 * m0;
+      g.m = (int)(2 * cur);
+      g.n = nrhs;
+      g.k = (int)nu;
+      g.lda = (int)nu;
+      g.ldb = (int)ld_x;
+      g.ldc = (int)ld_out;
+      g.alpha_re = -1.0;
+      g.beta_re = 1.0;
+      gd.push_back(g);
+    }
+    std::vector<GemmDesc> first{gd[0]};
+    const auto tiles = gemm_tiles(first);   // tiles of the largest chunk; a chunk takes a prefix
+    const GemmDesc* d_gd = ws.upload("field_gemm", gd);
+    const GemmTile* d_tiles = ws.upload("field_tiles", tiles);
+    const int bn = nrhs <= 16 ? 16 : 64;
+    for (size_t ci = 0; ci < gd.size(); ++ci) {
+      const int64_t m0 = (int64_t)ci * mc;
+      const int cur = gd[ci].m / 2;
+      launch_field_matrix(DG.elems.p, d_runs, (int)runs.size(), targets, m0, cur, m, Et, nu, d_near, s);
+      launch_gemm(d_gd + ci, d_tiles, (gd[ci].m + 63) / 64, nrhs, 0, (const c64*)Et, (const c64*)x, (c64*)out, 1, s,
+                  bn);
+    }
+    if (n_near) {
+      std::vector<unsigned int> fl((size_t)n_target);
+      FDS_HIP(hipMemcpyAsync(fl.data(), d_near, fl.size() * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+      FDS_HIP(hipStreamSynchronize(s));
+      int64_t c = 0;
+      for (unsigned int v : fl) c += v != 0;
+      *n_near = c;
+    }
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {

@@ -19,6 +19,8 @@ import math
 import numpy as np
 
 __all__ = [
+    "field_targets",
+    "random_boundary_values",
     "circle",
     "ellipse",
     "tripod",
@@ -161,3 +163,39 @@ def config_learned_eval():
     nodes (262144 complex unknowns), k_T = 8, lambda=2, mu=1, rho=1, leaf 64,
     ID tolerance 1e-8."""
     return dict(curves=multi_cavity(5, 128, 131072), lam=2.0, mu=1.0, rho=1.0, omega=8.0, tol=1e-8, leaf=64)
+
+
+def random_boundary_values(n_unknowns: int, nrhs: int, seed: int) -> np.ndarray:
+    """Seeded complex nodal values (nrhs, n_unknowns), real and imaginary
+    parts standard normal: inputs for checks of operations that are linear
+    in the boundary solution."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nrhs, n_unknowns)) + 1j * rng.standard_normal((nrhs, n_unknowns))
+
+
+def field_targets(curves, seed: int, n_far: int = 12, n_mid: int = 8,
+                  scales=(0.2, 0.05, 0.01, 0.002, 0.0005, 0.00005), n_inside: int = 4) -> np.ndarray:
+    """Seeded evaluation points around star-shaped curves: ``n_far`` on a
+    circle of 2.5 times the largest node radius about the centroid of all
+    nodes; per curve, ``n_mid`` random edge midpoints pushed away from the
+    curve's centroid by each factor in ``scales`` (1 + s), which puts them
+    at distances from about 1/5 of the curve size down to far below one
+    element length; and ``n_inside`` points pulled towards the centroid,
+    inside the curve.  Returns an (M, 2) float64 array."""
+    rng = np.random.default_rng(seed)
+    allp = np.concatenate(curves)
+    c0 = allp.mean(axis=0)
+    rad = 2.5 * np.max(np.linalg.norm(allp - c0, axis=1))
+    th = rng.uniform(0.0, 2.0 * math.pi, n_far)
+    pts = [c0 + rad * np.stack([np.cos(th), np.sin(th)], axis=1)]
+    for nodes in curves:
+        cc = nodes.mean(axis=0)
+        n = len(nodes)
+        e = rng.integers(0, n, n_mid)
+        mid = 0.5 * (nodes[e] + nodes[(e + 1) % n])
+        for s in scales:
+            pts.append(cc + (1.0 + s) * (mid - cc))
+        e = rng.integers(0, n, n_inside)
+        mid = 0.5 * (nodes[e] + nodes[(e + 1) % n])
+        pts.append(cc + rng.uniform(0.1, 0.7, n_inside)[:, None] * (mid - cc))
+    return np.concatenate(pts)
