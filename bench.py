@@ -50,6 +50,7 @@ def _args():
     p.add_argument("--no-ladder", action="store_true", help="skip the tripod accuracy ladder")
     p.add_argument("--no-sweep", action="store_true", help="skip the fictitious-frequency sweep")
     p.add_argument("--no-omega", action="store_true", help="skip the angular-frequency sweep")
+    p.add_argument("--no-field", action="store_true", help="skip the field evaluation off the boundary")
     return p.parse_args()
 
 
@@ -191,6 +192,10 @@ def main():
     if not a.no_omega:
         log("angular-frequency sweep")
         osweep = omega_sweep(fds)
+    fieldres = None
+    if not a.no_field:
+        log("field off the boundary")
+        fieldres = field_evaluation(fds)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -237,6 +242,7 @@ def main():
         "tripod_accuracy_ladder": ladder,
         "fictitious_frequency_sweep": sweep,
         "angular_frequency_sweep": osweep,
+        "field_evaluation": fieldres,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -500,6 +506,47 @@ def omega_sweep(fds, n=6400, omegas=None, proxies=(64, 128)):
         del ref
     return {"workload": f"tripod, {n} nodes, omega {omegas[0]}..{omegas[-1]} step 0.5, tol 1e-8, cells of 100 "
                         "nodes, 1 plane P-wave; error vs dense LU of the same system", "rows": rows}
+
+
+def field_evaluation(fds, n=6400, nrhs=180, grid=64, reps=3):
+    """Field off the boundary (integral representation of Section 3) on the
+    tripod with n nodes (omega = 2, material of Section 8): factor, solve
+    nrhs plane P-waves at 0, 2, ..., 358 degrees, then the total
+    displacement of every solution on a grid x grid lattice over
+    [-2, 2]^2 (points inside the cavity included: there the representation
+    gives about zero).  Reported: the field call's time (best of reps), its
+    throughput in (target, solution) values per second, the work per call
+    (target-element pairs, and the flop count of the product with the
+    solutions), and the largest |u| at lattice points inside the cavity."""
+    import torch
+    import synthetic as sy
+    c = sy.config_tripod(n, 1e-8)
+    curves = c["curves"]
+    F = fds.Factor(curves, c["omega"], c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"], autotune=False)
+    kinds = [0] * nrhs
+    angles = list(sy.plane_wave_angles(nrhs))
+    x = F.solve(F.rhs_plane(kinds, angles))
+    del F
+    g = np.linspace(-2.0, 2.0, grid)
+    T = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, n_near = fds.field(curves, c["omega"], c["lam"], c["mu"], c["rho"], x, T, kinds, angles)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    # lattice points inside the tripod: radius below the curve's at that angle
+    th = np.arctan2(T[:, 1], T[:, 0])
+    rad = (1.0 + 0.3 * np.cos(3.0 * th)) / 1.3
+    inside = np.hypot(T[:, 0], T[:, 1]) < 0.95 * rad
+    amax = float(torch.max(torch.abs(U[:, torch.from_numpy(inside).cuda()])).item())
+    t = min(ts)
+    M = len(T)
+    return {"workload": f"tripod, {n} nodes, omega 2, {nrhs} plane P-waves, {grid}x{grid} lattice over [-2, 2]^2",
+            "field_ms": round(1e3 * t, 3), "values_per_s": M * nrhs / t,
+            "target_element_pairs": M * n, "product_flop": 8 * (2 * M) * (2 * n) * nrhs,
+            "n_near": n_near, "max_abs_u_inside_cavity": amax, "inside_points": int(inside.sum())}
 
 
 def multi_cavity_configs(fds, blob, reps=2):

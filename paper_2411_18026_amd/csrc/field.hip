@@ -130,10 +130,13 @@ __device__ inline bool field_element(const MatConst& m, const Elem& e, double tx
   return d * kFieldMaxPanels < h;
 }
 
-__global__ void __launch_bounds__(256) k_field_matrix(const Elem* __restrict__ elems, const FieldRun* __restrict__ runs,
-                                                      const double* __restrict__ targets, int64_t m0, int mc,
-                                                      MatConst m, c64* __restrict__ Et, int64_t ld,
-                                                      unsigned int* __restrict__ near) {
+// Two wavefronts per SIMD (128 registers, 28 bytes per lane spilled): the
+// kernel values' long dependent chains need the second wavefront to hide
+// their latency (8.6 ms against 9.8 ms for the whole field call of 4096
+// targets x 6400 nodes x 180 solutions at one wavefront per SIMD).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_field_matrix(const Elem* __restrict__ elems, const FieldRun* __restrict__ runs, const double* __restrict__ targets,
+               int64_t m0, int mc, MatConst m, c64* __restrict__ Et, int64_t ld, unsigned int* __restrict__ near) {
   const int lane = threadIdx.x & 63;
   const int ml = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (ml >= mc) return;   // the whole wavefront
