@@ -2271,34 +2271,12 @@ int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, 
     int64_t mc = std::max<int64_t>(32, ((chunk_mb << 20) / per_target) / 32 * 32);
     mc = std::min<int64_t>({mc, n_target, (int64_t)4 * 65535});
     c64* Et = ws.get<c64>("field_E", (size_t)(nu * 2 * mc));
-    std::vector<GemmDesc> gd;
     for (int64_t m0 = 0; m0 < n_target; m0 += mc) {
-      const int64_t cur = std::min(mc, n_target - m0);
-      GemmDesc g{};
-      g.a_off = 0;
-      g.b_off = 0;
-      g.c_off = 2 * m0;
-      g.m = (int)(2 * cur);
-      g.n = nrhs;
-      g.k = (int)nu;
-      g.lda = (int)nu;
-      g.ldb = (int)ld_x;
-      g.ldc = (int)ld_out;
-      g.alpha_re = -1.0;
-      g.beta_re = 1.0;
-      gd.push_back(g);
-    }
-    std::vector<GemmDesc> first{gd[0]};
-    const auto tiles = gemm_tiles(first);   // tiles of the largest chunk; a chunk takes a prefix
-    const GemmDesc* d_gd = ws.upload("field_gemm", gd);
-    const GemmTile* d_tiles = ws.upload("field_tiles", tiles);
-    const int bn = nrhs <= 16 ? 16 : 64;
-    for (size_t ci = 0; ci < gd.size(); ++ci) {
-      const int64_t m0 = (int64_t)ci * mc;
-      const int cur = gd[ci].m / 2;
+      const int cur = (int)std::min(mc, n_target - m0);
       launch_field_matrix(DG.elems.p, d_runs, (int)runs.size(), targets, m0, cur, m, Et, nu, d_near, s);
-      launch_gemm(d_gd + ci, d_tiles, (gd[ci].m + 63) / 64, nrhs, 0, (const c64*)Et, (const c64*)x, (c64*)out, 1, s,
-                  bn);
+      // out = u^I - E X on the matrix cores (E^T is nu x 2 cur)
+      launch_zgemm_tn(2 * cur, nrhs, (int)nu, cmk(-1.0, 0.0), Et, nu, (const c64*)x, ld_x, cmk(1.0, 0.0),
+                      (c64*)out + 2 * m0, ld_out, s);
     }
     if (n_near) {
       std::vector<unsigned int> fl((size_t)n_target);

@@ -26,8 +26,8 @@
 // (start-hat integral of element t) + (end-hat integral of the element
 // before t), each element integrated once (one extra element per run).
 // The entries go to E^T: row 2 t + j, column 2 m + i, so that a wavefront
-// writes 63 consecutive 32-byte pairs per column.  The library GEMM then
-// forms out = u^I - E X for all solutions at once.
+// writes 63 consecutive 32-byte pairs per column.  The matrix-core GEMM
+// (launch_zgemm_tn) then forms out = u^I - E X for all solutions at once.
 #include <cmath>
 
 #include "field.hpp"

@@ -1747,6 +1747,126 @@ void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_ma
   FDS_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ MFMA GEMM, C = alpha A^T B + beta C
+// A workgroup of four wavefronts computes a 64 x 64 tile of C; each
+// wavefront a 32 x 32 block as 2 x 2 tiles of the FP64 16x16x4 MFMA, four
+// real products per complex one.  MFMA lanes: the A operand of lane l is row
+// l % 16, the B operand column l % 16, both at k group l / 16; result slot
+// v of lane l is row l / 16 + 4 v, column l % 16.  Per chunk of 16 k the
+// workgroup stages the 64 rows of A^T and the 64 columns of B in LDS (each
+// thread one run of four consecutive complex numbers of one column of A and
+// of B), double-buffered, one barrier per chunk; within a chunk lane group
+// g takes k = 4 g + v at step v (any assignment A and B share).  Rows,
+// columns and k beyond the matrix read as zero.  Workgroups are dealt to the
+// 8 XCDs in turn; tiles are renumbered so that each XCD runs a contiguous
+// range, the column tiles of a row tile together (they read the same rows
+// of A).
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kZLd = 17;   // LDS row pitch in complex numbers (16 k + 1)
+
+__device__ inline void zg_fetch(c64 (&ra)[4], c64 (&rb)[4], const c64* ap, const c64* bp, bool aok, bool bok,
+                                int kk, int k) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const bool ok = kk + v < k;
+    ra[v] = (aok && ok) ? ap[kk + v] : cmk(0.0, 0.0);
+    rb[v] = (bok && ok) ? bp[kk + v] : cmk(0.0, 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zgemm_tn(int m, int n, int k, c64 alpha, const c64* __restrict__ A,
+                                                  int64_t lda, const c64* __restrict__ B, int64_t ldb, c64 beta,
+                                                  c64* __restrict__ C, int64_t ldc, int tiles_n, int n_tiles) {
+  __shared__ c64 As[2][64 * kZLd];
+  __shared__ c64 Bs[2][64 * kZLd];
+  const int per = (int)(gridDim.x / 8);
+  const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (L >= n_tiles) return;   // the whole workgroup
+  const int tm = L / tiles_n, tn = L % tiles_n;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  // staging: thread tid loads row / column tid / 4 at k offset 4 (tid % 4)
+  const int srow = tid >> 2, sk = 4 * (tid & 3);
+  const int gi = tm * 64 + srow, gj = tn * 64 + srow;
+  const bool aok = gi < m, bok = gj < n;
+  const c64* ap = A + (int64_t)(aok ? gi : 0) * lda;
+  const c64* bp = B + (int64_t)(bok ? gj : 0) * ldb;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  d4v cr[2][2], ci[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) cr[t][u] = ci[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
+  c64 ra[4], rb[4];
+  zg_fetch(ra, rb, ap, bp, aok, bok, sk, k);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    As[0][srow * kZLd + sk + v] = ra[v];
+    Bs[0][srow * kZLd + sk + v] = rb[v];
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    const bool more = k0 + 16 < k;
+    if (more) zg_fetch(ra, rb, ap, bp, aok, bok, k0 + 16 + sk, k);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const c64 a = As[buf][(wr + 16 * t + r16) * kZLd + 4 * g + v];
+        const c64 b = Bs[buf][(wc + 16 * t + r16) * kZLd + 4 * g + v];
+        xr[t] = a.re, xi[t] = a.im, yr[t] = b.re, yi[t] = b.im;
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          cr[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[t], yr[u], cr[t][u], 0, 0, 0);
+          cr[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi[t], yi[u], cr[t][u], 0, 0, 0);
+          ci[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[t], yi[u], ci[t][u], 0, 0, 0);
+          ci[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[t], yr[u], ci[t][u], 0, 0, 0);
+        }
+    }
+    if (more) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        As[buf ^ 1][srow * kZLd + sk + v] = ra[v];
+        Bs[buf ^ 1][srow * kZLd + sk + v] = rb[v];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  const bool zero_beta = beta.re == 0.0 && beta.im == 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = tm * 64 + wr + 16 * t + g + 4 * v, col = tn * 64 + wc + 16 * u + r16;
+        if (row < m && col < n) {
+          c64* p = C + row + (int64_t)col * ldc;
+          c64 val = alpha * cmk(cr[t][u][v], ci[t][u][v]);
+          if (!zero_beta) val += beta * *p;
+          *p = val;
+        }
+      }
+}
+
+void launch_zgemm_tn(int m, int n, int k, c64 alpha, const c64* A, int64_t lda, const c64* B, int64_t ldb, c64 beta,
+                     c64* C, int64_t ldc, hipStream_t s) {
+  if (m < 1 || n < 1 || k < 1) return;
+  const int tiles_m = (m + 63) / 64, tiles_n = (n + 63) / 64;
+  const int n_tiles = tiles_m * tiles_n;
+  const int grid = (n_tiles + 7) / 8 * 8;
+  k_zgemm_tn<<<grid, 256, 0, s>>>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_n, n_tiles);
+  FDS_HIP(hipGetLastError());
+}
+
 int check_cpqr_sizes(const std::vector<CpqrDesc>& d) {
   int tall = 0;
   for (auto& x : d) {

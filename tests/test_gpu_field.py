@@ -82,7 +82,7 @@ def test_field_matches_oracle_on_two_curves(fdsmod):
     _check(fdsmod, curves, 3.0, 2.0, 1.0, 1.3, 2, 12)
 
 
-def test_field_chunks_and_tile_widths_are_bitwise_equal(fdsmod):
+def test_field_chunks_and_solution_counts_are_bitwise_equal(fdsmod):
     curves = [sy.tripod(300)]
     X = torch.from_numpy(sy.random_boundary_values(600, 20, 13)).cuda()
     T = sy.field_targets(curves, 13, n_far=40)
@@ -93,7 +93,7 @@ def test_field_chunks_and_tile_widths_are_bitwise_equal(fdsmod):
     finally:
         del os.environ["FDS_FIELD_CHUNK_MB"]
     assert torch.equal(full, chunked)
-    few, _ = fdsmod.field(curves, 2.0, 1.0, 1.0, 1.0, X[:3].contiguous(), T)   # 16-column GEMM tiles
+    few, _ = fdsmod.field(curves, 2.0, 1.0, 1.0, 1.0, X[:3].contiguous(), T)   # a 3-column product
     assert torch.equal(full[:3], few)
     one, _ = fdsmod.field(curves, 2.0, 1.0, 1.0, 1.0, X[5].contiguous(), T)    # a single vector
     assert torch.equal(full[5], one)
