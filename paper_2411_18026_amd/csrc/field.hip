@@ -90,17 +90,42 @@ __device__ inline void field_point(const MatConst& m, double dx, double dy, doub
     }
 }
 
+// One quadrature point at parameter u with weight wt (element length
+// included) added to the start-hat (As) and end-hat (Ae) integrals.
+__device__ inline void field_accumulate(const MatConst& m, const Elem& e, double tx, double ty, double u, double wt,
+                                        c64 (&As)[4], c64 (&Ae)[4]) {
+  c64 Md[4], Mv[4];
+  field_point(m, tx - (e.x0 + u * (e.x1 - e.x0)), ty - (e.y0 + u * (e.y1 - e.y0)), e.nx, e.ny, Md, Mv);
+  const double c0 = wt * (1.0 - u), c1 = wt * u;
+  const double d0 = wt * e.dN0, d1 = wt * e.dN1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    As[q] += d0 * Md[q] + c0 * Mv[q];
+    Ae[q] += d1 * Md[q] + c1 * Mv[q];
+  }
+}
+
 // Integrals of K against the start hat (As) and the end hat (Ae) of
 // element e for the target (tx, ty); returns whether the target is closer
-// than h / 64.
-__device__ inline bool field_element(const MatConst& m, const Elem& e, double tx, double ty, c64 (&As)[4],
-                                     c64 (&Ae)[4]) {
-  double qx = e.x1 - e.x0, qy = e.y1 - e.y0;
+// than h / 64.  When every lane of the wavefront takes the 4-point rule
+// (the far field: nearly all pairs) the loop is unrolled with the rule
+// read as wavefront-uniform constants; the arithmetic is the same.
+__device__ inline bool field_element(const MatConst& m, const Elem& e, double tx, double ty, bool live,
+                                     c64 (&As)[4], c64 (&Ae)[4]) {
+  const double qx = e.x1 - e.x0, qy = e.y1 - e.y0;
   double s = ((tx - e.x0) * qx + (ty - e.y0) * qy) / (qx * qx + qy * qy);
   s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
   const double px = e.x0 + s * qx - tx, py = e.y0 + s * qy - ty;
   const double d = sqrt(px * px + py * py);
   const double h = e.h;
+  if (__ballot(live && !(d >= 8.0 * h)) == 0ull) {
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) field_accumulate(m, e, tx, ty, c_fq.g4[k], c_fq.w4[k] * h, As, Ae);
+    }
+    return false;
+  }
+  if (!live) return false;
   const double* g;
   const double* w;
   int nq, np = 1;
@@ -114,26 +139,16 @@ __device__ inline bool field_element(const MatConst& m, const Elem& e, double tx
   }
   const double inv = 1.0 / np;
   for (int p = 0; p < np; ++p)
-    for (int k = 0; k < nq; ++k) {
-      const double u = (p + g[k]) * inv;
-      const double wt = w[k] * h * inv;
-      c64 Md[4], Mv[4];
-      field_point(m, tx - (e.x0 + u * qx), ty - (e.y0 + u * qy), e.nx, e.ny, Md, Mv);
-      const double c0 = wt * (1.0 - u), c1 = wt * u;
-      const double d0 = wt * e.dN0, d1 = wt * e.dN1;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        As[q] += d0 * Md[q] + c0 * Mv[q];
-        Ae[q] += d1 * Md[q] + c1 * Mv[q];
-      }
-    }
+    for (int k = 0; k < nq; ++k) field_accumulate(m, e, tx, ty, (p + g[k]) * inv, w[k] * h * inv, As, Ae);
   return d * kFieldMaxPanels < h;
 }
 
-// Two wavefronts per SIMD (128 registers, 28 bytes per lane spilled): the
-// kernel values' long dependent chains need the second wavefront to hide
-// their latency (8.6 ms against 9.8 ms for the whole field call of 4096
-// targets x 6400 nodes x 180 solutions at one wavefront per SIMD).
+// Two wavefronts per SIMD (256 registers with the accumulation registers,
+// 140 bytes per lane spilled): the kernel values' long dependent chains
+// need the second wavefront to hide their latency (8.6 ms against 9.8 ms
+// for the whole field call of 4096 targets x 6400 nodes x 180 solutions at
+// one wavefront per SIMD; the uniform 4-point path then took it from 7.7
+// to 7.3 ms).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_field_matrix(const Elem* __restrict__ elems, const FieldRun* __restrict__ runs, const double* __restrict__ targets,
                int64_t m0, int mc, MatConst m, c64* __restrict__ Et, int64_t ld, unsigned int* __restrict__ near) {
@@ -147,8 +162,9 @@ k_field_matrix(const Elem* __restrict__ elems, const FieldRun* __restrict__ runs
   c64 As[4], Ae[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) As[q] = Ae[q] = cmk(0.0, 0.0);
-  bool close = false;
-  if (el >= 0) close = field_element(m, elems[el], tx, ty, As, Ae);
+  // every lane takes part (the rule choice is voted over the wavefront);
+  // lanes past the run integrate nothing
+  const bool close = field_element(m, elems[el >= 0 ? el : run.first], tx, ty, el >= 0, As, Ae);
   c64 Pe[4];   // end-hat integral of the element before this lane's node
 #pragma unroll
   for (int q = 0; q < 4; ++q) Pe[q] = cmk(__shfl_up(Ae[q].re, 1), __shfl_up(Ae[q].im, 1));
