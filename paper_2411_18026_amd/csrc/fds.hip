@@ -2271,12 +2271,14 @@ int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, 
     int64_t mc = std::max<int64_t>(32, ((chunk_mb << 20) / per_target) / 32 * 32);
     mc = std::min<int64_t>({mc, n_target, (int64_t)4 * 65535});
     c64* Et = ws.get<c64>("field_E", (size_t)(nu * 2 * mc));
+    const int slabs = zgemm_tn_slabs((int)nu);
+    c64* Pz = slabs > 1 ? ws.get<c64>("field_P", (size_t)slabs * 2 * mc * nrhs) : nullptr;
     for (int64_t m0 = 0; m0 < n_target; m0 += mc) {
       const int cur = (int)std::min(mc, n_target - m0);
       launch_field_matrix(DG.elems.p, d_runs, (int)runs.size(), targets, m0, cur, m, Et, nu, d_near, s);
       // out = u^I - E X on the matrix cores (E^T is nu x 2 cur)
       launch_zgemm_tn(2 * cur, nrhs, (int)nu, cmk(-1.0, 0.0), Et, nu, (const c64*)x, ld_x, cmk(1.0, 0.0),
-                      (c64*)out + 2 * m0, ld_out, s);
+                      (c64*)out + 2 * m0, ld_out, Pz, s);
     }
     if (n_near) {
       std::vector<unsigned int> fl((size_t)n_target);

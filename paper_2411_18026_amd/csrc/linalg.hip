@@ -1757,13 +1757,19 @@ void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_ma
 // thread one run of four consecutive complex numbers of one column of A and
 // of B), double-buffered, one barrier per chunk; within a chunk lane group
 // g takes k = 4 g + v at step v (any assignment A and B share).  Rows,
-// columns and k beyond the matrix read as zero.  Workgroups are dealt to the
-// 8 XCDs in turn; tiles are renumbered so that each XCD runs a contiguous
-// range, the column tiles of a row tile together (they read the same rows
+// columns and k beyond the matrix read as zero.  K is cut into slabs of
+// kZSlab (the last one shorter): each workgroup does one (row tile, column
+// tile, slab) and, with more than one slab, writes its partial tile to P;
+// k_zgemm_reduce then adds the slabs in order.  The cut depends on k only,
+// so every entry of C is the same sum whatever m and n.  Workgroups are
+// dealt to the 8 XCDs in turn; work units are renumbered so that each XCD
+// runs a contiguous range: one slab of B at a time (it stays in that XCD's
+// L2), the column tiles of a row tile together (they read the same rows
 // of A).
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-constexpr int kZLd = 17;   // LDS row pitch in complex numbers (16 k + 1)
+constexpr int kZLd = 17;      // LDS row pitch in complex numbers (16 k + 1)
+constexpr int kZSlab = 1024;  // k per slab
 
 __device__ inline void zg_fetch(c64 (&ra)[4], c64 (&rb)[4], const c64* ap, const c64* bp, bool aok, bool bok,
                                 int kk, int k) {
@@ -1777,13 +1783,16 @@ __device__ inline void zg_fetch(c64 (&ra)[4], c64 (&rb)[4], const c64* ap, const
 
 __global__ void __launch_bounds__(256) k_zgemm_tn(int m, int n, int k, c64 alpha, const c64* __restrict__ A,
                                                   int64_t lda, const c64* __restrict__ B, int64_t ldb, c64 beta,
-                                                  c64* __restrict__ C, int64_t ldc, int tiles_n, int n_tiles) {
+                                                  c64* __restrict__ C, int64_t ldc, int tiles_n, int n_tiles,
+                                                  int n_slabs, c64* __restrict__ P) {
   __shared__ c64 As[2][64 * kZLd];
   __shared__ c64 Bs[2][64 * kZLd];
   const int per = (int)(gridDim.x / 8);
   const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (L >= n_tiles) return;   // the whole workgroup
-  const int tm = L / tiles_n, tn = L % tiles_n;
+  if (L >= n_tiles * n_slabs) return;   // the whole workgroup
+  const int ks = L / n_tiles, tl = L % n_tiles;
+  const int tm = tl / tiles_n, tn = tl % tiles_n;
+  const int kb = ks * kZSlab, ke = min(k, kb + kZSlab);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int r16 = lane & 15, g = lane >> 4;
@@ -1800,7 +1809,7 @@ __global__ void __launch_bounds__(256) k_zgemm_tn(int m, int n, int k, c64 alpha
 #pragma unroll
     for (int u = 0; u < 2; ++u) cr[t][u] = ci[t][u] = d4v{0.0, 0.0, 0.0, 0.0};
   c64 ra[4], rb[4];
-  zg_fetch(ra, rb, ap, bp, aok, bok, sk, k);
+  zg_fetch(ra, rb, ap, bp, aok, bok, kb + sk, ke);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     As[0][srow * kZLd + sk + v] = ra[v];
@@ -1808,9 +1817,9 @@ __global__ void __launch_bounds__(256) k_zgemm_tn(int m, int n, int k, c64 alpha
   }
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < k; k0 += 16) {
-    const bool more = k0 + 16 < k;
-    if (more) zg_fetch(ra, rb, ap, bp, aok, bok, k0 + 16 + sk, k);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    const bool more = k0 + 16 < ke;
+    if (more) zg_fetch(ra, rb, ap, bp, aok, bok, k0 + 16 + sk, ke);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double xr[2], xi[2], yr[2], yi[2];
@@ -1849,22 +1858,50 @@ __global__ void __launch_bounds__(256) k_zgemm_tn(int m, int n, int k, c64 alpha
       for (int v = 0; v < 4; ++v) {
         const int row = tm * 64 + wr + 16 * t + g + 4 * v, col = tn * 64 + wc + 16 * u + r16;
         if (row < m && col < n) {
-          c64* p = C + row + (int64_t)col * ldc;
-          c64 val = alpha * cmk(cr[t][u][v], ci[t][u][v]);
-          if (!zero_beta) val += beta * *p;
-          *p = val;
+          if (n_slabs > 1) {
+            P[(int64_t)ks * m * n + row + (int64_t)col * m] = cmk(cr[t][u][v], ci[t][u][v]);
+          } else {
+            c64* p = C + row + (int64_t)col * ldc;
+            c64 val = alpha * cmk(cr[t][u][v], ci[t][u][v]);
+            if (!zero_beta) val += beta * *p;
+            *p = val;
+          }
         }
       }
 }
 
+__global__ void k_zgemm_reduce(int m, int n, int n_slabs, const c64* __restrict__ P, c64 alpha, c64 beta,
+                               c64* __restrict__ C, int64_t ldc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * n) return;
+  const int row = (int)(t % m), col = (int)(t / m);
+  c64 acc = P[t];
+  for (int s = 1; s < n_slabs; ++s) acc += P[(int64_t)s * m * n + t];
+  c64* p = C + row + (int64_t)col * ldc;
+  c64 val = alpha * acc;
+  if (!(beta.re == 0.0 && beta.im == 0.0)) val += beta * *p;
+  *p = val;
+}
+
+int zgemm_tn_slabs(int k) { return (k + kZSlab - 1) / kZSlab; }
+
 void launch_zgemm_tn(int m, int n, int k, c64 alpha, const c64* A, int64_t lda, const c64* B, int64_t ldb, c64 beta,
-                     c64* C, int64_t ldc, hipStream_t s) {
+                     c64* C, int64_t ldc, c64* P, hipStream_t s) {
   if (m < 1 || n < 1 || k < 1) return;
   const int tiles_m = (m + 63) / 64, tiles_n = (n + 63) / 64;
   const int n_tiles = tiles_m * tiles_n;
-  const int grid = (n_tiles + 7) / 8 * 8;
-  k_zgemm_tn<<<grid, 256, 0, s>>>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_n, n_tiles);
+  const int n_slabs = zgemm_tn_slabs(k);
+  if (n_slabs > 1 && !P) throw Error(1, "zgemm: slab buffer missing");
+  const int64_t units = (int64_t)n_tiles * n_slabs;
+  if (units > ((int64_t)1 << 30)) throw Error(1, "zgemm: problem too large");
+  const int grid = (int)((units + 7) / 8 * 8);
+  k_zgemm_tn<<<grid, 256, 0, s>>>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, tiles_n, n_tiles, n_slabs, P);
   FDS_HIP(hipGetLastError());
+  if (n_slabs > 1) {
+    const int64_t cnt = (int64_t)m * n;
+    k_zgemm_reduce<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(m, n, n_slabs, P, alpha, beta, C, ldc);
+    FDS_HIP(hipGetLastError());
+  }
 }
 
 int check_cpqr_sizes(const std::vector<CpqrDesc>& d) {

@@ -86,9 +86,13 @@ template <typename T>
 void launch_gemm(const GemmDesc* d, const GemmTile* tiles, int n_tiles, int n_max, int n_override, const T* abase,
                  const T* bbase, T* cbase, int transA, hipStream_t s, int bn = 64);
 // C = alpha A^T B + beta C (complex FP64, column-major: A k x m, B k x n,
-// C m x n) on the FP64 matrix cores; one GEMM, no descriptors
+// C m x n) on the FP64 matrix cores; one GEMM, no descriptors.  K is cut
+// into zgemm_tn_slabs(k) slabs whose partial products go to P
+// (zgemm_tn_slabs(k) * m * n complex numbers; unused, may be null, for one
+// slab) and are added in slab order, so results do not depend on m or n.
+int zgemm_tn_slabs(int k);
 void launch_zgemm_tn(int m, int n, int k, c64 alpha, const c64* A, int64_t lda, const c64* B, int64_t ldb, c64 beta,
-                     c64* C, int64_t ldc, hipStream_t s);
+                     c64* C, int64_t ldc, c64* P, hipStream_t s);
 // 1 if some problem needs the tall variant (m > 2048 or n > 1024); throws
 // beyond 4096 columns
 int check_cpqr_sizes(const std::vector<CpqrDesc>& d);
