@@ -24,7 +24,8 @@
 //                put into one of six lists: tensor Gauss with 4, 6 or 10
 //                points per element chosen by the gap / element-length
 //                ratio, coincident, adjacent (two orientations);
-//   k_regular<Q> one thread per regular pair;
+//   k_regular<Q> one thread per regular pair (4 and 6 points);
+//   k_regular_wave10 one wavefront per 10-point pair;
 //   k_special<C>, k_special2<C>
 //                one wavefront per singular pair (the 80 or 288 points of
 //                its rule spread over the 64 lanes, then reduced); the
@@ -334,6 +335,52 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     regular_pair<Q>(list[t], jobs, elist, elems, m, res, np);
 }
 
+// 10-point pairs: one wavefront per pair (the 100 points of the tensor rule
+// over the 64 lanes, the 16 sums reduced by DPP).  A level has few of them
+// (about 20 000 per batch on the large ellipse), which at one thread per
+// pair filled a third of the SIMDs.
+__device__ inline void regular_pair_wave10(unsigned long long key, int lane, const Job* __restrict__ jobs,
+                                           const int* __restrict__ elist, const Elem* __restrict__ elems,
+                                           const MatConst& m, c64* __restrict__ res, int64_t np) {
+  Job jb;
+  int ie, je, ge, gf;
+  decode(key, jobs, elist, jb, ie, je, ge, gf);
+  const Elem e = elems[ge];
+  const Elem f = elems[gf];
+  PairRes A;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) A.R[k] = cmk(0.0, 0.0);
+  const double ox = e.x0 - f.x0, oy = e.y0 - f.y0;
+  const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
+  const double bx = f.x1 - f.x0, by = f.y1 - f.y0;
+  const double hh = e.h * f.h;
+  for (int p = lane; p < 100; p += 64) {
+    const int i = p / 10, j = p - 10 * i;
+    const double u = c_quad.g10[i], v = c_quad.g10[j];
+    acc_point_direct(m, ox + u * ax - v * bx, oy + u * ay - v * by, (c_quad.w10[i] * hh) * c_quad.w10[j], u, v,
+                     e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
+  }
+  const int64_t slot = pair_slot(jb, ie, je);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    c64 val = A.R[k];
+    val.re = wsum_full(val.re);
+    val.im = wsum_full(val.im);
+    if (lane == 0) res[k * np + slot] = val;
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_regular_wave10(const unsigned long long* __restrict__ list, const unsigned int* __restrict__ count_ptr,
+                 const Job* __restrict__ jobs, const int* __restrict__ elist, const Elem* __restrict__ elems,
+                 MatConst m, c64* __restrict__ res, int64_t np) {
+  const int64_t count = min((int64_t)*count_ptr, np);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < count; w += nw)
+    regular_pair_wave10(list[w], lane, jobs, elist, elems, m, res, np);
+}
+
 // ------------------------------------------------------------------ singular pairs
 template <int C>
 __device__ inline void special_pair(unsigned long long key, int lane, const Job* __restrict__ jobs,
@@ -573,7 +620,7 @@ void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned i
   mark(1);
   k_regular<6><<<greg, 128, 0, s>>>(lists + kQ6 * cap, counts + kQ6, jobs, elist, elems, m, res, np);
   mark(2);
-  k_regular<10><<<greg, 128, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
+  k_regular_wave10<<<gspc, 256, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
   mark(3);
   k_special<kCoinc><<<gspc, 256, 0, s>>>(lists + kCoinc * cap, counts + kCoinc, jobs, elist, elems, m, res, np);
   mark(4);
