@@ -134,8 +134,13 @@ def main():
     dom = int(np.argmax(cls_s))
     names = ["far_pairs_q4", "mid_pairs_q6", "near_pairs_q10", "coincident", "adjacent_next", "adjacent_prev"]
     achieved = FLOP_PER_EVAL * cls_e[dom] / cls_s[dom] / 1e12 if cls_s[dom] > 0 else 0.0
+    # HBM bytes per launch of the far-pair integrator from the two counter
+    # runs in profiles/far_pairs_q4_ellipse131072_hbm_counters.md: FETCH_SIZE
+    # 117220 KiB x 2.0 and WRITE_SIZE 934406 KiB x 1.0 per dispatch (the
+    # factors are what a plain 1 GiB copy reads on the same counters)
+    traffic = (117220 * 2.0 + 934406 * 1.0) * 1024 if names[dom] == "far_pairs_q4" else None
     roofline = {"bound": "alu", "kernel": f"k_regular/k_special ({names[dom]})", "achieved": round(achieved, 3),
-                "peak": 78.6, "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": None,
+                "peak": 78.6, "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": traffic,
                 "flop_per_eval": FLOP_PER_EVAL, "evals": int(cls_e[dom]), "launches": int(cls_n[dom]),
                 "avg_launch_ms": round(1e3 * cls_s[dom] / max(1, cls_n[dom]), 3)}
 
