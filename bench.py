@@ -51,6 +51,7 @@ def _args():
     p.add_argument("--no-sweep", action="store_true", help="skip the fictitious-frequency sweep")
     p.add_argument("--no-omega", action="store_true", help="skip the angular-frequency sweep")
     p.add_argument("--no-field", action="store_true", help="skip the field evaluation off the boundary")
+    p.add_argument("--no-complexity", action="store_true", help="skip the factor-time ladder over N")
     return p.parse_args()
 
 
@@ -201,6 +202,10 @@ def main():
     if not a.no_field:
         log("field off the boundary")
         fieldres = field_evaluation(fds)
+    cladder = None
+    if not a.no_complexity:
+        log("factor-time ladder over N")
+        cladder = complexity_ladder(fds)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -248,6 +253,7 @@ def main():
         "fictitious_frequency_sweep": sweep,
         "angular_frequency_sweep": osweep,
         "field_evaluation": fieldres,
+        "complexity_ladder": cladder,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -511,6 +517,70 @@ def omega_sweep(fds, n=6400, omegas=None, proxies=(64, 128)):
         del ref
     return {"workload": f"tripod, {n} nodes, omega {omegas[0]}..{omegas[-1]} step 0.5, tol 1e-8, cells of 100 "
                         "nodes, 1 plane P-wave; error vs dense LU of the same system", "rows": rows}
+
+
+def complexity_ladder(fds, exps=(12, 13, 14, 15, 16, 17), dense_max_exp=14, nrhs=180):
+    """Factor time against N, after the N-versus-time figure of Section 8.2:
+    the ellipse of the full case (1 x 0.5, omega 4, material and tolerance
+    as there, leaf 64, root at level 1) with 2^e nodes.  Per size: factor
+    seconds (best of two after a warm-up build), first-RHS milliseconds,
+    per-RHS microseconds (nrhs - 1 at once), levels, root size, largest
+    rank, and for the smaller sizes the seconds of a dense solve of the same
+    system on the GPU (our assembly + LU: the paper's conventional BEM).
+    Reported with the slope of log(factor time) against log(N) over the
+    four largest sizes (1 for linear)."""
+    import torch
+    import synthetic as sy
+    lam, mu, rho, omega, tol, leaf = 2.0, 1.0, 1.0, 4.0, 1e-8, 64
+    rows = []
+    for e in exps:
+        n = 2 ** e
+        log(f"  ladder 2^{e} nodes")
+        curves = [sy.ellipse(n, 1.0, 0.5)]
+        ts = []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            # the first build tunes the solve's launch shapes; later builds reuse them
+            F = fds.Factor(curves, omega, lam, mu, rho, tol, leaf=leaf, autotune=True)
+            torch.cuda.synchronize()
+            if rep > 0:
+                ts.append(time.perf_counter() - t0)
+            if rep < 2:
+                del F
+        rhs = F.rhs_plane([0] * nrhs, list(sy.plane_wave_angles(nrhs)))
+        F.solve(rhs[:1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x1 = F.solve(rhs[:1])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F.solve(rhs[1:])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        F.solve(rhs[1:])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        st = F.stats()
+        row = {"nodes": n, "unknowns": 2 * n, "factor_s": round(min(ts), 4), "first_rhs_ms": round(1e3 * (t2 - t1), 3),
+               "per_rhs_us": round(1e6 * (t4 - t3) / (nrhs - 1), 2), "levels": int(st["levels"]),
+               "root_size": int(st["root_size"]), "max_rank": int(st["max_rank"])}
+        if e <= dense_max_exp:
+            dofs = np.arange(2 * n)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            A = fds.entries(curves, omega, lam, mu, rho, dofs, dofs)
+            xd = torch.linalg.solve(A, rhs[0])
+            torch.cuda.synchronize()
+            row["dense_s"] = round(time.perf_counter() - t5, 4)
+            row["rel_err_vs_dense"] = float(torch.linalg.norm(x1[0] - xd) / torch.linalg.norm(xd))
+            del A, xd
+        del F, rhs
+        rows.append(row)
+    big = rows[-4:]
+    slope = float(np.polyfit(np.log([r["nodes"] for r in big]), np.log([r["factor_s"] for r in big]), 1)[0])
+    return {"workload": f"ellipse 1x0.5, 2^{exps[0]}..2^{exps[-1]} nodes, omega 4, leaf 64, tol 1e-8, {nrhs} P-waves",
+            "rows": rows, "factor_time_slope_log_log": round(slope, 3)}
 
 
 def field_evaluation(fds, n=6400, nrhs=180, grid=64, reps=3):
