@@ -169,7 +169,10 @@ int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c6
  * (sizes, pointers, kind not 0/1, only one of kind/angle given, nrhs >
  * 65535, leading dimensions above 2^31 - 1), FDS_EGEOM, FDS_ENOMEM,
  * FDS_EHIP.  Device scratch: the evaluation matrix of up to
- * FDS_FIELD_CHUNK_MB (environment, default 2048) MiB of targets at a time.
+ * FDS_FIELD_CHUNK_MB (environment, default 2048) MiB of targets at a time,
+ * and the partial products of the matrix-core product over slabs of 1024
+ * unknowns (ceil(N_unk / 1024) * 2 * chunk targets * nrhs complex numbers
+ * when N_unk > 1024).  Results do not depend on the chunk size.
  * Synchronous. */
 int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, double rho, int32_t nrhs,
               const fds_c64* x, int64_t ld_x, int64_t n_target, const double* targets, const int32_t* kind,
