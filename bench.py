@@ -58,7 +58,7 @@ def _args():
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the solver has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import torch
