@@ -168,11 +168,13 @@ int fds_apply(fds_factor f, int32_t nrhs, const fds_c64* x, int64_t ld_x, fds_c6
  * nrhs == 0 or n_target == 0: nothing to do (FDS_OK).  Errors: FDS_EINVAL
  * (sizes, pointers, kind not 0/1, only one of kind/angle given, nrhs >
  * 65535, leading dimensions above 2^31 - 1), FDS_EGEOM, FDS_ENOMEM,
- * FDS_EHIP.  Device scratch: the evaluation matrix of up to
- * FDS_FIELD_CHUNK_MB (environment, default 2048) MiB of targets at a time,
- * and the partial products of the matrix-core product over slabs of 1024
- * unknowns (ceil(N_unk / 1024) * 2 * chunk targets * nrhs complex numbers
- * when N_unk > 1024).  Results do not depend on the chunk size.
+ * FDS_EHIP.  Device scratch, for a chunk of targets at a time: the
+ * evaluation matrix (2 N_unk complex numbers per target) and the partial
+ * products of the matrix-core product over slabs of 1024 unknowns
+ * (2 ceil(N_unk / 1024) nrhs complex numbers per target when N_unk > 1024),
+ * together at most FDS_FIELD_CHUNK_MB (environment, default 2048) MiB
+ * unless one 32-target chunk needs more.  Results do not depend on the
+ * chunk size.
  * Synchronous. */
 int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, double rho, int32_t nrhs,
               const fds_c64* x, int64_t ld_x, int64_t n_target, const double* targets, const int32_t* kind,

@@ -2263,15 +2263,16 @@ int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, 
       d_ang = ws.upload("field_ang", std::vector<double>(angle, angle + nrhs));
     }
     launch_field_incident(targets, n_target, m, nrhs, d_kind, d_ang, (c64*)out, ld_out, s);
-    // targets per chunk of E^T (2 nu x 2 mc complex): at most FDS_FIELD_CHUNK_MB
-    // (default 2048) MiB, a multiple of 32 targets (one 64-row GEMM tile)
+    // targets per chunk: E^T (2 nu x 2 mc complex) and the product's slab
+    // partials (slabs x 2 mc x nrhs) within FDS_FIELD_CHUNK_MB (default 2048)
+    // MiB, a multiple of 32 targets (one 64-row GEMM tile), at least 32
     const char* env_chunk = std::getenv("FDS_FIELD_CHUNK_MB");
     const int64_t chunk_mb = env_chunk ? std::max<int64_t>(1, std::atoll(env_chunk)) : (int64_t)2048;
-    const int64_t per_target = 2 * nu * (int64_t)sizeof(c64);
+    const int slabs = zgemm_tn_slabs((int)nu);
+    const int64_t per_target = (2 * nu + (slabs > 1 ? (int64_t)slabs * 2 * nrhs : 0)) * (int64_t)sizeof(c64);
     int64_t mc = std::max<int64_t>(32, ((chunk_mb << 20) / per_target) / 32 * 32);
     mc = std::min<int64_t>({mc, n_target, (int64_t)4 * 65535});
     c64* Et = ws.get<c64>("field_E", (size_t)(nu * 2 * mc));
-    const int slabs = zgemm_tn_slabs((int)nu);
     c64* Pz = slabs > 1 ? ws.get<c64>("field_P", (size_t)slabs * 2 * mc * nrhs) : nullptr;
     for (int64_t m0 = 0; m0 < n_target; m0 += mc) {
       const int cur = (int)std::min(mc, n_target - m0);
