@@ -144,7 +144,7 @@ def test_field_full_size_sampled(fdsmod):
     X = sy.random_boundary_values(12800, 180, 15)
     g = np.linspace(-2.0, 2.0, 64)
     T = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
-    os.environ["FDS_FIELD_CHUNK_MB"] = "256"   # 640 targets per chunk
+    os.environ["FDS_FIELD_CHUNK_MB"] = "256"   # 544 targets per chunk
     try:
         U, n = fdsmod.field(curves, 2.0, 1.0, 1.0, 1.0, torch.from_numpy(X).cuda(), T)
     finally:
