@@ -2245,7 +2245,7 @@ int fds_field(const fds_geometry* geom, double omega, double lambda, double mu, 
       return FDS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     ensure_quad();
-    ensure_field_quad(make_quad_tables());
+    ensure_field_quad();
     DevGeom DG;
     DG.init(G, 0, s);
     fds_options o;

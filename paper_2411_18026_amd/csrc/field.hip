@@ -30,6 +30,7 @@
 // (launch_zgemm_tn) then forms out = u^I - E X for all solutions at once.
 #include <cmath>
 
+#include "assembly.hpp"
 #include "field.hpp"
 
 namespace fds {
@@ -42,8 +43,9 @@ __constant__ FieldQuad c_fq;
 
 static bool g_field_quad_ready = false;
 
-void ensure_field_quad(const QuadTables& q) {
+void ensure_field_quad() {
   if (g_field_quad_ready) return;
+  const QuadTables q = make_quad_tables();
   FieldQuad f;
   for (int i = 0; i < 4; ++i) f.g4[i] = q.g4[i], f.w4[i] = q.w4[i];
   for (int i = 0; i < 6; ++i) f.g6[i] = q.g6[i], f.w6[i] = q.w6[i];

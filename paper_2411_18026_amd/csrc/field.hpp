@@ -20,8 +20,9 @@ constexpr int kFieldMaxPanels = 64;   // panels of an element near a target
 std::vector<FieldRun> field_runs(const std::vector<int>& curve_off, const std::vector<int>& curve_n,
                                  const std::vector<int>& prev_node);
 
-// Gauss tables of the field kernel (once per process, from the host tables).
-void ensure_field_quad(const QuadTables& q);
+// Gauss tables of the field kernel (uploaded once per process from the
+// assembly's host tables).
+void ensure_field_quad();
 
 // Et (2 N x 2 mc, leading dimension ld >= 2 N): column 2 m + i, row 2 t + j
 // holds the integral over the two elements of node t of K_ij(x, y) times the
