@@ -11,7 +11,15 @@ right-hand side solved alone, then the other 179 in one batched solve
 (the paper's accounting of the 180-RHS experiment, Section 8.3).
 
 Prints one JSON line.  ``value`` is the factorisation time in seconds
-(lower is better); ``per_rhs_us`` the batched per-RHS solve time.
+(lower is better); ``per_rhs_us`` the batched per-RHS solve time;
+``roofline`` the far-pair integrator against the FP64 peak; ``cpu_baseline``
+the CPU oracle on a bounded sample.  Sections beside the headline (each
+with a --no-... switch): the mixed-precision and learned forms, the
+multi-cavity cases, accuracy against the oracle, the tripod accuracy ladder
+(Section 8.1), the fictitious-frequency and angular-frequency sweeps
+(Section 8.4), the field off the boundary (Section 3), the factor-time
+ladder over N (Section 8.2) and the multiple-right-hand-side experiment
+(Section 8.3).
 """
 from __future__ import annotations
 
