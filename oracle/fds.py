@@ -24,10 +24,13 @@ Readings where the paper is silent or ambiguous:
 * the ID rank is the first j with |R_jj| <= tol |R_11|; the pivot is the column of
   largest exactly recomputed remaining norm, ties within a relative 1e-12
   going to the lowest original column index;
-* the proxy surface of a cell is a 64-gon of radius 1.5 R about the centre
-  of the bounding box of the supports of its active hats (R the largest
-  distance from that centre to those support nodes), with P1 hats and the
-  outward normal;
+* the proxy surface of a cell is an m-gon of radius rho = 1.5 R about the
+  centre of the bounding box of the supports of its active hats (R the
+  largest distance from that centre to those support nodes), with P1 hats
+  and the outward normal; m = max(m_min, ceil(2 k_T rho) + 40) with m_min = 64
+  by default: an outgoing field on a circle of radius rho carries Fourier
+  modes up to about k_T rho, so the polygon must grow with the frequency
+  and the cell size once k_T rho exceeds about 12;
 * the near field of a cell at level l is every active row (column) DOF of
   the other level-l cells whose hat support meets the proxy disk;
 * entries between overlapping supports include I0/2.
@@ -44,7 +47,7 @@ from . import galerkin
 from .galerkin import Boundary, Polygon
 from .kernels import Material
 
-N_PROXY = 64
+N_PROXY = 64          # smallest proxy polygon
 PROXY_RATIO = 1.5
 TIE = 1e-12
 
@@ -123,6 +126,7 @@ class Cell:
     centre: np.ndarray = None
     radius: float = 0.0
     n_near: tuple = (0, 0)     # near rows / near columns of the proxy matrices
+    n_proxy: int = 0           # vertices of the proxy polygon
 
 
 def morton_order(centres):
@@ -254,8 +258,13 @@ def entries(bnd: Boundary, rows, cols, mat, proxy_rows=None, proxy_cols=None):
     return out
 
 
-def proxy_polygon(c, rho):
-    t = 2.0 * np.pi * np.arange(N_PROXY) / N_PROXY
+def proxy_count(k, rho, m_min=N_PROXY):
+    """Vertices of the proxy polygon of radius rho at wavenumber k."""
+    return max(int(m_min), int(math.ceil(2.0 * k * rho)) + 40)
+
+
+def proxy_polygon(c, rho, m=N_PROXY):
+    t = 2.0 * np.pi * np.arange(m) / m
     return Polygon(np.stack([c[0] + rho * np.cos(t), c[1] + rho * np.sin(t)], axis=1), sign=-1)
 
 
@@ -269,17 +278,19 @@ def cell_disk(bnd, c):
     c.radius = float(np.max(np.hypot(sup[:, 0] - c.centre[0], sup[:, 1] - c.centre[1])))
 
 
-def interaction_matrices(bnd, mat, c, others):
+def interaction_matrices(bnd, mat, c, others, m_min=N_PROXY):
     """Proxy-plus-near interaction matrices of a cell (Sections 7.1, 7.2):
     MV = A(proxy + near rows, cols) and MU = A(rows, proxy + near cols)."""
     rho = PROXY_RATIO * c.radius
-    P = proxy_polygon(c.centre, rho)
+    m = proxy_count(mat.kT, rho, m_min)
+    P = proxy_polygon(c.centre, rho, m)
     near_r = np.concatenate([o.rows for o in others]) if others else np.zeros(0, np.int64)
     near_c = np.concatenate([o.cols for o in others]) if others else np.zeros(0, np.int64)
     near_r = near_r[_support_meets_disk(bnd, near_r // 2, c.centre, rho)] if len(near_r) else near_r
     near_c = near_c[_support_meets_disk(bnd, near_c // 2, c.centre, rho)] if len(near_c) else near_c
     c.n_near = (len(near_r), len(near_c))
-    pdofs = np.arange(2 * N_PROXY)
+    c.n_proxy = m
+    pdofs = np.arange(2 * m)
     MV = entries(bnd, pdofs, c.cols, mat, proxy_rows=P)
     MU = entries(bnd, c.rows, pdofs, mat, proxy_cols=P)
     if len(near_r):
@@ -289,11 +300,11 @@ def interaction_matrices(bnd, mat, c, others):
     return MV, MU
 
 
-def compress_cell(bnd, mat, tol, c, others):
+def compress_cell(bnd, mat, tol, c, others, m_min=N_PROXY):
     """One cell of the upward step (Section 7.3, steps 3a-3b): proxy and
     near interaction matrices (Sections 7.1, 7.2), four IDs, and
     X = A_i^{-1} U_i, A~_i = (V_i X)^{-1} (Section 6.2)."""
-    MV, MU = interaction_matrices(bnd, mat, c, others)
+    MV, MU = interaction_matrices(bnd, mat, c, others, m_min)
     nc = [int(np.sum(c.cols % 2 == q)) for q in (0, 1)]
     nr = [int(np.sum(c.rows % 2 == q)) for q in (0, 1)]
     assert nc == nr
@@ -349,8 +360,9 @@ def leaf_sample(curves, lam, mu, rho, omega, tol, leaf, sample):
 class FDS:
     """Factorisation of the Galerkin system; ``solve`` applies it."""
 
-    def __init__(self, curves, lam, mu, rho, omega, tol, leaf=64, root_level=1, alpha=None):
+    def __init__(self, curves, lam, mu, rho, omega, tol, leaf=64, root_level=1, alpha=None, n_proxy=N_PROXY):
         self.mat = Material(lam, mu, rho, omega, alpha)
+        self.n_proxy = int(n_proxy)
         self.bnd = Boundary(curves)
         self.tol = float(tol)
         self.L, self.cells, self.perm = build_tree(self.bnd, leaf)
@@ -363,7 +375,7 @@ class FDS:
         for c in cells:
             cell_disk(bnd, c)
         for c in cells:
-            compress_cell(bnd, mat, self.tol, c, [o for o in cells if o is not c])
+            compress_cell(bnd, mat, self.tol, c, [o for o in cells if o is not c], self.n_proxy)
 
     def _merge(self, lev):
         """Diagonal blocks of the level-(lev-1) cells (rearrangement, Section 6.2)."""

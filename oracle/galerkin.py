@@ -108,9 +108,12 @@ def element_pairs(PA: Polygon, ea, PB: Polygon, fb, mat: Material, chunk: int = 
         prv = np.zeros(K, bool)
     regular = ~(coinc | nxt | prv)
 
-    if np.any(coinc):
-        idx = np.nonzero(coinc)[0]
-        u, v, w, off = qr.coincident_rule()
+    for hi in (False, True):
+        sel = coinc & ((mat.kT * PA.h[ea] > qr.KH_Q4) == hi)
+        if not np.any(sel):
+            continue
+        idx = np.nonzero(sel)[0]
+        u, v, w, off = qr.coincident_rule(qr.Q_COINC_HI if hi else qr.Q_COINC)
         for c0 in range(0, len(idx), chunk // 4):
             ii = idx[c0:c0 + chunk // 4]
             # x - y = (u - v)(p1 - p0) with u - v taken exactly from the rule
@@ -121,11 +124,13 @@ def element_pairs(PA: Polygon, ea, PB: Polygon, fb, mat: Material, chunk: int = 
             r += 0.5 * (h[:, None, None, None, None] * mass[None, :, :, None, None]
                         * np.eye(2)[None, None, None])
             out[ii] = r
-    for mask, flip_u in ((nxt, True), (prv, False)):
+    hi_pair = mat.kT * np.maximum(PA.h[ea], PB.h[fb]) > qr.KH_Q4
+    for mask, flip_u, hi in ((nxt, True, False), (prv, False, False), (nxt, True, True), (prv, False, True)):
+        mask = mask & (hi_pair == hi)
         if not np.any(mask):
             continue
         idx = np.nonzero(mask)[0]
-        up, vp, w = qr.adjacent_rule()
+        up, vp, w = qr.adjacent_rule(qr.Q_ADJ_HI if hi else qr.Q_ADJ)
         if flip_u:      # shared vertex is node 1 of e and node 0 of f
             u, v = 1.0 - up, vp
         else:           # shared vertex is node 0 of e and node 1 of f
@@ -146,7 +151,7 @@ def element_pairs(PA: Polygon, ea, PB: Polygon, fb, mat: Material, chunk: int = 
         idx = np.nonzero(regular)[0]
         delta = segment_distance(PA.p0[ea[idx]], PA.p1[ea[idx]], PB.p0[fb[idx]], PB.p1[fb[idx]])
         hmax = np.maximum(PA.h[ea[idx]], PB.h[fb[idx]])
-        qs = qr.regular_order(delta, hmax)
+        qs = qr.regular_order(delta, hmax, mat.kT)
         for q in np.unique(qs):
             jj = idx[qs == q]
             u, v, w = qr.tensor_rule(int(q))

@@ -9,7 +9,11 @@ already contain the reference Jacobians (the physical weight is w h_e h_f):
 * regular pair (different elements that share no vertex): tensor
   Gauss-Legendre with Q points per element, Q chosen from the gap
   delta = dist(e, f) relative to h = max(h_e, h_f):
-  delta >= FAR_RATIO h -> Q_FAR, delta >= NEAR_RATIO h -> Q_MID, else Q_NEAR.
+  delta >= FAR_RATIO h -> Q_FAR, delta >= NEAR_RATIO h -> Q_MID, else Q_NEAR;
+  and from the oscillation of the kernels over an element: at least Q_MID
+  points when k_T h > KH_Q4 and Q_NEAR when k_T h > KH_Q6 (k_T the larger
+  wavenumber; Q_NEAR holds to about k_T h = 8, beyond which the mesh does
+  not resolve the wave).
 * coincident pair (e == f): the square is split along its diagonal; on each
   triangle the offset d = |u - v| is mapped as d = s^P_COINC and s is
   integrated with Q_COINC Gauss points, the position along the diagonal with
@@ -17,6 +21,9 @@ already contain the reference Jacobians (the physical weight is w h_e h_f):
 * adjacent pair (one shared vertex): coordinates measured from the shared
   vertex; each of the two triangles is Duffy-mapped (u', v') = (xi, xi eta) or
   (xi eta, xi), xi = s^P_ADJ, with Q_ADJ x Q_ADJ Gauss points in (s, eta).
+* both singular rules take Q_COINC_HI and Q_ADJ_HI points in place of
+  Q_COINC and Q_ADJ when k_T h > KH_Q4 (h the longer element): the kernels
+  then oscillate over the pair.  Boundary elements need k_T h <= KH_MAX.
 
 The Gauss-Legendre nodes come from ``numpy.polynomial.legendre.leggauss``.
 """
@@ -31,10 +38,15 @@ Q_MID = 6
 Q_NEAR = 10
 FAR_RATIO = 8.0
 NEAR_RATIO = 2.0
+KH_Q4 = 0.5
+KH_Q6 = 2.5
+KH_MAX = 5.0
 Q_COINC = 20
 P_COINC = 6
 Q_ADJ = 12
 P_ADJ = 4
+Q_COINC_HI = 30
+Q_ADJ_HI = 24
 Q_RHS = 6
 
 
@@ -94,10 +106,14 @@ def adjacent_rule(q: int = Q_ADJ, p: int = P_ADJ):
     return np.concatenate([u1, u2]), np.concatenate([v1, v2]), np.concatenate([w, w])
 
 
-def regular_order(delta, h):
-    """Tensor order for a regular pair with gap delta and longer element h."""
+def regular_order(delta, h, k):
+    """Tensor order for a regular pair with gap delta, longer element h and
+    largest wavenumber k."""
     delta = np.asarray(delta)
+    h = np.broadcast_to(np.asarray(h, dtype=np.float64), delta.shape)
     q = np.full(delta.shape, Q_NEAR, dtype=np.int64)
     q[delta >= NEAR_RATIO * h] = Q_MID
     q[delta >= FAR_RATIO * h] = Q_FAR
+    q[(k * h > KH_Q4) & (q < Q_MID)] = Q_MID
+    q[k * h > KH_Q6] = Q_NEAR
     return q
