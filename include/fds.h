@@ -31,6 +31,7 @@
 #ifndef FDS_H
 #define FDS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -44,7 +45,9 @@ typedef enum {
   FDS_OK = 0,
   FDS_EINVAL = 1,     /* bad argument: null pointer, size < 1, ld too small, omega <= 0, mu <= 0,
                          lambda + mu <= 0, rho <= 0, tol outside (0, 1) */
-  FDS_EGEOM = 2,      /* a curve with fewer than 8 nodes, a zero-length element, clockwise curve */
+  FDS_EGEOM = 2,      /* a curve with fewer than 8 nodes, a zero-length element, clockwise curve; in
+                         fds_build also an element longer than 5 / k_T (the quadrature rules below hold
+                         up to k_T h = 5, about 1.3 elements per transverse wavelength) */
   FDS_ENOMEM = 3,     /* device or host allocation failed */
   FDS_EHIP = 4,       /* a HIP runtime call failed */
   FDS_ESINGULAR = 5,  /* zero or non-finite pivot in an LU factorisation */
@@ -59,7 +62,9 @@ typedef struct {
 
 typedef struct {
   int32_t leaf_nodes;       /* nodes per leaf cell (Section 5.1); default 64 */
-  int32_t n_proxy;          /* vertices of each proxy polygon (Section 7.1); default 64 */
+  int32_t n_proxy;          /* smallest proxy polygon (Section 7.1); default 64.  A cell whose proxy circle
+                               has radius rho gets max(n_proxy, ceil(2 k_T rho) + 40) vertices: an outgoing
+                               field on the circle carries Fourier modes up to about k_T rho */
   int32_t root_level;       /* level l0 at which the compressed system is solved (Section 7.3); default 1 */
   int32_t solve_graph;      /* 1: run the solve sweeps as a hipGraph captured once per nrhs on a library
                                stream (the caller's stream is synchronised first); default 0 */
@@ -109,12 +114,20 @@ int fds_options_default(fds_options* opt);
  * column-pivoted-QR interpolative decompositions, the inverse-free upward
  * elimination A~_i = (V_i A_i^{-1} U_i)^{-1}, and an LU of the compressed
  * system at level l0.  ``tol`` is the ID truncation tolerance (Section 8.1).
+ * Entries (Section 5.2; the paper gives no quadrature) by element pairs:
+ * tensor Gauss-Legendre with 4, 6 or 10 points per element for a gap of at
+ * least 8 h, at least 2 h, or less (h the longer element), at least 6
+ * points when k_T h > 0.5 and 10 when k_T h > 2.5; coincident pairs by a
+ * graded rule across the diagonal (20 offsets, 30 when k_T h > 0.5) and
+ * adjacent pairs by Duffy maps about the shared vertex (12 x 12 points per
+ * triangle, 24 x 24 when k_T h > 0.5).
  * Synchronous: returns when the factor is complete.  The factor lives in
  * device memory until fds_destroy.  opt == NULL selects the defaults. */
 int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, double rho,
               double tol, const fds_options* opt, void* stream, fds_factor* out);
 
-/* Number of complex unknowns 2 N. */
+/* Number of complex unknowns 2 N: both displacement components at each of the
+ * N nodes of the polygons (Section 4), numbered as stated at the top. */
 int fds_size(fds_factor f, int64_t* n_unknowns);
 
 /* Galerkin load vectors f^s_i = int psi^s (u^I_i + alpha (T u^I)_i) ds
@@ -269,6 +282,31 @@ void fds_destroy(fds_factor f);
  * safe to call at any time from the host. */
 void fds_release_cache(void);
 int64_t fds_cached_bytes(void);
+
+/* Device memory from the caller instead of the cache (so that, e.g.,
+ * PyTorch's caching allocator owns every buffer of the library; the
+ * interface asks for PyTorch as the provider of device memory):
+ *   alloc(bytes, device, stream, ctx) returns a device pointer of at least
+ *     ``bytes`` bytes on HIP device ``device``, to be used on ``stream``
+ *     (a hipStream_t), or NULL on failure (the entry point then returns
+ *     FDS_ENOMEM);
+ *   free_fn(ptr, bytes, device, stream, ctx) takes it back; ``stream`` is the
+ *     one named at allocation.  Work queued on that stream may still use the
+ *     block: the allocator may reuse it for later work on that stream (stream
+ *     order) but not on another stream before that work has finished (the
+ *     library synchronises any other stream that used the block before the
+ *     call).
+ * Both callbacks may run on any host thread, during any entry point.
+ * alloc == free_fn == NULL restores the library's cache.  The setting is
+ * process-wide.  Returns FDS_EINVAL if exactly one callback is NULL, or
+ * while the library holds device blocks (live factors; their blocks must go
+ * back to the allocator that made them): call it before the first
+ * fds_build or after every factor has been destroyed.  On success the
+ * cache is emptied, so fds_cached_bytes() stays 0 while the callbacks are
+ * set. */
+typedef void* (*fds_alloc_fn)(size_t bytes, int32_t device, void* stream, void* ctx);
+typedef void (*fds_free_fn)(void* ptr, size_t bytes, int32_t device, void* stream, void* ctx);
+int fds_set_allocator(fds_alloc_fn alloc, fds_free_fn free_fn, void* ctx);
 
 const char* fds_strerror(int code);
 /* Text of the last error raised on the calling thread (empty if none). */

@@ -24,7 +24,11 @@ _lib = None
 
 
 class FdsError(RuntimeError):
-    pass
+    """A library call returned a non-zero fds_status (``code``)."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 class _C64(ctypes.Structure):
@@ -77,7 +81,40 @@ EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
            "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
            "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes",
-           "fds_field"]
+           "fds_field", "fds_set_allocator"]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None      # the ctypes callbacks in use (kept alive)
+
+
+def use_torch_allocator():
+    """Route every device buffer of the library through PyTorch's caching
+    allocator (fds_set_allocator).  Call before the first factorisation or
+    after every factor has been destroyed."""
+    global _allocator_refs
+    import torch
+
+    def _alloc(nbytes, device, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+        except Exception:      # out of memory: the library reports FDS_ENOMEM
+            return None
+
+    def _free(ptr, nbytes, device, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(load().fds_set_allocator(refs[0], refs[1], None))
+    _allocator_refs = refs
+
+
+def use_library_allocator():
+    """Back to the library's own block cache."""
+    global _allocator_refs
+    _check(load().fds_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+    _allocator_refs = None
 
 
 def lib_path() -> str:
@@ -130,6 +167,7 @@ def load():
     L.fds_release_cache.restype = None
     L.fds_cached_bytes.argtypes = []
     L.fds_cached_bytes.restype = i64
+    L.fds_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     L.fds_cpqr_batched.argtypes = [i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, i32, vp, vp]
     _lib = L
@@ -139,7 +177,7 @@ def load():
 def _check(code):
     if code != 0:
         L = load()
-        raise FdsError(f"{L.fds_strerror(code).decode()} ({code}): {L.fds_last_error().decode()}")
+        raise FdsError(f"{L.fds_strerror(code).decode()} ({code}): {L.fds_last_error().decode()}", code)
 
 
 def _geometry(curves):
@@ -207,7 +245,7 @@ class NotConverged(FdsError):
     the last iterate."""
 
     def __init__(self, msg, x):
-        super().__init__(msg)
+        super().__init__(msg, 6)
         self.x = x
 
 

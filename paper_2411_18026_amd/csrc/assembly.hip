@@ -140,7 +140,7 @@ __device__ inline double seg_seg_dist(const Elem& e, const Elem& f) {
   return d;
 }
 
-__device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf) {
+__device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf, double kT) {
   if (e.poly == f.poly) {
     if (ge == gf) return kCoinc;
     const int n = e.npoly;
@@ -149,7 +149,9 @@ __device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf
   }
   const double d = seg_seg_dist(e, f);
   const double hm = fmax(e.h, f.h);
-  if (d >= kFarRatio * hm) return kQ4;
+  const double kh = kT * hm;
+  if (kh > kKhQ6) return kQ10;
+  if (d >= kFarRatio * hm && kh <= kKhQ4) return kQ4;
   if (d >= kNearRatio * hm) return kQ6;
   return kQ10;
 }
@@ -186,11 +188,18 @@ __global__ void k_elem_geometry(const double* __restrict__ xy, const int* __rest
 
 // proxy polygons: n_proxy vertices c + rho (cos 2 pi s/n, sin 2 pi s/n),
 // outward normal n = -J tau, t = J n = tau: d_s N0 = -1/h, d_s N1 = 1/h.
-__global__ void k_proxy_elems(const double* __restrict__ crd, int n_cells, int n_proxy, int poly_base,
-                              Elem* __restrict__ out) {
+__global__ void k_proxy_elems(const double* __restrict__ crd, const int* __restrict__ poff, int n_cells, int total,
+                              int poly_base, Elem* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_cells * n_proxy) return;
-  const int c = g / n_proxy, s = g % n_proxy;
+  if (g >= total) return;
+  // cell of element g: the last c with poff[c] <= g (poff ascending, poff[n_cells] = total)
+  int lo = 0, hi = n_cells - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const int c = lo, n_proxy = poff[c + 1] - poff[c], s = g - poff[c];
   const double cx = crd[3 * c], cy = crd[3 * c + 1], rho = crd[3 * c + 2];
   const double t0 = 2.0 * kPi * s / n_proxy;
   const double t1 = 2.0 * kPi * ((s + 1) % n_proxy) / n_proxy;
@@ -224,7 +233,7 @@ constexpr int kClsTile = 1024;
 __global__ void __launch_bounds__(256) k_classify(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
                                                   const int* __restrict__ elist, const Elem* __restrict__ elems,
                                                   unsigned long long* __restrict__ lists, int64_t list_cap,
-                                                  unsigned int* __restrict__ counters) {
+                                                  unsigned int* __restrict__ counters, double kT) {
   __shared__ unsigned int s_wcnt[4][kNumClass];
   __shared__ unsigned int s_base[4][kNumClass];
   const Tile t = tiles[blockIdx.x];
@@ -244,7 +253,7 @@ __global__ void __launch_bounds__(256) k_classify(const Tile* __restrict__ tiles
       int ie, je;
       pair_elems(jb, p, ie, je);
       const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
-      cls[j] = classify_pair(elems[ge], elems[gf], ge, gf);
+      cls[j] = classify_pair(elems[ge], elems[gf], ge, gf, kT);
     }
     off[j] = 0;
 #pragma unroll
@@ -432,12 +441,20 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
 #pragma unroll
   for (int k = 0; k < 16; ++k) A.R[k] = cmk(0.0, 0.0);
   const double hh = e.h * f.h;
+  // the longer rule when the kernels oscillate over the pair (uniform over
+  // the wavefront: one pair per wavefront)
+  const bool hi = m.kT * fmax(e.h, f.h) > kKhQ4;
   if (C == kCoinc) {
     const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
-    for (int p = lane; p < kNCoincPts; p += 64) {
-      const double off = c_quad.coff[p];
-      acc_point_direct(m, off * ax, off * ay, c_quad.cw[p] * hh, c_quad.cu[p], c_quad.cv[p], e.nx, e.ny, f.nx, f.ny,
-                       e.dN0, e.dN1, f.dN0, f.dN1, A);
+    const int npts = hi ? kNCoincHiPts : kNCoincPts;
+    const double* cu = hi ? c_quad.chu : c_quad.cu;
+    const double* cv = hi ? c_quad.chv : c_quad.cv;
+    const double* cw = hi ? c_quad.chw : c_quad.cw;
+    const double* co = hi ? c_quad.choff : c_quad.coff;
+    for (int p = lane; p < npts; p += 64) {
+      const double off = co[p];
+      acc_point_direct(m, off * ax, off * ay, cw[p] * hh, cu[p], cv[p], e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0,
+                       f.dN1, A);
     }
   } else {
     // vectors from the shared vertex to the far ends of e and f
@@ -453,12 +470,16 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
       Bx = f.x0 - f.x1;
       By = f.y0 - f.y1;
     }
-    for (int p = lane; p < kNAdjPts; p += 64) {
-      const double up = c_quad.au[p], vp = c_quad.av[p];
+    const int npts = hi ? kNAdjHiPts : kNAdjPts;
+    const double* au = hi ? c_quad.ahu : c_quad.au;
+    const double* av = hi ? c_quad.ahv : c_quad.av;
+    const double* aw = hi ? c_quad.ahw : c_quad.aw;
+    for (int p = lane; p < npts; p += 64) {
+      const double up = au[p], vp = av[p];
       const double u = (C == kAdjNext) ? 1.0 - up : up;
       const double v = (C == kAdjNext) ? vp : 1.0 - vp;
-      acc_point_direct(m, up * Ax - vp * Bx, up * Ay - vp * By, c_quad.aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny,
-                       e.dN0, e.dN1, f.dN0, f.dN1, A);
+      acc_point_direct(m, up * Ax - vp * Bx, up * Ay - vp * By, aw[p] * hh, u, v, e.nx, e.ny, f.nx, f.ny, e.dN0,
+                       e.dN1, f.dN0, f.dN1, A);
     }
   }
   const int64_t slot = pair_slot(jb, ie, je);
@@ -588,17 +609,17 @@ void launch_elem_geometry(const double* xy, const int* curve_of, const int* curv
   FDS_HIP(hipGetLastError());
 }
 
-void launch_proxy_elems(const double* crd, int n_cells, int n_proxy, int poly_base, Elem* out, hipStream_t s) {
-  const int n = n_cells * n_proxy;
-  if (n == 0) return;
-  k_proxy_elems<<<(n + 255) / 256, 256, 0, s>>>(crd, n_cells, n_proxy, poly_base, out);
+void launch_proxy_elems(const double* crd, const int* poff, int n_cells, int total, int poly_base, Elem* out,
+                        hipStream_t s) {
+  if (total == 0 || n_cells == 0) return;
+  k_proxy_elems<<<(total + 255) / 256, 256, 0, s>>>(crd, poff, n_cells, total, poly_base, out);
   FDS_HIP(hipGetLastError());
 }
 
 void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int* elist, const Elem* elems,
-                     unsigned long long* lists, int64_t cap, unsigned int* counters, hipStream_t s) {
+                     unsigned long long* lists, int64_t cap, unsigned int* counters, double kT, hipStream_t s) {
   if (n_tiles == 0) return;
-  k_classify<<<n_tiles, 256, 0, s>>>(tiles, jobs, elist, elems, lists, cap, counters);
+  k_classify<<<n_tiles, 256, 0, s>>>(tiles, jobs, elist, elems, lists, cap, counters, kT);
   FDS_HIP(hipGetLastError());
 }
 

@@ -11,9 +11,12 @@ namespace fds {
 void upload_quad_tables(const QuadTables& q);
 void launch_elem_geometry(const double* xy, const int* curve_of, const int* curve_off, const int* curve_n,
                           int n_elem, Elem* out, hipStream_t s);
-void launch_proxy_elems(const double* crd, int n_cells, int n_proxy, int poly_base, Elem* out, hipStream_t s);
+// proxy polygons: cell c gets poff[c+1] - poff[c] vertices on the circle
+// (crd[3c], crd[3c+1]) of radius crd[3c+2]; poff device, [n_cells + 1]
+void launch_proxy_elems(const double* crd, const int* poff, int n_cells, int total, int poly_base, Elem* out,
+                        hipStream_t s);
 void launch_classify(const Tile* tiles, int n_tiles, const Job* jobs, const int* elist, const Elem* elems,
-                     unsigned long long* lists, int64_t cap, unsigned int* counters, hipStream_t s);
+                     unsigned long long* lists, int64_t cap, unsigned int* counters, double kT, hipStream_t s);
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
                   const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
                   hipEvent_t* ev = nullptr);

@@ -47,59 +47,68 @@ static void gauss_legendre01(int n, double* x01, double* w01) {
   }
 }
 
+// coincident rule: d = s^P on each triangle of the square, 2-point Gauss
+// along the diagonal; Q offsets, 4 Q points
+static void coincident_rule(int Q, int P, double* cu, double* cv, double* cw, double* coff) {
+  std::vector<double> s(Q), ws(Q);
+  double g2[2], w2[2];
+  gauss_legendre01(Q, s.data(), ws.data());
+  gauss_legendre01(2, g2, w2);
+  int p = 0;
+  for (int i = 0; i < Q; ++i) {
+    const double d = std::pow(s[i], P);
+    const double wd = ws[i] * P * std::pow(s[i], P - 1);
+    const double ell = 1.0 - d;
+    for (int k = 0; k < 2; ++k) {
+      const double t = ell * g2[k];
+      const double w = wd * ell * w2[k];
+      cu[p] = t + d;
+      cv[p] = t;
+      cw[p] = w;
+      coff[p] = d;
+      ++p;
+      cu[p] = t;
+      cv[p] = t + d;
+      cw[p] = w;
+      coff[p] = -d;
+      ++p;
+    }
+  }
+}
+
+// adjacent rule: Duffy map of both triangles about the shared vertex,
+// xi = s^P, Q x Q points per triangle
+static void adjacent_rule(int Q, int P, double* au, double* av, double* aw) {
+  std::vector<double> s(Q), ws(Q), eta(Q), we(Q);
+  gauss_legendre01(Q, s.data(), ws.data());
+  gauss_legendre01(Q, eta.data(), we.data());
+  const int half = Q * Q;
+  for (int i = 0; i < Q; ++i) {
+    const double xi = std::pow(s[i], P);
+    const double wxi = ws[i] * P * std::pow(s[i], P - 1);
+    for (int j = 0; j < Q; ++j) {
+      const int p = i * Q + j;
+      const double w = wxi * we[j] * xi;
+      au[p] = xi;
+      av[p] = xi * eta[j];
+      aw[p] = w;
+      au[half + p] = xi * eta[j];
+      av[half + p] = xi;
+      aw[half + p] = w;
+    }
+  }
+}
+
 QuadTables make_quad_tables() {
   QuadTables q{};
   gauss_legendre01(4, q.g4, q.w4);
   gauss_legendre01(6, q.g6, q.w6);
   gauss_legendre01(10, q.g10, q.w10);
   gauss_legendre01(6, q.rg, q.rw);
-  // coincident: d = s^P on each triangle of the square, 2-point Gauss along the diagonal
-  {
-    double s[kQCoinc], ws[kQCoinc], g2[2], w2[2];
-    gauss_legendre01(kQCoinc, s, ws);
-    gauss_legendre01(2, g2, w2);
-    int p = 0;
-    for (int i = 0; i < kQCoinc; ++i) {
-      const double d = std::pow(s[i], kPCoinc);
-      const double wd = ws[i] * kPCoinc * std::pow(s[i], kPCoinc - 1);
-      const double ell = 1.0 - d;
-      for (int k = 0; k < 2; ++k) {
-        const double t = ell * g2[k];
-        const double w = wd * ell * w2[k];
-        q.cu[p] = t + d;
-        q.cv[p] = t;
-        q.cw[p] = w;
-        q.coff[p] = d;
-        ++p;
-        q.cu[p] = t;
-        q.cv[p] = t + d;
-        q.cw[p] = w;
-        q.coff[p] = -d;
-        ++p;
-      }
-    }
-  }
-  // adjacent: Duffy map of both triangles about the shared vertex, xi = s^P
-  {
-    double s[kQAdj], ws[kQAdj], eta[kQAdj], we[kQAdj];
-    gauss_legendre01(kQAdj, s, ws);
-    gauss_legendre01(kQAdj, eta, we);
-    const int half = kQAdj * kQAdj;
-    for (int i = 0; i < kQAdj; ++i) {
-      const double xi = std::pow(s[i], kPAdj);
-      const double wxi = ws[i] * kPAdj * std::pow(s[i], kPAdj - 1);
-      for (int j = 0; j < kQAdj; ++j) {
-        const int p = i * kQAdj + j;
-        const double w = wxi * we[j] * xi;
-        q.au[p] = xi;
-        q.av[p] = xi * eta[j];
-        q.aw[p] = w;
-        q.au[half + p] = xi * eta[j];
-        q.av[half + p] = xi;
-        q.aw[half + p] = w;
-      }
-    }
-  }
+  coincident_rule(kQCoinc, kPCoinc, q.cu, q.cv, q.cw, q.coff);
+  adjacent_rule(kQAdj, kPAdj, q.au, q.av, q.aw);
+  coincident_rule(kQCoincHi, kPCoinc, q.chu, q.chv, q.chw, q.choff);
+  adjacent_rule(kQAdjHi, kPAdj, q.ahu, q.ahv, q.ahw);
   return q;
 }
 
@@ -221,7 +230,7 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
     }
     FDS_HIP(hipMemsetAsync(d_cnt, 0, kNumClass * sizeof(unsigned), s));
     if (!ev.empty()) FDS_HIP(hipEventRecord(ev[0], s));
-    launch_classify(d_pt, (int)ptiles.size(), d_jobs, d_elist, d_elems, d_lists, np, d_cnt, s);
+    launch_classify(d_pt, (int)ptiles.size(), d_jobs, d_elist, d_elems, d_lists, np, d_cnt, m.kT, s);
     launch_pairs(d_lists, np, d_cnt, d_jobs, d_elist, d_elems, m, d_res, np, s, ev.empty() ? nullptr : ev.data() + 1);
     launch_gather(d_ot, (int)otiles.size(), d_jobs, d_dofs, d_pos, d_res, np, d_out, s);
     if (!ev.empty()) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -90,6 +91,24 @@ constexpr int kNCoincPts = 4 * kQCoinc;
 constexpr int kNAdjPts = 2 * kQAdj * kQAdj;
 constexpr double kFarRatio = 8.0;
 constexpr double kNearRatio = 2.0;
+// Orders grow with the oscillation of the kernels over an element: a
+// regular pair takes at least 6 points per element when k_T h > kKhQ4 and
+// 10 when k_T h > kKhQ6 (h the longer element); a singular pair takes the
+// longer rules below when k_T h > kKhQ4.  Boundary elements need
+// k_T h <= kKhMax.
+constexpr double kKhQ4 = 0.5;
+constexpr double kKhQ6 = 2.5;
+constexpr double kKhMax = 5.0;
+constexpr int kQCoincHi = 30;
+constexpr int kQAdjHi = 24;
+constexpr int kNCoincHiPts = 4 * kQCoincHi;
+constexpr int kNAdjHiPts = 2 * kQAdjHi * kQAdjHi;
+// smallest proxy polygon for a proxy radius rho at wavenumber k: outgoing
+// fields on the circle carry Fourier modes up to about k rho
+inline int proxy_count(double k, double rho, int m_min) {
+  const double m = std::ceil(2.0 * k * rho) + 40.0;
+  return m > (double)m_min ? (int)m : m_min;
+}
 
 // Sum over the 64 lanes of a wavefront with DPP moves inside each row of 16
 // lanes (swap neighbours, swap pairs, half-row mirror, row mirror: after
@@ -118,6 +137,9 @@ struct QuadTables {
   double cu[kNCoincPts], cv[kNCoincPts], cw[kNCoincPts], coff[kNCoincPts];
   double au[kNAdjPts], av[kNAdjPts], aw[kNAdjPts];
   double rg[6], rw[6];   // load-vector rule
+  // the longer singular rules (k_T h > kKhQ4)
+  double chu[kNCoincHiPts], chv[kNCoincHiPts], chw[kNCoincHiPts], choff[kNCoincHiPts];
+  double ahu[kNAdjHiPts], ahv[kNAdjHiPts], ahw[kNAdjHiPts];
 };
 
 class Error : public std::runtime_error {

@@ -45,9 +45,23 @@ class BlockCache {
   }
 
   void* alloc(size_t bytes, hipStream_t s, size_t* got) {
-    const size_t b = round_block(std::max<size_t>(bytes, 1));
     int dev = 0;
     FDS_HIP(hipGetDevice(&dev));
+    UserAllocator u;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      u = user_;
+    }
+    if (u.alloc) {   // the caller's allocator (called outside the lock): no caching
+      const size_t b = std::max<size_t>(bytes, 1);
+      void* p = u.alloc(b, dev, (void*)s, u.ctx);
+      if (!p) throw Error(3, "the allocator set by fds_set_allocator returned NULL");
+      std::lock_guard<std::mutex> g(mu_);
+      live_[p] = Live{b, dev, true, s};
+      *got = b;
+      return p;
+    }
+    const size_t b = round_block(std::max<size_t>(bytes, 1));
     {
       std::lock_guard<std::mutex> g(mu_);
       DeviceCache& dc = devs_[dev];
@@ -66,7 +80,7 @@ class BlockCache {
         events_.push_back(pick->second.ev);
         dc.free.erase(pick);
         dc.cached -= b;
-        live_[p] = Live{b, dev};
+        live_[p] = Live{b, dev, false, s};
         *got = b;
         return p;
       }
@@ -81,14 +95,14 @@ class BlockCache {
       }
     }
     std::lock_guard<std::mutex> g(mu_);
-    live_[p] = Live{b, dev};
+    live_[p] = Live{b, dev, false, s};
     *got = b;
     return p;
   }
 
   void free(void* p, hipStream_t s) {
     if (!p) return;
-    std::lock_guard<std::mutex> g(mu_);
+    std::unique_lock<std::mutex> g(mu_);
     auto it = live_.find(p);
     if (it == live_.end()) {
       (void)hipFree(p);
@@ -96,6 +110,16 @@ class BlockCache {
     }
     const Live l = it->second;
     live_.erase(it);
+    if (l.user) {
+      // a stream-ordered allocator may hand the block out again for work on
+      // the stream it was allocated for; work queued on another stream must
+      // have finished first
+      const UserAllocator u = user_;
+      g.unlock();
+      if (s != l.stream) (void)hipStreamSynchronize(s);
+      u.free(p, l.bytes, l.dev, (void*)l.stream, u.ctx);
+      return;
+    }
     hipEvent_t ev = nullptr;
     if (!events_.empty()) {
       ev = events_.back();
@@ -128,10 +152,21 @@ class BlockCache {
     for (auto& kv : devs_) trim_locked(kv.second, 0);
   }
 
+  // false while any block is live (it must go back to the allocator that made it)
+  bool set_user(const UserAllocator& u) {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!live_.empty()) return false;
+    for (auto& kv : devs_) trim_locked(kv.second, 0);
+    user_ = u;
+    return true;
+  }
+
  private:
   struct Live {
     size_t bytes;
     int dev;
+    bool user;          // made by the caller's allocator
+    hipStream_t stream; // stream named at allocation
   };
 
   void release_device(int dev) {
@@ -164,6 +199,7 @@ class BlockCache {
   std::map<int, DeviceCache> devs_;
   std::unordered_map<void*, Live> live_;
   std::vector<hipEvent_t> events_;
+  UserAllocator user_{};
 };
 
 }  // namespace
@@ -187,5 +223,7 @@ void cache_free(void* p, hipStream_t s) { BlockCache::get().free(p, s); }
 size_t cache_bytes() { return BlockCache::get().cached_bytes(); }
 
 void cache_release() { BlockCache::get().release_all(); }
+
+bool set_user_allocator(const UserAllocator& u) { return BlockCache::get().set_user(u); }
 
 }  // namespace fds

@@ -14,7 +14,8 @@
 // synchronising their stream, so blocks freed afterwards are idle.
 // Size classes: powers of two up to 1 MiB, then multiples of 2 MiB.  The
 // cache holds at most FDS_CACHE_LIMIT_MB (default 65536) MiB per device and
-// gives everything back on fds_release_cache().
+// gives everything back on fds_release_cache().  A caller can replace the
+// cache by an allocator of its own (fds_set_allocator).
 #pragma once
 
 #include <map>
@@ -24,6 +25,16 @@
 #include "common.hpp"
 
 namespace fds {
+
+// A caller's allocator (fds_set_allocator): when set, every device block
+// comes from it and goes back to it, bypassing the cache.
+struct UserAllocator {
+  void* (*alloc)(size_t bytes, int device, void* stream, void* ctx) = nullptr;
+  void (*free)(void* p, size_t bytes, int device, void* stream, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+// false (nothing changed) while blocks are live
+bool set_user_allocator(const UserAllocator& u);
 
 void set_alloc_stream(hipStream_t s, bool scoped);
 hipStream_t alloc_stream();

@@ -17,8 +17,10 @@
 //     columns of a component share the rank k_c = max(k_row, k_col) and take
 //     the first k_c pivots of their pivoted QRs, so that A~_i is square;
 //   * ID rank: first j with |R_jj| <= tol |R_11|;
-//   * proxy: n_proxy-gon (default 64) of radius 1.5 R about the centre of the
-//     bounding box of the supports of the cell's active hats, outward normal;
+//   * proxy: m-gon of radius rho = 1.5 R about the centre of the
+//     bounding box of the supports of the cell's active hats, outward normal,
+//     m = max(n_proxy, ceil(2 k_T rho) + 40) (an outgoing field on the circle
+//     carries Fourier modes up to about k_T rho);
 //   * near field: active DOFs of the other cells of the level whose hat
 //     support meets the proxy disk.
 // The host keeps only index bookkeeping (tree, DOF lists, near sets);
@@ -142,6 +144,15 @@ struct DevGeom {
     elems = DevBuf<Elem>((size_t)cap);
     launch_elem_geometry(xy.p, curve_of.p, curve_off.p, curve_n.p, G.n_nodes, elems.p, s);
   }
+  // room for at least ``need`` elements (boundary elements kept)
+  void reserve(int64_t need, hipStream_t s) {
+    if (need <= cap) return;
+    DevBuf<Elem> grown((size_t)need);
+    FDS_HIP(hipMemcpyAsync(grown.p, elems.p, (size_t)n_gamma * sizeof(Elem), hipMemcpyDeviceToDevice, s));
+    FDS_HIP(hipStreamSynchronize(s));
+    elems = std::move(grown);
+    cap = need;
+  }
 };
 
 // Side of a block from a list of boundary DOFs (2 t + i).  A per-thread slot
@@ -205,6 +216,7 @@ struct CellLevel {
   std::vector<int64_t> piv_off;
   int64_t a_tot = 0, piv_tot = 0;
   int bmax = 0;
+  int max_proxy = 0;                             // largest proxy polygon of the level
   // compression results (levels > l0)
   std::vector<int> k0, k1, r;
   std::vector<int> kr0, kc0, kr1, kc1;           // ranks at tolerance
@@ -1064,7 +1076,6 @@ static void compress_level(Factor& F, int lev) {
   CellLevel& lv = F.levels[lev];
   Workspace& ws = F.ws;
   hipStream_t s = F.stream;
-  const int np = F.opt.n_proxy;
   const int n = lv.n;
   auto ht0 = std::make_unique<HostTimer>(0);
   // proxy disks
@@ -1112,17 +1123,25 @@ static void compress_level(Factor& F, int lev) {
     }
   });
   ht0.reset();
-  // proxy elements
+  // proxy elements: per cell a polygon of npx[q] vertices (at least
+  // n_proxy, more when the wave oscillates faster than it resolves)
+  std::vector<int> npx(n), poff(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    npx[q] = proxy_count(F.m.kT, crd[3 * q + 2], F.opt.n_proxy);
+    poff[q + 1] = poff[q] + npx[q];
+    lv.max_proxy = std::max(lv.max_proxy, npx[q]);
+  }
   const int64_t pbase = F.DG.n_gamma;
-  if (pbase + (int64_t)n * np > F.DG.cap) throw Error(FDS_ENOMEM, "proxy element table too small");
-  launch_proxy_elems(ws.upload("crd", crd), n, np, G.n_curves, F.DG.elems.p + pbase, s);
+  F.DG.reserve(pbase + poff[n], s);
+  launch_proxy_elems(ws.upload("crd", crd), ws.upload("poff", poff), n, poff[n], G.n_curves, F.DG.elems.p + pbase,
+                     s);
   // interaction matrices: MV = A(proxy + near rows, cols) and MUt = A(rows, proxy + near cols)^T
   std::vector<int64_t> mv_off(n), mu_off(n);
   std::vector<int> mv_m(n), mu_m(n);
   int64_t mv_tot = 0, mu_tot = 0;
   for (int q = 0; q < n; ++q) {
-    mv_m[q] = 2 * np + (int)near_r[q].size();
-    mu_m[q] = 2 * np + (int)near_c[q].size();
+    mv_m[q] = 2 * npx[q] + (int)near_r[q].size();
+    mu_m[q] = 2 * npx[q] + (int)near_c[q].size();
     mv_off[q] = mv_tot;
     mv_tot += (int64_t)mv_m[q] * lv.b[q];
     mu_off[q] = mu_tot;
@@ -1137,7 +1156,7 @@ static void compress_level(Factor& F, int lev) {
     std::vector<BlockReq> reqs(n);
     parallel_for(n, [&](int q) {
       BlockReq& a = reqs[q];
-      side_add_proxy(a.rows, (int)(pbase + (int64_t)q * np), np);
+      side_add_proxy(a.rows, (int)(pbase + poff[q]), npx[q]);
       side_append(G, a.rows, near_r[q]);
       a.cols = side_from_dofs(G, lv.cols[q]);
       a.out_off = mv_off[q];
@@ -1151,7 +1170,7 @@ static void compress_level(Factor& F, int lev) {
     parallel_for(n, [&](int q) {
       BlockReq& a = reqs[q];
       a.rows = side_from_dofs(G, lv.rows[q]);
-      side_add_proxy(a.cols, (int)(pbase + (int64_t)q * np), np);
+      side_add_proxy(a.cols, (int)(pbase + poff[q]), npx[q]);
       side_append(G, a.cols, near_c[q]);
       a.out_off = mu_off[q];
       a.rs = mu_m[q];   // transposed storage
@@ -1972,6 +1991,10 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->stream = (hipStream_t)stream;
     F->ws.set_stream(F->stream);
     F->m = make_mat(omega, lambda, mu, rho, o, nullptr, nullptr);
+    if (F->m.kT * F->G.hmax > kKhMax) {   // the quadrature rules hold up to k_T h = kKhMax
+      delete F;
+      return FDS_EGEOM;
+    }
     if (o.rank_mode == FDS_RANK_LEARNED) {
       F->pred = DevBuf<float>(std::vector<float>(o.predictor, o.predictor + kMlpBlob));
       F->opt.predictor = nullptr;   // the caller's array is not kept
@@ -2164,6 +2187,19 @@ int fds_get_skeleton(fds_factor f, int32_t cell, int64_t* rows, int64_t* cols, i
 void fds_release_cache(void) { cache_release(); }
 
 int64_t fds_cached_bytes(void) { return (int64_t)cache_bytes(); }
+
+int fds_set_allocator(fds_alloc_fn alloc, fds_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return FDS_EINVAL;
+  UserAllocator u;
+  u.alloc = alloc;
+  u.free = free_fn;
+  u.ctx = alloc ? ctx : nullptr;
+  if (!set_user_allocator(u)) {
+    g_last_error = "device blocks are still held (destroy every factor first)";
+    return FDS_EINVAL;
+  }
+  return FDS_OK;
+}
 
 void fds_destroy(fds_factor f) {
   if (!f) return;

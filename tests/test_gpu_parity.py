@@ -51,8 +51,10 @@ GEOMS = {
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
-@pytest.mark.parametrize("omega", [1.0, 4.0])
+@pytest.mark.parametrize("omega", [1.0, 4.0, 14.5])
 def test_dense_entries(fdsmod, name, omega):
+    """At omega = 14.5 the 64-gon has k_T h = 1.4: the singular pairs take
+    the longer rules and the regular pairs at least 6 points."""
     curves = GEOMS[name]
     mat = Material(2.0, 1.0, 1.0, omega)
     bnd = galerkin.Boundary(curves)
@@ -60,6 +62,14 @@ def test_dense_entries(fdsmod, name, omega):
     n = A.shape[0]
     G = fdsmod.entries(curves, omega, 2.0, 1.0, 1.0, np.arange(n), np.arange(n)).cpu().numpy()
     assert np.max(np.abs(G - A)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_elements_too_long_for_the_wavenumber(fdsmod):
+    """The quadrature rules hold up to k_T h = 5: a 16-gon at omega = 40
+    (k_T h = 15.6) is refused with FDS_EGEOM."""
+    with pytest.raises(fdsmod.FdsError) as e:
+        fdsmod.Factor([sy.circle(16)], 40.0, 2.0, 1.0, 1.0, 1e-8, leaf=8)
+    assert e.value.code == 2
 
 
 def test_scattered_entries_and_alpha(fdsmod):
