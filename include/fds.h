@@ -100,7 +100,13 @@ typedef struct {
                                the fastest per class of nrhs (1 | 2-8 | 9-32 | 33+); the choice is cached per
                                device and leaf shape for later factorisations in the process; every shape
                                gives bitwise identical results.  0: fixed shapes */
-  int32_t reserved2;
+  int32_t mfma_sweeps;      /* 1 (default): plain FP64 factors run the upward solve sweep on the FP64
+                               matrix cores for 16 or more right-hand sides, one launch per level (LU solve by
+                               16-row blocks with inverted 16 x 16 diagonal blocks, then f~ = (A~_i V_i) g with
+                               A~_i V_i formed once per factor), for levels whose cells have at most 256
+                               unknowns and 192 skeleton unknowns; fewer right-hand sides take the LU-solve
+                               kernel and a GEMM with A~_i V_i; the downward sweep and larger levels use the
+                               LU-solve and GEMM kernels.  0: those kernels for every level */
 } fds_options;
 
 enum { FDS_PREC_FP64 = 0, FDS_PREC_MIXED = 1 };
@@ -199,7 +205,7 @@ typedef struct {
   int64_t n_unknowns;
   int64_t root_size;        /* order of the compressed system at l0 */
   int32_t max_rank;         /* largest per-component skeleton size */
-  int32_t reserved;
+  int32_t max_proxy;        /* largest proxy polygon (vertices) of any compressed cell */
   double factor_seconds;    /* wall time of fds_build */
   double assembly_seconds;  /* GPU time in the entry-assembly kernels during the build */
   double id_seconds;        /* GPU time in the pivoted QR / ID kernels */

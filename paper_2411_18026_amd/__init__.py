@@ -47,12 +47,12 @@ class _Options(ctypes.Structure):
                 ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double),
                 ("rank_mode", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("predictor", ctypes.POINTER(ctypes.c_float)), ("autotune", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("mfma_sweeps", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("root_level", ctypes.c_int32), ("n_unknowns", ctypes.c_int64),
-                ("root_size", ctypes.c_int64), ("max_rank", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("root_size", ctypes.c_int64), ("max_rank", ctypes.c_int32), ("max_proxy", ctypes.c_int32),
                 ("factor_seconds", ctypes.c_double), ("assembly_seconds", ctypes.c_double),
                 ("id_seconds", ctypes.c_double), ("merge_seconds", ctypes.c_double),
                 ("root_seconds", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
@@ -190,7 +190,8 @@ def _geometry(curves):
 
 
 def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False, mixed=False,
-             ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True):
+             ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True,
+             mfma_sweeps=True):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
@@ -212,6 +213,7 @@ def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, sol
     if seed is not None:
         o.seed = int(seed)
     o.autotune = int(bool(autotune))
+    o.mfma_sweeps = int(bool(mfma_sweeps))
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
@@ -258,11 +260,11 @@ class Factor:
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
                  alpha=None, stream=None, solve_graph=False, mixed=False, ir_max_iter=None, ir_rtol=None,
-                 ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True):
+                 ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True, mfma_sweeps=True):
         L = load()
         g, self._keep = _geometry(curves)
         o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph, mixed, ir_max_iter, ir_rtol,
-                     ir_dtol, predictor, oversample, seed, autotune)
+                     ir_dtol, predictor, oversample, seed, autotune, mfma_sweeps)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfds.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["assembly.hip", "assembly_host.hip", "linalg.hip", "learned.hip", "fds.hip", "devmem.hip", "field.hip"]
+SOURCES = ["assembly.hip", "assembly_host.hip", "linalg.hip", "learned.hip", "fds.hip", "devmem.hip", "field.hip",
+           "sweep.hip"]
 ARCH = os.environ.get("FDS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

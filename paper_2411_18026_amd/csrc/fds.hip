@@ -46,6 +46,7 @@
 #include "learned.hpp"
 #include "linalg.hpp"
 #include "parallel.hpp"
+#include "sweep.hpp"
 
 namespace fds {
 
@@ -204,6 +205,9 @@ struct SolveLevel {
   DevBuf<GemmDesc> g_v, g_at, g_dn1, g_dn2;  // V g, A~ (V g), A~ y - f~, g + X f~
   DevBuf<GemmTile> t_v, t_at, t_dn1, t_dn2;
   int n_lu = 0, n_tv = 0, n_tat = 0, n_tdn1 = 0, n_tdn2 = 0, bmax = 0;
+  DevBuf<GemmDesc> g_w;                      // matrix-core levels: f~ = W g (W = A~ V), for few columns
+  DevBuf<GemmTile> t_w;
+  int n_tw = 0;
   DevBuf<int64_t> up_src, up_dst;            // rows of f~ -> rows of the parent's F
   int64_t n_up = 0;
 };
@@ -237,6 +241,14 @@ struct CellLevel {
   // parent position of each skeleton entry (set when the parent is built)
   std::vector<std::vector<int>> ppos;
   SolveLevel plan;
+  // matrix-core sweeps (plain FP64 form, levels whose blocks have a
+  // variant): per-cell descriptors, composed LU permutations, inverted 16 x 16
+  // diagonal blocks; V then holds W = A~ V (the upward sweep's product)
+  bool mfma = false;
+  int nb_class = 0, nr_class = 0;
+  DevBuf<SweepCell> sweep;
+  DevBuf<int> perm;
+  DevBuf<c64> Dinv;
   // compressed-operator product (mixed form): y = B z per cell
   DevBuf<GemmDesc> g_diag;
   DevBuf<GemmTile> t_diag;
@@ -1131,6 +1143,7 @@ static void compress_level(Factor& F, int lev) {
     poff[q + 1] = poff[q] + npx[q];
     lv.max_proxy = std::max(lv.max_proxy, npx[q]);
   }
+  F.st.max_proxy = std::max(F.st.max_proxy, lv.max_proxy);
   const int64_t pbase = F.DG.n_gamma;
   F.DG.reserve(pbase + poff[n], s);
   launch_proxy_elems(ws.upload("crd", crd), ws.upload("poff", poff), n, poff[n], G.n_curves, F.DG.elems.p + pbase,
@@ -1469,6 +1482,96 @@ static void factor_root(Factor& F) {
 
 // Device descriptors of the solve (ncol = number of right-hand sides is
 // supplied at solve time).
+// Matrix-core sweeps of the plain form: for every compressed level whose
+// block orders have a variant, W_i = A~_i V_i (replacing V_i: the upward
+// sweep needs only the product), the LU's composed permutation and the
+// inverted diagonal blocks.
+static void prepare_mfma_sweeps(Factor& F) {
+  hipStream_t s = F.stream;
+  Workspace& ws = F.ws;
+  for (int lev = F.L; lev > F.l0; --lev) {
+    CellLevel& lv = F.levels[lev];
+    int rmax = 0;
+    for (int q = 0; q < lv.n; ++q) rmax = std::max(rmax, lv.r[q]);
+    if (!sweep_supported(lv.bmax, rmax)) continue;
+    std::vector<SweepCell> cells(lv.n);
+    std::vector<int> blk_cell, blk_k;
+    std::vector<GemmDesc> gd;
+    int64_t dtot = 0;
+    for (int q = 0; q < lv.n; ++q) {
+      SweepCell& c = cells[q];
+      const int b = lv.b[q], r = lv.r[q], nb = (b + 15) / 16;
+      c.a_off = lv.a_off[q];
+      c.dinv_off = dtot;
+      dtot += (int64_t)nb * 512;
+      c.v_off = lv.v_off[q];
+      c.at_off = lv.at_off[q];
+      c.x_off = lv.x_off[q];
+      c.f_off = lv.f_off[q];
+      c.t_off = lv.t_off[q];
+      c.perm_off = lv.piv_off[q];
+      c.piv_off = lv.piv_off[q];
+      c.b = b;
+      c.r = r;
+      for (int k = 0; k < nb; ++k) {
+        blk_cell.push_back(q);
+        blk_k.push_back(k);
+      }
+      if (r == 0) continue;
+      GemmDesc g{};   // W = A~ V
+      g.a_off = lv.at_off[q];
+      g.b_off = lv.v_off[q];
+      g.c_off = lv.v_off[q];
+      g.m = r;
+      g.n = b;
+      g.k = r;
+      g.lda = r;
+      g.ldb = r;
+      g.ldc = r;
+      g.alpha_re = 1.0;
+      gd.push_back(g);
+    }
+    lv.sweep = DevBuf<SweepCell>(cells);
+    lv.perm = DevBuf<int>((size_t)std::max<int64_t>(lv.piv_tot, 1));
+    lv.Dinv = DevBuf<c64>((size_t)std::max<int64_t>(dtot, 1));
+    launch_sweep_prepare(lv.sweep.p, lv.n, ws.upload("sw_bc", blk_cell), ws.upload("sw_bk", blk_k),
+                         (int)blk_cell.size(), lv.piv.p, lv.A.p, lv.perm.p, lv.Dinv.p, s);
+    if (!gd.empty()) {
+      DevBuf<c64> W((size_t)lv.V.n);
+      auto gt = gemm_tiles(gd);
+      int nmax = 0;
+      for (auto& g : gd) nmax = std::max(nmax, g.n);
+      launch_gemm(ws.upload("w_desc", gd), ws.upload("w_tiles", gt), (int)gt.size(), nmax, 0, lv.At.p, lv.V.p, W.p,
+                  0, s);
+      FDS_HIP(hipStreamSynchronize(s));   // the old V goes back to the cache now
+      lv.V = std::move(W);
+    }
+    // fewer columns than a slab: the LU-solve kernel, then f~ = W g by GEMM
+    std::vector<GemmDesc> gw;
+    for (int q = 0; q < lv.n; ++q) {
+      if (lv.r[q] == 0) continue;
+      GemmDesc g{};
+      g.a_off = lv.v_off[q];
+      g.b_off = lv.f_off[q];
+      g.c_off = lv.t_off[q];
+      g.m = lv.r[q];
+      g.k = lv.b[q];
+      g.lda = lv.r[q];
+      g.ldb = (int)lv.B;
+      g.ldc = (int)lv.R;
+      g.alpha_re = 1.0;
+      gw.push_back(g);
+    }
+    auto tw = gemm_tiles(gw);
+    lv.plan.g_w = DevBuf<GemmDesc>(gw);
+    lv.plan.t_w = DevBuf<GemmTile>(tw);
+    lv.plan.n_tw = (int)tw.size();
+    lv.mfma = true;
+    lv.nb_class = sweep_tile_class(lv.bmax);
+    lv.nr_class = sweep_tile_class(std::max(rmax, 1));
+  }
+}
+
 static void build_solve_plan(Factor& F) {
   HostTimer ht(6);
   const int L = F.L, l0 = F.l0;
@@ -1545,6 +1648,7 @@ static void build_solve_plan(Factor& F) {
     P.up_dst = DevBuf<int64_t>(di);
     P.n_up = (int64_t)si.size();
   }
+  if (F.opt.precision == FDS_PREC_FP64 && F.opt.mfma_sweeps) prepare_mfma_sweeps(F);
   if (F.opt.precision == FDS_PREC_MIXED) {
     // products with the FP64 diagonal blocks (without the children's A~) of
     // every compressed level: y_i = B_i z_i on the level vectors
@@ -1712,11 +1816,48 @@ static void run_sweeps(Factor& F, int nrhs, const SweepBufs& b, hipStream_t s) {
   const int L = F.L, l0 = F.l0;
   auto& levels = F.levels;
   const int ck = F.tune_chunk[nrhs_class(nrhs)], bn = F.tune_bn[nrhs_class(nrhs)];
+  auto sweep_launch = [&](int lev) {
+    CellLevel& lv = levels[lev];
+    SweepLaunch SL;
+    SL.cells = lv.sweep.p;
+    SL.n_cells = lv.n;
+    SL.n_slab = (nrhs + 15) / 16;
+    SL.ncol = nrhs;
+    SL.nb_class = lv.nb_class;
+    SL.nr_class = lv.nr_class;
+    SL.A = lv.A.p;
+    SL.Dinv = lv.Dinv.p;
+    SL.perm = lv.perm.p;
+    SL.W = lv.V.p;
+    SL.At = lv.At.p;
+    SL.X = lv.X.p;
+    SL.up_dst = lv.plan.up_dst.p;
+    SL.F = b.F[lev];
+    SL.ldF = lv.B;
+    SL.T = b.T[lev];
+    SL.ldT = lv.R;
+    SL.Fp = b.F[lev - 1];
+    SL.ldFp = levels[lev - 1].B;
+    return SL;
+  };
   // upward: g = A^{-1} f (in F), f~ = A~ (V g) (V g in Y, f~ in T)
   for (int lev = L; lev > l0; --lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
+    if (lv.mfma && nrhs >= kSweepMinCols) {   // one launch: g, f~ and the parent's rows
+      launch_sweep_up(sweep_launch(lev), s);
+      continue;
+    }
+    if (lv.mfma && nrhs <= kSweepFewCols) {
+      launch_sweep_few(sweep_launch(lev), true, s);
+      continue;
+    }
     launch_lu_solve(P.lu.p, P.n_lu, P.bmax, nrhs, nrhs, lv.A.p, lv.piv.p, b.F[lev], s, ck);
+    if (lv.mfma) {   // V holds W = A~ V
+      launch_gemm(P.g_w.p, P.t_w.p, P.n_tw, nrhs, nrhs, lv.V.p, b.F[lev], b.T[lev], 0, s, bn);
+      launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
+      continue;
+    }
     launch_gemm(P.g_v.p, P.t_v.p, P.n_tv, nrhs, nrhs, lv.V.p, b.F[lev], b.Y[lev], 0, s, bn);
     launch_gemm(P.g_at.p, P.t_at.p, P.n_tat, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s, bn);
     launch_copy_rows(P.n_up, P.up_src.p, P.up_dst.p, nrhs, b.T[lev], lv.R, b.F[lev - 1], levels[lev - 1].B, s);
@@ -1726,6 +1867,10 @@ static void run_sweeps(Factor& F, int nrhs, const SweepBufs& b, hipStream_t s) {
   for (int lev = l0 + 1; lev <= L; ++lev) {
     CellLevel& lv = levels[lev];
     SolveLevel& P = lv.plan;
+    if (lv.mfma && nrhs <= kSweepFewCols) {
+      launch_sweep_few(sweep_launch(lev), false, s);
+      continue;
+    }
     launch_copy_rows(P.n_up, P.up_dst.p, P.up_src.p, nrhs, b.F[lev - 1], levels[lev - 1].B, b.Y[lev], lv.R, s);
     launch_gemm(P.g_dn1.p, P.t_dn1.p, P.n_tdn1, nrhs, nrhs, lv.At.p, b.Y[lev], b.T[lev], 0, s, bn);
     launch_gemm(P.g_dn2.p, P.t_dn2.p, P.n_tdn2, nrhs, nrhs, lv.X.p, b.T[lev], b.F[lev], 0, s, bn);
@@ -1950,6 +2095,7 @@ int fds_options_default(fds_options* o) {
   o->seed = 0x5EED;
   o->predictor = nullptr;
   o->autotune = 1;
+  o->mfma_sweeps = 1;
   return FDS_OK;
 }
 
@@ -2035,9 +2181,9 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->st.root_size = F->root.n;
     int64_t bytes = 0;
     for (auto& lv : F->levels)
-      bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n) * sizeof(c64) +
+      bytes += (int64_t)(lv.A.n + lv.X.n + lv.At.n + lv.V.n + lv.Dinv.n) * sizeof(c64) +
                (int64_t)(lv.A32.n + lv.X32.n + lv.At32.n + lv.V32.n) * sizeof(c32) +
-               (lv.piv.n + lv.s_piv.n) * sizeof(int);
+               (lv.piv.n + lv.s_piv.n + lv.perm.n) * sizeof(int) + lv.sweep.n * sizeof(SweepCell);
     bytes += (int64_t)(F->root.A.n + F->root.B.n) * sizeof(c64);
     F->st.precision = o.precision;
     F->st.factor_bytes = bytes;

@@ -14,9 +14,21 @@ which calls only ``oracle/``):
 * eight cavities at k_T = 8 (proxy polygons of a few hundred vertices at the
   top levels).
 
-Tolerance: the two sides take the same decisions (pivots, ranks) from
-independently computed entries that agree to rounding; the solutions then
-differ by rounding amplified by the small dense blocks' conditioning.
+Decisions: every cell's four ranks and both skeletons (DOFs and their
+order) are identical.  The cases avoid exact ties of the pivoted QR: late in
+an ID the remaining column norms carry relative rounding errors far above
+any tie window, so two columns that tie in exact arithmetic (the centrally
+symmetric DOFs of an evenly sampled ellipse alone in its cell) may be taken
+in either order, or either one, by two implementations - several correct
+results; the multi-cavity case therefore uses odd node counts.
+
+Tolerance: the entries agree to about 1e-13 of each block's largest one;
+the multi-level elimination and the root LU amplify that by the conditioning
+of the compressed system (about 3e4 for the 16384-node ellipse, whose
+elements are 2e-4 long), so solutions are required to agree element-wise
+within 1e-9 of the largest oracle value (measured: 1.4e-10 on the ellipse),
+below the 1e-8 stated for the FP64 form.  Both solve paths (the matrix-core
+sweeps and the LU-solve/GEMM kernels) are checked.
 """
 import os
 import sys
@@ -60,7 +72,13 @@ def test_factor_and_solutions_match_oracle(fdsmod, name):
         r, cc = F.skeleton(int(cell))
         assert np.array_equal(r, g["rskel"][off[i]:off[i + 1]]), (name, int(cell))
         assert np.array_equal(cc, g["cskel"][off[i]:off[i + 1]]), (name, int(cell))
-    x = F.solve(F.rhs_plane(list(g["kinds"]), list(g["angles"]))).cpu().numpy().reshape(len(g["kinds"]), -1)
+    rhs = F.rhs_plane(list(g["kinds"]), list(g["angles"]))
     xo = g["x"]
-    for j in range(len(xo)):
-        assert np.max(np.abs(x[j] - xo[j])) <= 1e-10 * np.max(np.abs(xo[j])), (name, j)
+    Fg = fdsmod.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"],
+                       n_proxy=c["n_proxy"], root_level=int(g["root_level"]), alpha=c["alpha"], mfma_sweeps=False)
+    for Fx in (F, Fg):
+        x = Fx.solve(rhs).cpu().numpy().reshape(len(g["kinds"]), -1)
+        for j in range(len(xo)):
+            e = np.max(np.abs(x[j] - xo[j])) / np.max(np.abs(xo[j]))
+            print(f"{name} rhs {j}: max |x - x_oracle| / max |x_oracle| = {e:.2e}", flush=True)
+            assert e <= 1e-9, (name, j, e)
