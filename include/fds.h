@@ -158,6 +158,26 @@ int fds_rhs_plane(fds_factor f, int32_t nrhs, const int32_t* kind, const double*
 int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs,
               fds_c64* x, int64_t ld_x, void* stream);
 
+/* fds_solve without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same sweeps and kernels as fds_solve, and
+ * bitwise the same x, with the level vectors of the sweeps in a
+ * file-scope device array of 128 MiB (one per device, held until the
+ * process ends) instead of the factor's workspace.  Plain FP64 factors
+ * only (the mixed form needs refinement buffers: FDS_EINVAL).  The scratch
+ * needed is sum over the compressed levels of (B_l + 2 R_l) * nrhs * 16
+ * bytes (B_l the level's active unknowns, R_l its skeleton unknowns; about
+ * 19 MiB per right-hand side for the 131072-node ellipse at tol 1e-8);
+ * more than 128 MiB is refused with FDS_EINVAL (solve fewer right-hand
+ * sides per call).  Asynchronous: returns once the work is queued on
+ * ``stream`` (no host synchronisation, no allocation, no memset).  Every
+ * call on a device shares that device's scratch and leaves its contents
+ * behind: calls that overlap on one device (different streams, or other
+ * host threads) race, so the caller orders them.  Arguments and errors
+ * otherwise as fds_solve. */
+int fds_solve_noalloc(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fds_c64* x, int64_t ld_x,
+                      void* stream);
+
 /* y = A_c x with the FP64 compressed operator (Section 6.1: block-diagonal
  * part plus U (skeleton interactions) V, nested over the levels; Section
  * 6.2 for the parents' blocks), for a factor built with FDS_PREC_MIXED (the

@@ -81,7 +81,7 @@ EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
            "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
            "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes",
-           "fds_field", "fds_set_allocator"]
+           "fds_field", "fds_set_allocator", "fds_solve_noalloc"]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p)
@@ -139,6 +139,7 @@ def load():
     L.fds_size.argtypes = [vp, ctypes.POINTER(i64)]
     L.fds_rhs_plane.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, i64, vp]
     L.fds_solve.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.fds_solve_noalloc.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.fds_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
     L.fds_get_ranks.argtypes = [vp, ctypes.POINTER(i32), i64]
     L.fds_get_skeleton.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
@@ -310,6 +311,21 @@ class Factor:
             raise NotConverged(load().fds_last_error().decode(), out[0] if one else out)
         _check(code)
         return out[0] if one else out
+
+    def solve_noalloc(self, rhs, out, stream=None):
+        """fds_solve_noalloc: as ``solve`` for a plain FP64 factor, with the
+        sweeps' level vectors in the library's fixed device scratch; ``out``
+        (the shape of ``rhs``) is required.  Asynchronous on ``stream``."""
+        one = rhs.dim() == 1
+        r = rhs.reshape(1, -1) if one else rhs
+        o = out.reshape(1, -1) if one else out
+        _cuda_c128(r)
+        _cuda_c128(o)
+        if o.shape != r.shape:
+            raise FdsError("out must have the shape of rhs")
+        _check(load().fds_solve_noalloc(self._h, r.shape[0], ctypes.c_void_p(r.data_ptr()), self.n_unknowns,
+                                        ctypes.c_void_p(o.data_ptr()), self.n_unknowns, _stream(stream)))
+        return out
 
     def apply(self, x, out=None, stream=None):
         """y = A_c x with the FP64 compressed operator (mixed-form factors)."""

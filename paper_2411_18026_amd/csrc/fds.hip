@@ -1915,6 +1915,60 @@ static void run_solve(Factor& F, int nrhs, const c64* rhs, int64_t ld_rhs, c64* 
   launch_copy_rows(lf.B, F.leaf_iota.p, F.leaf_dofs_cols.p, nrhs, b.F[F.L], lf.B, x, ld_x, s);
 }
 
+// ------------------------------------------------------------------ solve without allocation
+// Device scratch of fds_solve_noalloc: the sweep level vectors of one call,
+// carved from one file-scope array.  Each device holds its own copy at its
+// own address; host code uses only the addresses returned by
+// hipGetSymbolAddress (the array's name in host code is not a device address).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_addr;   // device -> address of ``scratch`` there
+
+static unsigned char* scratch_address() {
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  FDS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(FDS_EHIP, "no device address for the solve scratch");
+  g_scratch_addr[dev] = static_cast<unsigned char*>(p);
+  return static_cast<unsigned char*>(p);
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// bytes of the level vectors of a solve with nrhs columns (as sweep_buffers)
+static size_t sweep_scratch_bytes(const Factor& F, int nrhs) {
+  size_t tot = 0;
+  for (int lev = F.l0; lev <= F.L; ++lev) {
+    tot += align256((size_t)F.levels[lev].B * nrhs * sizeof(c64));
+    if (lev > F.l0) tot += 2 * align256((size_t)F.levels[lev].R * nrhs * sizeof(c64));
+  }
+  return tot;
+}
+
+static SweepBufs sweep_buffers_at(const Factor& F, int nrhs, unsigned char* base) {
+  SweepBufs b;
+  b.F.assign(F.L + 1, nullptr);
+  b.T.assign(F.L + 1, nullptr);
+  b.Y.assign(F.L + 1, nullptr);
+  size_t off = 0;
+  for (int lev = F.l0; lev <= F.L; ++lev) {
+    b.F[lev] = reinterpret_cast<c64*>(base + off);
+    off += align256((size_t)F.levels[lev].B * nrhs * sizeof(c64));
+    if (lev > F.l0) {
+      b.T[lev] = reinterpret_cast<c64*>(base + off);
+      off += align256((size_t)F.levels[lev].R * nrhs * sizeof(c64));
+      b.Y[lev] = reinterpret_cast<c64*>(base + off);
+      off += align256((size_t)F.levels[lev].R * nrhs * sizeof(c64));
+    }
+  }
+  return b;
+}
+
 // ------------------------------------------------------------------ mixed form
 struct MixedBufs {
   std::vector<c32*> F, T, Y;   // FP32 sweep level vectors
@@ -2257,6 +2311,37 @@ int fds_solve(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fd
     FDS_HIP(hipStreamSynchronize(s));
     if (status == FDS_ENOCONV) g_last_error = "iterative refinement did not reach its tolerance";
     return status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_solve_noalloc(fds_factor f, int32_t nrhs, const fds_c64* rhs, int64_t ld_rhs, fds_c64* x, int64_t ld_x,
+                      void* stream) {
+  const int64_t N = f ? 2 * (int64_t)f->G.n_nodes : 0;
+  if (!f || nrhs < 1 || nrhs > 65535 || !rhs || !x || ld_rhs < N || ld_x < N) return FDS_EINVAL;
+  if (f->opt.precision != FDS_PREC_FP64) {
+    g_last_error = "fds_solve_noalloc: the mixed-precision form needs refinement buffers; use fds_solve";
+    return FDS_EINVAL;
+  }
+  const size_t need = sweep_scratch_bytes(*f, nrhs);
+  if (need > kNoAllocScratchBytes) {
+    g_last_error = "fds_solve_noalloc: " + std::to_string(nrhs) + " right-hand sides need " +
+                   std::to_string(need >> 20) + " MiB of scratch, more than its " +
+                   std::to_string(kNoAllocScratchBytes >> 20) + " MiB: solve fewer at a time";
+    return FDS_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* base = scratch_address();
+    const SweepBufs b = sweep_buffers_at(*f, nrhs, base);
+    CellLevel& lf = f->levels[f->L];
+    // every level vector is written before it is read: nothing to clear
+    launch_copy_rows(lf.B, f->leaf_dofs_rows.p, f->leaf_iota.p, nrhs, (const c64*)rhs, ld_rhs, b.F[f->L], lf.B, s);
+    run_sweeps(*f, nrhs, b, s);
+    launch_copy_rows(lf.B, f->leaf_iota.p, f->leaf_dofs_cols.p, nrhs, b.F[f->L], lf.B, (c64*)x, ld_x, s);
+    return FDS_OK;
   } catch (const std::exception& e) {
     g_last_error = e.what();
     return translate(e);
