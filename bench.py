@@ -2,8 +2,12 @@
 
 Workload (full size): ellipse with semi-axes 1 and 0.5, 131072 nodes
 (262144 complex unknowns), lambda=2, mu=1, rho=1, omega=4 (k_T a = 4), leaf
-64 nodes (L = 11), root level 1, ID tolerance 1e-8, 180 plane P-waves at
-0, 2, ..., 358 degrees; synthetic geometry, FP64 throughout.
+64 nodes (L = 11), root level 1, 180 plane P-waves at 0, 2, ..., 358
+degrees; synthetic geometry, FP64 throughout.  The headline is timed at the
+ID tolerance 1e-11, the loosest of 1e-8 ... 1e-11 at which every solution
+is within 1e-6 (relative 2-norm) of the solution of a tolerance-1e-12
+factor; the listed tolerance 1e-8 (3.7e-4 from that reference at this N) is
+reported beside it.
 
 One step = the whole hot path on that input: factorisation (assembly,
 IDs, inverse-free elimination, root LU), the 180 load vectors, the first
@@ -12,14 +16,17 @@ right-hand side solved alone, then the other 179 in one batched solve
 
 Prints one JSON line.  ``value`` is the factorisation time in seconds
 (lower is better); ``per_rhs_us`` the batched per-RHS solve time;
-``roofline`` the far-pair integrator against the FP64 peak; ``cpu_baseline``
-the CPU oracle on a bounded sample.  Sections beside the headline (each
-with a --no-... switch): the mixed-precision and learned forms, the
-multi-cavity cases, accuracy against the oracle, the tripod accuracy ladder
-(Section 8.1), the fictitious-frequency and angular-frequency sweeps
-(Section 8.4), the field off the boundary (Section 3), the factor-time
-ladder over N (Section 8.2) and the multiple-right-hand-side experiment
-(Section 8.3).
+``accuracy`` the largest error over the 180 solutions against the
+tolerance-1e-12 factor and a sampled residual of the exact Galerkin
+system; ``roofline`` the far-pair integrator against the FP64 peak and
+``roofline_solve`` the batched solve against the FP64 matrix peak;
+``cpu_baseline`` the CPU oracle on a bounded sample.  Sections beside the
+headline (each with a --no-... switch): the listed tolerance 1e-8, the
+mixed-precision and learned forms, the multi-cavity cases (with their
+accuracy), the tripod accuracy ladder (Section 8.1), the fictitious-
+frequency and angular-frequency sweeps (Section 8.4), the field off the
+boundary (Section 3), the factor-time ladder over N (Section 8.2) and the
+multiple-right-hand-side experiment (Section 8.3).
 """
 from __future__ import annotations
 
@@ -48,6 +55,8 @@ def _args():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--nodes", type=int, default=131072)
     p.add_argument("--nrhs", type=int, default=180)
+    p.add_argument("--tol", type=float, default=1e-11, help="ID tolerance of the headline factor")
+    p.add_argument("--no-tol8", action="store_true", help="skip the section at the listed tolerance 1e-8")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-accuracy", action="store_true",
                    help="skip the accuracy checks (second factorisation, sampled rows) after the timed steps")
@@ -78,7 +87,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     nodes = sy.ellipse(a.nodes, 1.0, 0.5)
-    lam, mu, rho, omega, tol, leaf = 2.0, 1.0, 1.0, 4.0, 1e-8, 64
+    lam, mu, rho, omega, tol, leaf = 2.0, 1.0, 1.0, 4.0, a.tol, 64
     kinds = np.zeros(a.nrhs, dtype=np.int32)
     angles = sy.plane_wave_angles(a.nrhs)
     stream = torch.cuda.current_stream()
@@ -118,22 +127,19 @@ def main():
     ranks = F.ranks()
     mean = {k: float(np.mean([t[k] for t in times])) for k in times[0]}
 
-    rel_res = comp_err = None
+    acc = Xref = Arows = rows = None
     if not a.no_accuracy:
         log("accuracy checks")
-        # relative residual on sampled rows of the exact Galerkin matrix
+        # sampled rows of the exact Galerkin matrix, and the solutions of a
+        # tolerance-1e-12 factor (the reference of the compression error)
         rng = np.random.default_rng(11)
         n_unk = F.n_unknowns
         rows = np.sort(rng.choice(n_unk, a.residual_rows, replace=False))
         Arows = fds.entries([nodes], omega, lam, mu, rho, rows, np.arange(n_unk))
-        X = torch.cat([x1.reshape(1, -1), xr], 0)           # (nrhs, N)
-        res = Arows @ X.T - rhs[:, rows].T                   # (rows, nrhs)
-        rel_res = (torch.linalg.norm(res, dim=0) / torch.linalg.norm(rhs[:, rows].T, dim=0)).max().item()
-        # compression error estimate: first RHS against a tol=1e-12 factorisation
         Fref = fds.Factor([nodes], omega, lam, mu, rho, 1e-12, leaf=leaf)
-        xref = Fref.solve(rhs[0])
-        comp_err = (torch.linalg.norm(x1 - xref) / torch.linalg.norm(xref)).item()
+        Xref = Fref.solve(rhs)
         del Fref
+        acc = accuracy(torch.cat([x1.reshape(1, -1), xr], 0), Xref, Arows, rows, rhs)
 
     # roofline of the dominant kernel: the far-pair integrator (tensor Gauss,
     # 4 points per element).  Algorithmic work: FLOP_PER_EVAL per quadrature
@@ -178,17 +184,40 @@ def main():
                "per_rhs_us": round(1e6 * (tg2 - tg1) / max(1, a.nrhs - 1), 2), "identical_to_plain": same}
     del Fg
 
+    # The other forms.  The mixed-precision form refines an FP32 elimination
+    # against the FP64 compressed operator: it converges where the FP32
+    # factor's error is below one (tol 1e-8 here), and is measured there,
+    # against the plain FP64 solutions of the same tolerance.  The learned
+    # form is measured at both tolerances (its predictor was trained at
+    # tol 1e-6 ... 1e-10 and abstains beyond that range).
+    tol8 = X8 = x18 = xr8 = None
+    if not (a.no_tol8 and a.no_mixed and a.no_learned):
+        log("plain FP64 form at the listed tolerance 1e-8")
+        tol8, X8 = tolerance_section(fds, nodes, omega, lam, mu, rho, 1e-8, leaf, rhs, Xref, Arows, rows)
+        x18, xr8 = X8[0], X8[1:]
     mixed = None
     if not a.no_mixed:
-        log("mixed-precision form")
-        mixed = mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr)
+        log("mixed-precision form (tol 1e-8)")
+        mixed = mixed_form(fds, nodes, omega, lam, mu, rho, 1e-8, leaf, rhs, x18, xr8, Xref)
+        log("mixed-precision form at the headline tolerance")
+        try:
+            mixed_hl = mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, Xref, reps=1)
+        except fds.NotConverged as e:
+            mixed_hl = {"tol": tol, "converged": False, "note": str(e)}
+        mixed = {"tol_1e-8": mixed, "headline_tol": mixed_hl}
     learned = learned_mixed = None
     blob = np.load(PREDICTOR) if not a.no_learned else None
     if blob is not None:
         log("learned forms")
-        learned = other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, predictor=blob)
-        learned_mixed = other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, predictor=blob,
-                                   mixed=True, solve_graph=True)
+        learned = {"tol_1e-8": other_form(fds, nodes, omega, lam, mu, rho, 1e-8, leaf, rhs, x18, xr8, Xref,
+                                          predictor=blob),
+                   "headline_tol": other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, Xref,
+                                              predictor=blob)}
+        try:
+            learned_mixed = other_form(fds, nodes, omega, lam, mu, rho, 1e-8, leaf, rhs, x18, xr8, Xref,
+                                       predictor=blob, mixed=True, solve_graph=True, ir_max_iter=IR_MAX_ITER)
+        except fds.NotConverged as e:
+            learned_mixed = {"tol": 1e-8, "converged": False, "note": str(e)}
     multi = None
     if not a.no_multi:
         log("multi-cavity configurations")
@@ -239,8 +268,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"ellipse 1x0.5, {a.nodes} nodes ({2 * a.nodes} complex unknowns), "
-                               f"kT=4, leaf 64, tol 1e-8, {a.nrhs} plane P-waves, plain FP64 form",
-                   "form": "plain-fp64"},
+                               f"kT=4, leaf 64, ID tol {a.tol:g} (the loosest with every solution within 1e-6 of a "
+                               f"tol-1e-12 factor), {a.nrhs} plane P-waves, plain FP64 form",
+                   "form": "plain-fp64", "tol": a.tol},
         "factor_s": round(mean["factor"], 4),
         "first_rhs_ms": round(1e3 * mean["first"], 3),
         "first_vector_s": round(mean["factor"] + mean["first"], 4),   # factor + first RHS (Section 8.3)
@@ -254,11 +284,11 @@ def main():
         "root_size": int(st["root_size"]),
         "max_rank": int(st["max_rank"]),
         "factor_gb": round(st["factor_bytes"] / 1e9, 3),
-        "sampled_rel_residual": rel_res,
-        "compression_err_vs_tol1e-12": comp_err,
+        "accuracy": acc,
         "class_seconds": [round(x, 5) for x in cls_s],
         "class_evals": [int(x) for x in cls_e],
         "batched_graph_form": batched,
+        "listed_tol_1e-8": tol8,
         "mixed_form": mixed,
         "learned_form": learned,
         "learned_graph_mixed_form": learned_mixed,
@@ -283,8 +313,60 @@ FLOP_PER_EVAL = 500
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")
 
+# refinement steps allowed to the mixed-precision forms here: the FP32
+# elimination contracts the error by 0.1 - 0.3 per step on this problem, and
+# 11 - 12 steps are needed at tol 1e-11 and with the learned skeletons (the
+# library's default is 10)
+IR_MAX_ITER = 20
 
-def other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2, **kw):
+
+def accuracy(X, Xref, Arows, rows, rhs):
+    """Relative 2-norm error of every solution (rows of X) against the
+    reference solutions Xref (largest and median over the right-hand
+    sides), whether all are within 1e-6, and the largest relative residual
+    ||A[rows] x - f[rows]|| / ||f[rows]|| on the sampled rows of the exact
+    Galerkin matrix."""
+    import torch
+    err = (torch.linalg.norm(X - Xref, dim=1) / torch.linalg.norm(Xref, dim=1)).cpu().numpy()
+    res = Arows @ X.T - rhs[:, rows].T
+    rel_res = (torch.linalg.norm(res, dim=0) / torch.linalg.norm(rhs[:, rows].T, dim=0)).max().item()
+    return {"err_vs_tol1e-12_max": float(err.max()), "err_vs_tol1e-12_median": float(np.median(err)),
+            "within_1e-6": bool(err.max() <= 1e-6), "sampled_rel_residual": rel_res}
+
+
+def tolerance_section(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, Xref, Arows, rows, reps=2):
+    """The plain FP64 form at another ID tolerance on the same input: factor,
+    first-RHS and per-RHS times (best of ``reps``), ranks, root size, factor
+    bytes and the accuracy against the tolerance-1e-12 reference; returns
+    the summary and the solutions."""
+    import torch
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = fds.Factor([nodes], omega, lam, mu, rho, tol, leaf=leaf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        y1 = F.solve(rhs[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        yr = F.solve(rhs[1:])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        st = F.stats()
+        cur = (t1 - t0, t2 - t1, t3 - t2)
+        best = cur if best is None else tuple(min(u, v) for u, v in zip(best, cur))
+        del F
+    out = {"tol": tol, "factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
+           "per_rhs_us": round(1e6 * best[2] / max(1, len(rhs) - 1), 2), "max_rank": int(st["max_rank"]),
+           "root_size": int(st["root_size"]), "factor_gb": round(st["factor_bytes"] / 1e9, 3)}
+    Y = torch.cat([y1.reshape(1, -1), yr], 0)
+    if Xref is not None:
+        out.update(accuracy(Y, Xref, Arows, rows, rhs))
+    return out, Y
+
+
+def other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, Xref=None, reps=2, **kw):
     """Another form of the factorisation on the same input (best of ``reps``):
     factor and solve times, the learned form's sketch / fallback counts, and
     the per-RHS relative difference from the plain FP64 solutions."""
@@ -309,24 +391,32 @@ def other_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2, 
     X = torch.cat([x1.reshape(1, -1), xr], 0)
     Y = torch.cat([y1.reshape(1, -1), yr], 0)
     err = (torch.linalg.norm(Y - X, dim=1) / torch.linalg.norm(X, dim=1)).cpu().numpy()
-    out = {"options": {k: (v if not isinstance(v, np.ndarray) else "rank_mlp_multicavity16k") for k, v in kw.items()},
+    out = {"tol": tol,
+           "options": {k: (v if not isinstance(v, np.ndarray) else "rank_mlp_multicavity16k") for k, v in kw.items()},
            "factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
            "per_rhs_us": round(1e6 * best[2] / max(1, len(rhs) - 1), 2), "id_s": round(st["id_seconds"], 4),
            "cells": int(st["cells_compressed"]), "cells_sketched": int(st["cells_sketched"]),
            "fallback_rank": int(st["cells_fallback_rank"]), "fallback_judge": int(st["cells_fallback_judge"]),
            "err_vs_plain_fp64_max": float(err.max())}
+    if Xref is not None:
+        e2 = (torch.linalg.norm(Y - Xref, dim=1) / torch.linalg.norm(Xref, dim=1)).cpu().numpy()
+        out["err_vs_tol1e-12_max"] = float(e2.max())
+        out["within_1e-6"] = bool(e2.max() <= 1e-6)
     if kw.get("mixed"):
         out["ir_iterations_batch"] = int(st["ir_iterations"])
     return out
 
 
-def tripod_ladder(fds, sizes=(400, 800, 1600, 3200)):
+def tripod_ladder(fds, sizes=(400, 800, 1600, 3200, 6400), single_sizes=(800, 1600, 3200, 6400, 12800, 25600)):
     """Accuracy experiment of Section 8.1 (Tables 1 and 2) on the tripod:
     relative 2-norm error of the factor's solution against a dense solve of
-    the same Galerkin system (entries from the assembly kernels, solved by
-    LAPACK on the host), one plane P-wave at angle 0; multi-level (root at
-    level 1) at three ID tolerances and single-level (root at level L - 1)
-    at 1e-8.  The paper's printed values are listed beside ours."""
+    the same Galerkin system (entries from the assembly kernels, LU on the
+    GPU: 51200 unknowns at the largest size), one plane P-wave at angle 0;
+    multi-level (root at level 1) at three ID tolerances for every size of
+    Table 1, and single-level (root at level L - 1) at 1e-8 for the sizes of
+    Table 2 up to 25600 nodes.  The paper's printed values are listed beside
+    ours."""
+    import torch
     import synthetic as sy
     paper = {}
     with open(os.path.join(ROOT, "tests", "golden", "tripod_error_tables.txt")) as fh:
@@ -335,28 +425,34 @@ def tripod_ladder(fds, sizes=(400, 800, 1600, 3200)):
                 t, n, L, l0, eps, err = line.split()
                 paper[(int(t), int(n), float(eps))] = float(err)
     rows = []
-    for n in sizes:
+    for n in sorted(set(sizes) | set(single_sizes)):
+        log(f"  tripod {n} nodes")
         base = sy.config_tripod(n, 1e-8)
         curves = base["curves"]
-        dofs = np.arange(2 * n)
-        A = fds.entries(curves, base["omega"], base["lam"], base["mu"], base["rho"], dofs, dofs).cpu().numpy()
+        runs = []
+        if n in sizes:
+            runs += [(False, t) for t in (1e-8, 1e-9, 1e-10)]
+        if n in single_sizes and base["L"] - 1 > 1:   # else the single-level variant is the multi-level one
+            runs.append((True, 1e-8))
         ref = None
-        for single, tols in ((False, (1e-8, 1e-9, 1e-10)), (True, (1e-8,))):
-            if single and base["L"] - 1 == 1:
-                continue   # the single-level variant is the multi-level one here
-            for tol in tols:
-                c = sy.config_tripod(n, tol, single)
-                F = fds.Factor(curves, c["omega"], c["lam"], c["mu"], c["rho"], tol, leaf=c["leaf"],
-                               root_level=c["root_level"], autotune=False)
-                b = F.rhs_plane([0], [0.0])
-                x = F.solve(b).cpu().numpy()[0]
-                if ref is None:
-                    ref = np.linalg.solve(A, b.cpu().numpy()[0])
-                err = float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
-                tab = 2 if single else 1
-                rows.append({"table": tab, "N": n, "L": c["L"], "l0": c["root_level"], "eps": tol,
-                             "rel_err": err, "paper_rel_err": paper.get((tab, n, tol))})
-                del F
+        for single, tol in runs:
+            c = sy.config_tripod(n, tol, single)
+            F = fds.Factor(curves, c["omega"], c["lam"], c["mu"], c["rho"], tol, leaf=c["leaf"],
+                           root_level=c["root_level"], autotune=False)
+            b = F.rhs_plane([0], [0.0])
+            x = F.solve(b)[0]
+            del F
+            if ref is None:
+                dofs = np.arange(2 * n)
+                A = fds.entries(curves, base["omega"], base["lam"], base["mu"], base["rho"], dofs, dofs)
+                ref = torch.linalg.solve(A, b[0])
+                del A
+                torch.cuda.empty_cache()
+            err = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+            tab = 2 if single else 1
+            rows.append({"table": tab, "N": n, "L": c["L"], "l0": c["root_level"], "eps": tol,
+                         "rel_err": err, "paper_rel_err": paper.get((tab, n, tol))})
+        del ref
     return {"workload": "tripod r=1 a=0.3 b=3, c_L=sqrt(3), c_T=1, rho=1, omega=2, cells of 100 nodes, "
                         "1 plane P-wave; error vs dense solve of the same system", "rows": rows}
 
@@ -483,9 +579,9 @@ def omega_sweep(fds, n=6400, omegas=None, proxies=(64, 128)):
     every omega and proxy polygon size: factor seconds (best of two), first
     solve milliseconds, largest rank, root size, and the relative error of
     the factor's solution against a dense solve of the same assembled
-    system (LU on the GPU; dense_s is that solve's assembly plus LU time,
-    the conventional BEM on this GPU).  Context: the paper's error at
-    omega = 2 for this size and tolerance is 8.4e-7 (Table 1)."""
+    system (LU on the GPU, used as the accuracy reference only).  Context:
+    the paper's error at omega = 2 for this size and tolerance is 8.4e-7
+    (Table 1)."""
     import torch
     import synthetic as sy
     if omegas is None:
@@ -516,19 +612,15 @@ def omega_sweep(fds, n=6400, omegas=None, proxies=(64, 128)):
             torch.cuda.synchronize()
             tsol = time.perf_counter() - t1
             if ref is None:
-                torch.cuda.synchronize()
-                td = time.perf_counter()
                 A = fds.entries(curves, w, c["lam"], c["mu"], c["rho"], dofs, dofs)
                 ref = torch.linalg.solve(A, b[0])
-                torch.cuda.synchronize()
-                dense_s = time.perf_counter() - td
                 del A
             err = float(torch.linalg.norm(x[0] - ref) / torch.linalg.norm(ref))
             st = F.stats()
             del F
             rows.append({"omega": w, "n_proxy": npx, "factor_s": round(min(ts), 4),
                          "first_solve_ms": round(1e3 * tsol, 3), "max_rank": int(st["max_rank"]),
-                         "root_size": int(st["root_size"]), "rel_err": err, "dense_s": round(dense_s, 3)})
+                         "root_size": int(st["root_size"]), "max_proxy": int(st["max_proxy"]), "rel_err": err})
         del ref
     return {"workload": f"tripod, {n} nodes, omega {omegas[0]}..{omegas[-1]} step 0.5, tol 1e-8, cells of 100 "
                         "nodes, 1 plane P-wave; error vs dense LU of the same system", "rows": rows}
@@ -580,13 +672,13 @@ def complexity_ladder(fds, exps=(12, 13, 14, 15, 16, 17), dense_max_exp=14, nrhs
     as there, leaf 64, root at level 1) with 2^e nodes.  Per size: factor
     seconds (best of two after a warm-up build), first-RHS milliseconds,
     per-RHS microseconds (nrhs - 1 at once), levels, root size, largest
-    rank, and for the smaller sizes the seconds of a dense solve of the same
-    system on the GPU (our assembly + LU: the paper's conventional BEM).
-    Reported with the slope of log(factor time) against log(N) over the
+    rank, and for the smaller sizes the error of the first solution
+    against a dense solve of the same system on the GPU (accuracy reference
+    only).  Reported with the slope of log(factor time) against log(N) over the
     four largest sizes (1 for linear)."""
     import torch
     import synthetic as sy
-    lam, mu, rho, omega, tol, leaf = 2.0, 1.0, 1.0, 4.0, 1e-8, 64
+    lam, mu, rho, omega, tol, leaf = 2.0, 1.0, 1.0, 4.0, a.tol, 64
     rows = []
     for e in exps:
         n = 2 ** e
@@ -622,12 +714,8 @@ def complexity_ladder(fds, exps=(12, 13, 14, 15, 16, 17), dense_max_exp=14, nrhs
                "root_size": int(st["root_size"]), "max_rank": int(st["max_rank"])}
         if e <= dense_max_exp:
             dofs = np.arange(2 * n)
-            torch.cuda.synchronize()
-            t5 = time.perf_counter()
             A = fds.entries(curves, omega, lam, mu, rho, dofs, dofs)
             xd = torch.linalg.solve(A, rhs[0])
-            torch.cuda.synchronize()
-            row["dense_s"] = round(time.perf_counter() - t5, 4)
             row["rel_err_vs_dense"] = float(torch.linalg.norm(x1[0] - xd) / torch.linalg.norm(xd))
             del A, xd
         del F, rhs
@@ -679,10 +767,31 @@ def field_evaluation(fds, n=6400, nrhs=180, grid=64, reps=3):
             "n_near": n_near, "max_abs_u_inside_cavity": amax, "inside_points": int(inside.sum())}
 
 
+def sampled_accuracy(fds, curves, c, X, rhs, nrows=32, seed=11):
+    """Accuracy of solutions X (nrhs x N) of a multi-cavity case: the largest
+    relative residual on sampled rows of the exact Galerkin matrix, and the
+    error against the solutions of a tolerance-1e-12 factor of the same
+    geometry (same proxy rule)."""
+    import torch
+    n_unk = X.shape[1]
+    rows = np.sort(np.random.default_rng(seed).choice(n_unk, nrows, replace=False))
+    Arows = fds.entries(curves, c["omega"], c["lam"], c["mu"], c["rho"], rows, np.arange(n_unk))
+    Fr = fds.Factor(curves, c["omega"], c["lam"], c["mu"], c["rho"], 1e-12, leaf=c["leaf"])
+    Xref = Fr.solve(rhs)
+    st = Fr.stats()
+    del Fr
+    out = accuracy(X, Xref, Arows, rows, rhs)
+    out["ref_max_rank"] = int(st["max_rank"])
+    out["ref_sampled_rel_residual"] = accuracy(Xref, Xref, Arows, rows, rhs)["sampled_rel_residual"]
+    return out
+
+
 def multi_cavity_configs(fds, blob, reps=2):
     """The uneven-leaf 64-cavity case (adaptive IDs; graph-captured solve of
     180 alternating P/S waves) and the learned form's 128-cavity k_T = 8
-    evaluation case (adaptive against learned factor times)."""
+    evaluation case (adaptive against learned factor times), each with its
+    accuracy (sampled residual of the exact system, error against a
+    tolerance-1e-12 factor)."""
     import torch
     import synthetic as sy
     out = {}
@@ -698,7 +807,7 @@ def multi_cavity_configs(fds, blob, reps=2):
         F.solve(rhs)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        F.solve(rhs)
+        X = F.solve(rhs)
         torch.cuda.synchronize()
         tsol.append(time.perf_counter() - t1)
         st = F.stats()
@@ -707,24 +816,33 @@ def multi_cavity_configs(fds, blob, reps=2):
                                                "180 alternating P/S waves, graph-captured solve",
                                    "factor_s": round(min(ts), 4), "per_rhs_us": round(1e6 * min(tsol) / 180, 2),
                                    "root_size": int(st["root_size"]), "max_rank": int(st["max_rank"]),
-                                   "levels": int(st["levels"])}
+                                   "max_proxy": int(st["max_proxy"]), "levels": int(st["levels"]),
+                                   "accuracy": sampled_accuracy(fds, c["curves"], c, X, rhs)}
+    del X, rhs
     c = sy.config_learned_eval()
     res = {}
     for name, kw in (("adaptive", {}), ("learned", {"predictor": blob} if blob is not None else None)):
         if kw is None:
             continue
         ts = []
-        for _ in range(reps):
+        for rep in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             F = fds.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], c["tol"], leaf=c["leaf"], **kw)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
             st = F.stats()
+            if rep == reps - 1:
+                rhs = F.rhs_plane([0] * 4, [0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi])
+                X = F.solve(rhs)
             del F
         res[name] = {"factor_s": round(min(ts), 4), "id_s": round(st["id_seconds"], 4),
                      "cells": int(st["cells_compressed"]), "cells_sketched": int(st["cells_sketched"]),
-                     "fallback_rank": int(st["cells_fallback_rank"]), "fallback_judge": int(st["cells_fallback_judge"])}
+                     "fallback_rank": int(st["cells_fallback_rank"]), "fallback_judge": int(st["cells_fallback_judge"]),
+                     "max_rank": int(st["max_rank"]), "max_proxy": int(st["max_proxy"]),
+                     "root_size": int(st["root_size"]),
+                     "accuracy_4_p_waves": sampled_accuracy(fds, c["curves"], c, X, rhs)}
+        del X, rhs
     if "learned" in res:
         res["learned_speedup"] = round(res["adaptive"]["factor_s"] / res["learned"]["factor_s"], 4)
     res["workload"] = "128 cavities (seed 5), 131072 nodes (262144 unknowns), k_T=8, tol 1e-8, leaf 64"
@@ -732,7 +850,7 @@ def multi_cavity_configs(fds, blob, reps=2):
     return out
 
 
-def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2):
+def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, Xref=None, reps=2):
     """The mixed-precision form on the same input: FP32 elimination and
     sweeps, FP64 IDs / root LU, each solve refined against the FP64
     compressed operator (default stop rule).  Reports the factor and solve
@@ -743,7 +861,7 @@ def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2):
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Fm = fds.Factor([nodes], omega, lam, mu, rho, tol, leaf=leaf, mixed=True)
+        Fm = fds.Factor([nodes], omega, lam, mu, rho, tol, leaf=leaf, mixed=True, ir_max_iter=IR_MAX_ITER)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         y1 = Fm.solve(rhs[0])
@@ -760,11 +878,14 @@ def mixed_form(fds, nodes, omega, lam, mu, rho, tol, leaf, rhs, x1, xr, reps=2):
     X = torch.cat([x1.reshape(1, -1), xr], 0)
     Y = torch.cat([y1.reshape(1, -1), yr], 0)
     err = (torch.linalg.norm(Y - X, dim=1) / torch.linalg.norm(X, dim=1)).cpu().numpy()
-    return {"factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
+    return {"tol": tol, "factor_s": round(best[0], 4), "first_rhs_ms": round(1e3 * best[1], 3),
             "per_rhs_us": round(1e6 * best[2] / max(1, len(rhs) - 1), 2),
             "ir_iterations_first": int(it1), "ir_iterations_batch": int(st["ir_iterations"]),
             "ir_residual": st["ir_residual"], "factor_gb": round(st["factor_bytes"] / 1e9, 3),
-            "err_vs_plain_fp64_max": float(err.max()), "err_vs_plain_fp64_median": float(np.median(err))}
+            "err_vs_plain_fp64_max": float(err.max()), "err_vs_plain_fp64_median": float(np.median(err)),
+            **({} if Xref is None else {
+                "err_vs_tol1e-12_max": float((torch.linalg.norm(Y - Xref, dim=1) /
+                                              torch.linalg.norm(Xref, dim=1)).max().item())})}
 
 
 def _oracle_worker_ready(_):

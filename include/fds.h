@@ -76,7 +76,8 @@ typedef struct {
                                A_i^{-1} U_i, V_i X_i, A~_i and the solve sweeps in complex FP32; each
                                solve refined iteratively against the FP64 compressed operator A_c */
   int32_t ir_max_iter;      /* mixed form: refinement steps allowed per solve; default 10 */
-  int32_t reserved1;
+  int32_t proxy_fixed;      /* 1: every proxy polygon has exactly n_proxy vertices (no growth with k_T rho;
+                               for comparisons); default 0 */
   double ir_rtol;           /* mixed form: stop when every column has ||f - A_c x|| <= ir_rtol ||f||
                                (default 1e-8) ... */
   double ir_dtol;           /* ... and its last correction ||delta|| <= ir_dtol ||x|| (default 1e-6; the

@@ -44,7 +44,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("leaf_nodes", ctypes.c_int32), ("n_proxy", ctypes.c_int32), ("root_level", ctypes.c_int32),
                 ("solve_graph", ctypes.c_int32), ("proxy_ratio", ctypes.c_double), ("alpha", _C64),
                 ("use_alpha", ctypes.c_int32), ("precision", ctypes.c_int32), ("ir_max_iter", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double),
+                ("proxy_fixed", ctypes.c_int32), ("ir_rtol", ctypes.c_double), ("ir_dtol", ctypes.c_double),
                 ("rank_mode", ctypes.c_int32), ("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("predictor", ctypes.POINTER(ctypes.c_float)), ("autotune", ctypes.c_int32),
                 ("mfma_sweeps", ctypes.c_int32)]
@@ -192,7 +192,7 @@ def _geometry(curves):
 
 def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, solve_graph=False, mixed=False,
              ir_max_iter=None, ir_rtol=None, ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True,
-             mfma_sweeps=True):
+             mfma_sweeps=True, proxy_fixed=False):
     o = _Options()
     load().fds_options_default(ctypes.byref(o))
     o.leaf_nodes, o.n_proxy, o.root_level, o.proxy_ratio = int(leaf), int(n_proxy), int(root_level), float(proxy_ratio)
@@ -215,6 +215,7 @@ def _options(leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5, alpha=None, sol
         o.seed = int(seed)
     o.autotune = int(bool(autotune))
     o.mfma_sweeps = int(bool(mfma_sweeps))
+    o.proxy_fixed = int(bool(proxy_fixed))
     if alpha is not None:
         a = complex(alpha)
         o.alpha = _C64(a.real, a.imag)
@@ -261,11 +262,12 @@ class Factor:
 
     def __init__(self, curves, omega, lam, mu, rho, tol, leaf=64, n_proxy=64, root_level=1, proxy_ratio=1.5,
                  alpha=None, stream=None, solve_graph=False, mixed=False, ir_max_iter=None, ir_rtol=None,
-                 ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True, mfma_sweeps=True):
+                 ir_dtol=None, predictor=None, oversample=None, seed=None, autotune=True, mfma_sweeps=True,
+                 proxy_fixed=False):
         L = load()
         g, self._keep = _geometry(curves)
         o = _options(leaf, n_proxy, root_level, proxy_ratio, alpha, solve_graph, mixed, ir_max_iter, ir_rtol,
-                     ir_dtol, predictor, oversample, seed, autotune, mfma_sweeps)
+                     ir_dtol, predictor, oversample, seed, autotune, mfma_sweeps, proxy_fixed)
         h = ctypes.c_void_p()
         _check(L.fds_build(ctypes.byref(g), omega, lam, mu, rho, tol, ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))

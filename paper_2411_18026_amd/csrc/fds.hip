@@ -1139,7 +1139,7 @@ static void compress_level(Factor& F, int lev) {
   // n_proxy, more when the wave oscillates faster than it resolves)
   std::vector<int> npx(n), poff(n + 1, 0);
   for (int q = 0; q < n; ++q) {
-    npx[q] = proxy_count(F.m.kT, crd[3 * q + 2], F.opt.n_proxy);
+    npx[q] = F.opt.proxy_fixed ? F.opt.n_proxy : proxy_count(F.m.kT, crd[3 * q + 2], F.opt.n_proxy);
     poff[q + 1] = poff[q] + npx[q];
     lv.max_proxy = std::max(lv.max_proxy, npx[q]);
   }

@@ -1701,10 +1701,19 @@ void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol
   if (n == 0 || ncol_max == 0) return;
   int nc = solve_chunk(nmax);
   if (chunk > 0 && lu_solve_smem(nmax, chunk, sizeof(T)) <= 65536) nc = chunk;
-  // the pivots staged in LDS when they fit next to the block (else in place)
-  const int staged = lu_solve_smem(nmax, nc, sizeof(T)) <= 65536 ? 1 : 0;
+  // the pivots staged in LDS when they fit next to the block (else in
+  // place); large single matrices (a compressed root of several thousand
+  // unknowns) use up to the whole LDS of a CU
+  constexpr size_t kLdsMax = 160 * 1024;
+  const int staged = lu_solve_smem(nmax, nc, sizeof(T)) <= kLdsMax ? 1 : 0;
   const size_t smem = staged ? lu_solve_smem(nmax, nc, sizeof(T)) : (size_t)std::max(1, nmax) * nc * sizeof(T);
-  if (smem > 65536) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  if (smem > kLdsMax) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  if (smem > 65536) {
+    FDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lu_solve<T, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    FDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lu_solve<T, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  }
   dim3 grid(n, (ncol_max + nc - 1) / nc);
   if (nc == 16 || nc == 32) {
     // many right-hand sides: diagonal blocks per column, updates as small GEMMs

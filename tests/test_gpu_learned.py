@@ -184,7 +184,8 @@ def test_learned_factor_accepts_sketches_and_stays_accurate(fdsmod):
     rhs = torch.from_numpy(np.ascontiguousarray(Fm.T)).to("cuda")
     ea = np.linalg.norm(Fa.solve(rhs).cpu().numpy().T - X) / np.linalg.norm(X)
     el = np.linalg.norm(Fl.solve(rhs).cpu().numpy().T - X) / np.linalg.norm(X)
-    assert el <= 10 * ea + 1e-12, (el, ea)
+    print(f"error vs dense: learned {el:.3e}, adaptive {ea:.3e}", flush=True)
+    assert el <= 2 * ea + 1e-12, (el, ea)
     # every accepted leaf skeleton admits an interpolation within tol
     S = ofds.FDS(curves, 2.0, 1.0, 1.0, omega, tol, leaf=leaf)
     mat = Material(2.0, 1.0, 1.0, omega)
@@ -221,12 +222,29 @@ def test_rank_log_features_match_oracle(fdsmod):
     assert np.all(log["k_pred"] == -1) and np.all(log["fallback"] == 0)
 
 
-def test_training_on_recorded_ranks_gains_over_an_untrained_network(fdsmod):
+def test_trained_predictor_against_the_adaptive_method(fdsmod):
     """The predictor trained by the library's own kernels on ranks the solver
-    recorded: on held-out geometries of the training family its sketches are
-    accepted at least as often as an untrained network's (same
-    initialisation) while sized far closer to the true ranks, with few
-    under-predictions."""
+    recorded (12 geometries of the training family at 4096 nodes), against
+    the method without it (every ID by the pivoted QR of its proxy-plus-near
+    matrix) on three held-out geometries of that family at tol 1e-8:
+
+    * what it gains: most cells take their ID from a sketch of
+      ceil(k_pred) + 10 rows instead of the full interaction matrix, and the
+      pivoted QR then works on under two thirds of the rows the adaptive
+      form factors (counted from the rank log, fallbacks charged with both
+      the sketch and the full matrix; measured 0.55, 70 % of the cells
+      from sketches);
+    * what it keeps: every skeleton admits its interpolation (judge), the
+      solutions differ from the adaptive ones by the compression error only
+      (within 1e3 tol), and few ranks are under-predicted;
+    * what it costs: both factor times and ID-stage times are measured (best
+      of three) and printed.  On this GPU the register-resident pivoted QR
+      reads each interaction matrix once, so a sketch (one more pass over
+      the matrix, then the judge's pass) does not shorten the ID stage: the
+      learned form is asserted to stay within 1.6x of the adaptive ID stage
+      and 1.3x of its factor time (measured 1.35x and 1.14x), not to beat
+      them."""
+    import time
     from paper_2411_18026_amd import predictor as pr
     train = [sy.training_geometry(i, nodes=4096) for i in range(12)]
     held = [sy.training_geometry(100 + i, nodes=4096) for i in range(3)]
@@ -234,22 +252,46 @@ def test_training_on_recorded_ranks_gains_over_an_untrained_network(fdsmod):
     blob0 = fdsmod.mlp_init(x, y, seed=3)
     blob, hist = fdsmod.mlp_train(blob0, x, y, 1500, 256, 2e-3, seed=4)
     assert hist[-1] < 0.05 * hist[0]
-    acc = {"t": 0, "0": 0}
-    slack = {"t": [], "0": []}
-    under, cells = [], 0
+
+    def timed(curves, k_t, **kw):
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = fdsmod.Factor(curves, k_t, 2.0, 1.0, 1.0, 1e-8, leaf=64, **kw)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0, F.stats()["id_seconds"])
+            best = t if best is None else (min(best[0], t[0]), min(best[1], t[1]))
+        return F, best
+
+    cells = accepted = 0
+    rows_adaptive = rows_learned = 0.0
+    t_a = t_l = id_a = id_l = 0.0
+    under = []
     for curves, k_t in held:
         xh, yh = pr.rank_log_dataset(curves, k_t, 2.0, 1.0, 1.0, 1e-8)
-        under.append(pr.evaluate(blob, xh, yh)["under"])
-        for b, tag in ((blob, "t"), (blob0, "0")):
-            F = fdsmod.Factor(curves, k_t, 2.0, 1.0, 1.0, 1e-8, leaf=64, predictor=b)
-            log = F.rank_log()
-            acc[tag] += int(np.sum(log["fallback"] == 0))
-            sel = log["k_pred"] >= 0
-            slack[tag].extend(list(log["k_pred"][sel] + 10 - log["rank"][sel].max(axis=1)))
-            if tag == "t":
-                cells += len(log["cell"])
-            F.close()
-    assert np.mean(under) < 0.15
-    assert acc["t"] >= 0.6 * cells and acc["t"] >= acc["0"], (acc, cells)
-    assert np.mean(np.abs(slack["t"])) < 0.5 * np.mean(np.abs(slack["0"])), (np.mean(np.abs(slack["t"])),
-                                                                              np.mean(np.abs(slack["0"])))
+        under.append(pr.evaluate(blob, xh, yh, oversample=10)["under"])
+        Fa, (ta, ia) = timed(curves, k_t)
+        Fl, (tl, il) = timed(curves, k_t, predictor=blob)
+        t_a, t_l, id_a, id_l = t_a + ta, t_l + tl, id_a + ia, id_l + il
+        log = Fl.rank_log()
+        m = np.exp(log["feat"][:, 4])                   # rows of the proxy-plus-near matrix
+        acc = log["fallback"] == 0
+        s_rows = np.ceil(np.maximum(log["k_pred"], 0)) + 10
+        cells += len(log["cell"])
+        accepted += int(acc.sum())
+        rows_adaptive += float(m.sum())
+        rows_learned += float(np.where(acc, s_rows, m + s_rows * (log["k_pred"] >= 0)).sum())
+        rhs = Fa.rhs_plane([0, 1], [0.0, 1.0])
+        xa, xl = Fa.solve(rhs), Fl.solve(rhs)
+        d = float((torch.linalg.norm(xa - xl, dim=1) / torch.linalg.norm(xa, dim=1)).max())
+        assert d < 1e3 * 1e-8, d
+        Fa.close()
+        Fl.close()
+    print(f"held-out: {accepted}/{cells} cells from sketches, QR rows {rows_learned / rows_adaptive:.3f} of the "
+          f"adaptive form's; factor {t_l:.3f} s learned vs {t_a:.3f} s adaptive, ID stage {id_l:.3f} s vs "
+          f"{id_a:.3f} s; under-predicted {np.mean(under):.3f}", flush=True)
+    assert accepted >= 0.6 * cells
+    assert rows_learned < 0.65 * rows_adaptive
+    assert np.mean(under) < 0.25
+    assert id_l < 1.6 * id_a and t_l < 1.3 * t_a
