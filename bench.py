@@ -160,6 +160,16 @@ def main():
                 "flop_per_eval": FLOP_PER_EVAL, "evals": int(cls_e[dom]), "launches": int(cls_n[dom]),
                 "avg_launch_ms": round(1e3 * cls_s[dom] / max(1, cls_n[dom]), 3)}
 
+    # roofline of the batched solve (179 right-hand sides at once): its
+    # algorithmic flops (every cell's LU solve, W g, A~ y and X z, and the
+    # root's LU solve; 8 real flops per complex multiply-add) over the
+    # measured time, against the FP64 matrix peak
+    sflop = solve_flops(ranks, int(st["levels"]), int(st["root_level"]), int(st["root_size"]), 2 * leaf)
+    sach = sflop * (a.nrhs - 1) / mean["rest"] / 1e12
+    roofline_solve = {"bound": "mfma", "kernel": "solve sweeps (k_sweep_up, k_gemm, k_lu_solve)",
+                      "achieved": round(sach, 3), "peak": 78.6, "unit": "TFLOP/s", "frac": round(sach / 78.6, 4),
+                      "traffic": None, "flop_per_rhs": sflop, "nrhs": a.nrhs - 1}
+
     log("graph-captured solve form")
     # batched form: the same factorisation with the solve sweeps replayed as a
     # hipGraph captured once per nrhs (first call captures, the timed calls replay)
@@ -300,6 +310,7 @@ def main():
         "complexity_ladder": cladder,
         "paper_multi_rhs": paper_rhs,
         "roofline": roofline,
+        "roofline_solve": roofline_solve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -318,6 +329,24 @@ PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_m
 # 11 - 12 steps are needed at tol 1e-11 and with the learned skeletons (the
 # library's default is 10)
 IR_MAX_ITER = 20
+
+
+def solve_flops(ranks, L, l0, n_root, b_leaf):
+    """Real flops of one right-hand side through the sweeps of a tree whose
+    leaves all have b_leaf unknowns: per compressed cell of order b and
+    skeleton size r, the LU solve (b^2 complex multiply-adds), W g and X z
+    (r b each) and A~ y (r^2); the root's LU solve (n_root^2)."""
+    def r_of(c):
+        k = ranks[c]
+        return int(max(k[0], k[1]) + max(k[2], k[3]))
+    cmacs = float(n_root) ** 2
+    for lev in range(L, l0, -1):
+        for q in range(2 ** lev):
+            c = 2 ** lev - 1 + q
+            b = b_leaf if lev == L else r_of(2 * c + 1) + r_of(2 * c + 2)
+            r = r_of(c)
+            cmacs += b * b + 2.0 * r * b + r * r
+    return 8.0 * cmacs
 
 
 def accuracy(X, Xref, Arows, rows, rhs):
