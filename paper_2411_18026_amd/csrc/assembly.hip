@@ -48,16 +48,63 @@ __constant__ QuadTables c_quad;
 // pair's 16 entries:
 //   entry[a][b][ij] += N_a dN_b M1 + w dN_a dN_b M2 + N_a N_b M3 + w dN_a N_b M4
 // (N the hat values, dN their constant tangential derivatives, w the
-// quadrature weight; N_a carries w).
-__device__ inline void point_blocks(const MatConst& m, double dx, double dy, double nx0, double nx1, double ny0,
-                                    double ny1, c64 (&M1)[4], c64 (&M2)[4], c64 (&M3)[4], c64 (&M4)[4]) {
-  const double r = sqrt(dx * dx + dy * dy);
-  const double ir = 1.0 / r;
+// quadrature weight; N_a carries w).  The blocks are formed entry by entry
+// (ij) and added at once, so only one entry's four values are live.  SER:
+// the point is known to lie on the small-argument series (k_T r < 1): the
+// same values without the Bessel-function branch.
+
+// A pair's 16 entries accumulated point by point (64 registers, which lets
+// two wavefronts share a SIMD; the special pairs sum them over the lanes of
+// their wavefront afterwards).  During the accumulation slot [a][b][ij]
+// (index 8 a + 4 b + ij) holds, instead of entry [a][b], the combination
+//   [0][0]: sum over a and b,  [0][1]: sum over a at b = 1,
+//   [1][0]: sum over b at a = 1,  [1][1]: the entry [1][1] itself,
+// which the hat structure (N_0 + N_1 = 1 for the values, dN_1 = -dN_0 for
+// the derivatives) makes cheaper to accumulate: 18 real multiply-adds per
+// point and ij instead of 32.  pair_entries turns the sums into entries.
+struct PairRes {
+  c64 R[16];
+};
+
+__device__ inline void pair_entries(PairRes& A) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const c64 ss = A.R[k], s1 = A.R[4 + k], t1 = A.R[8 + k], b11 = A.R[12 + k];
+    const c64 e01 = s1 - b11, e10 = t1 - b11;
+    A.R[k] = ss - e01 - e10 - b11;
+    A.R[4 + k] = e01;
+    A.R[8 + k] = e10;
+  }
+}
+
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2)/2 (each squares the relative error;
+// within about 1 ulp).
+__device__ inline double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+template <bool SER = false>
+__device__ inline void acc_point_direct(const MatConst& m, double dx, double dy, double w, double u, double v,
+                                        double nx0, double nx1, double ny0, double ny1, double dA0, double dA1,
+                                        double dB0, double dB1, PairRes& A) {
+  const double r2 = dx * dx + dy * dy;
+  const double ir = rsqrt_newton(r2);
+  const double r = r2 * ir;
   const double e0 = dx * ir, e1 = dy * ir;
   const double je0 = -e1, je1 = e0;
   const double a = m.kT * r;
   c64 h0a, h1a, h0b, E, chi;
-  kernel_values(a, m.sc, h0a, h1a, h0b, E, chi);
+  if (SER)
+    kernel_values_series(a, m.sc, h0a, h1a, h0b, E, chi);
+  else
+    kernel_values(a, m.sc, h0a, h1a, h0b, E, chi);
   const c64 phiT = cmk(-0.25 * h0a.im, 0.25 * h0a.re);
   const c64 phiL = cmk(-0.25 * h0b.im, 0.25 * h0b.re);
   const c64 q = cmk(-0.25 * m.kT * h1a.im, 0.25 * m.kT * h1a.re);   // (i/4) k_T H1(a)
@@ -73,8 +120,10 @@ __device__ inline void point_blocks(const MatConst& m, double dx, double dy, dou
   const c64 Z = mul_i(m.mu * al);              // i alpha mu
   const c64 P = phiT - cmk(-0.5 * E.im, 0.5 * E.re);   // Phi_T - (i/2) E
   const c64 hc = cmk(-0.5 * chi.im, 0.5 * chi.re);     // (i/2) chi
-  const c64 Kdnx = K * dnx;
+  const c64 PK = P + K * dnx;                  // the J parts of M1
   const c64 Kcg = K * cg;
+  const c64 ZE = Z * E, Zchi = Z * chi;
+  const c64 Kdny = K * dny;
   const double ex[2] = {e0, e1};
   const double jex[2] = {je0, je1};
   const double nx[2] = {nx0, nx1};
@@ -84,43 +133,38 @@ __device__ inline void point_blocks(const MatConst& m, double dx, double dy, dou
   const c64 arw = (m.rw2) * al;
   const c64 arwL = arw * phiL;
   const c64 arwT = arw * phiT;
+  // weights of the four accumulated combinations (dA1 = -dA0, dB1 = -dB0)
+  (void)dA0;
+  (void)dB0;
+  const double wu = w * u, wv = w * v, wuv = wu * v;
+  const double s1_m1 = w * dB1;                  // [0][1]: w dB1 M1 + w v M3
+  const double t1_m4 = w * dA1;                  // [1][0]: w u M3 + w dA1 M4
+  const double b_m1 = wu * dB1, b_m2 = (w * dA1) * dB1, b_m4 = (w * dA1) * v;   // [1][1]
+  // entry ij: J = [[0, -1], [1, 0]], delta the identity; terms with a zero
+  // factor J_ij or delta_ij are left out
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const double Jij = (i == j) ? 0.0 : (i == 0 ? -1.0 : 1.0);
-      const double dij = (i == j) ? 1.0 : 0.0;
-      M1[2 * i + j] = Jij * P - (ex[i] * jex[j]) * hc + Jij * Kdnx + (nx[i] * jex[j]) * Kcg;
-      M2[2 * i + j] = Z * ((-dij) * E + (jex[i] * jex[j]) * chi);
-      M3[2 * i + j] = dij * dny + (ex[i] * ny[j]) * cg + (nx[i] * ny[j]) * arwL + (tx[i] * ty[j]) * arwT;
-      M4[2 * i + j] = (-1.0) * (K * (Jij * dny + (jex[i] * ny[j]) * cg));
-    }
-}
-
-// A pair's 16 entries accumulated point by point (64 registers, which lets
-// two wavefronts share a SIMD; the special pairs sum them over the lanes of
-// their wavefront afterwards).
-struct PairRes {
-  c64 R[16];
-};
-
-__device__ inline void acc_point_direct(const MatConst& m, double dx, double dy, double w, double u, double v,
-                                        double nx0, double nx1, double ny0, double ny1, double dA0, double dA1,
-                                        double dB0, double dB1, PairRes& A) {
-  c64 M1[4], M2[4], M3[4], M4[4];
-  point_blocks(m, dx, dy, nx0, nx1, ny0, ny1, M1, M2, M3, M4);
-  const double Na[2] = {w * (1.0 - u), w * u};
-  const double Nb[2] = {1.0 - v, v};
-  const double wdA[2] = {w * dA0, w * dA1};
-  const double dB[2] = {dB0, dB1};
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-      const c64 T = dB[bb] * M1[k] + Nb[bb] * M3[k];
-      const c64 U = dB[bb] * M2[k] + Nb[bb] * M4[k];
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa) A.R[aa * 8 + bb * 4 + k] += Na[aa] * T + wdA[aa] * U;
+      const int k = 2 * i + j;
+      c64 M1 = (nx[i] * jex[j]) * Kcg - (ex[i] * jex[j]) * hc;
+      c64 M2 = (jex[i] * jex[j]) * Zchi;
+      c64 M3 = (ex[i] * ny[j]) * cg + (nx[i] * ny[j]) * arwL + (tx[i] * ty[j]) * arwT;
+      c64 M4 = -((jex[i] * ny[j]) * Kcg);
+      if (i == j) {
+        M2 -= ZE;
+        M3 += dny;
+      } else if (i == 0) {   // J_01 = -1
+        M1 -= PK;
+        M4 += Kdny;
+      } else {               // J_10 = 1
+        M1 += PK;
+        M4 -= Kdny;
+      }
+      A.R[k] += w * M3;
+      A.R[4 + k] += s1_m1 * M1 + wv * M3;
+      A.R[8 + k] += wu * M3 + t1_m4 * M4;
+      A.R[12 + k] += b_m1 * M1 + wuv * M3 + b_m2 * M2 + b_m4 * M4;
     }
 }
 
@@ -151,9 +195,23 @@ __device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf
   const double hm = fmax(e.h, f.h);
   const double kh = kT * hm;
   if (kh > kKhQ6) return kQ10;
-  if (d >= kFarRatio * hm && kh <= kKhQ4) return kQ4;
-  if (d >= kNearRatio * hm) return kQ6;
-  return kQ10;
+  int c;
+  if (d >= kFarRatio * hm && kh <= kKhQ4)
+    c = kQ4;
+  else if (d >= kNearRatio * hm)
+    c = kQ6;
+  else
+    return kQ10;
+  // the largest distance between two points of the elements is an endpoint distance
+  double dm2 = 0.0;
+  {
+    const double p[4][2] = {{e.x0 - f.x0, e.y0 - f.y0}, {e.x0 - f.x1, e.y0 - f.y1},
+                            {e.x1 - f.x0, e.y1 - f.y0}, {e.x1 - f.x1, e.y1 - f.y1}};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dm2 = fmax(dm2, p[k][0] * p[k][0] + p[k][1] * p[k][1]);
+  }
+  if (kT * sqrt(dm2) < kSeriesOnly) c = (c == kQ4) ? kQ4S : kQ6S;
+  return c;
 }
 
 // ------------------------------------------------------------------ geometry
@@ -298,7 +356,7 @@ __device__ inline void decode(unsigned long long key, const Job* jobs, const int
 }
 
 // ------------------------------------------------------------------ regular pairs
-template <int Q>
+template <int Q, bool SER>
 __device__ inline void regular_pair(unsigned long long key, const Job* __restrict__ jobs, const int* __restrict__ elist,
                                     const Elem* __restrict__ elems, const MatConst& m, c64* __restrict__ res,
                                     int64_t np) {
@@ -323,25 +381,26 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
       const double v = g[j];
       const double dx = ox + u * ax - v * bx;
       const double dy = oy + u * ay - v * by;
-      acc_point_direct(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
+      acc_point_direct<SER>(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   }
+  pair_entries(A);
   const int64_t slot = pair_slot(jb, ie, je);
 #pragma unroll
   for (int k = 0; k < 16; ++k) res[k * np + slot] = A.R[k];
 }
 
 // grid-stride over the class list; its length is read on the device.  Two
-// wavefronts per SIMD: the register budget is 256 per lane.
-template <int Q>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) k_regular(const unsigned long long* __restrict__ list,
-                                                 const unsigned int* __restrict__ count_ptr,
-                                                 const Job* __restrict__ jobs, const int* __restrict__ elist,
-                                                 const Elem* __restrict__ elems, MatConst m,
-                                                 c64* __restrict__ res, int64_t np) {
+// wavefronts per SIMD: the register budget is 256 per lane.  SER: the
+// series-only lists (no Bessel-function code, no call, fewer registers).
+template <int Q, bool SER>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_regular(const unsigned long long* __restrict__ list, const unsigned int* __restrict__ count_ptr,
+          const Job* __restrict__ jobs, const int* __restrict__ elist, const Elem* __restrict__ elems, MatConst m,
+          c64* __restrict__ res, int64_t np) {
   const int64_t count = min((int64_t)*count_ptr, np);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-    regular_pair<Q>(list[t], jobs, elist, elems, m, res, np);
+    regular_pair<Q, SER>(list[t], jobs, elist, elems, m, res, np);
 }
 
 // 10-point pairs: one wavefront per pair (the 100 points of the tensor rule
@@ -370,6 +429,7 @@ __device__ inline void regular_pair_wave10(unsigned long long key, int lane, con
                      e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
   }
   const int64_t slot = pair_slot(jb, ie, je);
+  pair_entries(A);   // linear: each lane's partial sums, then the lane sums
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     c64 val = A.R[k];
@@ -483,6 +543,7 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
     }
   }
   const int64_t slot = pair_slot(jb, ie, je);
+  pair_entries(A);   // linear: each lane's partial sums, then the lane sums
 #pragma unroll
   for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
@@ -630,16 +691,17 @@ int classify_tile_size() { return kClsTile; }
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
                   const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
                   hipEvent_t* ev) {
-  // ev (optional): 7 events bracketing the six class launches in order
+  // ev (optional): kNumClass + 1 events bracketing the class launches in
+  // the order of the class index
   auto mark = [&](int i) {
     if (ev) FDS_HIP(hipEventRecord(ev[i], s));
   };
   const unsigned greg = (unsigned)std::min<int64_t>((np + 127) / 128, 4096);
   const unsigned gspc = (unsigned)std::min<int64_t>((np + 3) / 4, 2048);
   mark(0);
-  k_regular<4><<<greg, 128, 0, s>>>(lists + kQ4 * cap, counts + kQ4, jobs, elist, elems, m, res, np);
+  k_regular<4, false><<<greg, 128, 0, s>>>(lists + kQ4 * cap, counts + kQ4, jobs, elist, elems, m, res, np);
   mark(1);
-  k_regular<6><<<greg, 128, 0, s>>>(lists + kQ6 * cap, counts + kQ6, jobs, elist, elems, m, res, np);
+  k_regular<6, false><<<greg, 128, 0, s>>>(lists + kQ6 * cap, counts + kQ6, jobs, elist, elems, m, res, np);
   mark(2);
   k_regular_wave10<<<gspc, 256, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
   mark(3);
@@ -649,6 +711,10 @@ void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned i
   mark(5);
   k_special2<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
   mark(6);
+  k_regular<4, true><<<greg, 128, 0, s>>>(lists + kQ4S * cap, counts + kQ4S, jobs, elist, elems, m, res, np);
+  mark(7);
+  k_regular<6, true><<<greg, 128, 0, s>>>(lists + kQ6S * cap, counts + kQ6S, jobs, elist, elems, m, res, np);
+  mark(8);
   FDS_HIP(hipGetLastError());
 }
 

@@ -53,11 +53,12 @@ struct AssemblyStats {
   static constexpr int kMaxBatches = 8192;
   double seconds = 0.0;
   int64_t evals = 0;
-  double class_seconds[kNumClass] = {0, 0, 0, 0, 0, 0};
-  int64_t class_evals[kNumClass] = {0, 0, 0, 0, 0, 0};
-  int64_t class_launches[kNumClass] = {0, 0, 0, 0, 0, 0};
+  // per reported class (the series-only lists count with their order)
+  double class_seconds[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
+  int64_t class_evals[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
+  int64_t class_launches[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
   unsigned int* d_counts = nullptr;       // kMaxBatches x kNumClass device counters
-  std::vector<std::vector<hipEvent_t>> pending;   // per batch: start, 7 class marks, end
+  std::vector<std::vector<hipEvent_t>> pending;   // per batch: start, kNumClass + 1 class marks, end
   void resolve(hipStream_t s);
   ~AssemblyStats();
 };

@@ -112,7 +112,8 @@ QuadTables make_quad_tables() {
   return q;
 }
 
-static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts, kNAdjPts};
+static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts, kNAdjPts, 16, 36};
+constexpr int kBatchEvents = kNumClass + 3;   // start, kNumClass + 1 class marks, end
 
 void AssemblyStats::resolve(hipStream_t s) {
   if (pending.empty()) return;
@@ -122,16 +123,17 @@ void AssemblyStats::resolve(hipStream_t s) {
   for (size_t b = 0; b < pending.size(); ++b) {
     auto& ev = pending[b];
     float ms = 0.f;
-    FDS_HIP(hipEventElapsedTime(&ms, ev[0], ev[8]));
+    FDS_HIP(hipEventElapsedTime(&ms, ev[0], ev[kBatchEvents - 1]));
     seconds += 1e-3 * ms;
     for (int c = 0; c < kNumClass; ++c) {
       const unsigned n = cnt[b * kNumClass + c];
+      const int pc = public_class(c);
       evals += (int64_t)n * kPointsPerClass[c];
-      class_evals[c] += (int64_t)n * kPointsPerClass[c];
-      if (n) class_launches[c] += 1;
+      class_evals[pc] += (int64_t)n * kPointsPerClass[c];
+      if (n) class_launches[pc] += 1;
       float cm = 0.f;
       FDS_HIP(hipEventElapsedTime(&cm, ev[1 + c], ev[2 + c]));
-      class_seconds[c] += 1e-3 * cm;
+      class_seconds[pc] += 1e-3 * cm;
     }
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -223,7 +225,7 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
       if (!st->d_counts)
         st->d_counts = ws.get<unsigned int>("asm_counts", (size_t)AssemblyStats::kMaxBatches * kNumClass);
       d_cnt = st->d_counts + st->pending.size() * kNumClass;
-      ev.resize(9);
+      ev.resize(kBatchEvents);
       for (auto& e : ev) FDS_HIP(hipEventCreate(&e));
     } else {
       d_cnt = ws.get<unsigned int>("asm_cnt_tmp", kNumClass);
@@ -234,7 +236,7 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
     launch_pairs(d_lists, np, d_cnt, d_jobs, d_elist, d_elems, m, d_res, np, s, ev.empty() ? nullptr : ev.data() + 1);
     launch_gather(d_ot, (int)otiles.size(), d_jobs, d_dofs, d_pos, d_res, np, d_out, s);
     if (!ev.empty()) {
-      FDS_HIP(hipEventRecord(ev[8], s));
+      FDS_HIP(hipEventRecord(ev[kBatchEvents - 1], s));
       st->pending.push_back(ev);
     }
     i0 = i1;

@@ -80,7 +80,29 @@ struct Tile {
   int64_t start;
 };
 
-enum PairClass : int { kQ4 = 0, kQ6 = 1, kQ10 = 2, kCoinc = 3, kAdjNext = 4, kAdjPrev = 5, kNumClass = 6 };
+// Element-pair classes.  kQ4S and kQ6S hold the 4- and 6-point pairs whose
+// kernels stay on their small-argument series at every point (k_T times the
+// largest distance between the two elements below kSeriesOnly): the same
+// arithmetic as kQ4 / kQ6, in a kernel without the Bessel-function code
+// (fewer registers).  They are reported with kQ4 and kQ6.
+enum PairClass : int {
+  kQ4 = 0,
+  kQ6 = 1,
+  kQ10 = 2,
+  kCoinc = 3,
+  kAdjNext = 4,
+  kAdjPrev = 5,
+  kQ4S = 6,
+  kQ6S = 7,
+  kNumClass = 8
+};
+constexpr int kNumPublicClass = 6;
+__host__ __device__ constexpr int public_class(int c) { return c == kQ4S ? kQ4 : (c == kQ6S ? kQ6 : c); }
+// a pair is series-only when k_T d_max < kSeriesOnly (d_max the largest
+// endpoint distance, which bounds every point distance); the margin below
+// the series switch (1) keeps rounding from deciding the class
+constexpr double kSeriesOnly = 0.999;
+static_assert(kSeriesOnly < kSeriesSwitch, "series-only pairs must stay below the series switch");
 
 // quadrature constants (filled at library initialisation)
 constexpr int kQCoinc = 20;

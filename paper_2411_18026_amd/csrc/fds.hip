@@ -2243,7 +2243,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     F->st.factor_bytes = bytes;
     F->st.assembly_seconds = F->ast.seconds;
     F->st.kernel_evals = F->ast.evals;
-    for (int c = 0; c < kNumClass; ++c) {
+    for (int c = 0; c < kNumPublicClass; ++c) {
       F->st.class_seconds[c] = F->ast.class_seconds[c];
       F->st.class_evals[c] = F->ast.class_evals[c];
       F->st.class_launches[c] = F->ast.class_launches[c];

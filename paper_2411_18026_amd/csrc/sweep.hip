@@ -153,12 +153,16 @@ __device__ inline void sweep_unit(int n_groups, int& cell, int& grp) {
   grp = slot % n_groups;
 }
 
-constexpr int kPanLd = 257;   // LDS pitch of a staged 16-column panel (rows), odd: no bank aliasing across columns
+// LDS pitch of a staged 16-column panel of a cell of at most 16 NB rows
+// (odd: no bank aliasing across columns); the smaller cells' panels leave
+// room for a second workgroup on the CU
+template <int NB>
+constexpr int pan_ld() { return 16 * NB + 1; }
 
 // One 16-column panel of a cell's LU, rows [r0, r1), columns [c0, c0 + 16),
 // staged in LDS with the 16 x 16 inverted diagonal block: the workgroup
 // loads it into registers while the previous panel is in use, then stores
-// it (P: kPanLd x 16 complex, D: 256 complex).  Rows at or beyond the
+// it (P: pan_ld x 16 complex, D: 256 complex).  Rows at or beyond the
 // order b (the padding of a partial last block) are stored as zeros: a
 // padded entry meets the zero part of an inverted diagonal block, and
 // 0 times stale LDS contents (possibly NaN) is not 0.
@@ -167,40 +171,35 @@ struct PanelRegs {
   c64 d;
 };
 
+// Thread t takes row r0 + t of the panel (a panel has at most 240 rows,
+// the workgroup 256 threads) and its 16 columns: consecutive threads read
+// consecutive rows of a column.
 __device__ inline void panel_fetch(PanelRegs& pr, const c64* __restrict__ L, int b, int r0, int r1, int c0,
                                    const c64* __restrict__ Di, int tid) {
-  const int rows = r1 - r0;
+  const int rr = r0 + tid;
+  const bool in = rr < r1 && rr < b;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int e = tid + 256 * t;   // e = c * rows + (row - r0)
-    c64 x = cmk(0.0, 0.0);
-    if (e < 16 * rows) {
-      const int c = e / rows, rr = r0 + e % rows;
-      if (rr < b) x = L[rr + (int64_t)(c0 + c) * b];
-    }
-    pr.v[t] = x;
-  }
+  for (int c = 0; c < 16; ++c) pr.v[c] = in ? L[rr + (int64_t)(c0 + c) * b] : cmk(0.0, 0.0);
   pr.d = Di[tid];
 }
 
+template <int LD>
 __device__ inline void panel_store(const PanelRegs& pr, c64* __restrict__ P, c64* __restrict__ D, int r0, int r1,
                                    int tid) {
-  const int rows = r1 - r0;
+  if (r0 + tid < r1)
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int e = tid + 256 * t;
-    if (e < 16 * rows) P[(e / rows) * kPanLd + r0 + e % rows] = pr.v[t];
-  }
+    for (int c = 0; c < 16; ++c) P[c * LD + r0 + tid] = pr.v[c];
   D[tid] = pr.d;
 }
 
 // acc -= P(rows [r0, r0 + 16), 16 panel columns) * B, P staged in LDS
+template <int LD>
 __device__ inline void mma_panel(MTile& acc, const c64* __restrict__ P, int r0, const MTile& B, int lane) {
   const int i = r0 + (lane & 15);
   double ar[4], ai[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const c64 a = P[((lane >> 4) + 4 * v) * kPanLd + i];
+    const c64 a = P[((lane >> 4) + 4 * v) * LD + i];
     ar[v] = -a.re;
     ai[v] = -a.im;
   }
@@ -225,7 +224,8 @@ __global__ void __launch_bounds__(256) k_sweep_up(const SweepCell* __restrict__ 
                                                   const int64_t* __restrict__ up_dst,
                                                   c64* __restrict__ Fv, int64_t ldF, c64* __restrict__ Tv,
                                                   int64_t ldT, c64* __restrict__ Fp, int64_t ldFp) {
-  __shared__ c64 Pan[2][16 * kPanLd];
+  constexpr int LD = pan_ld<NB>();
+  __shared__ c64 Pan[2][16 * LD];
   __shared__ c64 Dg[2][256];
   int q, grp;
   sweep_unit(n_groups, q, grp);
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_sweep_up(const SweepCell* __restrict__ 
   PanelRegs pr;
   const int bp = 16 * nb;   // rows of the forward panels, padding included
   panel_fetch(pr, L, b, 16, bp, 0, Di, tid);
-  panel_store(pr, Pan[0], Dg[0], 16, bp, tid);
+  panel_store<LD>(pr, Pan[0], Dg[0], 16, bp, tid);
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < 2 * NB; ++s) {
@@ -299,10 +299,10 @@ __global__ void __launch_bounds__(256) k_sweep_up(const SweepCell* __restrict__ 
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
             const bool upd = fwd ? (i > kk && i < nb) : (i < kk);
-            if (upd) mma_panel(X[i], Pan[buf], 16 * i, X[kk], lane);
+            if (upd) mma_panel<LD>(X[i], Pan[buf], 16 * i, X[kk], lane);
           }
         }
-      if (more) panel_store(pr, Pan[buf ^ 1], Dg[buf ^ 1], (sn < nb) ? 16 * sn + 16 : 0,
+      if (more) panel_store<LD>(pr, Pan[buf ^ 1], Dg[buf ^ 1], (sn < nb) ? 16 * sn + 16 : 0,
                             (sn < nb) ? bp : 16 * (2 * nb - 1 - sn), tid);
       __syncthreads();
     }
