@@ -262,7 +262,7 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         log("CPU oracle baseline")
-        cpu = cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf)
+        cpu = cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf, root_level=1)
 
     out = {
         "metric": "factor s + per-RHS solve us at N=262k, learned/mixed vs plain FP64 @1e-6 rel err",
@@ -923,42 +923,81 @@ def _oracle_worker_ready(_):
     return True
 
 
-def _oracle_cells(args):
-    """The oracle's upward-step work of some leaf cells, one BLAS thread."""
+def _oracle_level(args):
+    """The oracle's upward-step work of some cells of one level, one BLAS
+    thread: (level, [(seconds, ranks) per cell])."""
     from threadpoolctl import threadpool_limits
     from oracle import fds as ofds
-    nodes, lam, mu, rho, omega, tol, leaf, cells = args
+    nodes, lam, mu, rho, omega, tol, leaf, lev, k, cells = args
     with threadpool_limits(1):
-        ofds.leaf_sample([nodes], lam, mu, rho, omega, tol, leaf, cells)
-    return len(cells)
+        return lev, ofds.level_sample([nodes], lam, mu, rho, omega, tol, leaf, lev, k, cells)
 
 
-def cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf, per_core=6):
-    """Time the CPU oracle on a bounded sample of the same workload: the
-    upward-step work (leaf block, proxy and near interaction matrices, four
-    pivoted-QR IDs, LU / X / S / A~) of per_core evenly spaced leaf cells of
-    the full tree per host core, the cells split over one worker process per
-    core (at most 16), one BLAS thread each; the wall time of the pool is
-    extrapolated to all leaves."""
+def _oracle_root(args):
+    """The oracle's root step (assembly and LU of the compressed system), one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fds as ofds
+    nodes, lam, mu, rho, omega, leaf, l0, k = args
+    with threadpool_limits(1):
+        return ofds.root_sample([nodes], lam, mu, rho, omega, leaf, l0, k)
+
+
+def cpu_baseline(nodes, lam, mu, rho, omega, tol, leaf, root_level=1, leaf_per_core=2, per_level=2):
+    """Whole-factorisation estimate of the CPU oracle on the host cores, from
+    a bounded sample of the same workload:
+    * leaf level: leaf_per_core evenly spaced leaf cells per worker (leaf
+      block, proxy and near matrices, four pivoted-QR IDs, LU / X / S / A~);
+    * every level above: per_level evenly spaced cells with stand-in
+      skeletons (evenly spaced nodes of each child) of the leaf samples'
+      mean rank per component, the same per-cell work on the merged block;
+    * the root: assembly and LU of the compressed system of that rank.
+    One worker process per host core (at most 16), one BLAS thread each;
+    the projection runs a level's cells on all workers, ceil(cells /
+    workers) rounds of that level's mean per-cell time, and the root on
+    one core ("serial_seconds": every cell on one core).  Stand-in sets
+    spread over a cell need more rank than real skeletons once cells grow
+    large, so their rank is held at the leaf value."""
+    import math
     import multiprocessing as mp
     P = max(1, min(16, len(os.sched_getaffinity(0))))
-    n_leaves = 1
-    while leaf * n_leaves < len(nodes):
-        n_leaves *= 2
-    n_sample = P * per_core
-    sample = [int(i) for i in np.linspace(0, n_leaves - 1, n_sample)]
-    jobs = [(nodes, lam, mu, rho, omega, tol, leaf, sample[i::P]) for i in range(P)]
+    L = 0
+    while leaf * 2 ** L < len(nodes):
+        L += 1
+    l0 = min(root_level, L)
+    args = (nodes, lam, mu, rho, omega, tol, leaf)
+    per_cell = {}
+    t_start = time.perf_counter()
     with mp.get_context("spawn").Pool(P) as pool:
         pool.map(_oracle_worker_ready, range(P))
-        t0 = time.perf_counter()
-        done = sum(pool.map(_oracle_cells, jobs, chunksize=1))
-        dt = time.perf_counter() - t0
-    assert done == n_sample
-    return {"value": round(dt / n_sample * n_leaves, 2), "unit": "s", "cores": P, "kind": "oracle",
-            "sample": f"{n_sample} of {n_leaves} leaf cells of the same tree ({per_core} per core): leaf block, "
-                      f"proxy+near matrices, 4 pivoted-QR IDs, LU/X/S/A~ per cell, {P} worker processes with one "
-                      f"BLAS thread each, {dt:.1f} s wall, extrapolated linearly to all leaves (leaf level only: "
-                      f"a lower bound on the oracle's factor time)"}
+        n_leaf = P * leaf_per_core
+        leaf_cells = [int(i) for i in np.linspace(0, 2 ** L - 1, n_leaf)]
+        res = [r for _, rr in pool.map(_oracle_level, [(*args, L, 0, leaf_cells[i::P]) for i in range(P)],
+                                       chunksize=1) for r in rr]
+        per_cell[L] = [t for t, _ in res]
+        k = int(round(np.mean([kk for _, ks in res for kk in ks])))
+        jobs = []
+        for lev in range(L - 1, l0, -1):
+            cells = sorted({int(i) for i in np.linspace(0, 2 ** lev - 1, min(per_level, 2 ** lev))})
+            jobs += [(*args, lev, k, [c]) for c in cells]
+        root = pool.apply_async(_oracle_root, ((nodes, lam, mu, rho, omega, leaf, l0, k),))
+        for lev, rr in pool.map(_oracle_level, jobs, chunksize=1):
+            per_cell.setdefault(lev, []).extend(t for t, _ in rr)
+        t_root, n_root = root.get()
+    wall = time.perf_counter() - t_start
+    proj = {lev: math.ceil(2 ** lev / P) * float(np.mean(v)) for lev, v in per_cell.items()}
+    serial = sum(2 ** lev * float(np.mean(v)) for lev, v in per_cell.items()) + t_root
+    value = sum(proj.values()) + t_root
+    n_cells = sum(len(v) for v in per_cell.values())
+    return {"value": round(value, 2), "unit": "s", "cores": P, "kind": "oracle",
+            "sample": f"whole factorisation projected from {n_cells} sampled cells and the root ({wall:.1f} s wall): "
+                      f"{n_leaf} of {2 ** L} leaf cells ({leaf_per_core} per worker) and {per_level} cells of each "
+                      f"of levels {l0 + 1}..{L - 1} with stand-in skeletons of the leaf samples' mean rank {k} "
+                      f"per component (leaf block or merged block, proxy and near matrices, four pivoted-QR IDs, "
+                      f"LU / X / S / A~ per cell), root of order {n_root} (assembly + LU); per level, ceil(cells / "
+                      f"{P}) rounds of the mean per-cell time on {P} worker processes with one BLAS thread each",
+            "serial_seconds": round(serial, 1),
+            "level_seconds": {str(lev): round(v, 3) for lev, v in sorted(proj.items())},
+            "root_seconds": round(t_root, 3)}
 
 
 if __name__ == "__main__":

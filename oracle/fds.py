@@ -356,6 +356,66 @@ def leaf_sample(curves, lam, mu, rho, omega, tol, leaf, sample):
     return out
 
 
+def _stand_in_sets(perm, cells, lev, L, k):
+    """Active DOFs of every level-lev cell for the timing samples: at the
+    leaves all of the cell's DOFs; above them, per component, k evenly
+    spaced nodes of each child's node range, ordered as the rearrangement
+    orders skeletons (child a, child b, component by component).  They have
+    the sizes of skeletons of rank k, not their positions."""
+    out = []
+    for c in level_cells(cells, lev):
+        if lev == L:
+            nodes = perm[c.lo:c.hi]
+            c.rows = np.concatenate([2 * nodes, 2 * nodes + 1])
+        else:
+            a, b = cells[2 * c.index + 1], cells[2 * c.index + 2]
+            pick = [perm[ch.lo + (np.arange(min(k, ch.hi - ch.lo)) * (ch.hi - ch.lo)) // max(1, min(k, ch.hi - ch.lo))]
+                    for ch in (a, b)]
+            c.rows = np.concatenate([2 * pick[0], 2 * pick[1], 2 * pick[0] + 1, 2 * pick[1] + 1])
+        c.cols = c.rows.copy()
+        out.append(c)
+    return out
+
+
+def level_sample(curves, lam, mu, rho, omega, tol, leaf, lev, k, sample):
+    """Timing sample of one level of the factorisation: every level-lev cell
+    gets the stand-in active DOFs of _stand_in_sets (rank k above the
+    leaves), then each sampled cell's diagonal block is assembled and
+    compress_cell runs on it (the work of one cell of the upward loop,
+    Section 7.3 step 3).  Returns a list of (seconds, ranks) per sampled
+    cell; only the timing and the sizes are meaningful."""
+    import time
+    mat = Material(lam, mu, rho, omega)
+    bnd = Boundary(curves)
+    L, cells, perm = build_tree(bnd, leaf)
+    cs = _stand_in_sets(perm, cells, lev, L, k)
+    out = []
+    for q in sample:
+        c = cs[q]
+        t0 = time.perf_counter()
+        c.A = entries(bnd, c.rows, c.cols, mat)
+        cell_disk(bnd, c)
+        compress_cell(bnd, mat, tol, c, [o for o in cs if o is not c])
+        out.append((time.perf_counter() - t0, c.k))
+    return out
+
+
+def root_sample(curves, lam, mu, rho, omega, leaf, root_level, k):
+    """Timing sample of the root step (Section 7.3 step 4): the compressed
+    system of the level-root_level cells with stand-in skeletons of rank k
+    assembled and LU-factored.  Returns (seconds, order)."""
+    import time
+    mat = Material(lam, mu, rho, omega)
+    bnd = Boundary(curves)
+    L, cells, perm = build_tree(bnd, leaf)
+    top = _stand_in_sets(perm, cells, min(root_level, L), L, k)
+    rows = np.concatenate([c.rows for c in top])
+    cols = np.concatenate([c.cols for c in top])
+    t0 = time.perf_counter()
+    sla.lu_factor(entries(bnd, rows, cols, mat))
+    return time.perf_counter() - t0, len(rows)
+
+
 # ---------------------------------------------------------------- factor
 class FDS:
     """Factorisation of the Galerkin system; ``solve`` applies it."""

@@ -130,3 +130,21 @@ def test_tree_of_one_curve_is_the_midpoint_tree():
     bnd = galerkin.Boundary([sy.ellipse(1000, 1.0, 0.5)])
     L, cells, perm = _check_tree(bnd, 64)
     assert np.array_equal(perm, np.arange(1000))
+
+
+def test_timing_samples_do_the_factorisation_work():
+    """The CPU baseline's timing samples: at the leaf level the stand-in
+    active sets are the real ones, so a sampled leaf cell gets the ranks of
+    the same cell in a full factorisation; above it the sets have the
+    stand-in rank per component and child (sizes only); the root sample
+    factors a system of the top cells' stand-in order."""
+    nodes = sy.ellipse(256, 1.0, 0.5)
+    F = fds.FDS([nodes], 2.0, 1.0, 1.0, 4.0, 1e-8, leaf=32)
+    leaves = fds.level_cells(F.cells, F.L)
+    got = fds.level_sample([nodes], 2.0, 1.0, 1.0, 4.0, 1e-8, 32, F.L, 0, [0, 5, 7])
+    assert [k for _, k in got] == [leaves[q].k for q in (0, 5, 7)]
+    assert all(t > 0 for t, _ in got)
+    up = fds.level_sample([nodes], 2.0, 1.0, 1.0, 4.0, 1e-8, 32, F.L - 1, 8, [3])
+    assert 0 < up[0][1][0] <= 16 and 0 < up[0][1][1] <= 16
+    t, n = fds.root_sample([nodes], 2.0, 1.0, 1.0, 4.0, 32, 1, 8)
+    assert n == 2 * 2 * 2 * 8 and t > 0
