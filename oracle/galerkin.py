@@ -150,12 +150,12 @@ def element_pairs(PA: Polygon, ea, PB: Polygon, fb, mat: Material, chunk: int = 
     if np.any(regular):
         idx = np.nonzero(regular)[0]
         delta = segment_distance(PA.p0[ea[idx]], PA.p1[ea[idx]], PB.p0[fb[idx]], PB.p1[fb[idx]])
-        hmax = np.maximum(PA.h[ea[idx]], PB.h[fb[idx]])
-        qs = qr.regular_order(delta, hmax, mat.kT)
-        for q in np.unique(qs):
-            jj = idx[qs == q]
-            u, v, w = qr.tensor_rule(int(q))
-            step = max(1, chunk * 16 // (q * q))
+        qe, qf = qr.regular_orders(delta, PA.h[ea[idx]], PB.h[fb[idx]], mat.kT)
+        code = qe * 100 + qf
+        for c in np.unique(code):
+            jj = idx[code == c]
+            u, v, w = qr.tensor_rule(int(c // 100), int(c % 100))
+            step = max(1, chunk * 16 // len(w))
             for c0 in range(0, len(jj), step):
                 ii = jj[c0:c0 + step]
                 e_, f_ = ea[ii], fb[ii]

@@ -7,13 +7,18 @@ with v in [0,1]); every rule returns reference points (u, v) and weights that
 already contain the reference Jacobians (the physical weight is w h_e h_f):
 
 * regular pair (different elements that share no vertex): tensor
-  Gauss-Legendre with Q points per element, Q chosen from the gap
-  delta = dist(e, f) relative to h = max(h_e, h_f):
-  delta >= FAR_RATIO h -> Q_FAR, delta >= NEAR_RATIO h -> Q_MID, else Q_NEAR;
-  and from the oscillation of the kernels over an element: at least Q_MID
-  points when k_T h > KH_Q4 and Q_NEAR when k_T h > KH_Q6 (k_T the larger
-  wavenumber; Q_NEAR holds to about k_T h = 8, beyond which the mesh does
-  not resolve the wave).
+  Gauss-Legendre with q_e points along the test element and q_f along the
+  trial element, each element's order chosen from the gap delta = dist(e, f)
+  relative to that element's own length h:
+  delta >= RATIO_Q2 h -> 2, >= RATIO_Q3 h -> 3, >= FAR_RATIO h -> Q_FAR,
+  >= NEAR_RATIO h -> Q_MID, else Q_NEAR; and from the oscillation of the
+  kernels over the element (k_T the larger wavenumber): at least 3 points
+  when k_T h > KH_Q2, Q_FAR when k_T h > KH_Q3, Q_MID when k_T h > KH_Q4 and
+  Q_NEAR when k_T h > KH_Q6 (Q_NEAR holds to about k_T h = 8, beyond which
+  the mesh does not resolve the wave).  When either element needs Q_NEAR,
+  both take it.  (A q-point Gauss rule along an element of length h at
+  distance delta from the singularity converges like (h / 4 delta)^(2q); a
+  factor oscillating with wavenumber k adds a term like (k h)^(2q)/(2q)!.)
 * coincident pair (e == f): the square is split along its diagonal; on each
   triangle the offset d = |u - v| is mapped as d = s^P_COINC and s is
   integrated with Q_COINC Gauss points, the position along the diagonal with
@@ -36,8 +41,12 @@ import numpy as np
 Q_FAR = 4
 Q_MID = 6
 Q_NEAR = 10
+RATIO_Q2 = 512.0
+RATIO_Q3 = 32.0
 FAR_RATIO = 8.0
 NEAR_RATIO = 2.0
+KH_Q2 = 0.004
+KH_Q3 = 0.02
 KH_Q4 = 0.5
 KH_Q6 = 2.5
 KH_MAX = 5.0
@@ -58,11 +67,15 @@ def gauss01(q: int):
 
 
 @functools.lru_cache(maxsize=None)
-def tensor_rule(q: int):
-    g, w = gauss01(q)
-    u = np.repeat(g, q)
-    v = np.tile(g, q)
-    ww = np.repeat(w, q) * np.tile(w, q)
+def tensor_rule(qe: int, qf: int = None):
+    """Points (u, v) and weights of the tensor Gauss rule with qe points
+    along the test element (u) and qf along the trial element (v)."""
+    qf = qe if qf is None else qf
+    ge, we = gauss01(qe)
+    gf, wf = gauss01(qf)
+    u = np.repeat(ge, qf)
+    v = np.tile(gf, qe)
+    ww = np.repeat(we, qf) * np.tile(wf, qe)
     return u, v, ww
 
 
@@ -106,14 +119,31 @@ def adjacent_rule(q: int = Q_ADJ, p: int = P_ADJ):
     return np.concatenate([u1, u2]), np.concatenate([v1, v2]), np.concatenate([w, w])
 
 
-def regular_order(delta, h, k):
-    """Tensor order for a regular pair with gap delta, longer element h and
-    largest wavenumber k."""
-    delta = np.asarray(delta)
+def element_order(delta, h, k):
+    """Gauss points along one element of a regular pair: gap delta, the
+    element's own length h, largest wavenumber k."""
+    delta = np.asarray(delta, dtype=np.float64)
     h = np.broadcast_to(np.asarray(h, dtype=np.float64), delta.shape)
     q = np.full(delta.shape, Q_NEAR, dtype=np.int64)
     q[delta >= NEAR_RATIO * h] = Q_MID
     q[delta >= FAR_RATIO * h] = Q_FAR
-    q[(k * h > KH_Q4) & (q < Q_MID)] = Q_MID
-    q[k * h > KH_Q6] = Q_NEAR
+    q[delta >= RATIO_Q3 * h] = 3
+    q[delta >= RATIO_Q2 * h] = 2
+    kh = k * h
+    q[(kh > KH_Q2) & (q < 3)] = 3
+    q[(kh > KH_Q3) & (q < Q_FAR)] = Q_FAR
+    q[(kh > KH_Q4) & (q < Q_MID)] = Q_MID
+    q[kh > KH_Q6] = Q_NEAR
     return q
+
+
+def regular_orders(delta, he, hf, k):
+    """Orders (q_e, q_f) of the tensor rule of regular pairs with gap delta,
+    element lengths he (test) and hf (trial) and largest wavenumber k; both
+    Q_NEAR when either element needs it."""
+    qe = element_order(delta, he, k)
+    qf = element_order(delta, hf, k)
+    near = (qe == Q_NEAR) | (qf == Q_NEAR)
+    qe[near] = Q_NEAR
+    qf[near] = Q_NEAR
+    return qe, qf

@@ -13,9 +13,9 @@ largest entry:
 * adjacent pairs: distances from the shared vertex, a tensor product of two
   such graded rules (24 panels of 20 points each; the 1/r corner
   singularity);
-* regular pairs (4, 6 and 10 points per element, chosen by the gap, the
-  element length and the wavenumber): each element cut into panels with 20
-  points each;
+* regular pairs (2, 3, 4, 6 or 10 points along each element, chosen by the
+  gap, that element's length and the wavenumber): each element cut into
+  panels with 20 points each;
 * proxy pairs (a cell's proxy polygon against its own elements, both
   orientations): as regular pairs;
 * load vectors: 40-point Gauss per element.
@@ -126,17 +126,17 @@ def _oracle_pair(PA, e, PB, f, mat):
 
 
 def _regular_classes(P, e, mat, span=60):
-    """The first pair (smallest gap) of each regular quadrature order, with
-    trial elements e + 2 ... e + span and two far ones."""
+    """The first pair (smallest gap) of each regular tensor order (q_e, q_f),
+    with trial elements e + 2 ... e + span and three far ones."""
     n = P.n
     picks = {}
-    for j in list(range(2, min(span, n - 2))) + [n // 4, n // 2]:
+    for j in list(range(2, min(span, n - 2))) + [n // 8, n // 4, n // 2]:
         f = (e + j) % n
         if f in ((e - 1) % n, e, (e + 1) % n):
             continue
         d = galerkin.segment_distance(P.p0[e], P.p1[e], P.p0[f], P.p1[f])
-        q = int(qr.regular_order(np.array([d]), max(P.h[e], P.h[f]), mat.kT)[0])
-        picks.setdefault(q, f)
+        qe, qf = qr.regular_orders(np.array([d]), P.h[e], P.h[f], mat.kT)
+        picks.setdefault((int(qe[0]), int(qf[0])), f)
     return picks
 
 
@@ -177,7 +177,11 @@ def test_regular_pairs_each_order(workload):
         for q, f in _regular_classes(P, e, mat).items():
             seen.add(q)
             assert _rel(_oracle_pair(P, e, P, f, mat), ref_regular(P, e, P, f, mat)) < TOL, (name, e, f, q)
-    assert 4 in seen or mat.kT * P.h.max() > qr.KH_Q4
+    kh = mat.kT * P.h.max()
+    if kh <= qr.KH_Q2:
+        assert {(2, 2), (3, 3), (4, 4), (6, 6)} <= seen, (name, seen)
+    elif kh <= qr.KH_Q3:
+        assert {(3, 3), (4, 4), (6, 6)} <= seen and (2, 2) not in seen, (name, seen)
 
 
 def test_proxy_pairs_both_orientations(workload):
@@ -255,6 +259,33 @@ def test_frequency_rule_is_needed():
     ref = ref_adjacent(P, e, P, e + 1, mat, True)
     assert _rel(lo, ref) > 1e-9
     assert _rel(_oracle_pair(P, e, P, e + 1, mat), ref) < TOL
+
+
+def test_low_orders_need_their_limits():
+    """The 2- and 3-point rules hold only far away and at small k_T h: on the
+    tripod at omega = 14.5 (k_T h = 0.018) a pair 480 elements apart is off
+    by more than 1e-11 on 2 x 2 points (the oscillation over an element),
+    and on the ellipse a pair 16 elements apart is off by more than 1e-12 on
+    3 x 3 points (the gap); the oracle's choices for both are within 1e-11."""
+    P = Polygon(sy.tripod(6400), +1)
+    mat = Material(1.0, 1.0, 1.0, 14.5)
+    e, f = 0, 480
+    assert qr.KH_Q2 < mat.kT * max(P.h[e], P.h[f]) <= qr.KH_Q3
+    ref = ref_regular(P, e, P, f, mat)
+    assert _rel(_tensor_pair(P, e, P, f, mat, 2, 2), ref) > 1e-11
+    assert _rel(_oracle_pair(P, e, P, f, mat), ref) < TOL
+    P = Polygon(sy.ellipse(131072, 1.0, 0.5), +1)
+    mat = Material(2.0, 1.0, 1.0, 4.0)
+    e, f = 0, 16
+    ref = ref_regular(P, e, P, f, mat)
+    assert _rel(_tensor_pair(P, e, P, f, mat, 3, 3), ref) > 1e-12
+    assert _rel(_oracle_pair(P, e, P, f, mat), ref) < TOL
+
+
+def _tensor_pair(P, e, Q, f, mat, qe, qf):
+    u, v, w = qr.tensor_rule(qe, qf)
+    dvec = (P.p0[e] - Q.p0[f])[None, :] + u[:, None] * (P.p1[e] - P.p0[e]) - v[:, None] * (Q.p1[f] - Q.p0[f])
+    return _one(P, e, Q, f, u, v, w, dvec, mat)
 
 
 # ------------------------------------------------------------------ small case
