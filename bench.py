@@ -18,7 +18,7 @@ Prints one JSON line.  ``value`` is the factorisation time in seconds
 (lower is better); ``per_rhs_us`` the batched per-RHS solve time;
 ``accuracy`` the largest error over the 180 solutions against the
 tolerance-1e-12 factor and a sampled residual of the exact Galerkin
-system; ``roofline`` the far-pair integrator against the FP64 peak and
+system; ``roofline`` the dominant pair-integration kernel against the FP64 peak and
 ``roofline_solve`` the batched solve against the FP64 matrix peak;
 ``cpu_baseline`` the CPU oracle on a bounded sample.  Sections beside the
 headline (each with a --no-... switch): the listed tolerance 1e-8, the
@@ -141,24 +141,26 @@ def main():
         del Fref
         acc = accuracy(torch.cat([x1.reshape(1, -1), xr], 0), Xref, Arows, rows, rhs)
 
-    # roofline of the dominant kernel: the far-pair integrator (tensor Gauss,
-    # 4 points per element).  Algorithmic work: FLOP_PER_EVAL per quadrature
-    # point; time from HIP events around its launches inside the library.
+    # roofline of the dominant kernel: the pair-integration kernel with the
+    # most GPU time (in practice a regular-pair kernel, one thread per pair).
+    # Algorithmic work: FLOP_PER_EVAL per quadrature point; time from HIP
+    # events around each of its launches inside the library.
     cls_s = st["class_seconds"]
     cls_e = st["class_evals"]
-    cls_n = st["class_launches"]
-    dom = int(np.argmax(cls_s))
-    names = ["far_pairs_q4", "mid_pairs_q6", "near_pairs_q10", "coincident", "adjacent_next", "adjacent_prev"]
-    achieved = FLOP_PER_EVAL * cls_e[dom] / cls_s[dom] / 1e12 if cls_s[dom] > 0 else 0.0
-    # HBM bytes per launch of the far-pair integrator from the two counter
-    # runs in profiles/far_pairs_q4_ellipse131072_hbm_counters.md: FETCH_SIZE
-    # 117220 KiB x 2.0 and WRITE_SIZE 934406 KiB x 1.0 per dispatch (the
-    # factors are what a plain 1 GiB copy reads on the same counters)
-    traffic = (117220 * 2.0 + 934406 * 1.0) * 1024 if names[dom] == "far_pairs_q4" else None
-    roofline = {"bound": "alu", "kernel": f"k_regular/k_special ({names[dom]})", "achieved": round(achieved, 3),
+    ker_s = st["pair_kernel_seconds"]
+    ker_e = st["pair_kernel_evals"]
+    ker_n = st["pair_kernel_launches"]
+    dom = int(np.argmax(ker_s))
+    kname = fds.PAIR_KERNELS[dom]
+    achieved = FLOP_PER_EVAL * ker_e[dom] / ker_s[dom] / 1e12 if ker_s[dom] > 0 else 0.0
+    # HBM bytes per launch of that kernel from two counter runs (FETCH_SIZE,
+    # then WRITE_SIZE), each scaled by what the counter reads for a plain
+    # 1 GiB copy (2.0 and 1.0): profiles/pair_kernels_ellipse131072_hbm_counters.md
+    traffic = TRAFFIC_PER_LAUNCH.get(kname)
+    roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
                 "peak": 78.6, "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": traffic,
-                "flop_per_eval": FLOP_PER_EVAL, "evals": int(cls_e[dom]), "launches": int(cls_n[dom]),
-                "avg_launch_ms": round(1e3 * cls_s[dom] / max(1, cls_n[dom]), 3)}
+                "flop_per_eval": FLOP_PER_EVAL, "evals": int(ker_e[dom]), "launches": int(ker_n[dom]),
+                "avg_launch_ms": round(1e3 * ker_s[dom] / max(1, ker_n[dom]), 3)}
 
     # roofline of the batched solve (179 right-hand sides at once): its
     # algorithmic flops (every cell's LU solve, W g, A~ y and X z, and the
@@ -297,6 +299,7 @@ def main():
         "accuracy": acc,
         "class_seconds": [round(x, 5) for x in cls_s],
         "class_evals": [int(x) for x in cls_e],
+        "pair_kernels": {n: [round(t, 5), int(e)] for n, t, e in zip(fds.PAIR_KERNELS, ker_s, ker_e) if e},
         "batched_graph_form": batched,
         "listed_tol_1e-8": tol8,
         "mixed_form": mixed,
@@ -320,6 +323,9 @@ def main():
 # the assembly: Hankel functions at k_T r and k_L r plus the tensor algebra
 # of the four 2x2 kernel blocks and their accumulation)
 FLOP_PER_EVAL = 500
+# HBM bytes per launch of the dominant pair kernel, from the counter runs
+# recorded in profiles/ (None where not measured for the current code)
+TRAFFIC_PER_LAUNCH = {}
 
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")

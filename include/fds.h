@@ -234,11 +234,13 @@ typedef struct {
   double root_seconds;      /* GPU time of the root LU */
   int64_t factor_bytes;     /* device bytes held by the factor */
   int64_t kernel_evals;     /* quadrature-point kernel evaluations during the build */
-  /* per quadrature class of element pairs: 0/1/2 tensor Gauss with 4/6/10
-   * points per element, 3 coincident, 4/5 adjacent (two orientations) */
-  double class_seconds[6];  /* GPU time of that class's integration kernel, summed over launches */
+  /* per quadrature class of element pairs: 0 regular pairs with 2, 3 or 4
+   * Gauss points on the test element (and 2, 3, 4 or 6 on the trial
+   * element), 1 regular pairs with 6 on the test element, 2 the 10-point
+   * pairs, 3 coincident, 4/5 adjacent (two orientations) */
+  double class_seconds[6];  /* GPU time of that class's integration kernels, summed over launches */
   int64_t class_evals[6];   /* kernel evaluations (quadrature points) of that class */
-  int64_t class_launches[6];
+  int64_t class_launches[6];  /* assembly batches in which the class had pairs */
   /* mixed form, last solve: refinement steps taken, and the largest column
    * values of ||f - A_c x|| / ||f|| and ||delta|| / ||x|| at exit */
   int32_t precision;
@@ -261,6 +263,14 @@ typedef struct {
   int32_t tune_chunk[4];
   int32_t tune_gemm_cols[4];
   double tune_seconds;
+  /* the twelve pair-integration kernels of an assembly batch, in launch
+   * order: regular pairs with 2, 3, 4, 6 points on the test element (each
+   * general, then series-only), 10-point pairs, coincident, adjacent next,
+   * adjacent previous: GPU time summed over launches, quadrature points,
+   * launches that had pairs */
+  double pair_kernel_seconds[12];
+  int64_t pair_kernel_evals[12];
+  int64_t pair_kernel_launches[12];
 } fds_stats;
 
 int fds_get_stats(fds_factor f, fds_stats* s);

@@ -63,7 +63,14 @@ class _Stats(ctypes.Structure):
                 ("cells_compressed", ctypes.c_int64), ("cells_sketched", ctypes.c_int64),
                 ("cells_fallback_rank", ctypes.c_int64), ("cells_fallback_judge", ctypes.c_int64),
                 ("predict_seconds", ctypes.c_double), ("tune_chunk", ctypes.c_int32 * 4),
-                ("tune_gemm_cols", ctypes.c_int32 * 4), ("tune_seconds", ctypes.c_double)]
+                ("tune_gemm_cols", ctypes.c_int32 * 4), ("tune_seconds", ctypes.c_double),
+                ("pair_kernel_seconds", ctypes.c_double * 12), ("pair_kernel_evals", ctypes.c_int64 * 12),
+                ("pair_kernel_launches", ctypes.c_int64 * 12)]
+
+# the pair-integration kernels in the order of fds_stats.pair_kernel_*
+PAIR_KERNELS = ["k_regular<0, false>", "k_regular<0, true>", "k_regular<1, false>", "k_regular<1, true>",
+                "k_regular<2, false>", "k_regular<2, true>", "k_regular<3, false>", "k_regular<3, true>",
+                "k_regular_wave10", "k_special<1>", "k_special2<2>", "k_special2<3>"]
 
 
 class _RankRecord(ctypes.Structure):

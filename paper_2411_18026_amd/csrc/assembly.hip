@@ -21,10 +21,12 @@
 //
 // Pipeline for a batch of dense blocks ("jobs"):
 //   k_classify   every (row element, column element) pair of every job is
-//                put into one of six lists: tensor Gauss with 4, 6 or 10
-//                points per element chosen by the gap / element-length
-//                ratio, coincident, adjacent (two orientations);
-//   k_regular<Q> one thread per regular pair (4 and 6 points);
+//                put into a list by its quadrature class: regular pairs by
+//                the tensor orders (2, 3, 4 or 6 points along each element,
+//                chosen by the gap over that element's length and by k_T h)
+//                and whether they stay on the small-argument series; the
+//                10-point pairs; coincident; adjacent (two orientations);
+//   k_regular<OE,SER> one thread per regular pair with the test order OE;
 //   k_regular_wave10 one wavefront per 10-point pair;
 //   k_special<C>, k_special2<C>
 //                one wavefront per singular pair (the 80 or 288 points of
@@ -184,6 +186,22 @@ __device__ inline double seg_seg_dist(const Elem& e, const Elem& f) {
   return d;
 }
 
+// Index into the regular orders (0..kNumOrd-1 for 2, 3, 4, 6 points) of one
+// element of a regular pair with gap d, or kNumOrd for 10 points.
+__device__ inline int elem_order_index(double d, double h, double kT) {
+  int o = kNumOrd;
+  if (d >= kNearRatio * h) o = 3;
+  if (d >= kFarRatio * h) o = 2;
+  if (d >= kRatioQ3 * h) o = 1;
+  if (d >= kRatioQ2 * h) o = 0;
+  const double kh = kT * h;
+  if (kh > kKhQ2 && o < 1) o = 1;
+  if (kh > kKhQ3 && o < 2) o = 2;
+  if (kh > kKhQ4 && o < 3) o = 3;
+  if (kh > kKhQ6) o = kNumOrd;
+  return o;
+}
+
 __device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf, double kT) {
   if (e.poly == f.poly) {
     if (ge == gf) return kCoinc;
@@ -192,16 +210,8 @@ __device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf
     if (f.idx == (e.idx + n - 1) % n) return kAdjPrev;
   }
   const double d = seg_seg_dist(e, f);
-  const double hm = fmax(e.h, f.h);
-  const double kh = kT * hm;
-  if (kh > kKhQ6) return kQ10;
-  int c;
-  if (d >= kFarRatio * hm && kh <= kKhQ4)
-    c = kQ4;
-  else if (d >= kNearRatio * hm)
-    c = kQ6;
-  else
-    return kQ10;
+  const int oe = elem_order_index(d, e.h, kT), of = elem_order_index(d, f.h, kT);
+  if (oe == kNumOrd || of == kNumOrd) return kQ10;
   // the largest distance between two points of the elements is an endpoint distance
   double dm2 = 0.0;
   {
@@ -210,8 +220,7 @@ __device__ inline int classify_pair(const Elem& e, const Elem& f, int ge, int gf
 #pragma unroll
     for (int k = 0; k < 4; ++k) dm2 = fmax(dm2, p[k][0] * p[k][0] + p[k][1] * p[k][1]);
   }
-  if (kT * sqrt(dm2) < kSeriesOnly) c = (c == kQ4) ? kQ4S : kQ6S;
-  return c;
+  return reg_class(oe, of, kT * sqrt(dm2) < kSeriesOnly ? 1 : 0);
 }
 
 // ------------------------------------------------------------------ geometry
@@ -284,63 +293,47 @@ __global__ void k_proxy_elems(const double* __restrict__ crd, const int* __restr
 }
 
 // ------------------------------------------------------------------ classify
-// Each block takes a tile of up to kClsTile pairs (4 per thread); list slots
-// are reserved with one atomic per class per block.
+// Each block takes a tile of up to kClsTile pairs (4 per thread).  Slots are
+// counted per class with LDS atomics and reserved with one global atomic per
+// class per block; the order of a list does not matter (each pair's result
+// goes to its own slot).
 constexpr int kClsTile = 1024;
 
 __global__ void __launch_bounds__(256) k_classify(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
                                                   const int* __restrict__ elist, const Elem* __restrict__ elems,
                                                   unsigned long long* __restrict__ lists, int64_t list_cap,
                                                   unsigned int* __restrict__ counters, double kT) {
-  __shared__ unsigned int s_wcnt[4][kNumClass];
-  __shared__ unsigned int s_base[4][kNumClass];
+  __shared__ unsigned int s_cnt[kNumClass];
+  __shared__ unsigned int s_base[kNumClass];
   const Tile t = tiles[blockIdx.x];
   const Job jb = jobs[t.job];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = threadIdx.x; c < kNumClass; c += blockDim.x) s_cnt[c] = 0;
+  __syncthreads();
   int cls[4];
   unsigned int off[4];
-  unsigned int run[kNumClass];
-#pragma unroll
-  for (int c = 0; c < kNumClass; ++c) run[c] = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int li = j * 256 + threadIdx.x;
     cls[j] = -1;
+    off[j] = 0;
     if (li < t.count) {
       const int64_t p = t.start + li;
       int ie, je;
       pair_elems(jb, p, ie, je);
       const int ge = elist[jb.re_off + ie], gf = elist[jb.ce_off + je];
       cls[j] = classify_pair(elems[ge], elems[gf], ge, gf, kT);
-    }
-    off[j] = 0;
-#pragma unroll
-    for (int c = 0; c < kNumClass; ++c) {
-      const unsigned long long mask = __ballot(cls[j] == c);
-      if (cls[j] == c) off[j] = run[c] + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-      run[c] += (unsigned)__popcll(mask);
+      off[j] = atomicAdd(&s_cnt[cls[j]], 1u);
     }
   }
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < kNumClass; ++c) s_wcnt[wid][c] = run[c];
   __syncthreads();
-  if (threadIdx.x < kNumClass) {
-    const int c = threadIdx.x;
-    const unsigned tot = s_wcnt[0][c] + s_wcnt[1][c] + s_wcnt[2][c] + s_wcnt[3][c];
-    unsigned b = tot ? atomicAdd(&counters[c], tot) : 0u;
-    for (int w = 0; w < 4; ++w) {
-      s_base[w][c] = b;
-      b += s_wcnt[w][c];
-    }
-  }
+  for (int c = threadIdx.x; c < kNumClass; c += blockDim.x) s_base[c] = s_cnt[c] ? atomicAdd(&counters[c], s_cnt[c]) : 0u;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (cls[j] < 0) continue;
     const int64_t p = t.start + j * 256 + threadIdx.x;
     const unsigned long long key = ((unsigned long long)(unsigned)t.job << 32) | (unsigned long long)p;
-    const int64_t slot = (int64_t)s_base[wid][cls[j]] + off[j];
+    const int64_t slot = (int64_t)s_base[cls[j]] + off[j];
     if (slot < list_cap) lists[cls[j] * list_cap + slot] = key;
   }
 }
@@ -356,17 +349,27 @@ __device__ inline void decode(unsigned long long key, const Job* jobs, const int
 }
 
 // ------------------------------------------------------------------ regular pairs
-template <int Q, bool SER>
-__device__ inline void regular_pair(unsigned long long key, const Job* __restrict__ jobs, const int* __restrict__ elist,
-                                    const Elem* __restrict__ elems, const MatConst& m, c64* __restrict__ res,
-                                    int64_t np) {
+__device__ inline const double* gauss_points(int q) {
+  return q == 2 ? c_quad.g2 : (q == 3 ? c_quad.g3 : (q == 4 ? c_quad.g4 : c_quad.g6));
+}
+__device__ inline const double* gauss_weights(int q) {
+  return q == 2 ? c_quad.w2 : (q == 3 ? c_quad.w3 : (q == 4 ? c_quad.w4 : c_quad.w6));
+}
+
+// QE points along the test element (compile time), qf along the trial element
+template <int QE, bool SER>
+__device__ inline void regular_pair(unsigned long long key, int qf, const Job* __restrict__ jobs,
+                                    const int* __restrict__ elist, const Elem* __restrict__ elems, const MatConst& m,
+                                    c64* __restrict__ res, int64_t np) {
   Job jb;
   int ie, je, ge, gf;
   decode(key, jobs, elist, jb, ie, je, ge, gf);
   const Elem e = elems[ge];
   const Elem f = elems[gf];
-  const double* g = (Q == 4) ? c_quad.g4 : (Q == 6 ? c_quad.g6 : c_quad.g10);
-  const double* wq = (Q == 4) ? c_quad.w4 : (Q == 6 ? c_quad.w6 : c_quad.w10);
+  const double* ge_ = gauss_points(QE);
+  const double* we_ = gauss_weights(QE);
+  const double* gf_ = gauss_points(qf);
+  const double* wf_ = gauss_weights(qf);
   PairRes A;
 #pragma unroll
   for (int k = 0; k < 16; ++k) A.R[k] = cmk(0.0, 0.0);
@@ -374,14 +377,14 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
   const double ax = e.x1 - e.x0, ay = e.y1 - e.y0;
   const double bx = f.x1 - f.x0, by = f.y1 - f.y0;
   const double hh = e.h * f.h;
-  for (int i = 0; i < Q; ++i) {
-    const double u = g[i];
-    const double wu = wq[i] * hh;
-    for (int j = 0; j < Q; ++j) {
-      const double v = g[j];
+  for (int i = 0; i < QE; ++i) {
+    const double u = ge_[i];
+    const double wu = we_[i] * hh;
+    for (int j = 0; j < qf; ++j) {
+      const double v = gf_[j];
       const double dx = ox + u * ax - v * bx;
       const double dy = oy + u * ay - v * by;
-      acc_point_direct<SER>(m, dx, dy, wu * wq[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
+      acc_point_direct<SER>(m, dx, dy, wu * wf_[j], u, v, e.nx, e.ny, f.nx, f.ny, e.dN0, e.dN1, f.dN0, f.dN1, A);
     }
   }
   pair_entries(A);
@@ -390,17 +393,33 @@ __device__ inline void regular_pair(unsigned long long key, const Job* __restric
   for (int k = 0; k < 16; ++k) res[k * np + slot] = A.R[k];
 }
 
-// grid-stride over the class list; its length is read on the device.  Two
-// wavefronts per SIMD: the register budget is 256 per lane.  SER: the
-// series-only lists (no Bessel-function code, no call, fewer registers).
-template <int Q, bool SER>
+// The regular pairs with order index OE on the test element, one thread per
+// pair: the kNumOrd lists of that test order (one per trial order) taken in
+// sequence by a grid-stride loop, so neighbouring lanes mostly share their
+// trial order.  List lengths are read on the device.  Two wavefronts per
+// SIMD: the register budget is 256 per lane.  SER: the series-only lists
+// (no Bessel-function code, no call).
+template <int OE, bool SER>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_regular(const unsigned long long* __restrict__ list, const unsigned int* __restrict__ count_ptr,
+k_regular(const unsigned long long* __restrict__ lists, int64_t cap, const unsigned int* __restrict__ counts,
           const Job* __restrict__ jobs, const int* __restrict__ elist, const Elem* __restrict__ elems, MatConst m,
           c64* __restrict__ res, int64_t np) {
-  const int64_t count = min((int64_t)*count_ptr, np);
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-    regular_pair<Q, SER>(list[t], jobs, elist, elems, m, res, np);
+  int64_t cnt[kNumOrd], total = 0;
+#pragma unroll
+  for (int of = 0; of < kNumOrd; ++of) {
+    cnt[of] = min((int64_t)counts[reg_class(OE, of, SER ? 1 : 0)], cap);
+    total += cnt[of];
+  }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int of = 0;
+    int64_t i = t;
+    while (of < kNumOrd - 1 && i >= cnt[of]) {
+      i -= cnt[of];
+      ++of;
+    }
+    const unsigned long long key = lists[(int64_t)reg_class(OE, of, SER ? 1 : 0) * cap + i];
+    regular_pair<order_of(OE), SER>(key, order_of(of), jobs, elist, elems, m, res, np);
+  }
 }
 
 // 10-point pairs: one wavefront per pair (the 100 points of the tensor rule
@@ -691,30 +710,37 @@ int classify_tile_size() { return kClsTile; }
 void launch_pairs(const unsigned long long* lists, int64_t cap, const unsigned int* counts, const Job* jobs,
                   const int* elist, const Elem* elems, const MatConst& m, c64* res, int64_t np, hipStream_t s,
                   hipEvent_t* ev) {
-  // ev (optional): kNumClass + 1 events bracketing the class launches in
-  // the order of the class index
+  // ev (optional): kNumPairLaunches + 1 events bracketing the launches in order
   auto mark = [&](int i) {
     if (ev) FDS_HIP(hipEventRecord(ev[i], s));
   };
   const unsigned greg = (unsigned)std::min<int64_t>((np + 127) / 128, 4096);
   const unsigned gspc = (unsigned)std::min<int64_t>((np + 3) / 4, 2048);
   mark(0);
-  k_regular<4, false><<<greg, 128, 0, s>>>(lists + kQ4 * cap, counts + kQ4, jobs, elist, elems, m, res, np);
+  k_regular<0, false><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(1);
-  k_regular<6, false><<<greg, 128, 0, s>>>(lists + kQ6 * cap, counts + kQ6, jobs, elist, elems, m, res, np);
+  k_regular<0, true><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(2);
-  k_regular_wave10<<<gspc, 256, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
+  k_regular<1, false><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(3);
-  k_special<kCoinc><<<gspc, 256, 0, s>>>(lists + kCoinc * cap, counts + kCoinc, jobs, elist, elems, m, res, np);
+  k_regular<1, true><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(4);
-  k_special2<kAdjNext><<<gspc, 256, 0, s>>>(lists + kAdjNext * cap, counts + kAdjNext, jobs, elist, elems, m, res, np);
+  k_regular<2, false><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(5);
-  k_special2<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
+  k_regular<2, true><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(6);
-  k_regular<4, true><<<greg, 128, 0, s>>>(lists + kQ4S * cap, counts + kQ4S, jobs, elist, elems, m, res, np);
+  k_regular<3, false><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(7);
-  k_regular<6, true><<<greg, 128, 0, s>>>(lists + kQ6S * cap, counts + kQ6S, jobs, elist, elems, m, res, np);
+  k_regular<3, true><<<greg, 128, 0, s>>>(lists, cap, counts, jobs, elist, elems, m, res, np);
   mark(8);
+  k_regular_wave10<<<gspc, 256, 0, s>>>(lists + kQ10 * cap, counts + kQ10, jobs, elist, elems, m, res, np);
+  mark(9);
+  k_special<kCoinc><<<gspc, 256, 0, s>>>(lists + kCoinc * cap, counts + kCoinc, jobs, elist, elems, m, res, np);
+  mark(10);
+  k_special2<kAdjNext><<<gspc, 256, 0, s>>>(lists + kAdjNext * cap, counts + kAdjNext, jobs, elist, elems, m, res, np);
+  mark(11);
+  k_special2<kAdjPrev><<<gspc, 256, 0, s>>>(lists + kAdjPrev * cap, counts + kAdjPrev, jobs, elist, elems, m, res, np);
+  mark(12);
   FDS_HIP(hipGetLastError());
 }
 

@@ -45,6 +45,13 @@ struct BlockReq {
 
 class Workspace;
 
+// Pair-integration launches of a batch, in order: k_regular for test
+// orders 2, 3, 4, 6 (each general, then series-only), the 10-point pairs,
+// coincident, adjacent next, adjacent previous; and the reported class of
+// each (fds_stats).
+constexpr int kNumPairLaunches = 12;
+constexpr int launch_public_class(int li) { return li < 6 ? 0 : (li < 8 ? 1 : li - 6); }
+
 // Timing and work counts of the assembly launches.  Events and the device
 // class counters of every batch are recorded without synchronising;
 // ``resolve`` (after the stream has been synchronised) turns them into
@@ -57,8 +64,13 @@ struct AssemblyStats {
   double class_seconds[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
   int64_t class_evals[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
   int64_t class_launches[kNumPublicClass] = {0, 0, 0, 0, 0, 0};
+  // per pair-integration kernel (launch order)
+  double kernel_seconds[kNumPairLaunches] = {};
+  int64_t kernel_evals[kNumPairLaunches] = {};
+  int64_t kernel_launches[kNumPairLaunches] = {};
   unsigned int* d_counts = nullptr;       // kMaxBatches x kNumClass device counters
-  std::vector<std::vector<hipEvent_t>> pending;   // per batch: start, kNumClass + 1 class marks, end
+  std::vector<std::vector<hipEvent_t>> pending;   // per batch: start, kNumPairLaunches + 1 marks, end
+  hipEvent_t event();   // from a per-device pool of resolved events (creating one is slow)
   void resolve(hipStream_t s);
   ~AssemblyStats();
 };

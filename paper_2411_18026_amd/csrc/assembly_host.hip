@@ -2,6 +2,8 @@
 // dense block requests into classify / pair / gather launches.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "assembly.hpp"
@@ -101,6 +103,8 @@ static void adjacent_rule(int Q, int P, double* au, double* av, double* aw) {
 
 QuadTables make_quad_tables() {
   QuadTables q{};
+  gauss_legendre01(2, q.g2, q.w2);
+  gauss_legendre01(3, q.g3, q.w3);
   gauss_legendre01(4, q.g4, q.w4);
   gauss_legendre01(6, q.g6, q.w6);
   gauss_legendre01(10, q.g10, q.w10);
@@ -112,8 +116,39 @@ QuadTables make_quad_tables() {
   return q;
 }
 
-static const int kPointsPerClass[kNumClass] = {16, 36, 100, kNCoincPts, kNAdjPts, kNAdjPts, 16, 36};
-constexpr int kBatchEvents = kNumClass + 3;   // start, kNumClass + 1 class marks, end
+// quadrature points per pair and reported class of each list
+static int points_of_class(int c) {
+  if (c == kQ10) return 100;
+  if (c == kCoinc) return kNCoincPts;
+  if (c == kAdjNext || c == kAdjPrev) return kNAdjPts;
+  const int r = (c - kRegBase) / 2;
+  return order_of(r / kNumOrd) * order_of(r % kNumOrd);
+}
+static int public_class_of(int c) {
+  if (c < kRegBase) return 2 + c;
+  return ((c - kRegBase) / 2) / kNumOrd == kNumOrd - 1 ? 1 : 0;
+}
+// the launch (in launch_pairs' order) that integrates a list
+static int launch_of_class(int c) {
+  if (c < kRegBase) return 8 + c;
+  const int r = c - kRegBase;
+  return 2 * ((r / 2) / kNumOrd) + (r % 2);
+}
+constexpr int kBatchEvents = kNumPairLaunches + 3;   // start, kNumPairLaunches + 1 marks, end
+
+// resolved events of the current device, kept for later batches
+static std::mutex g_ev_mu;
+static std::map<int, std::vector<hipEvent_t>> g_ev_spare;
+static void give_back(const std::vector<hipEvent_t>& ev) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_ev_mu);
+  auto& v = g_ev_spare[dev];
+  v.insert(v.end(), ev.begin(), ev.end());
+}
 
 void AssemblyStats::resolve(hipStream_t s) {
   if (pending.empty()) return;
@@ -125,17 +160,27 @@ void AssemblyStats::resolve(hipStream_t s) {
     float ms = 0.f;
     FDS_HIP(hipEventElapsedTime(&ms, ev[0], ev[kBatchEvents - 1]));
     seconds += 1e-3 * ms;
+    bool busy[kNumPublicClass] = {}, lbusy[kNumPairLaunches] = {};
     for (int c = 0; c < kNumClass; ++c) {
       const unsigned n = cnt[b * kNumClass + c];
-      const int pc = public_class(c);
-      evals += (int64_t)n * kPointsPerClass[c];
-      class_evals[pc] += (int64_t)n * kPointsPerClass[c];
-      if (n) class_launches[pc] += 1;
-      float cm = 0.f;
-      FDS_HIP(hipEventElapsedTime(&cm, ev[1 + c], ev[2 + c]));
-      class_seconds[pc] += 1e-3 * cm;
+      const int pc = public_class_of(c), li = launch_of_class(c);
+      const int64_t e = (int64_t)n * points_of_class(c);
+      evals += e;
+      class_evals[pc] += e;
+      kernel_evals[li] += e;
+      busy[pc] = busy[pc] || n;
+      lbusy[li] = lbusy[li] || n;
     }
-    for (auto e : ev) (void)hipEventDestroy(e);
+    for (int li = 0; li < kNumPairLaunches; ++li) {
+      float cm = 0.f;
+      FDS_HIP(hipEventElapsedTime(&cm, ev[1 + li], ev[2 + li]));
+      class_seconds[launch_public_class(li)] += 1e-3 * cm;
+      kernel_seconds[li] += 1e-3 * cm;
+      if (lbusy[li]) kernel_launches[li] += 1;
+    }
+    for (int pc = 0; pc < kNumPublicClass; ++pc)
+      if (busy[pc]) class_launches[pc] += 1;
+    give_back(ev);
   }
   pending.clear();
 }
@@ -143,6 +188,23 @@ void AssemblyStats::resolve(hipStream_t s) {
 AssemblyStats::~AssemblyStats() {
   for (auto& ev : pending)
     for (auto e : ev) (void)hipEventDestroy(e);
+}
+
+hipEvent_t AssemblyStats::event() {
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    auto& v = g_ev_spare[dev];
+    if (!v.empty()) {
+      const hipEvent_t e = v.back();
+      v.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e;
+  FDS_HIP(hipEventCreate(&e));
+  return e;
 }
 
 void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, const MatConst& m, c64* d_out,
@@ -192,31 +254,46 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
       ot_off[k + 1] = ot_off[k] + (noj + 255) / 256;
       pair_off += npj;
     }
-    std::vector<int> elist((size_t)e_off[nb]), pos((size_t)p_off[nb]);
-    std::vector<Dof> dofs((size_t)d_off[nb]);
-    std::vector<Tile> ptiles((size_t)pt_off[nb]), otiles((size_t)ot_off[nb]);
+    // the batch's tables, packed straight into pinned host memory and sent
+    // in one copy: jobs, element lists, positions, DOFs, pair tiles, entry tiles
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_jobs = 0, o_elist = al(nb * sizeof(Job)), o_pos = o_elist + al((size_t)e_off[nb] * sizeof(int)),
+                 o_dofs = o_pos + al((size_t)std::max<int64_t>(p_off[nb], 1) * sizeof(int)),
+                 o_pt = o_dofs + al((size_t)d_off[nb] * sizeof(Dof)),
+                 o_ot = o_pt + al((size_t)pt_off[nb] * sizeof(Tile)),
+                 tot = o_ot + al((size_t)ot_off[nb] * sizeof(Tile));
+    char* hb = static_cast<char*>(ws.pinned(tot));
+    int* elist = reinterpret_cast<int*>(hb + o_elist);
+    int* pos = reinterpret_cast<int*>(hb + o_pos);
+    Dof* dofs = reinterpret_cast<Dof*>(hb + o_dofs);
+    Tile* ptiles = reinterpret_cast<Tile*>(hb + o_pt);
+    Tile* otiles = reinterpret_cast<Tile*>(hb + o_ot);
+    std::copy(jobs.begin(), jobs.end(), reinterpret_cast<Job*>(hb + o_jobs));
+    pos[0] = 0;
     parallel_for((int)nb, [&](int k) {
       const BlockReq& q = reqs[i0 + k];
       const Job& j = jobs[k];
-      std::copy(q.rows.elems.begin(), q.rows.elems.end(), elist.begin() + j.re_off);
-      std::copy(q.cols.elems.begin(), q.cols.elems.end(), elist.begin() + j.ce_off);
-      std::copy(q.rows.dofs.begin(), q.rows.dofs.end(), dofs.begin() + j.rd_off);
-      std::copy(q.cols.dofs.begin(), q.cols.dofs.end(), dofs.begin() + j.cd_off);
-      std::copy(q.rpos.begin(), q.rpos.end(), pos.begin() + p_off[k]);
-      std::copy(q.cpos.begin(), q.cpos.end(), pos.begin() + p_off[k] + q.rpos.size());
+      std::copy(q.rows.elems.begin(), q.rows.elems.end(), elist + j.re_off);
+      std::copy(q.cols.elems.begin(), q.cols.elems.end(), elist + j.ce_off);
+      std::copy(q.rows.dofs.begin(), q.rows.dofs.end(), dofs + j.rd_off);
+      std::copy(q.cols.dofs.begin(), q.cols.dofs.end(), dofs + j.cd_off);
+      std::copy(q.rpos.begin(), q.rpos.end(), pos + p_off[k]);
+      std::copy(q.cpos.begin(), q.cpos.end(), pos + p_off[k] + q.rpos.size());
       const int64_t npj = (int64_t)j.nre * j.nce, noj = (int64_t)j.nrd * j.ncd;
       int64_t t = pt_off[k];
       for (int64_t a = 0; a < npj; a += ct) ptiles[t++] = Tile{(int)k, (int)std::min<int64_t>(ct, npj - a), a};
       t = ot_off[k];
       for (int64_t a = 0; a < noj; a += 256) otiles[t++] = Tile{(int)k, (int)std::min<int64_t>(256, noj - a), a};
     });
-    if (pos.empty()) pos.push_back(0);
-    Job* d_jobs = ws.upload("asm_jobs", jobs);
-    int* d_elist = ws.upload("asm_elist", elist);
-    int* d_pos = ws.upload("asm_pos", pos);
-    Dof* d_dofs = ws.upload("asm_dofs", dofs);
-    Tile* d_pt = ws.upload("asm_ptiles", ptiles);
-    Tile* d_ot = ws.upload("asm_otiles", otiles);
+    char* db = ws.get<char>("asm_tables", tot);
+    ws.pinned_upload(db, tot);
+    Job* d_jobs = reinterpret_cast<Job*>(db + o_jobs);
+    int* d_elist = reinterpret_cast<int*>(db + o_elist);
+    int* d_pos = reinterpret_cast<int*>(db + o_pos);
+    Dof* d_dofs = reinterpret_cast<Dof*>(db + o_dofs);
+    Tile* d_pt = reinterpret_cast<Tile*>(db + o_pt);
+    Tile* d_ot = reinterpret_cast<Tile*>(db + o_ot);
+    const size_t n_ptiles = (size_t)pt_off[nb], n_otiles = (size_t)ot_off[nb];
     unsigned long long* d_lists = ws.get<unsigned long long>("asm_lists", (size_t)kNumClass * np);
     c64* d_res = ws.get<c64>("asm_res", (size_t)16 * np);
     unsigned int* d_cnt;
@@ -226,15 +303,15 @@ void assemble_blocks(const std::vector<BlockReq>& reqs, const Elem* d_elems, con
         st->d_counts = ws.get<unsigned int>("asm_counts", (size_t)AssemblyStats::kMaxBatches * kNumClass);
       d_cnt = st->d_counts + st->pending.size() * kNumClass;
       ev.resize(kBatchEvents);
-      for (auto& e : ev) FDS_HIP(hipEventCreate(&e));
+      for (auto& e : ev) e = st->event();
     } else {
       d_cnt = ws.get<unsigned int>("asm_cnt_tmp", kNumClass);
     }
     FDS_HIP(hipMemsetAsync(d_cnt, 0, kNumClass * sizeof(unsigned), s));
     if (!ev.empty()) FDS_HIP(hipEventRecord(ev[0], s));
-    launch_classify(d_pt, (int)ptiles.size(), d_jobs, d_elist, d_elems, d_lists, np, d_cnt, m.kT, s);
+    launch_classify(d_pt, (int)n_ptiles, d_jobs, d_elist, d_elems, d_lists, np, d_cnt, m.kT, s);
     launch_pairs(d_lists, np, d_cnt, d_jobs, d_elist, d_elems, m, d_res, np, s, ev.empty() ? nullptr : ev.data() + 1);
-    launch_gather(d_ot, (int)otiles.size(), d_jobs, d_dofs, d_pos, d_res, np, d_out, s);
+    launch_gather(d_ot, (int)n_otiles, d_jobs, d_dofs, d_pos, d_res, np, d_out, s);
     if (!ev.empty()) {
       FDS_HIP(hipEventRecord(ev[kBatchEvents - 1], s));
       st->pending.push_back(ev);

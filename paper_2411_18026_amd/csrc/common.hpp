@@ -80,24 +80,23 @@ struct Tile {
   int64_t start;
 };
 
-// Element-pair classes.  kQ4S and kQ6S hold the 4- and 6-point pairs whose
-// kernels stay on their small-argument series at every point (k_T times the
-// largest distance between the two elements below kSeriesOnly): the same
-// arithmetic as kQ4 / kQ6, in a kernel without the Bessel-function code
-// (fewer registers).  They are reported with kQ4 and kQ6.
-enum PairClass : int {
-  kQ4 = 0,
-  kQ6 = 1,
-  kQ10 = 2,
-  kCoinc = 3,
-  kAdjNext = 4,
-  kAdjPrev = 5,
-  kQ4S = 6,
-  kQ6S = 7,
-  kNumClass = 8
-};
+// Element-pair classes.  A regular pair (no shared vertex) is integrated
+// by a tensor Gauss rule with kOrders[oe] points along the test element and
+// kOrders[of] along the trial element, each order chosen from the gap and
+// that element's own length (elem_order_index); a pair is "series-only"
+// (ser = 1) when its kernels stay on their small-argument series at every
+// point (k_T times the largest distance between the two elements below
+// kSeriesOnly): the same arithmetic in a kernel without the Bessel-function
+// code.  Pairs that need 10 points on an element take 10 on both.
+constexpr int kNumOrd = 4;
+__host__ __device__ constexpr int order_of(int o) { return o == 0 ? 2 : (o == 1 ? 3 : (o == 2 ? 4 : 6)); }
+enum PairClass : int { kQ10 = 0, kCoinc = 1, kAdjNext = 2, kAdjPrev = 3, kRegBase = 4 };
+constexpr int kNumClass = kRegBase + 2 * kNumOrd * kNumOrd;
+__host__ __device__ constexpr int reg_class(int oe, int of, int ser) { return kRegBase + (oe * kNumOrd + of) * 2 + ser; }
+// Reported classes (fds_stats): 0 regular pairs with at most 4 points on the
+// test element, 1 regular pairs with 6, 2 the 10-point pairs, 3 coincident,
+// 4 and 5 adjacent (shared vertex at the end / the start of the test element).
 constexpr int kNumPublicClass = 6;
-__host__ __device__ constexpr int public_class(int c) { return c == kQ4S ? kQ4 : (c == kQ6S ? kQ6 : c); }
 // a pair is series-only when k_T d_max < kSeriesOnly (d_max the largest
 // endpoint distance, which bounds every point distance); the margin below
 // the series switch (1) keeps rounding from deciding the class
@@ -111,13 +110,19 @@ constexpr int kQAdj = 12;
 constexpr int kPAdj = 4;
 constexpr int kNCoincPts = 4 * kQCoinc;
 constexpr int kNAdjPts = 2 * kQAdj * kQAdj;
+// Gauss points along one element of a regular pair, by the gap d over the
+// element's length h: 2 from kRatioQ2, 3 from kRatioQ3, 4 from kFarRatio, 6
+// from kNearRatio, else 10.  Orders grow with the oscillation of the kernels
+// over the element: at least 3 points when k_T h > kKhQ2, 4 when
+// k_T h > kKhQ3, 6 when k_T h > kKhQ4 and 10 when k_T h > kKhQ6.  A singular
+// pair takes the longer rules below when k_T h > kKhQ4 (h the longer
+// element).  Boundary elements need k_T h <= kKhMax.
+constexpr double kRatioQ2 = 512.0;
+constexpr double kRatioQ3 = 32.0;
 constexpr double kFarRatio = 8.0;
 constexpr double kNearRatio = 2.0;
-// Orders grow with the oscillation of the kernels over an element: a
-// regular pair takes at least 6 points per element when k_T h > kKhQ4 and
-// 10 when k_T h > kKhQ6 (h the longer element); a singular pair takes the
-// longer rules below when k_T h > kKhQ4.  Boundary elements need
-// k_T h <= kKhMax.
+constexpr double kKhQ2 = 0.004;
+constexpr double kKhQ3 = 0.02;
 constexpr double kKhQ4 = 0.5;
 constexpr double kKhQ6 = 2.5;
 constexpr double kKhMax = 5.0;
@@ -155,7 +160,7 @@ __device__ inline double wsum_full(double v) {
 }
 
 struct QuadTables {
-  double g4[4], w4[4], g6[6], w6[6], g10[10], w10[10];
+  double g2[2], w2[2], g3[3], w3[3], g4[4], w4[4], g6[6], w6[6], g10[10], w10[10];
   double cu[kNCoincPts], cv[kNCoincPts], cw[kNCoincPts], coff[kNCoincPts];
   double au[kNAdjPts], av[kNAdjPts], aw[kNAdjPts];
   double rg[6], rw[6];   // load-vector rule

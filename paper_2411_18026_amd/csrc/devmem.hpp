@@ -129,6 +129,13 @@ class Workspace {
   ~Workspace() {
     for (auto& kv : bufs_)
       if (kv.second.p) cache_free(kv.second.p, alloc_stream());
+    for (Pinned& b : pin_) {
+      if (b.ev) {
+        if (b.pending) (void)hipEventSynchronize(b.ev);
+        (void)hipEventDestroy(b.ev);
+      }
+      if (b.p) (void)hipHostFree(b.p);
+    }
   }
   void set_stream(hipStream_t s) { s_ = s; }
   hipStream_t stream() const { return s_; }
@@ -163,6 +170,36 @@ class Workspace {
     return p;
   }
 
+  // Pinned host staging for uploads, two slots used in turn: pinned(bytes)
+  // returns the next slot (waiting for the copies of its previous contents,
+  // two uploads back, to complete), the caller fills it, and
+  // pinned_upload(dst, bytes) enqueues one copy of it to dst on the
+  // workspace stream.  A copy from pinned memory does not hold the host.
+  void* pinned(size_t bytes) {
+    pin_cur_ ^= 1;
+    Pinned& b = pin_[pin_cur_];
+    if (b.pending) {
+      FDS_HIP(hipEventSynchronize(b.ev));
+      b.pending = false;
+    }
+    if (b.bytes < bytes) {
+      if (b.p) FDS_HIP(hipHostFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+      const size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
+      FDS_HIP(hipHostMalloc(&b.p, nb, hipHostMallocDefault));
+      b.bytes = nb;
+    }
+    if (!b.ev) FDS_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    return b.p;
+  }
+  void pinned_upload(void* dst, size_t bytes) {
+    Pinned& b = pin_[pin_cur_];
+    if (bytes) FDS_HIP(hipMemcpyAsync(dst, b.p, bytes, hipMemcpyHostToDevice, s_));
+    FDS_HIP(hipEventRecord(b.ev, s_));
+    b.pending = true;
+  }
+
   size_t bytes() const {
     size_t t = 0;
     for (auto& kv : bufs_) t += kv.second.bytes;
@@ -174,7 +211,15 @@ class Workspace {
     void* p = nullptr;
     size_t bytes = 0;
   };
+  struct Pinned {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
   std::map<std::string, Buf> bufs_;
+  Pinned pin_[2];
+  int pin_cur_ = 0;
   hipStream_t s_;
 };
 

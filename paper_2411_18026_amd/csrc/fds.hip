@@ -460,9 +460,9 @@ static void layout_blocks(CellLevel& lv) {
 }
 
 // Host wall-time of the factorisation's phases (printed when FDS_TIMING is set).
-static double g_host_t[8];
-static const char* g_host_name[8] = {"disks+near", "interaction requests", "device waits", "parent merge",
-                                     "leaf blocks", "root", "solve plan", "other"};
+static double g_host_t[9];
+static const char* g_host_name[9] = {"disks+near", "interaction requests", "device waits", "parent merge",
+                                     "leaf blocks", "root", "solve plan", "other", "  of which packing+launch"};
 struct HostTimer {
   int k;
   std::chrono::steady_clock::time_point t0;
@@ -1176,6 +1176,7 @@ static void compress_level(Factor& F, int lev) {
       a.rs = 1;
       a.cs = mv_m[q];
     });
+    HostTimer hp(8);
     assemble_blocks(reqs, F.DG.elems.p, F.m, MV, ws, &F.ast);
   }
   {
@@ -1189,6 +1190,7 @@ static void compress_level(Factor& F, int lev) {
       a.rs = mu_m[q];   // transposed storage
       a.cs = 1;
     });
+    HostTimer hp(8);
     assemble_blocks(reqs, F.DG.elems.p, F.m, MU, ws, &F.ast);
   }
 
@@ -1489,6 +1491,7 @@ static void factor_root(Factor& F) {
 static void prepare_mfma_sweeps(Factor& F) {
   hipStream_t s = F.stream;
   Workspace& ws = F.ws;
+  std::vector<DevBuf<c64>> retired;   // the replaced V blocks, released after one wait at the end
   for (int lev = F.L; lev > F.l0; --lev) {
     CellLevel& lv = F.levels[lev];
     int rmax = 0;
@@ -1543,7 +1546,7 @@ static void prepare_mfma_sweeps(Factor& F) {
       for (auto& g : gd) nmax = std::max(nmax, g.n);
       launch_gemm(ws.upload("w_desc", gd), ws.upload("w_tiles", gt), (int)gt.size(), nmax, 0, lv.At.p, lv.V.p, W.p,
                   0, s);
-      FDS_HIP(hipStreamSynchronize(s));   // the old V goes back to the cache now
+      retired.push_back(std::move(lv.V));
       lv.V = std::move(W);
     }
     // fewer columns than a slab: the LU-solve kernel, then f~ = W g by GEMM
@@ -1570,6 +1573,7 @@ static void prepare_mfma_sweeps(Factor& F) {
     lv.nb_class = sweep_tile_class(lv.bmax);
     lv.nr_class = sweep_tile_class(std::max(rmax, 1));
   }
+  if (!retired.empty()) FDS_HIP(hipStreamSynchronize(s));
 }
 
 static void build_solve_plan(Factor& F) {
@@ -2224,7 +2228,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     }
     resolve_stats(*F);
     if (std::getenv("FDS_TIMING")) {
-      for (int k = 0; k < 8; ++k) std::fprintf(stderr, "[fds host] %-22s %8.2f ms\n", g_host_name[k], 1e3 * g_host_t[k]);
+      for (int k = 0; k < 9; ++k) std::fprintf(stderr, "[fds host] %-22s %8.2f ms\n", g_host_name[k], 1e3 * g_host_t[k]);
       std::fprintf(stderr, "[fds host] factor wall %8.2f ms\n", 1e3 * std::chrono::duration<double>(t1 - t0).count());
     }
     for (double& v : g_host_t) v = 0.0;
@@ -2247,6 +2251,11 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
       F->st.class_seconds[c] = F->ast.class_seconds[c];
       F->st.class_evals[c] = F->ast.class_evals[c];
       F->st.class_launches[c] = F->ast.class_launches[c];
+    }
+    for (int li = 0; li < kNumPairLaunches; ++li) {
+      F->st.pair_kernel_seconds[li] = F->ast.kernel_seconds[li];
+      F->st.pair_kernel_evals[li] = F->ast.kernel_evals[li];
+      F->st.pair_kernel_launches[li] = F->ast.kernel_launches[li];
     }
     *out = F;
     return FDS_OK;

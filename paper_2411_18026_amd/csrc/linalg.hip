@@ -149,14 +149,17 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, T
 // pivot rule and output layout as k_lu.  The panel (rows k0.., NB columns)
 // is factored in LDS; its row interchanges are then applied to the other
 // columns, U12 = L11^{-1} A12 is formed column by column, and the trailing
-// matrix gets one rank-NB update per panel.
-template <int NB, typename T>
-__global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ descs, T* __restrict__ base,
+// matrix gets one rank-NB update per panel.  TB threads per workgroup: 256
+// when a launch has a matrix per CU or more, 1024 for the few large
+// matrices of the upper levels (more wavefronts to hide the trailing
+// update's memory latency).
+template <int NB, typename T, int TB>
+__global__ void __launch_bounds__(TB) k_lu_blk(const LUDesc* __restrict__ descs, T* __restrict__ base,
                                                  int* __restrict__ piv, int* __restrict__ info) {
   extern __shared__ unsigned char smem_lu[];
   T* Pn = reinterpret_cast<T*>(smem_lu);   // panel, column-major with leading dimension ldp
-  __shared__ double sv[kBlk / 64];
-  __shared__ int si[kBlk / 64];
+  __shared__ double sv[TB / 64];
+  __shared__ int si[TB / 64];
   __shared__ int s_p;
   const LUDesc d = descs[blockIdx.x];
   T* A = base + d.a_off;
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
   int bad = 0;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = min(NB, n - k0), mp = n - k0;
-    for (int t = tid; t < mp * nb; t += kBlk) {
+    for (int t = tid; t < mp * nb; t += TB) {
       const int i = t % mp, c = t / mp;
       Pn[i + c * ldp] = A[(k0 + i) + (int64_t)(k0 + c) * lda];
     }
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
       // pivot: largest modulus in panel column j at rows >= j, lowest row on ties
       double best = -1.0;
       int bi = mp;
-      for (int i = j + tid; i < mp; i += kBlk) {
+      for (int i = j + tid; i < mp; i += TB) {
         const double v = abs2(Pn[i + j * ldp]);
         if (v > best) {
           best = v;
@@ -200,7 +203,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
       if (tid == 0) {
         double b = sv[0];
         int ib = si[0];
-        for (int w = 1; w < kBlk / 64; ++w)
+        for (int w = 1; w < TB / 64; ++w)
           if (sv[w] > b || (sv[w] == b && si[w] < ib)) {
             b = sv[w];
             ib = si[w];
@@ -219,19 +222,19 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
       __syncthreads();
       const T pj = Pn[j + j * ldp];
       const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
-      for (int i = j + 1 + tid; i < mp; i += kBlk) {
+      for (int i = j + 1 + tid; i < mp; i += TB) {
         const T l = Pn[i + j * ldp] * inv;
         Pn[i + j * ldp] = l;
         for (int c = j + 1; c < nb; ++c) Pn[i + c * ldp] -= l * Pn[j + c * ldp];
       }
       __syncthreads();
     }
-    for (int t = tid; t < mp * nb; t += kBlk) {
+    for (int t = tid; t < mp * nb; t += TB) {
       const int i = t % mp, c = t / mp;
       A[(k0 + i) + (int64_t)(k0 + c) * lda] = Pn[i + c * ldp];
     }
     // row interchanges of this panel on the columns outside it, one thread per column
-    for (int c = tid; c < n; c += kBlk) {
+    for (int c = tid; c < n; c += TB) {
       if (c >= k0 && c < k0 + nb) continue;
       T* col = A + (int64_t)c * lda;
       for (int j = 0; j < nb; ++j) {
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
     }
     __syncthreads();
     // U12 = L11^{-1} A12, one thread per column
-    for (int c = k0 + nb + tid; c < n; c += kBlk) {
+    for (int c = k0 + nb + tid; c < n; c += TB) {
       T* col = A + (int64_t)c * lda + k0;
       T x[NB];
 #pragma unroll
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_blk(const LUDesc* __restrict__ desc
     // A22 -= L21 U12
     const int m2 = n - k0 - nb;
     const int64_t tot = (int64_t)m2 * m2;
-    for (int64_t t = tid; t < tot; t += kBlk) {
+    for (int64_t t = tid; t < tot; t += TB) {
       const int i = (int)(t % m2), c = (int)(t / m2);
       const T* u = A + (int64_t)(k0 + nb + c) * lda + k0;
       T s = A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda];
@@ -1590,12 +1593,19 @@ void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, h
   if (n == 0) return;
   // panel of NB columns staged in LDS: nmax * NB * sizeof(T) <= 48 KiB
   const size_t row = (size_t)std::max(1, nmax) * sizeof(T);
-  if (row * 16 <= 49152)
-    k_lu_blk<16, T><<<n, kBlk, row * 16, s>>>(d, base, piv, info);
-  else if (row * 8 <= 49152)
-    k_lu_blk<8, T><<<n, kBlk, row * 8, s>>>(d, base, piv, info);
-  else if (row * 4 <= 49152)
-    k_lu_blk<4, T><<<n, kBlk, row * 4, s>>>(d, base, piv, info);
+  const bool wide = n >= 16 && n < 256 && nmax > 96;
+  if (row * 16 <= 49152) {
+    if (wide)
+      k_lu_blk<16, T, 1024><<<n, 1024, row * 16, s>>>(d, base, piv, info);
+    else
+      k_lu_blk<16, T, kBlk><<<n, kBlk, row * 16, s>>>(d, base, piv, info);
+  } else if (row * 8 <= 49152) {
+    if (wide)
+      k_lu_blk<8, T, 1024><<<n, 1024, row * 8, s>>>(d, base, piv, info);
+    else
+      k_lu_blk<8, T, kBlk><<<n, kBlk, row * 8, s>>>(d, base, piv, info);
+  } else if (row * 4 <= 49152)
+    k_lu_blk<4, T, kBlk><<<n, kBlk, row * 4, s>>>(d, base, piv, info);
   else
     k_lu<T><<<n, kBlk, 0, s>>>(d, base, piv, info);
   FDS_HIP(hipGetLastError());

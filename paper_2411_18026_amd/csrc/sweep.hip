@@ -79,23 +79,33 @@ __device__ inline void mma(MTile& acc, const c64* __restrict__ M, int64_t ld, in
 
 // ---------------------------------------------------------------- preparation
 // Composed row permutation of each cell's LU (row j swapped with piv[j],
-// j ascending): (P f)(i) = f(perm(i)).  One thread per cell.
-__global__ void k_compose_perm(const SweepCell* __restrict__ cells, int n_cells, const int* __restrict__ piv,
-                               int* __restrict__ perm) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+// j ascending): (P f)(i) = f(perm(i)).  One wavefront per cell: the
+// pivots into LDS, the swaps there by one lane, the result out by all.
+constexpr int kPermMax = 256;   // largest order of a matrix-core sweep cell
+
+__global__ void __launch_bounds__(64) k_compose_perm(const SweepCell* __restrict__ cells, int n_cells,
+                                                     const int* __restrict__ piv, int* __restrict__ perm) {
+  __shared__ int sp[kPermMax], sv[kPermMax];
+  const int q = blockIdx.x;
   if (q >= n_cells) return;
   const SweepCell c = cells[q];
-  int* p = perm + c.perm_off;
-  const int* pv = piv + c.piv_off;
-  for (int i = 0; i < c.b; ++i) p[i] = i;
-  for (int j = 0; j < c.b; ++j) {
-    const int k = pv[j];
-    if (k != j) {
-      const int t = p[j];
-      p[j] = p[k];
-      p[k] = t;
-    }
+  const int b = min(c.b, kPermMax);
+  for (int i = threadIdx.x; i < b; i += 64) {
+    sp[i] = i;
+    sv[i] = piv[c.piv_off + i];
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < b; ++j) {
+      const int k = sv[j];
+      if (k != j) {
+        const int t = sp[j];
+        sp[j] = sp[k];
+        sp[k] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < b; i += 64) perm[c.perm_off + i] = sp[i];
 }
 
 // Inverses of the 16 x 16 diagonal blocks of L (unit lower) and U (upper)
@@ -339,6 +349,174 @@ __global__ void __launch_bounds__(256) k_sweep_up(const SweepCell* __restrict__ 
   }
 }
 
+// Upward sweep of a level with few cells: a workgroup = one cell and one
+// 16-column slab, its four wavefronts splitting the 16-row tiles (tile i
+// belongs to wavefront i mod 4).  At step s the owner of tile k applies the
+// inverted diagonal block and publishes the result in LDS; every
+// wavefront then updates its own tiles below (forward) or above (backward)
+// with the staged panel.  f~ = W g afterwards from all tiles in LDS, the
+// rows j of W split the same way.  The same products in the same order as
+// k_sweep_up (bitwise the same results), four times the workgroups and a
+// quarter of the sequential tile products per step.
+template <int NB, int NR>
+__global__ void __launch_bounds__(256) k_sweep_up_rows(const SweepCell* __restrict__ cells, int n_cells, int n_slab,
+                                                       int ncol, const c64* __restrict__ A,
+                                                       const c64* __restrict__ Dinv, const int* __restrict__ perm,
+                                                       const c64* __restrict__ W, const int64_t* __restrict__ up_dst,
+                                                       c64* __restrict__ Fv, int64_t ldF, c64* __restrict__ Tv,
+                                                       int64_t ldT, c64* __restrict__ Fp, int64_t ldFp) {
+  static_assert(NB % 4 == 0 && NR % 4 == 0, "tiles are dealt to four wavefronts");
+  constexpr int LD = pan_ld<NB>();
+  constexpr int NT = NB / 4;
+  __shared__ c64 Pan[2][16 * LD];
+  __shared__ c64 Dg[2][256];
+  __shared__ double Xs[2][2][4][64];   // published tile: [buffer][re, im][v][lane]
+  static_assert(sizeof(Pan) >= (size_t)NB * 512 * sizeof(double), "all tiles fit in the panel buffers");
+  int q, slab;
+  sweep_unit(n_slab, q, slab);
+  if (q >= n_cells) return;   // the whole workgroup
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const SweepCell c = cells[q];
+  const int b = c.b, r = c.r, nb = (b + 15) / 16, nr = (r + 15) / 16;
+  const int col = slab * 16 + (lane & 15);
+  const bool cok = col < ncol;
+  const c64* L = A + c.a_off;
+  const c64* Di = Dinv + c.dinv_off;
+  const int* P = perm + c.perm_off;
+  // the wavefront's tiles i = 4 t + wv of f, in pivoted order
+  MTile X[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int i = 4 * t + wv;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = trow(16 * i, lane, v);
+      c64 f = cmk(0.0, 0.0);
+      if (i < nb && row < b && cok) f = Fv[c.f_off + P[row] + (int64_t)col * ldF];
+      X[t].re[v] = f.re;
+      X[t].im[v] = f.im;
+    }
+  }
+  PanelRegs pr;
+  const int bp = 16 * nb;
+  panel_fetch(pr, L, b, 16, bp, 0, Di, tid);
+  panel_store<LD>(pr, Pan[0], Dg[0], 16, bp, tid);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 2 * NB; ++s) {
+    if (s < 2 * nb) {
+      const int buf = s & 1;
+      const bool fwd = s < nb;
+      const int k = fwd ? s : 2 * nb - 1 - s;
+      const int sn = s + 1;
+      const bool more = sn < 2 * nb;
+      if (more) {
+        const bool fn = sn < nb;
+        const int kn = fn ? sn : 2 * nb - 1 - sn;
+        panel_fetch(pr, L, b, fn ? 16 * kn + 16 : 0, fn ? bp : 16 * kn, 16 * kn,
+                    Di + (int64_t)kn * 512 + (fn ? 0 : 256), tid);
+      }
+      // the owner of tile k: the diagonal block through its inverse, published
+      if ((k & 3) == wv) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (4 * t + wv == k) {
+            MTile out;
+            tile_zero(out);
+            double ar[4], ai[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const c64 a = Dg[buf][(lane & 15) + 16 * ((lane >> 4) + 4 * v)];
+              ar[v] = a.re;
+              ai[v] = a.im;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              out.re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[v], X[t].re[v], out.re, 0, 0, 0);
+              out.re = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[v], X[t].im[v], out.re, 0, 0, 0);
+              out.im = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[v], X[t].im[v], out.im, 0, 0, 0);
+              out.im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[v], X[t].re[v], out.im, 0, 0, 0);
+            }
+            X[t] = out;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              Xs[buf][0][v][lane] = out.re[v];
+              Xs[buf][1][v][lane] = out.im[v];
+            }
+          }
+      }
+      __syncthreads();
+      MTile B;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        B.re[v] = Xs[buf][0][v][lane];
+        B.im[v] = Xs[buf][1][v][lane];
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int i = 4 * t + wv;
+        const bool upd = fwd ? (i > k && i < nb) : (i < k);
+        if (upd) mma_panel<LD>(X[t], Pan[buf], 16 * i, B, lane);
+      }
+      if (more) panel_store<LD>(pr, Pan[buf ^ 1], Dg[buf ^ 1], (sn < nb) ? 16 * sn + 16 : 0,
+                                (sn < nb) ? bp : 16 * (2 * nb - 1 - sn), tid);
+      __syncthreads();
+    }
+  }
+  // g = A_i^{-1} f in place, each wavefront its tiles
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int i = 4 * t + wv;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = trow(16 * i, lane, v);
+      if (i < nb && row < b && cok) Fv[c.f_off + row + (int64_t)col * ldF] = cmk(X[t].re[v], X[t].im[v]);
+    }
+  }
+  if (r == 0) return;   // the whole workgroup
+  // every tile of g to LDS (the panel buffers are free), then f~ = W g with
+  // the rows j of W dealt to the wavefronts
+  double* Xa = reinterpret_cast<double*>(&Pan[0][0]);   // [tile][re, im][v][lane]
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int i = 4 * t + wv;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Xa[((i * 2 + 0) * 4 + v) * 64 + lane] = X[t].re[v];
+      Xa[((i * 2 + 1) * 4 + v) * 64 + lane] = X[t].im[v];
+    }
+  }
+  __syncthreads();
+  const int64_t* dst = up_dst + c.t_off;
+#pragma unroll
+  for (int jt = 0; jt < NR / 4; ++jt) {
+    const int j = 4 * jt + wv;
+    if (j >= nr) continue;
+    MTile Z;
+    tile_zero(Z);
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < nb) {
+        MTile G;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          G.re[v] = Xa[((k * 2 + 0) * 4 + v) * 64 + lane];
+          G.im[v] = Xa[((k * 2 + 1) * 4 + v) * 64 + lane];
+        }
+        mma<false>(Z, W + c.v_off, r, 16 * j, 16 * k, r, b, G, lane);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = trow(16 * j, lane, v);
+      if (row < r && cok) {
+        const c64 z = cmk(Z.re[v], Z.im[v]);
+        Tv[c.t_off + row + (int64_t)col * ldT] = z;
+        Fp[dst[row] + (int64_t)col * ldFp] = z;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- few right-hand sides
 // One to four right-hand sides (the first solve, sequential use): the
 // matrix-core tiles would be mostly empty, so one workgroup per cell runs
@@ -532,7 +710,7 @@ __global__ void __launch_bounds__(256) k_sweep_down_few(const SweepCell* __restr
 void launch_sweep_prepare(const SweepCell* cells, int n_cells, const int* blk_cell, const int* blk_k, int n_blk,
                           const int* piv, const c64* A, int* perm, c64* Dinv, hipStream_t s) {
   if (n_cells == 0) return;
-  k_compose_perm<<<(n_cells + 63) / 64, 64, 0, s>>>(cells, n_cells, piv, perm);
+  k_compose_perm<<<n_cells, 64, 0, s>>>(cells, n_cells, piv, perm);
   FDS_HIP(hipGetLastError());
   if (n_blk == 0) return;
   k_diag_inverse<<<n_blk, 64, 0, s>>>(cells, blk_cell, blk_k, A, Dinv);
@@ -541,9 +719,21 @@ void launch_sweep_prepare(const SweepCell* cells, int n_cells, const int* blk_ce
 
 int sweep_tile_class(int n) { return n <= 128 ? 8 : n <= 192 ? 12 : n <= 256 ? 16 : 0; }
 
+// The row-split kernel (one slab per workgroup, four times the
+// workgroups) for levels of fewer than kRowsBelow workgroups of four slabs,
+// and for the 16-tile class, whose sixteen tiles per wavefront do not fit
+// the four-slab kernel's registers.
+constexpr int kRowsBelow = 128;
+
 template <int NB, int NR>
 static void up_t(const SweepLaunch& L, hipStream_t s) {
   const int n_groups = (L.n_slab + 3) / 4;
+  if (NB == 16 || (int64_t)L.n_cells * n_groups < kRowsBelow) {
+    const int grid = 8 * ((L.n_cells + 7) / 8) * L.n_slab;
+    k_sweep_up_rows<NB, NR><<<grid, 256, 0, s>>>(L.cells, L.n_cells, L.n_slab, L.ncol, L.A, L.Dinv, L.perm, L.W,
+                                                 L.up_dst, L.F, L.ldF, L.T, L.ldT, L.Fp, L.ldFp);
+    return;
+  }
   const int grid = 8 * ((L.n_cells + 7) / 8) * n_groups;
   k_sweep_up<NB, NR><<<grid, 256, 0, s>>>(L.cells, L.n_cells, n_groups, L.ncol, L.A, L.Dinv, L.perm, L.W, L.up_dst,
                                           L.F, L.ldF, L.T, L.ldT, L.Fp, L.ldFp);
