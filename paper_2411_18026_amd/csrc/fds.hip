@@ -1491,7 +1491,6 @@ static void factor_root(Factor& F) {
 static void prepare_mfma_sweeps(Factor& F) {
   hipStream_t s = F.stream;
   Workspace& ws = F.ws;
-  std::vector<DevBuf<c64>> retired;   // the replaced V blocks, released after one wait at the end
   for (int lev = F.L; lev > F.l0; --lev) {
     CellLevel& lv = F.levels[lev];
     int rmax = 0;
@@ -1546,7 +1545,7 @@ static void prepare_mfma_sweeps(Factor& F) {
       for (auto& g : gd) nmax = std::max(nmax, g.n);
       launch_gemm(ws.upload("w_desc", gd), ws.upload("w_tiles", gt), (int)gt.size(), nmax, 0, lv.At.p, lv.V.p, W.p,
                   0, s);
-      retired.push_back(std::move(lv.V));
+      FDS_HIP(hipStreamSynchronize(s));   // the old V goes back to the cache now
       lv.V = std::move(W);
     }
     // fewer columns than a slab: the LU-solve kernel, then f~ = W g by GEMM
@@ -1573,7 +1572,6 @@ static void prepare_mfma_sweeps(Factor& F) {
     lv.nb_class = sweep_tile_class(lv.bmax);
     lv.nr_class = sweep_tile_class(std::max(rmax, 1));
   }
-  if (!retired.empty()) FDS_HIP(hipStreamSynchronize(s));
 }
 
 static void build_solve_plan(Factor& F) {
