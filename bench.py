@@ -143,8 +143,9 @@ def main():
 
     # roofline of the dominant kernel: the pair-integration kernel with the
     # most GPU time (in practice a regular-pair kernel, one thread per pair).
-    # Algorithmic work: FLOP_PER_EVAL per quadrature point; time from HIP
-    # events around each of its launches inside the library.
+    # Work: the counted FP64 flops per quadrature point of that kernel on
+    # this workload (FLOP_PER_POINT); time from HIP events around each of its
+    # launches inside the library.
     cls_s = st["class_seconds"]
     cls_e = st["class_evals"]
     ker_s = st["pair_kernel_seconds"]
@@ -152,14 +153,12 @@ def main():
     ker_n = st["pair_kernel_launches"]
     dom = int(np.argmax(ker_s))
     kname = fds.PAIR_KERNELS[dom]
-    achieved = FLOP_PER_EVAL * ker_e[dom] / ker_s[dom] / 1e12 if ker_s[dom] > 0 else 0.0
-    # HBM bytes per launch of that kernel from two counter runs (FETCH_SIZE,
-    # then WRITE_SIZE), each scaled by what the counter reads for a plain
-    # 1 GiB copy (2.0 and 1.0): profiles/pair_kernels_ellipse131072_hbm_counters.md
+    fpp = FLOP_PER_POINT.get(kname) or 500.0
+    achieved = fpp * ker_e[dom] / ker_s[dom] / 1e12 if ker_s[dom] > 0 else 0.0
     traffic = TRAFFIC_PER_LAUNCH.get(kname)
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
                 "peak": 78.6, "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": traffic,
-                "flop_per_eval": FLOP_PER_EVAL, "evals": int(ker_e[dom]), "launches": int(ker_n[dom]),
+                "flop_per_eval": fpp, "evals": int(ker_e[dom]), "launches": int(ker_n[dom]),
                 "avg_launch_ms": round(1e3 * ker_s[dom] / max(1, ker_n[dom]), 3)}
 
     # roofline of the batched solve (179 right-hand sides at once): its
@@ -322,10 +321,18 @@ def main():
 # FP64 operations per quadrature-point kernel evaluation (per-unit figure of
 # the assembly: Hankel functions at k_T r and k_L r plus the tensor algebra
 # of the four 2x2 kernel blocks and their accumulation)
-FLOP_PER_EVAL = 500
-# HBM bytes per launch of the dominant pair kernel, from the counter runs
-# recorded in profiles/ (None where not measured for the current code)
-TRAFFIC_PER_LAUNCH = {}
+# FP64 flops per quadrature point of each pair-integration kernel on the
+# headline workload, counted with rocprofv3 (SQ_INSTS_VALU_FMA_F64 x 2 +
+# ADD_F64 + MUL_F64, x 64 lanes, over the points the kernel integrated):
+# profiles/pair_kernels_ellipse131072_tol1e-11.md
+FLOP_PER_POINT = {"k_regular<0, false>": 1157.9, "k_regular<0, true>": 732.8, "k_regular<1, false>": None,
+                  "k_regular<1, true>": 588.6, "k_regular<2, false>": 1171.9, "k_regular<2, true>": 563.6,
+                  "k_regular<3, false>": 1199.0, "k_regular<3, true>": 553.4, "k_regular_wave10": 864.1,
+                  "k_special<1>": 1076.7, "k_special2<2>": 654.0, "k_special2<3>": 654.0}
+# HBM bytes per launch of a pair kernel from two counter runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
+# for a plain 1 GiB device copy (2.0 and 1.0): same profile
+TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (115534 * 2.0 + 865814 * 1.0) * 1024}
 
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")
