@@ -313,10 +313,12 @@ void fds_destroy(fds_factor f);
  * hipFree.  A freed block is handed out again at once for work on the
  * stream that freed it, and for another stream only after that stream has
  * passed the free.  At most FDS_CACHE_LIMIT_MB (environment, default
- * 65536) MiB are kept per device.  fds_release_cache hands every cached
- * block back to the runtime (blocks held by live factors are not touched);
- * fds_cached_bytes gives the bytes currently held by the cache.  Both are
- * safe to call at any time from the host. */
+ * 65536) MiB are kept per device.  The pinned host blocks that stage the
+ * factorisation's uploads are kept the same way (at most 512 MiB).
+ * fds_release_cache hands every cached device block and every cached pinned
+ * host block back to the runtime (blocks held by live factors are not
+ * touched); fds_cached_bytes gives the device bytes currently held by the
+ * cache.  Both are safe to call at any time from the host. */
 void fds_release_cache(void);
 int64_t fds_cached_bytes(void);
 

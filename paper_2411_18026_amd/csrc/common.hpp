@@ -159,6 +159,65 @@ __device__ inline double wsum_full(double v) {
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+// Row exchanges of two doubles between lane groups (v_permlane32_swap and
+// v_permlane16_swap of gfx950, on both 32-bit halves):
+//   swap_rows32: a <- [a 0..31, b 0..31],  b <- [a 32..63, b 32..63]
+//   swap_rows16: a <- [a 0..15, b 0..15, a 32..47, b 32..47],
+//                b <- [a 16..31, b 16..31, a 48..63, b 48..63]
+__device__ inline void swap_rows32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ inline void swap_rows16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sums over the 64 lanes of N values at once (N a multiple of 4), for a
+// fraction of the moves of N separate wsum_full: halve the values twice by
+// row exchanges (lanes 32 apart, then 16 apart; each exchange leaves half of
+// the lanes with one value and half with the other), then finish each of the
+// N/4 left in its rows of 16 lanes.  On return v[k] (k < N/4) holds, in
+// every lane of row r (lanes 16 r .. 16 r + 15), the 64-lane sum of input
+// v[k + r N/4]; wsum_rows_get reads a sum by its input index.  Every lane
+// of the wavefront must be active.
+template <int N>
+__device__ inline void wsum_rows(double (&v)[N]) {
+  static_assert(N % 4 == 0, "four rows of sums");
+  constexpr int H = N / 2, Q = N / 4;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    double a = v[k], b = v[k + H];
+    swap_rows32(a, b);
+    v[k] = a + b;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double a = v[k], b = v[k + Q];
+    swap_rows16(a, b);
+    v[k] = a + b;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    v[k] += dpp_move<0xB1>(v[k]);
+    v[k] += dpp_move<0x4E>(v[k]);
+    v[k] += dpp_move<0x141>(v[k]);
+    v[k] += dpp_move<0x140>(v[k]);
+  }
+}
+template <int N>
+__device__ inline double wsum_rows_get(const double (&v)[N], int i) {
+  return lane_value(v[i % (N / 4)], 16 * (i / (N / 4)));
+}
+
 struct QuadTables {
   double g2[2], w2[2], g3[3], w3[3], g4[4], w4[4], g6[6], w6[6], g10[10], w10[10];
   double cu[kNCoincPts], cv[kNCoincPts], cw[kNCoincPts], coff[kNCoincPts];

@@ -202,7 +202,70 @@ class BlockCache {
   UserAllocator user_{};
 };
 
+// Pinned host blocks of the workspaces' upload staging, kept across
+// factorisations: pinning pages (hipHostMalloc) costs milliseconds for the
+// multi-megabyte assembly tables, and hipHostFree waits for the device, so
+// each factorisation after the first reuses the blocks of earlier ones.
+class PinnedCache {
+ public:
+  static PinnedCache& get() {
+    static PinnedCache* c = new PinnedCache();   // never destroyed (runtime teardown order)
+    return *c;
+  }
+
+  void* alloc(size_t bytes, size_t* got) {
+    const size_t g = size_t(1) << 20;
+    const size_t b = (std::max<size_t>(bytes, 1) + g - 1) / g * g;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      // the smallest cached block that holds the request, if not far larger
+      auto it = free_.lower_bound(b);
+      if (it != free_.end() && it->first <= 4 * b) {
+        void* p = it->second;
+        *got = it->first;
+        cached_ -= it->first;
+        free_.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    FDS_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+    *got = b;
+    return p;
+  }
+
+  // the block must be idle (no copy from it still queued)
+  void free(void* p, size_t bytes) {
+    if (!p) return;
+    std::unique_lock<std::mutex> lk(mu_);
+    if (cached_ + bytes > kLimit) {
+      lk.unlock();
+      (void)hipHostFree(p);
+      return;
+    }
+    free_.emplace(bytes, p);
+    cached_ += bytes;
+  }
+
+  void release_all() {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) (void)hipHostFree(kv.second);
+    free_.clear();
+    cached_ = 0;
+  }
+
+ private:
+  static constexpr size_t kLimit = size_t(512) << 20;
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;   // by block size
+  size_t cached_ = 0;
+};
+
 }  // namespace
+
+void* pinned_alloc(size_t bytes, size_t* block_bytes) { return PinnedCache::get().alloc(bytes, block_bytes); }
+
+void pinned_free(void* p, size_t block_bytes) { PinnedCache::get().free(p, block_bytes); }
 
 void set_alloc_stream(hipStream_t s, bool scoped) {
   t_alloc_stream = s;
@@ -222,7 +285,10 @@ void cache_free(void* p, hipStream_t s) { BlockCache::get().free(p, s); }
 
 size_t cache_bytes() { return BlockCache::get().cached_bytes(); }
 
-void cache_release() { BlockCache::get().release_all(); }
+void cache_release() {
+  BlockCache::get().release_all();
+  PinnedCache::get().release_all();
+}
 
 bool set_user_allocator(const UserAllocator& u) { return BlockCache::get().set_user(u); }
 

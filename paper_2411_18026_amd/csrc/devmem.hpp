@@ -41,6 +41,10 @@ hipStream_t alloc_stream();
 bool alloc_scoped();
 void* cache_alloc(size_t bytes, size_t* block_bytes = nullptr);
 void cache_free(void* p, hipStream_t s);
+// Pinned host blocks (upload staging), cached process-wide; pinned_free takes
+// an idle block and the size pinned_alloc reported.
+void* pinned_alloc(size_t bytes, size_t* block_bytes);
+void pinned_free(void* p, size_t block_bytes);
 size_t cache_bytes();
 void cache_release();
 
@@ -134,7 +138,7 @@ class Workspace {
         if (b.pending) (void)hipEventSynchronize(b.ev);
         (void)hipEventDestroy(b.ev);
       }
-      if (b.p) (void)hipHostFree(b.p);
+      pinned_free(b.p, b.bytes);
     }
   }
   void set_stream(hipStream_t s) { s_ = s; }
@@ -183,12 +187,11 @@ class Workspace {
       b.pending = false;
     }
     if (b.bytes < bytes) {
-      if (b.p) FDS_HIP(hipHostFree(b.p));
+      const size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
+      pinned_free(b.p, b.bytes);
       b.p = nullptr;
       b.bytes = 0;
-      const size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
-      FDS_HIP(hipHostMalloc(&b.p, nb, hipHostMallocDefault));
-      b.bytes = nb;
+      b.p = pinned_alloc(nb, &b.bytes);
     }
     if (!b.ev) FDS_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
     return b.p;

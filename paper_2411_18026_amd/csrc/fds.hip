@@ -295,13 +295,16 @@ struct fds_factor_s {
   int tune_chunk[4] = {0, 0, 0, 0};         // autotuned LU-solve columns per workgroup per nrhs class
   int tune_bn[4] = {64, 64, 64, 64};        // autotuned GEMM tile width per nrhs class
   float* pred_host = nullptr;               // learned form: pinned copy of a level's predictions
-  size_t pred_host_n = 0;
+  size_t pred_host_n = 0, pred_host_bytes = 0;
   hipEvent_t pred_ev = nullptr;
   std::vector<fds_rank_record> rank_log;    // per compressed cell: features, ranks, prediction
   std::map<int64_t, hipGraphExec_t> graphs; // captured solve sweeps per (nrhs, kind)
   hipStream_t gstream = nullptr;            // library stream for graph capture and replay
   ~fds_factor_s() {
-    if (pred_host) (void)hipHostFree(pred_host);
+    if (pred_host) {
+      if (pred_ev) (void)hipEventSynchronize(pred_ev);
+      fds::pinned_free(pred_host, pred_host_bytes);
+    }
     if (pred_ev) (void)hipEventDestroy(pred_ev);
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (gstream) {
@@ -796,10 +799,13 @@ static std::vector<float> cell_features(const Factor& F, int lev, const std::vec
 static void launch_predictions(Factor& F, int lev, const std::vector<double>& crd, const std::vector<int>& mv_m) {
   const int n = F.levels[lev].n;
   if (F.pred_host_n < (size_t)n) {
-    if (F.pred_host) FDS_HIP(hipHostFree(F.pred_host));
+    if (F.pred_host) {
+      FDS_HIP(hipEventSynchronize(F.pred_ev));
+      pinned_free(F.pred_host, F.pred_host_bytes);
+    }
     F.pred_host = nullptr;
-    F.pred_host_n = 0;
-    FDS_HIP(hipHostMalloc((void**)&F.pred_host, (size_t)n * sizeof(float), hipHostMallocDefault));
+    F.pred_host_n = F.pred_host_bytes = 0;
+    F.pred_host = static_cast<float*>(pinned_alloc((size_t)n * sizeof(float), &F.pred_host_bytes));
     F.pred_host_n = (size_t)n;
   }
   if (!F.pred_ev) FDS_HIP(hipEventCreateWithFlags(&F.pred_ev, hipEventDisableTiming));

@@ -769,19 +769,24 @@ constexpr int kQrMaxM = 2048;    // rows with the Householder vector in LDS
 constexpr int kQrMaxN = 1024;
 constexpr int kQrMaxNTall = 4096;
 constexpr int64_t kQrwMinElems = 1 << 16;   // problems this large use the multi-workgroup QR
+constexpr int kQrFewProblems = 128;          // launches of at most this many problems: 1024 threads each
 
-// Reflector update of columns c[0..G) (g < ng valid) of one problem by one
-// wavefront: w = tau v^H a, a <- a - v w, and the exact norm of the part
+// Reflector update of columns cols[0..G) (g < ng valid) of one problem by
+// one wavefront: w = tau v^H a, a <- a - v w, and the exact norm of the part
 // below row j.  CH > 0: the trailing rows j.. of each column (at most 64 CH
-// of them) stay in registers between the two passes; CH = 0: two passes
-// over memory.  Per lane the rows are visited in the same order either way,
-// so the results do not depend on the variant.
+// of them) stay in registers between the two passes; CH = 0: two passes over
+// memory.  Per lane the rows are visited in the same order
+// either way, and the lane sums are taken together (wsum_rows) in both, so
+// the results do not depend on the variant.
 template <int G, int CH>
 __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j, const int (&cols)[G], int ng,
                                       const c64* v, c64 vtop, double tau, int lane, double* __restrict__ nrm) {
-  double wr[G], wi[G];
+  static_assert(G % 4 == 0, "lane sums four rows at a time");
+  double dw[2 * G];   // v^H a of column g: real part dw[g], imaginary dw[G + g]
+  double sq[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) wr[g] = wi[g] = 0.0;
+  for (int g = 0; g < G; ++g) dw[g] = dw[G + g] = sq[g] = 0.0;
+  c64 w[G];
   if constexpr (CH > 0) {
     c64 a[G][CH];
 #pragma unroll
@@ -792,18 +797,13 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         a[g][t] = (in && g < ng) ? A[i + (int64_t)cols[g] * lda] : cmk(0, 0);
-        wr[g] += vv.re * a[g][t].re + vv.im * a[g][t].im;   // conj(v) a
-        wi[g] += vv.re * a[g][t].im - vv.im * a[g][t].re;
+        dw[g] += vv.re * a[g][t].re + vv.im * a[g][t].im;   // conj(v) a
+        dw[G + g] += vv.re * a[g][t].im - vv.im * a[g][t].re;
       }
     }
+    wsum_rows<2 * G>(dw);
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      wr[g] = wsum_full(wr[g]);
-      wi[g] = wsum_full(wi[g]);
-    }
-    double sq[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) sq[g] = 0.0;
+    for (int g = 0; g < G; ++g) w[g] = cmk(tau * wsum_rows_get(dw, g), tau * wsum_rows_get(dw, G + g));
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
       const int i = j + lane + 64 * t;
@@ -812,16 +812,10 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g >= ng) continue;
-        const c64 w = cmk(tau * wr[g], tau * wi[g]);
-        const c64 x = a[g][t] - vv * w;
+        const c64 x = a[g][t] - vv * w[g];
         A[i + (int64_t)cols[g] * lda] = x;
         if (i > j) sq[g] += abs2(x);
       }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      sq[g] = wsum_full(sq[g]);
-      if (lane == 0 && g < ng) nrm[cols[g]] = sq[g];
     }
   } else {
 #pragma unroll
@@ -830,28 +824,31 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
       const c64* col = A + (int64_t)cols[g] * lda;
       for (int i = j + lane; i < m; i += 64) {
         const c64 x = col[i], vv = i == j ? vtop : v[i];
-        wr[g] += vv.re * x.re + vv.im * x.im;
-        wi[g] += vv.re * x.im - vv.im * x.re;
+        dw[g] += vv.re * x.re + vv.im * x.im;
+        dw[G + g] += vv.re * x.im - vv.im * x.re;
       }
     }
+    wsum_rows<2 * G>(dw);
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      wr[g] = wsum_full(wr[g]);
-      wi[g] = wsum_full(wi[g]);
-    }
+    for (int g = 0; g < G; ++g) w[g] = cmk(tau * wsum_rows_get(dw, g), tau * wsum_rows_get(dw, G + g));
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (g >= ng) continue;
       c64* col = A + (int64_t)cols[g] * lda;
-      const c64 w = cmk(tau * wr[g], tau * wi[g]);
-      double sq = 0.0;
       for (int i = j + lane; i < m; i += 64) {
-        const c64 x = col[i] - (i == j ? vtop : v[i]) * w;
+        const c64 x = col[i] - (i == j ? vtop : v[i]) * w[g];
         col[i] = x;
-        if (i > j) sq += abs2(x);
+        if (i > j) sq[g] += abs2(x);
       }
-      sq = wsum_full(sq);
-      if (lane == 0) nrm[cols[g]] = sq;
+    }
+  }
+  // lane 16 r writes the norms of columns r G/4 ..
+  wsum_rows<G>(sq);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int k = 0; k < G / 4; ++k) {
+      const int g = k + (lane >> 4) * (G / 4);
+      if (g < ng) nrm[cols[g]] = sq[k];
     }
   }
 }
@@ -872,11 +869,11 @@ __device__ inline double wmax_full(double v) {
 // Per step: pivot search by wavefront reductions (two barriers), column
 // swap, reflector (one wavefront), and the update of the trailing columns,
 // four at a time per wavefront.
-template <bool TALL>
-__global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ descs, c64* __restrict__ base,
+template <bool TALL, int TB>
+__global__ void __launch_bounds__(TB) k_cpqr(const CpqrDesc* __restrict__ descs, c64* __restrict__ base,
                                                int* __restrict__ piv, double tol, int* __restrict__ rank) {
   constexpr int NMAX = TALL ? kQrMaxNTall : kQrMaxN;
-  constexpr int NW = kBlk / 64;
+  constexpr int NW = TB / 64;
   constexpr int G = 4;
   __shared__ double nrm[NMAX];
   __shared__ int pv[NMAX];
@@ -890,7 +887,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   const int m = d.m, n = d.n, lda = d.lda;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int kmax = min(d.k_end, min(m, n));
-  for (int c = tid; c < n; c += kBlk) pv[c] = d.k_start == 0 ? c : P[c];
+  for (int c = tid; c < n; c += TB) pv[c] = d.k_start == 0 ? c : P[c];
   // exactly computed norms of the remaining part of each column
   for (int c = d.k_start + wid; c < n; c += NW) {
     double s = 0.0;
@@ -904,7 +901,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
   for (; j < kmax; ++j) {
     // pivot: largest norm; ties within a relative 1e-12 -> lowest original column
     double best = -1.0;
-    for (int c = j + tid; c < n; c += kBlk) best = fmax(best, nrm[c]);
+    for (int c = j + tid; c < n; c += TB) best = fmax(best, nrm[c]);
     best = wmax_full(best);
     if (lane == 0) s_max[wid] = best;
     __syncthreads();
@@ -912,7 +909,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
 #pragma unroll
     for (int w = 1; w < NW; ++w) top = fmax(top, s_max[w]);
     int bo = 0x7fffffff, bc = -1;
-    for (int c = j + tid; c < n; c += kBlk)
+    for (int c = j + tid; c < n; c += TB)
       if (nrm[c] >= top * (1.0 - 1e-12) && pv[c] < bo) {
         bo = pv[c];
         bc = c;
@@ -942,7 +939,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
     if (j == 0) r00 = rjj;
     if (rjj == 0.0 || (d.stop_at_tol && j > 0 && rjj <= tol * r00)) break;
     if (p != j) {
-      for (int i = tid; i < m; i += kBlk) {
+      for (int i = tid; i < m; i += TB) {
         const c64 t = A[i + (int64_t)j * lda];
         A[i + (int64_t)j * lda] = A[i + (int64_t)p * lda];
         A[i + (int64_t)p * lda] = t;
@@ -982,7 +979,7 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
     }
     __syncthreads();
     if (!TALL)
-      for (int i = j + 1 + tid; i < m; i += kBlk) colj[i] = cmk(0, 0);
+      for (int i = j + 1 + tid; i < m; i += TB) colj[i] = cmk(0, 0);
     const double tau = s_tau;
     const c64 vtop = s_vtop;
     const int rows = m - j;
@@ -1002,12 +999,12 @@ __global__ void __launch_bounds__(kBlk) k_cpqr(const CpqrDesc* __restrict__ desc
     }
     __syncthreads();
     if (TALL) {
-      for (int i = j + 1 + tid; i < m; i += kBlk) colj[i] = cmk(0, 0);
+      for (int i = j + 1 + tid; i < m; i += TB) colj[i] = cmk(0, 0);
       __syncthreads();
     }
   }
   __syncthreads();
-  for (int c = tid; c < n; c += kBlk) P[c] = pv[c];
+  for (int c = tid; c < n; c += TB) P[c] = pv[c];
   if (tid == 0) rank[blockIdx.x] = j;
 }
 
@@ -1177,42 +1174,42 @@ __global__ void __launch_bounds__(64 * kQrRegWaves) k_cpqr_reg(const CpqrDesc* _
     c64 vv[CH];
 #pragma unroll
     for (int t = 0; t < CH; ++t) vv[t] = vbuf[lane + 64 * t];
-    double wr[NS], wi[NS];
+    // w = v^H a of every slot (real parts in dw[sl], imaginary in dw[NS + sl]),
+    // summed over the lanes together
+    double dw[2 * NS];
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
-      wr[sl] = wi[sl] = 0.0;
+      dw[sl] = dw[NS + sl] = 0.0;
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
-        wr[sl] += vv[t].re * a[sl][t].re + vv[t].im * a[sl][t].im;   // conj(v) a
-        wi[sl] += vv[t].re * a[sl][t].im - vv[t].im * a[sl][t].re;
+        dw[sl] += vv[t].re * a[sl][t].re + vv[t].im * a[sl][t].im;   // conj(v) a
+        dw[NS + sl] += vv[t].re * a[sl][t].im - vv[t].im * a[sl][t].re;
       }
     }
+    wsum_rows<2 * NS>(dw);
+    c64 w[NS];
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl) {
-      wr[sl] = wsum_full(wr[sl]);
-      wi[sl] = wsum_full(wi[sl]);
-    }
+    for (int sl = 0; sl < NS; ++sl) w[sl] = cmk(tau * wsum_rows_get(dw, sl), tau * wsum_rows_get(dw, NS + sl));
     double sq[NS];
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       sq[sl] = 0.0;
       const int c = sl * NW + wid;
       if (c > j && c < n) {
-        const c64 w = cmk(tau * wr[sl], tau * wi[sl]);
 #pragma unroll
         for (int t = 0; t < CH; ++t) {
-          a[sl][t] = a[sl][t] - vv[t] * w;
+          a[sl][t] = a[sl][t] - vv[t] * w[sl];
           if (lane + 64 * t > j) sq[sl] += abs2(a[sl][t]);
         }
       }
     }
+    // the slots' remaining norms: lane 16 r writes those of slots r NS/4 ..
+    wsum_rows<NS>(sq);
+    if ((lane & 15) == 0) {
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl) sq[sl] = wsum_full(sq[sl]);
-    if (lane == 0) {
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) {
-        const int c = sl * NW + wid;
-        if (c > j && c < n) nrm[c] = sq[sl];
+      for (int k = 0; k < NS / 4; ++k) {
+        const int c = (k + (lane >> 4) * (NS / 4)) * NW + wid;
+        if (c > j && c < n) nrm[c] = sq[k];
       }
     }
     __syncthreads();
@@ -2038,10 +2035,16 @@ void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol
 
 void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int* rank, hipStream_t s, int tall) {
   if (n == 0) return;
-  if (tall)
-    k_cpqr<true><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
-  else
-    k_cpqr<false><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
+  // fewer problems than compute units: sixteen wavefronts per problem
+  // update its columns (the same arithmetic per column, so the same results)
+  const bool few = n <= kQrFewProblems;
+  if (tall) {
+    if (few) k_cpqr<true, 1024><<<n, 1024, 0, s>>>(d, base, piv, tol, rank);
+    else k_cpqr<true, kBlk><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
+  } else {
+    if (few) k_cpqr<false, 1024><<<n, 1024, 0, s>>>(d, base, piv, tol, rank);
+    else k_cpqr<false, kBlk><<<n, kBlk, 0, s>>>(d, base, piv, tol, rank);
+  }
   FDS_HIP(hipGetLastError());
 }
 
