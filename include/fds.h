@@ -384,6 +384,19 @@ int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* 
                      int32_t* piv, const int64_t* pivoff, const int64_t* kmax, double tol,
                      int32_t stop_at_tol, int32_t* rank, void* stream);
 
+/* Interpolation matrices of finished column IDs (Section 7.1): for problem
+ * p with rank k = rank[p] > 0 (host int32 [np]), the matrix at a + off[p]
+ * (device, m[p] x n[p], leading dimension m[p]) holding the partial QR and
+ * piv + pivoff[p] the pivots written by fds_cpqr_batched, writes
+ * W = [I, R11^{-1} R12] P^T (k x n[p], column-major, leading dimension k)
+ * at w + woff[p] (device), so that M ~ M(:, piv[0..k)) W.  R12 is
+ * overwritten by R11^{-1} R12.  Problems of rank 0 are skipped.  Ranks up
+ * to 64 stage R11 in LDS; larger ranks solve one column per thread.  Host
+ * int64 arrays [np].  Synchronous. */
+int fds_interp_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
+                       const int32_t* piv, const int64_t* pivoff, const int32_t* rank, fds_c64* w,
+                       const int64_t* woff, void* stream);
+
 /* Batched LU with partial pivoting (the factorisation of the diagonal
  * blocks A_i and of the compressed system, Sections 6.2, 6.3): for matrix p
  * the n[p] x n[p] column-major matrix at a + off[p] (device, ld n[p]) is

@@ -86,7 +86,7 @@ ENOCONV = 6
 
 EXPORTS = ["fds_options_default", "fds_build", "fds_size", "fds_rhs_plane", "fds_solve", "fds_apply", "fds_get_stats",
            "fds_get_ranks", "fds_get_skeleton", "fds_get_rank_log", "fds_destroy", "fds_strerror", "fds_last_error",
-           "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
+           "fds_entries", "fds_special_eval", "fds_cpqr_batched", "fds_interp_batched", "fds_lu_batched", "fds_rid_batched", "fds_mlp_init",
            "fds_mlp_forward", "fds_mlp_loss_grad", "fds_mlp_train", "fds_release_cache", "fds_cached_bytes",
            "fds_field", "fds_set_allocator", "fds_solve_noalloc"]
 
@@ -178,6 +178,7 @@ def load():
     L.fds_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     L.fds_cpqr_batched.argtypes = [i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, i32, vp, vp]
+    L.fds_interp_batched.argtypes = [i32, vp, pi64, pi64, pi64, vp, pi64, pi32, vp, pi64, vp]
     _lib = L
     return L
 
@@ -464,10 +465,11 @@ def special_eval(x, beta, stream=None):
     return out, outc
 
 
-def cpqr_batched(mats, tol, kmax=None, stop_at_tol=True, stream=None):
+def cpqr_batched(mats, tol, kmax=None, stop_at_tol=True, stream=None, interp=False):
     """Column-pivoted QR of a list of complex matrices on the GPU.  Returns
     (pivots, ranks, R-factors) with R the top ``rank`` rows of the reduced
-    matrix in pivoted column order."""
+    matrix in pivoted column order; with ``interp`` also the interpolation
+    matrix W (rank x n) of each ID, M ~ M[:, piv[:rank]] W."""
     import torch
     L = load()
     ms = [np.asarray(m, dtype=np.complex128) for m in mats]
@@ -499,7 +501,21 @@ def cpqr_batched(mats, tol, kmax=None, stop_at_tol=True, stream=None):
         A = flat_out[offs[i]:offs[i] + m.size].reshape(m.shape[1], m.shape[0]).T
         k = int(rk[i])
         res.append((pv[pvo[i]:pvo[i] + m.shape[1]].copy(), k, np.triu(A[:k, :])))
-    return res
+    if not interp:
+        return res
+    rk32 = np.ascontiguousarray(rk, dtype=np.int32)
+    woff = np.concatenate([[0], np.cumsum([int(rk[i]) * nn[i] for i in range(len(ms))])]).astype(np.int64)
+    w = torch.zeros(max(int(woff[-1]), 1), dtype=torch.complex128, device="cuda")
+    _check(L.fds_interp_batched(len(ms), ctypes.c_void_p(dev.data_ptr()), P(a_off), P(a_m), P(a_n),
+                                ctypes.c_void_p(piv.data_ptr()), P(a_pv),
+                                rk32.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(w.data_ptr()),
+                                P(np.ascontiguousarray(woff[:-1])), _stream(stream)))
+    wh = w.cpu().numpy()
+    out = []
+    for i, (pv_i, k, R) in enumerate(res):
+        W = wh[woff[i]:woff[i] + k * nn[i]].reshape(nn[i], k).T
+        out.append((pv_i, k, R, W))
+    return out
 
 
 def rid_batched(mats, sizes, tol, seed, gids=None, stream=None):

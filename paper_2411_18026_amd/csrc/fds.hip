@@ -1016,7 +1016,7 @@ static std::vector<int> learned_ids(Factor& F, int lev, const std::vector<double
     c64* Wj = ws.get<c64>("judge_W", (size_t)std::max<int64_t>(wtot, 1));
     const size_t nj = jv.size() + ju.size() + rdv.size() + rdu.size();
     double* ratio = ws.get<double>("judge_ratio", nj);
-    launch_interp(ws.upload("judge_interp", iw), (int)iw.size(), Y, dpiv, Wj, s, interp_nmax(iw));
+    launch_interp(ws.upload("judge_interp", iw), (int)iw.size(), Y, dpiv, Wj, s, interp_size(iw));
     launch_judge(ws.upload("judge_v", jv), (int)jv.size(), MV, Wj, dpiv, ratio, s);
     launch_judge(ws.upload("judge_u", ju), (int)ju.size(), MU, Wj, dpiv, ratio + jv.size(), s);
     if (!rdv.empty() || !rdu.empty()) {
@@ -1310,12 +1310,12 @@ static void compress_level(Factor& F, int lev) {
                                             lv.x_off[q] + coff + (int64_t)roff * b, b, 1, solved});
     }
   }
-  launch_interp(ws.upload("interp_v", ivm), (int)ivm.size(), MV, dpiv, lv.V.p, s, interp_nmax(ivm));
-  launch_interp(ws.upload("interp_u", ium), (int)ium.size(), MU, dpiv, lv.X.p, s, interp_nmax(ium));
+  launch_interp(ws.upload("interp_v", ivm), (int)ivm.size(), MV, dpiv, lv.V.p, s, interp_size(ivm));
+  launch_interp(ws.upload("interp_u", ium), (int)ium.size(), MU, dpiv, lv.X.p, s, interp_size(ium));
   if (!ivy.empty() || !iuy.empty()) {
     c64* Y = ws.get<c64>("sketch_Y", 1);
-    launch_interp(ws.upload("interp_vy", ivy), (int)ivy.size(), Y, dpiv, lv.V.p, s, interp_nmax(ivy));
-    launch_interp(ws.upload("interp_uy", iuy), (int)iuy.size(), Y, dpiv, lv.X.p, s, interp_nmax(iuy));
+    launch_interp(ws.upload("interp_vy", ivy), (int)ivy.size(), Y, dpiv, lv.V.p, s, interp_size(ivy));
+    launch_interp(ws.upload("interp_uy", iuy), (int)iuy.size(), Y, dpiv, lv.X.p, s, interp_size(iuy));
   }
   span_end(F);
 
@@ -2726,7 +2726,7 @@ int fds_rid_batched(int32_t np, const fds_c64* a, const int64_t* off, const int6
     }
     c64* W = ws.get<c64>("W", (size_t)std::max<int64_t>(wtot, 1));
     double* dratio = ws.get<double>("ratio", (size_t)np);
-    launch_interp(ws.upload("iw", iw), (int)iw.size(), Y, dpiv, W, s, interp_nmax(iw));
+    launch_interp(ws.upload("iw", iw), (int)iw.size(), Y, dpiv, W, s, interp_size(iw));
     launch_judge(ws.upload("jd", jd), (int)jd.size(), M, W, dpiv, dratio, s);
     if (!rd.empty()) {
       c64* E = ws.get<c64>("E", (size_t)etot);
@@ -2887,6 +2887,30 @@ int fds_cpqr_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* 
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);
     cpqr_factor(d, (c64*)a, piv, tol, rank, ws, "cpqr", s);
+    FDS_HIP(hipStreamSynchronize(s));
+    return FDS_OK;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return translate(e);
+  }
+}
+
+int fds_interp_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* m, const int64_t* n,
+                       const int32_t* piv, const int64_t* pivoff, const int32_t* rank, fds_c64* w,
+                       const int64_t* woff, void* stream) {
+  AllocScope scope((hipStream_t)stream);
+  if (np < 1 || !a || !off || !m || !n || !piv || !pivoff || !rank || !w || !woff) return FDS_EINVAL;
+  try {
+    std::vector<InterpDesc> d;
+    for (int i = 0; i < np; ++i) {
+      if (m[i] < 1 || n[i] < 1 || rank[i] < 0 || rank[i] > std::min(m[i], n[i])) return FDS_EINVAL;
+      if (rank[i] > 0)
+        d.push_back(InterpDesc{off[i], pivoff[i], (int)n[i], (int)m[i], rank[i], woff[i], rank[i], 0, 0});
+    }
+    if (d.empty()) return FDS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    launch_interp(ws.upload("interp", d), (int)d.size(), (c64*)a, piv, (c64*)w, s, interp_size(d));
     FDS_HIP(hipStreamSynchronize(s));
     return FDS_OK;
   } catch (const std::exception& e) {

@@ -1461,19 +1461,12 @@ __global__ void k_qrw_rank(int n, const QrwState* __restrict__ st, const int* __
 // then write W or W^T.
 // Grid: (problem, chunk of kInterpCols columns of W).
 constexpr int kInterpCols = 64;
+constexpr int kInterpSmallK = 64;   // k_interp_small: ranks up to this
 
-__global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ descs, c64* __restrict__ abase,
-                                                 const int* __restrict__ piv, c64* __restrict__ dbase) {
-  const InterpDesc d = descs[blockIdx.x];
-  const int c_lo = blockIdx.y * kInterpCols;
-  if (c_lo >= d.n) return;
-  const int c_hi = min(d.n, c_lo + kInterpCols);
-  c64* A = abase + d.a_off;
-  const int* P = piv + d.piv_off;
-  c64* D = dbase + d.d_off;
-  const int lda = d.lda, k = d.k;
-  const int tid = threadIdx.x;
-  for (int c = max(k, c_lo) + tid; c < c_hi && !d.solved; c += kBlk) {
+// Back substitution one column per thread (any rank), R1 read from memory.
+__device__ inline void interp_solve_columns(c64* __restrict__ A, int lda, int k, int c_lo, int c_hi, int tid,
+                                            int nthreads) {
+  for (int c = max(k, c_lo) + tid; c < c_hi; c += nthreads) {
     c64* col = A + (int64_t)c * lda;
     for (int i = k - 1; i >= 0; --i) {
       c64 s = col[i];
@@ -1481,14 +1474,18 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
       col[i] = cdiv(s, A[i + (int64_t)i * lda]);
     }
   }
-  __syncthreads();
-  for (int t = tid; t < k * (c_hi - c_lo); t += kBlk) {
+}
+
+__device__ inline void interp_write(const InterpDesc& d, const c64* __restrict__ A, const int* __restrict__ P,
+                                    c64* __restrict__ D, int c_lo, int c_hi, int tid, int nthreads) {
+  const int k = d.k;
+  for (int t = tid; t < k * (c_hi - c_lo); t += nthreads) {
     const int r = t % k, c = c_lo + t / k;     // W(r, P[c])
     c64 val;
     if (c < k)
       val = (r == c) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
     else
-      val = A[r + (int64_t)c * lda];
+      val = A[r + (int64_t)c * d.lda];
     const int cc = P[c];
     if (d.transpose)
       D[cc + (int64_t)r * d.d_ld] = val;
@@ -1497,6 +1494,100 @@ __global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(kBlk) k_interp(const InterpDesc* __restrict__ descs, c64* __restrict__ abase,
+                                                 const int* __restrict__ piv, c64* __restrict__ dbase) {
+  const InterpDesc d = descs[blockIdx.x];
+  const int c_lo = blockIdx.y * kInterpCols;
+  if (c_lo >= d.n) return;
+  const int c_hi = min(d.n, c_lo + kInterpCols);
+  c64* A = abase + d.a_off;
+  if (!d.solved) interp_solve_columns(A, d.lda, d.k, c_lo, c_hi, threadIdx.x, kBlk);
+  __syncthreads();
+  interp_write(d, A, piv + d.piv_off, dbase + d.d_off, c_lo, c_hi, threadIdx.x, kBlk);
+}
+
+// Ranks up to kInterpSmallK: R1 staged in LDS, the chunk's columns of R2 in
+// registers (lane = column, wavefront w holding rows w, w + 4, ...), and the
+// back substitution taken four rows at a time: the group's current rows go
+// through LDS, every thread finishes them for its column with the group's
+// 4 x 4 triangle, the wavefront owning each row stores it, and the rows
+// above are updated in registers.  A rank above the limit takes the
+// column-per-thread loop.
+__global__ void __launch_bounds__(256) k_interp_small(const InterpDesc* __restrict__ descs,
+                                                      c64* __restrict__ abase, const int* __restrict__ piv,
+                                                      c64* __restrict__ dbase) {
+  constexpr int KS = kInterpSmallK, NS = KS / 4;
+  static_assert(kInterpCols == 64, "one column per lane");
+  __shared__ c64 r1[KS * KS];   // R1, column-major with leading dimension KS
+  __shared__ c64 grp[4][kInterpCols];
+  const InterpDesc d = descs[blockIdx.x];
+  const int c_lo = blockIdx.y * kInterpCols;
+  if (c_lo >= d.n) return;
+  const int c_hi = min(d.n, c_lo + kInterpCols);
+  c64* A = abase + d.a_off;
+  const int lda = d.lda, k = d.k;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c0 = max(k, c_lo);
+  if (!d.solved && k > KS) {
+    interp_solve_columns(A, lda, k, c_lo, c_hi, tid, 256);
+  } else if (!d.solved && c0 < c_hi) {
+    for (int t = tid; t < k * k; t += 256) {
+      const int i = t % k, l = t / k;
+      r1[i + KS * l] = A[i + (int64_t)l * lda];
+    }
+    const int c = c0 + lane;
+    const bool act = c < c_hi;
+    c64 x[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = w + 4 * s;
+      x[s] = (act && i < k) ? A[i + (int64_t)c * lda] : cmk(0, 0);
+    }
+    __syncthreads();
+    for (int g = (k + 3) / 4 - 1; g >= 0; --g) {
+      // rows 4 g .. 4 g + 3 as they stand (row 4 g + w from wavefront w)
+      c64 xg = x[0];
+#pragma unroll
+      for (int s = 1; s < NS; ++s)
+        if (s == g) xg = x[s];
+      grp[w][lane] = xg;
+      __syncthreads();
+      c64 t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = grp[q][lane];
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const int l = 4 * g + q;
+        if (l < k) {
+          c64 sv = t[q];
+#pragma unroll
+          for (int p = q + 1; p < 4; ++p)
+            if (4 * g + p < k) sv -= r1[l + KS * (4 * g + p)] * t[p];
+          t[q] = cdiv(sv, r1[l + KS * l]);
+        } else {
+          t[q] = cmk(0, 0);
+        }
+      }
+      c64 tw = t[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (q == w) tw = t[q];
+      if (act && 4 * g + w < k) A[(4 * g + w) + (int64_t)c * lda] = tw;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s < g) {
+          const int i = w + 4 * s;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (4 * g + q < k) x[s] -= r1[i + KS * (4 * g + q)] * t[q];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  interp_write(d, A, piv + d.piv_off, dbase + d.d_off, c_lo, c_hi, tid, 256);
+}
 
 // ------------------------------------------------------------------ scatter / copies
 // Block scatter with an optional type conversion (FP32 A~ into FP64 blocks and back).
@@ -2048,17 +2139,24 @@ void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int*
   FDS_HIP(hipGetLastError());
 }
 
-void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s, int nmax) {
+void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s,
+                   InterpSize sz) {
   if (n == 0) return;
-  k_interp<<<dim3((unsigned)n, (unsigned)((std::max(nmax, 1) + kInterpCols - 1) / kInterpCols)), kBlk, 0, s>>>(
-      d, abase, piv, dbase);
+  const dim3 grid((unsigned)n, (unsigned)((std::max(sz.nmax, 1) + kInterpCols - 1) / kInterpCols));
+  if (sz.kmax <= kInterpSmallK)
+    k_interp_small<<<grid, 256, 0, s>>>(d, abase, piv, dbase);
+  else
+    k_interp<<<grid, kBlk, 0, s>>>(d, abase, piv, dbase);
   FDS_HIP(hipGetLastError());
 }
 
-int interp_nmax(const std::vector<InterpDesc>& d) {
-  int m = 0;
-  for (auto& x : d) m = std::max(m, x.n);
-  return m;
+InterpSize interp_size(const std::vector<InterpDesc>& d) {
+  InterpSize z;
+  for (auto& x : d) {
+    z.nmax = std::max(z.nmax, x.n);
+    z.kmax = std::max(z.kmax, x.k);
+  }
+  return z;
 }
 
 std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d) {

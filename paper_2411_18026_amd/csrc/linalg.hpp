@@ -104,8 +104,12 @@ void launch_cpqr(const CpqrDesc* d, int n, c64* base, int* piv, double tol, int*
 void cpqr_factor(const std::vector<CpqrDesc>& d, c64* base, int* piv, double tol, int* rank, Workspace& ws,
                  const std::string& tag, hipStream_t s);
 // nmax: the largest n of the batch (the grid covers it in column chunks)
-void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s, int nmax);
-int interp_nmax(const std::vector<InterpDesc>& d);
+struct InterpSize {      // largest n and k of a batch of InterpDesc
+  int nmax = 0, kmax = 0;
+};
+void launch_interp(const InterpDesc* d, int n, c64* abase, const int* piv, c64* dbase, hipStream_t s,
+                   InterpSize sz);
+InterpSize interp_size(const std::vector<InterpDesc>& d);
 std::vector<ScatterTile> scatter_tiles(const std::vector<ScatterDesc>& d);
 // (TS, TD) in {(c64, c64), (c32, c32), (c32, c64)}
 template <typename TS, typename TD>

@@ -127,6 +127,28 @@ def test_cpqr_register_variants_match_oracle(fdsmod):
             assert np.allclose(np.abs(np.diag(R)[:k]), np.abs(np.diag(R_o)[:k]), rtol=1e-10)
 
 
+def test_interpolation_matrices_match_oracle(fdsmod):
+    """W = [I, R11^{-1} R12] P^T of each ID against the oracle's, formed from
+    the same pivots and R factor.  The first batch (ranks 1 to 64) runs the
+    kernel that stages R11 in LDS, the second (ranks above 64) the
+    column-per-thread loop; up to 200 columns span several 64-column chunks
+    with ragged tails, and rank = n leaves no R12."""
+    rng = np.random.default_rng(31)
+    batches = ((((90, 60), 37), ((70, 64), 64), ((200, 150), 63), ((130, 200), 1), ((33, 5), 4),
+                ((100, 130), 64)),
+               (((300, 120), 90), ((260, 90), 65)))
+    for batch in batches:
+        mats = [rng.standard_normal(sh) + 1j * rng.standard_normal(sh) for sh, _ in batch]
+        kmax = [k for _, k in batch]
+        res = fdsmod.cpqr_batched(mats, 1e-8, kmax=kmax, stop_at_tol=False, interp=True)
+        for M, kk, (piv, k, R, W) in zip(mats, kmax, res):
+            n = M.shape[1]
+            assert k == kk and W.shape == (k, n)
+            assert np.array_equal(W[:, piv[:k]], np.eye(k))
+            Wo = ofds.id_matrix(piv, R, k, n)
+            assert np.max(np.abs(W - Wo)) <= 1e-10 * max(1.0, np.max(np.abs(Wo))), (M.shape, k)
+
+
 @pytest.mark.parametrize("name", ["circle64", "two_cavities"])
 def test_load_vectors(fdsmod, name):
     curves = GEOMS[name]
