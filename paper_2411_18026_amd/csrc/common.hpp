@@ -159,6 +159,29 @@ __device__ inline double wsum_full(double v) {
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+// maximum over the 64 lanes (same DPP pattern as wsum_full; every lane active)
+__device__ inline double wmax_full(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
+// Integer minimum over the 64 lanes (same DPP pattern; every lane active).
+template <int CTRL>
+__device__ inline int dpp_move_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline int wmin_int_full(int v) {
+  v = min(v, dpp_move_int<0xB1>(v));
+  v = min(v, dpp_move_int<0x4E>(v));
+  v = min(v, dpp_move_int<0x141>(v));
+  v = min(v, dpp_move_int<0x140>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
 // Row exchanges of two doubles between lane groups (v_permlane32_swap and
 // v_permlane16_swap of gfx950, on both 32-bit halves):
 //   swap_rows32: a <- [a 0..31, b 0..31],  b <- [a 32..63, b 32..63]

@@ -7,6 +7,8 @@
 // complex FP64 for the plain form, complex FP32 (FP32 accumulation) for the
 // merges and sweeps of the mixed-precision form.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "devmem.hpp"
 #include "linalg.hpp"
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, T
       }
       __syncthreads();
     }
-    const int p = si[0];
+    const int p = si[0] < n ? si[0] : j;   // no finite candidate: keep the row (reported below)
     const double pv = sv[0];
     __syncthreads();
     if (tid == 0) P[j] = p;
@@ -147,9 +149,10 @@ __global__ void __launch_bounds__(kBlk) k_lu(const LUDesc* __restrict__ descs, T
 
 // Blocked right-looking LU with partial pivoting, panel width NB.  Same
 // pivot rule and output layout as k_lu.  The panel (rows k0.., NB columns)
-// is factored in LDS; its row interchanges are then applied to the other
-// columns, U12 = L11^{-1} A12 is formed column by column, and the trailing
-// matrix gets one rank-NB update per panel.  TB threads per workgroup: 256
+// is factored in LDS by one wavefront; its row interchanges are then
+// applied to the other columns, U12 = L11^{-1} A12 is formed column by
+// column, and the trailing matrix gets one rank-NB update per panel in
+// register tiles.  TB threads per workgroup: 256
 // when a launch has a matrix per CU or more, 1024 for the few large
 // matrices of the upper levels (more wavefronts to hide the trailing
 // update's memory latency).
@@ -158,9 +161,7 @@ __global__ void __launch_bounds__(TB) k_lu_blk(const LUDesc* __restrict__ descs,
                                                  int* __restrict__ piv, int* __restrict__ info) {
   extern __shared__ unsigned char smem_lu[];
   T* Pn = reinterpret_cast<T*>(smem_lu);   // panel, column-major with leading dimension ldp
-  __shared__ double sv[TB / 64];
-  __shared__ int si[TB / 64];
-  __shared__ int s_p;
+  __shared__ int sp[NB];                   // the panel's pivot rows (relative to k0)
   const LUDesc d = descs[blockIdx.x];
   T* A = base + d.a_off;
   int* P = piv + d.piv_off;
@@ -175,60 +176,47 @@ __global__ void __launch_bounds__(TB) k_lu_blk(const LUDesc* __restrict__ descs,
       Pn[i + c * ldp] = A[(k0 + i) + (int64_t)(k0 + c) * lda];
     }
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      // pivot: largest modulus in panel column j at rows >= j, lowest row on ties
-      double best = -1.0;
-      int bi = mp;
-      for (int i = j + tid; i < mp; i += TB) {
-        const double v = abs2(Pn[i + j * ldp]);
-        if (v > best) {
-          best = v;
-          bi = i;
-        }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        sv[wid] = best;
-        si[wid] = bi;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double b = sv[0];
-        int ib = si[0];
-        for (int w = 1; w < TB / 64; ++w)
-          if (sv[w] > b || (sv[w] == b && si[w] < ib)) {
-            b = sv[w];
-            ib = si[w];
+    // the panel is factored by wavefront 0 alone: pivot search by lane
+    // reductions, no workgroup barrier per column (the LDS accesses of one
+    // wavefront take effect in program order; the fences keep the compiler
+    // from reordering them)
+    if (wid == 0) {
+      for (int j = 0; j < nb; ++j) {
+        // pivot: largest modulus in panel column j at rows >= j, lowest row on ties
+        double best = -1.0;
+        int bi = INT32_MAX;
+        for (int i = j + lane; i < mp; i += 64) {
+          const double v = abs2(Pn[i + j * ldp]);
+          if (v > best) {
+            best = v;
+            bi = i;
           }
-        s_p = ib;
-        P[k0 + j] = k0 + ib;
-        if (!(b > 0.0) || !isfinite(b)) bad = bad ? bad : k0 + j + 1;
+        }
+        const double top = wmax_full(best);
+        int p = wmin_int_full(best == top ? bi : INT32_MAX);
+        if (p >= mp) p = j;   // no finite candidate: keep the row (reported below)
+        if (lane == 0) {
+          sp[j] = p;
+          P[k0 + j] = k0 + p;
+          if (!(top > 0.0) || !isfinite(top)) bad = bad ? bad : k0 + j + 1;
+        }
+        if (p != j && lane < nb) {
+          const T t = Pn[j + lane * ldp];
+          Pn[j + lane * ldp] = Pn[p + lane * ldp];
+          Pn[p + lane * ldp] = t;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const T pj = Pn[j + j * ldp];
+        const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
+        for (int i = j + 1 + lane; i < mp; i += 64) {
+          const T l = Pn[i + j * ldp] * inv;
+          Pn[i + j * ldp] = l;
+          for (int c = j + 1; c < nb; ++c) Pn[i + c * ldp] -= l * Pn[j + c * ldp];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
-      __syncthreads();
-      const int p = s_p;
-      if (p != j && tid < nb) {
-        const T t = Pn[j + tid * ldp];
-        Pn[j + tid * ldp] = Pn[p + tid * ldp];
-        Pn[p + tid * ldp] = t;
-      }
-      __syncthreads();
-      const T pj = Pn[j + j * ldp];
-      const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
-      for (int i = j + 1 + tid; i < mp; i += TB) {
-        const T l = Pn[i + j * ldp] * inv;
-        Pn[i + j * ldp] = l;
-        for (int c = j + 1; c < nb; ++c) Pn[i + c * ldp] -= l * Pn[j + c * ldp];
-      }
-      __syncthreads();
     }
+    __syncthreads();
     for (int t = tid; t < mp * nb; t += TB) {
       const int i = t % mp, c = t / mp;
       A[(k0 + i) + (int64_t)(k0 + c) * lda] = Pn[i + c * ldp];
@@ -238,7 +226,7 @@ __global__ void __launch_bounds__(TB) k_lu_blk(const LUDesc* __restrict__ descs,
       if (c >= k0 && c < k0 + nb) continue;
       T* col = A + (int64_t)c * lda;
       for (int j = 0; j < nb; ++j) {
-        const int p = P[k0 + j];
+        const int p = k0 + sp[j];
         if (p != k0 + j) {
           const T t = col[k0 + j];
           col[k0 + j] = col[p];
@@ -264,17 +252,43 @@ __global__ void __launch_bounds__(TB) k_lu_blk(const LUDesc* __restrict__ descs,
       }
     }
     __syncthreads();
-    // A22 -= L21 U12
-    const int m2 = n - k0 - nb;
-    const int64_t tot = (int64_t)m2 * m2;
-    for (int64_t t = tid; t < tot; t += TB) {
-      const int i = (int)(t % m2), c = (int)(t / m2);
-      const T* u = A + (int64_t)(k0 + nb + c) * lda + k0;
-      T s = A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda];
+    // A22 -= L21 U12 in register tiles of TR x TC entries: rows ti + t2r a
+    // and columns tj + t2c b, so that a wavefront's lanes take consecutive
+    // rows (coalesced, conflict-free LDS reads of L21) and share the U12
+    // entries of a column; padded rows and columns read a valid entry and
+    // are not stored
+    {
+      constexpr int TR = TB >= 1024 ? 4 : 2, TC = 2;
+      const int m2 = n - k0 - nb, t2r = (m2 + TR - 1) / TR, t2c = (m2 + TC - 1) / TC;
+      T* A22 = A + (k0 + nb) + (int64_t)(k0 + nb) * lda;
+      const T* U12 = A + k0 + (int64_t)(k0 + nb) * lda;
+      for (int tt = tid; tt < t2r * t2c; tt += TB) {
+        const int ti = tt % t2r, tj = tt / t2r;
+        T acc[TR][TC];
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < nb) s -= Pn[(nb + i) + q * ldp] * u[q];
-      A[(k0 + nb + i) + (int64_t)(k0 + nb + c) * lda] = s;
+        for (int b = 0; b < TC; ++b)
+#pragma unroll
+          for (int a = 0; a < TR; ++a)
+            acc[a][b] = A22[min(ti + t2r * a, m2 - 1) + (int64_t)min(tj + t2c * b, m2 - 1) * lda];
+#pragma unroll 1
+        for (int q = 0; q < nb; ++q) {
+          T l[TR], u[TC];
+#pragma unroll
+          for (int a = 0; a < TR; ++a) l[a] = Pn[(nb + min(ti + t2r * a, m2 - 1)) + q * ldp];
+#pragma unroll
+          for (int b = 0; b < TC; ++b) u[b] = U12[q + (int64_t)min(tj + t2c * b, m2 - 1) * lda];
+#pragma unroll
+          for (int a = 0; a < TR; ++a)
+#pragma unroll
+            for (int b = 0; b < TC; ++b) cfms(acc[a][b], l[a], u[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < TC; ++b)
+#pragma unroll
+          for (int a = 0; a < TR; ++a)
+            if (ti + t2r * a < m2 && tj + t2c * b < m2)
+              A22[(ti + t2r * a) + (int64_t)(tj + t2c * b) * lda] = acc[a][b];
+      }
     }
     __syncthreads();
   }
@@ -335,6 +349,7 @@ __global__ void __launch_bounds__(kBlk) k_panel_lu(const LUDesc* __restrict__ de
           b = sv[w];
           ib = si[w];
         }
+      if (ib >= n) ib = col;   // no finite candidate: keep the row (reported below)
       s_p = ib;
       P[col] = ib;
       if ((!(b > 0.0) || !isfinite(b)) && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
@@ -362,34 +377,141 @@ __global__ void __launch_bounds__(kBlk) k_panel_lu(const LUDesc* __restrict__ de
   }
 }
 
-// row interchanges of panel k0 on every column outside it (one thread per column)
-template <typename T>
-__global__ void k_swap_outside(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base,
-                               const int* __restrict__ piv) {
-  const LUDesc d = descs[blockIdx.y];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k0 >= d.n || c >= d.n) return;
-  const int nb = min(kPanel, d.n - k0);
-  if (c >= k0 && c < k0 + nb) return;
-  T* col = base + d.a_off + (int64_t)c * d.lda;
-  const int* P = piv + d.piv_off;
+// The same panel step with the panel (rows k0.., KP columns) staged in LDS:
+// per column a pivot search by lane reductions and one exchange of partial
+// results between the wavefronts, the row swap and the rank-1 update in
+// LDS, then one write-back.  Dynamic LDS: (n - k0) KP entries.
+template <typename T, int KP>
+__global__ void __launch_bounds__(kBlk) k_panel_lu_lds(const LUDesc* __restrict__ descs, int k0,
+                                                       T* __restrict__ base, int* __restrict__ piv,
+                                                       int* __restrict__ info) {
+  extern __shared__ unsigned char smem_pl[];
+  T* Pn = reinterpret_cast<T*>(smem_pl);   // column-major, leading dimension mp
+  constexpr int NW = kBlk / 64;
+  __shared__ double s_v[NW];
+  __shared__ int s_i[NW];
+  const LUDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  T* A = base + d.a_off;
+  int* P = piv + d.piv_off;
+  const int n = d.n, lda = d.lda, nb = min(KP, n - k0), mp = n - k0;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int t = tid; t < mp * nb; t += kBlk) {
+    const int i = t % mp, c = t / mp;
+    Pn[i + c * mp] = A[(k0 + i) + (int64_t)(k0 + c) * lda];
+  }
+  __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    const int p = P[k0 + j];
-    if (p != k0 + j) {
-      const T t = col[k0 + j];
-      col[k0 + j] = col[p];
-      col[p] = t;
+    // pivot: largest modulus in column j at rows >= j, lowest row on ties
+    double best = -1.0;
+    int bi = INT32_MAX;
+    for (int i = j + tid; i < mp; i += kBlk) {
+      const double v = abs2(Pn[i + j * mp]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
     }
+    const double top = wmax_full(best);
+    const int wi = wmin_int_full(best == top ? bi : INT32_MAX);
+    if (lane == 0) {
+      s_v[wid] = top;
+      s_i[wid] = wi;
+    }
+    __syncthreads();
+    double b = s_v[0];
+    int p = s_i[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (s_v[w] > b || (s_v[w] == b && s_i[w] < p)) {
+        b = s_v[w];
+        p = s_i[w];
+      }
+    if (p >= mp) p = j;   // no finite candidate: keep the row (reported)
+    if (tid == 0) {
+      P[k0 + j] = k0 + p;
+      if ((!(b > 0.0) || !isfinite(b)) && info && info[blockIdx.x] == 0) info[blockIdx.x] = k0 + j + 1;
+    }
+    if (p != j && tid < nb) {
+      const T t = Pn[j + tid * mp];
+      Pn[j + tid * mp] = Pn[p + tid * mp];
+      Pn[p + tid * mp] = t;
+    }
+    __syncthreads();
+    const T pj = Pn[j + j * mp];
+    const T inv = abs2(pj) > 0 ? cdiv(Cx<T>::make(1.0, 0.0), pj) : zero<T>();
+    for (int i = j + 1 + tid; i < mp; i += kBlk) {
+      const T l = Pn[i + j * mp] * inv;
+      Pn[i + j * mp] = l;
+      for (int c = j + 1; c < nb; ++c) Pn[i + c * mp] -= l * Pn[j + c * mp];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < mp * nb; t += kBlk) {
+    const int i = t % mp, c = t / mp;
+    A[(k0 + i) + (int64_t)(k0 + c) * lda] = Pn[i + c * mp];
   }
 }
 
-// U12 = L11^{-1} A12 for the columns right of panel k0 (one thread per column)
-template <typename T>
-__global__ void __launch_bounds__(kBlk) k_trsm_u12(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base) {
-  __shared__ T L11[kPanel][kPanel + 1];
+// row interchanges of panel k0 (KP columns) on every column outside it:
+// the panel's interchanges composed into one permutation (simulated on the
+// rows k0.. in LDS by one thread), whose cnt <= 2 KP moved rows are then
+// applied with one thread per (column, moved row): every load of the
+// workgroup before its barrier, every store after it.  A workgroup takes
+// 256 / cnt of the columns outside the panel; the grid covers cnt = 64.
+// Dynamic LDS: n - k0 ints.
+template <typename T, int KP>
+__global__ void __launch_bounds__(256) k_swap_outside(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base,
+                                                      const int* __restrict__ piv) {
+  static_assert(2 * KP <= 64, "at least four columns per workgroup");
+  extern __shared__ int perm[];   // perm[x]: the row (relative to k0) whose entry ends at row x
+  __shared__ int s_row[2 * KP], s_src[2 * KP];
+  __shared__ int s_cnt;
   const LUDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
-  const int nb = min(kPanel, d.n - k0);
+  const int nb = min(KP, d.n - k0), mp = d.n - k0;
+  const int* P = piv + d.piv_off;
+  for (int i = threadIdx.x; i < mp; i += blockDim.x) perm[i] = i;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < nb; ++j) {
+      const int p = P[k0 + j] - k0;
+      if (p != j) {
+        const int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < mp; i += blockDim.x)
+    if (perm[i] != i) {
+      const int q = atomicAdd(&s_cnt, 1);
+      s_row[q] = i;
+      s_src[q] = perm[i];
+    }
+  __syncthreads();
+  const int cnt = s_cnt;
+  if (cnt == 0) return;
+  const int per = 256 / cnt, cl = threadIdx.x / cnt, q = threadIdx.x % cnt;
+  const int oc = blockIdx.x * per + cl;          // index among the columns outside the panel
+  const int c = oc < k0 ? oc : oc + nb;
+  const bool act = cl < per && c < d.n;
+  T* A = base + d.a_off + k0;
+  T v{};
+  if (act) v = A[s_src[q] + (int64_t)c * d.lda];
+  __syncthreads();
+  if (act) A[s_row[q] + (int64_t)c * d.lda] = v;
+}
+
+// U12 = L11^{-1} A12 for the columns right of panel k0 (KP columns; one
+// thread per column)
+template <typename T, int KP>
+__global__ void __launch_bounds__(kBlk) k_trsm_u12(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base) {
+  __shared__ T L11[KP][KP + 1];
+  const LUDesc d = descs[blockIdx.y];
+  if (k0 >= d.n) return;
+  const int nb = min(KP, d.n - k0);
   T* A = base + d.a_off;
   for (int t = threadIdx.x; t < nb * nb; t += kBlk) {
     const int r = t % nb, c = t / nb;
@@ -399,13 +521,13 @@ __global__ void __launch_bounds__(kBlk) k_trsm_u12(const LUDesc* __restrict__ de
   const int c = k0 + nb + blockIdx.x * kBlk + threadIdx.x;
   if (c >= d.n) return;
   T* col = A + (int64_t)c * d.lda + k0;
-  T x[kPanel];
+  T x[KP];
 #pragma unroll
-  for (int r = 0; r < kPanel; ++r) {
+  for (int r = 0; r < KP; ++r) {
     if (r < nb) {
       T s = col[r];
 #pragma unroll
-      for (int q = 0; q < kPanel; ++q)
+      for (int q = 0; q < KP; ++q)
         if (q < r) s -= L11[r][q] * x[q];
       x[r] = s;
       col[r] = s;
@@ -853,14 +975,6 @@ __device__ inline void qr_update_cols(c64* __restrict__ A, int lda, int m, int j
   }
 }
 
-// maximum over the 64 lanes (same DPP pattern as wsum_full; every lane active)
-__device__ inline double wmax_full(double v) {
-  v = fmax(v, dpp_move<0xB1>(v));
-  v = fmax(v, dpp_move<0x4E>(v));
-  v = fmax(v, dpp_move<0x141>(v));
-  v = fmax(v, dpp_move<0x140>(v));
-  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
-}
 
 // TALL = false: the Householder vector is staged in LDS (m <= kQrMaxM,
 // n <= kQrMaxN).  TALL = true: any m, n <= kQrMaxNTall; the vector is read
@@ -1008,19 +1122,6 @@ __global__ void __launch_bounds__(TB) k_cpqr(const CpqrDesc* __restrict__ descs,
   if (tid == 0) rank[blockIdx.x] = j;
 }
 
-// Integer minimum over the 64 lanes (same DPP pattern; every lane active).
-template <int CTRL>
-__device__ inline int dpp_move_int(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-__device__ inline int wmin_int_full(int v) {
-  v = min(v, dpp_move_int<0xB1>(v));
-  v = min(v, dpp_move_int<0x4E>(v));
-  v = min(v, dpp_move_int<0x141>(v));
-  v = min(v, dpp_move_int<0x140>(v));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
 
 // Register-resident pivoted QR for small problems (m <= 64 CH rows, n <= 8 NS
 // columns), same pivot and stopping rules as k_cpqr.  Eight wavefronts;
@@ -1676,6 +1777,23 @@ __global__ void k_flag_nonzero(int64_t n, const int* __restrict__ info, int* __r
 // ------------------------------------------------------------------ launchers
 // All launchers are asynchronous on ``s``: descriptor arrays are device
 // pointers owned by the caller (workspace or factor storage).
+// LDS a workgroup may take on the current device (queried once per device)
+static size_t max_lds_bytes() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  FDS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  FDS_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // the kernels' static LDS (a few hundred bytes) comes on top
+  const size_t b = v > 4096 ? (size_t)v - 4096 : 0;
+  cache[dev] = b;
+  return b;
+}
+
 template <typename T>
 void launch_lu(const LUDesc* d, int n, int nmax, T* base, int* piv, int* info, hipStream_t s) {
   if (n == 0) return;
@@ -1733,35 +1851,66 @@ void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Works
   FDS_HIP(hipMemsetAsync(inf_b, 0, big.size() * sizeof(int), s));
   if (!small.empty()) launch_lu(ws.upload(tag + "_ds", small), (int)small.size(), nsmall, base, piv, inf_s, s);
   const LUDesc* db = ws.upload(tag + "_db", big);
-  for (int k0 = 0; k0 < nbig; k0 += kPanel) {
-    k_panel_lu<T><<<(unsigned)big.size(), kBlk, 0, s>>>(db, k0, base, piv, inf_b);
-    FDS_HIP(hipGetLastError());
-    dim3 gs((unsigned)((nbig + 255) / 256), (unsigned)big.size());
-    k_swap_outside<T><<<gs, 256, 0, s>>>(db, k0, base, piv);
-    FDS_HIP(hipGetLastError());
-    const int rest = nbig - k0 - kPanel;
-    if (rest <= 0) continue;
-    dim3 gt((unsigned)((rest + kBlk - 1) / kBlk), (unsigned)big.size());
-    k_trsm_u12<T><<<gt, kBlk, 0, s>>>(db, k0, base);
-    FDS_HIP(hipGetLastError());
-    std::vector<GemmDesc> gd;
+  // panel width: 32 columns with the panel in LDS when it fits, else 16
+  // columns in LDS, else 32 columns worked in memory
+  const size_t lds_max = max_lds_bytes();
+  const size_t need32 = (size_t)nbig * kPanel * sizeof(T), need16 = (size_t)nbig * 16 * sizeof(T);
+  const int kp = need32 <= lds_max ? kPanel : (need16 <= lds_max ? 16 : kPanel);
+  const bool lds = need32 <= lds_max || need16 <= lds_max;
+  // every panel's trailing update, uploaded once
+  std::vector<GemmDesc> gd;
+  std::vector<GemmTile> gt_all;
+  std::vector<int64_t> g_off, t_off;
+  for (int k0 = 0; k0 < nbig; k0 += kp) {
+    g_off.push_back((int64_t)gd.size());
+    t_off.push_back((int64_t)gt_all.size());
+    const int g0 = (int)gd.size();
     for (const LUDesc& x : big) {
-      const int r = x.n - k0 - kPanel;
+      const int r = x.n - k0 - kp;
       if (r <= 0) continue;
       GemmDesc g{};
-      g.a_off = x.a_off + (k0 + kPanel) + (int64_t)k0 * x.lda;
-      g.b_off = x.a_off + k0 + (int64_t)(k0 + kPanel) * x.lda;
-      g.c_off = x.a_off + (k0 + kPanel) + (int64_t)(k0 + kPanel) * x.lda;
+      g.a_off = x.a_off + (k0 + kp) + (int64_t)k0 * x.lda;
+      g.b_off = x.a_off + k0 + (int64_t)(k0 + kp) * x.lda;
+      g.c_off = x.a_off + (k0 + kp) + (int64_t)(k0 + kp) * x.lda;
       g.m = g.n = r;
-      g.k = kPanel;
+      g.k = kp;
       g.lda = g.ldb = g.ldc = x.lda;
       g.alpha_re = -1.0;
       g.beta_re = 1.0;
       gd.push_back(g);
+      for (int tm = 0; tm * 64 < r; ++tm) gt_all.push_back(GemmTile{(int)gd.size() - 1 - g0, tm});
     }
-    const auto gt2 = gemm_tiles(gd);
-    launch_gemm(ws.upload(tag + "_g", gd), ws.upload(tag + "_gt", gt2), (int)gt2.size(), rest, 0, base, base, base,
-                0, s);
+  }
+  g_off.push_back((int64_t)gd.size());
+  t_off.push_back((int64_t)gt_all.size());
+  const GemmDesc* dgd = ws.upload(tag + "_g", gd);
+  const GemmTile* dgt = ws.upload(tag + "_gt", gt_all);
+  for (int k0 = 0, pi = 0; k0 < nbig; k0 += kp, ++pi) {
+    const size_t shm = (size_t)(nbig - k0) * kp * sizeof(T);
+    if (!lds)
+      k_panel_lu<T><<<(unsigned)big.size(), kBlk, 0, s>>>(db, k0, base, piv, inf_b);
+    else if (kp == kPanel)
+      k_panel_lu_lds<T, kPanel><<<(unsigned)big.size(), kBlk, shm, s>>>(db, k0, base, piv, inf_b);
+    else
+      k_panel_lu_lds<T, 16><<<(unsigned)big.size(), kBlk, shm, s>>>(db, k0, base, piv, inf_b);
+    FDS_HIP(hipGetLastError());
+    dim3 gs((unsigned)((nbig + 3) / 4), (unsigned)big.size());
+    const size_t shs = (size_t)(nbig - k0) * sizeof(int);
+    if (kp == kPanel)
+      k_swap_outside<T, kPanel><<<gs, 256, shs, s>>>(db, k0, base, piv);
+    else
+      k_swap_outside<T, 16><<<gs, 256, shs, s>>>(db, k0, base, piv);
+    FDS_HIP(hipGetLastError());
+    const int rest = nbig - k0 - kp;
+    if (rest <= 0) continue;
+    dim3 gt((unsigned)((rest + kBlk - 1) / kBlk), (unsigned)big.size());
+    if (kp == kPanel)
+      k_trsm_u12<T, kPanel><<<gt, kBlk, 0, s>>>(db, k0, base);
+    else
+      k_trsm_u12<T, 16><<<gt, kBlk, 0, s>>>(db, k0, base);
+    FDS_HIP(hipGetLastError());
+    const int nt = (int)(t_off[pi + 1] - t_off[pi]);
+    launch_gemm(dgd + g_off[pi], dgt + t_off[pi], nt, rest, 0, base, base, base, 0, s);
   }
   if (info) {
     // info slots back in the caller's order
