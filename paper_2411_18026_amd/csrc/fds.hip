@@ -298,6 +298,15 @@ struct fds_factor_s {
   size_t pred_host_n = 0, pred_host_bytes = 0;
   hipEvent_t pred_ev = nullptr;
   std::vector<fds_rank_record> rank_log;    // per compressed cell: features, ranks, prediction
+  // the next level to compress, prepared ahead (disks, interaction matrices)
+  struct LevelPrep {
+    int lev = -1;
+    std::vector<double> crd;                 // per cell: centre x, y and proxy radius
+    std::vector<int> mv_m, mu_m;             // rows of M^V, M^U^T per cell
+    std::vector<int64_t> mv_off, mu_off;
+    fds::c64* MV = nullptr;
+    fds::c64* MU = nullptr;
+  } prep;
   std::map<int64_t, hipGraphExec_t> graphs; // captured solve sweeps per (nrhs, kind)
   hipStream_t gstream = nullptr;            // library stream for graph capture and replay
   ~fds_factor_s() {
@@ -1089,7 +1098,9 @@ static void record_ranks(Factor& F, int lev, const std::vector<double>& crd, con
   F.st.cells_compressed += lv.n;
 }
 
-static void compress_level(Factor& F, int lev) {
+// Proxy disks, near sets and the interaction matrices M^V, M^U^T of level
+// lev (Sections 7.1, 7.2), enqueued; the IDs follow in compress_level.
+static void prepare_level(Factor& F, int lev) {
   const Geometry& G = F.G;
   CellLevel& lv = F.levels[lev];
   Workspace& ws = F.ws;
@@ -1108,15 +1119,22 @@ static void compress_level(Factor& F, int lev) {
   });
   for (int q = 0; q < n; ++q) maxrho = std::max(maxrho, crd[3 * q + 2]);
   // near sets via a node grid
+  // (the cells' row DOFs are disjoint, and so are their column DOFs)
   std::vector<int> row_owner(2 * (size_t)G.n_nodes, -1), col_owner(2 * (size_t)G.n_nodes, -1);
-  for (int q = 0; q < n; ++q) {
-    for (auto d : lv.rows[q]) row_owner[d] = q;
-    for (auto d : lv.cols[q]) col_owner[d] = q;
-  }
+  std::vector<char> has(G.n_nodes, 0);
+  parallel_for(n, [&](int q) {
+    for (auto d : lv.rows[q]) {
+      row_owner[d] = q;
+      __atomic_store_n(&has[d >> 1], (char)1, __ATOMIC_RELAXED);
+    }
+    for (auto d : lv.cols[q]) {
+      col_owner[d] = q;
+      __atomic_store_n(&has[d >> 1], (char)1, __ATOMIC_RELAXED);
+    }
+  });
   std::vector<int> active;
   for (int t = 0; t < G.n_nodes; ++t)
-    if (row_owner[2 * t] >= 0 || row_owner[2 * t + 1] >= 0 || col_owner[2 * t] >= 0 || col_owner[2 * t + 1] >= 0)
-      active.push_back(t);
+    if (has[t]) active.push_back(t);
   NodeGrid grid;
   grid.build(G, active, std::max(maxrho, 4.0 * G.hmax));
   std::vector<std::vector<int64_t>> near_r(n), near_c(n);
@@ -1199,8 +1217,31 @@ static void compress_level(Factor& F, int lev) {
     HostTimer hp(8);
     assemble_blocks(reqs, F.DG.elems.p, F.m, MU, ws, &F.ast);
   }
-
   ht1.reset();
+  Factor::LevelPrep& pr = F.prep;
+  pr.lev = lev;
+  pr.crd = std::move(crd);
+  pr.mv_m = std::move(mv_m);
+  pr.mu_m = std::move(mu_m);
+  pr.mv_off = std::move(mv_off);
+  pr.mu_off = std::move(mu_off);
+  pr.MV = MV;
+  pr.MU = MU;
+}
+
+static void compress_level(Factor& F, int lev) {
+  CellLevel& lv = F.levels[lev];
+  Workspace& ws = F.ws;
+  hipStream_t s = F.stream;
+  const int n = lv.n;
+  if (F.prep.lev != lev) throw Error(1, "internal: level " + std::to_string(lev) + " was not prepared");
+  const std::vector<double>& crd = F.prep.crd;
+  const std::vector<int>& mv_m = F.prep.mv_m;
+  const std::vector<int>& mu_m = F.prep.mu_m;
+  const std::vector<int64_t>& mv_off = F.prep.mv_off;
+  const std::vector<int64_t>& mu_off = F.prep.mu_off;
+  c64* MV = F.prep.MV;
+  c64* MU = F.prep.MU;
   // IDs: per cell V comp0, V comp1 (in MV) and U comp0, U comp1 (in MU^T)
   span_begin(F, 0);
   std::vector<CpqrDesc> qv(2 * n), qu(2 * n);
@@ -1342,14 +1383,12 @@ static void compress_level(Factor& F, int lev) {
   F.st.max_rank = std::max(F.st.max_rank, mr);
 }
 
-// Parent diagonal blocks of level lev-1 from level lev (rearrangement, Section 6.2).
-static void merge_to_parent(Factor& F, int lev) {
+// Parent DOF lists of level lev-1 from level lev (rearrangement, Section 6.2)
+// and the layout of the parent blocks.
+static void merge_lists(Factor& F, int lev) {
   HostTimer ht(3);
-  const Geometry& G = F.G;
   CellLevel& ch = F.levels[lev];
   CellLevel& pa = F.levels[lev - 1];
-  Workspace& ws = F.ws;
-  hipStream_t s = F.stream;
   pa.lev = lev - 1;
   pa.n = ch.n / 2;
   pa.rows.assign(pa.n, {});
@@ -1380,6 +1419,18 @@ static void merge_to_parent(Factor& F, int lev) {
     for (int j = 0; j < kb1; ++j) pb_.push_back(ka0 + kb0 + ka1 + j);
   }
   layout_blocks(pa);
+}
+
+// The parent blocks' entries: the children's A~ and the off-diagonal
+// interactions at skeleton pairs (enqueued after the parent level's
+// interaction matrices, which need only the parent DOF lists).
+static void merge_blocks(Factor& F, int lev) {
+  HostTimer ht(3);
+  const Geometry& G = F.G;
+  CellLevel& ch = F.levels[lev];
+  CellLevel& pa = F.levels[lev - 1];
+  Workspace& ws = F.ws;
+  hipStream_t s = F.stream;
   // diagonal sub-blocks: A~ of the children (plain form); the mixed form
   // keeps them out of the FP64 block and adds its FP32 A~ when the parent
   // level is eliminated
@@ -1389,22 +1440,21 @@ static void merge_to_parent(Factor& F, int lev) {
     place_child_at_t(F, lev - 1, [&](int p) { return pa.a_off[p]; }, [&](int p) { return pa.b[p]; }, ch.At.p,
                      pa.A.p, "c64");
   // off-diagonal: R_ab = A(rskel_a, cskel_b), R_ba = A(rskel_b, cskel_a)
-  std::vector<BlockReq> reqs;
-  for (int p = 0; p < pa.n; ++p) {
-    for (int side = 0; side < 2; ++side) {
-      const int a = 2 * p + side, b = 2 * p + 1 - side;
-      if (ch.r[a] == 0 || ch.r[b] == 0) continue;
-      BlockReq q;
-      q.rows = side_from_dofs(G, ch.rskel[a]);
-      q.cols = side_from_dofs(G, ch.cskel[b]);
-      q.out_off = pa.a_off[p];
-      q.rs = 1;
-      q.cs = pa.b[p];
-      q.rpos = ch.ppos[a];
-      q.cpos = ch.ppos[b];
-      reqs.push_back(std::move(q));
-    }
-  }
+  std::vector<int> pick;   // child a of each request (b = a ^ 1)
+  for (int a = 0; a < 2 * pa.n; ++a)
+    if (ch.r[a] != 0 && ch.r[a ^ 1] != 0) pick.push_back(a);
+  std::vector<BlockReq> reqs(pick.size());
+  parallel_for((int)pick.size(), [&](int k) {
+    const int a = pick[k], b = a ^ 1, p = a >> 1;
+    BlockReq& q = reqs[k];
+    q.rows = side_from_dofs(G, ch.rskel[a]);
+    q.cols = side_from_dofs(G, ch.cskel[b]);
+    q.out_off = pa.a_off[p];
+    q.rs = 1;
+    q.cs = pa.b[p];
+    q.rpos = ch.ppos[a];
+    q.cpos = ch.ppos[b];
+  });
   assemble_blocks(reqs, F.DG.elems.p, F.m, pa.A.p, ws, &F.ast);
 }
 
@@ -2214,9 +2264,14 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
     const int64_t proxy_cap = (int64_t)F->levels[F->L].n * o.n_proxy;
     F->DG.init(F->G, proxy_cap, F->stream);
     assemble_leaves(*F);
+    // level lev - 1's interaction matrices are enqueued behind level lev's
+    // elimination (their host work overlaps it), before the parent blocks
+    if (F->L > F->l0) prepare_level(*F, F->L);
     for (int lev = F->L; lev > F->l0; --lev) {
       compress_level(*F, lev);
-      merge_to_parent(*F, lev);
+      merge_lists(*F, lev);
+      if (lev - 1 > F->l0) prepare_level(*F, lev - 1);
+      merge_blocks(*F, lev);
     }
     factor_root(*F);
     build_solve_plan(*F);
