@@ -101,12 +101,12 @@ __device__ inline void acc_point_direct(const MatConst& m, double dx, double dy,
   const double r = r2 * ir;
   const double e0 = dx * ir, e1 = dy * ir;
   const double je0 = -e1, je1 = e0;
-  const double a = m.kT * r;
+  const double a = m.kT * r, ia = ir * m.ikT;
   c64 h0a, h1a, h0b, E, chi;
   if (SER)
-    kernel_values_series(a, m.sc, h0a, h1a, h0b, E, chi);
+    kernel_values_series(a, ia, m.sc, h0a, h1a, h0b, E, chi);
   else
-    kernel_values(a, m.sc, h0a, h1a, h0b, E, chi);
+    kernel_values(a, ia, m.sc, h0a, h1a, h0b, E, chi);
   const c64 phiT = cmk(-0.25 * h0a.im, 0.25 * h0a.re);
   const c64 phiL = cmk(-0.25 * h0b.im, 0.25 * h0b.re);
   const c64 q = cmk(-0.25 * m.kT * h1a.im, 0.25 * m.kT * h1a.re);   // (i/4) k_T H1(a)

@@ -28,6 +28,7 @@ struct Elem {
 // Material constants needed by the kernels.
 struct MatConst {
   double kT, kL, beta, mu, rw2;   // rw2 = rho omega^2
+  double ikT;                     // 1 / kT
   double alpha_re, alpha_im;
   SeriesCoef sc;                  // small-argument expansions for this beta
 };

@@ -109,6 +109,7 @@ static MatConst make_mat(double omega, double lam, double mu, double rho, const 
   const double cL = std::sqrt((lam + 2.0 * mu) / rho), cT = std::sqrt(mu / rho);
   m.kL = omega / cL;
   m.kT = omega / cT;
+  m.ikT = 1.0 / m.kT;
   m.beta = m.kL / m.kT;
   m.mu = mu;
   m.rw2 = rho * omega * omega;

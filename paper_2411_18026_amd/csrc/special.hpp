@@ -401,10 +401,11 @@ __host__ __device__ inline void e_chi(double a, double beta, const Hankel2& h, c
   chi = h2a - (beta * beta) * h2b;
 }
 
-// Small-argument form of the kernel ingredients with K terms of each series.
+// Small-argument form of the kernel ingredients with K terms of each series
+// (ia = 1/a, which the caller has from its own reciprocal square root).
 template <int K>
-__host__ __device__ inline void series_values(double a, double w, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b,
-                                              c64& E, c64& chi) {
+__host__ __device__ inline void series_values(double a, double ia, double w, const SeriesCoef& sc, c64& h0a,
+                                              c64& h1a, c64& h0b, c64& E, c64& chi) {
   const double wb = sc.b2 * w;
   const double L = log_pos(0.5 * a);
   const double tp = 2.0 / kPi;
@@ -413,7 +414,7 @@ __host__ __device__ inline void series_values(double a, double w, const SeriesCo
                Q7 = ser<K, 5>(wb);
   const double j1 = 0.5 * a * P2;
   h0a = cmk(P0, tp * ((L + kEulerGamma) * P0 + P1));
-  h1a = cmk(j1, -tp / a + tp * L * j1 - (0.5 * a / kPi) * P3);
+  h1a = cmk(j1, -tp * ia + tp * L * j1 - (a * (0.5 / kPi)) * P3);
   h0b = cmk(Q0, tp * ((L + sc.logbeta + kEulerGamma) * Q0 + Q1));
   const double e = 0.5 * (P2 - sc.b2 * Q2);
   const double e1 = -(0.5 / kPi) * (P3 - sc.b2 * Q3) - (sc.logbeta / kPi) * sc.b2 * Q2;
@@ -429,23 +430,23 @@ __host__ __device__ inline void series_values(double a, double w, const SeriesCo
 // terms for w < 1e-4, 6 for w < 5e-3, 8 for w < 5e-2, else 10).  The choice
 // depends on the point alone, so a result does not depend on which other
 // points share its wavefront.
-__host__ __device__ inline void kernel_values_series(double a, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b,
-                                                     c64& E, c64& chi) {
+__host__ __device__ inline void kernel_values_series(double a, double ia, const SeriesCoef& sc, c64& h0a, c64& h1a,
+                                                     c64& h0b, c64& E, c64& chi) {
   const double w = 0.25 * a * a;
   if (w >= 5e-2)
-    series_values<10>(a, w, sc, h0a, h1a, h0b, E, chi);
+    series_values<10>(a, ia, w, sc, h0a, h1a, h0b, E, chi);
   else if (w >= 5e-3)
-    series_values<8>(a, w, sc, h0a, h1a, h0b, E, chi);
+    series_values<8>(a, ia, w, sc, h0a, h1a, h0b, E, chi);
   else if (w >= 1e-4)
-    series_values<6>(a, w, sc, h0a, h1a, h0b, E, chi);
+    series_values<6>(a, ia, w, sc, h0a, h1a, h0b, E, chi);
   else
-    series_values<4>(a, w, sc, h0a, h1a, h0b, E, chi);
+    series_values<4>(a, ia, w, sc, h0a, h1a, h0b, E, chi);
 }
 
-__host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b, c64& E,
-                                              c64& chi) {
+__host__ __device__ inline void kernel_values(double a, double ia, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b,
+                                              c64& E, c64& chi) {
   if (a < kSeriesSwitch) {
-    kernel_values_series(a, sc, h0a, h1a, h0b, E, chi);
+    kernel_values_series(a, ia, sc, h0a, h1a, h0b, E, chi);
     return;
   }
   const Hankel2 h = hankel_pair(a, sc.beta * a);
@@ -453,6 +454,10 @@ __host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c6
   h1a = h.h1a;
   h0b = h.h0b;
   e_chi(a, sc.beta, h, E, chi);
+}
+__host__ __device__ inline void kernel_values(double a, const SeriesCoef& sc, c64& h0a, c64& h1a, c64& h0b, c64& E,
+                                              c64& chi) {
+  kernel_values(a, 1.0 / a, sc, h0a, h1a, h0b, E, chi);
 }
 
 }  // namespace fds
