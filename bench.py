@@ -318,21 +318,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# FP64 operations per quadrature-point kernel evaluation (per-unit figure of
-# the assembly: Hankel functions at k_T r and k_L r plus the tensor algebra
-# of the four 2x2 kernel blocks and their accumulation)
 # FP64 flops per quadrature point of each pair-integration kernel on the
 # headline workload, counted with rocprofv3 (SQ_INSTS_VALU_FMA_F64 x 2 +
 # ADD_F64 + MUL_F64, x 64 lanes, over the points the kernel integrated):
 # profiles/pair_kernels_ellipse131072_tol1e-11.md
-FLOP_PER_POINT = {"k_regular<0, false>": 1157.9, "k_regular<0, true>": 732.8, "k_regular<1, false>": None,
-                  "k_regular<1, true>": 588.6, "k_regular<2, false>": 1171.9, "k_regular<2, true>": 563.6,
-                  "k_regular<3, false>": 1199.0, "k_regular<3, true>": 553.4, "k_regular_wave10": 864.1,
-                  "k_special<1>": 1076.7, "k_special2<2>": 654.0, "k_special2<3>": 654.0}
+FLOP_PER_POINT = {"k_regular<0, false>": 1156.3, "k_regular<0, true>": 708.9, "k_regular<1, false>": None,
+                  "k_regular<1, true>": 565.7, "k_regular<2, false>": 1163.5, "k_regular<2, true>": 540.5,
+                  "k_regular<3, false>": 1187.9, "k_regular<3, true>": 530.4, "k_regular_wave10": 834.7,
+                  "k_special<1>": 1039.9, "k_special2<2>": 628.4, "k_special2<3>": 628.4}
 # HBM bytes per launch of a pair kernel from two counter runs (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
 # for a plain 1 GiB device copy (2.0 and 1.0): same profile
-TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (115534 * 2.0 + 865814 * 1.0) * 1024}
+TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (120294 * 2.0 + 866070 * 1.0) * 1024}
 
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")
