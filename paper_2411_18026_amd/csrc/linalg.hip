@@ -504,6 +504,28 @@ __global__ void __launch_bounds__(256) k_swap_outside(const LUDesc* __restrict__
   if (act) A[s_row[q] + (int64_t)c * d.lda] = v;
 }
 
+// The same interchanges one column per thread, in sequence (rows too many
+// for the composed permutation in LDS)
+template <typename T, int KP>
+__global__ void k_swap_outside_seq(const LUDesc* __restrict__ descs, int k0, T* __restrict__ base,
+                                   const int* __restrict__ piv) {
+  const LUDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k0 >= d.n || c >= d.n) return;
+  const int nb = min(KP, d.n - k0);
+  if (c >= k0 && c < k0 + nb) return;
+  T* col = base + d.a_off + (int64_t)c * d.lda;
+  const int* P = piv + d.piv_off;
+  for (int j = 0; j < nb; ++j) {
+    const int p = P[k0 + j];
+    if (p != k0 + j) {
+      const T t = col[k0 + j];
+      col[k0 + j] = col[p];
+      col[p] = t;
+    }
+  }
+}
+
 // U12 = L11^{-1} A12 for the columns right of panel k0 (KP columns; one
 // thread per column)
 template <typename T, int KP>
@@ -599,12 +621,11 @@ __device__ inline void load_permuted(const T* __restrict__ B, int64_t ldb, const
   __syncthreads();
 }
 
-template <typename T, bool WIDE>
+template <typename T, bool WIDE, bool GX = false>
 __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__ descs, int chunk, int ncol_override,
                                                    const T* __restrict__ abase, const int* __restrict__ piv,
                                                    T* __restrict__ bbase, int staged) {
   extern __shared__ unsigned char smem_sv[];
-  T* X = reinterpret_cast<T*>(smem_sv);
   const SolveDesc d = descs[blockIdx.x];
   const int ncol = ncol_override > 0 ? ncol_override : d.ncol;
   const int c0 = blockIdx.y * chunk;
@@ -614,8 +635,25 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
   T* B = bbase + d.b_off + (int64_t)c0 * d.ldb;
   const int n = d.n, lda = d.lda, nc = min(chunk, ncol - c0);
   const int tid = threadIdx.x;
-  int* perm = reinterpret_cast<int*>(X + (size_t)n * chunk);
-  load_permuted(B, d.ldb, P, n, nc, nc, X, perm, perm + n, staged);
+  // GX: the columns are solved in place in memory (a block too large for
+  // LDS); else staged in LDS
+  T* X = GX ? B : reinterpret_cast<T*>(smem_sv);
+  const int64_t ldx = GX ? d.ldb : n;
+  if (GX) {
+    if (tid < nc)
+      for (int j = 0; j < n; ++j) {
+        const int p = P[j];
+        if (p != j) {
+          const T t = X[j + tid * ldx];
+          X[j + tid * ldx] = X[p + tid * ldx];
+          X[p + tid * ldx] = t;
+        }
+      }
+    __syncthreads();
+  } else {
+    int* perm = reinterpret_cast<int*>(X + (size_t)n * chunk);
+    load_permuted(B, d.ldb, P, n, nc, nc, X, perm, perm + n, staged);
+  }
   const int cc = tid % nc;
   const int r0 = tid / nc;
   const int rs = kBlk / nc;
@@ -628,7 +666,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     for (int cg = 0; cg < (WIDE ? nc : 1) && tid < 8 * 16; cg += 8) {   // two wavefronts, 8 columns at a time
       const int col = cg + bc;
       const bool act = col < nc && br < nb;
-      T x = act ? X[k0 + br + col * n] : zero<T>();
+      T x = act ? X[k0 + br + col * ldx] : zero<T>();
       T l[SB];
 #pragma unroll
       for (int q = 0; q < SB; ++q) l[q] = (act && q < br) ? A[(k0 + br) + (int64_t)(k0 + q) * lda] : zero<T>();
@@ -637,22 +675,22 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         const T xq = row_bcast(x, q);
         if (br > q) cfms(x, l[q], xq);
       }
-      if (act) X[k0 + br + col * n] = x;
+      if (act) X[k0 + br + col * ldx] = x;
     }
     __syncthreads();
     if (r0 < rs)
       for (int i = k0 + nb + r0; i < n; i += rs) {
-        T s = X[i + cc * n];
+        T s = X[i + cc * ldx];
         if (nb == SB) {   // full block: all loads of the factor in flight at once
           T a[SB];
 #pragma unroll
           for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
 #pragma unroll
-          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * n]);
+          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * ldx]);
         } else {
-          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * n]);
+          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * ldx]);
         }
-        X[i + cc * n] = s;
+        X[i + cc * ldx] = s;
       }
     __syncthreads();
   }
@@ -662,7 +700,7 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
     for (int cg = 0; cg < (WIDE ? nc : 1) && tid < 8 * 16; cg += 8) {
       const int col = cg + bc;
       const bool act = col < nc && br < nb;
-      T x = act ? X[k0 + br + col * n] : zero<T>();
+      T x = act ? X[k0 + br + col * ldx] : zero<T>();
       T u[SB];
 #pragma unroll
       for (int q = 0; q < SB; ++q)
@@ -674,29 +712,30 @@ __global__ void __launch_bounds__(kBlk) k_lu_solve(const SolveDesc* __restrict__
         const T xq = row_bcast(x, q);
         if (q < nb && br < q) cfms(x, u[q], xq);
       }
-      if (act) X[k0 + br + col * n] = x;
+      if (act) X[k0 + br + col * ldx] = x;
     }
     __syncthreads();
     if (r0 < rs)
       for (int i = r0; i < k0; i += rs) {
-        T s = X[i + cc * n];
+        T s = X[i + cc * ldx];
         if (nb == SB) {
           T a[SB];
 #pragma unroll
           for (int q = 0; q < SB; ++q) a[q] = A[i + (int64_t)(k0 + q) * lda];
 #pragma unroll
-          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * n]);
+          for (int q = 0; q < SB; ++q) cfms(s, a[q], X[k0 + q + cc * ldx]);
         } else {
-          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * n]);
+          for (int q = 0; q < nb; ++q) cfms(s, A[i + (int64_t)(k0 + q) * lda], X[k0 + q + cc * ldx]);
         }
-        X[i + cc * n] = s;
+        X[i + cc * ldx] = s;
       }
     __syncthreads();
   }
-  for (int t = tid; t < n * nc; t += kBlk) {
-    const int i = t % n, c = t / n;
-    B[i + (int64_t)c * d.ldb] = X[i + c * n];
-  }
+  if (!GX)
+    for (int t = tid; t < n * nc; t += kBlk) {
+      const int i = t % n, c = t / n;
+      B[i + (int64_t)c * d.ldb] = X[i + c * n];
+    }
 }
 
 // Triangular solves with many right-hand sides, NC (16 or 32) columns per
@@ -1896,7 +1935,10 @@ void lu_factor(const std::vector<LUDesc>& d, T* base, int* piv, int* info, Works
     FDS_HIP(hipGetLastError());
     dim3 gs((unsigned)((nbig + 3) / 4), (unsigned)big.size());
     const size_t shs = (size_t)(nbig - k0) * sizeof(int);
-    if (kp == kPanel)
+    if (shs > lds_max)
+      k_swap_outside_seq<T, kPanel><<<dim3((unsigned)((nbig + 255) / 256), (unsigned)big.size()), 256, 0, s>>>(
+          db, k0, base, piv);
+    else if (kp == kPanel)
       k_swap_outside<T, kPanel><<<gs, 256, shs, s>>>(db, k0, base, piv);
     else
       k_swap_outside<T, 16><<<gs, 256, shs, s>>>(db, k0, base, piv);
@@ -1954,7 +1996,14 @@ void launch_lu_solve(const SolveDesc* d, int n, int nmax, int ncol_max, int ncol
   constexpr size_t kLdsMax = 160 * 1024;
   const int staged = lu_solve_smem(nmax, nc, sizeof(T)) <= kLdsMax ? 1 : 0;
   const size_t smem = staged ? lu_solve_smem(nmax, nc, sizeof(T)) : (size_t)std::max(1, nmax) * nc * sizeof(T);
-  if (smem > kLdsMax) throw Error(1, "lu_solve: matrix too large for LDS staging");
+  if (smem > kLdsMax) {
+    // solved in place in memory, 8 columns per workgroup
+    const int ng = 8;
+    dim3 grid(n, (ncol_max + ng - 1) / ng);
+    k_lu_solve<T, true, true><<<grid, kBlk, 0, s>>>(d, ng, ncol_override, abase, piv, bbase, 0);
+    FDS_HIP(hipGetLastError());
+    return;
+  }
   if (smem > 65536) {
     FDS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lu_solve<T, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));

@@ -63,3 +63,27 @@ def test_tripod_error_ladder(fdsmod, n):
     if n > 400:
         e1, _ = _error(fdsmod, n, 1e-8, True, A)
         assert e1 < 10.0 * paper[(2, n, 1e-8)], (n, e1)
+
+
+def test_large_root_solved_in_memory(fdsmod):
+    """The single-level tripod at 25600 nodes (Table 2's largest row in the
+    bench) has a root of about 18000 unknowns: its LU runs the
+    multi-workgroup form with panels in memory and row interchanges one
+    column per thread, and its solve, too large for LDS, runs in place in
+    memory.  Its solution agrees with the multi-level factor's (root at
+    level 1, a few hundred unknowns) to the compression error: both are
+    within about 1e-7 of the dense solution at tol 1e-10 (Tables 1 and 2),
+    a wrong root solve would be off by order one."""
+    n, tol = 25600, 1e-10
+    xs = []
+    for single in (True, False):
+        c = sy.config_tripod(n, tol, single)
+        F = fdsmod.Factor(c["curves"], c["omega"], c["lam"], c["mu"], c["rho"], tol, leaf=c["leaf"],
+                          root_level=c["root_level"], autotune=False)
+        if single:
+            assert F.stats()["root_size"] > 10000
+        b = F.rhs_plane([0, 1], [0.0, 0.7])
+        xs.append(F.solve(b))
+        del F
+    d = torch.linalg.norm(xs[0] - xs[1], dim=1) / torch.linalg.norm(xs[1], dim=1)
+    assert float(d.max()) < 1e-5, d
