@@ -778,7 +778,7 @@ def complexity_ladder(fds, tol, exps=(12, 13, 14, 15, 16, 17), dense_max_exp=14,
         rows.append(row)
     big = rows[-4:]
     slope = float(np.polyfit(np.log([r["nodes"] for r in big]), np.log([r["factor_s"] for r in big]), 1)[0])
-    return {"workload": f"ellipse 1x0.5, 2^{exps[0]}..2^{exps[-1]} nodes, omega 4, leaf 64, tol 1e-8, {nrhs} P-waves",
+    return {"workload": f"ellipse 1x0.5, 2^{exps[0]}..2^{exps[-1]} nodes, omega 4, leaf 64, tol {tol:g}, {nrhs} P-waves",
             "rows": rows, "factor_time_slope_log_log": round(slope, 3)}
 
 

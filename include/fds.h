@@ -403,10 +403,12 @@ int fds_interp_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t
  * overwritten by L (unit lower, below the diagonal) and U; piv (device int32,
  * n[p] entries at pivoff[p]) records that row k was swapped with row piv[k]
  * at step k (0-based).  Pivot: largest modulus in the column, lowest row on
- * ties.  Matrices up to 768 rows are factored by one workgroup each with the
- * panel in LDS, larger ones by the multi-workgroup blocked form (panels of
- * 32 columns).  info (host int32 [np]): 0, or 1 + the first step with a zero
- * or non-finite pivot.  Synchronous. */
+ * ties.  Matrices up to 384 rows are factored by one workgroup each with the
+ * panel in LDS (except those above 128 rows in a batch of at most 8),
+ * larger ones by the multi-workgroup blocked form (panels of 32 or 16
+ * columns in LDS when they fit, else in memory).  info (host int32 [np]):
+ * 0, or 1 + the first step with a zero or non-finite pivot (that column
+ * keeps its row).  Synchronous. */
 int fds_lu_batched(int32_t np, fds_c64* a, const int64_t* off, const int64_t* n, int32_t* piv,
                    const int64_t* pivoff, int32_t* info, void* stream);
 

@@ -23,6 +23,11 @@ def fdsmod():
     return m
 
 
+# about twice the measured errors (3.0e-7, 6.7e-7, 8.0e-6): a regression of
+# the compression at any size fails
+ERR_BOUND = {12: 6e-7, 13: 1.4e-6, 14: 1.6e-5}
+
+
 def test_ranks_bounded_under_refinement(fdsmod):
     stats = []
     for e in (12, 13, 14):
@@ -38,8 +43,9 @@ def test_ranks_bounded_under_refinement(fdsmod):
         A = fdsmod.entries(curves, 4.0, 2.0, 1.0, 1.0, dofs, dofs)
         xd = torch.linalg.solve(A, b[0])
         err = float(torch.linalg.norm(x - xd) / torch.linalg.norm(xd))
+        print(f"ellipse {n} nodes: max rank {st['max_rank']}, root {st['root_size']}, error {err:.2e}", flush=True)
         del A, F
-        assert err < 5e-5, (n, err)
+        assert err < ERR_BOUND[e], (n, err)
     lev = [s["levels"] for s in stats]
     assert lev[1] == lev[0] + 1 and lev[2] == lev[1] + 1
     ranks = [s["max_rank"] for s in stats]

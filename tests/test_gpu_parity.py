@@ -283,11 +283,17 @@ def test_cpqr_tall_variant_matches_oracle(fdsmod):
 def test_lu_batched_is_a_partial_pivoting_lu(fdsmod):
     """P A = L U to rounding with |L| <= 1 and every pivot the column's
     largest modulus, for sizes on both sides of the one-workgroup limit
-    (768): the LDS-panel kernels and the multi-workgroup blocked form."""
+    (384 rows; 128 in batches of at most 8): the one-workgroup kernel (7),
+    and the multi-workgroup blocked form with 32-column panels in LDS (130,
+    300), 16-column panels in LDS (500) and panels in memory (900, 1300)."""
     rng = np.random.default_rng(12)
-    sizes = [7, 130, 700, 900, 1300]
-    mats = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in sizes]
-    for A, (LU, piv, info) in zip(mats, fdsmod.lu_batched(mats)):
+    batches = [[7, 130, 300], [500], [900, 1300]]
+    mats, res = [], []
+    for sizes in batches:
+        ms = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in sizes]
+        mats += ms
+        res += fdsmod.lu_batched(ms)
+    for A, (LU, piv, info) in zip(mats, res):
         n = A.shape[0]
         assert info == 0
         L = np.tril(LU, -1) + np.eye(n)
@@ -298,10 +304,17 @@ def test_lu_batched_is_a_partial_pivoting_lu(fdsmod):
             PA[[k, piv[k]]] = PA[[piv[k], k]]
         assert np.linalg.norm(PA - L @ U) <= 1e-13 * n * np.linalg.norm(A)
         assert np.abs(L).max() <= 1.0 + 1e-12
-    # a zero column is reported at its step
+    # a zero column is reported at its step, by each form: panels in memory
+    # (900), in LDS (300), and the one-workgroup kernel (a batch of nine 100s)
     Z = rng.standard_normal((900, 900)) + 0j
     Z[:, 5] = 0.0
     assert fdsmod.lu_batched([Z])[0][2] == 6
+    Z = rng.standard_normal((300, 300)) + 0j
+    Z[:, 40] = 0.0
+    assert fdsmod.lu_batched([Z])[0][2] == 41
+    Zs = [rng.standard_normal((100, 100)) + 0j for _ in range(9)]
+    Zs[4][:, 17] = 0.0
+    assert [r[2] for r in fdsmod.lu_batched(Zs)] == [0, 0, 0, 0, 18, 0, 0, 0, 0]
 
 
 def test_autotuned_shapes_give_identical_solutions(fdsmod):
