@@ -18,6 +18,8 @@
 // cache by an allocator of its own (fds_set_allocator).
 #pragma once
 
+#include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -117,6 +119,45 @@ struct DevBuf {
     }
     return h;
   }
+};
+
+// A device array inside an arena (not owning).
+template <typename T>
+struct DevView {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+// Many small host arrays placed in one device allocation and sent with one
+// copy: each allocation through a caller's allocator and each copy from
+// pageable memory costs tens of microseconds, and a solve plan has a hundred
+// arrays.  add() records an array and the view to point at it; finish()
+// allocates the arena (256-byte aligned slices), uploads it and sets the
+// views.
+class ArenaBuilder {
+ public:
+  template <typename T>
+  void add(DevView<T>& v, const std::vector<T>& h) {
+    v.n = h.size();
+    v.p = nullptr;   // an empty array stays null
+    if (h.empty()) return;
+    const size_t off = (data_.size() + 255) / 256 * 256;
+    data_.resize(off + h.size() * sizeof(T));
+    std::memcpy(data_.data() + off, h.data(), h.size() * sizeof(T));
+    T** where = &v.p;
+    fix_.push_back([where, off](unsigned char* base) { *where = reinterpret_cast<T*>(base + off); });
+  }
+  // inside an AllocScope: a stream-ordered upload on its stream
+  void finish(DevBuf<unsigned char>& arena) {
+    arena = DevBuf<unsigned char>(data_);
+    for (auto& f : fix_) f(arena.p);
+    data_.clear();
+    fix_.clear();
+  }
+
+ private:
+  std::vector<unsigned char> data_;
+  std::vector<std::function<void(unsigned char*)>> fix_;
 };
 
 // Named grow-only device buffers.  A buffer is reallocated only when a

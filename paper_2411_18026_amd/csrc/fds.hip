@@ -202,14 +202,15 @@ static void side_append(const Geometry& G, Side& sd, const std::vector<int64_t>&
 // ------------------------------------------------------------------ factor data
 // Device-resident solve plan of one compressed level (built once per factor).
 struct SolveLevel {
-  DevBuf<SolveDesc> lu;                      // g_i = A_i^{-1} f_i (ncol given at solve time)
-  DevBuf<GemmDesc> g_v, g_at, g_dn1, g_dn2;  // V g, A~ (V g), A~ y - f~, g + X f~
-  DevBuf<GemmTile> t_v, t_at, t_dn1, t_dn2;
+  // arrays in the factor's plan arena
+  DevView<SolveDesc> lu;                       // g_i = A_i^{-1} f_i (ncol given at solve time)
+  DevView<GemmDesc> g_v, g_at, g_dn1, g_dn2;   // V g, A~ (V g), A~ y - f~, g + X f~
+  DevView<GemmTile> t_v, t_at, t_dn1, t_dn2;
   int n_lu = 0, n_tv = 0, n_tat = 0, n_tdn1 = 0, n_tdn2 = 0, bmax = 0;
-  DevBuf<GemmDesc> g_w;                      // matrix-core levels: f~ = W g (W = A~ V), for few columns
-  DevBuf<GemmTile> t_w;
+  DevView<GemmDesc> g_w;                       // matrix-core levels: f~ = W g (W = A~ V), for few columns
+  DevView<GemmTile> t_w;
   int n_tw = 0;
-  DevBuf<int64_t> up_src, up_dst;            // rows of f~ -> rows of the parent's F
+  DevView<int64_t> up_src, up_dst;             // rows of f~ -> rows of the parent's F
   int64_t n_up = 0;
 };
 
@@ -251,8 +252,8 @@ struct CellLevel {
   DevBuf<int> perm;
   DevBuf<c64> Dinv;
   // compressed-operator product (mixed form): y = B z per cell
-  DevBuf<GemmDesc> g_diag;
-  DevBuf<GemmTile> t_diag;
+  DevView<GemmDesc> g_diag;   // in the factor's plan arena
+  DevView<GemmTile> t_diag;
   int n_tdiag = 0;
 };
 
@@ -290,7 +291,8 @@ struct fds_factor_s {
   fds_stats st{};
   hipStream_t stream = nullptr;
   fds::Workspace ws;
-  fds::DevBuf<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
+  fds::DevBuf<unsigned char> plan_arena;    // the solve's descriptors and row maps (one allocation)
+  fds::DevView<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
   fds::DevBuf<int> sing;                    // per level: a block LU met a zero pivot
   int tune_chunk[4] = {0, 0, 0, 0};         // autotuned LU-solve columns per workgroup per nrhs class
@@ -1545,7 +1547,7 @@ static void factor_root(Factor& F) {
 // block orders have a variant, W_i = A~_i V_i (replacing V_i: the upward
 // sweep needs only the product), the LU's composed permutation and the
 // inverted diagonal blocks.
-static void prepare_mfma_sweeps(Factor& F) {
+static void prepare_mfma_sweeps(Factor& F, ArenaBuilder& ab) {
   hipStream_t s = F.stream;
   Workspace& ws = F.ws;
   for (int lev = F.L; lev > F.l0; --lev) {
@@ -1622,8 +1624,8 @@ static void prepare_mfma_sweeps(Factor& F) {
       gw.push_back(g);
     }
     auto tw = gemm_tiles(gw);
-    lv.plan.g_w = DevBuf<GemmDesc>(gw);
-    lv.plan.t_w = DevBuf<GemmTile>(tw);
+    ab.add(lv.plan.g_w, gw);
+    ab.add(lv.plan.t_w, tw);
     lv.plan.n_tw = (int)tw.size();
     lv.mfma = true;
     lv.nb_class = sweep_tile_class(lv.bmax);
@@ -1634,6 +1636,7 @@ static void prepare_mfma_sweeps(Factor& F) {
 static void build_solve_plan(Factor& F) {
   HostTimer ht(6);
   const int L = F.L, l0 = F.l0;
+  ArenaBuilder ab;
   for (int lev = L; lev > l0; --lev) {
     CellLevel& lv = F.levels[lev];
     CellLevel& pa = F.levels[lev - 1];
@@ -1681,18 +1684,18 @@ static void build_solve_plan(Factor& F) {
       d.beta_re = 1.0;
       gd2.push_back(d);
     }
-    P.lu = DevBuf<SolveDesc>(sd);
+    ab.add(P.lu, sd);
     P.n_lu = (int)sd.size();
     P.bmax = lv.bmax;
     auto tv = gemm_tiles(gv), tat = gemm_tiles(gat), td1 = gemm_tiles(gd1), td2 = gemm_tiles(gd2);
-    P.g_v = DevBuf<GemmDesc>(gv);
-    P.g_at = DevBuf<GemmDesc>(gat);
-    P.g_dn1 = DevBuf<GemmDesc>(gd1);
-    P.g_dn2 = DevBuf<GemmDesc>(gd2);
-    P.t_v = DevBuf<GemmTile>(tv);
-    P.t_at = DevBuf<GemmTile>(tat);
-    P.t_dn1 = DevBuf<GemmTile>(td1);
-    P.t_dn2 = DevBuf<GemmTile>(td2);
+    ab.add(P.g_v, gv);
+    ab.add(P.g_at, gat);
+    ab.add(P.g_dn1, gd1);
+    ab.add(P.g_dn2, gd2);
+    ab.add(P.t_v, tv);
+    ab.add(P.t_at, tat);
+    ab.add(P.t_dn1, td1);
+    ab.add(P.t_dn2, td2);
     P.n_tv = (int)tv.size();
     P.n_tat = (int)tat.size();
     P.n_tdn1 = (int)td1.size();
@@ -1703,11 +1706,11 @@ static void build_solve_plan(Factor& F) {
         si.push_back(lv.t_off[q] + j);
         di.push_back(pa.f_off[q / 2] + lv.ppos[q][j]);
       }
-    P.up_src = DevBuf<int64_t>(si);
-    P.up_dst = DevBuf<int64_t>(di);
+    ab.add(P.up_src, si);
+    ab.add(P.up_dst, di);
     P.n_up = (int64_t)si.size();
   }
-  if (F.opt.precision == FDS_PREC_FP64 && F.opt.mfma_sweeps) prepare_mfma_sweeps(F);
+  if (F.opt.precision == FDS_PREC_FP64 && F.opt.mfma_sweeps) prepare_mfma_sweeps(F, ab);
   if (F.opt.precision == FDS_PREC_MIXED) {
     // products with the FP64 diagonal blocks (without the children's A~) of
     // every compressed level: y_i = B_i z_i on the level vectors
@@ -1728,8 +1731,8 @@ static void build_solve_plan(Factor& F) {
         gd.push_back(g);
       }
       auto t = gemm_tiles(gd);
-      lv.g_diag = DevBuf<GemmDesc>(gd);
-      lv.t_diag = DevBuf<GemmTile>(t);
+      ab.add(lv.g_diag, gd);
+      ab.add(lv.t_diag, t);
       lv.n_tdiag = (int)t.size();
     }
   }
@@ -1741,9 +1744,10 @@ static void build_solve_plan(Factor& F) {
   }
   iota.resize(rows.size());
   std::iota(iota.begin(), iota.end(), 0);
-  F.leaf_dofs_rows = DevBuf<int64_t>(rows);
-  F.leaf_dofs_cols = DevBuf<int64_t>(cols);
-  F.leaf_iota = DevBuf<int64_t>(iota);
+  ab.add(F.leaf_dofs_rows, rows);
+  ab.add(F.leaf_dofs_cols, cols);
+  ab.add(F.leaf_iota, iota);
+  ab.finish(F.plan_arena);
 }
 
 // nrhs classes of the autotuner: 1 | 2-8 | 9-32 | 33+
