@@ -145,8 +145,8 @@ __device__ inline bool field_element(const MatConst& m, const Elem& e, double tx
   return d * kFieldMaxPanels < h;
 }
 
-// Two wavefronts per SIMD (256 registers with the accumulation registers,
-// 140 bytes per lane spilled): the kernel values' long dependent chains
+// Two wavefronts per SIMD (214 registers, none spilled when the series and
+// Bessel constants stay at their uses): the kernel values' long dependent chains
 // need the second wavefront to hide their latency (8.6 ms against 9.8 ms
 // for the whole field call of 4096 targets x 6400 nodes x 180 solutions at
 // one wavefront per SIMD; the uniform 4-point path then took it from 7.7
