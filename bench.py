@@ -322,14 +322,14 @@ def main():
 # headline workload, counted with rocprofv3 (SQ_INSTS_VALU_FMA_F64 x 2 +
 # ADD_F64 + MUL_F64, x 64 lanes, over the points the kernel integrated):
 # profiles/pair_kernels_ellipse131072_tol1e-11.md
-FLOP_PER_POINT = {"k_regular<0, false>": 1156.3, "k_regular<0, true>": 708.9, "k_regular<1, false>": None,
-                  "k_regular<1, true>": 565.7, "k_regular<2, false>": 1163.5, "k_regular<2, true>": 540.5,
-                  "k_regular<3, false>": 1187.9, "k_regular<3, true>": 530.4, "k_regular_wave10": 834.7,
+FLOP_PER_POINT = {"k_regular<0, false>": 1154.1, "k_regular<0, true>": 706.6, "k_regular<1, false>": None,
+                  "k_regular<1, true>": 562.8, "k_regular<2, false>": 1162.4, "k_regular<2, true>": 537.7,
+                  "k_regular<3, false>": 1185.8, "k_regular<3, true>": 527.5, "k_regular_wave10": 834.7,
                   "k_special<1>": 1039.9, "k_special2<2>": 628.4, "k_special2<3>": 628.4}
 # HBM bytes per launch of a pair kernel from two counter runs (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
 # for a plain 1 GiB device copy (2.0 and 1.0): same profile
-TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (120294 * 2.0 + 866070 * 1.0) * 1024}
+TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (66734 * 2.0 + 735895 * 1.0) * 1024}
 
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")

@@ -291,6 +291,7 @@ struct fds_factor_s {
   fds_stats st{};
   hipStream_t stream = nullptr;
   fds::Workspace ws;
+  fds::ArenaBuilder plan_ab;                // host side of plan_arena while the factorisation runs
   fds::DevBuf<unsigned char> plan_arena;    // the solve's descriptors and row maps (one allocation)
   fds::DevView<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
@@ -1633,11 +1634,14 @@ static void prepare_mfma_sweeps(Factor& F, ArenaBuilder& ab) {
   }
 }
 
-static void build_solve_plan(Factor& F) {
+// Host part of level lev's solve plan (descriptors, tiles, row maps), into
+// the factor's plan arena.  Everything it reads is final once the parent
+// level's lists are laid out, so the factorisation calls it right after
+// enqueueing the level's merge, while the GPU works.
+static void plan_level(Factor& F, int lev) {
   HostTimer ht(6);
-  const int L = F.L, l0 = F.l0;
-  ArenaBuilder ab;
-  for (int lev = L; lev > l0; --lev) {
+  ArenaBuilder& ab = F.plan_ab;
+  {
     CellLevel& lv = F.levels[lev];
     CellLevel& pa = F.levels[lev - 1];
     SolveLevel& P = lv.plan;
@@ -1710,6 +1714,15 @@ static void build_solve_plan(Factor& F) {
     ab.add(P.up_dst, di);
     P.n_up = (int64_t)si.size();
   }
+}
+
+// The rest of the solve plan (every level's plan_level has run): the
+// matrix-core sweep data, the mixed form's diagonal-block products and the
+// leaf DOF maps; then the arena goes up in one copy.
+static void build_solve_plan(Factor& F) {
+  HostTimer ht(6);
+  const int L = F.L, l0 = F.l0;
+  ArenaBuilder& ab = F.plan_ab;
   if (F.opt.precision == FDS_PREC_FP64 && F.opt.mfma_sweeps) prepare_mfma_sweeps(F, ab);
   if (F.opt.precision == FDS_PREC_MIXED) {
     // products with the FP64 diagonal blocks (without the children's A~) of
@@ -2277,6 +2290,7 @@ int fds_build(const fds_geometry* geom, double omega, double lambda, double mu, 
       merge_lists(*F, lev);
       if (lev - 1 > F->l0) prepare_level(*F, lev - 1);
       merge_blocks(*F, lev);
+      plan_level(*F, lev);
     }
     factor_root(*F);
     build_solve_plan(*F);
