@@ -1303,10 +1303,11 @@ static void compress_level(Factor& F, int lev) {
   lv.s_piv_off.resize(n);
   lv.t_off.resize(n);
   lv.x_tot = lv.at_tot = lv.v_tot = lv.s_piv_tot = lv.R = 0;
-  int rmax = 0;
-  for (int q = 0; q < n; ++q) {
+  parallel_for(n, [&](int q) {   // each cell's skeleton DOFs, on the host pool
     const int c0 = lv.n0[q];
     const int kk[2] = {lv.k0[q], lv.k1[q]};
+    lv.cskel[q].reserve(kk[0] + kk[1]);
+    lv.rskel[q].reserve(kk[0] + kk[1]);
     for (int comp = 0; comp < 2; ++comp) {
       const int base = comp ? c0 : 0;
       const int* pc = hpiv.data() + qv[2 * q + comp].piv_off;
@@ -1316,6 +1317,9 @@ static void compress_level(Factor& F, int lev) {
         lv.rskel[q].push_back(lv.rows[q][base + pr[j]]);
       }
     }
+  });
+  int rmax = 0;
+  for (int q = 0; q < n; ++q) {
     const int b = lv.b[q], r = lv.r[q];
     rmax = std::max(rmax, r);
     lv.x_off[q] = lv.x_tot;
