@@ -1402,11 +1402,13 @@ static void merge_lists(Factor& F, int lev) {
   pa.rows.assign(pa.n, {});
   pa.cols.assign(pa.n, {});
   ch.ppos.assign(ch.n, {});
-  for (int p = 0; p < pa.n; ++p) {
+  parallel_for(pa.n, [&](int p) {   // parents on the host thread pool
     const int a = 2 * p, b = 2 * p + 1;
     const int ka0 = ch.k0[a], kb0 = ch.k0[b], ka1 = ch.k1[a], kb1 = ch.k1[b];
     auto& R = pa.rows[p];
     auto& C = pa.cols[p];
+    R.reserve(ka0 + kb0 + ka1 + kb1);
+    C.reserve(ka0 + kb0 + ka1 + kb1);
     auto app = [](std::vector<int64_t>& dst, const std::vector<int64_t>& src, int o, int k) {
       dst.insert(dst.end(), src.begin() + o, src.begin() + o + k);
     };
@@ -1421,11 +1423,13 @@ static void merge_lists(Factor& F, int lev) {
     // parent position of each child skeleton entry (same pattern for rows and cols)
     auto& pa_ = ch.ppos[a];
     auto& pb_ = ch.ppos[b];
+    pa_.reserve(ka0 + ka1);
+    pb_.reserve(kb0 + kb1);
     for (int j = 0; j < ka0; ++j) pa_.push_back(j);
     for (int j = 0; j < ka1; ++j) pa_.push_back(ka0 + kb0 + j);
     for (int j = 0; j < kb0; ++j) pb_.push_back(ka0 + j);
     for (int j = 0; j < kb1; ++j) pb_.push_back(ka0 + kb0 + ka1 + j);
-  }
+  });
   layout_blocks(pa);
 }
 
