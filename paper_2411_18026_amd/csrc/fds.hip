@@ -248,7 +248,7 @@ struct CellLevel {
   // diagonal blocks; V then holds W = A~ V (the upward sweep's product)
   bool mfma = false;
   int nb_class = 0, nr_class = 0;
-  DevBuf<SweepCell> sweep;
+  DevView<SweepCell> sweep;   // in the factor's plan arena
   DevBuf<int> perm;
   DevBuf<c64> Dinv;
   // compressed-operator product (mixed form): y = B z per cell
@@ -293,6 +293,7 @@ struct fds_factor_s {
   fds::Workspace ws;
   fds::ArenaBuilder plan_ab;                // host side of plan_arena while the factorisation runs
   fds::DevBuf<unsigned char> plan_arena;    // the solve's descriptors and row maps (one allocation)
+  fds::DevBuf<unsigned char> plan_arena_sweep;   // the same, added before the matrix-core sweep preparation
   fds::DevView<int64_t> leaf_dofs_rows, leaf_dofs_cols, leaf_iota;
   fds::DevBuf<float> pred;                  // learned form: predictor blob
   fds::DevBuf<int> sing;                    // per level: a block LU met a zero pivot
@@ -1558,12 +1559,27 @@ static void factor_root(Factor& F) {
 // inverted diagonal blocks.
 static void prepare_mfma_sweeps(Factor& F, ArenaBuilder& ab) {
   hipStream_t s = F.stream;
-  Workspace& ws = F.ws;
+  // host arrays of every level first (one upload for all of them), then
+  // the per-level launches
+  struct Prep {
+    int lev = 0, rmax = 0, n_blk = 0, nmax = 0, n_gt = 0;
+    int64_t dtot = 0;
+    DevView<int> blk_cell, blk_k;
+    DevView<GemmDesc> gd;
+    DevView<GemmTile> gt;
+  };
+  std::vector<Prep> preps;
+  preps.reserve(F.L - F.l0);
+  ArenaBuilder pre;
   for (int lev = F.L; lev > F.l0; --lev) {
     CellLevel& lv = F.levels[lev];
     int rmax = 0;
     for (int q = 0; q < lv.n; ++q) rmax = std::max(rmax, lv.r[q]);
     if (!sweep_supported(lv.bmax, rmax)) continue;
+    preps.emplace_back();
+    Prep& P = preps.back();
+    P.lev = lev;
+    P.rmax = rmax;
     std::vector<SweepCell> cells(lv.n);
     std::vector<int> blk_cell, blk_k;
     std::vector<GemmDesc> gd;
@@ -1600,22 +1616,17 @@ static void prepare_mfma_sweeps(Factor& F, ArenaBuilder& ab) {
       g.ldc = r;
       g.alpha_re = 1.0;
       gd.push_back(g);
+      P.nmax = std::max(P.nmax, g.n);
     }
-    lv.sweep = DevBuf<SweepCell>(cells);
-    lv.perm = DevBuf<int>((size_t)std::max<int64_t>(lv.piv_tot, 1));
-    lv.Dinv = DevBuf<c64>((size_t)std::max<int64_t>(dtot, 1));
-    launch_sweep_prepare(lv.sweep.p, lv.n, ws.upload("sw_bc", blk_cell), ws.upload("sw_bk", blk_k),
-                         (int)blk_cell.size(), lv.piv.p, lv.A.p, lv.perm.p, lv.Dinv.p, s);
-    if (!gd.empty()) {
-      DevBuf<c64> W((size_t)lv.V.n);
-      auto gt = gemm_tiles(gd);
-      int nmax = 0;
-      for (auto& g : gd) nmax = std::max(nmax, g.n);
-      launch_gemm(ws.upload("w_desc", gd), ws.upload("w_tiles", gt), (int)gt.size(), nmax, 0, lv.At.p, lv.V.p, W.p,
-                  0, s);
-      FDS_HIP(hipStreamSynchronize(s));   // the old V goes back to the cache now
-      lv.V = std::move(W);
-    }
+    P.dtot = dtot;
+    P.n_blk = (int)blk_cell.size();
+    const auto gt = gemm_tiles(gd);
+    P.n_gt = (int)gt.size();
+    ab.add(lv.sweep, cells);   // kept with the solve plan
+    pre.add(P.blk_cell, blk_cell);
+    pre.add(P.blk_k, blk_k);
+    pre.add(P.gd, gd);
+    pre.add(P.gt, gt);
     // fewer columns than a slab: the LU-solve kernel, then f~ = W g by GEMM
     std::vector<GemmDesc> gw;
     for (int q = 0; q < lv.n; ++q) {
@@ -1636,10 +1647,30 @@ static void prepare_mfma_sweeps(Factor& F, ArenaBuilder& ab) {
     ab.add(lv.plan.g_w, gw);
     ab.add(lv.plan.t_w, tw);
     lv.plan.n_tw = (int)tw.size();
+  }
+  if (preps.empty()) return;
+  // the sweep cells go up now (the preparation kernels read them), with the
+  // rest of the solve plan added so far
+  ab.finish(F.plan_arena_sweep);
+  DevBuf<unsigned char> pre_arena;
+  pre.finish(pre_arena);
+  for (const Prep& P : preps) {
+    CellLevel& lv = F.levels[P.lev];
+    lv.perm = DevBuf<int>((size_t)std::max<int64_t>(lv.piv_tot, 1));
+    lv.Dinv = DevBuf<c64>((size_t)std::max<int64_t>(P.dtot, 1));
+    launch_sweep_prepare(lv.sweep.p, lv.n, P.blk_cell.p, P.blk_k.p, P.n_blk, lv.piv.p, lv.A.p, lv.perm.p, lv.Dinv.p,
+                         s);
+    if (P.n_gt > 0) {
+      DevBuf<c64> W((size_t)lv.V.n);
+      launch_gemm(P.gd.p, P.gt.p, P.n_gt, P.nmax, 0, lv.At.p, lv.V.p, W.p, 0, s);
+      FDS_HIP(hipStreamSynchronize(s));   // the old V goes back to the cache now
+      lv.V = std::move(W);
+    }
     lv.mfma = true;
     lv.nb_class = sweep_tile_class(lv.bmax);
-    lv.nr_class = sweep_tile_class(std::max(rmax, 1));
+    lv.nr_class = sweep_tile_class(std::max(P.rmax, 1));
   }
+  FDS_HIP(hipStreamSynchronize(s));   // the host arrays of pre_arena go back to the cache
 }
 
 // Host part of level lev's solve plan (descriptors, tiles, row maps), into
