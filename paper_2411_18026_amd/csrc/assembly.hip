@@ -581,6 +581,8 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
 }
 
 // ------------------------------------------------------------------ gather
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 __global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
                          const Dof* __restrict__ dofs, const int* __restrict__ pos,
                          const c64* __restrict__ res, int64_t np, c64* __restrict__ out) {
@@ -603,7 +605,10 @@ __global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       const int64_t slot = pair_slot(jb, ier[x], jec[y]);
-      s += res[(ia[x] * 8 + jb2[y] * 4 + k) * np + slot];
+      // each pair result is read once: a streaming (non-temporal) load
+      const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(res + (ia[x] * 8 + jb2[y] * 4 + k) * np + slot));
+      s.re += v.x;
+      s.im += v.y;
     }
   const int64_t rp = jb.rpos_off >= 0 ? pos[jb.rpos_off + r] : r;
   const int64_t cp = jb.cpos_off >= 0 ? pos[jb.cpos_off + c] : c;
