@@ -45,6 +45,9 @@ namespace fds {
 
 __constant__ QuadTables c_quad;
 
+// two doubles as one 16-byte vector (one load or store instruction)
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 // The four 2 x 2 blocks of one quadrature point (d = x - y, normals n_x,
 // n_y of the test and trial elements) whose hat-weighted sums make up a
 // pair's 16 entries:
@@ -390,7 +393,8 @@ __device__ inline void regular_pair(unsigned long long key, int qf, const Job* _
   pair_entries(A);
   const int64_t slot = pair_slot(jb, ie, je);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) res[k * np + slot] = A.R[k];
+  for (int k = 0; k < 16; ++k)   // read once, by the gather: streaming stores
+    __builtin_nontemporal_store(d2v{A.R[k].re, A.R[k].im}, reinterpret_cast<d2v*>(res + k * np + slot));
 }
 
 // The regular pairs with order index OE on the test element, one thread per
@@ -581,7 +585,6 @@ __device__ inline void special_pair(unsigned long long key, int lane, const Job*
 }
 
 // ------------------------------------------------------------------ gather
-typedef double d2v __attribute__((ext_vector_type(2)));
 
 __global__ void k_gather(const Tile* __restrict__ tiles, const Job* __restrict__ jobs,
                          const Dof* __restrict__ dofs, const int* __restrict__ pos,
