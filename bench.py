@@ -329,7 +329,7 @@ FLOP_PER_POINT = {"k_regular<0, false>": 1154.1, "k_regular<0, true>": 706.6, "k
 # HBM bytes per launch of a pair kernel from two counter runs (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
 # for a plain 1 GiB device copy (2.0 and 1.0): same profile
-TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (66734 * 2.0 + 735895 * 1.0) * 1024}
+TRAFFIC_PER_LAUNCH = {"k_regular<1, true>": (55298 * 2.0 + 745947 * 1.0) * 1024}
 
 
 PREDICTOR = os.path.join(ROOT, "paper_2411_18026_amd", "predictors", "rank_mlp_multicavity16k.npy")
